@@ -1,0 +1,244 @@
+/*
+ * lider.h -- C ABI of the MI355X (gfx950) LIDER library.
+ *
+ * LIDER (arXiv 2205.00970) is a two-layer learned index for dense retrieval:
+ * k-means clusters the corpus (Section 3.2); a "centroids retriever" core model
+ * indexes the centroids and one "in-cluster retriever" core model indexes each
+ * cluster (Section 3.3.2).  A core model hashes vectors with SK-LSH, sorts the
+ * hash keys, re-scales them (Section 5.1, Eq. (8)) and trains a two-stage linear
+ * RMI (Section 5.2) that predicts a key's location in the sorted array; a search
+ * scans a fixed-length window around the predicted location and scores the
+ * candidates exactly (Section 3.3.1).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device pointers (hipMalloc'd, e.g. a torch CUDA
+ *    tensor's data_ptr) on the current HIP device; *_host are host pointers.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Matrices are dense row-major; a "row" is one d-dimensional fp32 vector.
+ *  - Return value: LIDER_OK (0) or a negative lider_status.  On error a
+ *    description is available from lider_last_error() on the same thread.
+ *    Arguments are validated before anything is enqueued; an invalid call
+ *    enqueues nothing.  Faults of already-enqueued device work surface as
+ *    LIDER_EDEVICE from a later call or from the caller's stream sync.
+ *  - No C++ exception crosses this boundary.
+ */
+#ifndef LIDER_H
+#define LIDER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LIDER_OK = 0,
+  LIDER_EINVAL = -1,  /* bad argument (null pointer, size out of range, ...) */
+  LIDER_ENOMEM = -2,  /* device allocation failed (build only) */
+  LIDER_EDEVICE = -3, /* a HIP runtime call failed */
+  LIDER_ERANGE = -4,  /* a hash value does not fit in int32 */
+  LIDER_EBUSY = -5    /* reserved */
+} lider_status;
+
+typedef enum {
+  LIDER_F32 = 0,     /* IEEE fp32 */
+  LIDER_BF16 = 1,    /* bfloat16 (round to nearest even) */
+  LIDER_FP8E4M3 = 2  /* OCP fp8 e4m3 with one fp32 scale per row */
+} lider_dtype;
+
+/* Largest supported hash count per layer, clusters, k, and c. */
+#define LIDER_MAX_M 16
+#define LIDER_MAX_K 1024
+#define LIDER_MAX_C 128
+
+typedef struct lider_index lider_index; /* opaque; owns its device memory */
+
+/* Build parameters (Sections 3.2, 3.3, 5).
+ *  n_clusters     number of k-means clusters c of Table 1 (1..n).
+ *  m              hashes per key M of Table 1 (1..LIDER_MAX_M).
+ *  w              E2LSH bucket width (> 0): digit = floor((a.x + b) / w).
+ *  rmi_fanout     second-stage width W_i of the in-cluster RMIs (Section 7.2.1).
+ *  rmi_fanout_l1  second-stage width W_c of the centroids retriever (0 = same).
+ *  lsh_a_host     [2m x d] fp32 projections: rows 0..m-1 hash the centroids
+ *                 retriever, rows m..2m-1 are shared by every in-cluster
+ *                 retriever.  Copied; may be freed after the call.
+ *  lsh_b_host     [2m] fp32 offsets in [0, w).
+ *  assignment_dev optional [n] int32 cluster of each row (0..n_clusters-1);
+ *                 NULL runs k-means.  Empty clusters are allowed (their
+ *                 centroid is the zero vector).
+ *  kmeans_init_host [n_clusters] int64 row ids of the initial centroids
+ *                 (required when assignment_dev is NULL, distinct not required).
+ *  kmeans_iters   maximum Lloyd iterations (>= 1); stops early when an
+ *                 assignment repeats the previous one.
+ *  storage        LIDER_F32, or LIDER_BF16 to add a bf16 copy of the corpus
+ *                 for the precision form (the fp32 copy is always kept).
+ *  centroid_storage LIDER_F32, or LIDER_FP8E4M3 to add per-row-scaled fp8
+ *                 centroids for precision-form routing. */
+typedef struct {
+  int32_t n_clusters;
+  int32_t m;
+  int32_t rmi_fanout;
+  int32_t rmi_fanout_l1;
+  double w;
+  const float* lsh_a_host;
+  const float* lsh_b_host;
+  const int32_t* assignment_dev;
+  const int64_t* kmeans_init_host;
+  int32_t kmeans_iters;
+  int32_t storage;
+  int32_t centroid_storage;
+} lider_build_params;
+
+/* Build an index over corpus_dev [n x d] fp32 (Sections 3.2, 3.3.1, 3.3.2):
+ * k-means (unless an assignment is given), layer-2 digits of every row,
+ * per-cluster digit boxes and mixed-radix keys, a stable sort by
+ * (cluster, key, id), key re-scaling, RMI training, and a copy of the corpus
+ * reordered by that sort; then the same core model over the centroids.
+ * Runs on `stream` and synchronises it before returning.  The index keeps its
+ * own copy of everything; the caller may free corpus_dev afterwards.
+ * n in 1..2^31-1, d in 1..65536.  Errors: EINVAL, ENOMEM, EDEVICE, ERANGE. */
+int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build_params* params,
+                void* stream, lider_index** out);
+
+/* Release the index and all its device memory.  NULL is a no-op.  Must not be
+ * called while a search on the index is still running. */
+void lider_free(lider_index* index);
+
+/* Thread-local description of the last error (empty string if none). */
+const char* lider_last_error(void);
+
+/* Search options (lider_search_ex).  Zero-initialise for defaults.
+ *  r1             layer-1 window length (0 = r): centroids scanned around the
+ *                 centroids retriever's predicted location.
+ *  precision      LIDER_F32: exact fp32 rerank of every window row.
+ *                 LIDER_BF16: precision form -- bf16 first pass over the
+ *                 windows (needs storage = LIDER_BF16), shortlist of
+ *                 shortlist_mult*k per query, fp32 rerank of the shortlist from
+ *                 the fp32 copy; routing uses fp8 centroids if the index has
+ *                 them, else fp32.
+ *  shortlist_mult shortlist length per query in units of k (0 = 4).
+ *  persistent     1: run the rerank as a persistent kernel over the
+ *                 (cluster, row-tile) work list instead of one workgroup per
+ *                 tile.  Results are identical.
+ *  tile_rows      rows per rerank tile: 0 (default 64) or 32, 64, 128.
+ *  pair_tile      pairs per MFMA pass in the rerank: 0 (default 16) or 16, 32.
+ *  grid_mult      persistent grid = grid_mult * number of CUs (0 = 4). */
+typedef struct {
+  int32_t r1;
+  int32_t precision;
+  int32_t shortlist_mult;
+  int32_t persistent;
+  int32_t tile_rows;
+  int32_t pair_tile;
+  int32_t grid_mult;
+  int32_t reserved[9];
+} lider_search_opts;
+
+/* Optional device outputs of the intermediate search state, for parity checks.
+ * Each pointer may be NULL.
+ *  qdigits_dev [nq x 2m] int32   query digits (layer-1 set, then layer-2 set)
+ *  l1_dev      [nq x 3] int64    layer-1 predicted location, window start, length
+ *  routed_dev  [nq x c] int32    routed cluster ids (order unspecified, -1 pad)
+ *  pairs_dev   [nq x c x 3] int64 per routed cluster (same order): predicted
+ *                                location, window start, window length */
+typedef struct {
+  int32_t* qdigits_dev;
+  int64_t* l1_dev;
+  int32_t* routed_dev;
+  int64_t* pairs_dev;
+} lider_search_debug;
+
+/* Bytes of device workspace lider_search / lider_search_ex need for a batch.
+ * Returns 0 for invalid arguments. */
+size_t lider_search_workspace(const lider_index* index, int64_t nq, int32_t k, int32_t c,
+                              int32_t r, const lider_search_opts* opts);
+
+/* Batched search (Section 3.3.2): queries_dev [nq x d] fp32.  For each query:
+ * E2LSH digits of both layers; the centroids retriever's key, RMI location and
+ * window of r1 centroids, scored by inner product, top c clusters; in each
+ * routed cluster the in-cluster retriever's key, RMI location and window of r
+ * rows; exact inner-product scores of all window rows; top k over the union.
+ * Outputs ids_dev [nq x k] int64 (original row ids) and scores_dev [nq x k]
+ * fp32, each row sorted by score descending, ties by smaller id, padded with
+ * id -1 / score -inf.  ws_dev must hold lider_search_workspace(...) bytes (256-
+ * byte aligned).  Asynchronous on `stream`: nothing is allocated, nothing is
+ * synchronised, no host read-back.  k in 1..LIDER_MAX_K, c in
+ * 1..min(LIDER_MAX_C, n_clusters), r >= 1, nq >= 0 (0 is a no-op).
+ * Safe to call concurrently on different streams with separate workspaces. */
+int lider_search(const lider_index* index, const float* queries_dev, int64_t nq, int32_t k,
+                 int32_t c, int32_t r, int64_t* ids_dev, float* scores_dev, void* ws_dev,
+                 size_t ws_bytes, void* stream);
+
+/* lider_search with options (NULL = defaults) and optional debug outputs. */
+int lider_search_ex(const lider_index* index, const float* queries_dev, int64_t nq, int32_t k,
+                    int32_t c, int32_t r, int64_t* ids_dev, float* scores_dev, void* ws_dev,
+                    size_t ws_bytes, void* stream, const lider_search_opts* opts,
+                    const lider_search_debug* debug);
+
+/* ---------------------------------------------------------------- inspection */
+
+typedef struct {
+  int64_t n;
+  int32_t d, n_clusters, m, rmi_fanout, rmi_fanout_l1;
+  int32_t kmeans_iters_run; /* Lloyd assignments executed (0 if given) */
+  int64_t max_cluster;      /* largest cluster size */
+  double w;
+  int32_t storage, centroid_storage;
+} lider_info;
+
+int lider_get_info(const lider_index* index, lider_info* out);
+
+/* Exportable index arrays (host copies, synchronous). */
+typedef enum {
+  LIDER_X_CENTROIDS = 0,  /* [C x d] fp32, cluster-id order */
+  LIDER_X_ASSIGN = 1,     /* [n] int32 cluster of each original row */
+  LIDER_X_OFFSETS = 2,    /* [C+1] int64 first sorted position of each cluster */
+  LIDER_X_PERM = 3,       /* [n] int64 sorted position -> original row id */
+  LIDER_X_KEYS = 4,       /* [n] uint64 key at each sorted position */
+  LIDER_X_DIGITS = 5,     /* [n x m] int32 layer-2 digits per original row */
+  LIDER_X_L1_ORDER = 6,   /* [C] int64 layer-1 sorted position -> cluster id */
+  LIDER_X_L1_KEYS = 7,    /* [C] uint64 */
+  LIDER_X_L1_DIGITS = 8,  /* [C x m] int32 layer-1 digits per cluster id */
+  LIDER_X_MODEL_INT = 9,  /* [(C+1) x 3] int64: L, m_eff, F; model C = layer 1 */
+  LIDER_X_MODEL_BOX = 10, /* [(C+1) x 2m] int32: mins[m], maxs[m] */
+  LIDER_X_MODEL_KEY = 11, /* [(C+1) x 2] uint64: kmin, kmax */
+  LIDER_X_MODEL_DBL = 12, /* [(C+1) x 3] double: scale, root slope, root intercept */
+  LIDER_X_LEAVES = 13,    /* [C*F2 + F1] x 2 double: leaf slope, intercept */
+  LIDER_X_LEAF_ERR = 14,  /* [C*F2 + F1] x 2 int32: min and max (true - predicted) */
+  LIDER_X_REORDERED = 15  /* [n x d] fp32 corpus in sorted order */
+} lider_export_what;
+
+/* Bytes of one export (0 if unknown / not present). */
+size_t lider_export_bytes(const lider_index* index, int32_t what);
+/* Copy one array to host memory dst_host of dst_bytes >= lider_export_bytes. */
+int lider_export(const lider_index* index, int32_t what, void* dst_host, size_t dst_bytes);
+
+/* ------------------------------------------------------- stand-alone kernels */
+
+/* E2LSH digits (Section 4): out_dev[r*nh + i] = floor((A[i].X[r] + b[i]) / w)
+ * for X_dev [n x d], A_dev [nh x d], b_dev [nh] (all fp32, device), nh in 1..32.
+ * Projections run on fp32 MFMA; values within the rounding-error band of a
+ * bucket edge are recomputed sequentially in FP64, so the digits equal the
+ * FP64 definition exactly.  Allocates a temporary device list; synchronises
+ * `stream`.  Errors: EINVAL, ENOMEM, EDEVICE, ERANGE. */
+int lider_hash(const float* X_dev, int64_t n, int32_t d, const float* A_dev, const float* b_dev,
+               int32_t nh, double w, int32_t* out_dev, void* stream);
+
+/* One k-means assignment step (Section 3.2): assign_dev[i] = argmin_j
+ * ||X[i] - cent[j]||^2 decided in FP64 (ties to the smaller j); fp32 MFMA
+ * distances, FP64 recompute where the rounding-error bands of the two best
+ * overlap.  X_dev [n x d], cent_dev [C x d].  Allocates temporaries;
+ * synchronises `stream`. */
+int lider_kmeans_assign(const float* X_dev, int64_t n, int32_t d, const float* cent_dev,
+                        int32_t C, int32_t* assign_dev, void* stream);
+
+/* Test hook: the next lider_search / lider_search_ex call on this thread fails
+ * with `status` before enqueuing anything (0 clears the hook). */
+void lider_debug_fail_next(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIDER_H */

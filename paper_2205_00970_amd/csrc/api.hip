@@ -1,0 +1,408 @@
+// The C ABI (include/lider.h): argument validation, index allocation and
+// lifetime, build orchestration, search dispatch, exports and error state.
+#include <cstring>
+#include <new>
+
+#include "lider_internal.hpp"
+
+namespace lider {
+
+int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const float* b,
+                const float* anorm, int32_t nh, double w, int32_t* out, int64_t* list,
+                int32_t* counter, int32_t* status, int clamp, float* rownorm, hipStream_t st);
+
+namespace {
+thread_local std::string g_err;
+thread_local int32_t g_fail_next = 0;
+
+template <class T>
+int alloc(T** p, size_t count, const char* what) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return set_error(LIDER_ENOMEM, std::string("out of device memory: ") + what);
+  }
+  return LIDER_OK;
+}
+
+void free_device(Index& ix) {
+  void* ptrs[] = {ix.X,      ix.Xb,          ix.perm,     ix.perm32,    ix.keys,
+                  ix.digits, ix.assign,      ix.off,      ix.cent,      ix.cent_l1,
+                  ix.cent8,  ix.cent8_scale, ix.l1_order, ix.l1_order32, ix.l1_keys,
+                  ix.l1_digits, ix.A,        ix.b,        ix.anorm,     ix.cent_norm_max,
+                  ix.models, ix.leaves,      ix.leaf_err, ix.tiles[0],  ix.tiles[1],
+                  ix.tiles[2]};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+int set_error(int status, const std::string& msg) {
+  g_err = msg;
+  return status;
+}
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return LIDER_OK;
+  return set_error(LIDER_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace lider
+
+using namespace lider;
+
+struct lider_index {
+  Index ix;
+};
+
+extern "C" {
+
+const char* lider_last_error(void) { return g_err.c_str(); }
+
+void lider_debug_fail_next(int32_t status) { g_fail_next = status; }
+
+void lider_free(lider_index* index) {
+  if (!index) return;
+  free_device(index->ix);
+  delete index;
+}
+
+int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build_params* P,
+                void* stream, lider_index** out) {
+  g_err.clear();
+  if (!out) return set_error(LIDER_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!corpus_dev || !P) return set_error(LIDER_EINVAL, "corpus or params is NULL");
+  if (n < 1 || n > INT32_MAX) return set_error(LIDER_EINVAL, "n must be in 1..2^31-1");
+  if (d < 1 || d > 65536) return set_error(LIDER_EINVAL, "d must be in 1..65536");
+  if (P->n_clusters < 1 || P->n_clusters > n)
+    return set_error(LIDER_EINVAL, "n_clusters must be in 1..n");
+  if (P->m < 1 || P->m > LIDER_MAX_M) return set_error(LIDER_EINVAL, "m must be in 1..16");
+  if (!(P->w > 0.0) || !std::isfinite(P->w)) return set_error(LIDER_EINVAL, "w must be > 0");
+  if (P->rmi_fanout < 1 || P->rmi_fanout_l1 < 0)
+    return set_error(LIDER_EINVAL, "rmi_fanout must be >= 1");
+  if (!P->lsh_a_host || !P->lsh_b_host) return set_error(LIDER_EINVAL, "LSH parameters are NULL");
+  if (!P->assignment_dev && (!P->kmeans_init_host || P->kmeans_iters < 1))
+    return set_error(LIDER_EINVAL, "k-means needs kmeans_init_host and kmeans_iters >= 1");
+  if (P->storage != LIDER_F32 && P->storage != LIDER_BF16)
+    return set_error(LIDER_EINVAL, "storage must be LIDER_F32 or LIDER_BF16");
+  if (P->centroid_storage != LIDER_F32 && P->centroid_storage != LIDER_FP8E4M3)
+    return set_error(LIDER_EINVAL, "centroid_storage must be LIDER_F32 or LIDER_FP8E4M3");
+  if (!P->assignment_dev)
+    for (int32_t j = 0; j < P->n_clusters; ++j)
+      if (P->kmeans_init_host[j] < 0 || P->kmeans_init_host[j] >= n)
+        return set_error(LIDER_EINVAL, "kmeans_init_host id out of range");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  lider_index* h = new (std::nothrow) lider_index();
+  if (!h) return set_error(LIDER_ENOMEM, "out of host memory");
+  Index& ix = h->ix;
+  ix.n = n;
+  ix.d = d;
+  ix.C = P->n_clusters;
+  ix.m = P->m;
+  ix.F2 = P->rmi_fanout;
+  ix.F1 = P->rmi_fanout_l1 > 0 ? P->rmi_fanout_l1 : P->rmi_fanout;
+  ix.w = P->w;
+  ix.storage = P->storage;
+  ix.centroid_storage = P->centroid_storage;
+  (void)hipGetDevice(&ix.device);
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ix.device) == hipSuccess && prop.multiProcessorCount > 0)
+      ix.n_cu = prop.multiProcessorCount;
+  }
+  const int64_t C = ix.C, m = ix.m;
+  const int64_t nleaf = C * ix.F2 + ix.F1;
+  int rc = LIDER_OK;
+#define TRY(x)                 \
+  do {                         \
+    if (rc == LIDER_OK) rc = (x); \
+  } while (0)
+  TRY(alloc(&ix.X, size_t(n) * d, "reordered corpus"));
+  if (ix.storage == LIDER_BF16) TRY(alloc(&ix.Xb, size_t(n) * d, "bf16 corpus"));
+  TRY(alloc(&ix.perm, size_t(n), "perm"));
+  TRY(alloc(&ix.perm32, size_t(n), "perm32"));
+  TRY(alloc(&ix.keys, size_t(n), "keys"));
+  TRY(alloc(&ix.digits, size_t(n) * m, "digits"));
+  TRY(alloc(&ix.assign, size_t(n), "assignment"));
+  TRY(alloc(&ix.off, size_t(C) + 1, "offsets"));
+  TRY(alloc(&ix.cent, size_t(C) * d, "centroids"));
+  TRY(alloc(&ix.cent_l1, size_t(C) * d, "layer-1 centroids"));
+  if (ix.centroid_storage == LIDER_FP8E4M3) {
+    TRY(alloc(&ix.cent8, size_t(C) * d, "fp8 centroids"));
+    TRY(alloc(&ix.cent8_scale, size_t(C), "fp8 scales"));
+  }
+  TRY(alloc(&ix.l1_order, size_t(C), "layer-1 order"));
+  TRY(alloc(&ix.l1_order32, size_t(C), "layer-1 order"));
+  TRY(alloc(&ix.l1_keys, size_t(C), "layer-1 keys"));
+  TRY(alloc(&ix.l1_digits, size_t(C) * m, "layer-1 digits"));
+  TRY(alloc(&ix.A, size_t(2 * m) * d, "LSH projections"));
+  TRY(alloc(&ix.b, size_t(2 * m), "LSH offsets"));
+  TRY(alloc(&ix.anorm, size_t(2 * m), "LSH norms"));
+  TRY(alloc(&ix.cent_norm_max, 64, "centroid norm"));
+  TRY(alloc(&ix.models, size_t(C) + 1, "models"));
+  TRY(alloc(&ix.leaves, size_t(nleaf) * 2, "leaves"));
+  TRY(alloc(&ix.leaf_err, size_t(nleaf) * 2, "leaf errors"));
+  TRY(check_hip(hipMemcpyAsync(ix.A, P->lsh_a_host, size_t(2 * m) * d * 4, hipMemcpyHostToDevice, st),
+                "copy LSH projections"));
+  TRY(check_hip(hipMemcpyAsync(ix.b, P->lsh_b_host, size_t(2 * m) * 4, hipMemcpyHostToDevice, st),
+                "copy LSH offsets"));
+  if (rc == LIDER_OK) launch_norm_bounds(ix.A, int32_t(2 * m), d, ix.anorm, st);
+  if (rc == LIDER_OK) {
+    if (P->assignment_dev) {
+      // given clusters: copy, range-check, centroids = member means (empty: 0)
+      TRY(check_hip(hipMemcpyAsync(ix.assign, P->assignment_dev, size_t(n) * 4,
+                                   hipMemcpyDeviceToDevice, st),
+                    "copy assignment"));
+      if (rc == LIDER_OK) {
+        std::vector<int32_t> h_asg(static_cast<size_t>(n));
+        TRY(check_hip(hipMemcpyAsync(h_asg.data(), ix.assign, size_t(n) * 4, hipMemcpyDeviceToHost, st),
+                      "read assignment"));
+        TRY(check_hip(hipStreamSynchronize(st), "read assignment"));
+        if (rc == LIDER_OK)
+          for (int64_t i = 0; i < n; ++i)
+            if (h_asg[i] < 0 || h_asg[i] >= ix.C) {
+              rc = set_error(LIDER_EINVAL, "assignment value out of range");
+              break;
+            }
+      }
+      TRY(check_hip(hipMemsetAsync(ix.cent, 0, size_t(C) * d * 4, st), "zero centroids"));
+      void* scr = nullptr;
+      const size_t sb = centroid_means_scratch(n, ix.C);
+      if (rc == LIDER_OK && hipMalloc(&scr, sb) != hipSuccess)
+        rc = set_error(LIDER_ENOMEM, "out of device memory (centroid scratch)");
+      TRY(run_centroid_means(corpus_dev, n, d, ix.assign, ix.C, ix.cent, scr, sb, st));
+      TRY(check_hip(hipStreamSynchronize(st), "centroids"));
+      if (scr) (void)hipFree(scr);
+      ix.iters_run = 0;
+    } else {
+      TRY(run_kmeans(ix, corpus_dev, P->kmeans_init_host, P->kmeans_iters, st));
+    }
+  }
+  TRY(build_core_models(ix, corpus_dev, st));
+  TRY(check_hip(hipStreamSynchronize(st), "index build"));
+#undef TRY
+  if (rc != LIDER_OK) {
+    lider_free(h);
+    return rc;
+  }
+  *out = h;
+  return LIDER_OK;
+}
+
+int lider_get_info(const lider_index* index, lider_info* out) {
+  if (!index || !out) return set_error(LIDER_EINVAL, "NULL argument");
+  const Index& ix = index->ix;
+  out->n = ix.n;
+  out->d = ix.d;
+  out->n_clusters = ix.C;
+  out->m = ix.m;
+  out->rmi_fanout = ix.F2;
+  out->rmi_fanout_l1 = ix.F1;
+  out->kmeans_iters_run = ix.iters_run;
+  out->max_cluster = ix.max_cluster;
+  out->w = ix.w;
+  out->storage = ix.storage;
+  out->centroid_storage = ix.centroid_storage;
+  return LIDER_OK;
+}
+
+static int validate_search(const lider_index* index, const float* Q, int64_t nq, int32_t k,
+                           int32_t c, int32_t r, const lider_search_opts& o) {
+  if (!index) return set_error(LIDER_EINVAL, "index is NULL");
+  const Index& ix = index->ix;
+  if (nq < 0 || nq > INT32_MAX) return set_error(LIDER_EINVAL, "nq must be in 0..2^31-1");
+  if (k < 1 || k > LIDER_MAX_K) return set_error(LIDER_EINVAL, "k must be in 1..1024");
+  if (c < 1 || c > LIDER_MAX_C || c > ix.C)
+    return set_error(LIDER_EINVAL, "c must be in 1..min(128, n_clusters)");
+  if (r < 1) return set_error(LIDER_EINVAL, "r must be >= 1");
+  if (o.r1 < 0) return set_error(LIDER_EINVAL, "r1 must be >= 0");
+  if (o.precision != LIDER_F32 && o.precision != LIDER_BF16)
+    return set_error(LIDER_EINVAL, "precision must be LIDER_F32 or LIDER_BF16");
+  if (o.precision == LIDER_BF16 && !ix.Xb)
+    return set_error(LIDER_EINVAL, "precision LIDER_BF16 needs an index built with storage BF16");
+  if (o.precision == LIDER_BF16 && (ix.d % 8 != 0))
+    return set_error(LIDER_EINVAL, "precision LIDER_BF16 needs d divisible by 8");
+  if (o.shortlist_mult < 0 || (o.precision == LIDER_BF16 && int64_t(o.shortlist_mult > 0 ? o.shortlist_mult : 4) * k > 4096))
+    return set_error(LIDER_EINVAL, "shortlist_mult * k must be at most 4096");
+  if (o.tile_rows != 0 && o.tile_rows != 32 && o.tile_rows != 64 && o.tile_rows != 128)
+    return set_error(LIDER_EINVAL, "tile_rows must be 0, 32, 64 or 128");
+  if (o.grid_mult < 0 || o.grid_mult > 64) return set_error(LIDER_EINVAL, "grid_mult out of range");
+  if (nq > 0 && !Q) return set_error(LIDER_EINVAL, "queries pointer is NULL");
+  return LIDER_OK;
+}
+
+size_t lider_search_workspace(const lider_index* index, int64_t nq, int32_t k, int32_t c,
+                              int32_t r, const lider_search_opts* opts) {
+  lider_search_opts o;
+  std::memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  if (validate_search(index, reinterpret_cast<const float*>(1), nq, k, c, r, o) != LIDER_OK) return 0;
+  return search_workspace(index->ix, nq, k, c, r, o);
+}
+
+int lider_search_ex(const lider_index* index, const float* queries_dev, int64_t nq, int32_t k,
+                    int32_t c, int32_t r, int64_t* ids_dev, float* scores_dev, void* ws_dev,
+                    size_t ws_bytes, void* stream, const lider_search_opts* opts,
+                    const lider_search_debug* debug) {
+  g_err.clear();
+  if (g_fail_next) {
+    const int32_t s = g_fail_next;
+    g_fail_next = 0;
+    return set_error(s, "failure injected by lider_debug_fail_next");
+  }
+  lider_search_opts o;
+  std::memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  int rc = validate_search(index, queries_dev, nq, k, c, r, o);
+  if (rc != LIDER_OK) return rc;
+  if (nq == 0) return LIDER_OK;
+  if (!ids_dev || !scores_dev || !ws_dev) return set_error(LIDER_EINVAL, "output or workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws_dev) & 255)
+    return set_error(LIDER_EINVAL, "workspace must be 256-byte aligned");
+  return run_search(index->ix, queries_dev, nq, k, c, r, ids_dev, scores_dev, ws_dev, ws_bytes,
+                    static_cast<hipStream_t>(stream), o, debug);
+}
+
+int lider_search(const lider_index* index, const float* queries_dev, int64_t nq, int32_t k,
+                 int32_t c, int32_t r, int64_t* ids_dev, float* scores_dev, void* ws_dev,
+                 size_t ws_bytes, void* stream) {
+  return lider_search_ex(index, queries_dev, nq, k, c, r, ids_dev, scores_dev, ws_dev, ws_bytes,
+                         stream, nullptr, nullptr);
+}
+
+// ------------------------------------------------------------------ exports
+namespace {
+struct ExportSrc {
+  const void* dev;
+  size_t bytes;
+  int kind;  // 0 plain device copy, 1 model ints, 2 model box, 3 model keys, 4 model doubles
+};
+
+ExportSrc export_src(const Index& ix, int32_t what) {
+  const size_t n = size_t(ix.n), d = size_t(ix.d), C = size_t(ix.C), m = size_t(ix.m);
+  const size_t nleaf = C * ix.F2 + ix.F1;
+  switch (what) {
+    case LIDER_X_CENTROIDS: return {ix.cent, C * d * 4, 0};
+    case LIDER_X_ASSIGN: return {ix.assign, n * 4, 0};
+    case LIDER_X_OFFSETS: return {ix.off, (C + 1) * 8, 0};
+    case LIDER_X_PERM: return {ix.perm, n * 8, 0};
+    case LIDER_X_KEYS: return {ix.keys, n * 8, 0};
+    case LIDER_X_DIGITS: return {ix.digits, n * m * 4, 0};
+    case LIDER_X_L1_ORDER: return {ix.l1_order, C * 8, 0};
+    case LIDER_X_L1_KEYS: return {ix.l1_keys, C * 8, 0};
+    case LIDER_X_L1_DIGITS: return {ix.l1_digits, C * m * 4, 0};
+    case LIDER_X_MODEL_INT: return {ix.models, (C + 1) * 3 * 8, 1};
+    case LIDER_X_MODEL_BOX: return {ix.models, (C + 1) * 2 * m * 4, 2};
+    case LIDER_X_MODEL_KEY: return {ix.models, (C + 1) * 2 * 8, 3};
+    case LIDER_X_MODEL_DBL: return {ix.models, (C + 1) * 3 * 8, 4};
+    case LIDER_X_LEAVES: return {ix.leaves, nleaf * 2 * 8, 0};
+    case LIDER_X_LEAF_ERR: return {ix.leaf_err, nleaf * 2 * 4, 0};
+    case LIDER_X_REORDERED: return {ix.X, n * d * 4, 0};
+    default: return {nullptr, 0, 0};
+  }
+}
+}  // namespace
+
+size_t lider_export_bytes(const lider_index* index, int32_t what) {
+  if (!index) return 0;
+  return export_src(index->ix, what).bytes;
+}
+
+int lider_export(const lider_index* index, int32_t what, void* dst_host, size_t dst_bytes) {
+  g_err.clear();
+  if (!index || !dst_host) return set_error(LIDER_EINVAL, "NULL argument");
+  const Index& ix = index->ix;
+  const ExportSrc src = export_src(ix, what);
+  if (!src.dev) return set_error(LIDER_EINVAL, "unknown export");
+  if (dst_bytes < src.bytes) return set_error(LIDER_EINVAL, "destination too small");
+  if (src.kind == 0)
+    return check_hip(hipMemcpy(dst_host, src.dev, src.bytes, hipMemcpyDeviceToHost), "export");
+  std::vector<Model> M(size_t(ix.C) + 1);
+  int rc = check_hip(hipMemcpy(M.data(), ix.models, M.size() * sizeof(Model), hipMemcpyDeviceToHost),
+                     "export models");
+  if (rc != LIDER_OK) return rc;
+  for (size_t j = 0; j < M.size(); ++j) {
+    if (src.kind == 1) {
+      int64_t* o = static_cast<int64_t*>(dst_host) + 3 * j;
+      o[0] = M[j].L;
+      o[1] = M[j].m_eff;
+      o[2] = M[j].F;
+    } else if (src.kind == 2) {
+      int32_t* o = static_cast<int32_t*>(dst_host) + 2 * ix.m * j;
+      for (int i = 0; i < ix.m; ++i) {
+        o[i] = M[j].mins[i];
+        o[ix.m + i] = M[j].maxs[i];
+      }
+    } else if (src.kind == 3) {
+      uint64_t* o = static_cast<uint64_t*>(dst_host) + 2 * j;
+      o[0] = M[j].kmin;
+      o[1] = M[j].kmax;
+    } else {
+      double* o = static_cast<double*>(dst_host) + 3 * j;
+      o[0] = M[j].scale;
+      o[1] = M[j].root_a;
+      o[2] = M[j].root_b;
+    }
+  }
+  return LIDER_OK;
+}
+
+// ------------------------------------------------------- stand-alone kernels
+int lider_hash(const float* X_dev, int64_t n, int32_t d, const float* A_dev, const float* b_dev,
+               int32_t nh, double w, int32_t* out_dev, void* stream) {
+  g_err.clear();
+  if (!X_dev || !A_dev || !b_dev || !out_dev) return set_error(LIDER_EINVAL, "NULL argument");
+  if (n < 0 || d < 1 || nh < 1 || nh > 32 || !(w > 0.0))
+    return set_error(LIDER_EINVAL, "bad size argument");
+  if (n == 0) return LIDER_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* anorm = nullptr;
+  int64_t* list = nullptr;
+  int32_t* cs = nullptr;
+  int rc = alloc(&anorm, size_t(nh), "norms");
+  if (rc == LIDER_OK) rc = alloc(&list, size_t(n) * nh, "hash list");
+  if (rc == LIDER_OK) rc = alloc(&cs, 64, "counters");
+  if (rc == LIDER_OK) rc = check_hip(hipMemsetAsync(cs, 0, 256, st), "zero");
+  if (rc == LIDER_OK) {
+    launch_norm_bounds(A_dev, nh, d, anorm, st);
+    rc = run_hash_ex(X_dev, n, d, A_dev, b_dev, anorm, nh, w, out_dev, list, cs, cs + 1, 0,
+                     nullptr, st);
+  }
+  int32_t h_status = 0;
+  if (rc == LIDER_OK)
+    rc = check_hip(hipMemcpyAsync(&h_status, cs + 1, 4, hipMemcpyDeviceToHost, st), "status");
+  if (rc == LIDER_OK) rc = check_hip(hipStreamSynchronize(st), "hash");
+  if (rc == LIDER_OK && h_status) rc = set_error(LIDER_ERANGE, "a hash value does not fit in int32");
+  if (anorm) (void)hipFree(anorm);
+  if (list) (void)hipFree(list);
+  if (cs) (void)hipFree(cs);
+  return rc;
+}
+
+int lider_kmeans_assign(const float* X_dev, int64_t n, int32_t d, const float* cent_dev,
+                        int32_t C, int32_t* assign_dev, void* stream) {
+  g_err.clear();
+  if (!X_dev || !cent_dev || !assign_dev) return set_error(LIDER_EINVAL, "NULL argument");
+  if (n < 0 || d < 1 || C < 1) return set_error(LIDER_EINVAL, "bad size argument");
+  if (n == 0) return LIDER_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  void* scr = nullptr;
+  int32_t* changed = nullptr;
+  int rc = LIDER_OK;
+  if (hipMalloc(&scr, kmeans_assign_scratch(n, C)) != hipSuccess)
+    rc = set_error(LIDER_ENOMEM, "out of device memory (k-means scratch)");
+  if (rc == LIDER_OK) rc = alloc(&changed, 64, "counter");
+  if (rc == LIDER_OK) rc = check_hip(hipMemsetAsync(changed, 0, 256, st), "zero");
+  if (rc == LIDER_OK)
+    rc = run_kmeans_assign(X_dev, n, d, cent_dev, C, assign_dev, nullptr, changed, scr, st);
+  if (rc == LIDER_OK) rc = check_hip(hipStreamSynchronize(st), "k-means assignment");
+  if (scr) (void)hipFree(scr);
+  if (changed) (void)hipFree(changed);
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+// E2LSH projection digits h_i(x) = floor((a_i . x + b_i) / w) (Section 4; the
+// integer-valued base hash under SK-LSH's element-wise order, Section 4.2).
+//
+// The projection [rows x d] . [d x nh] runs on fp32 MFMA (v_mfma_f32_16x16x4f32,
+// one wave = 16 rows x 16 hashes).  The digit is an integer decided by a
+// floating-point value, so it must equal the FP64 definition exactly: a
+// projection whose fp32 value lies within a rigorous rounding-error band of a
+// bucket edge is queued and recomputed by a sequential FP64 dot product in
+// dimension order (fp32 products are exact in FP64, so FMA or not, every
+// rounding matches the definition).
+#include "lider_internal.hpp"
+
+namespace lider {
+
+// Projection kernel.  Block = 4 waves = 64 rows; lane l of a wave owns row /
+// hash (l % 16) and the dimension slot s = l / 16: for each 16-dimension step
+// the lane loads 4 consecutive dims [k0 + 4s, k0 + 4s + 4) of its row and of
+// its hash vector and feeds them to 4 MFMAs (the k index of an MFMA only needs
+// to map to the same dimension on both operands).
+template <bool VEC>
+__global__ __launch_bounds__(256) void hash_kernel(
+    const float* __restrict__ X, int64_t n, int32_t d, const float* __restrict__ A,
+    const float* __restrict__ bvec, const float* __restrict__ anorm, int32_t nh, double w,
+    int32_t* __restrict__ out, int64_t* __restrict__ list, int32_t* __restrict__ counter,
+    int32_t* __restrict__ status, int clamp, float* __restrict__ rownorm) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, s = lane >> 4;
+  const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
+  if (row0 >= n) return;
+  int64_t myrow = row0 + i;
+  if (myrow >= n) myrow = n - 1;  // keep loads in bounds; outputs are skipped
+  const float* xr = X + myrow * d;
+  const int h0 = i < nh ? i : nh - 1;
+  const int h1 = 16 + i < nh ? 16 + i : nh - 1;
+  const float* a0 = A + int64_t(h0) * d;
+  const float* a1 = A + int64_t(h1) * d;
+  const bool two = nh > 16;
+  floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  float ss = 0.f;
+  const int dfull = VEC ? (d & ~15) : 0;
+  for (int k0 = 0; k0 < dfull; k0 += 16) {
+    const int kk = k0 + 4 * s;
+    float4 xv = *reinterpret_cast<const float4*>(xr + kk);
+    float4 av = *reinterpret_cast<const float4*>(a0 + kk);
+    ss += xv.x * xv.x + xv.y * xv.y + xv.z * xv.z + xv.w * xv.w;
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, av.x, acc0, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, av.y, acc0, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, av.z, acc0, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, av.w, acc0, 0, 0, 0);
+    if (two) {
+      float4 bv = *reinterpret_cast<const float4*>(a1 + kk);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, bv.x, acc1, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, bv.y, acc1, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, bv.z, acc1, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, bv.w, acc1, 0, 0, 0);
+    }
+  }
+  for (int k0 = dfull; k0 < d; k0 += 16) {  // tail (or everything when !VEC)
+    float xe[4], ae[4], be[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int kk = k0 + 4 * s + e;
+      const bool in = kk < d;
+      xe[e] = in ? xr[kk] : 0.f;
+      ae[e] = in ? a0[kk] : 0.f;
+      be[e] = in ? a1[kk] : 0.f;
+      ss += xe[e] * xe[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xe[e], ae[e], acc0, 0, 0, 0);
+      if (two) acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xe[e], be[e], acc1, 0, 0, 0);
+    }
+  }
+  // |x|^2 of row i: sum the four dimension slots
+  ss += __shfl_xor(ss, 16);
+  ss += __shfl_xor(ss, 32);
+  const double coef = dot_err_coef(d);
+  const double gam = double(d + 2) * 5.9604644775390625e-08;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int ri = 4 * s + e;
+    const float ssr = __shfl(ss, ri);
+    const int64_t row = row0 + ri;
+    const double xn = sqrt(double(ssr) * (1.0 + 2.0 * gam)) * (1.0 + 9.5367431640625e-07);
+    if (rownorm && i == 0 && row < n) rownorm[row] = float(xn * (1.0 + 9.5367431640625e-07));
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int hash = t * 16 + i;
+      if (row >= n || hash >= nh) continue;
+      const float sv = t == 0 ? acc0[e] : acc1[e];
+      const double tv = (double(sv) + double(bvec[hash])) / w;
+      const double E = (coef * double(anorm[hash]) * xn + double(d) * 7.888609052210118e-31) / w +
+                       8.881784197001252e-16 * fabs(tv);
+      const double fl = floor(tv);
+      const double fr = tv - fl;
+      const double dist = fr < 1.0 - fr ? fr : 1.0 - fr;
+      const int64_t o = row * nh + hash;
+      if (!(dist > 2.0 * E)) {
+        const int32_t slot = atomicAdd(counter, 1);
+        list[slot] = o;
+      } else if (fl >= -2147483648.0 && fl <= 2147483647.0) {
+        out[o] = int32_t(fl);
+      } else if (clamp) {
+        out[o] = fl < 0 ? INT32_MIN : INT32_MAX;
+      } else {
+        atomicExch(status, int32_t(LIDER_ERANGE));
+      }
+    }
+  }
+}
+
+// Sequential FP64 recompute of queued (row, hash) projections.
+__global__ __launch_bounds__(256) void hash_fixup_kernel(
+    const float* __restrict__ X, int32_t d, const float* __restrict__ A,
+    const float* __restrict__ bvec, int32_t nh, double w, int32_t* __restrict__ out,
+    const int64_t* __restrict__ list, const int32_t* __restrict__ counter,
+    int32_t* __restrict__ status, int clamp) {
+  const int32_t cnt = *counter;
+  for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+    const int64_t o = list[t];
+    const int64_t row = o / nh;
+    const int hash = int(o - row * nh);
+    const float* xr = X + row * d;
+    const float* ar = A + int64_t(hash) * d;
+    double sacc = 0.0;
+    for (int l = 0; l < d; ++l) sacc = sacc + double(ar[l]) * double(xr[l]);
+    const double tv = (sacc + double(bvec[hash])) / w;
+    const double fl = floor(tv);
+    if (fl >= -2147483648.0 && fl <= 2147483647.0) {
+      out[o] = int32_t(fl);
+    } else if (clamp) {
+      out[o] = fl < 0 ? INT32_MIN : INT32_MAX;
+    } else {
+      atomicExch(status, int32_t(LIDER_ERANGE));
+    }
+  }
+}
+
+// Upper bounds of row norms (FP64, rounded up into fp32).
+__global__ void norm_bound_kernel(const float* __restrict__ A, int32_t rows, int32_t d,
+                                  float* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  double s = 0.0;
+  for (int l = 0; l < d; ++l) s += double(A[int64_t(r) * d + l]) * double(A[int64_t(r) * d + l]);
+  out[r] = float(sqrt(s) * (1.0 + 9.5367431640625e-07));
+}
+
+__global__ void zero_i32_kernel(int32_t* p, int64_t cnt) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < cnt;
+       t += int64_t(gridDim.x) * blockDim.x)
+    p[t] = 0;
+}
+
+void launch_norm_bounds(const float* A, int32_t rows, int32_t d, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(norm_bound_kernel, dim3((rows + 63) / 64), dim3(64), 0, st, A, rows, d, out);
+}
+
+size_t hash_list_capacity(int64_t n, int32_t nh) { return size_t(n) * size_t(nh); }
+
+// Enqueue digits of n rows into out [n x nh].  list must hold n*nh int64;
+// counter and status are single device ints (zeroed here).  rownorm (nullable)
+// receives an upper bound of each row's norm.
+int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const float* b,
+                const float* anorm, int32_t nh, double w, int32_t* out, int64_t* list,
+                int32_t* counter, int32_t* status, int clamp, float* rownorm, hipStream_t st) {
+  if (n <= 0) return LIDER_OK;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, counter, int64_t(1));
+  const bool vec = (d % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  const dim3 grid(unsigned((n + 63) / 64));
+  if (vec)
+    hipLaunchKernelGGL(hash_kernel<true>, grid, dim3(256), 0, st, X, n, d, A, b, anorm, nh, w,
+                       out, list, counter, status, clamp, rownorm);
+  else
+    hipLaunchKernelGGL(hash_kernel<false>, grid, dim3(256), 0, st, X, n, d, A, b, anorm, nh, w,
+                       out, list, counter, status, clamp, rownorm);
+  int64_t cap = n * nh;
+  int64_t blocks = (cap + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(hash_fixup_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, X, d, A, b, nh,
+                     w, out, list, counter, status, clamp);
+  return check_hip(hipGetLastError(), "hash kernels");
+}
+
+}  // namespace lider

@@ -1,0 +1,200 @@
+// Internal declarations of the gfx950 LIDER library: the device-resident index,
+// the per-core-model parameter block, and the exact (non-contracted) FP64 key /
+// RMI arithmetic shared by build and search kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lider.h"
+
+namespace lider {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Parameters of one core model (Sections 3.1, 5): the digit box of its items,
+// the re-scaling of its keys (Eq. (8)) and its two-stage linear RMI.
+struct alignas(16) Model {
+  int64_t L;         // items indexed
+  int64_t leaf_off;  // first leaf of this model in the index's leaf arrays
+  uint64_t kmin, kmax;
+  double scale;      // (L-1)/(kmax-kmin), 0 if all keys are equal
+  double root_a, root_b;
+  int32_t m_eff;     // leading digits that enter the key (radix product <= 2^53)
+  int32_t F;         // second-stage width
+  int32_t mins[LIDER_MAX_M];
+  int32_t maxs[LIDER_MAX_M];
+};
+
+static constexpr uint64_t kKeyLimit = uint64_t(1) << 53;
+
+// Mixed-radix key of a data tuple over the model's digit box (Section 5.1
+// first step, generalised from binary digits to integer digits); digit 0 is
+// the most significant, so numeric order is the element-wise SK-LSH order.
+__host__ __device__ inline uint64_t encode_data(const int32_t* h, const Model& M) {
+  uint64_t K = 0;
+  for (int i = 0; i < M.m_eff; ++i) {
+    uint64_t R = uint64_t(int64_t(M.maxs[i]) - int64_t(M.mins[i]) + 1);
+    K = K * R + uint64_t(int64_t(h[i]) - int64_t(M.mins[i]));
+  }
+  return K;
+}
+
+// Key of a query tuple: digits outside the box saturate (below: this and all
+// later digits at their minima; above: at their maxima, plus one), giving the
+// count of box tuples lexicographically before the query.
+__host__ __device__ inline uint64_t encode_query(const int32_t* h, const Model& M) {
+  uint64_t K = 0;
+  for (int i = 0; i < M.m_eff; ++i) {
+    uint64_t R = uint64_t(int64_t(M.maxs[i]) - int64_t(M.mins[i]) + 1);
+    if (h[i] < M.mins[i]) {
+      for (; i < M.m_eff; ++i) K = K * uint64_t(int64_t(M.maxs[i]) - int64_t(M.mins[i]) + 1);
+      return K;
+    }
+    if (h[i] > M.maxs[i]) {
+      for (; i < M.m_eff; ++i) {
+        uint64_t Ri = uint64_t(int64_t(M.maxs[i]) - int64_t(M.mins[i]) + 1);
+        K = K * Ri + (Ri - 1);
+      }
+      return K + 1;
+    }
+    K = K * R + uint64_t(int64_t(h[i]) - int64_t(M.mins[i]));
+  }
+  return K;
+}
+
+// Eq. (8) with a = 0, b = L-1: exact integer difference, one rounding.
+__host__ __device__ inline double rescale(uint64_t K, const Model& M) {
+#pragma clang fp contract(off)
+  return double(int64_t(K) - int64_t(M.kmin)) * M.scale;
+}
+
+// Second-stage model owning the root's predicted share of [0, L).
+__host__ __device__ inline int32_t leaf_of(double ra, double rb, int32_t F, int64_t L, double x) {
+#pragma clang fp contract(off)
+  double p0 = ra * x + rb;
+  double v = (p0 * double(F)) / double(L);
+  if (!(v >= 0.0)) return 0;
+  if (v >= double(F)) return F - 1;
+  return int32_t(v);
+}
+
+// Predicted location: nearest integer, clamped to [0, L-1] (Section 7.4).
+__host__ __device__ inline int64_t pos_of(double la, double lb, int64_t L, double x) {
+#pragma clang fp contract(off)
+  if (L <= 0) return 0;
+  double p = la * x + lb;
+  double q = floor(p + 0.5);
+  if (!(q >= 0.0)) return 0;
+  if (q > double(L - 1)) return L - 1;
+  return int64_t(q);
+}
+
+// Fixed-length bi-directional window: floor(r/2) to the left, shifted inward at
+// the ends to keep min(r, L) positions.
+__host__ __device__ inline void window_of(int64_t pos, int64_t r, int64_t L, int64_t* start,
+                                          int64_t* len) {
+  int64_t lenv = r < L ? r : L;
+  int64_t hi = L - r > 0 ? L - r : 0;
+  int64_t s = pos - r / 2;
+  if (s > hi) s = hi;
+  if (s < 0) s = 0;
+  *start = s;
+  *len = lenv;
+}
+
+__device__ inline int64_t locate(const Model& M, const double* leaves, const int32_t* qd) {
+  if (M.L <= 0) return 0;
+  uint64_t K = encode_query(qd, M);
+  double x = rescale(K, M);
+  int32_t j = leaf_of(M.root_a, M.root_b, M.F, M.L, x);
+  const double* lf = leaves + 2 * (M.leaf_off + j);
+  return pos_of(lf[0], lf[1], M.L, x);
+}
+
+// Rigorous bound on |fl32(a.b) - a.b| for a length-d fp32 dot product summed in
+// any order (plus the FP64 reference's own rounding), per unit of |a||b|.
+__host__ __device__ inline double dot_err_coef(int d) {
+  return double(d + 2) * (5.9604644775390625e-08 /* 2^-24 */ + 2.220446049250313e-16);
+}
+
+// ----------------------------------------------------------------- the index
+struct Index {
+  int device = 0;
+  int64_t n = 0;
+  int32_t d = 0, C = 0, m = 0, F2 = 0, F1 = 0;
+  double w = 1.0;
+  int32_t iters_run = 0;
+  int64_t max_cluster = 0;
+  int32_t storage = LIDER_F32, centroid_storage = LIDER_F32;
+  int32_t n_cu = 256;
+
+  float* X = nullptr;          // [n x d] reordered by (cluster, key, id)
+  __hip_bfloat16* Xb = nullptr;  // [n x d] bf16 copy (precision form)
+  int64_t* perm = nullptr;     // [n] sorted position -> original id
+  int32_t* perm32 = nullptr;   // [n] same, int32
+  uint64_t* keys = nullptr;    // [n]
+  int32_t* digits = nullptr;   // [n x m] per original id
+  int32_t* assign = nullptr;   // [n] per original id
+  int64_t* off = nullptr;      // [C+1]
+  float* cent = nullptr;       // [C x d] cluster-id order
+  float* cent_l1 = nullptr;    // [C x d] layer-1 order
+  uint8_t* cent8 = nullptr;    // [C x d] fp8 e4m3, layer-1 order
+  float* cent8_scale = nullptr;  // [C]
+  int64_t* l1_order = nullptr;   // [C] layer-1 position -> cluster id
+  int32_t* l1_order32 = nullptr;
+  uint64_t* l1_keys = nullptr;
+  int32_t* l1_digits = nullptr;  // [C x m]
+  float* A = nullptr;          // [2m x d]
+  float* b = nullptr;          // [2m]
+  float* anorm = nullptr;      // [2m] upper bounds of |A_i|
+  float* cent_norm_max = nullptr;  // [1] upper bound of max |centroid|
+  Model* models = nullptr;     // [C+1], model C = layer 1
+  double* leaves = nullptr;    // [(C*F2 + F1) x 2]
+  int32_t* leaf_err = nullptr; // [(C*F2 + F1) x 2]
+  // rerank tiles: (cluster, first row) of every tile of tile_rows rows, one
+  // table per supported tile size (32, 64, 128)
+  int32_t n_tiles[3] = {0, 0, 0};
+  int32_t* tiles[3] = {nullptr, nullptr, nullptr};  // [n_tiles x 2]: cluster, row0 (in-cluster)
+  std::vector<int64_t> h_off;  // host copy of off
+};
+
+int set_error(int status, const std::string& msg);
+int check_hip(hipError_t e, const char* what);
+
+// ------------------------------------------------------------- build kernels
+// hash.hip
+int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const float* b,
+                const float* anorm, int32_t nh, double w, int32_t* out, int64_t* list,
+                int32_t* counter, int32_t* status, int clamp, float* rownorm, hipStream_t st);
+size_t hash_list_capacity(int64_t n, int32_t nh);
+void launch_norm_bounds(const float* A, int32_t rows, int32_t d, float* out, hipStream_t st);
+
+// kmeans.hip
+int run_kmeans(Index& ix, const float* X, const int64_t* init_host, int32_t iters,
+               hipStream_t st);
+int run_kmeans_assign(const float* X, int64_t n, int32_t d, const float* cent, int32_t C,
+                      int32_t* assign, const int32_t* prev, int32_t* changed, void* scratch,
+                      hipStream_t st);
+size_t kmeans_assign_scratch(int64_t n, int32_t C);
+int run_centroid_means(const float* X, int64_t n, int32_t d, const int32_t* assign, int32_t C,
+                       float* cent, void* scratch, size_t scratch_bytes, hipStream_t st);
+size_t centroid_means_scratch(int64_t n, int32_t C);
+
+// core_build.hip
+int build_core_models(Index& ix, const float* Xin, hipStream_t st);
+
+// search.hip
+size_t search_workspace(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
+                        const lider_search_opts& o);
+int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c, int32_t r,
+               int64_t* ids, float* scores, void* ws, size_t ws_bytes, hipStream_t st,
+               const lider_search_opts& o, const lider_search_debug* dbg);
+
+}  // namespace lider

@@ -1,0 +1,961 @@
+// Batched LIDER search (Section 3.3.2) on gfx950.
+//
+//   1. E2LSH digits of every query for both layers (fp32 MFMA + FP64 edge
+//      recompute, hash.hip).
+//   2. Centroids retriever: key, RMI location, window of r1 centroids in its
+//      sorted order (contiguous rows of the layer-1-ordered centroid copy).
+//   3. Routing: inner products with the window centroids, top c clusters.  The
+//      set of routed clusters is decided in FP64 (an fp32 near-tie at the c-th
+//      place triggers a sequential FP64 rescoring of the window).
+//   4. In-cluster retrievers: per (query, routed cluster) pair the key, RMI
+//      location and window of r rows; pairs are grouped by cluster.
+//   5. Rerank (where the time goes): cluster-major; one workgroup per tile of
+//      consecutive rows of one cluster (rows are stored in sorted order, so a
+//      window is a contiguous slab) scores the tile against every pair whose
+//      window overlaps it with fp32 (or bf16) MFMA, writing each pair's window
+//      scores.  Optionally persistent over the tile list.
+//   6. Per query, top k over the union of its windows (score desc, id asc)
+//      with a radix select + bitonic sort in LDS (Section 6.2's final merge).
+#include <hip/hip_fp8.h>
+
+#include <algorithm>
+
+#include "lider_internal.hpp"
+
+namespace lider {
+
+int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const float* b,
+                const float* anorm, int32_t nh, double w, int32_t* out, int64_t* list,
+                int32_t* counter, int32_t* status, int clamp, float* rownorm, hipStream_t st);
+
+namespace {
+
+inline size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct alignas(16) Pair {
+  int32_t j, s, len, pos;
+};
+
+// Counters block layout (int32): [0] hash list count, [1] status,
+// [8..15] per-XCD tile counters of the persistent rerank.
+constexpr int kCtrWords = 64;
+
+struct Plan {
+  size_t o_ctr, o_qdig, o_hlist, o_qnorm, o_l1, o_rs, o_rs64, o_routed, o_pairs, o_ccount,
+      o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, total;
+  int32_t r1, rcap, S;
+};
+
+Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
+               const lider_search_opts& o) {
+  Plan p;
+  const int32_t r1 = int32_t(std::min<int64_t>(o.r1 > 0 ? o.r1 : r, ix.C));
+  const int32_t rcap = int32_t(std::max<int64_t>(1, std::min<int64_t>(r, ix.max_cluster)));
+  const int32_t mult = o.shortlist_mult > 0 ? o.shortlist_mult : 4;
+  const int32_t S = o.precision == LIDER_BF16 ? std::min(4096, mult * k) : 0;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += al256(bytes);
+    return at;
+  };
+  p.o_ctr = take(kCtrWords * 4);
+  p.o_qdig = take(size_t(nq) * 2 * ix.m * 4);
+  p.o_hlist = take(size_t(nq) * 2 * ix.m * 8);
+  p.o_qnorm = take(size_t(nq) * 4);
+  p.o_l1 = take(size_t(nq) * 3 * 4);
+  p.o_rs = take(size_t(nq) * r1 * 4);
+  p.o_rs64 = take(size_t(nq) * r1 * 8);
+  p.o_routed = take(size_t(nq) * c * 4);
+  p.o_pairs = take(size_t(nq) * c * sizeof(Pair));
+  p.o_ccount = take(size_t(ix.C) * 4);
+  p.o_cstart = take((size_t(ix.C) + 1) * 4);
+  p.o_cfill = take(size_t(ix.C) * 4);
+  p.o_wl = take(size_t(nq) * c * 4);
+  p.o_sbuf = take(size_t(nq) * c * rcap * 4);
+  p.o_qb = take(S ? size_t(nq) * ix.d * 2 : 0);
+  p.o_slist = take(S ? size_t(nq) * S * 4 : 0);
+  p.total = off;
+  p.r1 = r1;
+  p.rcap = rcap;
+  p.S = S;
+  return p;
+}
+
+__global__ void zero_kernel(int32_t* p, int64_t cnt) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < cnt;
+       t += int64_t(gridDim.x) * blockDim.x)
+    p[t] = 0;
+}
+
+// ------------------------------------------------------------ select helpers
+// Sort key of a score: ascending key <=> descending score; -0 == +0; NaN last.
+__device__ inline uint32_t score_key(float f) {
+  if (f == 0.f) f = 0.f;
+  uint32_t b = __float_as_uint(f);
+  if (f != f) return 0xffffffffu;
+  uint32_t ord = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return ~ord;
+}
+__device__ inline float key_score(uint32_t key) {
+  uint32_t ord = ~key;
+  uint32_t b = (ord & 0x80000000u) ? (ord & 0x7fffffffu) : ~ord;
+  return __uint_as_float(b);
+}
+
+constexpr int kTieCap = 1024;
+
+struct SelShared {
+  uint32_t hist[256];
+  uint32_t prefix, mask, kneed;
+  int32_t cnt_less, cnt_tie;
+  uint32_t tie_id[kTieCap];
+  int32_t tie_idx[kTieCap];
+  uint32_t red_id[8];
+  int32_t red_idx[8];
+};
+
+// Block-wide selection of the K smallest (key, id) among n candidates (ids
+// unique).  Writes (key << 32 | id) and the candidate index into srt/idx,
+// sorted ascending, padded to KP (power of two >= K) with ~0.  Returns
+// min(n, K).  Radix select on the 32-bit key (4 passes of 8 bits), exact tie
+// handling by id, then a bitonic sort of the K winners.
+template <int NT, class KeyF, class IdF>
+__device__ int block_select(int n, int K, int KP, KeyF key_of, IdF id_of, uint64_t* srt,
+                            int32_t* idx, SelShared& sh) {
+  const int tid = threadIdx.x;
+  int outn;
+  if (n <= K) {
+    for (int i = tid; i < n; i += NT) {
+      srt[i] = (uint64_t(key_of(i)) << 32) | id_of(i);
+      idx[i] = i;
+    }
+    outn = n;
+  } else {
+    if (tid == 0) {
+      sh.prefix = 0;
+      sh.mask = 0;
+      sh.kneed = uint32_t(K);
+    }
+    for (int shift = 24; shift >= 0; shift -= 8) {
+      for (int b = tid; b < 256; b += NT) sh.hist[b] = 0;
+      __syncthreads();
+      const uint32_t pre = sh.prefix, msk = sh.mask;
+      for (int i = tid; i < n; i += NT) {
+        const uint32_t k = key_of(i);
+        if ((k & msk) == pre) atomicAdd(&sh.hist[(k >> shift) & 255u], 1u);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t cum = 0, need = sh.kneed;
+        for (int b = 0; b < 256; ++b) {
+          if (cum + sh.hist[b] >= need) {
+            sh.prefix |= uint32_t(b) << shift;
+            sh.mask |= 255u << shift;
+            sh.kneed = need - cum;
+            break;
+          }
+          cum += sh.hist[b];
+        }
+        sh.cnt_less = 0;
+        sh.cnt_tie = 0;
+      }
+      __syncthreads();
+    }
+    const uint32_t T = sh.prefix;
+    const int kneed = int(sh.kneed);
+    for (int i = tid; i < n; i += NT) {
+      const uint32_t k = key_of(i);
+      if (k < T) {
+        const int slot = atomicAdd(&sh.cnt_less, 1);
+        srt[slot] = (uint64_t(k) << 32) | id_of(i);
+        idx[slot] = i;
+      } else if (k == T) {
+        const int slot = atomicAdd(&sh.cnt_tie, 1);
+        if (slot < kTieCap) {
+          sh.tie_id[slot] = id_of(i);
+          sh.tie_idx[slot] = i;
+        }
+      }
+    }
+    __syncthreads();
+    const int base = K - kneed;
+    const int ntie = sh.cnt_tie;
+    if (ntie <= kTieCap) {
+      for (int t = tid; t < ntie; t += NT) {
+        const uint32_t myid = sh.tie_id[t];
+        int rank = 0;
+        for (int u = 0; u < ntie; ++u) rank += sh.tie_id[u] < myid;
+        if (rank < kneed) {
+          srt[base + rank] = (uint64_t(T) << 32) | myid;
+          idx[base + rank] = sh.tie_idx[t];
+        }
+      }
+    } else {
+      // many exactly equal scores: take the kneed smallest ids one at a time
+      uint32_t last = 0;
+      bool first = true;
+      for (int rsel = 0; rsel < kneed; ++rsel) {
+        uint32_t best = 0xffffffffu;
+        int bidx = -1;
+        for (int i = tid; i < n; i += NT) {
+          if (key_of(i) != T) continue;
+          const uint32_t id = id_of(i);
+          if ((first || id > last) && id < best) {
+            best = id;
+            bidx = i;
+          }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          const uint32_t ob = __shfl_xor(best, o);
+          const int oi = __shfl_xor(bidx, o);
+          if (ob < best) {
+            best = ob;
+            bidx = oi;
+          }
+        }
+        if ((tid & 63) == 0) {
+          sh.red_id[tid >> 6] = best;
+          sh.red_idx[tid >> 6] = bidx;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          for (int w = 1; w < NT / 64; ++w)
+            if (sh.red_id[w] < sh.red_id[0]) {
+              sh.red_id[0] = sh.red_id[w];
+              sh.red_idx[0] = sh.red_idx[w];
+            }
+          srt[base + rsel] = (uint64_t(T) << 32) | sh.red_id[0];
+          idx[base + rsel] = sh.red_idx[0];
+        }
+        __syncthreads();
+        last = sh.red_id[0];
+        first = false;
+        __syncthreads();
+      }
+    }
+    outn = K;
+  }
+  __syncthreads();
+  for (int i = outn + tid; i < KP; i += NT) {
+    srt[i] = ~uint64_t(0);
+    idx[i] = -1;
+  }
+  __syncthreads();
+  for (int kk = 2; kk <= KP; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < KP; i += NT) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const bool up = (i & kk) == 0;
+          const uint64_t a = srt[i], b = srt[ixj];
+          if ((a > b) == up) {
+            srt[i] = b;
+            srt[ixj] = a;
+            const int32_t t = idx[i];
+            idx[i] = idx[ixj];
+            idx[ixj] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  return outn;
+}
+
+__host__ __device__ inline int pow2_at_least(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// ------------------------------------------------------------ layer 1
+__global__ void l1_kernel(const Model* __restrict__ models, const double* __restrict__ leaves,
+                          const int32_t* __restrict__ qdig, int32_t m, int64_t nq, int32_t C,
+                          int32_t r1, int32_t* __restrict__ l1) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const int64_t pos = locate(models[C], leaves, qdig + q * 2 * m);
+  int64_t s, len;
+  window_of(pos, r1, C, &s, &len);
+  l1[3 * q] = int32_t(pos);
+  l1[3 * q + 1] = int32_t(s);
+  l1[3 * q + 2] = int32_t(len);
+}
+
+// Decode one OCP fp8 e4m3 byte (exact in fp32).
+__device__ inline float e4m3_value(uint8_t v) {
+  const int e = (v >> 3) & 15, mnt = v & 7;
+  float a = e == 0 ? float(mnt) * 0.001953125f : ldexpf(1.f + float(mnt) * 0.125f, e - 7);
+  if (e == 15 && mnt == 7) a = __uint_as_float(0x7fc00000u);
+  return (v & 0x80) ? -a : a;
+}
+
+constexpr int kRouteNT = 256;
+
+// One workgroup per query: score the window centroids, pick the top c.
+// FP8 = precision form (per-row-scaled fp8 centroids, no FP64 decision).
+template <bool FP8>
+__global__ __launch_bounds__(kRouteNT) void route_kernel(
+    const float* __restrict__ Q, int32_t d, int64_t nq, const float* __restrict__ cent_l1,
+    const uint8_t* __restrict__ cent8, const float* __restrict__ cent8_scale,
+    const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
+    const float* __restrict__ qnorm, const float* __restrict__ cent_norm_max, int32_t c,
+    int32_t r1, float* __restrict__ rs, double* __restrict__ rs64, int32_t* __restrict__ routed) {
+  __shared__ SelShared sh;
+  __shared__ uint64_t srt[256];
+  __shared__ int32_t sidx[256];
+  __shared__ int s_amb;
+  __shared__ double rd[kRouteNT];
+  __shared__ int32_t ri[kRouteNT];
+  __shared__ int32_t rp[kRouteNT];
+  __shared__ int32_t chosen[LIDER_MAX_C];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    const float* qv = Q + q * d;
+    const int32_t s1 = l1[3 * q + 1], len1 = l1[3 * q + 2];
+    float* rsq = rs + q * r1;
+    for (int p = wave; p < len1; p += kRouteNT / 64) {
+      float acc = 0.f;
+      if (FP8) {
+        const uint8_t* mu = cent8 + int64_t(s1 + p) * d;
+        for (int l = lane; l < d; l += 64) acc += qv[l] * e4m3_value(mu[l]);
+      } else {
+        const float* mu = cent_l1 + int64_t(s1 + p) * d;
+        for (int l = lane; l < d; l += 64) acc += qv[l] * mu[l];
+      }
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (lane == 0) rsq[p] = FP8 ? acc * cent8_scale[s1 + p] : acc;
+    }
+    __syncthreads();
+    const int K = min(c + 1, len1);
+    const int KP = pow2_at_least(K);
+    block_select<kRouteNT>(
+        len1, K, KP, [&](int i) { return score_key(rsq[i]); },
+        [&](int i) { return uint32_t(l1_order32[s1 + i]); }, srt, sidx, sh);
+    if (tid == 0) {
+      s_amb = 0;
+      if (!FP8 && len1 > c) {
+        const double E = dot_err_coef(d) * double(qnorm[q]) * double(*cent_norm_max) +
+                         double(d) * 7.888609052210118e-31;
+        const double sc = double(key_score(uint32_t(srt[c - 1] >> 32)));
+        const double sn = double(key_score(uint32_t(srt[c] >> 32)));
+        s_amb = (sc - sn) <= 4.0 * E;
+      }
+    }
+    __syncthreads();
+    if (!s_amb) {
+      for (int t = tid; t < c; t += kRouteNT)
+        routed[q * c + t] = t < len1 ? int32_t(srt[t] & 0xffffffffu) : -1;
+    } else {
+      // FP64 decision: sequential FP64 inner products of every window centroid,
+      // then c rounds of (score desc, cluster id asc) selection.
+      double* r64 = rs64 + q * r1;
+      for (int p = tid; p < len1; p += kRouteNT) {
+        const float* mu = cent_l1 + int64_t(s1 + p) * d;
+        double acc = 0.0;
+        for (int l = 0; l < d; ++l) acc = acc + double(qv[l]) * double(mu[l]);
+        r64[p] = acc;
+      }
+      __syncthreads();
+      for (int t = 0; t < c; ++t) {
+        double bd = -INFINITY;
+        int32_t bi = 0x7fffffff, bp = -1;
+        for (int p = tid; p < len1; p += kRouteNT) {
+          const double v = r64[p];
+          const int32_t id = l1_order32[s1 + p];
+          if (bp < 0 || v > bd || (v == bd && id < bi)) {
+            if (v == -INFINITY && bp >= 0) continue;
+            bd = v;
+            bi = id;
+            bp = p;
+          }
+        }
+        rd[tid] = bd;
+        ri[tid] = bi;
+        rp[tid] = bp;
+        __syncthreads();
+        for (int o = kRouteNT / 2; o > 0; o >>= 1) {
+          if (tid < o) {
+            const double ov = rd[tid + o];
+            const int32_t oi = ri[tid + o], op = rp[tid + o];
+            const bool better = op >= 0 && (rp[tid] < 0 || ov > rd[tid] || (ov == rd[tid] && oi < ri[tid]));
+            if (better) {
+              rd[tid] = ov;
+              ri[tid] = oi;
+              rp[tid] = op;
+            }
+          }
+          __syncthreads();
+        }
+        if (tid == 0) {
+          chosen[t] = ri[0];
+          r64[rp[0]] = -INFINITY;
+        }
+        __syncthreads();
+      }
+      for (int t = tid; t < c; t += kRouteNT) routed[q * c + t] = chosen[t];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ layer 2 pairs
+__global__ void pairs_kernel(const Model* __restrict__ models, const double* __restrict__ leaves,
+                             const int32_t* __restrict__ qdig, int32_t m, int64_t np, int32_t c,
+                             int32_t r, const int32_t* __restrict__ routed, Pair* __restrict__ pairs,
+                             int32_t* __restrict__ ccount) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= np) return;
+  const int64_t q = t / c;
+  const int32_t j = routed[t];
+  Pair pr{-1, 0, 0, 0};
+  if (j >= 0) {
+    const Model& M = models[j];
+    const int64_t pos = locate(M, leaves, qdig + q * 2 * m + m);
+    int64_t s, len;
+    window_of(pos, r, M.L, &s, &len);
+    pr = Pair{j, int32_t(s), int32_t(len), int32_t(pos)};
+    if (len > 0) atomicAdd(&ccount[j], 1);
+  }
+  pairs[t] = pr;
+}
+
+// Exclusive scan of per-cluster pair counts (single workgroup).
+__global__ __launch_bounds__(1024) void scan_kernel(const int32_t* __restrict__ cnt, int32_t C,
+                                                    int32_t* __restrict__ start) {
+  __shared__ int32_t part[1024];
+  const int tid = threadIdx.x;
+  const int per = (C + 1023) / 1024;
+  const int a = tid * per, e = min(C, a + per);
+  int32_t s = 0;
+  for (int i = a; i < e; ++i) s += cnt[i];
+  part[tid] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int32_t v = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int32_t run = tid ? part[tid - 1] : 0;
+  for (int i = a; i < e; ++i) {
+    start[i] = run;
+    run += cnt[i];
+  }
+  if (tid == 1023) start[C] = part[1023];
+}
+
+__global__ void scatter_kernel(const Pair* __restrict__ pairs, int64_t np,
+                               const int32_t* __restrict__ start, int32_t* __restrict__ fill,
+                               int32_t* __restrict__ wl) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= np) return;
+  const Pair pr = pairs[t];
+  if (pr.j < 0 || pr.len <= 0) return;
+  wl[start[pr.j] + atomicAdd(&fill[pr.j], 1)] = int32_t(t);
+}
+
+// ------------------------------------------------------------ rerank
+constexpr int kPairCap = 256;
+
+struct TileShared {
+  int32_t lp[kPairCap], lq[kPairCap], ls[kPairCap], le[kPairCap];
+  int32_t cnt;
+  int32_t tile;
+};
+
+// Tile fetch: direct XCD-aware mapping of blockIdx (workgroups are dealt to the
+// 8 XCDs round-robin; a contiguous run of tiles -- the same clusters, the same
+// query rows -- goes to one XCD and its L2), or a persistent loop over per-XCD
+// atomic counters with stealing.
+__device__ inline int32_t next_tile(int persistent, int32_t ntiles, int32_t* __restrict__ ctr,
+                                    int32_t& state, TileShared& sh) {
+  const int32_t per = (ntiles + 7) / 8;
+  if (!persistent) {
+    if (state) return -1;
+    state = 1;
+    const int32_t xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
+    const int32_t t = xcd * per + loc;
+    return (loc < per && t < ntiles) ? t : -1;
+  }
+  if (threadIdx.x == 0) {
+    int32_t res = -1;
+    const int32_t home = blockIdx.x & 7;
+    for (int v = state; v < 8 && res < 0; ++v) {
+      const int32_t x = (home + v) & 7;
+      const int32_t lo = x * per, hi = min(ntiles, lo + per);
+      if (lo >= hi) {
+        state = v + 1;
+        continue;
+      }
+      const int32_t t = atomicAdd(&ctr[x], 1);
+      if (lo + t < hi) {
+        res = lo + t;
+      } else {
+        state = v + 1;
+      }
+    }
+    sh.tile = res;
+  }
+  __syncthreads();
+  const int32_t t = sh.tile;
+  __syncthreads();
+  return t;
+}
+
+// fp32 rerank.  RT rows per tile, RT/16 waves (wave w owns rows 16w..16w+15
+// of the tile), pairs in passes of 16: D[16 pairs x 16 rows] += Q . X^T on
+// v_mfma_f32_16x16x4f32, 4 MFMAs per float4 of both operands.
+template <int RT, bool VEC>
+__global__ __launch_bounds__(RT * 4) void score_f32_kernel(
+    const float* __restrict__ X, int32_t d, const int64_t* __restrict__ off,
+    const int32_t* __restrict__ tiles, int32_t ntiles, const int32_t* __restrict__ cstart,
+    const int32_t* __restrict__ wl, const Pair* __restrict__ pairs, int32_t c,
+    const float* __restrict__ Q, float* __restrict__ sbuf, int32_t rcap, int persistent,
+    int32_t* __restrict__ ctr) {
+  __shared__ TileShared sh;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, s = lane >> 4;
+  int32_t state = 0;
+  for (;;) {
+    const int32_t tile = next_tile(persistent, ntiles, ctr, state, sh);
+    if (tile < 0) break;
+    const int32_t j = tiles[2 * tile], row0 = tiles[2 * tile + 1];
+    const int64_t base = off[j];
+    const int32_t L = int32_t(off[j + 1] - base);
+    const int32_t rows_here = min(RT, L - row0);
+    const int32_t plo = cstart[j], phi = cstart[j + 1];
+    for (int32_t pb = plo; pb < phi; pb += kPairCap) {
+      if (tid == 0) sh.cnt = 0;
+      __syncthreads();
+      const int32_t pe = min(phi, pb + kPairCap);
+      for (int32_t u = pb + tid; u < pe; u += RT * 4) {
+        const int32_t pi = wl[u];
+        const Pair pr = pairs[pi];
+        if (pr.s < row0 + rows_here && pr.s + pr.len > row0) {
+          const int32_t slot = atomicAdd(&sh.cnt, 1);
+          sh.lp[slot] = pi;
+          sh.lq[slot] = pi / c;
+          sh.ls[slot] = pr.s;
+          sh.le[slot] = pr.s + pr.len;
+        }
+      }
+      __syncthreads();
+      const int32_t P = sh.cnt;
+      const int32_t wr0 = row0 + 16 * wave;
+      if (wr0 < row0 + rows_here) {
+        const int32_t myrow = min(wr0 + i, row0 + rows_here - 1);
+        const float* xr = X + (base + myrow) * d;
+        for (int32_t c0 = 0; c0 < P; c0 += 16) {
+          const int32_t pq = min(c0 + i, P - 1);
+          const float* qr = Q + int64_t(sh.lq[pq]) * d;
+          floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+          const int dfull = VEC ? (d & ~15) : 0;
+          for (int k0 = 0; k0 < dfull; k0 += 16) {
+            const int kk = k0 + 4 * s;
+            const float4 qv = *reinterpret_cast<const float4*>(qr + kk);
+            const float4 xv = *reinterpret_cast<const float4*>(xr + kk);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(qv.x, xv.x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(qv.y, xv.y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(qv.z, xv.z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(qv.w, xv.w, acc, 0, 0, 0);
+          }
+          for (int k0 = dfull; k0 < d; k0 += 16) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int kk = k0 + 4 * s + e;
+              const bool in = kk < d;
+              acc = __builtin_amdgcn_mfma_f32_16x16x4f32(in ? qr[kk] : 0.f, in ? xr[kk] : 0.f, acc,
+                                                         0, 0, 0);
+            }
+          }
+          const int32_t row = wr0 + i;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int32_t pp = c0 + 4 * s + e;
+            if (pp < P && row < row0 + rows_here && row >= sh.ls[pp] && row < sh.le[pp])
+              sbuf[int64_t(sh.lp[pp]) * rcap + (row - sh.ls[pp])] = acc[e];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// bf16 first pass of the precision form: v_mfma_f32_16x16x32_bf16, each lane
+// feeding 8 consecutive bf16 of its pair / row per MFMA.
+template <int RT>
+__global__ __launch_bounds__(RT * 4) void score_bf16_kernel(
+    const __hip_bfloat16* __restrict__ X, int32_t d, const int64_t* __restrict__ off,
+    const int32_t* __restrict__ tiles, int32_t ntiles, const int32_t* __restrict__ cstart,
+    const int32_t* __restrict__ wl, const Pair* __restrict__ pairs, int32_t c,
+    const __hip_bfloat16* __restrict__ Qb, float* __restrict__ sbuf, int32_t rcap, int persistent,
+    int32_t* __restrict__ ctr) {
+  __shared__ TileShared sh;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, s = lane >> 4;
+  int32_t state = 0;
+  for (;;) {
+    const int32_t tile = next_tile(persistent, ntiles, ctr, state, sh);
+    if (tile < 0) break;
+    const int32_t j = tiles[2 * tile], row0 = tiles[2 * tile + 1];
+    const int64_t base = off[j];
+    const int32_t L = int32_t(off[j + 1] - base);
+    const int32_t rows_here = min(RT, L - row0);
+    const int32_t plo = cstart[j], phi = cstart[j + 1];
+    for (int32_t pb = plo; pb < phi; pb += kPairCap) {
+      if (tid == 0) sh.cnt = 0;
+      __syncthreads();
+      const int32_t pe = min(phi, pb + kPairCap);
+      for (int32_t u = pb + tid; u < pe; u += RT * 4) {
+        const int32_t pi = wl[u];
+        const Pair pr = pairs[pi];
+        if (pr.s < row0 + rows_here && pr.s + pr.len > row0) {
+          const int32_t slot = atomicAdd(&sh.cnt, 1);
+          sh.lp[slot] = pi;
+          sh.lq[slot] = pi / c;
+          sh.ls[slot] = pr.s;
+          sh.le[slot] = pr.s + pr.len;
+        }
+      }
+      __syncthreads();
+      const int32_t P = sh.cnt;
+      const int32_t wr0 = row0 + 16 * wave;
+      if (wr0 < row0 + rows_here) {
+        const int32_t myrow = min(wr0 + i, row0 + rows_here - 1);
+        const __hip_bfloat16* xr = X + (base + myrow) * d;
+        for (int32_t c0 = 0; c0 < P; c0 += 16) {
+          const int32_t pq = min(c0 + i, P - 1);
+          const __hip_bfloat16* qr = Qb + int64_t(sh.lq[pq]) * d;
+          floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+          const int dfull = d & ~31;
+          for (int k0 = 0; k0 < dfull; k0 += 32) {
+            const int kk = k0 + 8 * s;
+            const bf16x8 qv = *reinterpret_cast<const bf16x8*>(qr + kk);
+            const bf16x8 xv = *reinterpret_cast<const bf16x8*>(xr + kk);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qv, xv, acc, 0, 0, 0);
+          }
+          for (int k0 = dfull; k0 < d; k0 += 32) {
+            bf16x8 qv, xv;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int kk = k0 + 8 * s + e;
+              const bool in = kk < d;
+              qv[e] = in ? __builtin_bit_cast(__bf16, qr[kk]) : (__bf16)0.f;
+              xv[e] = in ? __builtin_bit_cast(__bf16, xr[kk]) : (__bf16)0.f;
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qv, xv, acc, 0, 0, 0);
+          }
+          const int32_t row = wr0 + i;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int32_t pp = c0 + 4 * s + e;
+            if (pp < P && row < row0 + rows_here && row >= sh.ls[pp] && row < sh.le[pp])
+              sbuf[int64_t(sh.lp[pp]) * rcap + (row - sh.ls[pp])] = acc[e];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void to_bf16_kernel(const float* __restrict__ a, int64_t cnt,
+                               __hip_bfloat16* __restrict__ b) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < cnt;
+       t += int64_t(gridDim.x) * blockDim.x)
+    b[t] = __float2bfloat16(a[t]);
+}
+
+// ------------------------------------------------------------ final top-k
+constexpr int kSelNT = 256;
+constexpr int kKeyCache = 8192;
+
+struct CandView {
+  int32_t c;
+  const Pair* pr;     // the query's c pairs
+  const float* sb;    // its c score rows (stride rcap)
+  int32_t rcap;
+  int32_t start[LIDER_MAX_C + 1];
+};
+
+// Per query: top k (or a shortlist of S) over its windows.  MODE 0 = final
+// output; MODE 1 = shortlist of sorted-row indices for the fp32 rerank.
+template <int KPMAX, int MODE>
+__global__ __launch_bounds__(kSelNT) void select_kernel(
+    const Pair* __restrict__ pairs, const float* __restrict__ sbuf, int32_t rcap, int32_t c,
+    int64_t nq, int32_t K, const int64_t* __restrict__ off, const int32_t* __restrict__ perm32,
+    int64_t* __restrict__ ids, float* __restrict__ scores, int32_t kout,
+    int32_t* __restrict__ slist) {
+  __shared__ SelShared sh;
+  __shared__ uint64_t srt[KPMAX];
+  __shared__ int32_t sidx[KPMAX];
+  __shared__ uint32_t keys[kKeyCache];
+  __shared__ int32_t start[LIDER_MAX_C + 1];
+  __shared__ int32_t pj[LIDER_MAX_C], ps[LIDER_MAX_C];
+  const int tid = threadIdx.x;
+  for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    if (tid == 0) {
+      int32_t acc = 0;
+      for (int t = 0; t < c; ++t) {
+        const Pair pr = pairs[q * c + t];
+        start[t] = acc;
+        pj[t] = pr.j;
+        ps[t] = pr.s;
+        acc += pr.j >= 0 ? pr.len : 0;
+      }
+      start[c] = acc;
+    }
+    __syncthreads();
+    const int32_t n = start[c];
+    const float* sbq = sbuf + q * int64_t(c) * rcap;
+    auto slot_of = [&](int i) {
+      int lo = 0, hi = c;  // largest t with start[t] <= i
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= i)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      return lo;
+    };
+    const bool cached = n <= kKeyCache;
+    if (cached) {
+      for (int t = 0; t < c; ++t) {
+        const int32_t a = start[t], len = start[t + 1] - a;
+        for (int p = tid; p < len; p += kSelNT) keys[a + p] = score_key(sbq[int64_t(t) * rcap + p]);
+      }
+      __syncthreads();
+    }
+    auto key_of = [&](int i) {
+      if (cached) return keys[i];
+      const int t = slot_of(i);
+      return score_key(sbq[int64_t(t) * rcap + (i - start[t])]);
+    };
+    auto row_of = [&](int i) {
+      const int t = slot_of(i);
+      return off[pj[t]] + ps[t] + (i - start[t]);
+    };
+    auto id_of = [&](int i) { return uint32_t(perm32[row_of(i)]); };
+    const int KK = K;
+    const int KP = pow2_at_least(KK);
+    const int got = block_select<kSelNT>(n, KK, KP, key_of, id_of, srt, sidx, sh);
+    if (MODE == 0) {
+      for (int t = tid; t < kout; t += kSelNT) {
+        if (t < got) {
+          ids[q * kout + t] = int64_t(srt[t] & 0xffffffffu);
+          scores[q * kout + t] = key_score(uint32_t(srt[t] >> 32));
+        } else {
+          ids[q * kout + t] = -1;
+          scores[q * kout + t] = -INFINITY;
+        }
+      }
+    } else {
+      for (int t = tid; t < K; t += kSelNT)
+        slist[q * K + t] = t < got ? int32_t(row_of(sidx[t])) : -1;
+    }
+    __syncthreads();
+  }
+}
+
+// Precision form, second pass: exact fp32 inner products of the shortlisted
+// rows (from the fp32 copy), then the top k.  One workgroup per query; one
+// wave per row at a time, lanes over dimensions.
+template <int KPMAX>
+__global__ __launch_bounds__(kSelNT) void rerank_shortlist_kernel(
+    const float* __restrict__ X, int32_t d, const float* __restrict__ Q, int64_t nq,
+    const int32_t* __restrict__ slist, int32_t S, const int32_t* __restrict__ perm32, int32_t k,
+    int64_t* __restrict__ ids, float* __restrict__ scores) {
+  __shared__ SelShared sh;
+  __shared__ uint64_t srt[KPMAX];
+  __shared__ int32_t sidx[KPMAX];
+  __shared__ float sc[4096];
+  __shared__ int32_t rows[4096];
+  __shared__ int32_t s_n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+    for (int t = tid; t < S; t += kSelNT) {
+      const int32_t rw = slist[q * S + t];
+      rows[t] = rw;
+      if (rw >= 0) atomicMax(&s_n, t + 1);
+    }
+    __syncthreads();
+    const int n = s_n;
+    const float* qv = Q + q * d;
+    for (int t = wave; t < n; t += kSelNT / 64) {
+      const float* xr = X + int64_t(rows[t]) * d;
+      float acc = 0.f;
+      for (int l = lane; l < d; l += 64) acc += qv[l] * xr[l];
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (lane == 0) sc[t] = acc;
+    }
+    __syncthreads();
+    const int KP = pow2_at_least(k);
+    const int got = block_select<kSelNT>(
+        n, k, KP, [&](int i) { return score_key(sc[i]); },
+        [&](int i) { return uint32_t(perm32[rows[i]]); }, srt, sidx, sh);
+    for (int t = tid; t < k; t += kSelNT) {
+      if (t < got) {
+        ids[q * k + t] = int64_t(srt[t] & 0xffffffffu);
+        scores[q * k + t] = key_score(uint32_t(srt[t] >> 32));
+      } else {
+        ids[q * k + t] = -1;
+        scores[q * k + t] = -INFINITY;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ debug exports
+__global__ void debug_kernel(const int32_t* __restrict__ l1, const Pair* __restrict__ pairs,
+                             const int32_t* __restrict__ routed, int64_t nq, int32_t c,
+                             int64_t* __restrict__ l1o, int32_t* __restrict__ ro,
+                             int64_t* __restrict__ po) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < nq && l1o)
+    for (int u = 0; u < 3; ++u) l1o[3 * t + u] = l1[3 * t + u];
+  if (t < nq * c) {
+    if (ro) ro[t] = routed[t];
+    if (po) {
+      const Pair pr = pairs[t];
+      po[3 * t] = pr.j >= 0 ? pr.pos : 0;
+      po[3 * t + 1] = pr.j >= 0 ? pr.s : 0;
+      po[3 * t + 2] = pr.j >= 0 ? pr.len : 0;
+    }
+  }
+}
+
+template <int RT>
+void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, const int32_t* wl,
+                  const Pair* pairs, int32_t c, const float* Q, const __hip_bfloat16* Qb,
+                  float* sbuf, int32_t rcap, int persistent, int grid_mult, int32_t* ctr,
+                  hipStream_t st) {
+  const int32_t nt = ix.n_tiles[ti];
+  unsigned grid;
+  if (persistent)
+    grid = unsigned(std::max(8, ix.n_cu * grid_mult / 8 * 8));
+  else
+    grid = unsigned((nt + 7) / 8 * 8);
+  const bool vec = (ix.d % 4 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
+  if (bf16)
+    hipLaunchKernelGGL(score_bf16_kernel<RT>, dim3(grid), dim3(RT * 4), 0, st, ix.Xb, ix.d, ix.off,
+                       ix.tiles[ti], nt, cstart, wl, pairs, c, Qb, sbuf, rcap, persistent, ctr);
+  else if (vec)
+    hipLaunchKernelGGL((score_f32_kernel<RT, true>), dim3(grid), dim3(RT * 4), 0, st, ix.X, ix.d,
+                       ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c, Q, sbuf, rcap, persistent,
+                       ctr);
+  else
+    hipLaunchKernelGGL((score_f32_kernel<RT, false>), dim3(grid), dim3(RT * 4), 0, st, ix.X, ix.d,
+                       ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c, Q, sbuf, rcap, persistent,
+                       ctr);
+}
+
+}  // namespace
+
+size_t search_workspace(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
+                        const lider_search_opts& o) {
+  return make_plan(ix, nq, k, c, r, o).total;
+}
+
+int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c, int32_t r,
+               int64_t* ids, float* scores, void* ws, size_t ws_bytes, hipStream_t st,
+               const lider_search_opts& o, const lider_search_debug* dbg) {
+  const Plan p = make_plan(ix, nq, k, c, r, o);
+  if (ws_bytes < p.total)
+    return set_error(LIDER_EINVAL, "workspace too small: need " + std::to_string(p.total) +
+                                       " bytes, got " + std::to_string(ws_bytes));
+  char* W = static_cast<char*>(ws);
+  int32_t* ctr = reinterpret_cast<int32_t*>(W + p.o_ctr);
+  int32_t* qdig = reinterpret_cast<int32_t*>(W + p.o_qdig);
+  int64_t* hlist = reinterpret_cast<int64_t*>(W + p.o_hlist);
+  float* qnorm = reinterpret_cast<float*>(W + p.o_qnorm);
+  int32_t* l1 = reinterpret_cast<int32_t*>(W + p.o_l1);
+  float* rs = reinterpret_cast<float*>(W + p.o_rs);
+  double* rs64 = reinterpret_cast<double*>(W + p.o_rs64);
+  int32_t* routed = reinterpret_cast<int32_t*>(W + p.o_routed);
+  Pair* pairs = reinterpret_cast<Pair*>(W + p.o_pairs);
+  int32_t* ccount = reinterpret_cast<int32_t*>(W + p.o_ccount);
+  int32_t* cstart = reinterpret_cast<int32_t*>(W + p.o_cstart);
+  int32_t* cfill = reinterpret_cast<int32_t*>(W + p.o_cfill);
+  int32_t* wl = reinterpret_cast<int32_t*>(W + p.o_wl);
+  float* sbuf = reinterpret_cast<float*>(W + p.o_sbuf);
+  __hip_bfloat16* qb = reinterpret_cast<__hip_bfloat16*>(W + p.o_qb);
+  int32_t* slist = reinterpret_cast<int32_t*>(W + p.o_slist);
+  const int32_t m = ix.m, C = ix.C;
+  const int64_t np = nq * c;
+  const bool bf16 = o.precision == LIDER_BF16;
+
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, st, ctr, int64_t(kCtrWords));
+  hipLaunchKernelGGL(zero_kernel, dim3((C + 255) / 256), dim3(256), 0, st, ccount, int64_t(C));
+  hipLaunchKernelGGL(zero_kernel, dim3((C + 255) / 256), dim3(256), 0, st, cfill, int64_t(C));
+  int rc = run_hash_ex(Q, nq, ix.d, ix.A, ix.b, ix.anorm, 2 * m, ix.w, qdig, hlist, ctr, ctr + 1,
+                       1, qnorm, st);
+  if (rc != LIDER_OK) return rc;
+  hipLaunchKernelGGL(l1_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, st, ix.models,
+                     ix.leaves, qdig, m, nq, C, p.r1, l1);
+  const unsigned qgrid = unsigned(std::min<int64_t>(nq, 65535));
+  if (bf16 && ix.cent8)
+    hipLaunchKernelGGL(route_kernel<true>, dim3(qgrid), dim3(kRouteNT), 0, st, Q, ix.d, nq,
+                       ix.cent_l1, ix.cent8, ix.cent8_scale, ix.l1_order32, l1, qnorm,
+                       ix.cent_norm_max, c, p.r1, rs, rs64, routed);
+  else
+    hipLaunchKernelGGL(route_kernel<false>, dim3(qgrid), dim3(kRouteNT), 0, st, Q, ix.d, nq,
+                       ix.cent_l1, ix.cent8, ix.cent8_scale, ix.l1_order32, l1, qnorm,
+                       ix.cent_norm_max, c, p.r1, rs, rs64, routed);
+  hipLaunchKernelGGL(pairs_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, ix.models,
+                     ix.leaves, qdig, m, np, c, r, routed, pairs, ccount);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, ccount, C, cstart);
+  hipLaunchKernelGGL(scatter_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, pairs, np,
+                     cstart, cfill, wl);
+  if (bf16)
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(2048), dim3(256), 0, st, Q, nq * ix.d, qb);
+  const int tr = o.tile_rows == 32 ? 32 : o.tile_rows == 128 ? 128 : 64;
+  const int ti = tr == 32 ? 0 : tr == 64 ? 1 : 2;
+  const int gm = o.grid_mult > 0 ? o.grid_mult : 4;
+  if (tr == 32)
+    launch_score<32>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
+                     ctr + 8, st);
+  else if (tr == 64)
+    launch_score<64>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
+                     ctr + 8, st);
+  else
+    launch_score<128>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
+                      ctr + 8, st);
+  if (!bf16) {
+    if (k <= 128)
+      hipLaunchKernelGGL((select_kernel<128, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
+                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist);
+    else
+      hipLaunchKernelGGL((select_kernel<1024, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
+                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist);
+  } else {
+    if (p.S <= 512)
+      hipLaunchKernelGGL((select_kernel<512, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
+                         p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist);
+    else
+      hipLaunchKernelGGL((select_kernel<4096, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
+                         p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist);
+    if (k <= 128)
+      hipLaunchKernelGGL(rerank_shortlist_kernel<128>, dim3(qgrid), dim3(kSelNT), 0, st, ix.X,
+                         ix.d, Q, nq, slist, p.S, ix.perm32, k, ids, scores);
+    else
+      hipLaunchKernelGGL(rerank_shortlist_kernel<1024>, dim3(qgrid), dim3(kSelNT), 0, st, ix.X,
+                         ix.d, Q, nq, slist, p.S, ix.perm32, k, ids, scores);
+  }
+  if (dbg) {
+    if (dbg->qdigits_dev)
+      (void)hipMemcpyAsync(dbg->qdigits_dev, qdig, size_t(nq) * 2 * m * 4, hipMemcpyDeviceToDevice, st);
+    hipLaunchKernelGGL(debug_kernel, dim3(unsigned((np + 255) / 256 + 1)), dim3(256), 0, st, l1,
+                       pairs, routed, nq, c, dbg->l1_dev, dbg->routed_dev, dbg->pairs_dev);
+  }
+  return check_hip(hipGetLastError(), "search kernels");
+}
+
+}  // namespace lider

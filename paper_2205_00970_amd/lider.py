@@ -1,0 +1,269 @@
+"""Python binding of the gfx950 LIDER library (include/lider.h).
+
+Argument marshalling only: every step of build and search runs in the HIP
+library.  torch supplies device memory (tensors) and streams.  If the library
+is not built, every call raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libliderhip.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ERANGE, EBUSY = 0, -1, -2, -3, -4, -5
+F32, BF16, FP8E4M3 = 0, 1, 2
+MAX_K, MAX_C, MAX_M = 1024, 128, 16
+
+EXPORTS = {
+    "centroids": (0, np.float32), "assign": (1, np.int32), "offsets": (2, np.int64),
+    "perm": (3, np.int64), "keys": (4, np.uint64), "digits": (5, np.int32),
+    "l1_order": (6, np.int64), "l1_keys": (7, np.uint64), "l1_digits": (8, np.int32),
+    "model_int": (9, np.int64), "model_box": (10, np.int32), "model_key": (11, np.uint64),
+    "model_dbl": (12, np.float64), "leaves": (13, np.float64), "leaf_err": (14, np.int32),
+    "reordered": (15, np.float32),
+}
+
+
+class LiderError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lider status {status}: {msg}")
+        self.status = status
+
+
+class BuildParams(C.Structure):
+    _fields_ = [("n_clusters", C.c_int32), ("m", C.c_int32), ("rmi_fanout", C.c_int32),
+                ("rmi_fanout_l1", C.c_int32), ("w", C.c_double), ("lsh_a_host", C.c_void_p),
+                ("lsh_b_host", C.c_void_p), ("assignment_dev", C.c_void_p),
+                ("kmeans_init_host", C.c_void_p), ("kmeans_iters", C.c_int32),
+                ("storage", C.c_int32), ("centroid_storage", C.c_int32)]
+
+
+class SearchOpts(C.Structure):
+    _fields_ = [("r1", C.c_int32), ("precision", C.c_int32), ("shortlist_mult", C.c_int32),
+                ("persistent", C.c_int32), ("tile_rows", C.c_int32), ("pair_tile", C.c_int32),
+                ("grid_mult", C.c_int32), ("reserved", C.c_int32 * 9)]
+
+
+class SearchDebug(C.Structure):
+    _fields_ = [("qdigits_dev", C.c_void_p), ("l1_dev", C.c_void_p), ("routed_dev", C.c_void_p),
+                ("pairs_dev", C.c_void_p)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("n_clusters", C.c_int32), ("m", C.c_int32),
+                ("rmi_fanout", C.c_int32), ("rmi_fanout_l1", C.c_int32),
+                ("kmeans_iters_run", C.c_int32), ("max_cluster", C.c_int64), ("w", C.c_double),
+                ("storage", C.c_int32), ("centroid_storage", C.c_int32)]
+
+
+SYMBOLS = ["lider_build", "lider_free", "lider_last_error", "lider_search_workspace",
+           "lider_search", "lider_search_ex", "lider_get_info", "lider_export_bytes",
+           "lider_export", "lider_hash", "lider_kmeans_assign", "lider_debug_fail_next"]
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        p, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        L.lider_build.argtypes = [p, i64, i32, C.POINTER(BuildParams), p, C.POINTER(p)]
+        L.lider_free.argtypes = [p]
+        L.lider_free.restype = None
+        L.lider_last_error.restype = C.c_char_p
+        L.lider_search_workspace.argtypes = [p, i64, i32, i32, i32, C.POINTER(SearchOpts)]
+        L.lider_search_workspace.restype = sz
+        L.lider_search.argtypes = [p, p, i64, i32, i32, i32, p, p, p, sz, p]
+        L.lider_search_ex.argtypes = [p, p, i64, i32, i32, i32, p, p, p, sz, p,
+                                      C.POINTER(SearchOpts), C.POINTER(SearchDebug)]
+        L.lider_get_info.argtypes = [p, C.POINTER(Info)]
+        L.lider_export_bytes.argtypes = [p, i32]
+        L.lider_export_bytes.restype = sz
+        L.lider_export.argtypes = [p, i32, p, sz]
+        L.lider_hash.argtypes = [p, i64, i32, p, p, i32, C.c_double, p, p]
+        L.lider_kmeans_assign.argtypes = [p, i64, i32, p, i32, p, p]
+        L.lider_debug_fail_next.argtypes = [i32]
+        L.lider_debug_fail_next.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != OK:
+        raise LiderError(st, lib().lider_last_error().decode(errors="replace"))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, dtype, ndim=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _np_ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+_STORAGE = {"f32": F32, "bf16": BF16}
+_CSTORAGE = {"f32": F32, "fp8": FP8E4M3}
+_PREC = {"f32": F32, "bf16": BF16}
+
+
+class Index:
+    """A LIDER index resident in device memory (lider_build / lider_free)."""
+
+    def __init__(self, corpus, n_clusters, m, w, rmi_fanout, lsh, rmi_fanout_l1=0,
+                 kmeans_init=None, kmeans_iters=20, assignment=None, storage="f32",
+                 centroid_storage="f32", stream=None):
+        torch = _torch()
+        cp = _dev_ptr(corpus, torch.float32, 2, "corpus")
+        n, d = corpus.shape
+        A = np.ascontiguousarray(lsh[0], dtype=np.float32)
+        b = np.ascontiguousarray(lsh[1], dtype=np.float32)
+        if A.shape != (2 * m, d) or b.shape != (2 * m,):
+            raise ValueError("lsh must be (A [2m, d], b [2m])")
+        ini = None if kmeans_init is None else np.ascontiguousarray(kmeans_init, dtype=np.int64)
+        if assignment is None and (ini is None or ini.shape != (n_clusters,)):
+            raise ValueError("k-means needs kmeans_init of n_clusters row ids")
+        P = BuildParams(int(n_clusters), int(m), int(rmi_fanout), int(rmi_fanout_l1), float(w),
+                        _np_ptr(A), _np_ptr(b),
+                        None if assignment is None else _dev_ptr(assignment, torch.int32, 1,
+                                                                 "assignment"),
+                        _np_ptr(ini), int(kmeans_iters), _STORAGE[storage],
+                        _CSTORAGE[centroid_storage])
+        h = C.c_void_p()
+        _check(lib().lider_build(cp, n, d, C.byref(P), _stream(stream), C.byref(h)))
+        self._h = h
+        self._ws = None
+        self.n, self.d = int(n), int(d)
+        info = self.info()
+        self.C, self.m = info.n_clusters, info.m
+        self.F2, self.F1 = info.rmi_fanout, info.rmi_fanout_l1
+        self.max_cluster = info.max_cluster
+        self.iters_run = info.kmeans_iters_run
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().lider_free(self._h)
+            self._h = C.c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        out = Info()
+        _check(lib().lider_get_info(self._h, C.byref(out)))
+        return out
+
+    def export(self, what):
+        code, dt = EXPORTS[what]
+        nb = lib().lider_export_bytes(self._h, code)
+        out = np.empty(nb // np.dtype(dt).itemsize, dtype=dt)
+        _check(lib().lider_export(self._h, code, _np_ptr(out), nb))
+        return out
+
+    def workspace_bytes(self, nq, k, c, r, **opt):
+        o = self._opts(**opt)
+        return int(lib().lider_search_workspace(self._h, nq, k, c, r, C.byref(o)))
+
+    @staticmethod
+    def _opts(r1=0, precision="f32", shortlist_mult=0, persistent=False, tile_rows=0,
+              grid_mult=0):
+        o = SearchOpts()
+        o.r1, o.precision, o.shortlist_mult = int(r1), _PREC[precision], int(shortlist_mult)
+        o.persistent, o.tile_rows, o.grid_mult = int(bool(persistent)), int(tile_rows), int(grid_mult)
+        return o
+
+    def search(self, queries, k, c, r, r1=0, precision="f32", shortlist_mult=0,
+               persistent=False, tile_rows=0, grid_mult=0, debug=False, stream=None, ws=None,
+               out=None):
+        """Batched search; returns (ids int64 [nq,k], scores f32 [nq,k][, debug])."""
+        torch = _torch()
+        qp = _dev_ptr(queries, torch.float32, 2, "queries")
+        nq = queries.shape[0]
+        o = self._opts(r1, precision, shortlist_mult, persistent, tile_rows, grid_mult)
+        need = int(lib().lider_search_workspace(self._h, nq, k, c, r, C.byref(o)))
+        if need == 0 and nq > 0:
+            # invalid arguments: let lider_search_ex report which
+            _check(lib().lider_search_ex(self._h, qp, nq, k, c, r, None, None, None, 0,
+                                         _stream(stream), C.byref(o), None))
+        if ws is None:
+            if self._ws is None or self._ws.numel() < need:
+                self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=queries.device)
+            ws = self._ws
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int64, device=queries.device)
+            sc = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+        else:
+            ids, sc = out
+        dbg = None
+        dstruct = None
+        if debug:
+            dbg = dict(qdigits=torch.empty((nq, 2 * self.m), dtype=torch.int32, device=queries.device),
+                       l1=torch.empty((nq, 3), dtype=torch.int64, device=queries.device),
+                       routed=torch.empty((nq, c), dtype=torch.int32, device=queries.device),
+                       pairs=torch.empty((nq, c, 3), dtype=torch.int64, device=queries.device))
+            dstruct = SearchDebug(dbg["qdigits"].data_ptr(), dbg["l1"].data_ptr(),
+                                  dbg["routed"].data_ptr(), dbg["pairs"].data_ptr())
+        _check(lib().lider_search_ex(self._h, qp, nq, k, c, r, C.c_void_p(ids.data_ptr()),
+                                     C.c_void_p(sc.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                     ws.numel(), _stream(stream), C.byref(o),
+                                     C.byref(dstruct) if dstruct is not None else None))
+        return (ids, sc, dbg) if debug else (ids, sc)
+
+
+def hash(X, A, b, w, stream=None):
+    """E2LSH digits floor((A.x + b)/w) of X's rows (lider_hash)."""
+    torch = _torch()
+    xp = _dev_ptr(X, torch.float32, 2, "X")
+    ap = _dev_ptr(A, torch.float32, 2, "A")
+    bp = _dev_ptr(b, torch.float32, 1, "b")
+    out = torch.empty((X.shape[0], A.shape[0]), dtype=torch.int32, device=X.device)
+    _check(lib().lider_hash(xp, X.shape[0], X.shape[1], ap, bp, A.shape[0], float(w),
+                            C.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def kmeans_assign(X, cent, stream=None):
+    """One k-means assignment step, decided in FP64 (lider_kmeans_assign)."""
+    torch = _torch()
+    xp = _dev_ptr(X, torch.float32, 2, "X")
+    cp = _dev_ptr(cent, torch.float32, 2, "cent")
+    out = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
+    _check(lib().lider_kmeans_assign(xp, X.shape[0], X.shape[1], cp, cent.shape[0],
+                                     C.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def fail_next(status):
+    """Test hook: make the next search on this thread fail with `status`."""
+    lib().lider_debug_fail_next(int(status))

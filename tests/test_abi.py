@@ -1,0 +1,105 @@
+"""CPU checks of the C boundary: the built library exports every function
+include/lider.h declares, the binding's ctypes structs have the C layout, and
+argument validation rejects bad calls before touching a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2205_00970_amd import lider
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lider.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lider_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_binding_symbols():
+    assert declared_functions() == sorted(lider.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = C.CDLL(lider.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_struct_layouts_match_header():
+    prog = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "lider.h"
+#define P(T, f) printf("%s.%s %zu\n", #T, #f, offsetof(T, f));
+int main(void) {
+  printf("lider_build_params %zu\n", sizeof(lider_build_params));
+  P(lider_build_params, w) P(lider_build_params, lsh_a_host) P(lider_build_params, assignment_dev)
+  P(lider_build_params, kmeans_init_host) P(lider_build_params, kmeans_iters)
+  P(lider_build_params, centroid_storage)
+  printf("lider_search_opts %zu\n", sizeof(lider_search_opts));
+  P(lider_search_opts, grid_mult)
+  printf("lider_search_debug %zu\n", sizeof(lider_search_debug));
+  printf("lider_info %zu\n", sizeof(lider_info));
+  P(lider_info, max_cluster) P(lider_info, w) P(lider_info, centroid_storage)
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as td:
+        src = os.path.join(td, "layout.c")
+        exe = os.path.join(td, "layout")
+        open(src, "w").write(prog)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
+        out = dict(l.rsplit(" ", 1) for l in subprocess.check_output([exe]).decode().split("\n") if l)
+    py = {
+        "lider_build_params": C.sizeof(lider.BuildParams),
+        "lider_build_params.w": lider.BuildParams.w.offset,
+        "lider_build_params.lsh_a_host": lider.BuildParams.lsh_a_host.offset,
+        "lider_build_params.assignment_dev": lider.BuildParams.assignment_dev.offset,
+        "lider_build_params.kmeans_init_host": lider.BuildParams.kmeans_init_host.offset,
+        "lider_build_params.kmeans_iters": lider.BuildParams.kmeans_iters.offset,
+        "lider_build_params.centroid_storage": lider.BuildParams.centroid_storage.offset,
+        "lider_search_opts": C.sizeof(lider.SearchOpts),
+        "lider_search_opts.grid_mult": lider.SearchOpts.grid_mult.offset,
+        "lider_search_debug": C.sizeof(lider.SearchDebug),
+        "lider_info": C.sizeof(lider.Info),
+        "lider_info.max_cluster": lider.Info.max_cluster.offset,
+        "lider_info.w": lider.Info.w.offset,
+        "lider_info.centroid_storage": lider.Info.centroid_storage.offset,
+    }
+    for k, v in py.items():
+        assert int(out[k]) == v, k
+
+
+def test_validation_without_device():
+    L = lider.lib()
+    h = C.c_void_p()
+    P = lider.BuildParams()
+    assert L.lider_build(None, 10, 4, C.byref(P), None, C.byref(h)) == lider.EINVAL
+    assert b"NULL" in L.lider_last_error()
+    dummy = C.c_void_p(16)
+    P.n_clusters, P.m, P.rmi_fanout, P.w = 2, 0, 4, 1.0
+    assert L.lider_build(dummy, 10, 4, C.byref(P), None, C.byref(h)) == lider.EINVAL
+    assert b"m must be" in L.lider_last_error()
+    P.m, P.w = 4, -1.0
+    assert L.lider_build(dummy, 10, 4, C.byref(P), None, C.byref(h)) == lider.EINVAL
+    P.w, P.n_clusters = 1.0, 11
+    assert L.lider_build(dummy, 10, 4, C.byref(P), None, C.byref(h)) == lider.EINVAL
+    P.n_clusters = 2
+    assert L.lider_build(dummy, 10, 4, C.byref(P), None, C.byref(h)) == lider.EINVAL  # no LSH
+    assert not h.value
+    assert L.lider_search(None, dummy, 1, 10, 1, 1, dummy, dummy, dummy, 1 << 20, None) == lider.EINVAL
+    assert L.lider_search_workspace(None, 1, 10, 1, 1, None) == 0
+    L.lider_free(None)
+
+
+def test_fail_next_hook_precedes_validation():
+    L = lider.lib()
+    L.lider_debug_fail_next(lider.EBUSY)
+    assert L.lider_search(None, None, 0, 1, 1, 1, None, None, None, 0, None) == lider.EBUSY
+    assert L.lider_search(None, None, 0, 1, 1, 1, None, None, None, 0, None) == lider.EINVAL

@@ -1,0 +1,175 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  Integer results (digits, keys, orders, positions,
+routing sets, RMI parameters as bits) must be identical; ids and scores within
+the fp32 tolerance |d score| <= 1e-4 |q| |x|."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2205_00970_amd import datagen
+
+from parity_util import build_pair, compare_debug, compare_index, compare_topk
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    """The tiny mixture workload: N=20,000, d=128, 16 clusters, m=4, w=1,
+    RMI fanout 8, 100 queries; k-means from seeded initial ids."""
+    _torch()
+    X, lab, Q, src = datagen.tiny()
+    A, b = datagen.lsh_params(4, 128, 1.0)
+    init = datagen.kmeans_init(X.shape[0], 16)
+    gi, oi, Xd = build_pair(X, 16, 4, 1.0, 8, A, b, init_ids=init, iters=20)
+    return dict(X=X, Q=Q, gi=gi, oi=oi)
+
+
+def test_tiny_build_bit_exact(tiny):
+    compare_index(tiny["gi"], tiny["oi"])
+
+
+@pytest.mark.parametrize("k,c,r,r1", [(10, 4, 64, 0), (1, 1, 1, 0), (100, 4, 64, 8),
+                                       (10, 16, 5000, 16), (7, 3, 33, 5)])
+def test_tiny_search(tiny, k, c, r, r1):
+    torch = _torch()
+    X, Q, gi, oi = tiny["X"], tiny["Q"], tiny["gi"], tiny["oi"]
+    Qd = torch.from_numpy(Q).cuda()
+    ids, sc, dbg = gi.search(Qd, k, c, r, r1=r1, debug=True)
+    torch.cuda.synchronize()
+    oids, osc, odbg = oi.search(Q, k, c, r, r1 or None, debug=True)
+    compare_debug(dbg, odbg)
+    compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+
+
+def test_tiny_flat_special_case(tiny):
+    """All clusters, whole clusters, whole layer 1: exact (Flat) search."""
+    torch = _torch()
+    X, Q, gi = tiny["X"], tiny["Q"], tiny["gi"]
+    ids, sc = gi.search(torch.from_numpy(Q).cuda(), 10, 16, int(gi.max_cluster), r1=16)
+    bi, bs = oracle.bruteforce(X, Q, 10)
+    compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), bi, bs)
+
+
+@pytest.fixture(scope="module")
+def mid():
+    """768-d mixture of the 1M family at 60,000 rows, 64 clusters given by the
+    generator's labels (cluster 63 left empty), m=8, w=2, fanout 16 / 4."""
+    torch = _torch()
+    X, lab = datagen.mixture(60000, 768, ncomp=63, seed=5, device="cpu")
+    X = X.numpy()
+    lab = lab.numpy()
+    Qt, _ = datagen.queries_from(torch.from_numpy(X), 300, 0.1, seed=6)
+    Q = Qt.numpy()
+    A, b = datagen.lsh_params(8, 768, 2.0, seed=7)
+    gi, oi, Xd = build_pair(X, 64, 8, 2.0, 16, A, b, assignment=lab, F1=4)
+    return dict(X=X, Q=Q, gi=gi, oi=oi)
+
+
+def test_mid_build_bit_exact(mid):
+    compare_index(mid["gi"], mid["oi"])
+    assert mid["gi"].export("model_int").reshape(-1, 3)[63, 0] == 0  # the empty cluster
+
+
+@pytest.mark.parametrize("k,c,r,r1", [(10, 8, 256, 32), (100, 8, 256, 32), (10, 2, 2000, 64),
+                                       (1000, 16, 100, 20), (3, 1, 17, 1)])
+def test_mid_search(mid, k, c, r, r1):
+    torch = _torch()
+    X, Q, gi, oi = mid["X"], mid["Q"], mid["gi"], mid["oi"]
+    ids, sc, dbg = gi.search(torch.from_numpy(Q).cuda(), k, c, r, r1=r1, debug=True)
+    oids, osc, odbg = oi.search(Q, k, c, r, r1, debug=True)
+    compare_debug(dbg, odbg)
+    compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+
+
+def test_mid_schedules_identical(mid):
+    """Persistent and plain rerank, all tile sizes, sub-batches: bitwise equal."""
+    torch = _torch()
+    Qd = torch.from_numpy(mid["Q"]).cuda()
+    gi = mid["gi"]
+    ref = gi.search(Qd, 10, 8, 256, r1=32)
+    for kw in [dict(persistent=True), dict(tile_rows=32), dict(tile_rows=128),
+               dict(tile_rows=128, persistent=True, grid_mult=1), dict()]:
+        got = gi.search(Qd, 10, 8, 256, r1=32, **kw)
+        assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), kw
+    sub = gi.search(Qd[37:90].contiguous(), 10, 8, 256, r1=32)
+    assert torch.equal(sub[0], ref[0][37:90]) and torch.equal(sub[1], ref[1][37:90])
+
+
+@pytest.mark.parametrize("d", [100, 130])
+def test_odd_dimensions(d):
+    """d not a multiple of 16 (MFMA tail) and not a multiple of 4 (scalar path)."""
+    torch = _torch()
+    X, lab, Q, src = datagen.tiny(n=3000, d=d, ncomp=6, nq=40, seed=8, qseed=9)
+    A, b = datagen.lsh_params(3, d, 1.5, seed=10)
+    init = datagen.kmeans_init(3000, 6, seed=11)
+    gi, oi, _ = build_pair(X, 6, 3, 1.5, 4, A, b, init_ids=init, iters=10)
+    compare_index(gi, oi)
+    ids, sc, dbg = gi.search(torch.from_numpy(Q).cuda(), 5, 2, 40, r1=3, debug=True)
+    oids, osc, odbg = oi.search(Q, 5, 2, 40, 3, debug=True)
+    compare_debug(dbg, odbg)
+    compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+
+
+def test_hash_near_bucket_edges():
+    """Projections placed within 1e-7 of bucket edges take the FP64 path and
+    still equal the FP64 definition."""
+    torch = _torch()
+    from paper_2205_00970_amd import lider
+    g = np.random.default_rng(12)
+    d, nh, w = 768, 16, 2.0
+    A = g.standard_normal((nh, d)).astype(np.float32)
+    b = (g.random(nh) * w).astype(np.float32)
+    X = g.standard_normal((4096, d)).astype(np.float32)
+    # shift each row along A[0] so that a_0.x + b_0 lands near an edge
+    t = (X.astype(np.float64) @ A[0].astype(np.float64) + b[0]) / w
+    a0 = A[0].astype(np.float64)
+    X = (X + np.outer((np.round(t) - t) * w + 1e-7 * (g.random(4096) - 0.5), a0 / (a0 @ a0))
+         ).astype(np.float32)
+    got = lider.hash(torch.from_numpy(X).cuda(), torch.from_numpy(A).cuda(),
+                     torch.from_numpy(b).cuda(), w).cpu().numpy()
+    ref = oracle.digits(X, A, b, w)
+    assert np.array_equal(got, ref)
+
+
+def test_kmeans_assign_step():
+    """One assignment step on 768-d data with 1,000 centroids (FP64 decision)."""
+    torch = _torch()
+    from paper_2205_00970_amd import lider
+    Xt, lab = datagen.mixture(120000, 768, ncomp=1000, seed=13, device="cuda")
+    init = datagen.kmeans_init(120000, 1000, seed=14)
+    cent = Xt[torch.from_numpy(init).cuda()].contiguous()
+    got = lider.kmeans_assign(Xt, cent).cpu().numpy()
+    sample = np.random.default_rng(15).choice(120000, 3000, replace=False)
+    X = Xt.cpu().numpy()
+    ref = oracle.kmeans_assign(X[sample], cent.cpu().numpy())
+    assert np.array_equal(got[sample], ref)
+
+
+def test_errors_and_edge_cases(tiny):
+    torch = _torch()
+    from paper_2205_00970_amd import lider
+    gi = tiny["gi"]
+    Qd = torch.from_numpy(tiny["Q"]).cuda()
+    for bad in [dict(k=0, c=4, r=64), dict(k=10, c=17, r=64), dict(k=10, c=4, r=0),
+                dict(k=2000, c=4, r=64)]:
+        with pytest.raises(lider.LiderError) as e:
+            gi.search(Qd, **bad)
+        assert e.value.status == lider.EINVAL
+    ids, sc = gi.search(Qd[:0], 10, 4, 64)
+    assert ids.shape == (0, 10)
+    lider.fail_next(lider.EDEVICE)
+    with pytest.raises(lider.LiderError) as e:
+        gi.search(Qd, 10, 4, 64)
+    assert e.value.status == lider.EDEVICE
+    ids2, _ = gi.search(Qd, 10, 4, 64)  # the index is untouched
+    ids1, _ = gi.search(Qd, 10, 4, 64)
+    assert torch.equal(ids1, ids2)
+    with pytest.raises(lider.LiderError):
+        gi.search(Qd, 10, 4, 64, precision="bf16")  # index has no bf16 copy
