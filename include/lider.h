@@ -68,13 +68,19 @@ typedef struct lider_index lider_index; /* opaque; owns its device memory */
  *                 NULL runs k-means.  Empty clusters are allowed (their
  *                 centroid is the zero vector).
  *  kmeans_init_host [n_clusters] int64 row ids of the initial centroids
- *                 (required when assignment_dev is NULL, distinct not required).
+ *                 (required when assignment_dev is NULL, distinct not required);
+ *                 with kmeans_seeding = 1 only element 0 is read.
  *  kmeans_iters   maximum Lloyd iterations (>= 1); stops early when an
  *                 assignment repeats the previous one.
  *  storage        LIDER_F32, or LIDER_BF16 to add a bf16 copy of the corpus
  *                 for the precision form (the fp32 copy is always kept).
  *  centroid_storage LIDER_F32, or LIDER_FP8E4M3 to add per-row-scaled fp8
- *                 centroids for precision-form routing. */
+ *                 centroids for precision-form routing.
+ *  kmeans_seeding 0: initial centroids are the rows kmeans_init_host[0..C).
+ *                 1: farthest-first traversal -- the first centroid is row
+ *                 kmeans_init_host[0], each next one the row farthest (squared
+ *                 Euclidean, decided in FP64, ties to the smaller id) from its
+ *                 nearest chosen centroid. */
 typedef struct {
   int32_t n_clusters;
   int32_t m;
@@ -88,6 +94,7 @@ typedef struct {
   int32_t kmeans_iters;
   int32_t storage;
   int32_t centroid_storage;
+  int32_t kmeans_seeding;
 } lider_build_params;
 
 /* Build an index over corpus_dev [n x d] fp32 (Sections 3.2, 3.3.1, 3.3.2):
@@ -232,6 +239,24 @@ int lider_hash(const float* X_dev, int64_t n, int32_t d, const float* A_dev, con
  * synchronises `stream`. */
 int lider_kmeans_assign(const float* X_dev, int64_t n, int32_t d, const float* cent_dev,
                         int32_t C, int32_t* assign_dev, void* stream);
+
+/* ------------------------------------------------------------- profiling */
+
+/* Search stages timed by lider_profile_*: 0 query hashing, 1 layer-1 location
+ * and routing, 2 layer-2 locations and the per-cluster work list, 3 rerank
+ * (the window scoring kernel), 4 top-k selection (and the precision form's
+ * fp32 shortlist rerank). */
+#define LIDER_NSTAGES 5
+
+/* Start timing the next max_calls (1..4096) lider_search / lider_search_ex
+ * calls made on this thread: HIP events are created now and recorded on each
+ * call's stream around every stage (no allocation in the searches). */
+int lider_profile_begin(int32_t max_calls);
+
+/* Wait for the recorded events, return the summed device time of each stage
+ * in stage_ms[LIDER_NSTAGES] (milliseconds) and the number of timed calls,
+ * release the events and stop timing. */
+int lider_profile_end(double* stage_ms, int32_t* calls);
 
 /* Test hook: the next lider_search / lider_search_ex call on this thread fails
  * with `status` before enqueuing anything (0 clears the hook). */

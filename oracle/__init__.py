@@ -46,6 +46,7 @@ def lib():
         L.or_kmeans_assign.argtypes = [p, i64, i32, p, i32, p]
         L.or_kmeans_update.argtypes = [p, i64, i32, p, i32, p, p]
         L.or_kmeans.argtypes = [p, i64, i32, i32, p, i32, p, p, p]
+        L.or_kmeans_seed_farthest.argtypes = [p, i64, i32, i32, i64, p]
         L.or_rmi_train.argtypes = [p, i64, i32, p, p, p, p]
         L.or_rmi_predict.argtypes = [p, p, i32, i64, f64]
         L.or_rmi_predict.restype = i64
@@ -111,6 +112,15 @@ def kmeans_update(X, assign, cent):
     _check(lib().or_kmeans_update(_ptr(X), X.shape[0], X.shape[1], _ptr(assign),
                                   cent.shape[0], _ptr(cent), _ptr(counts)), "kmeans_update")
     return cent, counts
+
+
+def kmeans_seed_farthest(X, C, first):
+    """Farthest-first traversal from row `first`: C initial centre row ids."""
+    X = _f32(X)
+    ids = np.empty(C, np.int64)
+    _check(lib().or_kmeans_seed_farthest(_ptr(X), X.shape[0], X.shape[1], C, int(first),
+                                         _ptr(ids)), "kmeans_seed_farthest")
+    return ids
 
 
 def kmeans(X, C, init_ids, iters):
@@ -233,7 +243,7 @@ class Index:
     """Oracle LIDER index (Sections 3.2-3.3).  Keeps a reference to X."""
 
     def __init__(self, X, n_clusters, A, b, m, w, rmi_fanout, rmi_fanout_l1=None,
-                 assignment=None, init_ids=None, kmeans_iters=20):
+                 assignment=None, init_ids=None, kmeans_iters=20, seeding="given"):
         self.X = _f32(X)
         self.n, self.d = self.X.shape
         self.C, self.m, self.w = int(n_clusters), int(m), float(w)
@@ -243,6 +253,9 @@ class Index:
         assert self.A.shape == (2 * self.m, self.d) and self.b.shape == (2 * self.m,)
         asg = None if assignment is None else np.ascontiguousarray(assignment, dtype=np.int32)
         ini = None if init_ids is None else np.ascontiguousarray(init_ids, dtype=np.int64)
+        if asg is None and ini is not None and seeding == "farthest":
+            ini = kmeans_seed_farthest(self.X, self.C, int(ini[0]))
+        self.seeds = ini
         if asg is None and ini is None:
             raise ValueError("need an assignment or k-means initial ids")
         st = C.c_int(0)

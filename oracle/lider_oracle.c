@@ -128,6 +128,33 @@ int or_kmeans_update(const float* X, int64_t n, int32_t d, const int32_t* assign
   return OR_OK;
 }
 
+/* Reading: k-means initial centres by farthest-first traversal (the maximin
+ * rule of Gonzalez's k-center heuristic): the first centre is a given row;
+ * every next centre is the row whose squared Euclidean distance (FP64) to its
+ * nearest chosen centre is largest, ties to the smallest row id. */
+int or_kmeans_seed_farthest(const float* X, int64_t n, int32_t d, int32_t C, int64_t first,
+                            int64_t* ids) {
+  if (n < 1 || d < 1 || C < 1 || C > n || first < 0 || first >= n) return OR_EINVAL;
+  double* D = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!D) return OR_ENOMEM;
+  for (int64_t i = 0; i < n; ++i) D[i] = INFINITY;
+  ids[0] = first;
+  for (int32_t t = 1; t < C; ++t) {
+    const float* c = X + ids[t - 1] * d;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      double v = or_sqdist(X + i * d, c, d);
+      if (v < D[i]) D[i] = v;
+    }
+    int64_t best = 0;
+    for (int64_t i = 1; i < n; ++i)
+      if (D[i] > D[best]) best = i;
+    ids[t] = best;
+  }
+  free(D);
+  return OR_OK;
+}
+
 /* Lloyd iterations: cent <- X[init_ids]; repeat { assign; stop if nothing
  * changed (from the second assignment on); update } at most `iters` times.
  * On return the centroids are the means of the returned assignment. */

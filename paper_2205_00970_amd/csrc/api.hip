@@ -15,6 +15,17 @@ namespace {
 thread_local std::string g_err;
 thread_local int32_t g_fail_next = 0;
 
+struct Profile {
+  int32_t max_calls = 0, calls = 0;
+  std::vector<hipEvent_t> ev;  // (LIDER_NSTAGES + 1) per call
+};
+thread_local Profile g_prof;
+
+void profile_release() {
+  for (hipEvent_t e : g_prof.ev) (void)hipEventDestroy(e);
+  g_prof = Profile();
+}
+
 template <class T>
 int alloc(T** p, size_t count, const char* what) {
   *p = nullptr;
@@ -91,8 +102,10 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
     return set_error(LIDER_EINVAL, "storage must be LIDER_F32 or LIDER_BF16");
   if (P->centroid_storage != LIDER_F32 && P->centroid_storage != LIDER_FP8E4M3)
     return set_error(LIDER_EINVAL, "centroid_storage must be LIDER_F32 or LIDER_FP8E4M3");
+  if (P->kmeans_seeding != 0 && P->kmeans_seeding != 1)
+    return set_error(LIDER_EINVAL, "kmeans_seeding must be 0 or 1");
   if (!P->assignment_dev)
-    for (int32_t j = 0; j < P->n_clusters; ++j)
+    for (int32_t j = 0; j < (P->kmeans_seeding ? 1 : P->n_clusters); ++j)
       if (P->kmeans_init_host[j] < 0 || P->kmeans_init_host[j] >= n)
         return set_error(LIDER_EINVAL, "kmeans_init_host id out of range");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -179,7 +192,7 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
       if (scr) (void)hipFree(scr);
       ix.iters_run = 0;
     } else {
-      TRY(run_kmeans(ix, corpus_dev, P->kmeans_init_host, P->kmeans_iters, st));
+      TRY(run_kmeans(ix, corpus_dev, P->kmeans_init_host, P->kmeans_iters, P->kmeans_seeding, st));
     }
   }
   TRY(build_core_models(ix, corpus_dev, st));
@@ -263,8 +276,48 @@ int lider_search_ex(const lider_index* index, const float* queries_dev, int64_t 
   if (!ids_dev || !scores_dev || !ws_dev) return set_error(LIDER_EINVAL, "output or workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws_dev) & 255)
     return set_error(LIDER_EINVAL, "workspace must be 256-byte aligned");
+  hipEvent_t* ev = nullptr;
+  if (g_prof.calls < g_prof.max_calls) {
+    ev = g_prof.ev.data() + size_t(g_prof.calls) * (LIDER_NSTAGES + 1);
+    ++g_prof.calls;
+  }
   return run_search(index->ix, queries_dev, nq, k, c, r, ids_dev, scores_dev, ws_dev, ws_bytes,
-                    static_cast<hipStream_t>(stream), o, debug);
+                    static_cast<hipStream_t>(stream), o, debug, ev);
+}
+
+int lider_profile_begin(int32_t max_calls) {
+  g_err.clear();
+  if (max_calls < 1 || max_calls > 4096) return set_error(LIDER_EINVAL, "max_calls must be in 1..4096");
+  profile_release();
+  g_prof.ev.resize(size_t(max_calls) * (LIDER_NSTAGES + 1));
+  for (auto& e : g_prof.ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      profile_release();
+      return set_error(LIDER_EDEVICE, "hipEventCreate failed");
+    }
+  }
+  g_prof.max_calls = max_calls;
+  return LIDER_OK;
+}
+
+int lider_profile_end(double* stage_ms, int32_t* calls) {
+  g_err.clear();
+  if (!stage_ms || !calls) return set_error(LIDER_EINVAL, "NULL argument");
+  int rc = LIDER_OK;
+  for (int s = 0; s < LIDER_NSTAGES; ++s) stage_ms[s] = 0.0;
+  for (int32_t c = 0; c < g_prof.calls && rc == LIDER_OK; ++c) {
+    hipEvent_t* ev = g_prof.ev.data() + size_t(c) * (LIDER_NSTAGES + 1);
+    rc = check_hip(hipEventSynchronize(ev[LIDER_NSTAGES]), "profile event");
+    for (int s = 0; s < LIDER_NSTAGES && rc == LIDER_OK; ++s) {
+      float ms = 0.f;
+      rc = check_hip(hipEventElapsedTime(&ms, ev[s], ev[s + 1]), "profile elapsed time");
+      stage_ms[s] += ms;
+    }
+  }
+  *calls = g_prof.calls;
+  profile_release();
+  return rc;
 }
 
 int lider_search(const lider_index* index, const float* queries_dev, int64_t nq, int32_t k,

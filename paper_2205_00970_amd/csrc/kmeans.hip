@@ -11,6 +11,8 @@
 // rounded once to fp32; an empty cluster keeps its centroid.
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+
 #include "lider_internal.hpp"
 
 namespace lider {
@@ -344,6 +346,128 @@ int run_centroid_means(const float* X, int64_t n, int32_t d, const int32_t* assi
   return check_hip(hipGetLastError(), "centroid mean kernels");
 }
 
+// ----------------------------------------------------- farthest-first seeding
+// Round t: D_i <- min(D_i, |x_i - c_{t-1}|^2) in fp32 (relative error <= e),
+// then every row whose fp32 value is within the error band of the maximum is
+// rescored exactly (FP64 minimum over all chosen centroids, sequential sums)
+// and the FP64 argmax (ties to the smaller id) becomes centroid t.
+constexpr double kFFRel = 1.1920928955078125e-07;  // 2^-23 per dimension (fp32 + FP64 side)
+
+__global__ __launch_bounds__(256) void ff_update_kernel(const float* __restrict__ X, int64_t n,
+                                                        int32_t d, const float* __restrict__ c,
+                                                        float* __restrict__ D,
+                                                        uint32_t* __restrict__ maxbits, int first) {
+  __shared__ float wmax[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float mx = 0.f;
+  for (int64_t i = int64_t(blockIdx.x) * 4 + wave; i < n; i += int64_t(gridDim.x) * 4) {
+    const float* xr = X + i * d;
+    float s = 0.f;
+    for (int l = lane; l < d; l += 64) {
+      const float t = xr[l] - c[l];
+      s += t * t;
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    float v = first ? s : fminf(D[i], s);
+    if (lane == 0) D[i] = v;
+    mx = fmaxf(mx, v);
+  }
+  if (lane == 0) wmax[wave] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    atomicMax(maxbits, __float_as_uint(m));
+  }
+}
+
+__global__ void ff_candidates_kernel(const float* __restrict__ D, int64_t n, int32_t d,
+                                     const uint32_t* __restrict__ maxbits,
+                                     int64_t* __restrict__ cand, int32_t* __restrict__ ncand) {
+  const double e = double(d + 3) * kFFRel;
+  const double M = double(__uint_as_float(*maxbits));
+  const double T = M * (1.0 - 2.0 * e) / (1.0 + 2.0 * e) - double(d) * 7.888609052210118e-31;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    if (double(D[i]) >= T) cand[atomicAdd(ncand, 1)] = i;
+  }
+}
+
+// Exact FP64 distance of each candidate to its nearest chosen centroid.
+__global__ __launch_bounds__(256) void ff_exact_kernel(const float* __restrict__ X, int32_t d,
+                                                       const float* __restrict__ cent, int32_t t,
+                                                       const int64_t* __restrict__ cand,
+                                                       const int32_t* __restrict__ ncand,
+                                                       double* __restrict__ dex) {
+#pragma clang fp contract(off)
+  __shared__ double sd[256];
+  const int32_t cnt = *ncand;
+  for (int32_t k = blockIdx.x; k < cnt; k += gridDim.x) {
+    const float* xr = X + cand[k] * d;
+    double best = INFINITY;
+    for (int32_t j = threadIdx.x; j < t; j += blockDim.x) {
+      const float* mu = cent + int64_t(j) * d;
+      double acc = 0.0;
+      for (int l = 0; l < d; ++l) {
+        double df = double(xr[l]) - double(mu[l]);
+        acc = acc + df * df;
+      }
+      best = acc < best ? acc : best;
+    }
+    sd[threadIdx.x] = best;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sd[threadIdx.x] = fmin(sd[threadIdx.x], sd[threadIdx.x + o]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) dex[k] = sd[0];
+    __syncthreads();
+  }
+}
+
+// FP64 argmax over the candidates (ties to the smaller row id); writes the
+// new centroid row, resets the per-round counters.
+__global__ __launch_bounds__(256) void ff_pick_kernel(const float* __restrict__ X, int32_t d,
+                                                      float* __restrict__ cent, int32_t t,
+                                                      int64_t* __restrict__ cand,
+                                                      int32_t* __restrict__ ncand,
+                                                      const double* __restrict__ dex,
+                                                      uint32_t* __restrict__ maxbits) {
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  const int32_t cnt = *ncand;
+  double v = -1.0;
+  int64_t id = INT64_MAX;
+  for (int32_t k = threadIdx.x; k < cnt; k += blockDim.x) {
+    const double dv = dex[k];
+    const int64_t ci = cand[k];
+    if (dv > v || (dv == v && ci < id)) {
+      v = dv;
+      id = ci;
+    }
+  }
+  bv[threadIdx.x] = v;
+  bi[threadIdx.x] = id;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double ov = bv[threadIdx.x + o];
+      const int64_t oi = bi[threadIdx.x + o];
+      if (ov > bv[threadIdx.x] || (ov == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = ov;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t pick = bi[0] == INT64_MAX ? 0 : bi[0];  // no candidate only with NaN input
+  for (int l = threadIdx.x; l < d; l += blockDim.x) cent[int64_t(t) * d + l] = X[pick * d + l];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *ncand = 0;
+    *maxbits = 0;
+  }
+}
+
 __global__ void gather_rows_kernel(const float* __restrict__ X, int32_t d,
                                    const int64_t* __restrict__ ids, int32_t cnt,
                                    float* __restrict__ out) {
@@ -355,7 +479,7 @@ __global__ void gather_rows_kernel(const float* __restrict__ X, int32_t d,
 
 // Lloyd iterations into ix.cent / ix.assign.
 int run_kmeans(Index& ix, const float* X, const int64_t* init_host, int32_t iters,
-               hipStream_t st) {
+               int32_t seeding, hipStream_t st) {
   const int64_t n = ix.n;
   const int32_t C = ix.C, d = ix.d;
   int64_t* init_dev = nullptr;
@@ -380,9 +504,39 @@ int run_kmeans(Index& ix, const float* X, const int64_t* init_host, int32_t iter
                    "copy k-means initial ids");
   }
   if (rc == LIDER_OK) {
-    const int64_t tot = int64_t(C) * d;
+    const int64_t tot = int64_t(seeding ? 1 : C) * d;
     hipLaunchKernelGGL(gather_rows_kernel, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st,
-                       X, d, init_dev, C, ix.cent);
+                       X, d, init_dev, seeding ? 1 : C, ix.cent);
+  }
+  if (rc == LIDER_OK && seeding == 1 && C > 1) {
+    float* D = nullptr;
+    int64_t* cand = nullptr;
+    double* dex = nullptr;
+    if (hipMalloc(&D, size_t(n) * 4) != hipSuccess || hipMalloc(&cand, size_t(n) * 8) != hipSuccess ||
+        hipMalloc(&dex, size_t(n) * 8) != hipSuccess)
+      fail(LIDER_ENOMEM, "farthest-first buffers");
+    int32_t* ncand = changed;  // [0] candidate count, [1] max bits
+    uint32_t* maxbits = reinterpret_cast<uint32_t*>(changed + 1);
+    if (rc == LIDER_OK) {
+      hipLaunchKernelGGL(zero_i32_kernel2, dim3(1), dim3(64), 0, st, changed, int64_t(2));
+      const unsigned ub = unsigned(std::min<int64_t>((n + 3) / 4, 8192));
+      const unsigned cb = unsigned(std::min<int64_t>((n + 255) / 256, 4096));
+      for (int32_t t = 1; t < C; ++t) {
+        hipLaunchKernelGGL(ff_update_kernel, dim3(ub), dim3(256), 0, st, X, n, d,
+                           ix.cent + int64_t(t - 1) * d, D, maxbits, t == 1 ? 1 : 0);
+        hipLaunchKernelGGL(ff_candidates_kernel, dim3(cb), dim3(256), 0, st, D, n, d, maxbits,
+                           cand, ncand);
+        hipLaunchKernelGGL(ff_exact_kernel, dim3(256), dim3(256), 0, st, X, d, ix.cent, t, cand,
+                           ncand, dex);
+        hipLaunchKernelGGL(ff_pick_kernel, dim3(1), dim3(256), 0, st, X, d, ix.cent, t, cand,
+                           ncand, dex, maxbits);
+      }
+      rc = check_hip(hipGetLastError(), "farthest-first seeding");
+      if (rc == LIDER_OK) rc = check_hip(hipStreamSynchronize(st), "farthest-first seeding");
+    }
+    if (D) hipFree(D);
+    if (cand) hipFree(cand);
+    if (dex) hipFree(dex);
   }
   int cur = 0, fin = 0;
   int32_t it = 0;

@@ -178,7 +178,7 @@ void launch_norm_bounds(const float* A, int32_t rows, int32_t d, float* out, hip
 
 // kmeans.hip
 int run_kmeans(Index& ix, const float* X, const int64_t* init_host, int32_t iters,
-               hipStream_t st);
+               int32_t seeding, hipStream_t st);
 int run_kmeans_assign(const float* X, int64_t n, int32_t d, const float* cent, int32_t C,
                       int32_t* assign, const int32_t* prev, int32_t* changed, void* scratch,
                       hipStream_t st);
@@ -193,8 +193,9 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st);
 // search.hip
 size_t search_workspace(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
                         const lider_search_opts& o);
+// ev: NULL or LIDER_NSTAGES + 1 events recorded at the stage boundaries
 int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c, int32_t r,
                int64_t* ids, float* scores, void* ws, size_t ws_bytes, hipStream_t st,
-               const lider_search_opts& o, const lider_search_debug* dbg);
+               const lider_search_opts& o, const lider_search_debug* dbg, hipEvent_t* ev);
 
 }  // namespace lider

@@ -19,6 +19,7 @@
 #include <hip/hip_fp8.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "lider_internal.hpp"
 
@@ -505,98 +506,82 @@ __device__ inline int32_t next_tile(int persistent, int32_t ntiles, int32_t* __r
   return t;
 }
 
-// fp32 rerank.  RT rows per tile, RT/16 waves (wave w owns rows 16w..16w+15
-// of the tile), pairs in passes of 16: D[16 pairs x 16 rows] += Q . X^T on
-// v_mfma_f32_16x16x4f32, 4 MFMAs per float4 of both operands.
-template <int RT, bool VEC>
-__global__ __launch_bounds__(RT * 4) void score_f32_kernel(
-    const float* __restrict__ X, int32_t d, const int64_t* __restrict__ off,
-    const int32_t* __restrict__ tiles, int32_t ntiles, const int32_t* __restrict__ cstart,
-    const int32_t* __restrict__ wl, const Pair* __restrict__ pairs, int32_t c,
-    const float* __restrict__ Q, float* __restrict__ sbuf, int32_t rcap, int persistent,
-    int32_t* __restrict__ ctr) {
-  __shared__ TileShared sh;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int i = lane & 15, s = lane >> 4;
-  int32_t state = 0;
-  for (;;) {
-    const int32_t tile = next_tile(persistent, ntiles, ctr, state, sh);
-    if (tile < 0) break;
-    const int32_t j = tiles[2 * tile], row0 = tiles[2 * tile + 1];
-    const int64_t base = off[j];
-    const int32_t L = int32_t(off[j + 1] - base);
-    const int32_t rows_here = min(RT, L - row0);
-    const int32_t plo = cstart[j], phi = cstart[j + 1];
-    for (int32_t pb = plo; pb < phi; pb += kPairCap) {
-      if (tid == 0) sh.cnt = 0;
-      __syncthreads();
-      const int32_t pe = min(phi, pb + kPairCap);
-      for (int32_t u = pb + tid; u < pe; u += RT * 4) {
-        const int32_t pi = wl[u];
-        const Pair pr = pairs[pi];
-        if (pr.s < row0 + rows_here && pr.s + pr.len > row0) {
-          const int32_t slot = atomicAdd(&sh.cnt, 1);
-          sh.lp[slot] = pi;
-          sh.lq[slot] = pi / c;
-          sh.ls[slot] = pr.s;
-          sh.le[slot] = pr.s + pr.len;
-        }
-      }
-      __syncthreads();
-      const int32_t P = sh.cnt;
-      const int32_t wr0 = row0 + 16 * wave;
-      if (wr0 < row0 + rows_here) {
-        const int32_t myrow = min(wr0 + i, row0 + rows_here - 1);
-        const float* xr = X + (base + myrow) * d;
-        for (int32_t c0 = 0; c0 < P; c0 += 16) {
-          const int32_t pq = min(c0 + i, P - 1);
-          const float* qr = Q + int64_t(sh.lq[pq]) * d;
-          floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-          const int dfull = VEC ? (d & ~15) : 0;
-          for (int k0 = 0; k0 < dfull; k0 += 16) {
-            const int kk = k0 + 4 * s;
-            const float4 qv = *reinterpret_cast<const float4*>(qr + kk);
-            const float4 xv = *reinterpret_cast<const float4*>(xr + kk);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(qv.x, xv.x, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(qv.y, xv.y, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(qv.z, xv.z, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(qv.w, xv.w, acc, 0, 0, 0);
-          }
-          for (int k0 = dfull; k0 < d; k0 += 16) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int kk = k0 + 4 * s + e;
-              const bool in = kk < d;
-              acc = __builtin_amdgcn_mfma_f32_16x16x4f32(in ? qr[kk] : 0.f, in ? xr[kk] : 0.f, acc,
-                                                         0, 0, 0);
-            }
-          }
-          const int32_t row = wr0 + i;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int32_t pp = c0 + 4 * s + e;
-            if (pp < P && row < row0 + rows_here && row >= sh.ls[pp] && row < sh.le[pp])
-              sbuf[int64_t(sh.lp[pp]) * rcap + (row - sh.ls[pp])] = acc[e];
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
+// Rerank of one tile: RT consecutive rows of one cluster (contiguous in the
+// reordered corpus) against every (query, cluster) pair whose window overlaps
+// the tile.  The 4 waves split the dimension range (wave w owns a contiguous
+// quarter of the k-steps), so every X row and every query row of the tile is
+// read exactly once; each wave accumulates all RT rows x up to 32 pairs on
+// MFMA (fp32: v_mfma_f32_16x16x4f32, one float4 of both operands feeds 4
+// MFMAs; bf16: v_mfma_f32_16x16x32_bf16, 8 consecutive bf16 per lane), then the
+// 4 partial sums are added in wave order through LDS and written, coalesced
+// along rows, into each pair's window score row.  The summation order of a
+// score depends only on d, so results do not depend on the tile size, the
+// schedule or which other pairs share a pass.
+constexpr int kRerankWaves = 4;
+constexpr int kPassPairs = 32;
 
-// bf16 first pass of the precision form: v_mfma_f32_16x16x32_bf16, each lane
-// feeding 8 consecutive bf16 of its pair / row per MFMA.
-template <int RT>
-__global__ __launch_bounds__(RT * 4) void score_bf16_kernel(
-    const __hip_bfloat16* __restrict__ X, int32_t d, const int64_t* __restrict__ off,
+template <bool BF16, bool VEC>
+struct Feed;
+
+template <bool VEC>
+struct Feed<false, VEC> {  // fp32: 16 dims per k-step, 4 per lane
+  static constexpr int KS = 16;
+  typedef float4 T;
+  __device__ static T load(const float* row, int k, int d) {
+    if (VEC) {
+      if (k < d) return *reinterpret_cast<const float4*>(row + k);
+      return float4{0.f, 0.f, 0.f, 0.f};
+    }
+    float4 v;
+    v.x = k < d ? row[k] : 0.f;
+    v.y = k + 1 < d ? row[k + 1] : 0.f;
+    v.z = k + 2 < d ? row[k + 2] : 0.f;
+    v.w = k + 3 < d ? row[k + 3] : 0.f;
+    return v;
+  }
+  __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.x, x.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.y, x.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.z, x.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.w, x.w, acc, 0, 0, 0);
+  }
+};
+
+template <bool VEC>
+struct Feed<true, VEC> {  // bf16: 32 dims per k-step, 8 per lane (d % 8 == 0)
+  static constexpr int KS = 32;
+  typedef bf16x8 T;
+  __device__ static T load(const __hip_bfloat16* row, int k, int d) {
+    if (k < d) return *reinterpret_cast<const bf16x8*>(row + k);
+    T z;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.f;
+    return z;
+  }
+  __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(q, x, acc, 0, 0, 0);
+  }
+};
+
+template <int RT, bool BF16, bool VEC>
+__global__ __launch_bounds__(256) void rerank_kernel(
+    const void* __restrict__ Xv, int32_t d, const int64_t* __restrict__ off,
     const int32_t* __restrict__ tiles, int32_t ntiles, const int32_t* __restrict__ cstart,
     const int32_t* __restrict__ wl, const Pair* __restrict__ pairs, int32_t c,
-    const __hip_bfloat16* __restrict__ Qb, float* __restrict__ sbuf, int32_t rcap, int persistent,
+    const void* __restrict__ Qv, float* __restrict__ sbuf, int32_t rcap, int persistent,
     int32_t* __restrict__ ctr) {
+  typedef typename std::conditional<BF16, __hip_bfloat16, float>::type E;
+  typedef Feed<BF16, VEC> F;
+  constexpr int RC = RT / 16;
   __shared__ TileShared sh;
+  __shared__ float part[kRerankWaves][kPassPairs][RT];
+  const E* X = static_cast<const E*>(Xv);
+  const E* Q = static_cast<const E*>(Qv);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i = lane & 15, s = lane >> 4;
+  const int nsteps = (d + F::KS - 1) / F::KS;
+  const int ks0 = wave * nsteps / kRerankWaves, ks1 = (wave + 1) * nsteps / kRerankWaves;
+  const int sub = BF16 ? 8 * s : 4 * s;
   int32_t state = 0;
   for (;;) {
     const int32_t tile = next_tile(persistent, ntiles, ctr, state, sh);
@@ -606,11 +591,15 @@ __global__ __launch_bounds__(RT * 4) void score_bf16_kernel(
     const int32_t L = int32_t(off[j + 1] - base);
     const int32_t rows_here = min(RT, L - row0);
     const int32_t plo = cstart[j], phi = cstart[j + 1];
+    const E* xr[RC];
+#pragma unroll
+    for (int rc = 0; rc < RC; ++rc)
+      xr[rc] = X + (base + min(row0 + 16 * rc + i, row0 + rows_here - 1)) * d;
     for (int32_t pb = plo; pb < phi; pb += kPairCap) {
       if (tid == 0) sh.cnt = 0;
       __syncthreads();
       const int32_t pe = min(phi, pb + kPairCap);
-      for (int32_t u = pb + tid; u < pe; u += RT * 4) {
+      for (int32_t u = pb + tid; u < pe; u += 256) {
         const int32_t pi = wl[u];
         const Pair pr = pairs[pi];
         if (pr.s < row0 + rows_here && pr.s + pr.len > row0) {
@@ -623,42 +612,54 @@ __global__ __launch_bounds__(RT * 4) void score_bf16_kernel(
       }
       __syncthreads();
       const int32_t P = sh.cnt;
-      const int32_t wr0 = row0 + 16 * wave;
-      if (wr0 < row0 + rows_here) {
-        const int32_t myrow = min(wr0 + i, row0 + rows_here - 1);
-        const __hip_bfloat16* xr = X + (base + myrow) * d;
-        for (int32_t c0 = 0; c0 < P; c0 += 16) {
-          const int32_t pq = min(c0 + i, P - 1);
-          const __hip_bfloat16* qr = Qb + int64_t(sh.lq[pq]) * d;
-          floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-          const int dfull = d & ~31;
-          for (int k0 = 0; k0 < dfull; k0 += 32) {
-            const int kk = k0 + 8 * s;
-            const bf16x8 qv = *reinterpret_cast<const bf16x8*>(qr + kk);
-            const bf16x8 xv = *reinterpret_cast<const bf16x8*>(xr + kk);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qv, xv, acc, 0, 0, 0);
-          }
-          for (int k0 = dfull; k0 < d; k0 += 32) {
-            bf16x8 qv, xv;
+      for (int32_t g0 = 0; g0 < P; g0 += kPassPairs) {
+        const int np = min(kPassPairs, P - g0);
+        const int npc = (np + 15) / 16;
+        floatx4 acc[RC][2];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              const int kk = k0 + 8 * s + e;
-              const bool in = kk < d;
-              qv[e] = in ? __builtin_bit_cast(__bf16, qr[kk]) : (__bf16)0.f;
-              xv[e] = in ? __builtin_bit_cast(__bf16, xr[kk]) : (__bf16)0.f;
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qv, xv, acc, 0, 0, 0);
-          }
-          const int32_t row = wr0 + i;
+        for (int rc = 0; rc < RC; ++rc) {
+          acc[rc][0] = floatx4{0.f, 0.f, 0.f, 0.f};
+          acc[rc][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+        const E* q0 = Q + int64_t(sh.lq[g0 + min(i, np - 1)]) * d;
+        const E* q1 = Q + int64_t(sh.lq[g0 + min(16 + i, np - 1)]) * d;
+        for (int ks = ks0; ks < ks1; ++ks) {
+          const int k = ks * F::KS + sub;
+          typename F::T xv[RC];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int32_t pp = c0 + 4 * s + e;
-            if (pp < P && row < row0 + rows_here && row >= sh.ls[pp] && row < sh.le[pp])
-              sbuf[int64_t(sh.lp[pp]) * rcap + (row - sh.ls[pp])] = acc[e];
+          for (int rc = 0; rc < RC; ++rc) xv[rc] = F::load(xr[rc], k, d);
+          const typename F::T qa = F::load(q0, k, d);
+#pragma unroll
+          for (int rc = 0; rc < RC; ++rc) F::mfma(qa, xv[rc], acc[rc][0]);
+          if (npc > 1) {
+            const typename F::T qb = F::load(q1, k, d);
+#pragma unroll
+            for (int rc = 0; rc < RC; ++rc) F::mfma(qb, xv[rc], acc[rc][1]);
           }
         }
+#pragma unroll
+        for (int pc = 0; pc < 2; ++pc) {
+          if (pc < npc) {
+#pragma unroll
+            for (int rc = 0; rc < RC; ++rc)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) part[wave][pc * 16 + 4 * s + e][rc * 16 + i] = acc[rc][pc][e];
+          }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < np * RT; idx += 256) {
+          const int pp = idx / RT, rr = idx - pp * RT;
+          const int32_t row = row0 + rr;
+          const int32_t a = sh.ls[g0 + pp];
+          if (rr < rows_here && row >= a && row < sh.le[g0 + pp]) {
+            float v = part[0][pp][rr];
+#pragma unroll
+            for (int w = 1; w < kRerankWaves; ++w) v += part[w][pp][rr];
+            sbuf[int64_t(sh.lp[g0 + pp]) * rcap + (row - a)] = v;
+          }
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
 }
@@ -845,16 +846,17 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
     grid = unsigned((nt + 7) / 8 * 8);
   const bool vec = (ix.d % 4 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
   if (bf16)
-    hipLaunchKernelGGL(score_bf16_kernel<RT>, dim3(grid), dim3(RT * 4), 0, st, ix.Xb, ix.d, ix.off,
-                       ix.tiles[ti], nt, cstart, wl, pairs, c, Qb, sbuf, rcap, persistent, ctr);
+    hipLaunchKernelGGL((rerank_kernel<RT, true, true>), dim3(grid), dim3(256), 0, st,
+                       (const void*)ix.Xb, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)Qb, sbuf, rcap, persistent, ctr);
   else if (vec)
-    hipLaunchKernelGGL((score_f32_kernel<RT, true>), dim3(grid), dim3(RT * 4), 0, st, ix.X, ix.d,
-                       ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c, Q, sbuf, rcap, persistent,
-                       ctr);
+    hipLaunchKernelGGL((rerank_kernel<RT, false, true>), dim3(grid), dim3(256), 0, st,
+                       (const void*)ix.X, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)Q, sbuf, rcap, persistent, ctr);
   else
-    hipLaunchKernelGGL((score_f32_kernel<RT, false>), dim3(grid), dim3(RT * 4), 0, st, ix.X, ix.d,
-                       ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c, Q, sbuf, rcap, persistent,
-                       ctr);
+    hipLaunchKernelGGL((rerank_kernel<RT, false, false>), dim3(grid), dim3(256), 0, st,
+                       (const void*)ix.X, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)Q, sbuf, rcap, persistent, ctr);
 }
 
 }  // namespace
@@ -866,7 +868,7 @@ size_t search_workspace(const Index& ix, int64_t nq, int32_t k, int32_t c, int32
 
 int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c, int32_t r,
                int64_t* ids, float* scores, void* ws, size_t ws_bytes, hipStream_t st,
-               const lider_search_opts& o, const lider_search_debug* dbg) {
+               const lider_search_opts& o, const lider_search_debug* dbg, hipEvent_t* ev) {
   const Plan p = make_plan(ix, nq, k, c, r, o);
   if (ws_bytes < p.total)
     return set_error(LIDER_EINVAL, "workspace too small: need " + std::to_string(p.total) +
@@ -892,12 +894,17 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   const int64_t np = nq * c;
   const bool bf16 = o.precision == LIDER_BF16;
 
+  auto mark = [&](int i) {
+    if (ev) (void)hipEventRecord(ev[i], st);
+  };
+  mark(0);
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, st, ctr, int64_t(kCtrWords));
   hipLaunchKernelGGL(zero_kernel, dim3((C + 255) / 256), dim3(256), 0, st, ccount, int64_t(C));
   hipLaunchKernelGGL(zero_kernel, dim3((C + 255) / 256), dim3(256), 0, st, cfill, int64_t(C));
   int rc = run_hash_ex(Q, nq, ix.d, ix.A, ix.b, ix.anorm, 2 * m, ix.w, qdig, hlist, ctr, ctr + 1,
                        1, qnorm, st);
   if (rc != LIDER_OK) return rc;
+  mark(1);
   hipLaunchKernelGGL(l1_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, st, ix.models,
                      ix.leaves, qdig, m, nq, C, p.r1, l1);
   const unsigned qgrid = unsigned(std::min<int64_t>(nq, 65535));
@@ -909,6 +916,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
     hipLaunchKernelGGL(route_kernel<false>, dim3(qgrid), dim3(kRouteNT), 0, st, Q, ix.d, nq,
                        ix.cent_l1, ix.cent8, ix.cent8_scale, ix.l1_order32, l1, qnorm,
                        ix.cent_norm_max, c, p.r1, rs, rs64, routed);
+  mark(2);
   hipLaunchKernelGGL(pairs_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, ix.models,
                      ix.leaves, qdig, m, np, c, r, routed, pairs, ccount);
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, ccount, C, cstart);
@@ -916,6 +924,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
                      cstart, cfill, wl);
   if (bf16)
     hipLaunchKernelGGL(to_bf16_kernel, dim3(2048), dim3(256), 0, st, Q, nq * ix.d, qb);
+  mark(3);
   const int tr = o.tile_rows == 32 ? 32 : o.tile_rows == 128 ? 128 : 64;
   const int ti = tr == 32 ? 0 : tr == 64 ? 1 : 2;
   const int gm = o.grid_mult > 0 ? o.grid_mult : 4;
@@ -928,6 +937,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   else
     launch_score<128>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
                       ctr + 8, st);
+  mark(4);
   if (!bf16) {
     if (k <= 128)
       hipLaunchKernelGGL((select_kernel<128, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
@@ -949,6 +959,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
       hipLaunchKernelGGL(rerank_shortlist_kernel<1024>, dim3(qgrid), dim3(kSelNT), 0, st, ix.X,
                          ix.d, Q, nq, slist, p.S, ix.perm32, k, ids, scores);
   }
+  mark(5);
   if (dbg) {
     if (dbg->qdigits_dev)
       (void)hipMemcpyAsync(dbg->qdigits_dev, qdig, size_t(nq) * 2 * m * 4, hipMemcpyDeviceToDevice, st);

@@ -39,7 +39,8 @@ class BuildParams(C.Structure):
                 ("rmi_fanout_l1", C.c_int32), ("w", C.c_double), ("lsh_a_host", C.c_void_p),
                 ("lsh_b_host", C.c_void_p), ("assignment_dev", C.c_void_p),
                 ("kmeans_init_host", C.c_void_p), ("kmeans_iters", C.c_int32),
-                ("storage", C.c_int32), ("centroid_storage", C.c_int32)]
+                ("storage", C.c_int32), ("centroid_storage", C.c_int32),
+                ("kmeans_seeding", C.c_int32)]
 
 
 class SearchOpts(C.Structure):
@@ -62,7 +63,10 @@ class Info(C.Structure):
 
 SYMBOLS = ["lider_build", "lider_free", "lider_last_error", "lider_search_workspace",
            "lider_search", "lider_search_ex", "lider_get_info", "lider_export_bytes",
-           "lider_export", "lider_hash", "lider_kmeans_assign", "lider_debug_fail_next"]
+           "lider_export", "lider_hash", "lider_kmeans_assign", "lider_profile_begin",
+           "lider_profile_end", "lider_debug_fail_next"]
+NSTAGES = 5
+STAGES = ["hash", "route", "worklist", "rerank", "select"]
 
 _lib = None
 
@@ -90,6 +94,8 @@ def lib():
         L.lider_export.argtypes = [p, i32, p, sz]
         L.lider_hash.argtypes = [p, i64, i32, p, p, i32, C.c_double, p, p]
         L.lider_kmeans_assign.argtypes = [p, i64, i32, p, i32, p, p]
+        L.lider_profile_begin.argtypes = [i32]
+        L.lider_profile_end.argtypes = [C.POINTER(C.c_double), C.POINTER(i32)]
         L.lider_debug_fail_next.argtypes = [i32]
         L.lider_debug_fail_next.restype = None
         _lib = L
@@ -139,7 +145,7 @@ class Index:
 
     def __init__(self, corpus, n_clusters, m, w, rmi_fanout, lsh, rmi_fanout_l1=0,
                  kmeans_init=None, kmeans_iters=20, assignment=None, storage="f32",
-                 centroid_storage="f32", stream=None):
+                 centroid_storage="f32", seeding="given", stream=None):
         torch = _torch()
         cp = _dev_ptr(corpus, torch.float32, 2, "corpus")
         n, d = corpus.shape
@@ -148,14 +154,15 @@ class Index:
         if A.shape != (2 * m, d) or b.shape != (2 * m,):
             raise ValueError("lsh must be (A [2m, d], b [2m])")
         ini = None if kmeans_init is None else np.ascontiguousarray(kmeans_init, dtype=np.int64)
-        if assignment is None and (ini is None or ini.shape != (n_clusters,)):
-            raise ValueError("k-means needs kmeans_init of n_clusters row ids")
+        seed_mode = {"given": 0, "farthest": 1}[seeding]
+        if assignment is None and (ini is None or ini.shape[0] < (1 if seed_mode else n_clusters)):
+            raise ValueError("k-means needs kmeans_init row ids")
         P = BuildParams(int(n_clusters), int(m), int(rmi_fanout), int(rmi_fanout_l1), float(w),
                         _np_ptr(A), _np_ptr(b),
                         None if assignment is None else _dev_ptr(assignment, torch.int32, 1,
                                                                  "assignment"),
                         _np_ptr(ini), int(kmeans_iters), _STORAGE[storage],
-                        _CSTORAGE[centroid_storage])
+                        _CSTORAGE[centroid_storage], seed_mode)
         h = C.c_void_p()
         _check(lib().lider_build(cp, n, d, C.byref(P), _stream(stream), C.byref(h)))
         self._h = h
@@ -262,6 +269,19 @@ def kmeans_assign(X, cent, stream=None):
     _check(lib().lider_kmeans_assign(xp, X.shape[0], X.shape[1], cp, cent.shape[0],
                                      C.c_void_p(out.data_ptr()), _stream(stream)))
     return out
+
+
+def profile_begin(max_calls):
+    """Time the stages of this thread's next max_calls searches (HIP events)."""
+    _check(lib().lider_profile_begin(int(max_calls)))
+
+
+def profile_end():
+    """Return ({stage: summed ms}, timed calls) of the profiled searches."""
+    ms = (C.c_double * NSTAGES)()
+    calls = C.c_int32(0)
+    _check(lib().lider_profile_end(ms, C.byref(calls)))
+    return {STAGES[i]: float(ms[i]) for i in range(NSTAGES)}, int(calls.value)
 
 
 def fail_next(status):

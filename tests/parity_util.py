@@ -8,7 +8,7 @@ SCORE_TOL = 1e-4  # |score difference| <= SCORE_TOL * |q| * |x| (fp32 vs FP64)
 
 
 def build_pair(X, n_clusters, m, w, F, A, b, assignment=None, init_ids=None, iters=20, F1=0,
-               storage="f32", centroid_storage="f32"):
+               storage="f32", centroid_storage="f32", seeding="given"):
     """GPU index and oracle index over the same host data."""
     import torch
     from paper_2205_00970_amd import lider
@@ -17,9 +17,10 @@ def build_pair(X, n_clusters, m, w, F, A, b, assignment=None, init_ids=None, ite
         np.ascontiguousarray(assignment, dtype=np.int32)).cuda()
     gi = lider.Index(Xd, n_clusters, m, w, F, (A, b), rmi_fanout_l1=F1, kmeans_init=init_ids,
                      kmeans_iters=iters, assignment=asg_d, storage=storage,
-                     centroid_storage=centroid_storage)
+                     centroid_storage=centroid_storage, seeding=seeding)
     oi = oracle.Index(X, n_clusters, A, b, m, w, F, rmi_fanout_l1=(F1 or None),
-                      assignment=assignment, init_ids=init_ids, kmeans_iters=iters)
+                      assignment=assignment, init_ids=init_ids, kmeans_iters=iters,
+                      seeding=seeding)
     return gi, oi, Xd
 
 

@@ -41,7 +41,7 @@ int main(void) {
   printf("lider_build_params %zu\n", sizeof(lider_build_params));
   P(lider_build_params, w) P(lider_build_params, lsh_a_host) P(lider_build_params, assignment_dev)
   P(lider_build_params, kmeans_init_host) P(lider_build_params, kmeans_iters)
-  P(lider_build_params, centroid_storage)
+  P(lider_build_params, centroid_storage) P(lider_build_params, kmeans_seeding)
   printf("lider_search_opts %zu\n", sizeof(lider_search_opts));
   P(lider_search_opts, grid_mult)
   printf("lider_search_debug %zu\n", sizeof(lider_search_debug));
@@ -64,6 +64,7 @@ int main(void) {
         "lider_build_params.kmeans_init_host": lider.BuildParams.kmeans_init_host.offset,
         "lider_build_params.kmeans_iters": lider.BuildParams.kmeans_iters.offset,
         "lider_build_params.centroid_storage": lider.BuildParams.centroid_storage.offset,
+        "lider_build_params.kmeans_seeding": lider.BuildParams.kmeans_seeding.offset,
         "lider_search_opts": C.sizeof(lider.SearchOpts),
         "lider_search_opts.grid_mult": lider.SearchOpts.grid_mult.offset,
         "lider_search_debug": C.sizeof(lider.SearchDebug),

@@ -102,6 +102,26 @@ def test_mid_schedules_identical(mid):
     assert torch.equal(sub[0], ref[0][37:90]) and torch.equal(sub[1], ref[1][37:90])
 
 
+@pytest.mark.parametrize("n,C,d", [(20000, 16, 128), (30000, 48, 768)])
+def test_farthest_first_kmeans_bit_exact(n, C, d):
+    """Farthest-first seeding + Lloyd: every integer decision in FP64."""
+    torch = _torch()
+    if d == 128:
+        X, lab, Q, src = datagen.tiny(n=n, d=d, ncomp=C, seed=30, qseed=31)
+    else:
+        Xt, lab = datagen.mixture(n, d, ncomp=C, seed=32, device="cpu")
+        X = Xt.numpy()
+        Q = datagen.queries_from(Xt, 64, 0.1, seed=33)[0].numpy()
+    A, b = datagen.lsh_params(6, d, 2.0, seed=34)
+    init = datagen.kmeans_init(n, C, seed=35)
+    gi, oi, _ = build_pair(X, C, 6, 2.0, 8, A, b, init_ids=init, iters=15, seeding="farthest")
+    compare_index(gi, oi)
+    ids, sc, dbg = gi.search(torch.from_numpy(Q).cuda(), 10, 2, 4000, r1=C, debug=True)
+    oids, osc, odbg = oi.search(Q, 10, 2, 4000, C, debug=True)
+    compare_debug(dbg, odbg)
+    compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+
+
 @pytest.mark.parametrize("d", [100, 130])
 def test_odd_dimensions(d):
     """d not a multiple of 16 (MFMA tail) and not a multiple of 4 (scalar path)."""

@@ -205,6 +205,32 @@ def test_kmeans_recovers_separated_blobs():
         assert np.allclose(cent[j], X[lab == j].astype(np.float64).mean(0), atol=1e-5)
 
 
+def test_farthest_first_seeds_match_numpy_maximin():
+    g = np.random.default_rng(16)
+    X = (g.standard_normal((700, 12)) * g.uniform(0.5, 3, (700, 1))).astype(np.float32)
+    ids = oracle.kmeans_seed_farthest(X, 9, 5)
+    Xd = X.astype(np.float64)
+    ref = [5]
+    D = np.full(700, np.inf)
+    for t in range(1, 9):
+        D = np.minimum(D, ((Xd - Xd[ref[-1]]) ** 2).sum(1))
+        ref.append(int(np.argmax(D)))  # first maximum = smallest id
+    assert list(ids) == ref
+    # every chosen row maximises the distance to its nearest earlier centre
+    for t in range(1, 9):
+        dmin = ((Xd[:, None, :] - Xd[ids[:t]][None]) ** 2).sum(-1).min(1)
+        assert dmin[ids[t]] == dmin.max()
+
+
+def test_farthest_first_seeds_every_blob():
+    g = np.random.default_rng(17)
+    centers = g.standard_normal((7, 20)) * 30
+    lab = np.repeat(np.arange(7), 50)
+    X = (centers[lab] + g.standard_normal((350, 20))).astype(np.float32)
+    ids = oracle.kmeans_seed_farthest(X, 7, 0)
+    assert sorted(lab[ids].tolist()) == list(range(7))
+
+
 def test_kmeans_objective_never_increases():
     X, lab, _, _ = datagen.tiny(n=3000, d=32)
     init = datagen.kmeans_init(3000, 16)
