@@ -44,7 +44,7 @@ void free_device(Index& ix) {
                   ix.cent8,  ix.cent8_scale, ix.l1_order, ix.l1_order32, ix.l1_keys,
                   ix.l1_digits, ix.A,        ix.b,        ix.anorm,     ix.cent_norm_max,
                   ix.models, ix.leaves,      ix.leaf_err, ix.tiles[0],  ix.tiles[1],
-                  ix.tiles[2]};
+                  ix.tiles[2], ix.l1_off,    ix.l1_tiles};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }

@@ -458,7 +458,23 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
                    "copy tile table");
     if (rc != LIDER_OK) return rc;
   }
-  return LIDER_OK;
+  {  // layer-1 tiles
+    std::vector<int32_t> t;
+    for (int32_t r0 = 0; r0 < C; r0 += 64) {
+      t.push_back(0);
+      t.push_back(r0);
+    }
+    const int64_t lo[2] = {0, C};
+    ix.n_l1_tiles = int32_t(t.size() / 2);
+    if (hipMalloc(&ix.l1_tiles, al256(t.size() * 4)) != hipSuccess ||
+        hipMalloc(&ix.l1_off, 256) != hipSuccess)
+      return set_error(LIDER_ENOMEM, "out of device memory (layer-1 tiles)");
+    rc = check_hip(hipMemcpy(ix.l1_tiles, t.data(), t.size() * 4, hipMemcpyHostToDevice),
+                   "copy layer-1 tiles");
+    if (rc == LIDER_OK)
+      rc = check_hip(hipMemcpy(ix.l1_off, lo, sizeof(lo), hipMemcpyHostToDevice), "copy offsets");
+  }
+  return rc;
 }
 
 }  // namespace lider

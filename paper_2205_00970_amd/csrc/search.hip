@@ -42,8 +42,8 @@ struct alignas(16) Pair {
 constexpr int kCtrWords = 64;
 
 struct Plan {
-  size_t o_ctr, o_qdig, o_hlist, o_qnorm, o_l1, o_rs, o_rs64, o_routed, o_pairs, o_ccount,
-      o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, total;
+  size_t o_ctr, o_qdig, o_hlist, o_qnorm, o_l1, o_l1p, o_l1cs, o_rs, o_rs64, o_routed, o_pairs,
+      o_ccount, o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, total;
   int32_t r1, rcap, S;
 };
 
@@ -65,6 +65,8 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   p.o_hlist = take(size_t(nq) * 2 * ix.m * 8);
   p.o_qnorm = take(size_t(nq) * 4);
   p.o_l1 = take(size_t(nq) * 3 * 4);
+  p.o_l1p = take(size_t(nq) * sizeof(Pair));
+  p.o_l1cs = take(2 * 4);
   p.o_rs = take(size_t(nq) * r1 * 4);
   p.o_rs64 = take(size_t(nq) * r1 * 8);
   p.o_routed = take(size_t(nq) * c * 4);
@@ -74,7 +76,7 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   p.o_cfill = take(size_t(ix.C) * 4);
   p.o_wl = take(size_t(nq) * c * 4);
   p.o_sbuf = take(size_t(nq) * c * rcap * 4);
-  p.o_qb = take(S ? size_t(nq) * ix.d * 2 : 0);
+  p.o_qb = take((S || ix.cent8) ? size_t(nq) * ix.d * 2 : 0);
   p.o_slist = take(S ? size_t(nq) * S * 4 : 0);
   p.total = off;
   p.r1 = r1;
@@ -272,10 +274,18 @@ __host__ __device__ inline int pow2_at_least(int v) {
 }
 
 // ------------------------------------------------------------ layer 1
+// Centroids retriever: location and window of every query; the window is also
+// written as a (cluster 0, start, length) pair so the tile-scoring kernel can
+// score layer 1 exactly like a cluster of C rows.
 __global__ void l1_kernel(const Model* __restrict__ models, const double* __restrict__ leaves,
                           const int32_t* __restrict__ qdig, int32_t m, int64_t nq, int32_t C,
-                          int32_t r1, int32_t* __restrict__ l1) {
+                          int32_t r1, int32_t* __restrict__ l1, Pair* __restrict__ l1pairs,
+                          int32_t* __restrict__ l1cs) {
   const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q == 0) {
+    l1cs[0] = 0;
+    l1cs[1] = int32_t(nq);
+  }
   if (q >= nq) return;
   const int64_t pos = locate(models[C], leaves, qdig + q * 2 * m);
   int64_t s, len;
@@ -283,53 +293,141 @@ __global__ void l1_kernel(const Model* __restrict__ models, const double* __rest
   l1[3 * q] = int32_t(pos);
   l1[3 * q + 1] = int32_t(s);
   l1[3 * q + 2] = int32_t(len);
-}
-
-// Decode one OCP fp8 e4m3 byte (exact in fp32).
-__device__ inline float e4m3_value(uint8_t v) {
-  const int e = (v >> 3) & 15, mnt = v & 7;
-  float a = e == 0 ? float(mnt) * 0.001953125f : ldexpf(1.f + float(mnt) * 0.125f, e - 7);
-  if (e == 15 && mnt == 7) a = __uint_as_float(0x7fc00000u);
-  return (v & 0x80) ? -a : a;
+  l1pairs[q] = Pair{0, int32_t(s), int32_t(len), int32_t(pos)};
 }
 
 constexpr int kRouteNT = 256;
 
-// One workgroup per query: score the window centroids, pick the top c.
-// FP8 = precision form (per-row-scaled fp8 centroids, no FP64 decision).
+__device__ inline uint64_t wave_min_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t lo = __shfl_xor(uint32_t(v), o);
+    const uint32_t hi = __shfl_xor(uint32_t(v >> 32), o);
+    const uint64_t ov = (uint64_t(hi) << 32) | lo;
+    v = ov < v ? ov : v;
+  }
+  return v;
+}
+
+// Error bound of one fp32 window score against its FP64 definition.
+__device__ inline double route_err(int d, float qn, float cmax) {
+  return dot_err_coef(d) * double(qn) * double(cmax) + double(d) * 7.888609052210118e-31;
+}
+
+// FP64 decision of the routed set by one wave: sequential FP64 inner products
+// of every window centroid, then c rounds of (score desc, cluster id asc).
+__device__ void route_fp64_wave(const float* __restrict__ qv, int32_t d,
+                                const float* __restrict__ cent_l1,
+                                const int32_t* __restrict__ l1_order32, int32_t s1, int32_t len1,
+                                int32_t c, double* __restrict__ r64, int32_t* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  for (int p = lane; p < len1; p += 64) {
+    const float* mu = cent_l1 + int64_t(s1 + p) * d;
+    double acc = 0.0;
+    for (int l = 0; l < d; ++l) acc = acc + double(qv[l]) * double(mu[l]);
+    r64[p] = acc;
+  }
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+  for (int t = 0; t < c; ++t) {
+    double bv = -INFINITY;
+    int32_t bi = 0x7fffffff, bp = -1;
+    for (int p = lane; p < len1; p += 64) {
+      const double v = r64[p];
+      if (v == -INFINITY) continue;  // already chosen
+      const int32_t id = l1_order32[s1 + p];
+      if (bp < 0 || v > bv || (v == bv && id < bi)) {
+        bv = v;
+        bi = id;
+        bp = p;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o);
+      const int32_t oi = __shfl_xor(bi, o), op = __shfl_xor(bp, o);
+      if (op >= 0 && (bp < 0 || ov > bv || (ov == bv && oi < bi))) {
+        bv = ov;
+        bi = oi;
+        bp = op;
+      }
+    }
+    if (lane == 0) {
+      out[t] = bp >= 0 ? bi : -1;
+      if (bp >= 0) r64[bp] = -INFINITY;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Routing, one wave per query (c + 1 <= 64): extract the c + 1 best window
+// scores by repeated wave minima of (key, position); if the c-th and
+// (c+1)-th are closer than the error band, decide in FP64.
 template <bool FP8>
-__global__ __launch_bounds__(kRouteNT) void route_kernel(
+__global__ __launch_bounds__(256) void route_select_wave_kernel(
     const float* __restrict__ Q, int32_t d, int64_t nq, const float* __restrict__ cent_l1,
-    const uint8_t* __restrict__ cent8, const float* __restrict__ cent8_scale,
     const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
     const float* __restrict__ qnorm, const float* __restrict__ cent_norm_max, int32_t c,
-    int32_t r1, float* __restrict__ rs, double* __restrict__ rs64, int32_t* __restrict__ routed) {
+    int32_t r1, const float* __restrict__ rs, double* __restrict__ rs64,
+    int32_t* __restrict__ routed) {
+  __shared__ uint64_t ext[4][65];
+  __shared__ int32_t chosen[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
+    const int32_t s1 = l1[3 * q + 1], len1 = l1[3 * q + 2];
+    const float* rsq = rs + q * r1;
+    const int want = min(len1, c + 1);
+    uint64_t prev = 0;
+    int got = 0;
+    for (int t = 0; t < want; ++t) {
+      uint64_t best = ~uint64_t(0);
+      for (int p = lane; p < len1; p += 64) {
+        const uint64_t v = (uint64_t(score_key(rsq[p])) << 32) | uint32_t(p);
+        if ((t == 0 || v > prev) && v < best) best = v;
+      }
+      best = wave_min_u64(best);
+      if (lane == 0) ext[wave][t] = best;
+      prev = best;
+      ++got;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    bool amb = false;
+    if (!FP8 && len1 > c) {
+      const double sc = double(key_score(uint32_t(ext[wave][c - 1] >> 32)));
+      const double sn = double(key_score(uint32_t(ext[wave][c] >> 32)));
+      amb = (sc - sn) <= 4.0 * route_err(d, qnorm[q], *cent_norm_max);
+    }
+    if (!amb) {
+      for (int t = lane; t < c; t += 64)
+        routed[q * c + t] =
+            t < min(got, c) ? l1_order32[s1 + int32_t(ext[wave][t] & 0xffffffffu)] : -1;
+    } else {
+      route_fp64_wave(Q + q * d, d, cent_l1, l1_order32, s1, len1, c, rs64 + q * r1,
+                      chosen[wave]);
+      for (int t = lane; t < c; t += 64) routed[q * c + t] = chosen[wave][t];
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Routing, one workgroup per query (any c): radix selection of c + 1.
+template <bool FP8>
+__global__ __launch_bounds__(kRouteNT) void route_select_block_kernel(
+    const float* __restrict__ Q, int32_t d, int64_t nq, const float* __restrict__ cent_l1,
+    const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
+    const float* __restrict__ qnorm, const float* __restrict__ cent_norm_max, int32_t c,
+    int32_t r1, const float* __restrict__ rs, double* __restrict__ rs64,
+    int32_t* __restrict__ routed) {
   __shared__ SelShared sh;
   __shared__ uint64_t srt[256];
   __shared__ int32_t sidx[256];
   __shared__ int s_amb;
-  __shared__ double rd[kRouteNT];
-  __shared__ int32_t ri[kRouteNT];
-  __shared__ int32_t rp[kRouteNT];
   __shared__ int32_t chosen[LIDER_MAX_C];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
-    const float* qv = Q + q * d;
     const int32_t s1 = l1[3 * q + 1], len1 = l1[3 * q + 2];
-    float* rsq = rs + q * r1;
-    for (int p = wave; p < len1; p += kRouteNT / 64) {
-      float acc = 0.f;
-      if (FP8) {
-        const uint8_t* mu = cent8 + int64_t(s1 + p) * d;
-        for (int l = lane; l < d; l += 64) acc += qv[l] * e4m3_value(mu[l]);
-      } else {
-        const float* mu = cent_l1 + int64_t(s1 + p) * d;
-        for (int l = lane; l < d; l += 64) acc += qv[l] * mu[l];
-      }
-      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-      if (lane == 0) rsq[p] = FP8 ? acc * cent8_scale[s1 + p] : acc;
-    }
-    __syncthreads();
+    const float* rsq = rs + q * r1;
     const int K = min(c + 1, len1);
     const int KP = pow2_at_least(K);
     block_select<kRouteNT>(
@@ -338,11 +436,9 @@ __global__ __launch_bounds__(kRouteNT) void route_kernel(
     if (tid == 0) {
       s_amb = 0;
       if (!FP8 && len1 > c) {
-        const double E = dot_err_coef(d) * double(qnorm[q]) * double(*cent_norm_max) +
-                         double(d) * 7.888609052210118e-31;
         const double sc = double(key_score(uint32_t(srt[c - 1] >> 32)));
         const double sn = double(key_score(uint32_t(srt[c] >> 32)));
-        s_amb = (sc - sn) <= 4.0 * E;
+        s_amb = (sc - sn) <= 4.0 * route_err(d, qnorm[q], *cent_norm_max);
       }
     }
     __syncthreads();
@@ -350,52 +446,9 @@ __global__ __launch_bounds__(kRouteNT) void route_kernel(
       for (int t = tid; t < c; t += kRouteNT)
         routed[q * c + t] = t < len1 ? int32_t(srt[t] & 0xffffffffu) : -1;
     } else {
-      // FP64 decision: sequential FP64 inner products of every window centroid,
-      // then c rounds of (score desc, cluster id asc) selection.
-      double* r64 = rs64 + q * r1;
-      for (int p = tid; p < len1; p += kRouteNT) {
-        const float* mu = cent_l1 + int64_t(s1 + p) * d;
-        double acc = 0.0;
-        for (int l = 0; l < d; ++l) acc = acc + double(qv[l]) * double(mu[l]);
-        r64[p] = acc;
-      }
+      if (tid < 64)
+        route_fp64_wave(Q + q * d, d, cent_l1, l1_order32, s1, len1, c, rs64 + q * r1, chosen);
       __syncthreads();
-      for (int t = 0; t < c; ++t) {
-        double bd = -INFINITY;
-        int32_t bi = 0x7fffffff, bp = -1;
-        for (int p = tid; p < len1; p += kRouteNT) {
-          const double v = r64[p];
-          const int32_t id = l1_order32[s1 + p];
-          if (bp < 0 || v > bd || (v == bd && id < bi)) {
-            if (v == -INFINITY && bp >= 0) continue;
-            bd = v;
-            bi = id;
-            bp = p;
-          }
-        }
-        rd[tid] = bd;
-        ri[tid] = bi;
-        rp[tid] = bp;
-        __syncthreads();
-        for (int o = kRouteNT / 2; o > 0; o >>= 1) {
-          if (tid < o) {
-            const double ov = rd[tid + o];
-            const int32_t oi = ri[tid + o], op = rp[tid + o];
-            const bool better = op >= 0 && (rp[tid] < 0 || ov > rd[tid] || (ov == rd[tid] && oi < ri[tid]));
-            if (better) {
-              rd[tid] = ov;
-              ri[tid] = oi;
-              rp[tid] = op;
-            }
-          }
-          __syncthreads();
-        }
-        if (tid == 0) {
-          chosen[t] = ri[0];
-          r64[rp[0]] = -INFINITY;
-        }
-        __syncthreads();
-      }
       for (int t = tid; t < c; t += kRouteNT) routed[q * c + t] = chosen[t];
     }
     __syncthreads();
@@ -520,12 +573,18 @@ __device__ inline int32_t next_tile(int persistent, int32_t ntiles, int32_t* __r
 constexpr int kRerankWaves = 4;
 constexpr int kPassPairs = 32;
 
-template <bool BF16, bool VEC>
+// Operand feeds.  FMT 0: fp32 rows and queries; 1: bf16 rows and queries;
+// 2: fp8 e4m3 rows (decoded exactly to bf16) and bf16 queries.
+enum { kF32 = 0, kBF16 = 1, kFP8 = 2 };
+
+template <int FMT, bool VEC>
 struct Feed;
 
 template <bool VEC>
-struct Feed<false, VEC> {  // fp32: 16 dims per k-step, 4 per lane
+struct Feed<kF32, VEC> {  // 16 dims per k-step, 4 per lane
   static constexpr int KS = 16;
+  typedef float XE;
+  typedef float QE;
   typedef float4 T;
   __device__ static T load(const float* row, int k, int d) {
     if (VEC) {
@@ -539,6 +598,7 @@ struct Feed<false, VEC> {  // fp32: 16 dims per k-step, 4 per lane
     v.w = k + 3 < d ? row[k + 3] : 0.f;
     return v;
   }
+  __device__ static T loadx(const float* row, int k, int d) { return load(row, k, d); }
   __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.x, x.x, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.y, x.y, acc, 0, 0, 0);
@@ -547,41 +607,86 @@ struct Feed<false, VEC> {  // fp32: 16 dims per k-step, 4 per lane
   }
 };
 
+__device__ inline bf16x8 bf16x8_zero() {
+  bf16x8 z;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.f;
+  return z;
+}
+
 template <bool VEC>
-struct Feed<true, VEC> {  // bf16: 32 dims per k-step, 8 per lane (d % 8 == 0)
+struct Feed<kBF16, VEC> {  // 32 dims per k-step, 8 per lane (d % 8 == 0)
   static constexpr int KS = 32;
+  typedef __hip_bfloat16 XE;
+  typedef __hip_bfloat16 QE;
   typedef bf16x8 T;
   __device__ static T load(const __hip_bfloat16* row, int k, int d) {
     if (k < d) return *reinterpret_cast<const bf16x8*>(row + k);
-    T z;
+    return bf16x8_zero();
+  }
+  __device__ static T loadx(const __hip_bfloat16* row, int k, int d) { return load(row, k, d); }
+  __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(q, x, acc, 0, 0, 0);
+  }
+};
+
+// Decode one OCP fp8 e4m3 byte (exact in fp32 and in bf16).
+__device__ inline float e4m3_value(uint8_t v) {
+  const int e = (v >> 3) & 15, mnt = v & 7;
+  float a = e == 0 ? float(mnt) * 0.001953125f : ldexpf(1.f + float(mnt) * 0.125f, e - 7);
+  if (e == 15 && mnt == 7) a = __uint_as_float(0x7fc00000u);
+  return (v & 0x80) ? -a : a;
+}
+
+template <bool VEC>
+struct Feed<kFP8, VEC> {  // fp8 rows, bf16 queries, 32 dims per k-step (d % 8 == 0)
+  static constexpr int KS = 32;
+  typedef uint8_t XE;
+  typedef __hip_bfloat16 QE;
+  typedef bf16x8 T;
+  __device__ static T load(const __hip_bfloat16* row, int k, int d) {
+    if (k < d) return *reinterpret_cast<const bf16x8*>(row + k);
+    return bf16x8_zero();
+  }
+  __device__ static T loadx(const uint8_t* row, int k, int d) {
+    if (!(k < d)) return bf16x8_zero();
+    const uint2 raw = *reinterpret_cast<const uint2*>(row + k);
+    T v;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.f;
-    return z;
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t w = e < 4 ? raw.x : raw.y;
+      v[e] = (__bf16)e4m3_value(uint8_t(w >> (8 * (e & 3))));
+    }
+    return v;
   }
   __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(q, x, acc, 0, 0, 0);
   }
 };
 
-template <int RT, bool BF16, bool VEC>
+// wl == NULL: pair u of the cluster is pair u (identity work list).
+// pair_chunk > 0: workgroup (x, y) handles pairs [y*pair_chunk, (y+1)*pair_chunk)
+// of its tile's cluster.  row_scale (nullable) multiplies each row's scores.
+template <int RT, int FMT, bool VEC>
 __global__ __launch_bounds__(256) void rerank_kernel(
     const void* __restrict__ Xv, int32_t d, const int64_t* __restrict__ off,
     const int32_t* __restrict__ tiles, int32_t ntiles, const int32_t* __restrict__ cstart,
     const int32_t* __restrict__ wl, const Pair* __restrict__ pairs, int32_t c,
     const void* __restrict__ Qv, float* __restrict__ sbuf, int32_t rcap, int persistent,
-    int32_t* __restrict__ ctr) {
-  typedef typename std::conditional<BF16, __hip_bfloat16, float>::type E;
-  typedef Feed<BF16, VEC> F;
+    int32_t* __restrict__ ctr, int32_t pair_chunk, const float* __restrict__ row_scale) {
+  typedef Feed<FMT, VEC> F;
+  typedef typename F::XE XE;
+  typedef typename F::QE QE;
   constexpr int RC = RT / 16;
   __shared__ TileShared sh;
   __shared__ float part[kRerankWaves][kPassPairs][RT];
-  const E* X = static_cast<const E*>(Xv);
-  const E* Q = static_cast<const E*>(Qv);
+  const XE* X = static_cast<const XE*>(Xv);
+  const QE* Q = static_cast<const QE*>(Qv);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i = lane & 15, s = lane >> 4;
   const int nsteps = (d + F::KS - 1) / F::KS;
   const int ks0 = wave * nsteps / kRerankWaves, ks1 = (wave + 1) * nsteps / kRerankWaves;
-  const int sub = BF16 ? 8 * s : 4 * s;
+  const int sub = F::KS == 32 ? 8 * s : 4 * s;
   int32_t state = 0;
   for (;;) {
     const int32_t tile = next_tile(persistent, ntiles, ctr, state, sh);
@@ -590,8 +695,12 @@ __global__ __launch_bounds__(256) void rerank_kernel(
     const int64_t base = off[j];
     const int32_t L = int32_t(off[j + 1] - base);
     const int32_t rows_here = min(RT, L - row0);
-    const int32_t plo = cstart[j], phi = cstart[j + 1];
-    const E* xr[RC];
+    int32_t plo = cstart[j], phi = cstart[j + 1];
+    if (pair_chunk > 0) {
+      plo += int32_t(blockIdx.y) * pair_chunk;
+      phi = min(phi, plo + pair_chunk);
+    }
+    const XE* xr[RC];
 #pragma unroll
     for (int rc = 0; rc < RC; ++rc)
       xr[rc] = X + (base + min(row0 + 16 * rc + i, row0 + rows_here - 1)) * d;
@@ -600,7 +709,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(
       __syncthreads();
       const int32_t pe = min(phi, pb + kPairCap);
       for (int32_t u = pb + tid; u < pe; u += 256) {
-        const int32_t pi = wl[u];
+        const int32_t pi = wl ? wl[u] : u;
         const Pair pr = pairs[pi];
         if (pr.s < row0 + rows_here && pr.s + pr.len > row0) {
           const int32_t slot = atomicAdd(&sh.cnt, 1);
@@ -621,13 +730,13 @@ __global__ __launch_bounds__(256) void rerank_kernel(
           acc[rc][0] = floatx4{0.f, 0.f, 0.f, 0.f};
           acc[rc][1] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
-        const E* q0 = Q + int64_t(sh.lq[g0 + min(i, np - 1)]) * d;
-        const E* q1 = Q + int64_t(sh.lq[g0 + min(16 + i, np - 1)]) * d;
+        const QE* q0 = Q + int64_t(sh.lq[g0 + min(i, np - 1)]) * d;
+        const QE* q1 = Q + int64_t(sh.lq[g0 + min(16 + i, np - 1)]) * d;
         for (int ks = ks0; ks < ks1; ++ks) {
           const int k = ks * F::KS + sub;
           typename F::T xv[RC];
 #pragma unroll
-          for (int rc = 0; rc < RC; ++rc) xv[rc] = F::load(xr[rc], k, d);
+          for (int rc = 0; rc < RC; ++rc) xv[rc] = F::loadx(xr[rc], k, d);
           const typename F::T qa = F::load(q0, k, d);
 #pragma unroll
           for (int rc = 0; rc < RC; ++rc) F::mfma(qa, xv[rc], acc[rc][0]);
@@ -655,6 +764,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(
             float v = part[0][pp][rr];
 #pragma unroll
             for (int w = 1; w < kRerankWaves; ++w) v += part[w][pp][rr];
+            if (row_scale) v *= row_scale[base + row];
             sbuf[int64_t(sh.lp[g0 + pp]) * rcap + (row - a)] = v;
           }
         }
@@ -763,6 +873,162 @@ __global__ __launch_bounds__(kSelNT) void select_kernel(
   }
 }
 
+// Per query top K (K <= 64), one wave per query: repeated wave minima of
+// (key, candidate index) extract the K + 1 best; an exact key tie at the K-th
+// place is resolved by original id over all tied candidates; the winners are
+// finally ordered by (score desc, id asc).  MODE 0 writes ids / scores, MODE 1
+// the shortlist of sorted-row indices.
+constexpr int kWaveKeyCache = 2048;
+
+template <int MODE>
+__global__ __launch_bounds__(256) void wave_select_kernel(
+    const Pair* __restrict__ pairs, const float* __restrict__ sbuf, int32_t rcap, int32_t c,
+    int64_t nq, int32_t K, const int64_t* __restrict__ off, const int32_t* __restrict__ perm32,
+    int64_t* __restrict__ ids, float* __restrict__ scores, int32_t kout,
+    int32_t* __restrict__ slist) {
+  __shared__ uint32_t keys[4][kWaveKeyCache];
+  __shared__ int32_t start[4][LIDER_MAX_C + 1];
+  __shared__ int32_t pj[4][LIDER_MAX_C], ps[4][LIDER_MAX_C];
+  __shared__ uint64_t ext[4][65];
+  __shared__ uint32_t wkey[4][64], wid[4][64];
+  __shared__ int64_t wrow[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
+    if (lane == 0) {
+      int32_t acc = 0;
+      for (int t = 0; t < c; ++t) {
+        const Pair pr = pairs[q * c + t];
+        start[wave][t] = acc;
+        pj[wave][t] = pr.j;
+        ps[wave][t] = pr.s;
+        acc += pr.j >= 0 ? pr.len : 0;
+      }
+      start[wave][c] = acc;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    const int32_t* st = start[wave];
+    const int32_t n = st[c];
+    const float* sbq = sbuf + q * int64_t(c) * rcap;
+    const bool cached = n <= kWaveKeyCache;
+    if (cached) {
+      for (int t = 0; t < c; ++t) {
+        const int32_t a = st[t], len = st[t + 1] - a;
+        for (int p = lane; p < len; p += 64) keys[wave][a + p] = score_key(sbq[int64_t(t) * rcap + p]);
+      }
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+    }
+    auto slot_of = [&](int32_t i) {
+      int lo = 0, hi = c;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (st[mid] <= i)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      return lo;
+    };
+    auto row_of = [&](int32_t i) {
+      const int t = slot_of(i);
+      return off[pj[wave][t]] + ps[wave][t] + (i - st[t]);
+    };
+    // extraction of the K + 1 smallest (key, index)
+    const int want = min(n, K + 1);
+    uint64_t prev = 0;
+    for (int r = 0; r < want; ++r) {
+      uint64_t best = ~uint64_t(0);
+      if (cached) {
+        for (int32_t i = lane; i < n; i += 64) {
+          const uint64_t v = (uint64_t(keys[wave][i]) << 32) | uint32_t(i);
+          if ((r == 0 || v > prev) && v < best) best = v;
+        }
+      } else {
+        for (int t = 0; t < c; ++t) {
+          const int32_t a = st[t], len = st[t + 1] - a;
+          for (int p = lane; p < len; p += 64) {
+            const uint64_t v =
+                (uint64_t(score_key(sbq[int64_t(t) * rcap + p])) << 32) | uint32_t(a + p);
+            if ((r == 0 || v > prev) && v < best) best = v;
+          }
+        }
+      }
+      best = wave_min_u64(best);
+      if (lane == 0) ext[wave][r] = best;
+      prev = best;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    const int got = min(want, K);
+    if (lane < got) {
+      const uint64_t v = ext[wave][lane];
+      const int64_t row = row_of(int32_t(v & 0xffffffffu));
+      wkey[wave][lane] = uint32_t(v >> 32);
+      wid[wave][lane] = uint32_t(perm32[row]);
+      wrow[wave][lane] = row;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    if (want == K + 1 && uint32_t(ext[wave][K - 1] >> 32) == uint32_t(ext[wave][K] >> 32)) {
+      // exact tie at the boundary: the tied places go to the smallest ids
+      const uint32_t T = uint32_t(ext[wave][K - 1] >> 32);
+      int need = 0;
+      for (int t = 0; t < K; ++t) need += wkey[wave][t] == T;
+      uint64_t last = 0;
+      for (int r = 0; r < need; ++r) {
+        uint64_t best = ~uint64_t(0);
+        for (int t = 0; t < c; ++t) {
+          const int32_t a = st[t], len = st[t + 1] - a;
+          for (int p = lane; p < len; p += 64) {
+            const uint32_t kk = cached ? keys[wave][a + p] : score_key(sbq[int64_t(t) * rcap + p]);
+            if (kk != T) continue;
+            const int64_t row = off[pj[wave][t]] + ps[wave][t] + p;
+            const uint64_t v = (uint64_t(uint32_t(perm32[row])) << 32) | uint32_t(row);
+            if ((r == 0 || v > last) && v < best) best = v;
+          }
+        }
+        best = wave_min_u64(best);
+        if (lane == 0) {
+          wid[wave][K - need + r] = uint32_t(best >> 32);
+          wrow[wave][K - need + r] = int64_t(uint32_t(best & 0xffffffffu));
+        }
+        last = best;
+      }
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+    }
+    // order the winners by (key, id) and write
+    int rank = 0;
+    uint32_t myk = 0, myid = 0;
+    int64_t myrow = 0;
+    if (lane < got) {
+      myk = wkey[wave][lane];
+      myid = wid[wave][lane];
+      myrow = wrow[wave][lane];
+      for (int u = 0; u < got; ++u) {
+        const uint32_t ku = wkey[wave][u], iu = wid[wave][u];
+        rank += (ku < myk) || (ku == myk && iu < myid);
+      }
+    }
+    if (MODE == 0) {
+      if (lane < got) {
+        ids[q * kout + rank] = int64_t(myid);
+        scores[q * kout + rank] = key_score(myk);
+      }
+      for (int t = got + lane; t < kout; t += 64) {
+        ids[q * kout + t] = -1;
+        scores[q * kout + t] = -INFINITY;
+      }
+    } else {
+      if (lane < got) slist[q * K + rank] = int32_t(myrow);
+      for (int t = got + lane; t < K; t += 64) slist[q * K + t] = -1;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // Precision form, second pass: exact fp32 inner products of the shortlisted
 // rows (from the fp32 copy), then the top k.  One workgroup per query; one
 // wave per row at a time, lanes over dimensions.
@@ -846,17 +1112,45 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
     grid = unsigned((nt + 7) / 8 * 8);
   const bool vec = (ix.d % 4 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
   if (bf16)
-    hipLaunchKernelGGL((rerank_kernel<RT, true, true>), dim3(grid), dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<RT, kBF16, true>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.Xb, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Qb, sbuf, rcap, persistent, ctr);
+                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr);
   else if (vec)
-    hipLaunchKernelGGL((rerank_kernel<RT, false, true>), dim3(grid), dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<RT, kF32, true>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.X, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Q, sbuf, rcap, persistent, ctr);
+                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr);
   else
-    hipLaunchKernelGGL((rerank_kernel<RT, false, false>), dim3(grid), dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<RT, kF32, false>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.X, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Q, sbuf, rcap, persistent, ctr);
+                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr);
+}
+
+// Layer-1 window scores: the centroids (layer-1 order) are one "cluster" of C
+// rows tiled by 64, every query is one pair with its r1-window; the query list
+// is split over gridDim.y.
+constexpr int kL1PairChunk = 256;
+
+void launch_l1_scores(const Index& ix, bool fp8, int64_t nq, const int32_t* l1cs,
+                      const Pair* l1pairs, const float* Q, const __hip_bfloat16* Qb, float* rs,
+                      int32_t r1, hipStream_t st) {
+  const int32_t nt = ix.n_l1_tiles;
+  const dim3 grid(unsigned((nt + 7) / 8 * 8), unsigned((nq + kL1PairChunk - 1) / kL1PairChunk));
+  const bool vec = (ix.d % 4 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
+  if (fp8)
+    hipLaunchKernelGGL((rerank_kernel<64, kFP8, true>), grid, dim3(256), 0, st,
+                       (const void*)ix.cent8, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
+                       (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
+                       (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale);
+  else if (vec)
+    hipLaunchKernelGGL((rerank_kernel<64, kF32, true>), grid, dim3(256), 0, st,
+                       (const void*)ix.cent_l1, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
+                       (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
+                       (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr);
+  else
+    hipLaunchKernelGGL((rerank_kernel<64, kF32, false>), grid, dim3(256), 0, st,
+                       (const void*)ix.cent_l1, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
+                       (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
+                       (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr);
 }
 
 }  // namespace
@@ -879,6 +1173,8 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   int64_t* hlist = reinterpret_cast<int64_t*>(W + p.o_hlist);
   float* qnorm = reinterpret_cast<float*>(W + p.o_qnorm);
   int32_t* l1 = reinterpret_cast<int32_t*>(W + p.o_l1);
+  Pair* l1pairs = reinterpret_cast<Pair*>(W + p.o_l1p);
+  int32_t* l1cs = reinterpret_cast<int32_t*>(W + p.o_l1cs);
   float* rs = reinterpret_cast<float*>(W + p.o_rs);
   double* rs64 = reinterpret_cast<double*>(W + p.o_rs64);
   int32_t* routed = reinterpret_cast<int32_t*>(W + p.o_routed);
@@ -906,24 +1202,38 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   if (rc != LIDER_OK) return rc;
   mark(1);
   hipLaunchKernelGGL(l1_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, st, ix.models,
-                     ix.leaves, qdig, m, nq, C, p.r1, l1);
+                     ix.leaves, qdig, m, nq, C, p.r1, l1, l1pairs, l1cs);
+  const bool fp8 = bf16 && ix.cent8;
+  if (fp8 || bf16)
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(2048), dim3(256), 0, st, Q, nq * ix.d, qb);
+  launch_l1_scores(ix, fp8, nq, l1cs, l1pairs, Q, qb, rs, p.r1, st);
   const unsigned qgrid = unsigned(std::min<int64_t>(nq, 65535));
-  if (bf16 && ix.cent8)
-    hipLaunchKernelGGL(route_kernel<true>, dim3(qgrid), dim3(kRouteNT), 0, st, Q, ix.d, nq,
-                       ix.cent_l1, ix.cent8, ix.cent8_scale, ix.l1_order32, l1, qnorm,
-                       ix.cent_norm_max, c, p.r1, rs, rs64, routed);
-  else
-    hipLaunchKernelGGL(route_kernel<false>, dim3(qgrid), dim3(kRouteNT), 0, st, Q, ix.d, nq,
-                       ix.cent_l1, ix.cent8, ix.cent8_scale, ix.l1_order32, l1, qnorm,
-                       ix.cent_norm_max, c, p.r1, rs, rs64, routed);
+  const unsigned wgrid = unsigned(std::min<int64_t>((nq + 3) / 4, 65535));
+  if (c + 1 <= 64) {
+    if (fp8)
+      hipLaunchKernelGGL(route_select_wave_kernel<true>, dim3(wgrid), dim3(256), 0, st, Q, ix.d,
+                         nq, ix.cent_l1, ix.l1_order32, l1, qnorm, ix.cent_norm_max, c, p.r1, rs,
+                         rs64, routed);
+    else
+      hipLaunchKernelGGL(route_select_wave_kernel<false>, dim3(wgrid), dim3(256), 0, st, Q, ix.d,
+                         nq, ix.cent_l1, ix.l1_order32, l1, qnorm, ix.cent_norm_max, c, p.r1, rs,
+                         rs64, routed);
+  } else {
+    if (fp8)
+      hipLaunchKernelGGL(route_select_block_kernel<true>, dim3(qgrid), dim3(kRouteNT), 0, st, Q,
+                         ix.d, nq, ix.cent_l1, ix.l1_order32, l1, qnorm, ix.cent_norm_max, c,
+                         p.r1, rs, rs64, routed);
+    else
+      hipLaunchKernelGGL(route_select_block_kernel<false>, dim3(qgrid), dim3(kRouteNT), 0, st, Q,
+                         ix.d, nq, ix.cent_l1, ix.l1_order32, l1, qnorm, ix.cent_norm_max, c,
+                         p.r1, rs, rs64, routed);
+  }
   mark(2);
   hipLaunchKernelGGL(pairs_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, ix.models,
                      ix.leaves, qdig, m, np, c, r, routed, pairs, ccount);
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, ccount, C, cstart);
   hipLaunchKernelGGL(scatter_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, pairs, np,
                      cstart, cfill, wl);
-  if (bf16)
-    hipLaunchKernelGGL(to_bf16_kernel, dim3(2048), dim3(256), 0, st, Q, nq * ix.d, qb);
   mark(3);
   const int tr = o.tile_rows == 32 ? 32 : o.tile_rows == 128 ? 128 : 64;
   const int ti = tr == 32 ? 0 : tr == 64 ? 1 : 2;
@@ -939,14 +1249,20 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
                       ctr + 8, st);
   mark(4);
   if (!bf16) {
-    if (k <= 128)
+    if (k <= 64)
+      hipLaunchKernelGGL(wave_select_kernel<0>, dim3(wgrid), dim3(256), 0, st, pairs, sbuf, p.rcap,
+                         c, nq, k, ix.off, ix.perm32, ids, scores, k, slist);
+    else if (k <= 128)
       hipLaunchKernelGGL((select_kernel<128, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
                          p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist);
     else
       hipLaunchKernelGGL((select_kernel<1024, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
                          p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist);
   } else {
-    if (p.S <= 512)
+    if (p.S <= 64)
+      hipLaunchKernelGGL(wave_select_kernel<1>, dim3(wgrid), dim3(256), 0, st, pairs, sbuf, p.rcap,
+                         c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist);
+    else if (p.S <= 512)
       hipLaunchKernelGGL((select_kernel<512, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
                          p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist);
     else

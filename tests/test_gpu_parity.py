@@ -193,3 +193,33 @@ def test_errors_and_edge_cases(tiny):
     assert torch.equal(ids1, ids2)
     with pytest.raises(lider.LiderError):
         gi.search(Qd, 10, 4, 64, precision="bf16")  # index has no bf16 copy
+
+
+@pytest.mark.parametrize("k", [10, 100])
+def test_precision_form(mid, k):
+    """bf16 windows + fp8 routing + fp32 rerank of a 4k shortlist: every
+    returned score is the exact fp32 score of its id (within tolerance of
+    FP64), ids are unique, and the results agree closely with the fp32 path."""
+    torch = _torch()
+    from paper_2205_00970_amd import lider
+    X, Q = mid["X"], mid["Q"]
+    A, b = datagen.lsh_params(8, 768, 2.0, seed=7)
+    lab = mid["oi"].assignment()
+    gi = lider.Index(torch.from_numpy(X).cuda(), 64, 8, 2.0, 16, (A, b), rmi_fanout_l1=4,
+                     assignment=torch.from_numpy(lab).cuda(), storage="bf16",
+                     centroid_storage="fp8")
+    Qd = torch.from_numpy(Q).cuda()
+    ids, sc = gi.search(Qd, k, 4, 4000, r1=64, precision="bf16")
+    ref, _ = gi.search(Qd, k, 4, 4000, r1=64)
+    ids, sc, ref = ids.cpu().numpy(), sc.cpu().numpy(), ref.cpu().numpy()
+    qn = np.linalg.norm(Q.astype(np.float64), axis=1)
+    xn = np.linalg.norm(X.astype(np.float64), axis=1)
+    agree = 0
+    for q in range(Q.shape[0]):
+        g = ids[q][ids[q] >= 0]
+        assert len(set(g.tolist())) == len(g)
+        s64 = oracle.pair_scores(X, Q, np.full(len(g), q), g)
+        assert np.all(np.abs(sc[q][:len(g)] - s64) <= 1e-4 * qn[q] * xn[g])
+        assert np.all(np.diff(sc[q][:len(g)]) <= 0)
+        agree += len(set(g.tolist()) & set(ref[q][ref[q] >= 0].tolist()))
+    assert agree >= 0.95 * (ref >= 0).sum()
