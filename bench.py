@@ -91,6 +91,8 @@ def main():
                     help="profiling run: no sweep, no side measurements, no CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calib", action="store_true",
+                    help="also run a plain 1 GiB fp32 copy kernel (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -196,6 +198,14 @@ def main():
         f"{achieved:,.0f} GB/s ({achieved / 8000:.1%} of 8 TB/s)")
 
     extra = {}
+    if args.calib:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).uniform_()
+        bcopy = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=bcopy)
+        torch.cuda.synchronize()
+        del a, bcopy
+        log("calibration copy: 3 x (1 GiB read + 1 GiB write)")
     if not args.quick:
         # literal point (c=8, r=256, r1=r) for k=10 and k=100
         for kk in (10, 100):

@@ -12,21 +12,24 @@
 
 namespace lider {
 
-// Projection kernel.  Block = 4 waves = 64 rows; lane l of a wave owns row /
-// hash (l % 16) and the dimension slot s = l / 16: for each 16-dimension step
-// the lane loads 4 consecutive dims [k0 + 4s, k0 + 4s + 4) of its row and of
-// its hash vector and feeds them to 4 MFMAs (the k index of an MFMA only needs
-// to map to the same dimension on both operands).
+// Projection kernel.  Block = 4 waves = 16 rows; the waves split the
+// dimension range (wave w owns a contiguous quarter of the 16-dimension
+// steps).  Lane l of a wave owns row / hash (l % 16) and the dimension slot
+// s = l / 16: per step it loads 4 consecutive dims [k0 + 4s, k0 + 4s + 4) of
+// its row and of its hash vector and feeds them to 4 MFMAs (the k index of an
+// MFMA only needs to map to the same dimension on both operands).  Partial
+// projections are added in wave order through LDS.
 template <bool VEC>
 __global__ __launch_bounds__(256) void hash_kernel(
     const float* __restrict__ X, int64_t n, int32_t d, const float* __restrict__ A,
     const float* __restrict__ bvec, const float* __restrict__ anorm, int32_t nh, double w,
     int32_t* __restrict__ out, int64_t* __restrict__ list, int32_t* __restrict__ counter,
     int32_t* __restrict__ status, int clamp, float* __restrict__ rownorm) {
+  __shared__ float part[4][32][16];  // [wave][hash][row]
+  __shared__ float pss[4][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, s = lane >> 4;
-  const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
-  if (row0 >= n) return;
+  const int64_t row0 = int64_t(blockIdx.x) * 16;
   int64_t myrow = row0 + i;
   if (myrow >= n) myrow = n - 1;  // keep loads in bounds; outputs are skipped
   const float* xr = X + myrow * d;
@@ -37,69 +40,111 @@ __global__ __launch_bounds__(256) void hash_kernel(
   const bool two = nh > 16;
   floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
   float ss = 0.f;
-  const int dfull = VEC ? (d & ~15) : 0;
-  for (int k0 = 0; k0 < dfull; k0 += 16) {
-    const int kk = k0 + 4 * s;
-    float4 xv = *reinterpret_cast<const float4*>(xr + kk);
-    float4 av = *reinterpret_cast<const float4*>(a0 + kk);
-    ss += xv.x * xv.x + xv.y * xv.y + xv.z * xv.z + xv.w * xv.w;
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, av.x, acc0, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, av.y, acc0, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, av.z, acc0, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, av.w, acc0, 0, 0, 0);
-    if (two) {
-      float4 bv = *reinterpret_cast<const float4*>(a1 + kk);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, bv.x, acc1, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, bv.y, acc1, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, bv.z, acc1, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, bv.w, acc1, 0, 0, 0);
-    }
-  }
-  for (int k0 = dfull; k0 < d; k0 += 16) {  // tail (or everything when !VEC)
+  const int nk = (d + 15) / 16;
+  const int k0s = wave * nk / 4, k1s = (wave + 1) * nk / 4;
+  for (int ks = k0s; ks < k1s; ++ks) {
+    const int kk = ks * 16 + 4 * s;
     float xe[4], ae[4], be[4];
+    if (VEC && kk + 3 < d) {
+      const float4 xv = *reinterpret_cast<const float4*>(xr + kk);
+      const float4 av = *reinterpret_cast<const float4*>(a0 + kk);
+      const float4 bv = *reinterpret_cast<const float4*>(a1 + kk);
+      xe[0] = xv.x; xe[1] = xv.y; xe[2] = xv.z; xe[3] = xv.w;
+      ae[0] = av.x; ae[1] = av.y; ae[2] = av.z; ae[3] = av.w;
+      be[0] = bv.x; be[1] = bv.y; be[2] = bv.z; be[3] = bv.w;
+    } else {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int kk = k0 + 4 * s + e;
-      const bool in = kk < d;
-      xe[e] = in ? xr[kk] : 0.f;
-      ae[e] = in ? a0[kk] : 0.f;
-      be[e] = in ? a1[kk] : 0.f;
-      ss += xe[e] * xe[e];
+      for (int e = 0; e < 4; ++e) {
+        const bool in = kk + e < d;
+        xe[e] = in ? xr[kk + e] : 0.f;
+        ae[e] = in ? a0[kk + e] : 0.f;
+        be[e] = in ? a1[kk + e] : 0.f;
+      }
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
+      ss += xe[e] * xe[e];
       acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xe[e], ae[e], acc0, 0, 0, 0);
       if (two) acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xe[e], be[e], acc1, 0, 0, 0);
     }
   }
-  // |x|^2 of row i: sum the four dimension slots
+  // |x|^2 of row i over this wave's dims: sum the four dimension slots
   ss += __shfl_xor(ss, 16);
   ss += __shfl_xor(ss, 32);
-  const double coef = dot_err_coef(d);
-  const double gam = double(d + 2) * 5.9604644775390625e-08;
+  if (s == 0) pss[wave][i] = ss;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const int ri = 4 * s + e;
-    const float ssr = __shfl(ss, ri);
+    part[wave][i][4 * s + e] = acc0[e];
+    if (two) part[wave][16 + i][4 * s + e] = acc1[e];
+  }
+  __syncthreads();
+  const double coef = dot_err_coef(d);
+  const double gam = double(d + 2) * 5.9604644775390625e-08;
+  for (int o = threadIdx.x; o < 16 * nh; o += 256) {
+    const int ri = o / nh, hash = o - ri * nh;
     const int64_t row = row0 + ri;
+    if (row >= n) continue;
+    const float ssr = ((pss[0][ri] + pss[1][ri]) + pss[2][ri]) + pss[3][ri];
+    const float sv = ((part[0][hash][ri] + part[1][hash][ri]) + part[2][hash][ri]) + part[3][hash][ri];
     const double xn = sqrt(double(ssr) * (1.0 + 2.0 * gam)) * (1.0 + 9.5367431640625e-07);
-    if (rownorm && i == 0 && row < n) rownorm[row] = float(xn * (1.0 + 9.5367431640625e-07));
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int hash = t * 16 + i;
-      if (row >= n || hash >= nh) continue;
-      const float sv = t == 0 ? acc0[e] : acc1[e];
-      const double tv = (double(sv) + double(bvec[hash])) / w;
-      const double E = (coef * double(anorm[hash]) * xn + double(d) * 7.888609052210118e-31) / w +
-                       8.881784197001252e-16 * fabs(tv);
+    if (rownorm && hash == 0) rownorm[row] = float(xn * (1.0 + 9.5367431640625e-07));
+    const double tv = (double(sv) + double(bvec[hash])) / w;
+    const double E = (coef * double(anorm[hash]) * xn + double(d) * 7.888609052210118e-31) / w +
+                     8.881784197001252e-16 * fabs(tv);
+    const double fl = floor(tv);
+    const double fr = tv - fl;
+    const double dist = fr < 1.0 - fr ? fr : 1.0 - fr;
+    const int64_t oi = row * nh + hash;
+    if (!(dist > 2.0 * E)) {
+      const int32_t slot = atomicAdd(counter, 1);
+      list[slot] = oi;
+    } else if (fl >= -2147483648.0 && fl <= 2147483647.0) {
+      out[oi] = int32_t(fl);
+    } else if (clamp) {
+      out[oi] = fl < 0 ? INT32_MIN : INT32_MAX;
+    } else {
+      atomicExch(status, int32_t(LIDER_ERANGE));
+    }
+  }
+}
+
+// Sequential FP64 recompute of queued (row, hash) projections, one wave per
+// entry: the wave stages the row and the hash vector in LDS with coalesced
+// loads, then one lane sums the products in dimension order.
+constexpr int kFixupLds = 1024;
+
+__global__ __launch_bounds__(256) void hash_fixup_kernel(
+    const float* __restrict__ X, int32_t d, const float* __restrict__ A,
+    const float* __restrict__ bvec, int32_t nh, double w, int32_t* __restrict__ out,
+    const int64_t* __restrict__ list, const int32_t* __restrict__ counter,
+    int32_t* __restrict__ status, int clamp) {
+  __shared__ float sx[4][kFixupLds], sa[4][kFixupLds];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int32_t cnt = *counter;
+  const bool staged = d <= kFixupLds;
+  for (int32_t t = blockIdx.x * 4 + wave; t < cnt; t += gridDim.x * 4) {
+    const int64_t o = list[t];
+    const int64_t row = o / nh;
+    const int hash = int(o - row * nh);
+    const float* xr = X + row * d;
+    const float* ar = A + int64_t(hash) * d;
+    if (staged) {
+      for (int l = lane; l < d; l += 64) {
+        sx[wave][l] = xr[l];
+        sa[wave][l] = ar[l];
+      }
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (lane == 0) {
+      double sacc = 0.0;
+      if (staged)
+        for (int l = 0; l < d; ++l) sacc = sacc + double(sa[wave][l]) * double(sx[wave][l]);
+      else
+        for (int l = 0; l < d; ++l) sacc = sacc + double(ar[l]) * double(xr[l]);
+      const double tv = (sacc + double(bvec[hash])) / w;
       const double fl = floor(tv);
-      const double fr = tv - fl;
-      const double dist = fr < 1.0 - fr ? fr : 1.0 - fr;
-      const int64_t o = row * nh + hash;
-      if (!(dist > 2.0 * E)) {
-        const int32_t slot = atomicAdd(counter, 1);
-        list[slot] = o;
-      } else if (fl >= -2147483648.0 && fl <= 2147483647.0) {
+      if (fl >= -2147483648.0 && fl <= 2147483647.0) {
         out[o] = int32_t(fl);
       } else if (clamp) {
         out[o] = fl < 0 ? INT32_MIN : INT32_MAX;
@@ -107,33 +152,8 @@ __global__ __launch_bounds__(256) void hash_kernel(
         atomicExch(status, int32_t(LIDER_ERANGE));
       }
     }
-  }
-}
-
-// Sequential FP64 recompute of queued (row, hash) projections.
-__global__ __launch_bounds__(256) void hash_fixup_kernel(
-    const float* __restrict__ X, int32_t d, const float* __restrict__ A,
-    const float* __restrict__ bvec, int32_t nh, double w, int32_t* __restrict__ out,
-    const int64_t* __restrict__ list, const int32_t* __restrict__ counter,
-    int32_t* __restrict__ status, int clamp) {
-  const int32_t cnt = *counter;
-  for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
-    const int64_t o = list[t];
-    const int64_t row = o / nh;
-    const int hash = int(o - row * nh);
-    const float* xr = X + row * d;
-    const float* ar = A + int64_t(hash) * d;
-    double sacc = 0.0;
-    for (int l = 0; l < d; ++l) sacc = sacc + double(ar[l]) * double(xr[l]);
-    const double tv = (sacc + double(bvec[hash])) / w;
-    const double fl = floor(tv);
-    if (fl >= -2147483648.0 && fl <= 2147483647.0) {
-      out[o] = int32_t(fl);
-    } else if (clamp) {
-      out[o] = fl < 0 ? INT32_MIN : INT32_MAX;
-    } else {
-      atomicExch(status, int32_t(LIDER_ERANGE));
-    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -169,7 +189,7 @@ int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const floa
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, counter, int64_t(1));
   const bool vec = (d % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-  const dim3 grid(unsigned((n + 63) / 64));
+  const dim3 grid(unsigned((n + 15) / 16));
   if (vec)
     hipLaunchKernelGGL(hash_kernel<true>, grid, dim3(256), 0, st, X, n, d, A, b, anorm, nh, w,
                        out, list, counter, status, clamp, rownorm);
@@ -177,8 +197,8 @@ int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const floa
     hipLaunchKernelGGL(hash_kernel<false>, grid, dim3(256), 0, st, X, n, d, A, b, anorm, nh, w,
                        out, list, counter, status, clamp, rownorm);
   int64_t cap = n * nh;
-  int64_t blocks = (cap + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
+  int64_t blocks = (cap + 3) / 4;
+  if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(hash_fixup_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, X, d, A, b, nh,
                      w, out, list, counter, status, clamp);
   return check_hip(hipGetLastError(), "hash kernels");

@@ -580,6 +580,14 @@ enum { kF32 = 0, kBF16 = 1, kFP8 = 2 };
 template <int FMT, bool VEC>
 struct Feed;
 
+// Rows streamed once per launch are loaded with the non-temporal hint.
+template <class T>
+__device__ inline T stream_load(const T* p, bool nt) {
+  return nt ? __builtin_nontemporal_load(p) : *p;
+}
+
+// VEC = 16-byte loads; for fp32 VEC also means d % 16 == 0 (every k-step is
+// full), so loads carry no bounds branch and the k-loop pipelines.
 template <bool VEC>
 struct Feed<kF32, VEC> {  // 16 dims per k-step, 4 per lane
   static constexpr int KS = 16;
@@ -587,10 +595,7 @@ struct Feed<kF32, VEC> {  // 16 dims per k-step, 4 per lane
   typedef float QE;
   typedef float4 T;
   __device__ static T load(const float* row, int k, int d) {
-    if (VEC) {
-      if (k < d) return *reinterpret_cast<const float4*>(row + k);
-      return float4{0.f, 0.f, 0.f, 0.f};
-    }
+    if (VEC) return *reinterpret_cast<const float4*>(row + k);
     float4 v;
     v.x = k < d ? row[k] : 0.f;
     v.y = k + 1 < d ? row[k + 1] : 0.f;
@@ -598,7 +603,13 @@ struct Feed<kF32, VEC> {  // 16 dims per k-step, 4 per lane
     v.w = k + 3 < d ? row[k + 3] : 0.f;
     return v;
   }
-  __device__ static T loadx(const float* row, int k, int d) { return load(row, k, d); }
+  __device__ static T loadx(const float* row, int k, int d, bool nt) {
+    if (VEC) {
+      const floatx4 v = stream_load(reinterpret_cast<const floatx4*>(row + k), nt);
+      return float4{v[0], v[1], v[2], v[3]};
+    }
+    return load(row, k, d);
+  }
   __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.x, x.x, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.y, x.y, acc, 0, 0, 0);
@@ -614,17 +625,24 @@ __device__ inline bf16x8 bf16x8_zero() {
   return z;
 }
 
+// bf16 / fp8 feeds need d % 8 == 0; VEC additionally means d % 32 == 0.  A
+// partial last k-step reads a clamped in-bounds address and zeroes the value
+// (no branch around the load).
 template <bool VEC>
-struct Feed<kBF16, VEC> {  // 32 dims per k-step, 8 per lane (d % 8 == 0)
+struct Feed<kBF16, VEC> {  // 32 dims per k-step, 8 per lane
   static constexpr int KS = 32;
   typedef __hip_bfloat16 XE;
   typedef __hip_bfloat16 QE;
   typedef bf16x8 T;
   __device__ static T load(const __hip_bfloat16* row, int k, int d) {
-    if (k < d) return *reinterpret_cast<const bf16x8*>(row + k);
-    return bf16x8_zero();
+    if (VEC) return *reinterpret_cast<const bf16x8*>(row + k);
+    const bf16x8 v = *reinterpret_cast<const bf16x8*>(row + (k < d ? k : d - 8));
+    return k < d ? v : bf16x8_zero();
   }
-  __device__ static T loadx(const __hip_bfloat16* row, int k, int d) { return load(row, k, d); }
+  __device__ static T loadx(const __hip_bfloat16* row, int k, int d, bool nt) {
+    if (VEC) return stream_load(reinterpret_cast<const bf16x8*>(row + k), nt);
+    return load(row, k, d);
+  }
   __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(q, x, acc, 0, 0, 0);
   }
@@ -639,35 +657,83 @@ __device__ inline float e4m3_value(uint8_t v) {
 }
 
 template <bool VEC>
-struct Feed<kFP8, VEC> {  // fp8 rows, bf16 queries, 32 dims per k-step (d % 8 == 0)
+struct Feed<kFP8, VEC> {  // fp8 rows, bf16 queries, 32 dims per k-step
   static constexpr int KS = 32;
   typedef uint8_t XE;
   typedef __hip_bfloat16 QE;
   typedef bf16x8 T;
   __device__ static T load(const __hip_bfloat16* row, int k, int d) {
-    if (k < d) return *reinterpret_cast<const bf16x8*>(row + k);
-    return bf16x8_zero();
+    return Feed<kBF16, VEC>::load(row, k, d);
   }
-  __device__ static T loadx(const uint8_t* row, int k, int d) {
-    if (!(k < d)) return bf16x8_zero();
-    const uint2 raw = *reinterpret_cast<const uint2*>(row + k);
+  __device__ static T loadx(const uint8_t* row, int k, int d, bool nt) {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    const int kk = VEC ? k : (k < d ? k : d - 8);
+    const u32x2 rv = stream_load(reinterpret_cast<const u32x2*>(row + kk), nt);
     T v;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const uint32_t w = e < 4 ? raw.x : raw.y;
+      const uint32_t w = e < 4 ? rv[0] : rv[1];
       v[e] = (__bf16)e4m3_value(uint8_t(w >> (8 * (e & 3))));
     }
-    return v;
+    return (VEC || k < d) ? v : bf16x8_zero();
   }
   __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(q, x, acc, 0, 0, 0);
   }
 };
 
+// The k-loop of one pass, software-pipelined with two register sets (no
+// copies of loaded data): the loads of one step are in flight while the MFMAs
+// of the previous step run.  The last load of the paired loop is clamped to
+// the final step (a redundant cache hit when the step count is even).
+template <class F, int RC, int NPC, bool NT>
+__device__ __forceinline__ void load_step(const typename F::XE* const (&xr)[RC],
+                                          const typename F::QE* q0, const typename F::QE* q1,
+                                          int k, int d, typename F::T (&x)[RC],
+                                          typename F::T& qa, typename F::T& qb) {
+#pragma unroll
+  for (int rc = 0; rc < RC; ++rc) x[rc] = F::loadx(xr[rc], k, d, NT);
+  qa = F::load(q0, k, d);
+  if (NPC > 1) qb = F::load(q1, k, d);
+}
+
+template <class F, int RC, int NPC>
+__device__ __forceinline__ void mfma_step(const typename F::T (&x)[RC], const typename F::T& qa,
+                                          const typename F::T& qb, floatx4 (&acc)[RC][2]) {
+#pragma unroll
+  for (int rc = 0; rc < RC; ++rc) F::mfma(qa, x[rc], acc[rc][0]);
+  if (NPC > 1) {
+#pragma unroll
+    for (int rc = 0; rc < RC; ++rc) F::mfma(qb, x[rc], acc[rc][1]);
+  }
+}
+
+template <class F, int RC, int NPC, bool NT>
+__device__ __forceinline__ void pass_loop(const typename F::XE* const (&xr)[RC],
+                                          const typename F::QE* q0, const typename F::QE* q1,
+                                          int ks0, int ks1, int sub, int d,
+                                          floatx4 (&acc)[RC][2]) {
+  typename F::T xa[RC], xb[RC], qa0, qa1, qb0, qb1;
+  load_step<F, RC, NPC, NT>(xr, q0, q1, ks0 * F::KS + sub, d, xa, qa0, qa1);
+  int ks = ks0;
+  for (; ks + 1 < ks1; ks += 2) {
+    load_step<F, RC, NPC, NT>(xr, q0, q1, (ks + 1) * F::KS + sub, d, xb, qb0, qb1);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
+    mfma_step<F, RC, NPC>(xa, qa0, qa1, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    const int kn = (ks + 2 < ks1 ? ks + 2 : ks1 - 1) * F::KS + sub;
+    load_step<F, RC, NPC, NT>(xr, q0, q1, kn, d, xa, qa0, qa1);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_step<F, RC, NPC>(xb, qb0, qb1, acc);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (ks < ks1) mfma_step<F, RC, NPC>(xa, qa0, qa1, acc);
+}
+
 // wl == NULL: pair u of the cluster is pair u (identity work list).
 // pair_chunk > 0: workgroup (x, y) handles pairs [y*pair_chunk, (y+1)*pair_chunk)
 // of its tile's cluster.  row_scale (nullable) multiplies each row's scores.
-template <int RT, int FMT, bool VEC>
+template <int RT, int FMT, bool VEC, bool NT>
 __global__ __launch_bounds__(256) void rerank_kernel(
     const void* __restrict__ Xv, int32_t d, const int64_t* __restrict__ off,
     const int32_t* __restrict__ tiles, int32_t ntiles, const int32_t* __restrict__ cstart,
@@ -732,19 +798,11 @@ __global__ __launch_bounds__(256) void rerank_kernel(
         }
         const QE* q0 = Q + int64_t(sh.lq[g0 + min(i, np - 1)]) * d;
         const QE* q1 = Q + int64_t(sh.lq[g0 + min(16 + i, np - 1)]) * d;
-        for (int ks = ks0; ks < ks1; ++ks) {
-          const int k = ks * F::KS + sub;
-          typename F::T xv[RC];
-#pragma unroll
-          for (int rc = 0; rc < RC; ++rc) xv[rc] = F::loadx(xr[rc], k, d);
-          const typename F::T qa = F::load(q0, k, d);
-#pragma unroll
-          for (int rc = 0; rc < RC; ++rc) F::mfma(qa, xv[rc], acc[rc][0]);
-          if (npc > 1) {
-            const typename F::T qb = F::load(q1, k, d);
-#pragma unroll
-            for (int rc = 0; rc < RC; ++rc) F::mfma(qb, xv[rc], acc[rc][1]);
-          }
+        if (ks0 < ks1) {
+          if (npc > 1)
+            pass_loop<F, RC, 2, NT>(xr, q0, q1, ks0, ks1, sub, d, acc);
+          else
+            pass_loop<F, RC, 1, NT>(xr, q0, q1, ks0, ks1, sub, d, acc);
         }
 #pragma unroll
         for (int pc = 0; pc < 2; ++pc) {
@@ -1110,17 +1168,21 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
     grid = unsigned(std::max(8, ix.n_cu * grid_mult / 8 * 8));
   else
     grid = unsigned((nt + 7) / 8 * 8);
-  const bool vec = (ix.d % 4 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
-  if (bf16)
-    hipLaunchKernelGGL((rerank_kernel<RT, kBF16, true>), dim3(grid), dim3(256), 0, st,
+  const bool vec = (ix.d % 16 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
+  if (bf16 && ix.d % 32 != 0)
+    hipLaunchKernelGGL((rerank_kernel<RT, kBF16, false, true>), dim3(grid), dim3(256), 0, st,
+                       (const void*)ix.Xb, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr);
+  else if (bf16)
+    hipLaunchKernelGGL((rerank_kernel<RT, kBF16, true, true>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.Xb, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr);
   else if (vec)
-    hipLaunchKernelGGL((rerank_kernel<RT, kF32, true>), dim3(grid), dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<RT, kF32, true, true>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.X, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr);
   else
-    hipLaunchKernelGGL((rerank_kernel<RT, kF32, false>), dim3(grid), dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<RT, kF32, false, true>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.X, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr);
 }
@@ -1135,19 +1197,24 @@ void launch_l1_scores(const Index& ix, bool fp8, int64_t nq, const int32_t* l1cs
                       int32_t r1, hipStream_t st) {
   const int32_t nt = ix.n_l1_tiles;
   const dim3 grid(unsigned((nt + 7) / 8 * 8), unsigned((nq + kL1PairChunk - 1) / kL1PairChunk));
-  const bool vec = (ix.d % 4 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
-  if (fp8)
-    hipLaunchKernelGGL((rerank_kernel<64, kFP8, true>), grid, dim3(256), 0, st,
+  const bool vec = (ix.d % 16 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
+  if (fp8 && ix.d % 32 != 0)
+    hipLaunchKernelGGL((rerank_kernel<64, kFP8, false, false>), grid, dim3(256), 0, st,
+                       (const void*)ix.cent8, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
+                       (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
+                       (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale);
+  else if (fp8)
+    hipLaunchKernelGGL((rerank_kernel<64, kFP8, true, false>), grid, dim3(256), 0, st,
                        (const void*)ix.cent8, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale);
   else if (vec)
-    hipLaunchKernelGGL((rerank_kernel<64, kF32, true>), grid, dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<64, kF32, true, false>), grid, dim3(256), 0, st,
                        (const void*)ix.cent_l1, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr);
   else
-    hipLaunchKernelGGL((rerank_kernel<64, kF32, false>), grid, dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<64, kF32, false, false>), grid, dim3(256), 0, st,
                        (const void*)ix.cent_l1, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr);
