@@ -91,6 +91,13 @@ def main():
                     help="profiling run: no sweep, no side measurements, no CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", default="search", choices=["search", "batching", "serving"],
+                    help="search: the 1M x 768 headline; batching: 4M x 768 Zipf clusters, "
+                         "65,536 queries in batches of 1-4096; serving: see serving.py")
+    ap.add_argument("--serve-n", dest="serve_n", type=int, default=0,
+                    help="serving workload corpus size (default 21,000,000)")
+    ap.add_argument("--serve-queries", dest="serve_queries", type=int, default=0,
+                    help="queries per arrival rate in the serving workload (default 110,000)")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB fp32 copy kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -103,6 +110,11 @@ def main():
     from paper_2205_00970_amd import datagen, lider
 
     torch.backends.cuda.matmul.allow_tf32 = False
+    if args.workload == "batching":
+        return run_batching(args, torch, datagen, lider)
+    if args.workload == "serving":
+        from paper_2205_00970_amd import serving
+        return serving.bench_main(args, exact_topk, recall_at)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     n, d, C, m, w, F = args.n, 768, args.clusters, 8, 2.0, 64
@@ -260,6 +272,65 @@ def main():
         **extra,
     }
     print(json.dumps(line), flush=True)
+
+
+def run_batching(args, torch, datagen, lider):
+    """Batching form: N=4,000,000 d=768 (bf16 copy + fp32 master), 4,096 clusters
+    with Zipf(1.1) sizes in [50, 200,000] (the generator's components, given as
+    the clustering), 65,536 queries in batches of U[1, 4096]; c=16, r=512,
+    k=100.  Plain schedule vs the autotuned (possibly persistent) one."""
+    from paper_2205_00970_amd import autotune
+    dev = torch.device("cuda:0")
+    n, d, C, m, w, F = 4_000_000, 768, 4096, 8, 2.0, 64
+    k, c, r = 100, 16, 512
+    t0 = time.time()
+    sizes = datagen.zipf_sizes(n, C, 1.1, 50, 200_000)
+    X, lab = datagen.mixture(n, d, ncomp=C, seed=10, device="cuda", sizes=sizes)
+    Q, _ = datagen.queries_from(X, 65536, 0.1, seed=11)
+    A, b = datagen.lsh_params(m, d, w, seed=12)
+    torch.cuda.synchronize()
+    log(f"data {n}x{d}, cluster sizes {sizes.max()}..{sizes.min()}, in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    gi = lider.Index(X, C, m, w, F, (A, b), assignment=lab, storage="bf16", centroid_storage="fp8")
+    torch.cuda.synchronize()
+    log(f"build {time.time() - t0:.2f}s")
+    g = np.random.default_rng(13)
+    bs = []
+    tot = 0
+    while tot < Q.shape[0]:
+        bsz = int(min(g.integers(1, 4097), Q.shape[0] - tot))
+        bs.append((tot, bsz))
+        tot += bsz
+    sample = Q[:2048].contiguous()
+    gt_ids, gt_sc = exact_topk(torch, X, sample, k)
+    tuner = autotune.Autotuner(gi)
+    res = {"workload": f"gaussian-mixture N={n} d={d}, {C} Zipf(1.1) clusters "
+                       f"({int(sizes.min())}..{int(sizes.max())} rows), 65,536 queries in "
+                       f"{len(bs)} batches of U[1,4096]", "k": k, "c": c, "r": r}
+    for prec in ("f32", "bf16"):
+        for r1 in (r, C):
+            ids, _ = gi.search(sample, k, c, r, r1=r1, precision=prec)
+            rec = recall_at(torch, X, sample, ids, gt_sc, 10)
+            # tune every batch-size bucket on a representative batch
+            buckets = sorted({autotune.bucket(bsz) for _, bsz in bs})
+            for bk in buckets:
+                tuner.tune(Q[:min(bk, Q.shape[0])].contiguous(), k, c, r, r1, prec)
+            for mode in ("plain", "tuned"):
+                outs = []
+                for a, bsz in bs:  # warm (and allocate workspaces)
+                    gi.search(Q[a:a + bsz], k, c, r, r1=r1, precision=prec)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for a, bsz in bs:
+                    sch = tuner.schedule(bsz, k, c, r, r1, prec) if mode == "tuned" else {}
+                    gi.search(Q[a:a + bsz], k, c, r, r1=r1, precision=prec, **sch)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t
+                res[f"{prec}_r1_{r1}_{mode}_qps"] = round(Q.shape[0] / dt)
+                log(f"{prec} r1={r1} {mode}: {Q.shape[0] / dt:,.0f} q/s (recall@10 {rec:.4f})")
+            res[f"{prec}_r1_{r1}_recall10"] = round(rec, 4)
+    res["schedules"] = tuner.cache
+    print(json.dumps(res), flush=True)
 
 
 def cpu_baseline(X, lab, Q, A, b, C, m, w, F, c, r, r1, seconds):

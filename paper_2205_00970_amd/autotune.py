@@ -1,0 +1,80 @@
+"""Schedule autotuner for the rerank kernel (batching form).
+
+For one shape bucket -- (index shape, precision, k, c, r, r1, batch-size
+bucket) -- it times every candidate schedule of the window-scoring kernel
+(rows per tile 32 / 64 / 128, one workgroup per tile or a persistent grid of
+2 / 4 / 8 workgroups per CU pulling tiles from per-XCD counters) on a
+representative batch, checks that every candidate returns bit-identical ids
+and scores, and keeps the fastest.  Results are cached in memory and,
+optionally, in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+CANDIDATES = [dict(tile_rows=t, persistent=False, grid_mult=0) for t in (32, 64, 128)] + [
+    dict(tile_rows=t, persistent=True, grid_mult=g) for t in (64, 128) for g in (2, 4, 8)]
+
+
+def bucket(nq):
+    """Power-of-two batch-size bucket."""
+    b = 1
+    while b < nq:
+        b <<= 1
+    return b
+
+
+class Autotuner:
+    def __init__(self, index, path=None, reps=5):
+        self.index = index
+        self.path = path
+        self.reps = reps
+        self.cache = {}
+        if path and os.path.exists(path):
+            with open(path) as f:
+                self.cache = json.load(f)
+
+    def key(self, nq, k, c, r, r1, precision):
+        ix = self.index
+        return (f"n{ix.n}-d{ix.d}-C{ix.C}-{precision}-k{k}-c{c}-r{r}-r1{r1}-b{bucket(nq)}")
+
+    def tune(self, queries, k, c, r, r1=0, precision="f32"):
+        """Best schedule for this bucket (tuning on `queries` if not cached)."""
+        import torch
+        from . import lider
+        key = self.key(queries.shape[0], k, c, r, r1, precision)
+        if key in self.cache:
+            return self.cache[key]
+        ref = None
+        best = None
+        timings = []
+        for cand in CANDIDATES:
+            out = self.index.search(queries, k, c, r, r1=r1, precision=precision, **cand)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = out
+            elif not (torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])):
+                raise RuntimeError(f"schedule {cand} changed the results")
+            lider.profile_begin(self.reps)
+            for _ in range(self.reps):
+                self.index.search(queries, k, c, r, r1=r1, precision=precision, **cand)
+            torch.cuda.synchronize()
+            stages, calls = lider.profile_end()
+            ms = stages["rerank"] / calls
+            timings.append(dict(cand, rerank_ms=round(ms, 4)))
+            if best is None or ms < best[0]:
+                best = (ms, cand)
+        res = dict(best[1], rerank_ms=round(best[0], 4), candidates=timings)
+        self.cache[key] = res
+        if self.path:
+            with open(self.path, "w") as f:
+                json.dump(self.cache, f, indent=1)
+        return res
+
+    def schedule(self, nq, k, c, r, r1=0, precision="f32"):
+        """Cached schedule for a bucket (defaults if the bucket was never tuned)."""
+        res = self.cache.get(self.key(nq, k, c, r, r1, precision))
+        if res is None:
+            return dict(tile_rows=64, persistent=False, grid_mult=0)
+        return {k2: res[k2] for k2 in ("tile_rows", "persistent", "grid_mult")}
