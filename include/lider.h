@@ -125,9 +125,12 @@ const char* lider_last_error(void);
  *                 the fp32 copy; routing uses fp8 centroids if the index has
  *                 them, else fp32.
  *  shortlist_mult shortlist length per query in units of k (0 = 4).
- *  persistent     1: run the rerank as a persistent kernel over the
- *                 (cluster, row-tile) work list instead of one workgroup per
- *                 tile.  Results are identical.
+ *  persistent     0: one workgroup per row tile of the whole index (tiles no
+ *                 window touches exit at once).  1: a persistent grid pulls the
+ *                 index's tiles from per-XCD counters.  2: the tiles some window
+ *                 overlaps are first collected into a work list on the device
+ *                 and a persistent grid pulls only those (best for small or
+ *                 sparse batches on large indexes).  Results are identical.
  *  tile_rows      rows per rerank tile: 0 (default 64) or 32, 64, 128.
  *  pair_tile      pairs per MFMA pass in the rerank: 0 (default 16) or 16, 32.
  *  grid_mult      persistent grid = grid_mult * number of CUs (0 = 4). */

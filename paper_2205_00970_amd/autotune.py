@@ -2,8 +2,10 @@
 
 For one shape bucket -- (index shape, precision, k, c, r, r1, batch-size
 bucket) -- it times every candidate schedule of the window-scoring kernel
-(rows per tile 32 / 64 / 128, one workgroup per tile or a persistent grid of
-2 / 4 / 8 workgroups per CU pulling tiles from per-XCD counters) on a
+(rows per tile 32 / 64 / 128; one workgroup per tile, a persistent grid of
+2 / 4 / 8 workgroups per CU pulling tiles from per-XCD counters, or the same
+grid pulling only the tiles some window overlaps from a work list built on the
+device) on a
 representative batch, checks that every candidate returns bit-identical ids
 and scores, and keeps the fastest.  Results are cached in memory and,
 optionally, in a JSON file.
@@ -13,8 +15,9 @@ from __future__ import annotations
 import json
 import os
 
-CANDIDATES = [dict(tile_rows=t, persistent=False, grid_mult=0) for t in (32, 64, 128)] + [
-    dict(tile_rows=t, persistent=True, grid_mult=g) for t in (64, 128) for g in (2, 4, 8)]
+CANDIDATES = [dict(tile_rows=t, persistent=0, grid_mult=0) for t in (32, 64, 128)] + [
+    dict(tile_rows=t, persistent=p, grid_mult=g) for p in (1, 2) for t in (64, 128)
+    for g in (2, 4, 8)]
 
 
 def bucket(nq):
@@ -76,5 +79,5 @@ class Autotuner:
         """Cached schedule for a bucket (defaults if the bucket was never tuned)."""
         res = self.cache.get(self.key(nq, k, c, r, r1, precision))
         if res is None:
-            return dict(tile_rows=64, persistent=False, grid_mult=0)
+            return dict(tile_rows=64, persistent=0, grid_mult=0)
         return {k2: res[k2] for k2 in ("tile_rows", "persistent", "grid_mult")}

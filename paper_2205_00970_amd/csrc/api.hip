@@ -44,7 +44,8 @@ void free_device(Index& ix) {
                   ix.cent8,  ix.cent8_scale, ix.l1_order, ix.l1_order32, ix.l1_keys,
                   ix.l1_digits, ix.A,        ix.b,        ix.anorm,     ix.cent_norm_max,
                   ix.models, ix.leaves,      ix.leaf_err, ix.tiles[0],  ix.tiles[1],
-                  ix.tiles[2], ix.l1_off,    ix.l1_tiles};
+                  ix.tiles[2], ix.l1_off,    ix.l1_tiles,  ix.tile_base[0], ix.tile_base[1],
+                  ix.tile_base[2]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -244,6 +245,7 @@ static int validate_search(const lider_index* index, const float* Q, int64_t nq,
   if (o.tile_rows != 0 && o.tile_rows != 32 && o.tile_rows != 64 && o.tile_rows != 128)
     return set_error(LIDER_EINVAL, "tile_rows must be 0, 32, 64 or 128");
   if (o.grid_mult < 0 || o.grid_mult > 64) return set_error(LIDER_EINVAL, "grid_mult out of range");
+  if (o.persistent < 0 || o.persistent > 2) return set_error(LIDER_EINVAL, "persistent must be 0, 1 or 2");
   if (nq > 0 && !Q) return set_error(LIDER_EINVAL, "queries pointer is NULL");
   return LIDER_OK;
 }

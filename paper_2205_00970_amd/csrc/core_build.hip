@@ -443,14 +443,21 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
   // rerank tile tables: (cluster, first in-cluster row) for 32/64/128-row tiles
   const int sizes[3] = {32, 64, 128};
   for (int s = 0; s < 3; ++s) {
-    std::vector<int32_t> t;
+    std::vector<int32_t> t, tb;
     for (int32_t j = 0; j < C; ++j) {
+      tb.push_back(int32_t(t.size() / 2));
       const int64_t L = ix.h_off[j + 1] - ix.h_off[j];
       for (int64_t r0 = 0; r0 < L; r0 += sizes[s]) {
         t.push_back(j);
         t.push_back(int32_t(r0));
       }
     }
+    tb.push_back(int32_t(t.size() / 2));
+    if (hipMalloc(&ix.tile_base[s], al256(tb.size() * 4)) != hipSuccess)
+      return set_error(LIDER_ENOMEM, "out of device memory (tile table)");
+    rc = check_hip(hipMemcpy(ix.tile_base[s], tb.data(), tb.size() * 4, hipMemcpyHostToDevice),
+                   "copy tile bases");
+    if (rc != LIDER_OK) return rc;
     ix.n_tiles[s] = int32_t(t.size() / 2);
     if (hipMalloc(&ix.tiles[s], al256(t.size() * 4 + 4)) != hipSuccess)
       return set_error(LIDER_ENOMEM, "out of device memory (tile table)");

@@ -38,12 +38,13 @@ struct alignas(16) Pair {
 };
 
 // Counters block layout (int32): [0] hash list count, [1] status,
-// [8..15] per-XCD tile counters of the persistent rerank.
+// [8..15] per-XCD tile counters of the persistent rerank, [16] active-tile
+// count, [17] active-tile fetch counter.
 constexpr int kCtrWords = 64;
 
 struct Plan {
   size_t o_ctr, o_qdig, o_hlist, o_qnorm, o_l1, o_l1p, o_l1cs, o_rs, o_rs64, o_routed, o_pairs,
-      o_ccount, o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, total;
+      o_ccount, o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, o_aflag, o_alist, total;
   int32_t r1, rcap, S;
 };
 
@@ -78,6 +79,10 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   p.o_sbuf = take(size_t(nq) * c * rcap * 4);
   p.o_qb = take((S || ix.cent8) ? size_t(nq) * ix.d * 2 : 0);
   p.o_slist = take(S ? size_t(nq) * S * 4 : 0);
+  const int ti = o.tile_rows == 32 ? 0 : o.tile_rows == 128 ? 2 : 1;
+  const size_t nt = o.persistent == 2 ? size_t(ix.n_tiles[ti]) : 0;
+  p.o_aflag = take(nt * 4);
+  p.o_alist = take(nt * 4);
   p.total = off;
   p.r1 = r1;
   p.rcap = rcap;
@@ -511,6 +516,22 @@ __global__ void scatter_kernel(const Pair* __restrict__ pairs, int64_t np,
   wl[start[pr.j] + atomicAdd(&fill[pr.j], 1)] = int32_t(t);
 }
 
+// Active-tile work list: every pair marks the tiles its window overlaps; the
+// first marker of a tile appends it to the list (order unspecified; each
+// tile's result does not depend on the order).
+__global__ void mark_tiles_kernel(const Pair* __restrict__ pairs, int64_t np, int32_t RT,
+                                  const int32_t* __restrict__ tile_base,
+                                  int32_t* __restrict__ flag, int32_t* __restrict__ alist,
+                                  int32_t* __restrict__ count) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= np) return;
+  const Pair pr = pairs[t];
+  if (pr.j < 0 || pr.len <= 0) return;
+  const int32_t b = tile_base[pr.j];
+  for (int32_t u = b + pr.s / RT; u <= b + (pr.s + pr.len - 1) / RT; ++u)
+    if (atomicExch(&flag[u], 1) == 0) alist[atomicAdd(count, 1)] = u;
+}
+
 // ------------------------------------------------------------ rerank
 constexpr int kPairCap = 256;
 
@@ -525,8 +546,19 @@ struct TileShared {
 // query rows -- goes to one XCD and its L2), or a persistent loop over per-XCD
 // atomic counters with stealing.
 __device__ inline int32_t next_tile(int persistent, int32_t ntiles, int32_t* __restrict__ ctr,
-                                    int32_t& state, TileShared& sh) {
+                                    int32_t& state, TileShared& sh,
+                                    const int32_t* __restrict__ alist) {
   const int32_t per = (ntiles + 7) / 8;
+  if (persistent == 2) {  // active-tile list: ctr[8] = count, ctr[9] = fetch counter
+    if (threadIdx.x == 0) {
+      const int32_t idx = atomicAdd(&ctr[9], 1);
+      sh.tile = idx < ctr[8] ? alist[idx] : -1;
+    }
+    __syncthreads();
+    const int32_t t = sh.tile;
+    __syncthreads();
+    return t;
+  }
   if (!persistent) {
     if (state) return -1;
     state = 1;
@@ -739,7 +771,8 @@ __global__ __launch_bounds__(256) void rerank_kernel(
     const int32_t* __restrict__ tiles, int32_t ntiles, const int32_t* __restrict__ cstart,
     const int32_t* __restrict__ wl, const Pair* __restrict__ pairs, int32_t c,
     const void* __restrict__ Qv, float* __restrict__ sbuf, int32_t rcap, int persistent,
-    int32_t* __restrict__ ctr, int32_t pair_chunk, const float* __restrict__ row_scale) {
+    int32_t* __restrict__ ctr, int32_t pair_chunk, const float* __restrict__ row_scale,
+    const int32_t* __restrict__ alist) {
   typedef Feed<FMT, VEC> F;
   typedef typename F::XE XE;
   typedef typename F::QE QE;
@@ -755,7 +788,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(
   const int sub = F::KS == 32 ? 8 * s : 4 * s;
   int32_t state = 0;
   for (;;) {
-    const int32_t tile = next_tile(persistent, ntiles, ctr, state, sh);
+    const int32_t tile = next_tile(persistent, ntiles, ctr, state, sh, alist);
     if (tile < 0) break;
     const int32_t j = tiles[2 * tile], row0 = tiles[2 * tile + 1];
     const int64_t base = off[j];
@@ -1161,7 +1194,7 @@ template <int RT>
 void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, const int32_t* wl,
                   const Pair* pairs, int32_t c, const float* Q, const __hip_bfloat16* Qb,
                   float* sbuf, int32_t rcap, int persistent, int grid_mult, int32_t* ctr,
-                  hipStream_t st) {
+                  const int32_t* alist, hipStream_t st) {
   const int32_t nt = ix.n_tiles[ti];
   unsigned grid;
   if (persistent)
@@ -1172,19 +1205,19 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
   if (bf16 && ix.d % 32 != 0)
     hipLaunchKernelGGL((rerank_kernel<RT, kBF16, false, true>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.Xb, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr);
+                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
   else if (bf16)
     hipLaunchKernelGGL((rerank_kernel<RT, kBF16, true, true>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.Xb, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr);
+                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
   else if (vec)
     hipLaunchKernelGGL((rerank_kernel<RT, kF32, true, true>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.X, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr);
+                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
   else
     hipLaunchKernelGGL((rerank_kernel<RT, kF32, false, true>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.X, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr);
+                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
 }
 
 // Layer-1 window scores: the centroids (layer-1 order) are one "cluster" of C
@@ -1202,22 +1235,26 @@ void launch_l1_scores(const Index& ix, bool fp8, int64_t nq, const int32_t* l1cs
     hipLaunchKernelGGL((rerank_kernel<64, kFP8, false, false>), grid, dim3(256), 0, st,
                        (const void*)ix.cent8, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
-                       (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale);
+                       (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale,
+                       (const int32_t*)nullptr);
   else if (fp8)
     hipLaunchKernelGGL((rerank_kernel<64, kFP8, true, false>), grid, dim3(256), 0, st,
                        (const void*)ix.cent8, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
-                       (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale);
+                       (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale,
+                       (const int32_t*)nullptr);
   else if (vec)
     hipLaunchKernelGGL((rerank_kernel<64, kF32, true, false>), grid, dim3(256), 0, st,
                        (const void*)ix.cent_l1, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
-                       (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr);
+                       (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr,
+                       (const int32_t*)nullptr);
   else
     hipLaunchKernelGGL((rerank_kernel<64, kF32, false, false>), grid, dim3(256), 0, st,
                        (const void*)ix.cent_l1, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
-                       (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr);
+                       (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr,
+                       (const int32_t*)nullptr);
 }
 
 }  // namespace
@@ -1253,6 +1290,8 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   float* sbuf = reinterpret_cast<float*>(W + p.o_sbuf);
   __hip_bfloat16* qb = reinterpret_cast<__hip_bfloat16*>(W + p.o_qb);
   int32_t* slist = reinterpret_cast<int32_t*>(W + p.o_slist);
+  int32_t* aflag = reinterpret_cast<int32_t*>(W + p.o_aflag);
+  int32_t* alist = reinterpret_cast<int32_t*>(W + p.o_alist);
   const int32_t m = ix.m, C = ix.C;
   const int64_t np = nq * c;
   const bool bf16 = o.precision == LIDER_BF16;
@@ -1305,15 +1344,22 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   const int tr = o.tile_rows == 32 ? 32 : o.tile_rows == 128 ? 128 : 64;
   const int ti = tr == 32 ? 0 : tr == 64 ? 1 : 2;
   const int gm = o.grid_mult > 0 ? o.grid_mult : 4;
+  if (o.persistent == 2) {
+    const int32_t nt = ix.n_tiles[ti];
+    hipLaunchKernelGGL(zero_kernel, dim3(unsigned(std::min<int64_t>((nt + 255) / 256, 4096))),
+                       dim3(256), 0, st, aflag, int64_t(nt));
+    hipLaunchKernelGGL(mark_tiles_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st,
+                       pairs, np, tr, ix.tile_base[ti], aflag, alist, ctr + 16);
+  }
   if (tr == 32)
     launch_score<32>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
-                     ctr + 8, st);
+                     ctr + 8, alist, st);
   else if (tr == 64)
     launch_score<64>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
-                     ctr + 8, st);
+                     ctr + 8, alist, st);
   else
     launch_score<128>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
-                      ctr + 8, st);
+                      ctr + 8, alist, st);
   mark(4);
   if (!bf16) {
     if (k <= 64)

@@ -207,7 +207,7 @@ class Index:
               grid_mult=0):
         o = SearchOpts()
         o.r1, o.precision, o.shortlist_mult = int(r1), _PREC[precision], int(shortlist_mult)
-        o.persistent, o.tile_rows, o.grid_mult = int(bool(persistent)), int(tile_rows), int(grid_mult)
+        o.persistent, o.tile_rows, o.grid_mult = int(persistent), int(tile_rows), int(grid_mult)
         return o
 
     def search(self, queries, k, c, r, r1=0, precision="f32", shortlist_mult=0,

@@ -95,7 +95,9 @@ def test_mid_schedules_identical(mid):
     gi = mid["gi"]
     ref = gi.search(Qd, 10, 8, 256, r1=32)
     for kw in [dict(persistent=True), dict(tile_rows=32), dict(tile_rows=128),
-               dict(tile_rows=128, persistent=True, grid_mult=1), dict()]:
+               dict(tile_rows=128, persistent=True, grid_mult=1), dict(persistent=2),
+               dict(tile_rows=32, persistent=2, grid_mult=1),
+               dict(tile_rows=128, persistent=2, grid_mult=8), dict()]:
         got = gi.search(Qd, 10, 8, 256, r1=32, **kw)
         assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), kw
     sub = gi.search(Qd[37:90].contiguous(), 10, 8, 256, r1=32)
