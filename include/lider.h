@@ -132,7 +132,9 @@ const char* lider_last_error(void);
  *                 and a persistent grid pulls only those (best for small or
  *                 sparse batches on large indexes).  Results are identical.
  *  tile_rows      rows per rerank tile: 0 (default 64) or 32, 64, 128.
- *  pair_tile      pairs per MFMA pass in the rerank: 0 (default 16) or 16, 32.
+ *  l1_dense       0: when r1 covers every centroid, the layer-1 scores are one
+ *                 dense query x centroid product on MFMA (default); -1: always
+ *                 the window kernel.  Results are identical.
  *  grid_mult      persistent grid = grid_mult * number of CUs (0 = 4). */
 typedef struct {
   int32_t r1;
@@ -140,7 +142,7 @@ typedef struct {
   int32_t shortlist_mult;
   int32_t persistent;
   int32_t tile_rows;
-  int32_t pair_tile;
+  int32_t l1_dense;
   int32_t grid_mult;
   int32_t reserved[9];
 } lider_search_opts;

@@ -44,7 +44,7 @@ void free_device(Index& ix) {
                   ix.cent8,  ix.cent8_scale, ix.l1_order, ix.l1_order32, ix.l1_keys,
                   ix.l1_digits, ix.A,        ix.b,        ix.anorm,     ix.cent_norm_max,
                   ix.models, ix.leaves,      ix.leaf_err, ix.tiles[0],  ix.tiles[1],
-                  ix.tiles[2], ix.l1_off,    ix.l1_tiles,  ix.tile_base[0], ix.tile_base[1],
+                  ix.tiles[2], ix.l1_tiles,  ix.tile_base[0], ix.tile_base[1],
                   ix.tile_base[2]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -246,6 +246,7 @@ static int validate_search(const lider_index* index, const float* Q, int64_t nq,
     return set_error(LIDER_EINVAL, "tile_rows must be 0, 32, 64 or 128");
   if (o.grid_mult < 0 || o.grid_mult > 64) return set_error(LIDER_EINVAL, "grid_mult out of range");
   if (o.persistent < 0 || o.persistent > 2) return set_error(LIDER_EINVAL, "persistent must be 0, 1 or 2");
+  if (o.l1_dense != 0 && o.l1_dense != -1) return set_error(LIDER_EINVAL, "l1_dense must be 0 or -1");
   if (nq > 0 && !Q) return set_error(LIDER_EINVAL, "queries pointer is NULL");
   return LIDER_OK;
 }

@@ -440,25 +440,28 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
   ix.max_cluster = 0;
   for (int32_t j = 0; j < C; ++j)
     ix.max_cluster = std::max<int64_t>(ix.max_cluster, ix.h_off[j + 1] - ix.h_off[j]);
-  // rerank tile tables: (cluster, first in-cluster row) for 32/64/128-row tiles
+  // rerank tile tables for 32/64/128-row tiles, 4 int32 per tile: cluster,
+  // first in-cluster row, first row in the reordered corpus, rows in the tile
   const int sizes[3] = {32, 64, 128};
   for (int s = 0; s < 3; ++s) {
     std::vector<int32_t> t, tb;
     for (int32_t j = 0; j < C; ++j) {
-      tb.push_back(int32_t(t.size() / 2));
+      tb.push_back(int32_t(t.size() / 4));
       const int64_t L = ix.h_off[j + 1] - ix.h_off[j];
       for (int64_t r0 = 0; r0 < L; r0 += sizes[s]) {
         t.push_back(j);
         t.push_back(int32_t(r0));
+        t.push_back(int32_t(ix.h_off[j] + r0));
+        t.push_back(int32_t(std::min<int64_t>(sizes[s], L - r0)));
       }
     }
-    tb.push_back(int32_t(t.size() / 2));
+    tb.push_back(int32_t(t.size() / 4));
     if (hipMalloc(&ix.tile_base[s], al256(tb.size() * 4)) != hipSuccess)
       return set_error(LIDER_ENOMEM, "out of device memory (tile table)");
     rc = check_hip(hipMemcpy(ix.tile_base[s], tb.data(), tb.size() * 4, hipMemcpyHostToDevice),
                    "copy tile bases");
     if (rc != LIDER_OK) return rc;
-    ix.n_tiles[s] = int32_t(t.size() / 2);
+    ix.n_tiles[s] = int32_t(t.size() / 4);
     if (hipMalloc(&ix.tiles[s], al256(t.size() * 4 + 4)) != hipSuccess)
       return set_error(LIDER_ENOMEM, "out of device memory (tile table)");
     rc = check_hip(hipMemcpy(ix.tiles[s], t.data(), t.size() * 4, hipMemcpyHostToDevice),
@@ -470,16 +473,14 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
     for (int32_t r0 = 0; r0 < C; r0 += 64) {
       t.push_back(0);
       t.push_back(r0);
+      t.push_back(r0);
+      t.push_back(std::min(64, C - r0));
     }
-    const int64_t lo[2] = {0, C};
-    ix.n_l1_tiles = int32_t(t.size() / 2);
-    if (hipMalloc(&ix.l1_tiles, al256(t.size() * 4)) != hipSuccess ||
-        hipMalloc(&ix.l1_off, 256) != hipSuccess)
+    ix.n_l1_tiles = int32_t(t.size() / 4);
+    if (hipMalloc(&ix.l1_tiles, al256(t.size() * 4)) != hipSuccess)
       return set_error(LIDER_ENOMEM, "out of device memory (layer-1 tiles)");
     rc = check_hip(hipMemcpy(ix.l1_tiles, t.data(), t.size() * 4, hipMemcpyHostToDevice),
                    "copy layer-1 tiles");
-    if (rc == LIDER_OK)
-      rc = check_hip(hipMemcpy(ix.l1_off, lo, sizeof(lo), hipMemcpyHostToDevice), "copy offsets");
   }
   return rc;
 }

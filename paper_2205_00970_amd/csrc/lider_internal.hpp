@@ -161,12 +161,11 @@ struct Index {
   // rerank tiles: (cluster, first row) of every tile of tile_rows rows, one
   // table per supported tile size (32, 64, 128)
   int32_t n_tiles[3] = {0, 0, 0};
-  int32_t* tiles[3] = {nullptr, nullptr, nullptr};  // [n_tiles x 2]: cluster, row0 (in-cluster)
+  int32_t* tiles[3] = {nullptr, nullptr, nullptr};  // [n_tiles x 4]: cluster, row0, global row0, rows
   int32_t* tile_base[3] = {nullptr, nullptr, nullptr};  // [C+1] first tile of each cluster
   // layer-1 scoring: the C centroids as one 64-row-tiled "cluster"
-  int64_t* l1_off = nullptr;   // {0, C}
   int32_t n_l1_tiles = 0;
-  int32_t* l1_tiles = nullptr;  // [n_l1_tiles x 2]: 0, row0
+  int32_t* l1_tiles = nullptr;  // [n_l1_tiles x 4]: 0, row0, row0, rows
   std::vector<int64_t> h_off;  // host copy of off
 };
 

@@ -642,6 +642,9 @@ struct Feed<kF32, VEC> {  // 16 dims per k-step, 4 per lane
     }
     return load(row, k, d);
   }
+  typedef T Raw;
+  __device__ static Raw raw(const float* row, int k, int d, bool nt) { return loadx(row, k, d, nt); }
+  __device__ static T dec(const Raw& v, int, int) { return v; }
   __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.x, x.x, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.y, x.y, acc, 0, 0, 0);
@@ -675,6 +678,11 @@ struct Feed<kBF16, VEC> {  // 32 dims per k-step, 8 per lane
     if (VEC) return stream_load(reinterpret_cast<const bf16x8*>(row + k), nt);
     return load(row, k, d);
   }
+  typedef T Raw;
+  __device__ static Raw raw(const __hip_bfloat16* row, int k, int d, bool nt) {
+    return loadx(row, k, d, nt);
+  }
+  __device__ static T dec(const Raw& v, int, int) { return v; }
   __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(q, x, acc, 0, 0, 0);
   }
@@ -697,10 +705,12 @@ struct Feed<kFP8, VEC> {  // fp8 rows, bf16 queries, 32 dims per k-step
   __device__ static T load(const __hip_bfloat16* row, int k, int d) {
     return Feed<kBF16, VEC>::load(row, k, d);
   }
-  __device__ static T loadx(const uint8_t* row, int k, int d, bool nt) {
-    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  typedef uint32_t Raw __attribute__((ext_vector_type(2)));  // 8 undecoded bytes
+  __device__ static Raw raw(const uint8_t* row, int k, int d, bool nt) {
     const int kk = VEC ? k : (k < d ? k : d - 8);
-    const u32x2 rv = stream_load(reinterpret_cast<const u32x2*>(row + kk), nt);
+    return stream_load(reinterpret_cast<const Raw*>(row + kk), nt);
+  }
+  __device__ static T dec(const Raw& rv, int k, int d) {
     T v;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -708,6 +718,9 @@ struct Feed<kFP8, VEC> {  // fp8 rows, bf16 queries, 32 dims per k-step
       v[e] = (__bf16)e4m3_value(uint8_t(w >> (8 * (e & 3))));
     }
     return (VEC || k < d) ? v : bf16x8_zero();
+  }
+  __device__ static T loadx(const uint8_t* row, int k, int d, bool nt) {
+    return dec(raw(row, k, d, nt), k, d);
   }
   __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(q, x, acc, 0, 0, 0);
@@ -740,13 +753,21 @@ __device__ __forceinline__ void mfma_step(const typename F::T (&x)[RC], const ty
   }
 }
 
+// xa holds the rows' first k-step when `pre` is set (issued before the pair
+// scan so that the tile's first HBM reads overlap it).
 template <class F, int RC, int NPC, bool NT>
 __device__ __forceinline__ void pass_loop(const typename F::XE* const (&xr)[RC],
                                           const typename F::QE* q0, const typename F::QE* q1,
                                           int ks0, int ks1, int sub, int d,
-                                          floatx4 (&acc)[RC][2]) {
-  typename F::T xa[RC], xb[RC], qa0, qa1, qb0, qb1;
-  load_step<F, RC, NPC, NT>(xr, q0, q1, ks0 * F::KS + sub, d, xa, qa0, qa1);
+                                          floatx4 (&acc)[RC][2], typename F::T (&xa)[RC],
+                                          bool pre) {
+  typename F::T xb[RC], qa0, qa1, qb0, qb1;
+  if (pre) {
+    qa0 = F::load(q0, ks0 * F::KS + sub, d);
+    if (NPC > 1) qa1 = F::load(q1, ks0 * F::KS + sub, d);
+  } else {
+    load_step<F, RC, NPC, NT>(xr, q0, q1, ks0 * F::KS + sub, d, xa, qa0, qa1);
+  }
   int ks = ks0;
   for (; ks + 1 < ks1; ks += 2) {
     load_step<F, RC, NPC, NT>(xr, q0, q1, (ks + 1) * F::KS + sub, d, xb, qb0, qb1);
@@ -767,8 +788,8 @@ __device__ __forceinline__ void pass_loop(const typename F::XE* const (&xr)[RC],
 // of its tile's cluster.  row_scale (nullable) multiplies each row's scores.
 template <int RT, int FMT, bool VEC, bool NT>
 __global__ __launch_bounds__(256) void rerank_kernel(
-    const void* __restrict__ Xv, int32_t d, const int64_t* __restrict__ off,
-    const int32_t* __restrict__ tiles, int32_t ntiles, const int32_t* __restrict__ cstart,
+    const void* __restrict__ Xv, int32_t d, const int32_t* __restrict__ tiles, int32_t ntiles,
+    const int32_t* __restrict__ cstart,
     const int32_t* __restrict__ wl, const Pair* __restrict__ pairs, int32_t c,
     const void* __restrict__ Qv, float* __restrict__ sbuf, int32_t rcap, int persistent,
     int32_t* __restrict__ ctr, int32_t pair_chunk, const float* __restrict__ row_scale,
@@ -790,10 +811,9 @@ __global__ __launch_bounds__(256) void rerank_kernel(
   for (;;) {
     const int32_t tile = next_tile(persistent, ntiles, ctr, state, sh, alist);
     if (tile < 0) break;
-    const int32_t j = tiles[2 * tile], row0 = tiles[2 * tile + 1];
-    const int64_t base = off[j];
-    const int32_t L = int32_t(off[j + 1] - base);
-    const int32_t rows_here = min(RT, L - row0);
+    const int4 td = reinterpret_cast<const int4*>(tiles)[tile];
+    const int32_t j = td.x, row0 = td.y, rows_here = td.w;
+    const int64_t grow = td.z;  // first row of the tile in the reordered corpus
     int32_t plo = cstart[j], phi = cstart[j + 1];
     if (pair_chunk > 0) {
       plo += int32_t(blockIdx.y) * pair_chunk;
@@ -802,7 +822,13 @@ __global__ __launch_bounds__(256) void rerank_kernel(
     const XE* xr[RC];
 #pragma unroll
     for (int rc = 0; rc < RC; ++rc)
-      xr[rc] = X + (base + min(row0 + 16 * rc + i, row0 + rows_here - 1)) * d;
+      xr[rc] = X + (grow + min(16 * rc + i, rows_here - 1)) * d;
+    typename F::T xa[RC];
+    bool pre = plo < phi && ks0 < ks1;
+    if (pre) {
+#pragma unroll
+      for (int rc = 0; rc < RC; ++rc) xa[rc] = F::loadx(xr[rc], ks0 * F::KS + sub, d, NT);
+    }
     for (int32_t pb = plo; pb < phi; pb += kPairCap) {
       if (tid == 0) sh.cnt = 0;
       __syncthreads();
@@ -833,9 +859,10 @@ __global__ __launch_bounds__(256) void rerank_kernel(
         const QE* q1 = Q + int64_t(sh.lq[g0 + min(16 + i, np - 1)]) * d;
         if (ks0 < ks1) {
           if (npc > 1)
-            pass_loop<F, RC, 2, NT>(xr, q0, q1, ks0, ks1, sub, d, acc);
+            pass_loop<F, RC, 2, NT>(xr, q0, q1, ks0, ks1, sub, d, acc, xa, pre);
           else
-            pass_loop<F, RC, 1, NT>(xr, q0, q1, ks0, ks1, sub, d, acc);
+            pass_loop<F, RC, 1, NT>(xr, q0, q1, ks0, ks1, sub, d, acc, xa, pre);
+          pre = false;
         }
 #pragma unroll
         for (int pc = 0; pc < 2; ++pc) {
@@ -855,13 +882,113 @@ __global__ __launch_bounds__(256) void rerank_kernel(
             float v = part[0][pp][rr];
 #pragma unroll
             for (int w = 1; w < kRerankWaves; ++w) v += part[w][pp][rr];
-            if (row_scale) v *= row_scale[base + row];
+            if (row_scale) v *= row_scale[grow + rr];
             sbuf[int64_t(sh.lp[g0 + pp]) * rcap + (row - a)] = v;
           }
         }
         __syncthreads();
       }
     }
+  }
+}
+
+// Layer-1 scores when every query's centroid window is the whole layer 1
+// (r1 = C): the dense product rs[q][p] = <Q[q], cent_l1[p]>, a GEMM on MFMA.
+// One 128 x 128 output tile per workgroup; workgroups are dealt to the 8 XCDs
+// round-robin, so consecutive tiles of one XCD share their query rows in its
+// L2.  Each wave owns a 64 x 64 quadrant (4 x 4 blocks of 16 x 16) over the
+// whole dimension range and reads its operand fragments straight from the
+// cache hierarchy, double-buffered across k-steps.  row_scale (nullable)
+// multiplies each centroid's scores (fp8 storage).  The routing decision only
+// uses these scores through an order-independent error bound, so the
+// summation order differs freely from the tiled window kernel.
+constexpr int kGemmTile = 128;
+
+template <class F>
+__device__ __forceinline__ void gemm_load(const typename F::QE* const (&qr)[4],
+                                          const typename F::XE* const (&xr)[4], int k, int d,
+                                          typename F::T (&qa)[4], typename F::Raw (&xa)[4]) {
+#pragma unroll
+  for (int b = 0; b < 4; ++b) qa[b] = F::load(qr[b], k, d);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) xa[b] = F::raw(xr[b], k, d, false);
+}
+
+// Centroid fragments are decoded (fp8 -> bf16) one block at a time, right
+// before their MFMAs, to keep the double-buffered registers small.
+template <class F>
+__device__ __forceinline__ void gemm_mfma(const typename F::T (&qa)[4],
+                                          const typename F::Raw (&xa)[4], int k, int d,
+                                          floatx4 (&acc)[4][4]) {
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const typename F::T x = F::dec(xa[nb], k, d);
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) F::mfma(qa[mb], x, acc[mb][nb]);
+  }
+}
+
+template <int FMT, bool VEC>
+__global__ __launch_bounds__(256) void l1_gemm_kernel(const void* __restrict__ Qv, int64_t nq,
+                                                      const void* __restrict__ Cv, int32_t C,
+                                                      int32_t d, const float* __restrict__ row_scale,
+                                                      float* __restrict__ rs) {
+  typedef Feed<FMT, VEC> F;
+  typedef typename F::XE XE;
+  typedef typename F::QE QE;
+  const QE* Q = static_cast<const QE*>(Qv);
+  const XE* X = static_cast<const XE*>(Cv);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, s = lane >> 4;
+  const int sub = F::KS == 32 ? 8 * s : 4 * s;
+  const int64_t ntc = (C + kGemmTile - 1) / kGemmTile;
+  const int64_t nblk = (nq + kGemmTile - 1) / kGemmTile * ntc;
+  const int64_t per = (nblk + 7) / 8;
+  const int64_t t = int64_t(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if ((blockIdx.x >> 3) >= per || t >= nblk) return;
+  const int64_t q0 = (t / ntc) * kGemmTile + (wave & 1) * 64;
+  const int32_t c0 = int32_t(t % ntc) * kGemmTile + (wave >> 1) * 64;
+  const QE* qr[4];
+  const XE* xr[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    qr[b] = Q + min(q0 + 16 * b + i, nq - 1) * d;
+    xr[b] = X + int64_t(min(c0 + 16 * b + i, C - 1)) * d;
+  }
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int nsteps = (d + F::KS - 1) / F::KS;
+  typename F::T qa[4], qb[4];
+  typename F::Raw xa[4], xb[4];
+  gemm_load<F>(qr, xr, sub, d, qa, xa);
+  int ks = 0;
+  for (; ks + 1 < nsteps; ks += 2) {
+    const int k1 = (ks + 1) * F::KS + sub, k2 = (ks + 2 < nsteps ? ks + 2 : nsteps - 1) * F::KS + sub;
+    gemm_load<F>(qr, xr, k1, d, qb, xb);
+    __builtin_amdgcn_sched_barrier(0);
+    gemm_mfma<F>(qa, xa, ks * F::KS + sub, d, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    gemm_load<F>(qr, xr, k2, d, qa, xa);
+    __builtin_amdgcn_sched_barrier(0);
+    gemm_mfma<F>(qb, xb, k1, d, acc);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (ks < nsteps) gemm_mfma<F>(qa, xa, ks * F::KS + sub, d, acc);
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int32_t p = c0 + 16 * nb + i;
+    if (p >= C) continue;
+    const float sc = row_scale ? row_scale[p] : 1.f;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t q = q0 + 16 * mb + 4 * s + e;
+        if (q < nq) rs[q * C + p] = row_scale ? acc[mb][nb][e] * sc : acc[mb][nb][e];
+      }
   }
 }
 
@@ -1204,19 +1331,19 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
   const bool vec = (ix.d % 16 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
   if (bf16 && ix.d % 32 != 0)
     hipLaunchKernelGGL((rerank_kernel<RT, kBF16, false, true>), dim3(grid), dim3(256), 0, st,
-                       (const void*)ix.Xb, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
   else if (bf16)
     hipLaunchKernelGGL((rerank_kernel<RT, kBF16, true, true>), dim3(grid), dim3(256), 0, st,
-                       (const void*)ix.Xb, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
   else if (vec)
     hipLaunchKernelGGL((rerank_kernel<RT, kF32, true, true>), dim3(grid), dim3(256), 0, st,
-                       (const void*)ix.X, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
   else
     hipLaunchKernelGGL((rerank_kernel<RT, kF32, false, true>), dim3(grid), dim3(256), 0, st,
-                       (const void*)ix.X, ix.d, ix.off, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
 }
 
@@ -1233,28 +1360,48 @@ void launch_l1_scores(const Index& ix, bool fp8, int64_t nq, const int32_t* l1cs
   const bool vec = (ix.d % 16 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
   if (fp8 && ix.d % 32 != 0)
     hipLaunchKernelGGL((rerank_kernel<64, kFP8, false, false>), grid, dim3(256), 0, st,
-                       (const void*)ix.cent8, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
+                       (const void*)ix.cent8, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale,
                        (const int32_t*)nullptr);
   else if (fp8)
     hipLaunchKernelGGL((rerank_kernel<64, kFP8, true, false>), grid, dim3(256), 0, st,
-                       (const void*)ix.cent8, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
+                       (const void*)ix.cent8, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale,
                        (const int32_t*)nullptr);
   else if (vec)
     hipLaunchKernelGGL((rerank_kernel<64, kF32, true, false>), grid, dim3(256), 0, st,
-                       (const void*)ix.cent_l1, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
+                       (const void*)ix.cent_l1, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr,
                        (const int32_t*)nullptr);
   else
     hipLaunchKernelGGL((rerank_kernel<64, kF32, false, false>), grid, dim3(256), 0, st,
-                       (const void*)ix.cent_l1, ix.d, ix.l1_off, ix.l1_tiles, nt, l1cs,
+                       (const void*)ix.cent_l1, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr,
                        (const int32_t*)nullptr);
+}
+
+// Dense layer-1 scores (r1 = C) on the GEMM kernel.
+void launch_l1_gemm(const Index& ix, bool fp8, int64_t nq, const float* Q,
+                    const __hip_bfloat16* Qb, float* rs, hipStream_t st) {
+  const int64_t nblk = (nq + kGemmTile - 1) / kGemmTile * ((ix.C + kGemmTile - 1) / kGemmTile);
+  const dim3 grid(unsigned((nblk + 7) / 8 * 8));
+  const bool vec = (ix.d % 16 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
+  if (fp8 && ix.d % 32 == 0)
+    hipLaunchKernelGGL((l1_gemm_kernel<kFP8, true>), grid, dim3(256), 0, st, (const void*)Qb, nq,
+                       (const void*)ix.cent8, ix.C, ix.d, (const float*)ix.cent8_scale, rs);
+  else if (fp8)
+    hipLaunchKernelGGL((l1_gemm_kernel<kFP8, false>), grid, dim3(256), 0, st, (const void*)Qb,
+                       nq, (const void*)ix.cent8, ix.C, ix.d, (const float*)ix.cent8_scale, rs);
+  else if (vec)
+    hipLaunchKernelGGL((l1_gemm_kernel<kF32, true>), grid, dim3(256), 0, st, (const void*)Q, nq,
+                       (const void*)ix.cent_l1, ix.C, ix.d, (const float*)nullptr, rs);
+  else
+    hipLaunchKernelGGL((l1_gemm_kernel<kF32, false>), grid, dim3(256), 0, st, (const void*)Q, nq,
+                       (const void*)ix.cent_l1, ix.C, ix.d, (const float*)nullptr, rs);
 }
 
 }  // namespace
@@ -1312,7 +1459,10 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   const bool fp8 = bf16 && ix.cent8;
   if (fp8 || bf16)
     hipLaunchKernelGGL(to_bf16_kernel, dim3(2048), dim3(256), 0, st, Q, nq * ix.d, qb);
-  launch_l1_scores(ix, fp8, nq, l1cs, l1pairs, Q, qb, rs, p.r1, st);
+  if (p.r1 == C && o.l1_dense >= 0)
+    launch_l1_gemm(ix, fp8, nq, Q, qb, rs, st);
+  else
+    launch_l1_scores(ix, fp8, nq, l1cs, l1pairs, Q, qb, rs, p.r1, st);
   const unsigned qgrid = unsigned(std::min<int64_t>(nq, 65535));
   const unsigned wgrid = unsigned(std::min<int64_t>((nq + 3) / 4, 65535));
   if (c + 1 <= 64) {

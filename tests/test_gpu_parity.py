@@ -104,6 +104,27 @@ def test_mid_schedules_identical(mid):
     assert torch.equal(sub[0], ref[0][37:90]) and torch.equal(sub[1], ref[1][37:90])
 
 
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_mid_dense_layer1_identical(mid, precision):
+    """r1 = C: the dense layer-1 GEMM and the window kernel route identically."""
+    torch = _torch()
+    from paper_2205_00970_amd import lider
+    X, Q = mid["X"], mid["Q"]
+    gi = mid["gi"]
+    if precision == "bf16":
+        A, b = datagen.lsh_params(8, 768, 2.0, seed=7)
+        gi = lider.Index(torch.from_numpy(X).cuda(), 64, 8, 2.0, 16, (A, b), rmi_fanout_l1=4,
+                         assignment=torch.from_numpy(mid["oi"].assignment()).cuda(),
+                         storage="bf16", centroid_storage="fp8")
+    Qd = torch.from_numpy(Q).cuda()
+    for sl in (slice(None), slice(5, 6), slice(17, 300)):
+        q = Qd[sl].contiguous()
+        a = gi.search(q, 10, 3, 500, r1=64, precision=precision, debug=True)
+        b = gi.search(q, 10, 3, 500, r1=64, precision=precision, debug=True, l1_dense=False)
+        assert torch.equal(a[2]["routed"], b[2]["routed"])
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
 @pytest.mark.parametrize("n,C,d", [(20000, 16, 128), (30000, 48, 768)])
 def test_farthest_first_kmeans_bit_exact(n, C, d):
     """Farthest-first seeding + Lloyd: every integer decision in FP64."""
@@ -133,10 +154,11 @@ def test_odd_dimensions(d):
     init = datagen.kmeans_init(3000, 6, seed=11)
     gi, oi, _ = build_pair(X, 6, 3, 1.5, 4, A, b, init_ids=init, iters=10)
     compare_index(gi, oi)
-    ids, sc, dbg = gi.search(torch.from_numpy(Q).cuda(), 5, 2, 40, r1=3, debug=True)
-    oids, osc, odbg = oi.search(Q, 5, 2, 40, 3, debug=True)
-    compare_debug(dbg, odbg)
-    compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+    for r1 in (3, 6):  # window kernel, then the dense layer-1 product (r1 = C)
+        ids, sc, dbg = gi.search(torch.from_numpy(Q).cuda(), 5, 2, 40, r1=r1, debug=True)
+        oids, osc, odbg = oi.search(Q, 5, 2, 40, r1, debug=True)
+        compare_debug(dbg, odbg)
+        compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
 
 
 def test_hash_near_bucket_edges():
