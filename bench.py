@@ -204,7 +204,8 @@ def main():
     achieved = alg_bytes / (rr_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 4), "traffic": None,
-                "kernel": "score_f32_kernel<64,true>", "kernel_ms": round(rr_ms, 4),
+                "kernel": "rerank_kernel (fp32 wide feed, one wave per row tile)",
+                "kernel_ms": round(rr_ms, 4),
                 "union_rows": U, "window_rows": sum_len, "algorithmic_bytes": alg_bytes}
     log(f"rerank: union rows {U:,}, {alg_bytes / 1e9:.3f} GB algorithmic, {rr_ms:.3f} ms -> "
         f"{achieved:,.0f} GB/s ({achieved / 8000:.1%} of 8 TB/s)")

@@ -125,17 +125,21 @@ const char* lider_last_error(void);
  *                 the fp32 copy; routing uses fp8 centroids if the index has
  *                 them, else fp32.
  *  shortlist_mult shortlist length per query in units of k (0 = 4).
- *  persistent     0: one workgroup per row tile of the whole index (tiles no
- *                 window touches exit at once).  1: a persistent grid pulls the
- *                 index's tiles from per-XCD counters.  2: the tiles some window
- *                 overlaps are first collected into a work list on the device
- *                 and a persistent grid pulls only those (best for small or
+ *  persistent     0: one wave per row tile of the whole index (tiles no window
+ *                 touches exit at once).  1: a persistent grid whose waves pull
+ *                 the index's tiles from per-XCD counters.  2: the tiles some
+ *                 window overlaps are first collected into a work list on the
+ *                 device and a persistent grid pulls only those (for small or
  *                 sparse batches on large indexes).  Results are identical.
- *  tile_rows      rows per rerank tile: 0 (default 64) or 32, 64, 128.
+ *  tile_rows      rows per rerank tile (one wave per tile): 32, 64, 128, or 0
+ *                 (128 when clusters average at least 512 rows, else 64).
  *  l1_dense       0: when r1 covers every centroid, the layer-1 scores are one
  *                 dense query x centroid product on MFMA (default); -1: always
  *                 the window kernel.  Results are identical.
- *  grid_mult      persistent grid = grid_mult * number of CUs (0 = 4). */
+ *  grid_mult      persistent grid = grid_mult * number of CUs (0 = 4).
+ *  pass_pairs     (query, cluster) pairs per MFMA pass of the rerank: 16, 32,
+ *                 or 0 (16 when there are at most 12 pairs per cluster on
+ *                 average, else 32).  Results are identical. */
 typedef struct {
   int32_t r1;
   int32_t precision;
@@ -144,7 +148,8 @@ typedef struct {
   int32_t tile_rows;
   int32_t l1_dense;
   int32_t grid_mult;
-  int32_t reserved[9];
+  int32_t pass_pairs;
+  int32_t reserved[8];
 } lider_search_opts;
 
 /* Optional device outputs of the intermediate search state, for parity checks.

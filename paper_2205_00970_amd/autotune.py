@@ -2,22 +2,24 @@
 
 For one shape bucket -- (index shape, precision, k, c, r, r1, batch-size
 bucket) -- it times every candidate schedule of the window-scoring kernel
-(rows per tile 32 / 64 / 128; one workgroup per tile, a persistent grid of
-2 / 4 / 8 workgroups per CU pulling tiles from per-XCD counters, or the same
-grid pulling only the tiles some window overlaps from a work list built on the
-device) on a
-representative batch, checks that every candidate returns bit-identical ids
-and scores, and keeps the fastest.  Results are cached in memory and,
-optionally, in a JSON file.
+(rows per wave tile 64 / 128; 16 or 32 pairs per MFMA pass; one wave per tile
+of the whole index, a persistent grid of 1 / 2 / 4 workgroups per CU pulling
+tiles in chunks from per-XCD counters, or the same grid dealt only the tiles
+some window overlaps from a list built on the device) on a representative
+batch, checks that every candidate returns bit-identical ids and scores, and
+keeps the fastest.  Results are cached in memory and, optionally, in a JSON
+file.
 """
 from __future__ import annotations
 
 import json
 import os
 
-CANDIDATES = [dict(tile_rows=t, persistent=0, grid_mult=0) for t in (32, 64, 128)] + [
-    dict(tile_rows=t, persistent=p, grid_mult=g) for p in (1, 2) for t in (64, 128)
-    for g in (2, 4, 8)]
+KEYS = ("tile_rows", "persistent", "grid_mult", "pass_pairs")
+CANDIDATES = ([dict(tile_rows=t, persistent=0, grid_mult=0, pass_pairs=pp)
+               for t in (64, 128) for pp in (16, 32)]
+              + [dict(tile_rows=t, persistent=p, grid_mult=g, pass_pairs=0)
+                 for p in (1, 2) for t in (64, 128) for g in (1, 2, 4)])
 
 
 def bucket(nq):
@@ -79,5 +81,5 @@ class Autotuner:
         """Cached schedule for a bucket (defaults if the bucket was never tuned)."""
         res = self.cache.get(self.key(nq, k, c, r, r1, precision))
         if res is None:
-            return dict(tile_rows=64, persistent=0, grid_mult=0)
-        return {k2: res[k2] for k2 in ("tile_rows", "persistent", "grid_mult")}
+            return dict(tile_rows=0, persistent=0, grid_mult=0, pass_pairs=0)
+        return {k2: res[k2] for k2 in KEYS}

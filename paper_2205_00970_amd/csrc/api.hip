@@ -247,6 +247,8 @@ static int validate_search(const lider_index* index, const float* Q, int64_t nq,
   if (o.grid_mult < 0 || o.grid_mult > 64) return set_error(LIDER_EINVAL, "grid_mult out of range");
   if (o.persistent < 0 || o.persistent > 2) return set_error(LIDER_EINVAL, "persistent must be 0, 1 or 2");
   if (o.l1_dense != 0 && o.l1_dense != -1) return set_error(LIDER_EINVAL, "l1_dense must be 0 or -1");
+  if (o.pass_pairs != 0 && o.pass_pairs != 16 && o.pass_pairs != 32)
+    return set_error(LIDER_EINVAL, "pass_pairs must be 0, 16 or 32");
   if (nq > 0 && !Q) return set_error(LIDER_EINVAL, "queries pointer is NULL");
   return LIDER_OK;
 }

@@ -108,10 +108,20 @@ __global__ __launch_bounds__(256) void hash_kernel(
   }
 }
 
-// Sequential FP64 recompute of queued (row, hash) projections, one wave per
-// entry: the wave stages the row and the hash vector in LDS with coalesced
-// loads, then one lane sums the products in dimension order.
+// FP64 recompute of queued (row, hash) projections, one wave per entry.  The
+// definition is the sequential FP64 sum in dimension order.  The wave first
+// sums the same exact products (fp32 x fp32 is exact in FP64) in parallel; two
+// FP64 sums of the same d terms in different orders differ by at most
+// 2 (d-1) 2^-53 sum|p| (to first order), so when the parallel value is farther
+// than a generous multiple of that from a bucket edge, both floors agree.
+// Only entries inside that much narrower band run the sequential loop (one
+// lane, operands staged in LDS).
 constexpr int kFixupLds = 1024;
+
+__device__ inline double wave_sum_f64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
 
 __global__ __launch_bounds__(256) void hash_fixup_kernel(
     const float* __restrict__ X, int32_t d, const float* __restrict__ A,
@@ -119,6 +129,7 @@ __global__ __launch_bounds__(256) void hash_fixup_kernel(
     const int64_t* __restrict__ list, const int32_t* __restrict__ counter,
     int32_t* __restrict__ status, int clamp) {
   __shared__ float sx[4][kFixupLds], sa[4][kFixupLds];
+  __shared__ int s_seq[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t cnt = *counter;
   const bool staged = d <= kFixupLds;
@@ -128,22 +139,39 @@ __global__ __launch_bounds__(256) void hash_fixup_kernel(
     const int hash = int(o - row * nh);
     const float* xr = X + row * d;
     const float* ar = A + int64_t(hash) * d;
-    if (staged) {
-      for (int l = lane; l < d; l += 64) {
-        sx[wave][l] = xr[l];
-        sa[wave][l] = ar[l];
+    double ps = 0.0, pa = 0.0;
+    for (int l = lane; l < d; l += 64) {
+      const float xv = xr[l], av = ar[l];
+      if (staged) {
+        sx[wave][l] = xv;
+        sa[wave][l] = av;
       }
-      __threadfence_block();
-      __builtin_amdgcn_wave_barrier();
+      const double pr = double(av) * double(xv);
+      ps += pr;
+      pa += fabs(pr);
     }
+    ps = wave_sum_f64(ps);
+    pa = wave_sum_f64(pa);
+    const double u = 1.1102230246251565e-16;  // 2^-53
+    const double tp = (ps + double(bvec[hash])) / w;
+    const double fp = floor(tp);
+    const double fr = tp - fp;
+    const double dist = fr < 1.0 - fr ? fr : 1.0 - fr;
+    const double band = 8.0 * (double(d) * u * pa + u * (fabs(ps) + fabs(double(bvec[hash])))) / w +
+                        8.0 * u * fabs(tp);
+    if (lane == 0) s_seq[wave] = !(dist > band);
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
     if (lane == 0) {
-      double sacc = 0.0;
-      if (staged)
-        for (int l = 0; l < d; ++l) sacc = sacc + double(sa[wave][l]) * double(sx[wave][l]);
-      else
-        for (int l = 0; l < d; ++l) sacc = sacc + double(ar[l]) * double(xr[l]);
-      const double tv = (sacc + double(bvec[hash])) / w;
-      const double fl = floor(tv);
+      double fl = fp;
+      if (s_seq[wave]) {
+        double sacc = 0.0;
+        if (staged)
+          for (int l = 0; l < d; ++l) sacc = sacc + double(sa[wave][l]) * double(sx[wave][l]);
+        else
+          for (int l = 0; l < d; ++l) sacc = sacc + double(ar[l]) * double(xr[l]);
+        fl = floor((sacc + double(bvec[hash])) / w);
+      }
       if (fl >= -2147483648.0 && fl <= 2147483647.0) {
         out[o] = int32_t(fl);
       } else if (clamp) {

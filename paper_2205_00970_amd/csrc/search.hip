@@ -39,7 +39,7 @@ struct alignas(16) Pair {
 
 // Counters block layout (int32): [0] hash list count, [1] status,
 // [8..15] per-XCD tile counters of the persistent rerank, [16] active-tile
-// count, [17] active-tile fetch counter.
+// count.
 constexpr int kCtrWords = 64;
 
 struct Plan {
@@ -47,6 +47,15 @@ struct Plan {
       o_ccount, o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, o_aflag, o_alist, total;
   int32_t r1, rcap, S;
 };
+
+// Rerank tile table in use: 0/1/2 = 32/64/128 rows per tile.  Default: 128
+// when clusters average at least 512 rows, else 64.
+int tile_index(const Index& ix, const lider_search_opts& o) {
+  if (o.tile_rows == 32) return 0;
+  if (o.tile_rows == 64) return 1;
+  if (o.tile_rows == 128) return 2;
+  return ix.n >= 512 * int64_t(ix.C) ? 2 : 1;
+}
 
 Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
                const lider_search_opts& o) {
@@ -79,7 +88,7 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   p.o_sbuf = take(size_t(nq) * c * rcap * 4);
   p.o_qb = take((S || ix.cent8) ? size_t(nq) * ix.d * 2 : 0);
   p.o_slist = take(S ? size_t(nq) * S * 4 : 0);
-  const int ti = o.tile_rows == 32 ? 0 : o.tile_rows == 128 ? 2 : 1;
+  const int ti = tile_index(ix, o);
   const size_t nt = o.persistent == 2 ? size_t(ix.n_tiles[ti]) : 0;
   p.o_aflag = take(nt * 4);
   p.o_alist = take(nt * 4);
@@ -533,81 +542,89 @@ __global__ void mark_tiles_kernel(const Pair* __restrict__ pairs, int64_t np, in
 }
 
 // ------------------------------------------------------------ rerank
-constexpr int kPairCap = 256;
+// Per-wave list of the pairs overlapping the wave's current tile (one ballot
+// round of 64 pairs at a time).
+constexpr int kWavePairCap = 64;
 
-struct TileShared {
-  int32_t lp[kPairCap], lq[kPairCap], ls[kPairCap], le[kPairCap];
-  int32_t cnt;
-  int32_t tile;
+struct WaveShared {
+  int32_t lp[kWavePairCap], lq[kWavePairCap], ls[kWavePairCap], le[kWavePairCap];
 };
 
-// Tile fetch: direct XCD-aware mapping of blockIdx (workgroups are dealt to the
-// 8 XCDs round-robin; a contiguous run of tiles -- the same clusters, the same
-// query rows -- goes to one XCD and its L2), or a persistent loop over per-XCD
-// atomic counters with stealing.
-__device__ inline int32_t next_tile(int persistent, int32_t ntiles, int32_t* __restrict__ ctr,
-                                    int32_t& state, TileShared& sh,
-                                    const int32_t* __restrict__ alist) {
-  const int32_t per = (ntiles + 7) / 8;
-  if (persistent == 2) {  // active-tile list: ctr[8] = count, ctr[9] = fetch counter
-    if (threadIdx.x == 0) {
-      const int32_t idx = atomicAdd(&ctr[9], 1);
-      sh.tile = idx < ctr[8] ? alist[idx] : -1;
-    }
-    __syncthreads();
-    const int32_t t = sh.tile;
-    __syncthreads();
-    return t;
-  }
-  if (!persistent) {
-    if (state) return -1;
-    state = 1;
-    const int32_t xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
-    const int32_t t = xcd * per + loc;
-    return (loc < per && t < ntiles) ? t : -1;
-  }
-  if (threadIdx.x == 0) {
-    int32_t res = -1;
-    const int32_t home = blockIdx.x & 7;
-    for (int v = state; v < 8 && res < 0; ++v) {
-      const int32_t x = (home + v) & 7;
-      const int32_t lo = x * per, hi = min(ntiles, lo + per);
-      if (lo >= hi) {
-        state = v + 1;
-        continue;
-      }
-      const int32_t t = atomicAdd(&ctr[x], 1);
-      if (lo + t < hi) {
-        res = lo + t;
-      } else {
-        state = v + 1;
-      }
-    }
-    sh.tile = res;
-  }
-  __syncthreads();
-  const int32_t t = sh.tile;
-  __syncthreads();
-  return t;
+// Tile fetch, one tile per wave.  Direct (persistent = 0): workgroups are
+// dealt to the 8 XCDs round-robin, so the block -> tile map gives each XCD a
+// contiguous run of tiles (the same clusters, the same query rows, one L2) and
+// the 4 waves of a block take 4 consecutive tiles.
+__device__ inline int32_t direct_tile(int32_t ntiles) {
+  const int32_t nb = (ntiles + 3) / 4;  // blocks of 4 tiles
+  const int32_t per = (nb + 7) / 8;
+  const int32_t xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
+  const int32_t b = xcd * per + loc;
+  const int32_t t = b * 4 + int32_t(threadIdx.x >> 6);
+  return (loc < per && b < nb && t < ntiles) ? t : -1;
 }
 
-// Rerank of one tile: RT consecutive rows of one cluster (contiguous in the
-// reordered corpus) against every (query, cluster) pair whose window overlaps
-// the tile.  The 4 waves split the dimension range (wave w owns a contiguous
-// quarter of the k-steps), so every X row and every query row of the tile is
-// read exactly once; each wave accumulates all RT rows x up to 32 pairs on
-// MFMA (fp32: v_mfma_f32_16x16x4f32, one float4 of both operands feeds 4
-// MFMAs; bf16: v_mfma_f32_16x16x32_bf16, 8 consecutive bf16 per lane), then the
-// 4 partial sums are added in wave order through LDS and written, coalesced
-// along rows, into each pair's window score row.  The summation order of a
-// score depends only on d, so results do not depend on the tile size, the
-// schedule or which other pairs share a pass.
+// Persistent fetch state of one wave.
+struct FetchState {
+  int32_t v = 0;              // exhausted per-XCD ranges (persistent = 1)
+  int32_t cur = 0, end = 0;   // current chunk of tiles (persistent = 1)
+  int32_t k = 0;              // list entries taken so far (persistent = 2)
+};
+constexpr int kFetchChunk = 8;
+
+// Persistent fetch of the wave's next tile.  persistent = 1 (called by lane 0):
+// the index's tiles are split into 8 contiguous ranges, one per XCD, each
+// drained in chunks of kFetchChunk tiles through its own atomic counter
+// (ctr[0..7]; one device-scope atomic per chunk, not per tile); a wave starts
+// on its own XCD's range and steals from the others once it is empty.
+// persistent = 2: the device-built list of active tiles (ctr[8] entries) is
+// dealt to the grid's waves round-robin, without atomics.
+__device__ inline int32_t fetch_tile(int persistent, int32_t ntiles, int32_t* __restrict__ ctr,
+                                     FetchState& st, const int32_t* __restrict__ alist) {
+  if (persistent == 2) {
+    const int64_t W = int64_t(gridDim.x) * (blockDim.x >> 6);
+    const int64_t idx = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6) + st.k * W;
+    ++st.k;
+    return idx < ctr[8] ? alist[idx] : -1;
+  }
+  if (st.cur < st.end) return st.cur++;
+  const int32_t per = (ntiles + 7) / 8;
+  const int32_t home = blockIdx.x & 7;
+  for (; st.v < 8; ++st.v) {
+    const int32_t x = (home + st.v) & 7;
+    const int32_t lo = x * per, hi = min(ntiles, lo + per);
+    if (lo >= hi) continue;
+    const int32_t t = lo + atomicAdd(&ctr[x], kFetchChunk);
+    if (t < hi) {
+      st.cur = t + 1;
+      st.end = min(hi, t + kFetchChunk);
+      return t;
+    }
+  }
+  return -1;
+}
+
+// Rerank of one tile per wave: RT consecutive rows of one cluster (contiguous
+// in the reordered corpus) against every (query, cluster) pair whose window
+// overlaps the tile.  The wave streams its rows once over the whole dimension
+// range and accumulates RT rows x up to 16 * NPCM pairs on MFMA (fp32:
+// v_mfma_f32_16x16x4f32, one float4 of both operands feeds 4 MFMAs; bf16:
+// v_mfma_f32_16x16x32_bf16, 8 consecutive bf16 per lane), then writes each
+// finished score from its accumulator straight into the pair's window score
+// row (16 consecutive rows per store).  No cross-wave reduction or barrier:
+// the 4 waves of a workgroup run their tiles independently.  A score is one
+// accumulator summed over the k-steps in order, so results do not depend on
+// the tile size, the schedule or which other pairs share a pass.
 constexpr int kRerankWaves = 4;
-constexpr int kPassPairs = 32;
 
 // Operand feeds.  FMT 0: fp32 rows and queries; 1: bf16 rows and queries;
-// 2: fp8 e4m3 rows (decoded exactly to bf16) and bf16 queries.
-enum { kF32 = 0, kBF16 = 1, kFP8 = 2 };
+// 2: fp8 e4m3 rows (decoded exactly to bf16) and bf16 queries; 3 / 4: fp32 /
+// bf16 with two 16-byte loads per lane and row per k-step, 64 bytes apart, so
+// the 4 lanes of a row cover one whole 128-byte line of it per step (the
+// streamed corpus feeds: a line is requested by two instructions issued back
+// to back instead of by two consecutive k-steps).  Lane slot s covers the
+// dimensions [SUBW*s, SUBW*s + SUBW) of the first load and the same range
+// plus KS/2 of the second.
+enum { kF32 = 0, kBF16 = 1, kFP8 = 2, kF32W = 3, kBF16W = 4 };
 
 template <int FMT, bool VEC>
 struct Feed;
@@ -622,7 +639,7 @@ __device__ inline T stream_load(const T* p, bool nt) {
 // full), so loads carry no bounds branch and the k-loop pipelines.
 template <bool VEC>
 struct Feed<kF32, VEC> {  // 16 dims per k-step, 4 per lane
-  static constexpr int KS = 16;
+  static constexpr int KS = 16, SUBW = 4;
   typedef float XE;
   typedef float QE;
   typedef float4 T;
@@ -665,7 +682,7 @@ __device__ inline bf16x8 bf16x8_zero() {
 // (no branch around the load).
 template <bool VEC>
 struct Feed<kBF16, VEC> {  // 32 dims per k-step, 8 per lane
-  static constexpr int KS = 32;
+  static constexpr int KS = 32, SUBW = 8;
   typedef __hip_bfloat16 XE;
   typedef __hip_bfloat16 QE;
   typedef bf16x8 T;
@@ -698,7 +715,7 @@ __device__ inline float e4m3_value(uint8_t v) {
 
 template <bool VEC>
 struct Feed<kFP8, VEC> {  // fp8 rows, bf16 queries, 32 dims per k-step
-  static constexpr int KS = 32;
+  static constexpr int KS = 32, SUBW = 8;
   typedef uint8_t XE;
   typedef __hip_bfloat16 QE;
   typedef bf16x8 T;
@@ -724,6 +741,60 @@ struct Feed<kFP8, VEC> {  // fp8 rows, bf16 queries, 32 dims per k-step
   }
   __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(q, x, acc, 0, 0, 0);
+  }
+};
+
+struct F32x2 {
+  float4 a, b;
+};
+
+// VEC: d % 32 == 0 (every k-step is full, loads carry no bounds branch).
+template <bool VEC>
+struct Feed<kF32W, VEC> {  // 32 dims per k-step: 4 + 4 per lane
+  static constexpr int KS = 32, SUBW = 4;
+  typedef float XE;
+  typedef float QE;
+  typedef F32x2 T;
+  typedef T Raw;
+  __device__ static T load(const float* row, int k, int d) {
+    return T{Feed<kF32, VEC>::load(row, k, d), Feed<kF32, VEC>::load(row, k + 16, d)};
+  }
+  __device__ static T loadx(const float* row, int k, int d, bool nt) {
+    return T{Feed<kF32, VEC>::loadx(row, k, d, nt), Feed<kF32, VEC>::loadx(row, k + 16, d, nt)};
+  }
+  __device__ static Raw raw(const float* row, int k, int d, bool nt) { return loadx(row, k, d, nt); }
+  __device__ static T dec(const Raw& v, int, int) { return v; }
+  __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
+    Feed<kF32, VEC>::mfma(q.a, x.a, acc);
+    Feed<kF32, VEC>::mfma(q.b, x.b, acc);
+  }
+};
+
+struct BF16x2 {
+  bf16x8 a, b;
+};
+
+// VEC: d % 64 == 0; otherwise d % 8 == 0 and partial steps are zero-filled.
+template <bool VEC>
+struct Feed<kBF16W, VEC> {  // 64 dims per k-step: 8 + 8 per lane
+  static constexpr int KS = 64, SUBW = 8;
+  typedef __hip_bfloat16 XE;
+  typedef __hip_bfloat16 QE;
+  typedef BF16x2 T;
+  typedef T Raw;
+  __device__ static T load(const __hip_bfloat16* row, int k, int d) {
+    return T{Feed<kBF16, VEC>::load(row, k, d), Feed<kBF16, VEC>::load(row, k + 32, d)};
+  }
+  __device__ static T loadx(const __hip_bfloat16* row, int k, int d, bool nt) {
+    return T{Feed<kBF16, VEC>::loadx(row, k, d, nt), Feed<kBF16, VEC>::loadx(row, k + 32, d, nt)};
+  }
+  __device__ static Raw raw(const __hip_bfloat16* row, int k, int d, bool nt) {
+    return loadx(row, k, d, nt);
+  }
+  __device__ static T dec(const Raw& v, int, int) { return v; }
+  __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
+    Feed<kBF16, VEC>::mfma(q.a, x.a, acc);
+    Feed<kBF16, VEC>::mfma(q.b, x.b, acc);
   }
 };
 
@@ -786,7 +857,10 @@ __device__ __forceinline__ void pass_loop(const typename F::XE* const (&xr)[RC],
 // wl == NULL: pair u of the cluster is pair u (identity work list).
 // pair_chunk > 0: workgroup (x, y) handles pairs [y*pair_chunk, (y+1)*pair_chunk)
 // of its tile's cluster.  row_scale (nullable) multiplies each row's scores.
-template <int RT, int FMT, bool VEC, bool NT>
+// NPCM: 16-pair column blocks per MFMA pass (1 or 2); tiles overlapped by more
+// pairs take several passes.  Each pair's accumulation is the same in every
+// grouping, so results do not depend on NPCM.
+template <int RT, int FMT, bool VEC, bool NT, int NPCM = 2>
 __global__ __launch_bounds__(256) void rerank_kernel(
     const void* __restrict__ Xv, int32_t d, const int32_t* __restrict__ tiles, int32_t ntiles,
     const int32_t* __restrict__ cstart,
@@ -798,18 +872,28 @@ __global__ __launch_bounds__(256) void rerank_kernel(
   typedef typename F::XE XE;
   typedef typename F::QE QE;
   constexpr int RC = RT / 16;
-  __shared__ TileShared sh;
-  __shared__ float part[kRerankWaves][kPassPairs][RT];
+  constexpr int PP = 16 * NPCM;  // pairs per pass
+  __shared__ WaveShared shw[kRerankWaves];
   const XE* X = static_cast<const XE*>(Xv);
   const QE* Q = static_cast<const QE*>(Qv);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  WaveShared& sh = shw[wave];
   const int i = lane & 15, s = lane >> 4;
   const int nsteps = (d + F::KS - 1) / F::KS;
-  const int ks0 = wave * nsteps / kRerankWaves, ks1 = (wave + 1) * nsteps / kRerankWaves;
-  const int sub = F::KS == 32 ? 8 * s : 4 * s;
-  int32_t state = 0;
-  for (;;) {
-    const int32_t tile = next_tile(persistent, ntiles, ctr, state, sh, alist);
+  const int sub = F::SUBW * s;
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  FetchState fs;
+  for (int it = 0;; ++it) {
+    int32_t tile;
+    if (persistent == 1) {
+      int32_t t = -1;
+      if (lane == 0) t = fetch_tile(1, ntiles, ctr, fs, alist);
+      tile = __shfl(t, 0);
+    } else if (persistent == 2) {
+      tile = fetch_tile(2, ntiles, ctr, fs, alist);
+    } else {
+      tile = it == 0 ? direct_tile(ntiles) : -1;
+    }
     if (tile < 0) break;
     const int4 td = reinterpret_cast<const int4*>(tiles)[tile];
     const int32_t j = td.x, row0 = td.y, rows_here = td.w;
@@ -824,31 +908,35 @@ __global__ __launch_bounds__(256) void rerank_kernel(
     for (int rc = 0; rc < RC; ++rc)
       xr[rc] = X + (grow + min(16 * rc + i, rows_here - 1)) * d;
     typename F::T xa[RC];
-    bool pre = plo < phi && ks0 < ks1;
-    if (pre) {
+    bool pre = plo < phi;
+    if (pre) {  // the first k-step's rows, in flight during the pair scan
 #pragma unroll
-      for (int rc = 0; rc < RC; ++rc) xa[rc] = F::loadx(xr[rc], ks0 * F::KS + sub, d, NT);
+      for (int rc = 0; rc < RC; ++rc) xa[rc] = F::loadx(xr[rc], sub, d, NT);
     }
-    for (int32_t pb = plo; pb < phi; pb += kPairCap) {
-      if (tid == 0) sh.cnt = 0;
-      __syncthreads();
-      const int32_t pe = min(phi, pb + kPairCap);
-      for (int32_t u = pb + tid; u < pe; u += 256) {
-        const int32_t pi = wl ? wl[u] : u;
-        const Pair pr = pairs[pi];
-        if (pr.s < row0 + rows_here && pr.s + pr.len > row0) {
-          const int32_t slot = atomicAdd(&sh.cnt, 1);
-          sh.lp[slot] = pi;
-          sh.lq[slot] = pi / c;
-          sh.ls[slot] = pr.s;
-          sh.le[slot] = pr.s + pr.len;
-        }
+    for (int32_t pb = plo; pb < phi; pb += kWavePairCap) {
+      const int32_t u = pb + lane;
+      bool hit = false;
+      int32_t pi = 0;
+      Pair pr{0, 0, 0, 0};
+      if (u < phi) {
+        pi = wl ? wl[u] : u;
+        pr = pairs[pi];
+        hit = pr.s < row0 + rows_here && pr.s + pr.len > row0;
       }
-      __syncthreads();
-      const int32_t P = sh.cnt;
-      for (int32_t g0 = 0; g0 < P; g0 += kPassPairs) {
-        const int np = min(kPassPairs, P - g0);
-        const int npc = (np + 15) / 16;
+      const uint64_t m = __ballot(hit);
+      if (hit) {
+        const int slot = __popcll(m & below);
+        sh.lp[slot] = pi;
+        sh.lq[slot] = pi / c;
+        sh.ls[slot] = pr.s;
+        sh.le[slot] = pr.s + pr.len;
+      }
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+      const int P = __popcll(m);
+      for (int g0 = 0; g0 < P; g0 += PP) {
+        const int np = min(PP, P - g0);
+        const int npc = NPCM == 1 ? 1 : (np + 15) / 16;
         floatx4 acc[RC][2];
 #pragma unroll
         for (int rc = 0; rc < RC; ++rc) {
@@ -857,37 +945,36 @@ __global__ __launch_bounds__(256) void rerank_kernel(
         }
         const QE* q0 = Q + int64_t(sh.lq[g0 + min(i, np - 1)]) * d;
         const QE* q1 = Q + int64_t(sh.lq[g0 + min(16 + i, np - 1)]) * d;
-        if (ks0 < ks1) {
-          if (npc > 1)
-            pass_loop<F, RC, 2, NT>(xr, q0, q1, ks0, ks1, sub, d, acc, xa, pre);
-          else
-            pass_loop<F, RC, 1, NT>(xr, q0, q1, ks0, ks1, sub, d, acc, xa, pre);
-          pre = false;
-        }
+        if (NPCM > 1 && npc > 1)
+          pass_loop<F, RC, 2, NT>(xr, q0, q1, 0, nsteps, sub, d, acc, xa, pre);
+        else
+          pass_loop<F, RC, 1, NT>(xr, q0, q1, 0, nsteps, sub, d, acc, xa, pre);
+        pre = false;
+        // D layout: acc[rc][pc][e] = pair g0 + 16 pc + 4 s + e, row 16 rc + i
 #pragma unroll
-        for (int pc = 0; pc < 2; ++pc) {
-          if (pc < npc) {
+        for (int pc = 0; pc < NPCM; ++pc) {
 #pragma unroll
-            for (int rc = 0; rc < RC; ++rc)
+          for (int e = 0; e < 4; ++e) {
+            const int pp = 16 * pc + 4 * s + e;
+            if (pc < npc && pp < np) {
+              const int32_t a = sh.ls[g0 + pp], en = sh.le[g0 + pp];
+              float* dst = sbuf + int64_t(sh.lp[g0 + pp]) * rcap - a;
 #pragma unroll
-              for (int e = 0; e < 4; ++e) part[wave][pc * 16 + 4 * s + e][rc * 16 + i] = acc[rc][pc][e];
+              for (int rc = 0; rc < RC; ++rc) {
+                const int rr = 16 * rc + i;
+                const int32_t row = row0 + rr;
+                if (rr < rows_here && row >= a && row < en) {
+                  float v = acc[rc][pc][e];
+                  if (row_scale) v *= row_scale[grow + rr];
+                  dst[row] = v;
+                }
+              }
+            }
           }
         }
-        __syncthreads();
-        for (int idx = tid; idx < np * RT; idx += 256) {
-          const int pp = idx / RT, rr = idx - pp * RT;
-          const int32_t row = row0 + rr;
-          const int32_t a = sh.ls[g0 + pp];
-          if (rr < rows_here && row >= a && row < sh.le[g0 + pp]) {
-            float v = part[0][pp][rr];
-#pragma unroll
-            for (int w = 1; w < kRerankWaves; ++w) v += part[w][pp][rr];
-            if (row_scale) v *= row_scale[grow + rr];
-            sbuf[int64_t(sh.lp[g0 + pp]) * rcap + (row - a)] = v;
-          }
-        }
-        __syncthreads();
       }
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
     }
   }
 }
@@ -940,7 +1027,7 @@ __global__ __launch_bounds__(256) void l1_gemm_kernel(const void* __restrict__ Q
   const XE* X = static_cast<const XE*>(Cv);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, s = lane >> 4;
-  const int sub = F::KS == 32 ? 8 * s : 4 * s;
+  const int sub = F::SUBW * s;
   const int64_t ntc = (C + kGemmTile - 1) / kGemmTile;
   const int64_t nblk = (nq + kGemmTile - 1) / kGemmTile * ntc;
   const int64_t per = (nblk + 7) / 8;
@@ -1098,13 +1185,13 @@ __global__ __launch_bounds__(kSelNT) void select_kernel(
 // the shortlist of sorted-row indices.
 constexpr int kWaveKeyCache = 2048;
 
-template <int MODE>
+template <int MODE, int R>
 __global__ __launch_bounds__(256) void wave_select_kernel(
     const Pair* __restrict__ pairs, const float* __restrict__ sbuf, int32_t rcap, int32_t c,
     int64_t nq, int32_t K, const int64_t* __restrict__ off, const int32_t* __restrict__ perm32,
     int64_t* __restrict__ ids, float* __restrict__ scores, int32_t kout,
     int32_t* __restrict__ slist) {
-  __shared__ uint32_t keys[4][kWaveKeyCache];
+  __shared__ uint32_t keys[4][R == 0 ? kWaveKeyCache : 1];
   __shared__ int32_t start[4][LIDER_MAX_C + 1];
   __shared__ int32_t pj[4][LIDER_MAX_C], ps[4][LIDER_MAX_C];
   __shared__ uint64_t ext[4][65];
@@ -1128,7 +1215,7 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
     const int32_t* st = start[wave];
     const int32_t n = st[c];
     const float* sbq = sbuf + q * int64_t(c) * rcap;
-    const bool cached = n <= kWaveKeyCache;
+    const bool cached = R == 0 && n <= kWaveKeyCache;
     if (cached) {
       for (int t = 0; t < c; ++t) {
         const int32_t a = st[t], len = st[t + 1] - a;
@@ -1152,12 +1239,33 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
       const int t = slot_of(i);
       return off[pj[wave][t]] + ps[wave][t] + (i - st[t]);
     };
+    // R > 0 (n <= 64 R): candidate i = lane + 64 j keeps its key in register j
+    uint32_t kr[R > 0 ? R : 1];
+    if (R > 0) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int32_t i = lane + 64 * j;
+        uint32_t kv = 0xffffffffu;
+        if (i < n) {
+          const int t = slot_of(i);
+          kv = score_key(sbq[int64_t(t) * rcap + (i - st[t])]);
+        }
+        kr[j] = kv;
+      }
+    }
     // extraction of the K + 1 smallest (key, index)
     const int want = min(n, K + 1);
     uint64_t prev = 0;
     for (int r = 0; r < want; ++r) {
       uint64_t best = ~uint64_t(0);
-      if (cached) {
+      if (R > 0) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const int32_t i = lane + 64 * j;
+          const uint64_t v = (uint64_t(kr[j]) << 32) | uint32_t(i);
+          if (i < n && (r == 0 || v > prev) && v < best) best = v;
+        }
+      } else if (cached) {
         for (int32_t i = lane; i < n; i += 64) {
           const uint64_t v = (uint64_t(keys[wave][i]) << 32) | uint32_t(i);
           if ((r == 0 || v > prev) && v < best) best = v;
@@ -1298,6 +1406,70 @@ __global__ __launch_bounds__(kSelNT) void rerank_shortlist_kernel(
   }
 }
 
+// Precision form, second pass for short lists (S <= 64): one wave per query.
+// The wave scores 4 shortlisted rows at a time, 16 lanes per row, each lane
+// owning the float4 slots [4 c + 64 j, 4 c + 64 j + 4) of the dimension range
+// (every load instruction reads 256 contiguous bytes of each of 4 rows);
+// lane partials are reduced over the 16 lanes by a fixed xor tree.  Then each
+// lane ranks one candidate by (score desc, id asc).  Needs d % 4 == 0 and
+// 16-byte aligned rows.
+__global__ __launch_bounds__(256) void wave_shortlist_kernel(
+    const float* __restrict__ X, int32_t d, const float* __restrict__ Q, int64_t nq,
+    const int32_t* __restrict__ slist, int32_t S, const int32_t* __restrict__ perm32, int32_t k,
+    int64_t* __restrict__ ids, float* __restrict__ scores) {
+  __shared__ float sc[4][64];
+  __shared__ uint32_t sid[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
+    const int32_t myrow = lane < S ? slist[q * S + lane] : -1;
+    const uint64_t valid = __ballot(myrow >= 0);
+    const int n = valid == ~uint64_t(0) ? 64 : __ffsll((long long)~valid) - 1;  // valid prefix
+    const float* qv = Q + q * d;
+    for (int t0 = 0; t0 < n; t0 += 4) {
+      const int t = min(t0 + g, n - 1);
+      const int32_t rw = __shfl(myrow, t);
+      const float* xr = X + int64_t(rw) * d;
+      float acc = 0.f;
+#pragma unroll 4
+      for (int l = 4 * c16; l < d; l += 64) {
+        const float4 xv = *reinterpret_cast<const float4*>(xr + l);
+        const float4 qq = *reinterpret_cast<const float4*>(qv + l);
+        acc += xv.x * qq.x;
+        acc += xv.y * qq.y;
+        acc += xv.z * qq.z;
+        acc += xv.w * qq.w;
+      }
+      acc += __shfl_xor(acc, 8);
+      acc += __shfl_xor(acc, 4);
+      acc += __shfl_xor(acc, 2);
+      acc += __shfl_xor(acc, 1);
+      if (c16 == 0 && t0 + g < n) sc[wave][t0 + g] = acc;
+    }
+    if (lane < n) sid[wave][lane] = uint32_t(perm32[myrow]);
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    if (lane < n) {
+      const uint32_t mk = score_key(sc[wave][lane]), mi = sid[wave][lane];
+      int rank = 0;
+      for (int u = 0; u < n; ++u) {
+        const uint32_t ku = score_key(sc[wave][u]), iu = sid[wave][u];
+        rank += (ku < mk) || (ku == mk && iu < mi);
+      }
+      if (rank < k) {
+        ids[q * k + rank] = int64_t(mi);
+        scores[q * k + rank] = key_score(mk);
+      }
+    }
+    for (int t = n + lane; t < k; t += 64) {
+      ids[q * k + t] = -1;
+      scores[q * k + t] = -INFINITY;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // ------------------------------------------------------------ debug exports
 __global__ void debug_kernel(const int32_t* __restrict__ l1, const Pair* __restrict__ pairs,
                              const int32_t* __restrict__ routed, int64_t nq, int32_t c,
@@ -1317,32 +1489,77 @@ __global__ void debug_kernel(const int32_t* __restrict__ l1, const Pair* __restr
   }
 }
 
+// Wave-per-query selection; candidate keys live in registers when every
+// query's candidate count (at most c * rcap) fits 64 R of them.
+template <int MODE>
+void launch_wave_select(unsigned wgrid, hipStream_t st, const Pair* pairs, const float* sbuf,
+                        int32_t rcap, int32_t c, int64_t nq, int32_t K, const int64_t* off,
+                        const int32_t* perm32, int64_t* ids, float* scores, int32_t kout,
+                        int32_t* slist) {
+  const int64_t nmax = int64_t(c) * rcap;
+  if (nmax <= 512)
+    hipLaunchKernelGGL((wave_select_kernel<MODE, 8>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist);
+  else if (nmax <= 1024)
+    hipLaunchKernelGGL((wave_select_kernel<MODE, 16>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist);
+  else if (nmax <= 2048)
+    hipLaunchKernelGGL((wave_select_kernel<MODE, 32>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist);
+  else
+    hipLaunchKernelGGL((wave_select_kernel<MODE, 0>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist);
+}
+
 template <int RT>
 void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, const int32_t* wl,
                   const Pair* pairs, int32_t c, const float* Q, const __hip_bfloat16* Qb,
                   float* sbuf, int32_t rcap, int persistent, int grid_mult, int32_t* ctr,
-                  const int32_t* alist, hipStream_t st) {
+                  const int32_t* alist, int npcm, hipStream_t st) {
   const int32_t nt = ix.n_tiles[ti];
   unsigned grid;
   if (persistent)
     grid = unsigned(std::max(8, ix.n_cu * grid_mult / 8 * 8));
   else
-    grid = unsigned((nt + 7) / 8 * 8);
-  const bool vec = (ix.d % 16 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
-  if (bf16 && ix.d % 32 != 0)
-    hipLaunchKernelGGL((rerank_kernel<RT, kBF16, false, true>), dim3(grid), dim3(256), 0, st,
+    grid = unsigned(((nt + 3) / 4 + 7) / 8 * 8);
+  const bool vec = (ix.d % 32 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
+  if (npcm == 1) {
+    if (bf16 && ix.d % 64 != 0)
+      hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false, 1>), dim3(grid), dim3(256), 0,
+                         st, (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                         (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
+                         alist);
+    else if (bf16)
+      hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false, 1>), dim3(grid), dim3(256), 0,
+                         st, (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                         (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
+                         alist);
+    else if (vec)
+      hipLaunchKernelGGL((rerank_kernel<RT, kF32W, true, false, 1>), dim3(grid), dim3(256), 0,
+                         st, (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                         (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
+                         alist);
+    else
+      hipLaunchKernelGGL((rerank_kernel<RT, kF32W, false, false, 1>), dim3(grid), dim3(256), 0,
+                         st, (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                         (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
+                         alist);
+    return;
+  }
+  if (bf16 && ix.d % 64 != 0)
+    hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
   else if (bf16)
-    hipLaunchKernelGGL((rerank_kernel<RT, kBF16, true, true>), dim3(grid), dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
   else if (vec)
-    hipLaunchKernelGGL((rerank_kernel<RT, kF32, true, true>), dim3(grid), dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<RT, kF32W, true, false>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
   else
-    hipLaunchKernelGGL((rerank_kernel<RT, kF32, false, true>), dim3(grid), dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<RT, kF32W, false, false>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
 }
@@ -1356,7 +1573,8 @@ void launch_l1_scores(const Index& ix, bool fp8, int64_t nq, const int32_t* l1cs
                       const Pair* l1pairs, const float* Q, const __hip_bfloat16* Qb, float* rs,
                       int32_t r1, hipStream_t st) {
   const int32_t nt = ix.n_l1_tiles;
-  const dim3 grid(unsigned((nt + 7) / 8 * 8), unsigned((nq + kL1PairChunk - 1) / kL1PairChunk));
+  const dim3 grid(unsigned(((nt + 3) / 4 + 7) / 8 * 8),
+                  unsigned((nq + kL1PairChunk - 1) / kL1PairChunk));
   const bool vec = (ix.d % 16 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
   if (fp8 && ix.d % 32 != 0)
     hipLaunchKernelGGL((rerank_kernel<64, kFP8, false, false>), grid, dim3(256), 0, st,
@@ -1491,9 +1709,12 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   hipLaunchKernelGGL(scatter_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, pairs, np,
                      cstart, cfill, wl);
   mark(3);
-  const int tr = o.tile_rows == 32 ? 32 : o.tile_rows == 128 ? 128 : 64;
-  const int ti = tr == 32 ? 0 : tr == 64 ? 1 : 2;
+  const int ti = tile_index(ix, o);
+  const int tr = 32 << ti;
   const int gm = o.grid_mult > 0 ? o.grid_mult : 4;
+  // pairs per MFMA pass: 16 when clusters average few pairs (fewer registers,
+  // higher occupancy), else 32
+  const int npcm = o.pass_pairs == 16 ? 1 : o.pass_pairs == 32 ? 2 : (np <= 12 * int64_t(C) ? 1 : 2);
   if (o.persistent == 2) {
     const int32_t nt = ix.n_tiles[ti];
     hipLaunchKernelGGL(zero_kernel, dim3(unsigned(std::min<int64_t>((nt + 255) / 256, 4096))),
@@ -1503,18 +1724,18 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   }
   if (tr == 32)
     launch_score<32>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
-                     ctr + 8, alist, st);
+                     ctr + 8, alist, npcm, st);
   else if (tr == 64)
     launch_score<64>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
-                     ctr + 8, alist, st);
+                     ctr + 8, alist, npcm, st);
   else
     launch_score<128>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
-                      ctr + 8, alist, st);
+                      ctr + 8, alist, npcm, st);
   mark(4);
   if (!bf16) {
     if (k <= 64)
-      hipLaunchKernelGGL(wave_select_kernel<0>, dim3(wgrid), dim3(256), 0, st, pairs, sbuf, p.rcap,
-                         c, nq, k, ix.off, ix.perm32, ids, scores, k, slist);
+      launch_wave_select<0>(wgrid, st, pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids,
+                            scores, k, slist);
     else if (k <= 128)
       hipLaunchKernelGGL((select_kernel<128, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
                          p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist);
@@ -1523,15 +1744,18 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
                          p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist);
   } else {
     if (p.S <= 64)
-      hipLaunchKernelGGL(wave_select_kernel<1>, dim3(wgrid), dim3(256), 0, st, pairs, sbuf, p.rcap,
-                         c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist);
+      launch_wave_select<1>(wgrid, st, pairs, sbuf, p.rcap, c, nq, p.S, ix.off, ix.perm32, ids,
+                            scores, k, slist);
     else if (p.S <= 512)
       hipLaunchKernelGGL((select_kernel<512, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
                          p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist);
     else
       hipLaunchKernelGGL((select_kernel<4096, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
                          p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist);
-    if (k <= 128)
+    if (p.S <= 64 && ix.d % 4 == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0)
+      hipLaunchKernelGGL(wave_shortlist_kernel, dim3(wgrid), dim3(256), 0, st, ix.X, ix.d, Q, nq,
+                         slist, p.S, ix.perm32, k, ids, scores);
+    else if (k <= 128)
       hipLaunchKernelGGL(rerank_shortlist_kernel<128>, dim3(qgrid), dim3(kSelNT), 0, st, ix.X,
                          ix.d, Q, nq, slist, p.S, ix.perm32, k, ids, scores);
     else

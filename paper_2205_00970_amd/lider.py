@@ -46,7 +46,7 @@ class BuildParams(C.Structure):
 class SearchOpts(C.Structure):
     _fields_ = [("r1", C.c_int32), ("precision", C.c_int32), ("shortlist_mult", C.c_int32),
                 ("persistent", C.c_int32), ("tile_rows", C.c_int32), ("l1_dense", C.c_int32),
-                ("grid_mult", C.c_int32), ("reserved", C.c_int32 * 9)]
+                ("grid_mult", C.c_int32), ("pass_pairs", C.c_int32), ("reserved", C.c_int32 * 8)]
 
 
 class SearchDebug(C.Structure):
@@ -204,21 +204,23 @@ class Index:
 
     @staticmethod
     def _opts(r1=0, precision="f32", shortlist_mult=0, persistent=False, tile_rows=0,
-              grid_mult=0, l1_dense=True):
+              grid_mult=0, l1_dense=True, pass_pairs=0):
         o = SearchOpts()
         o.r1, o.precision, o.shortlist_mult = int(r1), _PREC[precision], int(shortlist_mult)
         o.persistent, o.tile_rows, o.grid_mult = int(persistent), int(tile_rows), int(grid_mult)
         o.l1_dense = 0 if l1_dense else -1
+        o.pass_pairs = int(pass_pairs)
         return o
 
     def search(self, queries, k, c, r, r1=0, precision="f32", shortlist_mult=0,
                persistent=False, tile_rows=0, grid_mult=0, debug=False, stream=None, ws=None,
-               out=None, l1_dense=True):
+               out=None, l1_dense=True, pass_pairs=0):
         """Batched search; returns (ids int64 [nq,k], scores f32 [nq,k][, debug])."""
         torch = _torch()
         qp = _dev_ptr(queries, torch.float32, 2, "queries")
         nq = queries.shape[0]
-        o = self._opts(r1, precision, shortlist_mult, persistent, tile_rows, grid_mult, l1_dense)
+        o = self._opts(r1, precision, shortlist_mult, persistent, tile_rows, grid_mult, l1_dense,
+                       pass_pairs)
         need = int(lib().lider_search_workspace(self._h, nq, k, c, r, C.byref(o)))
         if need == 0 and nq > 0:
             # invalid arguments: let lider_search_ex report which
