@@ -981,41 +981,42 @@ __global__ __launch_bounds__(256) void rerank_kernel(
 
 // Layer-1 scores when every query's centroid window is the whole layer 1
 // (r1 = C): the dense product rs[q][p] = <Q[q], cent_l1[p]>, a GEMM on MFMA.
-// One 128 x 128 output tile per workgroup; workgroups are dealt to the 8 XCDs
-// round-robin, so consecutive tiles of one XCD share their query rows in its
-// L2.  Each wave owns a 64 x 64 quadrant (4 x 4 blocks of 16 x 16) over the
-// whole dimension range and reads its operand fragments straight from the
-// cache hierarchy, double-buffered across k-steps.  row_scale (nullable)
-// multiplies each centroid's scores (fp8 storage).  The routing decision only
-// uses these scores through an order-independent error bound, so the
-// summation order differs freely from the tiled window kernel.
-constexpr int kGemmTile = 128;
+// One (32 MB) x 128 output tile per workgroup; workgroups are dealt to the 8
+// XCDs round-robin, so consecutive tiles of one XCD share their query rows in
+// its L2.  Each wave owns a (16 MB) x 64 block (MB x 4 MFMA blocks of 16 x 16)
+// over the whole dimension range and reads its operand fragments straight
+// from the cache hierarchy, double-buffered across k-steps.  MB = 2 halves
+// the tile so that small batches still fill the chip in whole rounds.
+// row_scale (nullable) multiplies each centroid's scores (fp8 storage).  The
+// routing decision only uses these scores through an order-independent error
+// bound, so the summation order differs freely from the tiled window kernel.
+constexpr int kGemmTileN = 128;
 
-template <class F>
-__device__ __forceinline__ void gemm_load(const typename F::QE* const (&qr)[4],
+template <class F, int MB>
+__device__ __forceinline__ void gemm_load(const typename F::QE* const (&qr)[MB],
                                           const typename F::XE* const (&xr)[4], int k, int d,
-                                          typename F::T (&qa)[4], typename F::Raw (&xa)[4]) {
+                                          typename F::T (&qa)[MB], typename F::Raw (&xa)[4]) {
 #pragma unroll
-  for (int b = 0; b < 4; ++b) qa[b] = F::load(qr[b], k, d);
+  for (int b = 0; b < MB; ++b) qa[b] = F::load(qr[b], k, d);
 #pragma unroll
   for (int b = 0; b < 4; ++b) xa[b] = F::raw(xr[b], k, d, false);
 }
 
 // Centroid fragments are decoded (fp8 -> bf16) one block at a time, right
 // before their MFMAs, to keep the double-buffered registers small.
-template <class F>
-__device__ __forceinline__ void gemm_mfma(const typename F::T (&qa)[4],
+template <class F, int MB>
+__device__ __forceinline__ void gemm_mfma(const typename F::T (&qa)[MB],
                                           const typename F::Raw (&xa)[4], int k, int d,
-                                          floatx4 (&acc)[4][4]) {
+                                          floatx4 (&acc)[MB][4]) {
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) {
     const typename F::T x = F::dec(xa[nb], k, d);
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) F::mfma(qa[mb], x, acc[mb][nb]);
+    for (int mb = 0; mb < MB; ++mb) F::mfma(qa[mb], x, acc[mb][nb]);
   }
 }
 
-template <int FMT, bool VEC>
+template <int FMT, bool VEC, int MB>
 __global__ __launch_bounds__(256) void l1_gemm_kernel(const void* __restrict__ Qv, int64_t nq,
                                                       const void* __restrict__ Cv, int32_t C,
                                                       int32_t d, const float* __restrict__ row_scale,
@@ -1023,54 +1024,54 @@ __global__ __launch_bounds__(256) void l1_gemm_kernel(const void* __restrict__ Q
   typedef Feed<FMT, VEC> F;
   typedef typename F::XE XE;
   typedef typename F::QE QE;
+  constexpr int TM = 32 * MB;  // query rows per workgroup tile
   const QE* Q = static_cast<const QE*>(Qv);
   const XE* X = static_cast<const XE*>(Cv);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, s = lane >> 4;
   const int sub = F::SUBW * s;
-  const int64_t ntc = (C + kGemmTile - 1) / kGemmTile;
-  const int64_t nblk = (nq + kGemmTile - 1) / kGemmTile * ntc;
+  const int64_t ntc = (C + kGemmTileN - 1) / kGemmTileN;
+  const int64_t nblk = (nq + TM - 1) / TM * ntc;
   const int64_t per = (nblk + 7) / 8;
   const int64_t t = int64_t(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if ((blockIdx.x >> 3) >= per || t >= nblk) return;
-  const int64_t q0 = (t / ntc) * kGemmTile + (wave & 1) * 64;
-  const int32_t c0 = int32_t(t % ntc) * kGemmTile + (wave >> 1) * 64;
-  const QE* qr[4];
+  const int64_t q0 = (t / ntc) * TM + (wave & 1) * (16 * MB);
+  const int32_t c0 = int32_t(t % ntc) * kGemmTileN + (wave >> 1) * 64;
+  const QE* qr[MB];
   const XE* xr[4];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    qr[b] = Q + min(q0 + 16 * b + i, nq - 1) * d;
-    xr[b] = X + int64_t(min(c0 + 16 * b + i, C - 1)) * d;
-  }
-  floatx4 acc[4][4];
+  for (int b = 0; b < MB; ++b) qr[b] = Q + min(q0 + 16 * b + i, nq - 1) * d;
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+  for (int b = 0; b < 4; ++b) xr[b] = X + int64_t(min(c0 + 16 * b + i, C - 1)) * d;
+  floatx4 acc[MB][4];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int nsteps = (d + F::KS - 1) / F::KS;
-  typename F::T qa[4], qb[4];
+  typename F::T qa[MB], qb[MB];
   typename F::Raw xa[4], xb[4];
-  gemm_load<F>(qr, xr, sub, d, qa, xa);
+  gemm_load<F, MB>(qr, xr, sub, d, qa, xa);
   int ks = 0;
   for (; ks + 1 < nsteps; ks += 2) {
     const int k1 = (ks + 1) * F::KS + sub, k2 = (ks + 2 < nsteps ? ks + 2 : nsteps - 1) * F::KS + sub;
-    gemm_load<F>(qr, xr, k1, d, qb, xb);
+    gemm_load<F, MB>(qr, xr, k1, d, qb, xb);
     __builtin_amdgcn_sched_barrier(0);
-    gemm_mfma<F>(qa, xa, ks * F::KS + sub, d, acc);
+    gemm_mfma<F, MB>(qa, xa, ks * F::KS + sub, d, acc);
     __builtin_amdgcn_sched_barrier(0);
-    gemm_load<F>(qr, xr, k2, d, qa, xa);
+    gemm_load<F, MB>(qr, xr, k2, d, qa, xa);
     __builtin_amdgcn_sched_barrier(0);
-    gemm_mfma<F>(qb, xb, k1, d, acc);
+    gemm_mfma<F, MB>(qb, xb, k1, d, acc);
     __builtin_amdgcn_sched_barrier(0);
   }
-  if (ks < nsteps) gemm_mfma<F>(qa, xa, ks * F::KS + sub, d, acc);
+  if (ks < nsteps) gemm_mfma<F, MB>(qa, xa, ks * F::KS + sub, d, acc);
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) {
     const int32_t p = c0 + 16 * nb + i;
     if (p >= C) continue;
     const float sc = row_scale ? row_scale[p] : 1.f;
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t q = q0 + 16 * mb + 4 * s + e;
@@ -1602,24 +1603,35 @@ void launch_l1_scores(const Index& ix, bool fp8, int64_t nq, const int32_t* l1cs
                        (const int32_t*)nullptr);
 }
 
-// Dense layer-1 scores (r1 = C) on the GEMM kernel.
-void launch_l1_gemm(const Index& ix, bool fp8, int64_t nq, const float* Q,
-                    const __hip_bfloat16* Qb, float* rs, hipStream_t st) {
-  const int64_t nblk = (nq + kGemmTile - 1) / kGemmTile * ((ix.C + kGemmTile - 1) / kGemmTile);
+// Dense layer-1 scores (r1 = C) on the GEMM kernel: 128-row query tiles when
+// that still gives at least 4 workgroups per CU, else 64-row tiles.
+template <int MB>
+void launch_l1_gemm_mb(const Index& ix, bool fp8, int64_t nq, const float* Q,
+                       const __hip_bfloat16* Qb, float* rs, hipStream_t st) {
+  const int64_t nblk = (nq + 32 * MB - 1) / (32 * MB) * ((ix.C + kGemmTileN - 1) / kGemmTileN);
   const dim3 grid(unsigned((nblk + 7) / 8 * 8));
   const bool vec = (ix.d % 16 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
   if (fp8 && ix.d % 32 == 0)
-    hipLaunchKernelGGL((l1_gemm_kernel<kFP8, true>), grid, dim3(256), 0, st, (const void*)Qb, nq,
-                       (const void*)ix.cent8, ix.C, ix.d, (const float*)ix.cent8_scale, rs);
+    hipLaunchKernelGGL((l1_gemm_kernel<kFP8, true, MB>), grid, dim3(256), 0, st, (const void*)Qb,
+                       nq, (const void*)ix.cent8, ix.C, ix.d, (const float*)ix.cent8_scale, rs);
   else if (fp8)
-    hipLaunchKernelGGL((l1_gemm_kernel<kFP8, false>), grid, dim3(256), 0, st, (const void*)Qb,
+    hipLaunchKernelGGL((l1_gemm_kernel<kFP8, false, MB>), grid, dim3(256), 0, st, (const void*)Qb,
                        nq, (const void*)ix.cent8, ix.C, ix.d, (const float*)ix.cent8_scale, rs);
   else if (vec)
-    hipLaunchKernelGGL((l1_gemm_kernel<kF32, true>), grid, dim3(256), 0, st, (const void*)Q, nq,
-                       (const void*)ix.cent_l1, ix.C, ix.d, (const float*)nullptr, rs);
+    hipLaunchKernelGGL((l1_gemm_kernel<kF32, true, MB>), grid, dim3(256), 0, st, (const void*)Q,
+                       nq, (const void*)ix.cent_l1, ix.C, ix.d, (const float*)nullptr, rs);
   else
-    hipLaunchKernelGGL((l1_gemm_kernel<kF32, false>), grid, dim3(256), 0, st, (const void*)Q, nq,
-                       (const void*)ix.cent_l1, ix.C, ix.d, (const float*)nullptr, rs);
+    hipLaunchKernelGGL((l1_gemm_kernel<kF32, false, MB>), grid, dim3(256), 0, st, (const void*)Q,
+                       nq, (const void*)ix.cent_l1, ix.C, ix.d, (const float*)nullptr, rs);
+}
+
+void launch_l1_gemm(const Index& ix, bool fp8, int64_t nq, const float* Q,
+                    const __hip_bfloat16* Qb, float* rs, hipStream_t st) {
+  const int64_t nblk4 = (nq + 127) / 128 * ((ix.C + kGemmTileN - 1) / kGemmTileN);
+  if (nblk4 >= 4 * int64_t(ix.n_cu))
+    launch_l1_gemm_mb<4>(ix, fp8, nq, Q, Qb, rs, st);
+  else
+    launch_l1_gemm_mb<2>(ix, fp8, nq, Q, Qb, rs, st);
 }
 
 }  // namespace
