@@ -43,6 +43,10 @@ def lib():
         p = C.c_void_p
         i32, i64, u64, f64 = C.c_int32, C.c_int64, C.c_uint64, C.c_double
         L.or_digits.argtypes = [p, i64, i32, p, p, i32, f64, p]
+        L.or_digits_sign.argtypes = [p, i64, i32, p, i32, p]
+        L.or_dist_e.argtypes = [u64, u64, i32, i32]
+        L.or_dist_e.restype = i64
+        L.or_window_expand_pub.argtypes = [p, i64, i64, i64, u64, i32, i32, p, p]
         L.or_kmeans_assign.argtypes = [p, i64, i32, p, i32, p]
         L.or_kmeans_update.argtypes = [p, i64, i32, p, i32, p, p]
         L.or_kmeans.argtypes = [p, i64, i32, i32, p, i32, p, p, p]
@@ -55,10 +59,10 @@ def lib():
         L.or_encode_box.argtypes = [p, i32, p, p, i32, p]
         L.or_encode_box.restype = u64
         L.or_window_pub.argtypes = [i64, i64, i64, p, p]
-        L.or_build.argtypes = [p, i64, i32, i32, p, p, i32, p, p, i32, f64, i32, i32, p]
+        L.or_build.argtypes = [p, i64, i32, i32, p, p, i32, p, p, i32, f64, i32, i32, i32, p]
         L.or_build.restype = p
         L.or_free.argtypes = [p]
-        L.or_search.argtypes = [p, p, i64, i32, i32, i32, i32, p, p, p, p, p, p]
+        L.or_search.argtypes = [p, p, i64, i32, i32, i32, i32, i32, p, p, p, p, p, p]
         L.or_bruteforce.argtypes = [p, i64, i32, p, i64, i32, p, p]
         L.or_pair_scores.argtypes = [p, p, i32, p, p, i64, p]
         L.or_iters_run.argtypes = [p]
@@ -68,7 +72,7 @@ def lib():
             getattr(L, name).argtypes = [p, p]
         L.or_get_l1.argtypes = [p, p, p, p]
         L.or_get_model.argtypes = [p, i32, p, p, p, p, p, p, p, p]
-        L.or_core.argtypes = [i64, i32, i32, p, p, p, p, p, p, p, p, p, p, p]
+        L.or_core.argtypes = [i64, i32, i32, p, i32, p, p, p, p, p, p, p, p, p, p]
         L.or_core_query.argtypes = [i64, i32, i32, i32, p, p, p, p, p, p, p, p]
         L.or_core_query.restype = i64
         _lib = L
@@ -94,6 +98,30 @@ def digits(X, A, b, w):
     _check(lib().or_digits(_ptr(X), X.shape[0], X.shape[1], _ptr(A), _ptr(b), A.shape[0],
                            float(w), _ptr(out)), "digits")
     return out
+
+
+def digits_sign(X, A):
+    """Random-hyperplane bits: out[r, i] = 1 if A[i] . X[r] >= 0 else 0."""
+    X, A = _f32(X), _f32(A)
+    out = np.empty((X.shape[0], A.shape[0]), np.int32)
+    _check(lib().or_digits_sign(_ptr(X), X.shape[0], X.shape[1], _ptr(A), A.shape[0],
+                                _ptr(out)), "digits_sign")
+    return out
+
+
+def dist_e(K1, K2, m, B):
+    """2^B * dist_e of two m-bit hashkeys (an exact integer)."""
+    return int(lib().or_dist_e(int(K1), int(K2), int(m), int(B)))
+
+
+def window_expand(keys, pos, r, Kq, m, B):
+    """(start, length) of the dist_e-guided expansion around `pos`."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    st = np.zeros(1, np.int64)
+    ln = np.zeros(1, np.int64)
+    lib().or_window_expand_pub(_ptr(keys), keys.shape[0], int(pos), int(r), int(Kq), int(m),
+                               int(B), _ptr(st), _ptr(ln))
+    return int(st[0]), int(ln[0])
 
 
 def kmeans_assign(X, cent):
@@ -191,8 +219,9 @@ def pair_scores(X, Q, qi, xi):
     return out
 
 
-def core(digits, F):
-    """Build one stand-alone core model over items given in ascending id order."""
+def core(digits, F, binary=False):
+    """Build one stand-alone core model over items given in ascending id order
+    (binary: bit hashkeys with the fixed [0, 1] box, key = Decimal(bits))."""
     dg = np.ascontiguousarray(digits, dtype=np.int32)
     L, m = dg.shape
     order = np.empty(L, np.int64)
@@ -205,7 +234,8 @@ def core(digits, F):
     leaf = np.zeros(2 * F)
     elo = np.zeros(F, np.int32)
     ehi = np.zeros(F, np.int32)
-    _check(lib().or_core(L, m, F, _ptr(dg), _ptr(order), _ptr(keys), _ptr(me), _ptr(mins),
+    _check(lib().or_core(L, m, F, _ptr(dg), int(bool(binary)), _ptr(order), _ptr(keys), _ptr(me),
+                         _ptr(mins),
                          _ptr(maxs), _ptr(kk), _ptr(dbl), _ptr(leaf), _ptr(elo), _ptr(ehi)),
            "core")
     model = Model(L, int(me[0]), F, mins, maxs, int(kk[0]), int(kk[1]), float(dbl[0]),
@@ -243,10 +273,12 @@ class Index:
     """Oracle LIDER index (Sections 3.2-3.3).  Keeps a reference to X."""
 
     def __init__(self, X, n_clusters, A, b, m, w, rmi_fanout, rmi_fanout_l1=None,
-                 assignment=None, init_ids=None, kmeans_iters=20, seeding="given"):
+                 assignment=None, init_ids=None, kmeans_iters=20, seeding="given",
+                 hash_kind="e2lsh"):
         self.X = _f32(X)
         self.n, self.d = self.X.shape
         self.C, self.m, self.w = int(n_clusters), int(m), float(w)
+        self.kind = {"e2lsh": 0, "sign": 1}[hash_kind]
         self.F2 = int(rmi_fanout)
         self.F1 = int(rmi_fanout_l1 if rmi_fanout_l1 is not None else rmi_fanout)
         self.A, self.b = _f32(A), _f32(b)
@@ -261,7 +293,7 @@ class Index:
         st = C.c_int(0)
         h = lib().or_build(_ptr(self.X), self.n, self.d, self.C, _ptr(asg), _ptr(ini),
                            int(kmeans_iters), _ptr(self.A), _ptr(self.b), self.m, self.w,
-                           self.F2, self.F1, C.byref(st))
+                           self.F2, self.F1, self.kind, C.byref(st))
         _check(st.value, "build")
         self._h = C.c_void_p(h)
 
@@ -328,7 +360,7 @@ class Index:
                      int(kk[1]), float(dbl[0]), dbl[1:3].copy(), leaf, elo, ehi)
 
     # -- search ----------------------------------------------------------------
-    def search(self, Q, k, c, r, r1=None, debug=False):
+    def search(self, Q, k, c, r, r1=None, debug=False, expand_bits=0):
         Q = _f32(Q)
         nq = Q.shape[0]
         r1 = r if r1 is None else r1
@@ -340,7 +372,8 @@ class Index:
                        l1=np.empty((nq, 3), np.int64),
                        routed=np.empty((nq, c), np.int32),
                        pairs=np.empty((nq, c, 3), np.int64))
-        _check(lib().or_search(self._h, _ptr(Q), nq, k, c, r, r1, _ptr(ids), _ptr(sc),
+        _check(lib().or_search(self._h, _ptr(Q), nq, k, c, r, r1, int(expand_bits), _ptr(ids),
+                               _ptr(sc),
                                _ptr(dbg["qdigits"]) if dbg else None,
                                _ptr(dbg["l1"]) if dbg else None,
                                _ptr(dbg["routed"]) if dbg else None,

@@ -49,6 +49,24 @@ static int or_digit(const float* a, const float* x, int32_t d, float b, double w
   return OR_OK;
 }
 
+/* Section 4.1 (the cosine variant of ESK-LSH): random-hyperplane LSH, one
+ * bit per hash function, h_i(x) = 1 if a_i . x >= 0 else 0, with the same
+ * sequential FP64 dot product.  Reading: a projection of exactly zero gives 1. */
+static int32_t or_bit(const float* a, const float* x, int32_t d) {
+  double s = 0.0;
+  for (int32_t l = 0; l < d; ++l) s = s + (double)a[l] * (double)x[l];
+  return s >= 0.0 ? 1 : 0;
+}
+
+int or_digits_sign(const float* X, int64_t n, int32_t d, const float* A, int32_t nh,
+                   int32_t* out) {
+  if (n < 0 || d < 1 || nh < 1) return OR_EINVAL;
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < n; ++r)
+    for (int32_t i = 0; i < nh; ++i) out[r * nh + i] = or_bit(A + (int64_t)i * d, X + r * d, d);
+  return OR_OK;
+}
+
 /* Digits of n rows: out[r*nh + i] = h_i(X[r]).  A is [nh x d] row-major. */
 int or_digits(const float* X, int64_t n, int32_t d, const float* A, const float* b,
               int32_t nh, double w, int32_t* out) {
@@ -417,13 +435,70 @@ void or_window_pub(int64_t pos, int64_t r, int64_t L, int64_t* start, int64_t* l
   or_window(pos, r, L, start, len);
 }
 
+/* Section 4.2, extended hashkey distance of two m-bit hashkeys (bit 1 most
+ * significant, as Decimal() reads them):
+ *   dist_e(K1, K2) = KL(K1, K2) + KD_e(K1, K2) / C,   C = 2^B,
+ * KL = the non-prefix length (m minus the length of the common prefix), KD_e =
+ * |Decimal(K1[l+1 .. l+B]) - Decimal(K2[l+1 .. l+B])| over the B bits right
+ * after the common prefix of length l.  Returned as the integer
+ * C * dist_e = KL * 2^B + KD_e (exact).  Reading: when fewer than B bits follow
+ * the prefix, the sub-sequence is the remaining bits (still divided by 2^B). */
+int64_t or_dist_e(uint64_t K1, uint64_t K2, int32_t m, int32_t B) {
+  int32_t l = 0;
+  while (l < m && ((K1 >> (m - 1 - l)) & 1u) == ((K2 >> (m - 1 - l)) & 1u)) ++l;
+  int64_t KL = m - l;
+  int64_t v1 = 0, v2 = 0;
+  for (int32_t t = l; t < l + B && t < m; ++t) {
+    v1 = v1 * 2 + (int64_t)((K1 >> (m - 1 - t)) & 1u);
+    v2 = v2 * 2 + (int64_t)((K2 >> (m - 1 - t)) & 1u);
+  }
+  int64_t KD = v1 > v2 ? v1 - v2 : v2 - v1;
+  return KL * ((int64_t)1 << B) + KD;
+}
+
+/* Bi-directional expansion search guided by dist_e (Sections 3.3.1, 4.2):
+ * starting from the predicted location, the range grows one position at a
+ * time on the side whose next hashkey is closer to the query hashkey Kq in
+ * dist_e, until min(r, L) positions are taken; when one side is exhausted the
+ * other continues.  keys[0..L) is the sorted hashkey array.  Reading: the
+ * predicted location itself is taken first and a tie goes to the left side. */
+static void or_window_expand(const uint64_t* keys, int64_t L, int64_t pos, int64_t r,
+                             uint64_t Kq, int32_t m, int32_t B, int64_t* start, int64_t* len) {
+  int64_t take = r < L ? r : L;
+  if (take <= 0) {
+    *start = 0;
+    *len = 0;
+    return;
+  }
+  int64_t lo = pos - 1, hi = pos + 1, got = 1;
+  while (got < take) {
+    if (lo < 0) {
+      ++hi;
+    } else if (hi >= L) {
+      --lo;
+    } else if (or_dist_e(keys[lo], Kq, m, B) <= or_dist_e(keys[hi], Kq, m, B)) {
+      --lo;
+    } else {
+      ++hi;
+    }
+    ++got;
+  }
+  *start = lo + 1;
+  *len = take;
+}
+
+void or_window_expand_pub(const uint64_t* keys, int64_t L, int64_t pos, int64_t r, uint64_t Kq,
+                          int32_t m, int32_t B, int64_t* start, int64_t* len) {
+  or_window_expand(keys, L, pos, r, Kq, m, B, start, len);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Build one core model over L items whose digits (row-major, m per item) and
  * ids are given in ascending id order (Section 3.3.1): hash keys are sorted
  * (SK-LSH order, ties by id), re-scaled (Eq. (8)) and the RMI is trained on
  * (key, location).  order[p] = index (into the given items) at location p. */
 static int or_core_build(or_model* M, int64_t L, int32_t m, int32_t F, const int32_t* digits,
-                         int64_t* order, uint64_t* keys_sorted);
+                         int32_t binary, int64_t* order, uint64_t* keys_sorted);
 
 typedef struct {
   uint64_t key;
@@ -438,8 +513,10 @@ static int or_kv_cmp(const void* a, const void* b) {
   return 0;
 }
 
+/* binary: the hashkeys are bits (Section 4.1) and the key is Decimal() of
+ * the bit string (Section 5.1): the box is fixed at [0, 1] for every bit. */
 static int or_core_build(or_model* M, int64_t L, int32_t m, int32_t F, const int32_t* digits,
-                         int64_t* order, uint64_t* keys_sorted) {
+                         int32_t binary, int64_t* order, uint64_t* keys_sorted) {
   memset(M, 0, sizeof(*M));
   M->L = L;
   M->m = m;
@@ -451,15 +528,16 @@ static int or_core_build(or_model* M, int64_t L, int32_t m, int32_t F, const int
   if (L == 0) return OR_OK;
   int32_t mins[OR_MAX_M], maxs[OR_MAX_M];
   for (int32_t i = 0; i < m; ++i) {
-    mins[i] = digits[i];
-    maxs[i] = digits[i];
+    mins[i] = binary ? 0 : digits[i];
+    maxs[i] = binary ? 1 : digits[i];
   }
-  for (int64_t t = 1; t < L; ++t)
-    for (int32_t i = 0; i < m; ++i) {
-      int32_t v = digits[t * m + i];
-      if (v < mins[i]) mins[i] = v;
-      if (v > maxs[i]) maxs[i] = v;
-    }
+  if (!binary)
+    for (int64_t t = 1; t < L; ++t)
+      for (int32_t i = 0; i < m; ++i) {
+        int32_t v = digits[t * m + i];
+        if (v < mins[i]) mins[i] = v;
+        if (v > maxs[i]) maxs[i] = v;
+      }
   or_model_box(M, m, mins, maxs);
   or_kv* kv = (or_kv*)malloc(sizeof(or_kv) * (size_t)L);
   double* x = (double*)malloc(sizeof(double) * (size_t)L);
@@ -505,6 +583,7 @@ typedef struct {
   int64_t n;
   int32_t d, C, m, F2, F1;
   double w;
+  int32_t kind;        /* 0: Euclidean E2LSH digits, 1: sign bits (Section 4.1) */
   const float* X;      /* caller-owned corpus, original id order [n x d] */
   float* A;            /* [2m x d]: rows 0..m-1 layer 1, m..2m-1 layer 2 */
   float* b;            /* [2m] */
@@ -548,10 +627,10 @@ void or_free(or_index* ix) {
  * centroids (layer 1) and one per cluster over its members (layer 2). */
 or_index* or_build(const float* X, int64_t n, int32_t d, int32_t C, const int32_t* assign_in,
                    const int64_t* init_ids, int32_t kmeans_iters, const float* A, const float* b,
-                   int32_t m, double w, int32_t F2, int32_t F1, int* status) {
+                   int32_t m, double w, int32_t F2, int32_t F1, int32_t kind, int* status) {
   *status = OR_EINVAL;
   if (n < 1 || d < 1 || C < 1 || C > n || m < 1 || m > OR_MAX_M || !(w > 0.0) || F2 < 1 ||
-      F1 < 1)
+      F1 < 1 || kind < 0 || kind > 1 || (kind == 1 && m > 53))
     return NULL;
   or_index* ix = (or_index*)calloc(1, sizeof(or_index));
   if (!ix) {
@@ -565,6 +644,7 @@ or_index* or_build(const float* X, int64_t n, int32_t d, int32_t C, const int32_
   ix->F2 = F2;
   ix->F1 = F1;
   ix->w = w;
+  ix->kind = kind;
   ix->X = X;
   ix->A = (float*)malloc(sizeof(float) * (size_t)2 * m * d);
   ix->b = (float*)malloc(sizeof(float) * (size_t)2 * m);
@@ -616,7 +696,8 @@ or_index* or_build(const float* X, int64_t n, int32_t d, int32_t C, const int32_
     return NULL;
   }
   /* layer-2 digits of every row (hash set rows m..2m-1) */
-  st = or_digits(X, n, d, A + (size_t)m * d, b + m, m, w, ix->digits);
+  st = kind ? or_digits_sign(X, n, d, A + (size_t)m * d, m, ix->digits)
+            : or_digits(X, n, d, A + (size_t)m * d, b + m, m, w, ix->digits);
   if (st != OR_OK) {
     or_free(ix);
     *status = st;
@@ -645,7 +726,7 @@ or_index* or_build(const float* X, int64_t n, int32_t d, int32_t C, const int32_
   st = OR_OK;
   for (int32_t j = 0; j < C && st == OR_OK; ++j) {
     int64_t o = ix->off[j], L = ix->off[j + 1] - o;
-    st = or_core_build(&ix->models[j], L, m, F2, mdig + o * m, order + o, ix->keys + o);
+    st = or_core_build(&ix->models[j], L, m, F2, mdig + o * m, kind, order + o, ix->keys + o);
     for (int64_t p = 0; p < L; ++p) ix->perm[o + p] = members[o + order[o + p]];
   }
   free(fill);
@@ -659,9 +740,11 @@ or_index* or_build(const float* X, int64_t n, int32_t d, int32_t C, const int32_
   }
   /* layer 1: the centroids retriever over the C centroids (hash set rows
    * 0..m-1), ids = cluster index */
-  st = or_digits(ix->cent, C, d, A, b, m, w, ix->l1_digits);
+  st = kind ? or_digits_sign(ix->cent, C, d, A, m, ix->l1_digits)
+            : or_digits(ix->cent, C, d, A, b, m, w, ix->l1_digits);
   if (st == OR_OK)
-    st = or_core_build(&ix->models[C], C, m, F1, ix->l1_digits, ix->l1_order, ix->l1_keys);
+    st = or_core_build(&ix->models[C], C, m, F1, ix->l1_digits, kind, ix->l1_order,
+                       ix->l1_keys);
   if (st != OR_OK) {
     or_free(ix);
     *status = st;
@@ -715,9 +798,11 @@ static double or_dot(const float* a, const float* x, int32_t d) {
  *   routed [nq x c]          routed cluster ids, score desc, id asc (-1 pad)
  *   pairs [nq x c x 3]       per routed cluster: location, start, length */
 int or_search(const or_index* ix, const float* Q, int64_t nq, int32_t k, int32_t c, int32_t r,
-              int32_t r1, int64_t* ids, double* scores, int32_t* qdig, int64_t* l1,
-              int32_t* routed, int64_t* pairs) {
+              int32_t r1, int32_t expand_bits, int64_t* ids, double* scores, int32_t* qdig,
+              int64_t* l1, int32_t* routed, int64_t* pairs) {
   if (!ix || nq < 0 || k < 1 || c < 1 || c > ix->C || r < 1 || r1 < 1) return OR_EINVAL;
+  /* expand_bits = B > 0: dist_e-guided expansion (binary hashkeys only) */
+  if (expand_bits < 0 || expand_bits > 16 || (expand_bits > 0 && ix->kind != 1)) return OR_EINVAL;
   const int32_t m = ix->m, d = ix->d, C = ix->C;
   int status = OR_OK;
 #pragma omp parallel
@@ -733,7 +818,9 @@ int or_search(const or_index* ix, const float* Q, int64_t nq, int32_t k, int32_t
       for (int64_t q = 0; q < nq; ++q) {
         const float* qv = Q + q * d;
         for (int32_t i = 0; i < 2 * m; ++i) {
-          if (or_digit(ix->A + (int64_t)i * d, qv, d, ix->b[i], ix->w, dg + i) != OR_OK) {
+          if (ix->kind) {
+            dg[i] = or_bit(ix->A + (int64_t)i * d, qv, d);
+          } else if (or_digit(ix->A + (int64_t)i * d, qv, d, ix->b[i], ix->w, dg + i) != OR_OK) {
 #pragma omp atomic write
             status = OR_ERANGE;
             dg[i] = 0;
@@ -747,7 +834,10 @@ int or_search(const or_index* ix, const float* Q, int64_t nq, int32_t k, int32_t
         const or_model* M1 = &ix->models[C];
         int64_t pos1 = or_model_locate(M1, dg, &K, &xq);
         int64_t s1, len1;
-        or_window(pos1, r1, C, &s1, &len1);
+        if (expand_bits)
+          or_window_expand(ix->l1_keys, C, pos1, r1, K, m, expand_bits, &s1, &len1);
+        else
+          or_window(pos1, r1, C, &s1, &len1);
         if (l1) {
           l1[q * 3 + 0] = pos1;
           l1[q * 3 + 1] = s1;
@@ -768,7 +858,10 @@ int or_search(const or_index* ix, const float* Q, int64_t nq, int32_t k, int32_t
             int64_t j = rb[t].id;
             const or_model* Mj = &ix->models[j];
             pos = or_model_locate(Mj, dg + m, &K, &xq);
-            or_window(pos, r, Mj->L, &s, &len);
+            if (expand_bits)
+              or_window_expand(ix->keys + ix->off[j], Mj->L, pos, r, K, m, expand_bits, &s, &len);
+            else
+              or_window(pos, r, Mj->L, &s, &len);
             for (int64_t p = s; p < s + len; ++p) {
               int64_t id = ix->perm[ix->off[j] + p];
               or_topk_push(best, &nb, k, or_dot(qv, ix->X + id * d, d), id);
@@ -882,12 +975,12 @@ void or_get_model(const or_index* ix, int32_t j, int64_t* ints, int32_t* mins, i
 /* ------------------------------------------------------------------------ */
 /* One stand-alone core model for the tests: build from digits given in
  * ascending id order, export its parameters, locate query digits. */
-int or_core(int64_t L, int32_t m, int32_t F, const int32_t* digits, int64_t* order,
-            uint64_t* keys, int32_t* meff, int32_t* mins, int32_t* maxs, uint64_t* kminmax,
-            double* dbl, double* leaf, int32_t* elo, int32_t* ehi) {
+int or_core(int64_t L, int32_t m, int32_t F, const int32_t* digits, int32_t binary,
+            int64_t* order, uint64_t* keys, int32_t* meff, int32_t* mins, int32_t* maxs,
+            uint64_t* kminmax, double* dbl, double* leaf, int32_t* elo, int32_t* ehi) {
   if (L < 0 || m < 1 || m > OR_MAX_M || F < 1) return OR_EINVAL;
   or_model M;
-  int st = or_core_build(&M, L, m, F, digits, order, keys);
+  int st = or_core_build(&M, L, m, F, digits, binary, order, keys);
   if (st == OR_OK) {
     *meff = M.m_eff;
     for (int32_t i = 0; i < m; ++i) {
