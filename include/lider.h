@@ -52,6 +52,10 @@ typedef enum {
 #define LIDER_MAX_K 1024
 #define LIDER_MAX_C 128
 
+/* Hash families (lider_build_params.hash_kind). */
+#define LIDER_HASH_E2LSH 0
+#define LIDER_HASH_SIGN 1
+
 typedef struct lider_index lider_index; /* opaque; owns its device memory */
 
 /* Build parameters (Sections 3.2, 3.3, 5).
@@ -80,7 +84,15 @@ typedef struct lider_index lider_index; /* opaque; owns its device memory */
  *                 1: farthest-first traversal -- the first centroid is row
  *                 kmeans_init_host[0], each next one the row farthest (squared
  *                 Euclidean, decided in FP64, ties to the smaller id) from its
- *                 nearest chosen centroid. */
+ *                 nearest chosen centroid.
+ *  hash_kind      LIDER_HASH_E2LSH: integer digits floor((a.x + b) / w), keys
+ *                 mixed-radix over each model's digit box.  LIDER_HASH_SIGN:
+ *                 the cosine variant of Section 4.1 -- one bit per hash,
+ *                 1 if a.x >= 0 else 0 (decided in FP64 like the digits; w and
+ *                 lsh_b_host are ignored, lsh_b_host may be NULL), key =
+ *                 Decimal(bits) (Section 5.1), i.e. the box is [0, 1] for
+ *                 every bit.  Use on normalised embeddings (inner product =
+ *                 cosine similarity). */
 typedef struct {
   int32_t n_clusters;
   int32_t m;
@@ -95,6 +107,7 @@ typedef struct {
   int32_t storage;
   int32_t centroid_storage;
   int32_t kmeans_seeding;
+  int32_t hash_kind;
 } lider_build_params;
 
 /* Build an index over corpus_dev [n x d] fp32 (Sections 3.2, 3.3.1, 3.3.2):
@@ -137,6 +150,13 @@ const char* lider_last_error(void);
  *                 dense query x centroid product on MFMA (default); -1: always
  *                 the window kernel.  Results are identical.
  *  grid_mult      persistent grid = grid_mult * number of CUs (0 = 4).
+ *  expand_bits    0: fixed window of r (r1) positions, floor(r/2) left of the
+ *                 predicted location (shifted inward at the ends).  B in 1..16:
+ *                 dist_e-guided expansion (Section 4.2, C = 2^B), only for
+ *                 LIDER_HASH_SIGN indexes -- from the predicted location the
+ *                 range grows on the side whose next hashkey is closer to the
+ *                 query's in dist_e (ties to the left) until r (r1) positions
+ *                 are taken.  Applies to both layers.
  *  pass_pairs     (query, cluster) pairs per MFMA pass of the rerank: 16, 32,
  *                 or 0 (16 when there are at most 12 pairs per cluster on
  *                 average, else 32).  Results are identical. */
@@ -149,7 +169,8 @@ typedef struct {
   int32_t l1_dense;
   int32_t grid_mult;
   int32_t pass_pairs;
-  int32_t reserved[8];
+  int32_t expand_bits;
+  int32_t reserved[7];
 } lider_search_opts;
 
 /* Optional device outputs of the intermediate search state, for parity checks.

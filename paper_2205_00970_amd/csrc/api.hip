@@ -7,9 +7,6 @@
 
 namespace lider {
 
-int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const float* b,
-                const float* anorm, int32_t nh, double w, int32_t* out, int64_t* list,
-                int32_t* counter, int32_t* status, int clamp, float* rownorm, hipStream_t st);
 
 namespace {
 thread_local std::string g_err;
@@ -93,10 +90,15 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
   if (P->n_clusters < 1 || P->n_clusters > n)
     return set_error(LIDER_EINVAL, "n_clusters must be in 1..n");
   if (P->m < 1 || P->m > LIDER_MAX_M) return set_error(LIDER_EINVAL, "m must be in 1..16");
-  if (!(P->w > 0.0) || !std::isfinite(P->w)) return set_error(LIDER_EINVAL, "w must be > 0");
+  if (P->hash_kind != LIDER_HASH_E2LSH && P->hash_kind != LIDER_HASH_SIGN)
+    return set_error(LIDER_EINVAL, "hash_kind must be LIDER_HASH_E2LSH or LIDER_HASH_SIGN");
+  const bool sign = P->hash_kind == LIDER_HASH_SIGN;
+  if (!sign && (!(P->w > 0.0) || !std::isfinite(P->w)))
+    return set_error(LIDER_EINVAL, "w must be > 0");
   if (P->rmi_fanout < 1 || P->rmi_fanout_l1 < 0)
     return set_error(LIDER_EINVAL, "rmi_fanout must be >= 1");
-  if (!P->lsh_a_host || !P->lsh_b_host) return set_error(LIDER_EINVAL, "LSH parameters are NULL");
+  if (!P->lsh_a_host || (!sign && !P->lsh_b_host))
+    return set_error(LIDER_EINVAL, "LSH parameters are NULL");
   if (!P->assignment_dev && (!P->kmeans_init_host || P->kmeans_iters < 1))
     return set_error(LIDER_EINVAL, "k-means needs kmeans_init_host and kmeans_iters >= 1");
   if (P->storage != LIDER_F32 && P->storage != LIDER_BF16)
@@ -119,7 +121,8 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
   ix.m = P->m;
   ix.F2 = P->rmi_fanout;
   ix.F1 = P->rmi_fanout_l1 > 0 ? P->rmi_fanout_l1 : P->rmi_fanout;
-  ix.w = P->w;
+  ix.w = sign ? 1.0 : P->w;
+  ix.hash_kind = P->hash_kind;
   ix.storage = P->storage;
   ix.centroid_storage = P->centroid_storage;
   (void)hipGetDevice(&ix.device);
@@ -162,8 +165,12 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
   TRY(alloc(&ix.leaf_err, size_t(nleaf) * 2, "leaf errors"));
   TRY(check_hip(hipMemcpyAsync(ix.A, P->lsh_a_host, size_t(2 * m) * d * 4, hipMemcpyHostToDevice, st),
                 "copy LSH projections"));
-  TRY(check_hip(hipMemcpyAsync(ix.b, P->lsh_b_host, size_t(2 * m) * 4, hipMemcpyHostToDevice, st),
-                "copy LSH offsets"));
+  if (P->lsh_b_host)
+    TRY(check_hip(hipMemcpyAsync(ix.b, P->lsh_b_host, size_t(2 * m) * 4, hipMemcpyHostToDevice,
+                                 st),
+                  "copy LSH offsets"));
+  else
+    TRY(check_hip(hipMemsetAsync(ix.b, 0, size_t(2 * m) * 4, st), "clear LSH offsets"));
   if (rc == LIDER_OK) launch_norm_bounds(ix.A, int32_t(2 * m), d, ix.anorm, st);
   if (rc == LIDER_OK) {
     if (P->assignment_dev) {
@@ -249,6 +256,10 @@ static int validate_search(const lider_index* index, const float* Q, int64_t nq,
   if (o.l1_dense != 0 && o.l1_dense != -1) return set_error(LIDER_EINVAL, "l1_dense must be 0 or -1");
   if (o.pass_pairs != 0 && o.pass_pairs != 16 && o.pass_pairs != 32)
     return set_error(LIDER_EINVAL, "pass_pairs must be 0, 16 or 32");
+  if (o.expand_bits < 0 || o.expand_bits > 16)
+    return set_error(LIDER_EINVAL, "expand_bits must be in 0..16");
+  if (o.expand_bits > 0 && index->ix.hash_kind != LIDER_HASH_SIGN)
+    return set_error(LIDER_EINVAL, "expand_bits needs an index built with LIDER_HASH_SIGN");
   if (nq > 0 && !Q) return set_error(LIDER_EINVAL, "queries pointer is NULL");
   return LIDER_OK;
 }
@@ -428,7 +439,7 @@ int lider_hash(const float* X_dev, int64_t n, int32_t d, const float* A_dev, con
   if (rc == LIDER_OK) {
     launch_norm_bounds(A_dev, nh, d, anorm, st);
     rc = run_hash_ex(X_dev, n, d, A_dev, b_dev, anorm, nh, w, out_dev, list, cs, cs + 1, 0,
-                     nullptr, st);
+                     nullptr, st, LIDER_HASH_E2LSH);
   }
   int32_t h_status = 0;
   if (rc == LIDER_OK)

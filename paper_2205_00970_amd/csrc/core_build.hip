@@ -15,9 +15,6 @@
 
 namespace lider {
 
-int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const float* b,
-                const float* anorm, int32_t nh, double w, int32_t* out, int64_t* list,
-                int32_t* counter, int32_t* status, int clamp, float* rownorm, hipStream_t st);
 
 namespace {
 
@@ -272,9 +269,10 @@ struct Bufs {
 // Build one layer's core models over n items (digits per item id, model of
 // each item in seg, NULL = all in model 0).  Outputs: perm [n] (location ->
 // item id), keys [n], off [nseg + 1].
+// binary: bit hashkeys; every model's box is [0, 1] (key = Decimal(bits)).
 int build_layer(const int32_t* dig, int32_t m, const int32_t* seg, int64_t n, int32_t nseg,
                 int32_t F, Model* mb, int64_t leaf_base, double* leaves, int32_t* leaf_err,
-                int64_t* perm, uint64_t* keys, int64_t* off, hipStream_t st) {
+                int64_t* perm, uint64_t* keys, int64_t* off, bool binary, hipStream_t st) {
   Bufs B;
   int32_t* mins = B.get<int32_t>(size_t(nseg) * m);
   int32_t* maxs = B.get<int32_t>(size_t(nseg) * m);
@@ -291,10 +289,10 @@ int build_layer(const int32_t* dig, int32_t m, const int32_t* seg, int64_t n, in
   if (!mins || !maxs || !cnt || !K || !K1 || !io || !id1 || !segk || !seg2 || !idx2 || !x || !lf)
     return set_error(LIDER_ENOMEM, "out of device memory while building core models");
   const dim3 g(1024), blk(256);
-  hipLaunchKernelGGL(fill_i32, g, blk, 0, st, mins, int64_t(nseg) * m, INT32_MAX);
-  hipLaunchKernelGGL(fill_i32, g, blk, 0, st, maxs, int64_t(nseg) * m, INT32_MIN);
+  hipLaunchKernelGGL(fill_i32, g, blk, 0, st, mins, int64_t(nseg) * m, binary ? 0 : INT32_MAX);
+  hipLaunchKernelGGL(fill_i32, g, blk, 0, st, maxs, int64_t(nseg) * m, binary ? 1 : INT32_MIN);
   hipLaunchKernelGGL(fill_i32, g, blk, 0, st, cnt, int64_t(nseg), 0);
-  hipLaunchKernelGGL(box_kernel, g, blk, 0, st, dig, m, seg, n, mins, maxs);
+  if (!binary) hipLaunchKernelGGL(box_kernel, g, blk, 0, st, dig, m, seg, n, mins, maxs);
   hipLaunchKernelGGL(count_kernel, g, blk, 0, st, seg, n, cnt);
   hipLaunchKernelGGL(model_init_kernel, dim3((nseg + 255) / 256), blk, 0, st, mb, nseg, m, F,
                      leaf_base, mins, maxs, cnt);
@@ -398,11 +396,12 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
   int64_t* l1off = B.get<int64_t>(2);
   if (!list || !cs || !l1off) return set_error(LIDER_ENOMEM, "out of device memory (hash list)");
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, cs, int64_t(64), 0);
+  const bool binary = ix.hash_kind == LIDER_HASH_SIGN;
   int rc = run_hash_ex(Xin, n, d, ix.A + size_t(m) * d, ix.b + m, ix.anorm + m, m, ix.w,
-                       ix.digits, list, cs, cs + 1, 0, nullptr, st);
+                       ix.digits, list, cs, cs + 1, 0, nullptr, st, ix.hash_kind);
   if (rc != LIDER_OK) return rc;
   rc = build_layer(ix.digits, m, ix.assign, n, C, ix.F2, ix.models, 0, ix.leaves, ix.leaf_err,
-                   ix.perm, ix.keys, ix.off, st);
+                   ix.perm, ix.keys, ix.off, binary, st);
   if (rc != LIDER_OK) return rc;
   {
     const int64_t blocks = std::min<int64_t>((n + 3) / 4, 65536);
@@ -411,10 +410,10 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
   }
   // layer 1: the centroids retriever
   rc = run_hash_ex(ix.cent, C, d, ix.A, ix.b, ix.anorm, m, ix.w, ix.l1_digits, list, cs, cs + 1, 0,
-                   nullptr, st);
+                   nullptr, st, ix.hash_kind);
   if (rc != LIDER_OK) return rc;
   rc = build_layer(ix.l1_digits, m, nullptr, C, 1, ix.F1, ix.models + C, int64_t(C) * ix.F2,
-                   ix.leaves, ix.leaf_err, ix.l1_order, ix.l1_keys, l1off, st);
+                   ix.leaves, ix.leaf_err, ix.l1_order, ix.l1_keys, l1off, binary, st);
   if (rc != LIDER_OK) return rc;
   hipLaunchKernelGGL(reorder_kernel, dim3(unsigned((C + 3) / 4)), dim3(256), 0, st, ix.cent, d,
                      ix.l1_order, int64_t(C), ix.cent_l1, (__hip_bfloat16*)nullptr, ix.l1_order32);

@@ -1,5 +1,7 @@
 // E2LSH projection digits h_i(x) = floor((a_i . x + b_i) / w) (Section 4; the
-// integer-valued base hash under SK-LSH's element-wise order, Section 4.2).
+// integer-valued base hash under SK-LSH's element-wise order, Section 4.2), or
+// random-hyperplane bits h_i(x) = [a_i . x >= 0] (the cosine variant, Section
+// 4.1).
 //
 // The projection [rows x d] . [d x nh] runs on fp32 MFMA (v_mfma_f32_16x16x4f32,
 // one wave = 16 rows x 16 hashes).  The digit is an integer decided by a
@@ -24,7 +26,7 @@ __global__ __launch_bounds__(256) void hash_kernel(
     const float* __restrict__ X, int64_t n, int32_t d, const float* __restrict__ A,
     const float* __restrict__ bvec, const float* __restrict__ anorm, int32_t nh, double w,
     int32_t* __restrict__ out, int64_t* __restrict__ list, int32_t* __restrict__ counter,
-    int32_t* __restrict__ status, int clamp, float* __restrict__ rownorm) {
+    int32_t* __restrict__ status, int clamp, float* __restrict__ rownorm, int kind) {
   __shared__ float part[4][32][16];  // [wave][hash][row]
   __shared__ float pss[4][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -88,13 +90,23 @@ __global__ __launch_bounds__(256) void hash_kernel(
     const float sv = ((part[0][hash][ri] + part[1][hash][ri]) + part[2][hash][ri]) + part[3][hash][ri];
     const double xn = sqrt(double(ssr) * (1.0 + 2.0 * gam)) * (1.0 + 9.5367431640625e-07);
     if (rownorm && hash == 0) rownorm[row] = float(xn * (1.0 + 9.5367431640625e-07));
+    const int64_t oi = row * nh + hash;
+    if (kind == LIDER_HASH_SIGN) {  // bit = [a.x >= 0]: decided unless |a.x| is within the band
+      const double E = coef * double(anorm[hash]) * xn + double(d) * 7.888609052210118e-31;
+      if (!(fabs(double(sv)) > 2.0 * E)) {
+        const int32_t slot = atomicAdd(counter, 1);
+        list[slot] = oi;
+      } else {
+        out[oi] = sv > 0.f ? 1 : 0;
+      }
+      continue;
+    }
     const double tv = (double(sv) + double(bvec[hash])) / w;
     const double E = (coef * double(anorm[hash]) * xn + double(d) * 7.888609052210118e-31) / w +
                      8.881784197001252e-16 * fabs(tv);
     const double fl = floor(tv);
     const double fr = tv - fl;
     const double dist = fr < 1.0 - fr ? fr : 1.0 - fr;
-    const int64_t oi = row * nh + hash;
     if (!(dist > 2.0 * E)) {
       const int32_t slot = atomicAdd(counter, 1);
       list[slot] = oi;
@@ -127,7 +139,7 @@ __global__ __launch_bounds__(256) void hash_fixup_kernel(
     const float* __restrict__ X, int32_t d, const float* __restrict__ A,
     const float* __restrict__ bvec, int32_t nh, double w, int32_t* __restrict__ out,
     const int64_t* __restrict__ list, const int32_t* __restrict__ counter,
-    int32_t* __restrict__ status, int clamp) {
+    int32_t* __restrict__ status, int clamp, int kind) {
   __shared__ float sx[4][kFixupLds], sa[4][kFixupLds];
   __shared__ int s_seq[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -153,12 +165,15 @@ __global__ __launch_bounds__(256) void hash_fixup_kernel(
     ps = wave_sum_f64(ps);
     pa = wave_sum_f64(pa);
     const double u = 1.1102230246251565e-16;  // 2^-53
-    const double tp = (ps + double(bvec[hash])) / w;
-    const double fp = floor(tp);
-    const double fr = tp - fp;
-    const double dist = fr < 1.0 - fr ? fr : 1.0 - fr;
-    const double band = 8.0 * (double(d) * u * pa + u * (fabs(ps) + fabs(double(bvec[hash])))) / w +
-                        8.0 * u * fabs(tp);
+    const bool sign = kind == LIDER_HASH_SIGN;
+    const double bh = sign ? 0.0 : double(bvec[hash]);
+    const double tp = sign ? ps : (ps + bh) / w;
+    const double fp = sign ? (ps >= 0.0 ? 1.0 : 0.0) : floor(tp);
+    const double fr = tp - floor(tp);
+    const double dist = sign ? fabs(ps) : (fr < 1.0 - fr ? fr : 1.0 - fr);
+    const double band = sign ? 8.0 * double(d) * u * pa
+                             : 8.0 * (double(d) * u * pa + u * (fabs(ps) + fabs(bh))) / w +
+                                   8.0 * u * fabs(tp);
     if (lane == 0) s_seq[wave] = !(dist > band);
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
@@ -170,7 +185,7 @@ __global__ __launch_bounds__(256) void hash_fixup_kernel(
           for (int l = 0; l < d; ++l) sacc = sacc + double(sa[wave][l]) * double(sx[wave][l]);
         else
           for (int l = 0; l < d; ++l) sacc = sacc + double(ar[l]) * double(xr[l]);
-        fl = floor((sacc + double(bvec[hash])) / w);
+        fl = sign ? (sacc >= 0.0 ? 1.0 : 0.0) : floor((sacc + bh) / w);
       }
       if (fl >= -2147483648.0 && fl <= 2147483647.0) {
         out[o] = int32_t(fl);
@@ -212,7 +227,8 @@ size_t hash_list_capacity(int64_t n, int32_t nh) { return size_t(n) * size_t(nh)
 // receives an upper bound of each row's norm.
 int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const float* b,
                 const float* anorm, int32_t nh, double w, int32_t* out, int64_t* list,
-                int32_t* counter, int32_t* status, int clamp, float* rownorm, hipStream_t st) {
+                int32_t* counter, int32_t* status, int clamp, float* rownorm, hipStream_t st,
+                int kind) {
   if (n <= 0) return LIDER_OK;
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, counter, int64_t(1));
   const bool vec = (d % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
@@ -220,15 +236,15 @@ int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const floa
   const dim3 grid(unsigned((n + 15) / 16));
   if (vec)
     hipLaunchKernelGGL(hash_kernel<true>, grid, dim3(256), 0, st, X, n, d, A, b, anorm, nh, w,
-                       out, list, counter, status, clamp, rownorm);
+                       out, list, counter, status, clamp, rownorm, kind);
   else
     hipLaunchKernelGGL(hash_kernel<false>, grid, dim3(256), 0, st, X, n, d, A, b, anorm, nh, w,
-                       out, list, counter, status, clamp, rownorm);
+                       out, list, counter, status, clamp, rownorm, kind);
   int64_t cap = n * nh;
   int64_t blocks = (cap + 3) / 4;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(hash_fixup_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, X, d, A, b, nh,
-                     w, out, list, counter, status, clamp);
+                     w, out, list, counter, status, clamp, kind);
   return check_hip(hipGetLastError(), "hash kernels");
 }
 

@@ -109,13 +109,61 @@ __host__ __device__ inline void window_of(int64_t pos, int64_t r, int64_t L, int
   *len = lenv;
 }
 
-__device__ inline int64_t locate(const Model& M, const double* leaves, const int32_t* qd) {
+__device__ inline int64_t locate(const Model& M, const double* leaves, const int32_t* qd,
+                                 uint64_t* Kout = nullptr) {
   if (M.L <= 0) return 0;
   uint64_t K = encode_query(qd, M);
+  if (Kout) *Kout = K;
   double x = rescale(K, M);
   int32_t j = leaf_of(M.root_a, M.root_b, M.F, M.L, x);
   const double* lf = leaves + 2 * (M.leaf_off + j);
   return pos_of(lf[0], lf[1], M.L, x);
+}
+
+// Extended hashkey distance of two m-bit hashkeys (Section 4.2), scaled by
+// C = 2^B to an exact integer: KL * 2^B + KD_e, with KL the non-prefix length
+// and KD_e the absolute difference of the (at most) B bits right after the
+// common prefix read as binary numbers.
+__host__ __device__ inline int64_t dist_e_scaled(uint64_t a, uint64_t b, int m, int B) {
+  const uint64_t x = a ^ b;
+  if (x == 0) return 0;
+  int p = 63;  // most significant differing bit (bit 0 = least significant)
+  while (!((x >> p) & 1u)) --p;
+  const int nb = B < p + 1 ? B : p + 1;
+  const uint64_t mask = (uint64_t(1) << nb) - 1;
+  const int64_t v1 = int64_t((a >> (p + 1 - nb)) & mask), v2 = int64_t((b >> (p + 1 - nb)) & mask);
+  const int64_t kl = p + 1;  // non-prefix length: m minus the common prefix m - 1 - p
+  (void)m;
+  return kl * (int64_t(1) << B) + (v1 > v2 ? v1 - v2 : v2 - v1);
+}
+
+// dist_e-guided bi-directional expansion over a sorted key array (Sections
+// 3.3.1, 4.2): the predicted location first, then one position at a time on
+// the side whose next key is closer to Kq (ties to the left) until min(r, L)
+// positions are taken; the range stays contiguous.
+__device__ inline void window_expand(const uint64_t* __restrict__ keys, int64_t L, int64_t pos,
+                                     int64_t r, uint64_t Kq, int m, int B, int64_t* start,
+                                     int64_t* len) {
+  const int64_t take = r < L ? r : L;
+  if (take <= 0) {
+    *start = 0;
+    *len = 0;
+    return;
+  }
+  int64_t lo = pos - 1, hi = pos + 1;
+  int64_t dl = lo >= 0 ? dist_e_scaled(keys[lo], Kq, m, B) : 0;
+  int64_t dh = hi < L ? dist_e_scaled(keys[hi], Kq, m, B) : 0;
+  for (int64_t got = 1; got < take; ++got) {
+    if (lo >= 0 && (hi >= L || dl <= dh)) {
+      --lo;
+      if (lo >= 0) dl = dist_e_scaled(keys[lo], Kq, m, B);
+    } else {
+      ++hi;
+      if (hi < L) dh = dist_e_scaled(keys[hi], Kq, m, B);
+    }
+  }
+  *start = lo + 1;
+  *len = take;
 }
 
 // Rigorous bound on |fl32(a.b) - a.b| for a length-d fp32 dot product summed in
@@ -133,6 +181,7 @@ struct Index {
   int32_t iters_run = 0;
   int64_t max_cluster = 0;
   int32_t storage = LIDER_F32, centroid_storage = LIDER_F32;
+  int32_t hash_kind = LIDER_HASH_E2LSH;
   int32_t n_cu = 256;
 
   float* X = nullptr;          // [n x d] reordered by (cluster, key, id)
@@ -176,7 +225,8 @@ int check_hip(hipError_t e, const char* what);
 // hash.hip
 int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const float* b,
                 const float* anorm, int32_t nh, double w, int32_t* out, int64_t* list,
-                int32_t* counter, int32_t* status, int clamp, float* rownorm, hipStream_t st);
+                int32_t* counter, int32_t* status, int clamp, float* rownorm, hipStream_t st,
+                int kind = 0);
 size_t hash_list_capacity(int64_t n, int32_t nh);
 void launch_norm_bounds(const float* A, int32_t rows, int32_t d, float* out, hipStream_t st);
 

@@ -25,9 +25,6 @@
 
 namespace lider {
 
-int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const float* b,
-                const float* anorm, int32_t nh, double w, int32_t* out, int64_t* list,
-                int32_t* counter, int32_t* status, int clamp, float* rownorm, hipStream_t st);
 
 namespace {
 
@@ -291,19 +288,26 @@ __host__ __device__ inline int pow2_at_least(int v) {
 // Centroids retriever: location and window of every query; the window is also
 // written as a (cluster 0, start, length) pair so the tile-scoring kernel can
 // score layer 1 exactly like a cluster of C rows.
+// expand_bits > 0: the window is the dist_e-guided expansion over the sorted
+// key array (keys), else the fixed window around the predicted location.
 __global__ void l1_kernel(const Model* __restrict__ models, const double* __restrict__ leaves,
                           const int32_t* __restrict__ qdig, int32_t m, int64_t nq, int32_t C,
                           int32_t r1, int32_t* __restrict__ l1, Pair* __restrict__ l1pairs,
-                          int32_t* __restrict__ l1cs) {
+                          int32_t* __restrict__ l1cs, const uint64_t* __restrict__ keys,
+                          int32_t expand_bits) {
   const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q == 0) {
     l1cs[0] = 0;
     l1cs[1] = int32_t(nq);
   }
   if (q >= nq) return;
-  const int64_t pos = locate(models[C], leaves, qdig + q * 2 * m);
+  uint64_t K = 0;
+  const int64_t pos = locate(models[C], leaves, qdig + q * 2 * m, &K);
   int64_t s, len;
-  window_of(pos, r1, C, &s, &len);
+  if (expand_bits > 0)
+    window_expand(keys, C, pos, r1, K, m, expand_bits, &s, &len);
+  else
+    window_of(pos, r1, C, &s, &len);
   l1[3 * q] = int32_t(pos);
   l1[3 * q + 1] = int32_t(s);
   l1[3 * q + 2] = int32_t(len);
@@ -473,7 +477,8 @@ __global__ __launch_bounds__(kRouteNT) void route_select_block_kernel(
 __global__ void pairs_kernel(const Model* __restrict__ models, const double* __restrict__ leaves,
                              const int32_t* __restrict__ qdig, int32_t m, int64_t np, int32_t c,
                              int32_t r, const int32_t* __restrict__ routed, Pair* __restrict__ pairs,
-                             int32_t* __restrict__ ccount) {
+                             int32_t* __restrict__ ccount, const uint64_t* __restrict__ keys,
+                             const int64_t* __restrict__ off, int32_t expand_bits) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= np) return;
   const int64_t q = t / c;
@@ -481,9 +486,13 @@ __global__ void pairs_kernel(const Model* __restrict__ models, const double* __r
   Pair pr{-1, 0, 0, 0};
   if (j >= 0) {
     const Model& M = models[j];
-    const int64_t pos = locate(M, leaves, qdig + q * 2 * m + m);
+    uint64_t K = 0;
+    const int64_t pos = locate(M, leaves, qdig + q * 2 * m + m, &K);
     int64_t s, len;
-    window_of(pos, r, M.L, &s, &len);
+    if (expand_bits > 0)
+      window_expand(keys + off[j], M.L, pos, r, K, m, expand_bits, &s, &len);
+    else
+      window_of(pos, r, M.L, &s, &len);
     pr = Pair{j, int32_t(s), int32_t(len), int32_t(pos)};
     if (len > 0) atomicAdd(&ccount[j], 1);
   }
@@ -1681,11 +1690,12 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   hipLaunchKernelGGL(zero_kernel, dim3((C + 255) / 256), dim3(256), 0, st, ccount, int64_t(C));
   hipLaunchKernelGGL(zero_kernel, dim3((C + 255) / 256), dim3(256), 0, st, cfill, int64_t(C));
   int rc = run_hash_ex(Q, nq, ix.d, ix.A, ix.b, ix.anorm, 2 * m, ix.w, qdig, hlist, ctr, ctr + 1,
-                       1, qnorm, st);
+                       1, qnorm, st, ix.hash_kind);
   if (rc != LIDER_OK) return rc;
   mark(1);
   hipLaunchKernelGGL(l1_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, st, ix.models,
-                     ix.leaves, qdig, m, nq, C, p.r1, l1, l1pairs, l1cs);
+                     ix.leaves, qdig, m, nq, C, p.r1, l1, l1pairs, l1cs, ix.l1_keys,
+                     o.expand_bits);
   const bool fp8 = bf16 && ix.cent8;
   if (fp8 || bf16)
     hipLaunchKernelGGL(to_bf16_kernel, dim3(2048), dim3(256), 0, st, Q, nq * ix.d, qb);
@@ -1716,7 +1726,8 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   }
   mark(2);
   hipLaunchKernelGGL(pairs_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, ix.models,
-                     ix.leaves, qdig, m, np, c, r, routed, pairs, ccount);
+                     ix.leaves, qdig, m, np, c, r, routed, pairs, ccount, ix.keys, ix.off,
+                     o.expand_bits);
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, ccount, C, cstart);
   hipLaunchKernelGGL(scatter_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, pairs, np,
                      cstart, cfill, wl);

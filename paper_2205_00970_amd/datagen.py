@@ -96,6 +96,16 @@ def queries_from(X, nq, noise, seed=1):
     return Q.contiguous(), src
 
 
+def normalize_rows(X):
+    """Rows scaled to unit L2 norm (embeddings for the cosine variant); works on
+    numpy arrays and torch tensors."""
+    if isinstance(X, np.ndarray):
+        nrm = np.linalg.norm(X.astype(np.float64), axis=1, keepdims=True)
+        return (X / np.maximum(nrm, 1e-30)).astype(np.float32)
+    nrm = X.double().norm(dim=1, keepdim=True).clamp_min(1e-30)
+    return (X.double() / nrm).float()
+
+
 def zipf_sizes(n, ncomp, s=1.1, lo=50, hi=200000):
     """Component sizes proportional to i^-s, clipped to [lo, hi] and
     water-filled to sum exactly n (remainder to the largest unclipped)."""

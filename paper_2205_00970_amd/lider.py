@@ -40,13 +40,14 @@ class BuildParams(C.Structure):
                 ("lsh_b_host", C.c_void_p), ("assignment_dev", C.c_void_p),
                 ("kmeans_init_host", C.c_void_p), ("kmeans_iters", C.c_int32),
                 ("storage", C.c_int32), ("centroid_storage", C.c_int32),
-                ("kmeans_seeding", C.c_int32)]
+                ("kmeans_seeding", C.c_int32), ("hash_kind", C.c_int32)]
 
 
 class SearchOpts(C.Structure):
     _fields_ = [("r1", C.c_int32), ("precision", C.c_int32), ("shortlist_mult", C.c_int32),
                 ("persistent", C.c_int32), ("tile_rows", C.c_int32), ("l1_dense", C.c_int32),
-                ("grid_mult", C.c_int32), ("pass_pairs", C.c_int32), ("reserved", C.c_int32 * 8)]
+                ("grid_mult", C.c_int32), ("pass_pairs", C.c_int32), ("expand_bits", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
 
 
 class SearchDebug(C.Structure):
@@ -145,12 +146,15 @@ class Index:
 
     def __init__(self, corpus, n_clusters, m, w, rmi_fanout, lsh, rmi_fanout_l1=0,
                  kmeans_init=None, kmeans_iters=20, assignment=None, storage="f32",
-                 centroid_storage="f32", seeding="given", stream=None):
+                 centroid_storage="f32", seeding="given", hash_kind="e2lsh", stream=None):
+        """hash_kind "e2lsh": integer digits floor((a.x + b) / w); "sign": the
+        cosine variant (bits [a.x >= 0], key = Decimal(bits); w and b unused)."""
         torch = _torch()
         cp = _dev_ptr(corpus, torch.float32, 2, "corpus")
         n, d = corpus.shape
+        kind = {"e2lsh": 0, "sign": 1}[hash_kind]
         A = np.ascontiguousarray(lsh[0], dtype=np.float32)
-        b = np.ascontiguousarray(lsh[1], dtype=np.float32)
+        b = np.ascontiguousarray(lsh[1] if lsh[1] is not None else np.zeros(2 * m), dtype=np.float32)
         if A.shape != (2 * m, d) or b.shape != (2 * m,):
             raise ValueError("lsh must be (A [2m, d], b [2m])")
         ini = None if kmeans_init is None else np.ascontiguousarray(kmeans_init, dtype=np.int64)
@@ -162,7 +166,7 @@ class Index:
                         None if assignment is None else _dev_ptr(assignment, torch.int32, 1,
                                                                  "assignment"),
                         _np_ptr(ini), int(kmeans_iters), _STORAGE[storage],
-                        _CSTORAGE[centroid_storage], seed_mode)
+                        _CSTORAGE[centroid_storage], seed_mode, kind)
         h = C.c_void_p()
         _check(lib().lider_build(cp, n, d, C.byref(P), _stream(stream), C.byref(h)))
         self._h = h
@@ -173,6 +177,7 @@ class Index:
         self.F2, self.F1 = info.rmi_fanout, info.rmi_fanout_l1
         self.max_cluster = info.max_cluster
         self.iters_run = info.kmeans_iters_run
+        self.hash_kind = hash_kind
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -204,23 +209,24 @@ class Index:
 
     @staticmethod
     def _opts(r1=0, precision="f32", shortlist_mult=0, persistent=False, tile_rows=0,
-              grid_mult=0, l1_dense=True, pass_pairs=0):
+              grid_mult=0, l1_dense=True, pass_pairs=0, expand_bits=0):
         o = SearchOpts()
         o.r1, o.precision, o.shortlist_mult = int(r1), _PREC[precision], int(shortlist_mult)
         o.persistent, o.tile_rows, o.grid_mult = int(persistent), int(tile_rows), int(grid_mult)
         o.l1_dense = 0 if l1_dense else -1
         o.pass_pairs = int(pass_pairs)
+        o.expand_bits = int(expand_bits)
         return o
 
     def search(self, queries, k, c, r, r1=0, precision="f32", shortlist_mult=0,
                persistent=False, tile_rows=0, grid_mult=0, debug=False, stream=None, ws=None,
-               out=None, l1_dense=True, pass_pairs=0):
+               out=None, l1_dense=True, pass_pairs=0, expand_bits=0):
         """Batched search; returns (ids int64 [nq,k], scores f32 [nq,k][, debug])."""
         torch = _torch()
         qp = _dev_ptr(queries, torch.float32, 2, "queries")
         nq = queries.shape[0]
         o = self._opts(r1, precision, shortlist_mult, persistent, tile_rows, grid_mult, l1_dense,
-                       pass_pairs)
+                       pass_pairs, expand_bits)
         need = int(lib().lider_search_workspace(self._h, nq, k, c, r, C.byref(o)))
         if need == 0 and nq > 0:
             # invalid arguments: let lider_search_ex report which
