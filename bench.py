@@ -262,6 +262,7 @@ def main():
         log(f"precision form: {args.nq / dt:,.0f} q/s, recall@10 "
             f"{extra['precision_bf16']['recall10']}")
         extra["persistent_qps"] = round(args.nq / timed(10, c, r, r1, reps=5, persistent=True)[0])
+        extra["cosine"] = cosine_variant(args, torch, datagen, lider, X, lab, Q, C, F, log)
 
     cpu = None
     if not args.quick and not args.no_cpu_baseline:
@@ -351,6 +352,41 @@ def run_batching(args, torch, datagen, lider):
             res[f"{prec}_r1_{r1}_recall10"] = round(rec, 4)
     res["schedules"] = tuner.cache
     print(json.dumps(res), flush=True)
+
+
+def cosine_variant(args, torch, datagen, lider, X, lab, Q, C, F, log):
+    """The cosine variant on the same mixture, rows and queries normalised:
+    random-hyperplane bits (m = 10 = ceil(log2 of the ~1,000-row clusters)),
+    key = Decimal(bits), clusters = the generator's labels.  Recall@10 and q/s
+    at the literal point (c=8, r=r1=256) with the fixed window and with the
+    dist_e-guided expansion (B = 3), and at whole-cluster windows."""
+    Xn = datagen.normalize_rows(X)
+    Qn = datagen.normalize_rows(Q)
+    m = 10
+    A, _ = datagen.lsh_params(m, X.shape[1], 1.0, seed=12)
+    gi = lider.Index(Xn, C, m, 1.0, F, (A, None), assignment=lab.to(torch.int32),
+                     hash_kind="sign")
+    _, gt_sc = exact_topk(torch, Xn, Qn, 10)
+    out = {"m": m}
+    for name, (c, r, r1, B) in {"literal_fixed": (8, 256, 256, 0),
+                                "literal_expand_B3": (8, 256, 256, 3),
+                                "whole_cluster": (1, int(gi.max_cluster), C, 0)}.items():
+        ids = torch.empty((Qn.shape[0], 10), dtype=torch.int64, device=Qn.device)
+        sc = torch.empty((Qn.shape[0], 10), dtype=torch.float32, device=Qn.device)
+        gi.search(Qn, 10, c, r, r1=r1, expand_bits=B, out=(ids, sc))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            gi.search(Qn, 10, c, r, r1=r1, expand_bits=B, out=(ids, sc))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / 5
+        rec = recall_at(torch, Xn, Qn, ids, gt_sc, 10)
+        out[name] = dict(c=c, r=r, r1=r1, expand_bits=B, qps=round(Qn.shape[0] / dt),
+                         recall10=round(rec, 4))
+        log(f"cosine {name}: {Qn.shape[0] / dt:,.0f} q/s, recall@10 {rec:.4f}")
+    del gi, Xn
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(X, lab, Q, A, b, C, m, w, F, c, r, r1, seconds):

@@ -137,35 +137,6 @@ __host__ __device__ inline int64_t dist_e_scaled(uint64_t a, uint64_t b, int m, 
   return kl * (int64_t(1) << B) + (v1 > v2 ? v1 - v2 : v2 - v1);
 }
 
-// dist_e-guided bi-directional expansion over a sorted key array (Sections
-// 3.3.1, 4.2): the predicted location first, then one position at a time on
-// the side whose next key is closer to Kq (ties to the left) until min(r, L)
-// positions are taken; the range stays contiguous.
-__device__ inline void window_expand(const uint64_t* __restrict__ keys, int64_t L, int64_t pos,
-                                     int64_t r, uint64_t Kq, int m, int B, int64_t* start,
-                                     int64_t* len) {
-  const int64_t take = r < L ? r : L;
-  if (take <= 0) {
-    *start = 0;
-    *len = 0;
-    return;
-  }
-  int64_t lo = pos - 1, hi = pos + 1;
-  int64_t dl = lo >= 0 ? dist_e_scaled(keys[lo], Kq, m, B) : 0;
-  int64_t dh = hi < L ? dist_e_scaled(keys[hi], Kq, m, B) : 0;
-  for (int64_t got = 1; got < take; ++got) {
-    if (lo >= 0 && (hi >= L || dl <= dh)) {
-      --lo;
-      if (lo >= 0) dl = dist_e_scaled(keys[lo], Kq, m, B);
-    } else {
-      ++hi;
-      if (hi < L) dh = dist_e_scaled(keys[hi], Kq, m, B);
-    }
-  }
-  *start = lo + 1;
-  *len = take;
-}
-
 // Rigorous bound on |fl32(a.b) - a.b| for a length-d fp32 dot product summed in
 // any order (plus the FP64 reference's own rounding), per unit of |a||b|.
 __host__ __device__ inline double dot_err_coef(int d) {

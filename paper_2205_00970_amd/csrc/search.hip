@@ -41,7 +41,7 @@ constexpr int kCtrWords = 64;
 
 struct Plan {
   size_t o_ctr, o_qdig, o_hlist, o_qnorm, o_l1, o_l1p, o_l1cs, o_rs, o_rs64, o_routed, o_pairs,
-      o_ccount, o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, o_aflag, o_alist, total;
+      o_ccount, o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, o_aflag, o_alist, o_kq, total;
   int32_t r1, rcap, S;
 };
 
@@ -89,6 +89,7 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   const size_t nt = o.persistent == 2 ? size_t(ix.n_tiles[ti]) : 0;
   p.o_aflag = take(nt * 4);
   p.o_alist = take(nt * 4);
+  p.o_kq = take(o.expand_bits > 0 ? size_t(nq) * std::max<int32_t>(c, 1) * 8 : 0);
   p.total = off;
   p.r1 = r1;
   p.rcap = rcap;
@@ -288,13 +289,11 @@ __host__ __device__ inline int pow2_at_least(int v) {
 // Centroids retriever: location and window of every query; the window is also
 // written as a (cluster 0, start, length) pair so the tile-scoring kernel can
 // score layer 1 exactly like a cluster of C rows.
-// expand_bits > 0: the window is the dist_e-guided expansion over the sorted
-// key array (keys), else the fixed window around the predicted location.
+// kq (nullable) receives each query's layer-1 key for the dist_e expansion.
 __global__ void l1_kernel(const Model* __restrict__ models, const double* __restrict__ leaves,
                           const int32_t* __restrict__ qdig, int32_t m, int64_t nq, int32_t C,
                           int32_t r1, int32_t* __restrict__ l1, Pair* __restrict__ l1pairs,
-                          int32_t* __restrict__ l1cs, const uint64_t* __restrict__ keys,
-                          int32_t expand_bits) {
+                          int32_t* __restrict__ l1cs, uint64_t* __restrict__ kq) {
   const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q == 0) {
     l1cs[0] = 0;
@@ -304,10 +303,8 @@ __global__ void l1_kernel(const Model* __restrict__ models, const double* __rest
   uint64_t K = 0;
   const int64_t pos = locate(models[C], leaves, qdig + q * 2 * m, &K);
   int64_t s, len;
-  if (expand_bits > 0)
-    window_expand(keys, C, pos, r1, K, m, expand_bits, &s, &len);
-  else
-    window_of(pos, r1, C, &s, &len);
+  window_of(pos, r1, C, &s, &len);  // the expansion (if any) replaces s later
+  if (kq) kq[q] = K;
   l1[3 * q] = int32_t(pos);
   l1[3 * q + 1] = int32_t(s);
   l1[3 * q + 2] = int32_t(len);
@@ -477,8 +474,7 @@ __global__ __launch_bounds__(kRouteNT) void route_select_block_kernel(
 __global__ void pairs_kernel(const Model* __restrict__ models, const double* __restrict__ leaves,
                              const int32_t* __restrict__ qdig, int32_t m, int64_t np, int32_t c,
                              int32_t r, const int32_t* __restrict__ routed, Pair* __restrict__ pairs,
-                             int32_t* __restrict__ ccount, const uint64_t* __restrict__ keys,
-                             const int64_t* __restrict__ off, int32_t expand_bits) {
+                             int32_t* __restrict__ ccount, uint64_t* __restrict__ kq) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= np) return;
   const int64_t q = t / c;
@@ -489,14 +485,83 @@ __global__ void pairs_kernel(const Model* __restrict__ models, const double* __r
     uint64_t K = 0;
     const int64_t pos = locate(M, leaves, qdig + q * 2 * m + m, &K);
     int64_t s, len;
-    if (expand_bits > 0)
-      window_expand(keys + off[j], M.L, pos, r, K, m, expand_bits, &s, &len);
-    else
-      window_of(pos, r, M.L, &s, &len);
+    window_of(pos, r, M.L, &s, &len);  // the expansion (if any) replaces s later
+    if (kq) kq[t] = K;
     pr = Pair{j, int32_t(s), int32_t(len), int32_t(pos)};
     if (len > 0) atomicAdd(&ccount[j], 1);
   }
   pairs[t] = pr;
+}
+
+// dist_e-guided bi-directional expansion (Sections 3.3.1, 4.2), one wave per
+// item (a query's layer-1 window, or a (query, cluster) pair).  From the
+// predicted location the range grows one position at a time on the side whose
+// next hashkey is closer to the query's in dist_e (ties to the left, the other
+// side once one is exhausted) until min(r, L) positions are taken.  The wave
+// scores the next 64 candidates of a side at once into LDS; lane 0 runs the
+// sequential two-pointer decisions over them and the exhausted side is
+// refilled.  Only the window start changes (the length is min(r, L)).
+// layer 1: items are queries, the array is the centroids retriever's keys
+// (L = C) and the l1 rows are updated too; else items are pairs and the array
+// of cluster j is keys + off[j].
+constexpr int64_t kNoDist = INT64_MAX;
+
+__global__ __launch_bounds__(256) void expand_kernel(const uint64_t* __restrict__ keys,
+                                                     const int64_t* __restrict__ off, int64_t L1,
+                                                     Pair* __restrict__ items, int64_t nitems,
+                                                     const uint64_t* __restrict__ kq, int32_t r,
+                                                     int32_t m, int32_t B,
+                                                     int32_t* __restrict__ l1) {
+  __shared__ int64_t dl[4][64], dr[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t t = int64_t(blockIdx.x) * 4 + wave;
+  if (t >= nitems) return;
+  const Pair pr = items[t];
+  if (pr.j < 0 || pr.len <= 0) return;
+  const uint64_t* ka = off ? keys + off[pr.j] : keys;
+  const int64_t L = off ? off[pr.j + 1] - off[pr.j] : L1;
+  const int64_t take = pr.len;  // = min(r, L)
+  const uint64_t Kq = kq[t];
+  int64_t lo = pr.pos - 1, hi = pr.pos + 1, got = 1;
+  int il = 64, ir = 64;
+  while (got < take) {
+    if (il == 64) {
+      const int64_t p = lo - lane;
+      dl[wave][lane] = p >= 0 ? dist_e_scaled(ka[p], Kq, m, B) : kNoDist;
+      il = 0;
+    }
+    if (ir == 64) {
+      const int64_t p = hi + lane;
+      dr[wave][lane] = p < L ? dist_e_scaled(ka[p], Kq, m, B) : kNoDist;
+      ir = 0;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+      while (got < take && il < 64 && ir < 64) {
+        const int64_t a = dl[wave][il], b = dr[wave][ir];
+        if (a != kNoDist && (b == kNoDist || a <= b)) {
+          ++il;
+          --lo;
+        } else {
+          ++ir;
+          ++hi;
+        }
+        ++got;
+      }
+    }
+    lo = __shfl(lo, 0);
+    hi = __shfl(hi, 0);
+    got = __shfl(got, 0);
+    il = __shfl(il, 0);
+    ir = __shfl(ir, 0);
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (lane == 0) {
+    items[t].s = int32_t(lo + 1);
+    if (l1) l1[3 * t + 1] = int32_t(lo + 1);
+  }
 }
 
 // Exclusive scan of per-cluster pair counts (single workgroup).
@@ -1678,6 +1743,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   int32_t* slist = reinterpret_cast<int32_t*>(W + p.o_slist);
   int32_t* aflag = reinterpret_cast<int32_t*>(W + p.o_aflag);
   int32_t* alist = reinterpret_cast<int32_t*>(W + p.o_alist);
+  uint64_t* kq = reinterpret_cast<uint64_t*>(W + p.o_kq);
   const int32_t m = ix.m, C = ix.C;
   const int64_t np = nq * c;
   const bool bf16 = o.precision == LIDER_BF16;
@@ -1694,8 +1760,12 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   if (rc != LIDER_OK) return rc;
   mark(1);
   hipLaunchKernelGGL(l1_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, st, ix.models,
-                     ix.leaves, qdig, m, nq, C, p.r1, l1, l1pairs, l1cs, ix.l1_keys,
-                     o.expand_bits);
+                     ix.leaves, qdig, m, nq, C, p.r1, l1, l1pairs, l1cs,
+                     o.expand_bits > 0 ? kq : (uint64_t*)nullptr);
+  if (o.expand_bits > 0)
+    hipLaunchKernelGGL(expand_kernel, dim3(unsigned((nq + 3) / 4)), dim3(256), 0, st, ix.l1_keys,
+                       (const int64_t*)nullptr, int64_t(C), l1pairs, nq, kq, p.r1, m,
+                       o.expand_bits, l1);
   const bool fp8 = bf16 && ix.cent8;
   if (fp8 || bf16)
     hipLaunchKernelGGL(to_bf16_kernel, dim3(2048), dim3(256), 0, st, Q, nq * ix.d, qb);
@@ -1726,8 +1796,11 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   }
   mark(2);
   hipLaunchKernelGGL(pairs_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, ix.models,
-                     ix.leaves, qdig, m, np, c, r, routed, pairs, ccount, ix.keys, ix.off,
-                     o.expand_bits);
+                     ix.leaves, qdig, m, np, c, r, routed, pairs, ccount,
+                     o.expand_bits > 0 ? kq : (uint64_t*)nullptr);
+  if (o.expand_bits > 0)
+    hipLaunchKernelGGL(expand_kernel, dim3(unsigned((np + 3) / 4)), dim3(256), 0, st, ix.keys,
+                       ix.off, int64_t(0), pairs, np, kq, r, m, o.expand_bits, (int32_t*)nullptr);
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, ccount, C, cstart);
   hipLaunchKernelGGL(scatter_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, pairs, np,
                      cstart, cfill, wl);
