@@ -146,9 +146,14 @@ const char* lider_last_error(void);
  *                 sparse batches on large indexes).  Results are identical.
  *  tile_rows      rows per rerank tile (one wave per tile): 32, 64, 128, or 0
  *                 (128 when clusters average at least 512 rows, else 64).
- *  l1_dense       0: when r1 covers every centroid, the layer-1 scores are one
- *                 dense query x centroid product on MFMA (default); -1: always
- *                 the window kernel.  Results are identical.
+ *  l1_dense       0 (default): when r1 covers every centroid, the layer-1
+ *                 scores are one dense query x centroid product on MFMA; with
+ *                 precision LIDER_F32 and c < 64 it runs in bf16 and only the
+ *                 centroids whose bf16 score is within twice its rigorous error
+ *                 bound of the c-th best are rescored in sequential FP64 to
+ *                 decide the routed set.  1: the dense product in fp32 (no
+ *                 bf16 candidates).  -1: always the window kernel.  The routed
+ *                 sets, and so all results, are identical.
  *  grid_mult      persistent grid = grid_mult * number of CUs (0 = 4).
  *  expand_bits    0: fixed window of r (r1) positions, floor(r/2) left of the
  *                 predicted location (shifted inward at the ends).  B in 1..16:

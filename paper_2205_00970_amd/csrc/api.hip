@@ -38,7 +38,7 @@ int alloc(T** p, size_t count, const char* what) {
 void free_device(Index& ix) {
   void* ptrs[] = {ix.X,      ix.Xb,          ix.perm,     ix.perm32,    ix.keys,
                   ix.digits, ix.assign,      ix.off,      ix.cent,      ix.cent_l1,
-                  ix.cent8,  ix.cent8_scale, ix.l1_order, ix.l1_order32, ix.l1_keys,
+                  ix.cent8,  ix.cent8_scale, ix.cent_l1_b, ix.l1_order, ix.l1_order32, ix.l1_keys,
                   ix.l1_digits, ix.A,        ix.b,        ix.anorm,     ix.cent_norm_max,
                   ix.models, ix.leaves,      ix.leaf_err, ix.tiles[0],  ix.tiles[1],
                   ix.tiles[2], ix.l1_tiles,  ix.tile_base[0], ix.tile_base[1],
@@ -152,6 +152,7 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
     TRY(alloc(&ix.cent8, size_t(C) * d, "fp8 centroids"));
     TRY(alloc(&ix.cent8_scale, size_t(C), "fp8 scales"));
   }
+  if (d % 8 == 0) TRY(alloc(&ix.cent_l1_b, size_t(C) * d, "bf16 layer-1 centroids"));
   TRY(alloc(&ix.l1_order, size_t(C), "layer-1 order"));
   TRY(alloc(&ix.l1_order32, size_t(C), "layer-1 order"));
   TRY(alloc(&ix.l1_keys, size_t(C), "layer-1 keys"));
@@ -253,7 +254,7 @@ static int validate_search(const lider_index* index, const float* Q, int64_t nq,
     return set_error(LIDER_EINVAL, "tile_rows must be 0, 32, 64 or 128");
   if (o.grid_mult < 0 || o.grid_mult > 64) return set_error(LIDER_EINVAL, "grid_mult out of range");
   if (o.persistent < 0 || o.persistent > 2) return set_error(LIDER_EINVAL, "persistent must be 0, 1 or 2");
-  if (o.l1_dense != 0 && o.l1_dense != -1) return set_error(LIDER_EINVAL, "l1_dense must be 0 or -1");
+  if (o.l1_dense < -1 || o.l1_dense > 1) return set_error(LIDER_EINVAL, "l1_dense must be -1, 0 or 1");
   if (o.pass_pairs != 0 && o.pass_pairs != 16 && o.pass_pairs != 32)
     return set_error(LIDER_EINVAL, "pass_pairs must be 0, 16 or 32");
   if (o.expand_bits < 0 || o.expand_bits > 16)

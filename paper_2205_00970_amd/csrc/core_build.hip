@@ -350,6 +350,13 @@ __global__ void reorder_kernel(const float* __restrict__ X, int32_t d,
   }
 }
 
+__global__ void bf16_copy_kernel(const float* __restrict__ a, int64_t cnt,
+                                 __hip_bfloat16* __restrict__ b) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < cnt;
+       t += int64_t(gridDim.x) * blockDim.x)
+    b[t] = __float2bfloat16(a[t]);
+}
+
 __global__ void i64_to_i32(const int64_t* __restrict__ a, int64_t n, int32_t* __restrict__ b) {
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
        t += int64_t(gridDim.x) * blockDim.x)
@@ -424,6 +431,9 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
   if (ix.cent8)
     hipLaunchKernelGGL(fp8_rows_kernel, dim3((C + 3) / 4), dim3(256), 0, st, ix.cent_l1, C, d,
                        ix.cent8, ix.cent8_scale);
+  if (ix.cent_l1_b)
+    hipLaunchKernelGGL(bf16_copy_kernel, dim3(1024), dim3(256), 0, st, ix.cent_l1,
+                       int64_t(C) * d, ix.cent_l1_b);
   rc = check_hip(hipGetLastError(), "index finishing kernels");
   if (rc != LIDER_OK) return rc;
   int32_t h_status = 0;

@@ -167,6 +167,7 @@ struct Index {
   float* cent_l1 = nullptr;    // [C x d] layer-1 order
   uint8_t* cent8 = nullptr;    // [C x d] fp8 e4m3, layer-1 order
   float* cent8_scale = nullptr;  // [C]
+  __hip_bfloat16* cent_l1_b = nullptr;  // [C x d] bf16 copy of cent_l1 (routing candidates)
   int64_t* l1_order = nullptr;   // [C] layer-1 position -> cluster id
   int32_t* l1_order32 = nullptr;
   uint64_t* l1_keys = nullptr;

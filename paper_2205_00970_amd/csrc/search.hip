@@ -83,7 +83,7 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   p.o_cfill = take(size_t(ix.C) * 4);
   p.o_wl = take(size_t(nq) * c * 4);
   p.o_sbuf = take(size_t(nq) * c * rcap * 4);
-  p.o_qb = take((S || ix.cent8) ? size_t(nq) * ix.d * 2 : 0);
+  p.o_qb = take((S || ix.cent8 || ix.cent_l1_b) ? size_t(nq) * ix.d * 2 : 0);
   p.o_slist = take(S ? size_t(nq) * S * 4 : 0);
   const int ti = tile_index(ix, o);
   const size_t nt = o.persistent == 2 ? size_t(ix.n_tiles[ti]) : 0;
@@ -426,6 +426,147 @@ __global__ __launch_bounds__(256) void route_select_wave_kernel(
   }
 }
 
+constexpr int kRefineLds = 1024;
+
+// Exact routing from bf16 candidate scores (window = every centroid, c < 64),
+// one wave per query.  rs holds scores of bf16-rounded query and centroids
+// with fp32 accumulation; each is within E = ecoef |q| max|mu| of the exact
+// inner product.  Every centroid of the exact top c has an approximate score
+// of at least T - 2E, T the c-th largest approximate score, so the exact top c
+// is contained in the candidates above that threshold.  Exactly c candidates:
+// they are the routed set.  More (up to 64): they are rescored by the oracle's
+// sequential FP64 dot product and the top c taken by (score desc, cluster id
+// asc).  More than 64: the whole window is rescored (route_fp64_wave).  R:
+// approximate scores kept in registers per lane (len1 <= 64 R), else re-read.
+template <int R>
+__global__ __launch_bounds__(256) void route_refine_kernel(
+    const float* __restrict__ Q, int32_t d, int64_t nq, const float* __restrict__ cent_l1,
+    const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
+    const float* __restrict__ qnorm, const float* __restrict__ cent_norm_max, double ecoef,
+    int32_t c, int32_t r1, const float* __restrict__ rs, double* __restrict__ rs64,
+    int32_t* __restrict__ routed) {
+  __shared__ int32_t cand[4][64];
+  __shared__ int32_t chosen[4][64];
+  __shared__ double csc[4][64];
+  __shared__ float sq[4][kRefineLds], smu[4][kRefineLds];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool staged = d <= kRefineLds;
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
+    const int32_t s1 = l1[3 * q + 1], len1 = l1[3 * q + 2];
+    const float* rsq = rs + q * r1;
+    float v[R > 0 ? R : 1];
+    if (R > 0) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int p = lane + 64 * j;
+        v[j] = p < len1 ? rsq[p] : 0.f;
+      }
+    }
+    auto score = [&](int j, int p) { return R > 0 ? v[j] : rsq[p]; };
+    // T: the c-th largest approximate score (c rounds of a wave minimum over
+    // score keys; the index part keeps equal scores apart)
+    uint64_t prev = 0;
+    for (int t = 0; t < c; ++t) {
+      uint64_t best = ~uint64_t(0);
+      if (R > 0) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const int p = lane + 64 * j;
+          const uint64_t key = (uint64_t(score_key(v[j])) << 32) | uint32_t(p);
+          if (p < len1 && (t == 0 || key > prev) && key < best) best = key;
+        }
+      } else {
+        for (int p = lane; p < len1; p += 64) {
+          const uint64_t key = (uint64_t(score_key(rsq[p])) << 32) | uint32_t(p);
+          if ((t == 0 || key > prev) && key < best) best = key;
+        }
+      }
+      prev = wave_min_u64(best);
+    }
+    const double E = ecoef * double(qnorm[q]) * double(*cent_norm_max) +
+                     double(d) * 7.52316384526264e-37;  // d * 2^-120: subnormal products
+    const double thr = double(key_score(uint32_t(prev >> 32))) - 2.0 * E;
+    int n = 0;
+    const int nchunk = (len1 + 63) / 64;
+    for (int jc = 0; jc < nchunk; ++jc) {
+      const int p = jc * 64 + lane;
+      float sv = 0.f;
+      if (R > 0) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+          if (j == jc) sv = v[j];
+      } else if (p < len1) {
+        sv = rsq[p];
+      }
+      const bool in = p < len1 && double(sv) >= thr;
+      const uint64_t m = __ballot(in);
+      const int slot = n + __popcll(m & below);
+      if (in && slot < 64) cand[wave][slot] = p;
+      n += __popcll(m);
+    }
+    (void)score;
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    const float* qv = Q + q * d;
+    if (n == c) {  // the candidates are the routed set; listed by approximate score
+      float sv = 0.f;
+      int32_t p = 0;
+      if (lane < c) {
+        p = cand[wave][lane];
+        sv = rsq[p];
+      }
+      const uint64_t key = (uint64_t(score_key(sv)) << 32) | uint32_t(p);
+      int rank = 0;
+      for (int u = 0; u < c; ++u) rank += __shfl(key, u) < key;
+      if (lane < c) routed[q * c + rank] = l1_order32[s1 + p];
+    } else if (n > 64) {
+      route_fp64_wave(qv, d, cent_l1, l1_order32, s1, len1, c, rs64 + q * r1, chosen[wave]);
+      for (int t = lane; t < c; t += 64) routed[q * c + t] = chosen[wave][t];
+    } else {
+      // sequential FP64 dot products, one candidate at a time: the wave stages
+      // the query and the centroid row in LDS, lane 0 sums in dimension order
+      if (staged)
+        for (int l = lane; l < d; l += 64) sq[wave][l] = qv[l];
+      for (int t = 0; t < n; ++t) {
+        const float* mu = cent_l1 + int64_t(s1 + cand[wave][t]) * d;
+        if (staged) {
+          for (int l = lane; l < d; l += 64) smu[wave][l] = mu[l];
+          __threadfence_block();
+          __builtin_amdgcn_wave_barrier();
+        }
+        if (lane == 0) {
+          double acc = 0.0;
+          if (staged) {
+#pragma unroll 8
+            for (int l = 0; l < d; ++l) acc = acc + double(sq[wave][l]) * double(smu[wave][l]);
+          } else {
+            for (int l = 0; l < d; ++l) acc = acc + double(qv[l]) * double(mu[l]);
+          }
+          csc[wave][t] = acc;
+        }
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+      }
+      double sc = -INFINITY;
+      int32_t id = 0x7fffffff;
+      if (lane < n) {
+        sc = csc[wave][lane];
+        id = l1_order32[s1 + cand[wave][lane]];
+      }
+      int rank = 0;
+      for (int u = 0; u < n; ++u) {
+        const double su = __shfl(sc, u);
+        const int32_t iu = __shfl(id, u);
+        rank += (su > sc) || (su == sc && iu < id);
+      }
+      if (lane < n && rank < c) routed[q * c + rank] = id;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // Routing, one workgroup per query (any c): radix selection of c + 1.
 template <bool FP8>
 __global__ __launch_bounds__(kRouteNT) void route_select_block_kernel(
@@ -690,6 +831,12 @@ __device__ inline int32_t fetch_tile(int persistent, int32_t ntiles, int32_t* __
 // the tile size, the schedule or which other pairs share a pass.
 constexpr int kRerankWaves = 4;
 
+// A wave-uniform value, moved to a scalar register.
+__device__ inline int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+constexpr int32_t kBufWord3 = 0x00020000;  // buffer resource word 3 for gfx9-family targets
+
 // Operand feeds.  FMT 0: fp32 rows and queries; 1: bf16 rows and queries;
 // 2: fp8 e4m3 rows (decoded exactly to bf16) and bf16 queries; 3 / 4: fp32 /
 // bf16 with two 16-byte loads per lane and row per k-step, 64 bytes apart, so
@@ -838,6 +985,13 @@ struct Feed<kF32W, VEC> {  // 32 dims per k-step: 4 + 4 per lane
   }
   __device__ static Raw raw(const float* row, int k, int d, bool nt) { return loadx(row, k, d, nt); }
   __device__ static T dec(const Raw& v, int, int) { return v; }
+  // Both 16-byte halves from a buffer resource at byte offset voff (range
+  // checked: out-of-range reads return zero).
+  __device__ static T loadb(__amdgpu_buffer_rsrc_t rs, int32_t voff) {
+    const i32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 0);
+    const i32x4 b = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 64, 0, 0);
+    return T{__builtin_bit_cast(float4, a), __builtin_bit_cast(float4, b)};
+  }
   __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
     Feed<kF32, VEC>::mfma(q.a, x.a, acc);
     Feed<kF32, VEC>::mfma(q.b, x.b, acc);
@@ -866,9 +1020,37 @@ struct Feed<kBF16W, VEC> {  // 64 dims per k-step: 8 + 8 per lane
     return loadx(row, k, d, nt);
   }
   __device__ static T dec(const Raw& v, int, int) { return v; }
+  __device__ static T loadb(__amdgpu_buffer_rsrc_t rs, int32_t voff) {
+    const i32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 0);
+    const i32x4 b = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 64, 0, 0);
+    return T{__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b)};
+  }
   __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
     Feed<kBF16, VEC>::mfma(q.a, x.a, acc);
     Feed<kBF16, VEC>::mfma(q.b, x.b, acc);
+  }
+};
+
+// Row sources of a tile.  PtrRows: one pointer per 16-row block (rows past the
+// tile clamped to its last row).  BufRows: the tile as one buffer resource of
+// rows * d elements; lane row r of block rc sits at byte (16 rc + r) d esz, and
+// rows past the tile fall outside the resource and read as zero.
+template <class F, int RC>
+struct PtrRows {
+  const typename F::XE* xr[RC];
+  __device__ typename F::T load(int rc, int k, int d, bool nt) const {
+    return F::loadx(xr[rc], k, d, nt);
+  }
+};
+
+template <class F, int RC>
+struct BufRows {
+  __amdgpu_buffer_rsrc_t rs;
+  int32_t vbase;    // byte offset of the lane's row in block 0
+  int32_t rstride;  // bytes between row blocks (16 rows)
+  int32_t esz;
+  __device__ typename F::T load(int rc, int k, int, bool) const {
+    return F::loadb(rs, vbase + rc * rstride + k * esz);
   }
 };
 
@@ -876,13 +1058,13 @@ struct Feed<kBF16W, VEC> {  // 64 dims per k-step: 8 + 8 per lane
 // copies of loaded data): the loads of one step are in flight while the MFMAs
 // of the previous step run.  The last load of the paired loop is clamped to
 // the final step (a redundant cache hit when the step count is even).
-template <class F, int RC, int NPC, bool NT>
-__device__ __forceinline__ void load_step(const typename F::XE* const (&xr)[RC],
+template <class F, int RC, int NPC, bool NT, class Src>
+__device__ __forceinline__ void load_step(const Src& src,
                                           const typename F::QE* q0, const typename F::QE* q1,
                                           int k, int d, typename F::T (&x)[RC],
                                           typename F::T& qa, typename F::T& qb) {
 #pragma unroll
-  for (int rc = 0; rc < RC; ++rc) x[rc] = F::loadx(xr[rc], k, d, NT);
+  for (int rc = 0; rc < RC; ++rc) x[rc] = src.load(rc, k, d, NT);
   qa = F::load(q0, k, d);
   if (NPC > 1) qb = F::load(q1, k, d);
 }
@@ -900,8 +1082,8 @@ __device__ __forceinline__ void mfma_step(const typename F::T (&x)[RC], const ty
 
 // xa holds the rows' first k-step when `pre` is set (issued before the pair
 // scan so that the tile's first HBM reads overlap it).
-template <class F, int RC, int NPC, bool NT>
-__device__ __forceinline__ void pass_loop(const typename F::XE* const (&xr)[RC],
+template <class F, int RC, int NPC, bool NT, class Src>
+__device__ __forceinline__ void pass_loop(const Src& xr,
                                           const typename F::QE* q0, const typename F::QE* q1,
                                           int ks0, int ks1, int sub, int d,
                                           floatx4 (&acc)[RC][2], typename F::T (&xa)[RC],
@@ -947,6 +1129,10 @@ __global__ __launch_bounds__(256) void rerank_kernel(
   typedef typename F::QE QE;
   constexpr int RC = RT / 16;
   constexpr int PP = 16 * NPCM;  // pairs per pass
+  // full-line corpus feeds stream through a buffer resource (fewer address
+  // registers; rows past a partial tile read as zero instead of being clamped)
+  constexpr bool kBuf = VEC && (FMT == kF32W || FMT == kBF16W);
+  typedef typename std::conditional<kBuf, BufRows<F, RC>, PtrRows<F, RC>>::type Src;
   __shared__ WaveShared shw[kRerankWaves];
   const XE* X = static_cast<const XE*>(Xv);
   const QE* Q = static_cast<const QE*>(Qv);
@@ -969,23 +1155,32 @@ __global__ __launch_bounds__(256) void rerank_kernel(
       tile = it == 0 ? direct_tile(ntiles) : -1;
     }
     if (tile < 0) break;
-    const int4 td = reinterpret_cast<const int4*>(tiles)[tile];
-    const int32_t j = td.x, row0 = td.y, rows_here = td.w;
-    const int64_t grow = td.z;  // first row of the tile in the reordered corpus
-    int32_t plo = cstart[j], phi = cstart[j + 1];
+    // tile descriptor and pair range are wave-uniform: keep them in SGPRs
+    const int4 td = reinterpret_cast<const int4*>(tiles)[uni(tile)];
+    const int32_t j = uni(td.x), row0 = uni(td.y), rows_here = uni(td.w);
+    const int64_t grow = uni(td.z);  // first row of the tile in the reordered corpus
+    int32_t plo = uni(cstart[j]), phi = uni(cstart[j + 1]);
     if (pair_chunk > 0) {
       plo += int32_t(blockIdx.y) * pair_chunk;
       phi = min(phi, plo + pair_chunk);
     }
-    const XE* xr[RC];
+    Src xr;
+    if constexpr (kBuf) {
+      xr.esz = int32_t(sizeof(XE));
+      xr.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<XE*>(X + grow * d), 0,
+                                                int32_t(rows_here) * d * xr.esz, kBufWord3);
+      xr.vbase = i * d * xr.esz;
+      xr.rstride = 16 * d * xr.esz;
+    } else {
 #pragma unroll
-    for (int rc = 0; rc < RC; ++rc)
-      xr[rc] = X + (grow + min(16 * rc + i, rows_here - 1)) * d;
+      for (int rc = 0; rc < RC; ++rc)
+        xr.xr[rc] = X + (grow + min(16 * rc + i, rows_here - 1)) * d;
+    }
     typename F::T xa[RC];
     bool pre = plo < phi;
     if (pre) {  // the first k-step's rows, in flight during the pair scan
 #pragma unroll
-      for (int rc = 0; rc < RC; ++rc) xa[rc] = F::loadx(xr[rc], sub, d, NT);
+      for (int rc = 0; rc < RC; ++rc) xa[rc] = xr.load(rc, sub, d, NT);
     }
     for (int32_t pb = plo; pb < phi; pb += kWavePairCap) {
       const int32_t u = pb + lane;
@@ -1020,9 +1215,9 @@ __global__ __launch_bounds__(256) void rerank_kernel(
         const QE* q0 = Q + int64_t(sh.lq[g0 + min(i, np - 1)]) * d;
         const QE* q1 = Q + int64_t(sh.lq[g0 + min(16 + i, np - 1)]) * d;
         if (NPCM > 1 && npc > 1)
-          pass_loop<F, RC, 2, NT>(xr, q0, q1, 0, nsteps, sub, d, acc, xa, pre);
+          pass_loop<F, RC, 2, NT, Src>(xr, q0, q1, 0, nsteps, sub, d, acc, xa, pre);
         else
-          pass_loop<F, RC, 1, NT>(xr, q0, q1, 0, nsteps, sub, d, acc, xa, pre);
+          pass_loop<F, RC, 1, NT, Src>(xr, q0, q1, 0, nsteps, sub, d, acc, xa, pre);
         pre = false;
         // D layout: acc[rc][pc][e] = pair g0 + 16 pc + 4 s + e, row 16 rc + i
 #pragma unroll
@@ -1699,6 +1894,28 @@ void launch_l1_gemm_mb(const Index& ix, bool fp8, int64_t nq, const float* Q,
                        nq, (const void*)ix.cent_l1, ix.C, ix.d, (const float*)nullptr, rs);
 }
 
+// bf16 query x bf16 centroid product (candidate scores of the exact routing).
+void launch_l1_gemm_bf16(const Index& ix, int64_t nq, const __hip_bfloat16* Qb, float* rs,
+                         hipStream_t st) {
+  const int64_t nblk4 = (nq + 127) / 128 * ((ix.C + kGemmTileN - 1) / kGemmTileN);
+  const int mb = nblk4 >= int64_t(ix.n_cu) ? 4 : 2;  // operand traffic from L2 bounds it
+  const int64_t nblk = (nq + 32 * mb - 1) / (32 * mb) * ((ix.C + kGemmTileN - 1) / kGemmTileN);
+  const dim3 grid(unsigned((nblk + 7) / 8 * 8));
+  const bool vec = ix.d % 32 == 0;
+  if (vec && mb == 4)
+    hipLaunchKernelGGL((l1_gemm_kernel<kBF16, true, 4>), grid, dim3(256), 0, st, (const void*)Qb,
+                       nq, (const void*)ix.cent_l1_b, ix.C, ix.d, (const float*)nullptr, rs);
+  else if (vec)
+    hipLaunchKernelGGL((l1_gemm_kernel<kBF16, true, 2>), grid, dim3(256), 0, st, (const void*)Qb,
+                       nq, (const void*)ix.cent_l1_b, ix.C, ix.d, (const float*)nullptr, rs);
+  else if (mb == 4)
+    hipLaunchKernelGGL((l1_gemm_kernel<kBF16, false, 4>), grid, dim3(256), 0, st, (const void*)Qb,
+                       nq, (const void*)ix.cent_l1_b, ix.C, ix.d, (const float*)nullptr, rs);
+  else
+    hipLaunchKernelGGL((l1_gemm_kernel<kBF16, false, 2>), grid, dim3(256), 0, st, (const void*)Qb,
+                       nq, (const void*)ix.cent_l1_b, ix.C, ix.d, (const float*)nullptr, rs);
+}
+
 void launch_l1_gemm(const Index& ix, bool fp8, int64_t nq, const float* Q,
                     const __hip_bfloat16* Qb, float* rs, hipStream_t st) {
   const int64_t nblk4 = (nq + 127) / 128 * ((ix.C + kGemmTileN - 1) / kGemmTileN);
@@ -1767,15 +1984,30 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
                        (const int64_t*)nullptr, int64_t(C), l1pairs, nq, kq, p.r1, m,
                        o.expand_bits, l1);
   const bool fp8 = bf16 && ix.cent8;
-  if (fp8 || bf16)
+  // exact routing from bf16 candidates: dense layer 1, fp32 path, c < 64
+  const bool refine = !bf16 && p.r1 == C && o.l1_dense == 0 && c + 1 <= 64 && ix.cent_l1_b;
+  if (fp8 || bf16 || refine)
     hipLaunchKernelGGL(to_bf16_kernel, dim3(2048), dim3(256), 0, st, Q, nq * ix.d, qb);
-  if (p.r1 == C && o.l1_dense >= 0)
+  if (refine)
+    launch_l1_gemm_bf16(ix, nq, qb, rs, st);
+  else if (p.r1 == C && o.l1_dense >= 0)
     launch_l1_gemm(ix, fp8, nq, Q, qb, rs, st);
   else
     launch_l1_scores(ix, fp8, nq, l1cs, l1pairs, Q, qb, rs, p.r1, st);
   const unsigned qgrid = unsigned(std::min<int64_t>(nq, 65535));
   const unsigned wgrid = unsigned(std::min<int64_t>((nq + 3) / 4, 65535));
-  if (c + 1 <= 64) {
+  if (refine) {
+    const double u = 0.00390625;  // 2^-8: bf16 rounding of each operand
+    const double ecoef = 2.0 * u + u * u + dot_err_coef(ix.d) * (1.0 + u) * (1.0 + u);
+    if (p.r1 <= 16 * 64)
+      hipLaunchKernelGGL(route_refine_kernel<16>, dim3(wgrid), dim3(256), 0, st, Q, ix.d, nq,
+                         ix.cent_l1, ix.l1_order32, l1, qnorm, ix.cent_norm_max, ecoef, c, p.r1,
+                         rs, rs64, routed);
+    else
+      hipLaunchKernelGGL(route_refine_kernel<0>, dim3(wgrid), dim3(256), 0, st, Q, ix.d, nq,
+                         ix.cent_l1, ix.l1_order32, l1, qnorm, ix.cent_norm_max, ecoef, c, p.r1,
+                         rs, rs64, routed);
+  } else if (c + 1 <= 64) {
     if (fp8)
       hipLaunchKernelGGL(route_select_wave_kernel<true>, dim3(wgrid), dim3(256), 0, st, Q, ix.d,
                          nq, ix.cent_l1, ix.l1_order32, l1, qnorm, ix.cent_norm_max, c, p.r1, rs,

@@ -213,7 +213,8 @@ class Index:
         o = SearchOpts()
         o.r1, o.precision, o.shortlist_mult = int(r1), _PREC[precision], int(shortlist_mult)
         o.persistent, o.tile_rows, o.grid_mult = int(persistent), int(tile_rows), int(grid_mult)
-        o.l1_dense = 0 if l1_dense else -1
+        # True: automatic dense layer 1; False: window kernel; or the raw code
+        o.l1_dense = 0 if l1_dense is True else -1 if l1_dense is False else int(l1_dense)
         o.pass_pairs = int(pass_pairs)
         o.expand_bits = int(expand_bits)
         return o

@@ -106,7 +106,8 @@ def test_mid_schedules_identical(mid):
 
 @pytest.mark.parametrize("precision", ["f32", "bf16"])
 def test_mid_dense_layer1_identical(mid, precision):
-    """r1 = C: the dense layer-1 GEMM and the window kernel route identically."""
+    """r1 = C: the bf16-candidate routing, the fp32 dense GEMM and the window
+    kernel route identically."""
     torch = _torch()
     from paper_2205_00970_amd import lider
     X, Q = mid["X"], mid["Q"]
@@ -120,9 +121,33 @@ def test_mid_dense_layer1_identical(mid, precision):
     for sl in (slice(None), slice(5, 6), slice(17, 300)):
         q = Qd[sl].contiguous()
         a = gi.search(q, 10, 3, 500, r1=64, precision=precision, debug=True)
-        b = gi.search(q, 10, 3, 500, r1=64, precision=precision, debug=True, l1_dense=False)
-        assert torch.equal(a[2]["routed"], b[2]["routed"])
-        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+        for mode in (False, 1):  # window kernel; dense fp32 without bf16 candidates
+            b = gi.search(q, 10, 3, 500, r1=64, precision=precision, debug=True, l1_dense=mode)
+            # the routed sets agree (their listing order is not part of the result)
+            assert torch.equal(a[2]["routed"].sort(dim=1)[0], b[2]["routed"].sort(dim=1)[0])
+            assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_mid_routing_near_ties(mid):
+    """Queries with many equal or nearly equal centroid scores (zero vectors,
+    midpoints of two centroids, tiny perturbations of them): the bf16-candidate
+    routing still returns the FP64 routed sets of the oracle."""
+    torch = _torch()
+    X, gi, oi = mid["X"], mid["gi"], mid["oi"]
+    cent = oi.centroids()
+    rng = np.random.default_rng(12)
+    rows = [np.zeros(768, np.float32)]
+    for _ in range(40):
+        a, b = rng.choice(63, 2, replace=False)
+        mpt = 0.5 * (cent[a] + cent[b])
+        rows.append(mpt)
+        rows.append(mpt + 1e-6 * rng.standard_normal(768))
+    Q = np.ascontiguousarray(np.stack(rows).astype(np.float32))
+    for c in (1, 2, 5):
+        ids, sc, dbg = gi.search(torch.from_numpy(Q).cuda(), 10, c, 300, r1=64, debug=True)
+        oids, osc, odbg = oi.search(Q, 10, c, 300, 64, debug=True)
+        compare_debug(dbg, odbg)
+        compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
 
 
 @pytest.mark.parametrize("n,C,d", [(20000, 16, 128), (30000, 48, 768)])
