@@ -313,14 +313,27 @@ __global__ void l1_kernel(const Model* __restrict__ models, const double* __rest
 
 constexpr int kRouteNT = 256;
 
+// Minimum over the 64 lanes of a wave (all lanes active), on DPP: inclusive
+// prefix minima within each row of 16 (row_shr 1, 2, 4, 8; a lane whose
+// source lies before its row keeps its own value), then row_bcast:15 and
+// row_bcast:31 carry the row minima up to lane 63, which is read back.
+__device__ inline uint32_t dpp_min_u32(uint32_t v) {
+  auto step = [](uint32_t x, uint32_t y) { return x < y ? x : y; };
+  v = step(v, uint32_t(__builtin_amdgcn_update_dpp(int(v), int(v), 0x111, 0xf, 0xf, false)));
+  v = step(v, uint32_t(__builtin_amdgcn_update_dpp(int(v), int(v), 0x112, 0xf, 0xf, false)));
+  v = step(v, uint32_t(__builtin_amdgcn_update_dpp(int(v), int(v), 0x114, 0xf, 0xf, false)));
+  v = step(v, uint32_t(__builtin_amdgcn_update_dpp(int(v), int(v), 0x118, 0xf, 0xf, false)));
+  v = step(v, uint32_t(__builtin_amdgcn_update_dpp(int(v), int(v), 0x142, 0xa, 0xf, false)));
+  v = step(v, uint32_t(__builtin_amdgcn_update_dpp(int(v), int(v), 0x143, 0xc, 0xf, false)));
+  return uint32_t(__builtin_amdgcn_readlane(int(v), 63));
+}
+
+// 64-bit minimum: the minimum high word, then the minimum low word among the
+// lanes holding it.
 __device__ inline uint64_t wave_min_u64(uint64_t v) {
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint32_t lo = __shfl_xor(uint32_t(v), o);
-    const uint32_t hi = __shfl_xor(uint32_t(v >> 32), o);
-    const uint64_t ov = (uint64_t(hi) << 32) | lo;
-    v = ov < v ? ov : v;
-  }
-  return v;
+  const uint32_t hi = dpp_min_u32(uint32_t(v >> 32));
+  const uint32_t lo = dpp_min_u32(uint32_t(v >> 32) == hi ? uint32_t(v) : 0xffffffffu);
+  return (uint64_t(hi) << 32) | lo;
 }
 
 // Error bound of one fp32 window score against its FP64 definition.
