@@ -59,7 +59,7 @@ def lib():
         L.or_encode_box.argtypes = [p, i32, p, p, i32, p]
         L.or_encode_box.restype = u64
         L.or_window_pub.argtypes = [i64, i64, i64, p, p]
-        L.or_build.argtypes = [p, i64, i32, i32, p, p, i32, p, p, i32, f64, i32, i32, i32, p]
+        L.or_build.argtypes = [p, i64, i32, i32, p, p, i32, p, p, i32, i32, f64, i32, i32, i32, p]
         L.or_build.restype = p
         L.or_free.argtypes = [p]
         L.or_search.argtypes = [p, p, i64, i32, i32, i32, i32, i32, p, p, p, p, p, p]
@@ -270,19 +270,25 @@ class Model:
 
 
 class Index:
-    """Oracle LIDER index (Sections 3.2-3.3).  Keeps a reference to X."""
+    """Oracle LIDER index (Sections 3.2-3.3).  Keeps a reference to X.
+
+    n_arrays = H hashkey arrays per core model (Section 3.3.1): A is
+    [2 H m, d] -- rows h*m.. hash array h of the centroids retriever, rows
+    H*m + h*m.. array h of every in-cluster retriever -- and b is [2 H m]."""
 
     def __init__(self, X, n_clusters, A, b, m, w, rmi_fanout, rmi_fanout_l1=None,
                  assignment=None, init_ids=None, kmeans_iters=20, seeding="given",
-                 hash_kind="e2lsh"):
+                 hash_kind="e2lsh", n_arrays=1):
         self.X = _f32(X)
         self.n, self.d = self.X.shape
         self.C, self.m, self.w = int(n_clusters), int(m), float(w)
         self.kind = {"e2lsh": 0, "sign": 1}[hash_kind]
         self.F2 = int(rmi_fanout)
         self.F1 = int(rmi_fanout_l1 if rmi_fanout_l1 is not None else rmi_fanout)
+        self.H = int(n_arrays)
         self.A, self.b = _f32(A), _f32(b)
-        assert self.A.shape == (2 * self.m, self.d) and self.b.shape == (2 * self.m,)
+        nh = 2 * self.H * self.m
+        assert self.A.shape == (nh, self.d) and self.b.shape == (nh,)
         asg = None if assignment is None else np.ascontiguousarray(assignment, dtype=np.int32)
         ini = None if init_ids is None else np.ascontiguousarray(init_ids, dtype=np.int64)
         if asg is None and ini is not None and seeding == "farthest":
@@ -292,7 +298,7 @@ class Index:
             raise ValueError("need an assignment or k-means initial ids")
         st = C.c_int(0)
         h = lib().or_build(_ptr(self.X), self.n, self.d, self.C, _ptr(asg), _ptr(ini),
-                           int(kmeans_iters), _ptr(self.A), _ptr(self.b), self.m, self.w,
+                           int(kmeans_iters), _ptr(self.A), _ptr(self.b), self.m, self.H, self.w,
                            self.F2, self.F1, self.kind, C.byref(st))
         _check(st.value, "build")
         self._h = C.c_void_p(h)
@@ -322,30 +328,33 @@ class Index:
         lib().or_get_offsets(self._h, _ptr(out))
         return out
 
-    def perm(self):
-        out = np.empty(self.n, np.int64)
+    def perm(self, array=0):
+        """Sorted position -> original id in hashkey array `array`."""
+        out = np.empty((self.H, self.n), np.int64)
         lib().or_get_perm(self._h, _ptr(out))
-        return out
+        return out[array].copy()
 
-    def keys(self):
-        out = np.empty(self.n, np.uint64)
+    def keys(self, array=0):
+        out = np.empty((self.H, self.n), np.uint64)
         lib().or_get_keys(self._h, _ptr(out))
-        return out
+        return out[array].copy()
 
-    def digits(self):
-        out = np.empty((self.n, self.m), np.int32)
+    def digits(self, array=0):
+        out = np.empty((self.H, self.n, self.m), np.int32)
         lib().or_get_digits(self._h, _ptr(out))
-        return out
+        return out[array].copy()
 
-    def layer1(self):
-        order = np.empty(self.C, np.int64)
-        keys = np.empty(self.C, np.uint64)
-        dig = np.empty((self.C, self.m), np.int32)
+    def layer1(self, array=0):
+        order = np.empty((self.H, self.C), np.int64)
+        keys = np.empty((self.H, self.C), np.uint64)
+        dig = np.empty((self.H, self.C, self.m), np.int32)
         lib().or_get_l1(self._h, _ptr(order), _ptr(keys), _ptr(dig))
-        return order, keys, dig
+        return order[array].copy(), keys[array].copy(), dig[array].copy()
 
-    def model(self, j):
+    def model(self, j, array=0):
+        """Core model j of hashkey array `array` (j = C: the centroids retriever)."""
         F = self.F1 if j == self.C else self.F2
+        j = array * (self.C + 1) + j
         ints = np.zeros(3, np.int64)
         mins = np.zeros(self.m, np.int32)
         maxs = np.zeros(self.m, np.int32)
@@ -367,15 +376,19 @@ class Index:
         ids = np.empty((nq, k), np.int64)
         sc = np.empty((nq, k), np.float64)
         dbg = None
+        H = self.H
         if debug:
-            dbg = dict(qdigits=np.empty((nq, 2 * self.m), np.int32),
-                       l1=np.empty((nq, 3), np.int64),
+            dbg = dict(qdigits=np.empty((nq, 2 * H * self.m), np.int32),
+                       l1=np.empty((nq, H, 3), np.int64),
                        routed=np.empty((nq, c), np.int32),
-                       pairs=np.empty((nq, c, 3), np.int64))
+                       pairs=np.empty((nq, c, H, 3), np.int64))
         _check(lib().or_search(self._h, _ptr(Q), nq, k, c, r, r1, int(expand_bits), _ptr(ids),
                                _ptr(sc),
                                _ptr(dbg["qdigits"]) if dbg else None,
                                _ptr(dbg["l1"]) if dbg else None,
                                _ptr(dbg["routed"]) if dbg else None,
                                _ptr(dbg["pairs"]) if dbg else None), "search")
+        if debug and H == 1:  # one array: l1 [nq, 3], pairs [nq, c, 3]
+            dbg["l1"] = dbg["l1"][:, 0]
+            dbg["pairs"] = dbg["pairs"][:, :, 0]
         return (ids, sc, dbg) if debug else (ids, sc)

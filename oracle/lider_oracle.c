@@ -578,26 +578,29 @@ static int64_t or_model_locate(const or_model* M, const int32_t* qdigits, uint64
 }
 
 /* ------------------------------------------------------------------------ */
-/* The two-layer index (Sections 3.2, 3.3.2). */
+/* The two-layer index (Sections 3.2, 3.3.2).  Every core model keeps H
+ * hashkey arrays, each with its own hash functions, sorted array and RMI
+ * (Sections 3.3.1, 4.3); H = 1 is the single-array core model.  Arrays are
+ * stored array-major: array h of a per-row table starts at h * n. */
 typedef struct {
   int64_t n;
-  int32_t d, C, m, F2, F1;
+  int32_t d, C, m, F2, F1, H;
   double w;
   int32_t kind;        /* 0: Euclidean E2LSH digits, 1: sign bits (Section 4.1) */
   const float* X;      /* caller-owned corpus, original id order [n x d] */
-  float* A;            /* [2m x d]: rows 0..m-1 layer 1, m..2m-1 layer 2 */
-  float* b;            /* [2m] */
+  float* A;            /* [2Hm x d]: rows h*m.. layer-1 array h, H*m + h*m.. layer-2 array h */
+  float* b;            /* [2Hm] */
   float* cent;         /* [C x d] */
   int32_t* assign;     /* [n] */
   int32_t iters_run;
   int64_t* off;        /* [C+1] first sorted position of each cluster */
-  int64_t* perm;       /* [n] sorted position -> original id */
-  uint64_t* keys;      /* [n] key at each sorted position */
-  int32_t* digits;     /* [n x m] layer-2 digits per original id */
-  or_model* models;    /* [C+1]; models[C] is the centroids retriever */
-  int64_t* l1_order;   /* [C] layer-1 sorted position -> cluster id */
-  uint64_t* l1_keys;   /* [C] */
-  int32_t* l1_digits;  /* [C x m] layer-1 digits per cluster id */
+  int64_t* perm;       /* [H x n] sorted position in array h -> original id */
+  uint64_t* keys;      /* [H x n] key at each sorted position of array h */
+  int32_t* digits;     /* [H x n x m] layer-2 digits of array h per original id */
+  or_model* models;    /* [H x (C+1)]; model h*(C+1) + C is array h of the centroids retriever */
+  int64_t* l1_order;   /* [H x C] layer-1 sorted position in array h -> cluster id */
+  uint64_t* l1_keys;   /* [H x C] */
+  int32_t* l1_digits;  /* [H x C x m] layer-1 digits of array h per cluster id */
 } or_index;
 
 void or_free(or_index* ix) {
@@ -611,7 +614,7 @@ void or_free(or_index* ix) {
   free(ix->keys);
   free(ix->digits);
   if (ix->models)
-    for (int32_t j = 0; j <= ix->C; ++j) {
+    for (int64_t j = 0; j < (int64_t)ix->H * (ix->C + 1); ++j) {
       free(ix->models[j].leaf);
       free(ix->models[j].elo);
       free(ix->models[j].ehi);
@@ -623,14 +626,23 @@ void or_free(or_index* ix) {
   free(ix);
 }
 
-/* Build: k-means (or a given assignment), then one core model over the
- * centroids (layer 1) and one per cluster over its members (layer 2). */
+/* Digits of n rows under hash functions A (nh rows), either family. */
+static int or_hash_rows(const or_index* ix, const float* X, int64_t n, const float* A,
+                        const float* b, int32_t* out) {
+  return ix->kind ? or_digits_sign(X, n, ix->d, A, ix->m, out)
+                  : or_digits(X, n, ix->d, A, b, ix->m, ix->w, out);
+}
+
+/* Build: k-means (or a given assignment), then for each of the H arrays one
+ * core model over the centroids (layer 1) and one per cluster over its
+ * members (layer 2). */
 or_index* or_build(const float* X, int64_t n, int32_t d, int32_t C, const int32_t* assign_in,
                    const int64_t* init_ids, int32_t kmeans_iters, const float* A, const float* b,
-                   int32_t m, double w, int32_t F2, int32_t F1, int32_t kind, int* status) {
+                   int32_t m, int32_t H, double w, int32_t F2, int32_t F1, int32_t kind,
+                   int* status) {
   *status = OR_EINVAL;
-  if (n < 1 || d < 1 || C < 1 || C > n || m < 1 || m > OR_MAX_M || !(w > 0.0) || F2 < 1 ||
-      F1 < 1 || kind < 0 || kind > 1 || (kind == 1 && m > 53))
+  if (n < 1 || d < 1 || C < 1 || C > n || m < 1 || m > OR_MAX_M || H < 1 || H > 64 ||
+      !(w > 0.0) || F2 < 1 || F1 < 1 || kind < 0 || kind > 1 || (kind == 1 && m > 53))
     return NULL;
   or_index* ix = (or_index*)calloc(1, sizeof(or_index));
   if (!ix) {
@@ -641,31 +653,36 @@ or_index* or_build(const float* X, int64_t n, int32_t d, int32_t C, const int32_
   ix->d = d;
   ix->C = C;
   ix->m = m;
+  ix->H = H;
   ix->F2 = F2;
   ix->F1 = F1;
   ix->w = w;
   ix->kind = kind;
   ix->X = X;
-  ix->A = (float*)malloc(sizeof(float) * (size_t)2 * m * d);
-  ix->b = (float*)malloc(sizeof(float) * (size_t)2 * m);
+  const size_t nh = (size_t)2 * H * m;
+  ix->A = (float*)malloc(sizeof(float) * nh * d);
+  ix->b = (float*)malloc(sizeof(float) * nh);
   ix->cent = (float*)malloc(sizeof(float) * (size_t)C * d);
   ix->assign = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
   ix->off = (int64_t*)calloc((size_t)C + 1, sizeof(int64_t));
-  ix->perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
-  ix->keys = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
-  ix->digits = (int32_t*)malloc(sizeof(int32_t) * (size_t)n * m);
-  ix->models = (or_model*)calloc((size_t)C + 1, sizeof(or_model));
-  ix->l1_order = (int64_t*)malloc(sizeof(int64_t) * (size_t)C);
-  ix->l1_keys = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)C);
-  ix->l1_digits = (int32_t*)malloc(sizeof(int32_t) * (size_t)C * m);
+  ix->perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)H * n);
+  ix->keys = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)H * n);
+  ix->digits = (int32_t*)malloc(sizeof(int32_t) * (size_t)H * n * m);
+  ix->models = (or_model*)calloc((size_t)H * (C + 1), sizeof(or_model));
+  ix->l1_order = (int64_t*)malloc(sizeof(int64_t) * (size_t)H * C);
+  ix->l1_keys = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)H * C);
+  ix->l1_digits = (int32_t*)malloc(sizeof(int32_t) * (size_t)H * C * m);
   if (!ix->A || !ix->b || !ix->cent || !ix->assign || !ix->off || !ix->perm || !ix->keys ||
       !ix->digits || !ix->models || !ix->l1_order || !ix->l1_keys || !ix->l1_digits) {
     or_free(ix);
     *status = OR_ENOMEM;
     return NULL;
   }
-  memcpy(ix->A, A, sizeof(float) * (size_t)2 * m * d);
-  memcpy(ix->b, b, sizeof(float) * (size_t)2 * m);
+  memcpy(ix->A, A, sizeof(float) * nh * d);
+  if (b)
+    memcpy(ix->b, b, sizeof(float) * nh);
+  else
+    memset(ix->b, 0, sizeof(float) * nh);
   int st;
   if (assign_in) {
     for (int64_t i = 0; i < n; ++i) {
@@ -695,14 +712,6 @@ or_index* or_build(const float* X, int64_t n, int32_t d, int32_t C, const int32_
     *status = st;
     return NULL;
   }
-  /* layer-2 digits of every row (hash set rows m..2m-1) */
-  st = kind ? or_digits_sign(X, n, d, A + (size_t)m * d, m, ix->digits)
-            : or_digits(X, n, d, A + (size_t)m * d, b + m, m, w, ix->digits);
-  if (st != OR_OK) {
-    or_free(ix);
-    *status = st;
-    return NULL;
-  }
   /* members of each cluster in ascending id order */
   for (int64_t i = 0; i < n; ++i) ix->off[ix->assign[i] + 1] += 1;
   for (int32_t j = 0; j < C; ++j) ix->off[j + 1] += ix->off[j];
@@ -721,30 +730,35 @@ or_index* or_build(const float* X, int64_t n, int32_t d, int32_t C, const int32_
   }
   for (int32_t j = 0; j < C; ++j) fill[j] = ix->off[j];
   for (int64_t i = 0; i < n; ++i) members[fill[ix->assign[i]]++] = i;
-  for (int64_t p = 0; p < n; ++p)
-    memcpy(mdig + p * m, ix->digits + members[p] * m, sizeof(int32_t) * m);
   st = OR_OK;
-  for (int32_t j = 0; j < C && st == OR_OK; ++j) {
-    int64_t o = ix->off[j], L = ix->off[j + 1] - o;
-    st = or_core_build(&ix->models[j], L, m, F2, mdig + o * m, kind, order + o, ix->keys + o);
-    for (int64_t p = 0; p < L; ++p) ix->perm[o + p] = members[o + order[o + p]];
+  for (int32_t h = 0; h < H && st == OR_OK; ++h) {
+    /* layer-2 digits of every row under array h's hash set */
+    int32_t* dig = ix->digits + (size_t)h * n * m;
+    const size_t row2 = (size_t)H * m + (size_t)h * m;
+    st = or_hash_rows(ix, X, n, A + row2 * d, ix->b + row2, dig);
+    if (st != OR_OK) break;
+    for (int64_t p = 0; p < n; ++p)
+      memcpy(mdig + p * m, dig + members[p] * m, sizeof(int32_t) * m);
+    for (int32_t j = 0; j < C && st == OR_OK; ++j) {
+      int64_t o = ix->off[j], L = ix->off[j + 1] - o;
+      st = or_core_build(&ix->models[(int64_t)h * (C + 1) + j], L, m, F2, mdig + o * m, kind,
+                         order + o, ix->keys + (size_t)h * n + o);
+      for (int64_t p = 0; p < L; ++p) ix->perm[(size_t)h * n + o + p] = members[o + order[o + p]];
+    }
+    if (st != OR_OK) break;
+    /* layer 1: the centroids retriever over the C centroids (array h's hash
+     * set rows h*m..), ids = cluster index */
+    int32_t* dg1 = ix->l1_digits + (size_t)h * C * m;
+    const size_t row1 = (size_t)h * m;
+    st = or_hash_rows(ix, ix->cent, C, A + row1 * d, ix->b + row1, dg1);
+    if (st == OR_OK)
+      st = or_core_build(&ix->models[(int64_t)h * (C + 1) + C], C, m, F1, dg1, kind,
+                         ix->l1_order + (size_t)h * C, ix->l1_keys + (size_t)h * C);
   }
   free(fill);
   free(members);
   free(mdig);
   free(order);
-  if (st != OR_OK) {
-    or_free(ix);
-    *status = st;
-    return NULL;
-  }
-  /* layer 1: the centroids retriever over the C centroids (hash set rows
-   * 0..m-1), ids = cluster index */
-  st = kind ? or_digits_sign(ix->cent, C, d, A, m, ix->l1_digits)
-            : or_digits(ix->cent, C, d, A, b, m, w, ix->l1_digits);
-  if (st == OR_OK)
-    st = or_core_build(&ix->models[C], C, m, F1, ix->l1_digits, kind, ix->l1_order,
-                       ix->l1_keys);
   if (st != OR_OK) {
     or_free(ix);
     *status = st;
@@ -791,33 +805,46 @@ static double or_dot(const float* a, const float* x, int32_t d) {
 /* Search (Section 3.3.2): layer-1 core model routes the query to c clusters;
  * each routed cluster's core model predicts a location and scans r positions
  * around it; all candidates are scored exactly and merged into the top k.
+ * With H arrays per core model (Section 3.3.1) every array predicts its own
+ * location and scans its own window; a core model's candidates are the union
+ * of its H windows, each item counted once.  Reading: the merge of the
+ * per-array results is the top of that union (score desc, id asc), which is
+ * the same as merging the per-array top lists and dropping repeats.
  * Reading: raw inner product is the score for routing and ranking.
  * Outputs: ids/scores [nq x k] (pad -1 / -inf).  Optional debug outputs:
- *   qdig [nq x 2m]           query digits (layer-1 set, then layer-2 set)
- *   l1   [nq x 3]            layer-1 predicted location, window start, length
+ *   qdig [nq x 2Hm]          query digits (layer-1 sets h = 0..H-1, then layer 2)
+ *   l1   [nq x H x 3]        per array: layer-1 predicted location, window start, length
  *   routed [nq x c]          routed cluster ids, score desc, id asc (-1 pad)
- *   pairs [nq x c x 3]       per routed cluster: location, start, length */
+ *   pairs [nq x c x H x 3]   per routed cluster and array: location, start, length */
 int or_search(const or_index* ix, const float* Q, int64_t nq, int32_t k, int32_t c, int32_t r,
               int32_t r1, int32_t expand_bits, int64_t* ids, double* scores, int32_t* qdig,
               int64_t* l1, int32_t* routed, int64_t* pairs) {
   if (!ix || nq < 0 || k < 1 || c < 1 || c > ix->C || r < 1 || r1 < 1) return OR_EINVAL;
   /* expand_bits = B > 0: dist_e-guided expansion (binary hashkeys only) */
   if (expand_bits < 0 || expand_bits > 16 || (expand_bits > 0 && ix->kind != 1)) return OR_EINVAL;
-  const int32_t m = ix->m, d = ix->d, C = ix->C;
+  const int32_t m = ix->m, d = ix->d, C = ix->C, H = ix->H;
+  const int64_t n = ix->n;
+  const int32_t nh = 2 * H * m;
   int status = OR_OK;
 #pragma omp parallel
   {
-    int32_t* dg = (int32_t*)malloc(sizeof(int32_t) * 2 * m);
+    int32_t* dg = (int32_t*)malloc(sizeof(int32_t) * nh);
     or_cand* rb = (or_cand*)malloc(sizeof(or_cand) * (size_t)c);
     or_cand* best = (or_cand*)malloc(sizeof(or_cand) * (size_t)k);
-    if (!dg || !rb || !best) {
+    /* last (query, item) that took each centroid / row: repeats across the
+     * arrays of one core model are skipped */
+    int64_t* seen1 = (int64_t*)malloc(sizeof(int64_t) * (size_t)C);
+    int64_t* seen2 = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    if (!dg || !rb || !best || !seen1 || !seen2) {
 #pragma omp atomic write
       status = OR_ENOMEM;
     } else {
+      for (int32_t j = 0; j < C; ++j) seen1[j] = -1;
+      for (int64_t i = 0; i < n; ++i) seen2[i] = -1;
 #pragma omp for schedule(dynamic, 4)
       for (int64_t q = 0; q < nq; ++q) {
         const float* qv = Q + q * d;
-        for (int32_t i = 0; i < 2 * m; ++i) {
+        for (int32_t i = 0; i < nh; ++i) {
           if (ix->kind) {
             dg[i] = or_bit(ix->A + (int64_t)i * d, qv, d);
           } else if (or_digit(ix->A + (int64_t)i * d, qv, d, ix->b[i], ix->w, dg + i) != OR_OK) {
@@ -827,50 +854,63 @@ int or_search(const or_index* ix, const float* Q, int64_t nq, int32_t k, int32_t
           }
         }
         if (qdig)
-          for (int32_t i = 0; i < 2 * m; ++i) qdig[q * 2 * m + i] = dg[i];
-        /* layer 1: centroids retriever */
+          for (int32_t i = 0; i < nh; ++i) qdig[q * nh + i] = dg[i];
+        /* layer 1: centroids retriever, the union of its H windows */
         uint64_t K;
         double xq;
-        const or_model* M1 = &ix->models[C];
-        int64_t pos1 = or_model_locate(M1, dg, &K, &xq);
-        int64_t s1, len1;
-        if (expand_bits)
-          or_window_expand(ix->l1_keys, C, pos1, r1, K, m, expand_bits, &s1, &len1);
-        else
-          or_window(pos1, r1, C, &s1, &len1);
-        if (l1) {
-          l1[q * 3 + 0] = pos1;
-          l1[q * 3 + 1] = s1;
-          l1[q * 3 + 2] = len1;
-        }
         int32_t nr = 0;
-        for (int64_t p = s1; p < s1 + len1; ++p) {
-          int64_t j = ix->l1_order[p];
-          or_topk_push(rb, &nr, c, or_dot(qv, ix->cent + j * d, d), j);
+        for (int32_t h = 0; h < H; ++h) {
+          const or_model* M1 = &ix->models[(int64_t)h * (C + 1) + C];
+          const int64_t* ord = ix->l1_order + (size_t)h * C;
+          int64_t pos1 = or_model_locate(M1, dg + h * m, &K, &xq);
+          int64_t s1, len1;
+          if (expand_bits)
+            or_window_expand(ix->l1_keys + (size_t)h * C, C, pos1, r1, K, m, expand_bits, &s1,
+                             &len1);
+          else
+            or_window(pos1, r1, C, &s1, &len1);
+          if (l1) {
+            l1[(q * H + h) * 3 + 0] = pos1;
+            l1[(q * H + h) * 3 + 1] = s1;
+            l1[(q * H + h) * 3 + 2] = len1;
+          }
+          for (int64_t p = s1; p < s1 + len1; ++p) {
+            int64_t j = ord[p];
+            if (seen1[j] == q) continue;
+            seen1[j] = q;
+            or_topk_push(rb, &nr, c, or_dot(qv, ix->cent + j * d, d), j);
+          }
         }
         if (routed)
           for (int32_t t = 0; t < c; ++t) routed[q * c + t] = t < nr ? (int32_t)rb[t].id : -1;
         /* layer 2: in-cluster retrievers, then the merge */
         int32_t nb = 0;
         for (int32_t t = 0; t < c; ++t) {
-          int64_t pos = 0, s = 0, len = 0;
-          if (t < nr) {
-            int64_t j = rb[t].id;
-            const or_model* Mj = &ix->models[j];
-            pos = or_model_locate(Mj, dg + m, &K, &xq);
-            if (expand_bits)
-              or_window_expand(ix->keys + ix->off[j], Mj->L, pos, r, K, m, expand_bits, &s, &len);
-            else
-              or_window(pos, r, Mj->L, &s, &len);
-            for (int64_t p = s; p < s + len; ++p) {
-              int64_t id = ix->perm[ix->off[j] + p];
-              or_topk_push(best, &nb, k, or_dot(qv, ix->X + id * d, d), id);
+          for (int32_t h = 0; h < H; ++h) {
+            int64_t pos = 0, s = 0, len = 0;
+            if (t < nr) {
+              int64_t j = rb[t].id;
+              const or_model* Mj = &ix->models[(int64_t)h * (C + 1) + j];
+              const int64_t o = ix->off[j];
+              pos = or_model_locate(Mj, dg + H * m + h * m, &K, &xq);
+              if (expand_bits)
+                or_window_expand(ix->keys + (size_t)h * n + o, Mj->L, pos, r, K, m, expand_bits,
+                                 &s, &len);
+              else
+                or_window(pos, r, Mj->L, &s, &len);
+              for (int64_t p = s; p < s + len; ++p) {
+                int64_t id = ix->perm[(size_t)h * n + o + p];
+                if (seen2[id] == q * c + t) continue;
+                seen2[id] = q * c + t;
+                or_topk_push(best, &nb, k, or_dot(qv, ix->X + id * d, d), id);
+              }
             }
-          }
-          if (pairs) {
-            pairs[(q * c + t) * 3 + 0] = pos;
-            pairs[(q * c + t) * 3 + 1] = s;
-            pairs[(q * c + t) * 3 + 2] = len;
+            if (pairs) {
+              int64_t* pp = pairs + ((q * c + t) * H + h) * 3;
+              pp[0] = pos;
+              pp[1] = s;
+              pp[2] = len;
+            }
           }
         }
         for (int32_t t = 0; t < k; ++t) {
@@ -882,6 +922,8 @@ int or_search(const or_index* ix, const float* Q, int64_t nq, int32_t k, int32_t
     free(dg);
     free(rb);
     free(best);
+    free(seen1);
+    free(seen2);
   }
   return status;
 }
@@ -935,21 +977,24 @@ void or_get_assign(const or_index* ix, int32_t* out) {
 void or_get_offsets(const or_index* ix, int64_t* out) {
   memcpy(out, ix->off, sizeof(int64_t) * ((size_t)ix->C + 1));
 }
+/* Per-array tables, array-major: [H x n], [H x n], [H x n x m]. */
 void or_get_perm(const or_index* ix, int64_t* out) {
-  memcpy(out, ix->perm, sizeof(int64_t) * (size_t)ix->n);
+  memcpy(out, ix->perm, sizeof(int64_t) * (size_t)ix->H * ix->n);
 }
 void or_get_keys(const or_index* ix, uint64_t* out) {
-  memcpy(out, ix->keys, sizeof(uint64_t) * (size_t)ix->n);
+  memcpy(out, ix->keys, sizeof(uint64_t) * (size_t)ix->H * ix->n);
 }
 void or_get_digits(const or_index* ix, int32_t* out) {
-  memcpy(out, ix->digits, sizeof(int32_t) * (size_t)ix->n * ix->m);
+  memcpy(out, ix->digits, sizeof(int32_t) * (size_t)ix->H * ix->n * ix->m);
 }
+/* [H x C], [H x C], [H x C x m] */
 void or_get_l1(const or_index* ix, int64_t* order, uint64_t* keys, int32_t* digits) {
-  memcpy(order, ix->l1_order, sizeof(int64_t) * (size_t)ix->C);
-  memcpy(keys, ix->l1_keys, sizeof(uint64_t) * (size_t)ix->C);
-  memcpy(digits, ix->l1_digits, sizeof(int32_t) * (size_t)ix->C * ix->m);
+  memcpy(order, ix->l1_order, sizeof(int64_t) * (size_t)ix->H * ix->C);
+  memcpy(keys, ix->l1_keys, sizeof(uint64_t) * (size_t)ix->H * ix->C);
+  memcpy(digits, ix->l1_digits, sizeof(int32_t) * (size_t)ix->H * ix->C * ix->m);
 }
-/* Model j (0..C-1 clusters, C = layer 1).  ints: L, m_eff, F; mins/maxs [m];
+/* Model j = h * (C+1) + i of array h: i = 0..C-1 clusters, i = C layer 1.
+ * ints: L, m_eff, F; mins/maxs [m];
  * keys: kmin, kmax; dbl: scale, root slope, root intercept; leaf [2F];
  * elo/ehi [F]. */
 void or_get_model(const or_index* ix, int32_t j, int64_t* ints, int32_t* mins, int32_t* maxs,

@@ -32,14 +32,22 @@ def tiny(n=20000, d=128, ncomp=16, sigma=0.3, nq=100, qnoise=0.05, seed=0, qseed
     return X, lab, Q, src
 
 
-def lsh_params(m, d, w, seed=2):
-    """E2LSH draws for both layers: A [2m, d] ~ N(0,1), b [2m] ~ U[0, w).
-    Rows 0..m-1 are the centroids retriever's functions, m..2m-1 the
-    in-cluster retrievers' (one shared set)."""
+def lsh_params(m, d, w, seed=2, n_arrays=1):
+    """E2LSH draws for both layers and H = n_arrays hashkey arrays:
+    A [2Hm, d] ~ N(0,1), b [2Hm] ~ U[0, w).  Rows h*m.. are array h of the
+    centroids retriever, rows H*m + h*m.. array h of the in-cluster retrievers
+    (one set per array shared by every cluster)."""
     g = np.random.default_rng(seed)
-    A = g.standard_normal((2 * m, d)).astype(np.float32)
-    b = (g.random(2 * m) * w).astype(np.float32)
+    A = g.standard_normal((2 * n_arrays * m, d)).astype(np.float32)
+    b = (g.random(2 * n_arrays * m) * w).astype(np.float32)
     return A, b
+
+
+def array_params(A, b, m, n_arrays, h):
+    """The single-array hash set [2m, d] of array h of a stacked [2Hm, d] set."""
+    H = n_arrays
+    rows = np.r_[h * m:(h + 1) * m, H * m + h * m:H * m + (h + 1) * m]
+    return A[rows].copy(), b[rows].copy()
 
 
 def kmeans_init(n, n_clusters, seed=3):
