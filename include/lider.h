@@ -47,8 +47,10 @@ typedef enum {
   LIDER_FP8E4M3 = 2  /* OCP fp8 e4m3 with one fp32 scale per row */
 } lider_dtype;
 
-/* Largest supported hash count per layer, clusters, k, and c. */
+/* Largest supported hash count per array, hashkey arrays per core model,
+ * k, and c. */
 #define LIDER_MAX_M 16
+#define LIDER_MAX_H 16
 #define LIDER_MAX_K 1024
 #define LIDER_MAX_C 128
 
@@ -60,14 +62,21 @@ typedef struct lider_index lider_index; /* opaque; owns its device memory */
 
 /* Build parameters (Sections 3.2, 3.3, 5).
  *  n_clusters     number of k-means clusters c of Table 1 (1..n).
- *  m              hashes per key M of Table 1 (1..LIDER_MAX_M).
+ *  m              hashes per key M of Table 1 (1..LIDER_MAX_M), per array.
+ *  n_arrays       hashkey arrays H per core model (Section 3.3.1; 0 means 1,
+ *                 at most LIDER_MAX_H).  Each array has its own hash functions,
+ *                 sorted array and RMI; a search scans one window per array and
+ *                 scores the union of the windows (each item once).  With H > 1
+ *                 no cluster may hold more than 65536 rows.
  *  w              E2LSH bucket width (> 0): digit = floor((a.x + b) / w).
  *  rmi_fanout     second-stage width W_i of the in-cluster RMIs (Section 7.2.1).
  *  rmi_fanout_l1  second-stage width W_c of the centroids retriever (0 = same).
- *  lsh_a_host     [2m x d] fp32 projections: rows 0..m-1 hash the centroids
- *                 retriever, rows m..2m-1 are shared by every in-cluster
- *                 retriever.  Copied; may be freed after the call.
- *  lsh_b_host     [2m] fp32 offsets in [0, w).
+ *  lsh_a_host     [2Hm x d] fp32 projections: rows h*m..h*m+m-1 hash array h
+ *                 of the centroids retriever, rows H*m + h*m.. array h of
+ *                 every in-cluster retriever (one set per array, shared by the
+ *                 clusters).  For H = 1: rows 0..m-1 layer 1, m..2m-1 layer 2.
+ *                 Copied; may be freed after the call.
+ *  lsh_b_host     [2Hm] fp32 offsets in [0, w), same row order.
  *  assignment_dev optional [n] int32 cluster of each row (0..n_clusters-1);
  *                 NULL runs k-means.  Empty clusters are allowed (their
  *                 centroid is the zero vector).
@@ -108,6 +117,7 @@ typedef struct {
   int32_t centroid_storage;
   int32_t kmeans_seeding;
   int32_t hash_kind;
+  int32_t n_arrays;
 } lider_build_params;
 
 /* Build an index over corpus_dev [n x d] fp32 (Sections 3.2, 3.3.1, 3.3.2):
@@ -153,7 +163,10 @@ const char* lider_last_error(void);
  *                 bound of the c-th best are rescored in sequential FP64 to
  *                 decide the routed set.  1: the dense product in fp32 (no
  *                 bf16 candidates).  -1: always the window kernel.  The routed
- *                 sets, and so all results, are identical.
+ *                 sets, and so all results, are identical.  With n_arrays > 1
+ *                 and r1 < n_clusters, layer 1 always takes the dense fp32
+ *                 product and routes among the union of the H windows (at
+ *                 most 65536 clusters); with r1 = n_clusters, -1 acts as 1.
  *  grid_mult      persistent grid = grid_mult * number of CUs (0 = 4).
  *  expand_bits    0: fixed window of r (r1) positions, floor(r/2) left of the
  *                 predicted location (shifted inward at the ends).  B in 1..16:
@@ -179,12 +192,15 @@ typedef struct {
 } lider_search_opts;
 
 /* Optional device outputs of the intermediate search state, for parity checks.
- * Each pointer may be NULL.
- *  qdigits_dev [nq x 2m] int32   query digits (layer-1 set, then layer-2 set)
- *  l1_dev      [nq x 3] int64    layer-1 predicted location, window start, length
+ * Each pointer may be NULL.  H = the index's n_arrays.
+ *  qdigits_dev [nq x 2Hm] int32  query digits (layer-1 sets of arrays 0..H-1,
+ *                                then the layer-2 sets)
+ *  l1_dev      [nq x H x 3] int64 per array: layer-1 predicted location,
+ *                                window start, length
  *  routed_dev  [nq x c] int32    routed cluster ids (order unspecified, -1 pad)
- *  pairs_dev   [nq x c x 3] int64 per routed cluster (same order): predicted
- *                                location, window start, window length */
+ *  pairs_dev   [nq x c x H x 3] int64 per routed cluster (same order) and
+ *                                array: predicted location, window start,
+ *                                window length */
 typedef struct {
   int32_t* qdigits_dev;
   int64_t* l1_dev;
@@ -198,10 +214,12 @@ size_t lider_search_workspace(const lider_index* index, int64_t nq, int32_t k, i
                               int32_t r, const lider_search_opts* opts);
 
 /* Batched search (Section 3.3.2): queries_dev [nq x d] fp32.  For each query:
- * E2LSH digits of both layers; the centroids retriever's key, RMI location and
+ * hash digits of both layers; the centroids retriever's key, RMI location and
  * window of r1 centroids, scored by inner product, top c clusters; in each
  * routed cluster the in-cluster retriever's key, RMI location and window of r
  * rows; exact inner-product scores of all window rows; top k over the union.
+ * With H hashkey arrays every array contributes its own window in both layers
+ * and the candidates of a core model are the union of its H windows.
  * Outputs ids_dev [nq x k] int64 (original row ids) and scores_dev [nq x k]
  * fp32, each row sorted by score descending, ties by smaller id, padded with
  * id -1 / score -inf.  ws_dev must hold lider_search_workspace(...) bytes (256-
@@ -228,27 +246,30 @@ typedef struct {
   int64_t max_cluster;      /* largest cluster size */
   double w;
   int32_t storage, centroid_storage;
+  int32_t n_arrays;         /* hashkey arrays per core model */
 } lider_info;
 
 int lider_get_info(const lider_index* index, lider_info* out);
 
-/* Exportable index arrays (host copies, synchronous). */
+/* Exportable index arrays (host copies, synchronous).  Per-array tables are
+ * array-major (array h's block follows array h-1's); H = n_arrays.  The
+ * reordered corpus and every "sorted position" of a search are array 0's. */
 typedef enum {
   LIDER_X_CENTROIDS = 0,  /* [C x d] fp32, cluster-id order */
   LIDER_X_ASSIGN = 1,     /* [n] int32 cluster of each original row */
   LIDER_X_OFFSETS = 2,    /* [C+1] int64 first sorted position of each cluster */
-  LIDER_X_PERM = 3,       /* [n] int64 sorted position -> original row id */
-  LIDER_X_KEYS = 4,       /* [n] uint64 key at each sorted position */
-  LIDER_X_DIGITS = 5,     /* [n x m] int32 layer-2 digits per original row */
-  LIDER_X_L1_ORDER = 6,   /* [C] int64 layer-1 sorted position -> cluster id */
-  LIDER_X_L1_KEYS = 7,    /* [C] uint64 */
-  LIDER_X_L1_DIGITS = 8,  /* [C x m] int32 layer-1 digits per cluster id */
-  LIDER_X_MODEL_INT = 9,  /* [(C+1) x 3] int64: L, m_eff, F; model C = layer 1 */
-  LIDER_X_MODEL_BOX = 10, /* [(C+1) x 2m] int32: mins[m], maxs[m] */
-  LIDER_X_MODEL_KEY = 11, /* [(C+1) x 2] uint64: kmin, kmax */
-  LIDER_X_MODEL_DBL = 12, /* [(C+1) x 3] double: scale, root slope, root intercept */
-  LIDER_X_LEAVES = 13,    /* [C*F2 + F1] x 2 double: leaf slope, intercept */
-  LIDER_X_LEAF_ERR = 14,  /* [C*F2 + F1] x 2 int32: min and max (true - predicted) */
+  LIDER_X_PERM = 3,       /* [H x n] int64 sorted position -> original row id */
+  LIDER_X_KEYS = 4,       /* [H x n] uint64 key at each sorted position */
+  LIDER_X_DIGITS = 5,     /* [H x n x m] int32 layer-2 digits per original row */
+  LIDER_X_L1_ORDER = 6,   /* [H x C] int64 layer-1 sorted position -> cluster id */
+  LIDER_X_L1_KEYS = 7,    /* [H x C] uint64 */
+  LIDER_X_L1_DIGITS = 8,  /* [H x C x m] int32 layer-1 digits per cluster id */
+  LIDER_X_MODEL_INT = 9,  /* [H x (C+1) x 3] int64: L, m_eff, F; model C = layer 1 */
+  LIDER_X_MODEL_BOX = 10, /* [H x (C+1) x 2m] int32: mins[m], maxs[m] */
+  LIDER_X_MODEL_KEY = 11, /* [H x (C+1) x 2] uint64: kmin, kmax */
+  LIDER_X_MODEL_DBL = 12, /* [H x (C+1) x 3] double: scale, root slope, root intercept */
+  LIDER_X_LEAVES = 13,    /* [H x (C*F2 + F1)] x 2 double: leaf slope, intercept */
+  LIDER_X_LEAF_ERR = 14,  /* [H x (C*F2 + F1)] x 2 int32: min and max (true - predicted) */
   LIDER_X_REORDERED = 15  /* [n x d] fp32 corpus in sorted order */
 } lider_export_what;
 
@@ -260,7 +281,7 @@ int lider_export(const lider_index* index, int32_t what, void* dst_host, size_t 
 /* ------------------------------------------------------- stand-alone kernels */
 
 /* E2LSH digits (Section 4): out_dev[r*nh + i] = floor((A[i].X[r] + b[i]) / w)
- * for X_dev [n x d], A_dev [nh x d], b_dev [nh] (all fp32, device), nh in 1..32.
+ * for X_dev [n x d], A_dev [nh x d], b_dev [nh] (all fp32, device), nh in 1..512.
  * Projections run on fp32 MFMA; values within the rounding-error band of a
  * bucket edge are recomputed sequentially in FP64, so the digits equal the
  * FP64 definition exactly.  Allocates a temporary device list; synchronises

@@ -42,7 +42,7 @@ void free_device(Index& ix) {
                   ix.l1_digits, ix.A,        ix.b,        ix.anorm,     ix.cent_norm_max,
                   ix.models, ix.leaves,      ix.leaf_err, ix.tiles[0],  ix.tiles[1],
                   ix.tiles[2], ix.l1_tiles,  ix.tile_base[0], ix.tile_base[1],
-                  ix.tile_base[2]};
+                  ix.tile_base[2], ix.amap,  ix.l1map};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -107,6 +107,8 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
     return set_error(LIDER_EINVAL, "centroid_storage must be LIDER_F32 or LIDER_FP8E4M3");
   if (P->kmeans_seeding != 0 && P->kmeans_seeding != 1)
     return set_error(LIDER_EINVAL, "kmeans_seeding must be 0 or 1");
+  if (P->n_arrays < 0 || P->n_arrays > LIDER_MAX_H)
+    return set_error(LIDER_EINVAL, "n_arrays must be in 0..16");
   if (!P->assignment_dev)
     for (int32_t j = 0; j < (P->kmeans_seeding ? 1 : P->n_clusters); ++j)
       if (P->kmeans_init_host[j] < 0 || P->kmeans_init_host[j] >= n)
@@ -123,6 +125,7 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
   ix.F1 = P->rmi_fanout_l1 > 0 ? P->rmi_fanout_l1 : P->rmi_fanout;
   ix.w = sign ? 1.0 : P->w;
   ix.hash_kind = P->hash_kind;
+  ix.H = P->n_arrays > 0 ? P->n_arrays : 1;
   ix.storage = P->storage;
   ix.centroid_storage = P->centroid_storage;
   (void)hipGetDevice(&ix.device);
@@ -131,8 +134,8 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
     if (hipGetDeviceProperties(&prop, ix.device) == hipSuccess && prop.multiProcessorCount > 0)
       ix.n_cu = prop.multiProcessorCount;
   }
-  const int64_t C = ix.C, m = ix.m;
-  const int64_t nleaf = C * ix.F2 + ix.F1;
+  const int64_t C = ix.C, m = ix.m, H = ix.H;
+  const int64_t nleaf = H * (C * ix.F2 + ix.F1);
   int rc = LIDER_OK;
 #define TRY(x)                 \
   do {                         \
@@ -140,10 +143,14 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
   } while (0)
   TRY(alloc(&ix.X, size_t(n) * d, "reordered corpus"));
   if (ix.storage == LIDER_BF16) TRY(alloc(&ix.Xb, size_t(n) * d, "bf16 corpus"));
-  TRY(alloc(&ix.perm, size_t(n), "perm"));
+  TRY(alloc(&ix.perm, size_t(H) * n, "perm"));
   TRY(alloc(&ix.perm32, size_t(n), "perm32"));
-  TRY(alloc(&ix.keys, size_t(n), "keys"));
-  TRY(alloc(&ix.digits, size_t(n) * m, "digits"));
+  TRY(alloc(&ix.keys, size_t(H) * n, "keys"));
+  TRY(alloc(&ix.digits, size_t(H) * n * m, "digits"));
+  if (H > 1) {
+    TRY(alloc(&ix.amap, size_t(H - 1) * n, "array position maps"));
+    TRY(alloc(&ix.l1map, size_t(H - 1) * C, "layer-1 array position maps"));
+  }
   TRY(alloc(&ix.assign, size_t(n), "assignment"));
   TRY(alloc(&ix.off, size_t(C) + 1, "offsets"));
   TRY(alloc(&ix.cent, size_t(C) * d, "centroids"));
@@ -153,26 +160,27 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
     TRY(alloc(&ix.cent8_scale, size_t(C), "fp8 scales"));
   }
   if (d % 8 == 0) TRY(alloc(&ix.cent_l1_b, size_t(C) * d, "bf16 layer-1 centroids"));
-  TRY(alloc(&ix.l1_order, size_t(C), "layer-1 order"));
+  TRY(alloc(&ix.l1_order, size_t(H) * C, "layer-1 order"));
   TRY(alloc(&ix.l1_order32, size_t(C), "layer-1 order"));
-  TRY(alloc(&ix.l1_keys, size_t(C), "layer-1 keys"));
-  TRY(alloc(&ix.l1_digits, size_t(C) * m, "layer-1 digits"));
-  TRY(alloc(&ix.A, size_t(2 * m) * d, "LSH projections"));
-  TRY(alloc(&ix.b, size_t(2 * m), "LSH offsets"));
-  TRY(alloc(&ix.anorm, size_t(2 * m), "LSH norms"));
+  TRY(alloc(&ix.l1_keys, size_t(H) * C, "layer-1 keys"));
+  TRY(alloc(&ix.l1_digits, size_t(H) * C * m, "layer-1 digits"));
+  const int64_t nh = 2 * H * m;
+  TRY(alloc(&ix.A, size_t(nh) * d, "LSH projections"));
+  TRY(alloc(&ix.b, size_t(nh), "LSH offsets"));
+  TRY(alloc(&ix.anorm, size_t(nh), "LSH norms"));
   TRY(alloc(&ix.cent_norm_max, 64, "centroid norm"));
-  TRY(alloc(&ix.models, size_t(C) + 1, "models"));
+  TRY(alloc(&ix.models, size_t(H) * (C + 1), "models"));
   TRY(alloc(&ix.leaves, size_t(nleaf) * 2, "leaves"));
   TRY(alloc(&ix.leaf_err, size_t(nleaf) * 2, "leaf errors"));
-  TRY(check_hip(hipMemcpyAsync(ix.A, P->lsh_a_host, size_t(2 * m) * d * 4, hipMemcpyHostToDevice, st),
+  TRY(check_hip(hipMemcpyAsync(ix.A, P->lsh_a_host, size_t(nh) * d * 4, hipMemcpyHostToDevice, st),
                 "copy LSH projections"));
   if (P->lsh_b_host)
-    TRY(check_hip(hipMemcpyAsync(ix.b, P->lsh_b_host, size_t(2 * m) * 4, hipMemcpyHostToDevice,
+    TRY(check_hip(hipMemcpyAsync(ix.b, P->lsh_b_host, size_t(nh) * 4, hipMemcpyHostToDevice,
                                  st),
                   "copy LSH offsets"));
   else
-    TRY(check_hip(hipMemsetAsync(ix.b, 0, size_t(2 * m) * 4, st), "clear LSH offsets"));
-  if (rc == LIDER_OK) launch_norm_bounds(ix.A, int32_t(2 * m), d, ix.anorm, st);
+    TRY(check_hip(hipMemsetAsync(ix.b, 0, size_t(nh) * 4, st), "clear LSH offsets"));
+  if (rc == LIDER_OK) launch_norm_bounds(ix.A, int32_t(nh), d, ix.anorm, st);
   if (rc == LIDER_OK) {
     if (P->assignment_dev) {
       // given clusters: copy, range-check, centroids = member means (empty: 0)
@@ -229,6 +237,7 @@ int lider_get_info(const lider_index* index, lider_info* out) {
   out->w = ix.w;
   out->storage = ix.storage;
   out->centroid_storage = ix.centroid_storage;
+  out->n_arrays = ix.H;
   return LIDER_OK;
 }
 
@@ -261,6 +270,9 @@ static int validate_search(const lider_index* index, const float* Q, int64_t nq,
     return set_error(LIDER_EINVAL, "expand_bits must be in 0..16");
   if (o.expand_bits > 0 && index->ix.hash_kind != LIDER_HASH_SIGN)
     return set_error(LIDER_EINVAL, "expand_bits needs an index built with LIDER_HASH_SIGN");
+  if (ix.H > 1 && ix.C > 65536 && std::min<int64_t>(o.r1 > 0 ? o.r1 : r, ix.C) < ix.C)
+    return set_error(LIDER_EINVAL,
+                     "with n_arrays > 1 and r1 < n_clusters, n_clusters must be at most 65536");
   if (nq > 0 && !Q) return set_error(LIDER_EINVAL, "queries pointer is NULL");
   return LIDER_OK;
 }
@@ -354,21 +366,22 @@ struct ExportSrc {
 
 ExportSrc export_src(const Index& ix, int32_t what) {
   const size_t n = size_t(ix.n), d = size_t(ix.d), C = size_t(ix.C), m = size_t(ix.m);
-  const size_t nleaf = C * ix.F2 + ix.F1;
+  const size_t H = size_t(ix.H);
+  const size_t nleaf = H * (C * ix.F2 + ix.F1), nm = H * (C + 1);
   switch (what) {
     case LIDER_X_CENTROIDS: return {ix.cent, C * d * 4, 0};
     case LIDER_X_ASSIGN: return {ix.assign, n * 4, 0};
     case LIDER_X_OFFSETS: return {ix.off, (C + 1) * 8, 0};
-    case LIDER_X_PERM: return {ix.perm, n * 8, 0};
-    case LIDER_X_KEYS: return {ix.keys, n * 8, 0};
-    case LIDER_X_DIGITS: return {ix.digits, n * m * 4, 0};
-    case LIDER_X_L1_ORDER: return {ix.l1_order, C * 8, 0};
-    case LIDER_X_L1_KEYS: return {ix.l1_keys, C * 8, 0};
-    case LIDER_X_L1_DIGITS: return {ix.l1_digits, C * m * 4, 0};
-    case LIDER_X_MODEL_INT: return {ix.models, (C + 1) * 3 * 8, 1};
-    case LIDER_X_MODEL_BOX: return {ix.models, (C + 1) * 2 * m * 4, 2};
-    case LIDER_X_MODEL_KEY: return {ix.models, (C + 1) * 2 * 8, 3};
-    case LIDER_X_MODEL_DBL: return {ix.models, (C + 1) * 3 * 8, 4};
+    case LIDER_X_PERM: return {ix.perm, H * n * 8, 0};
+    case LIDER_X_KEYS: return {ix.keys, H * n * 8, 0};
+    case LIDER_X_DIGITS: return {ix.digits, H * n * m * 4, 0};
+    case LIDER_X_L1_ORDER: return {ix.l1_order, H * C * 8, 0};
+    case LIDER_X_L1_KEYS: return {ix.l1_keys, H * C * 8, 0};
+    case LIDER_X_L1_DIGITS: return {ix.l1_digits, H * C * m * 4, 0};
+    case LIDER_X_MODEL_INT: return {ix.models, nm * 3 * 8, 1};
+    case LIDER_X_MODEL_BOX: return {ix.models, nm * 2 * m * 4, 2};
+    case LIDER_X_MODEL_KEY: return {ix.models, nm * 2 * 8, 3};
+    case LIDER_X_MODEL_DBL: return {ix.models, nm * 3 * 8, 4};
     case LIDER_X_LEAVES: return {ix.leaves, nleaf * 2 * 8, 0};
     case LIDER_X_LEAF_ERR: return {ix.leaf_err, nleaf * 2 * 4, 0};
     case LIDER_X_REORDERED: return {ix.X, n * d * 4, 0};
@@ -391,7 +404,7 @@ int lider_export(const lider_index* index, int32_t what, void* dst_host, size_t 
   if (dst_bytes < src.bytes) return set_error(LIDER_EINVAL, "destination too small");
   if (src.kind == 0)
     return check_hip(hipMemcpy(dst_host, src.dev, src.bytes, hipMemcpyDeviceToHost), "export");
-  std::vector<Model> M(size_t(ix.C) + 1);
+  std::vector<Model> M(size_t(ix.H) * (size_t(ix.C) + 1));
   int rc = check_hip(hipMemcpy(M.data(), ix.models, M.size() * sizeof(Model), hipMemcpyDeviceToHost),
                      "export models");
   if (rc != LIDER_OK) return rc;
@@ -426,7 +439,7 @@ int lider_hash(const float* X_dev, int64_t n, int32_t d, const float* A_dev, con
                int32_t nh, double w, int32_t* out_dev, void* stream) {
   g_err.clear();
   if (!X_dev || !A_dev || !b_dev || !out_dev) return set_error(LIDER_EINVAL, "NULL argument");
-  if (n < 0 || d < 1 || nh < 1 || nh > 32 || !(w > 0.0))
+  if (n < 0 || d < 1 || nh < 1 || nh > 512 || !(w > 0.0))
     return set_error(LIDER_EINVAL, "bad size argument");
   if (n == 0) return LIDER_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -390,40 +390,82 @@ __global__ void cent_norm_max_kernel(const float* __restrict__ cent, int32_t C, 
   if (lane == 0) atomicMax(maxbits, __float_as_uint(float(sqrt(s) * (1.0 + 9.5367431640625e-07))));
 }
 
+// Position maps between hashkey arrays: inv[perm0[p]] = p, then
+// map[p] = inv[permh[p]] (array h's sorted position -> array 0's).
+__global__ void inverse_kernel(const int64_t* __restrict__ perm, int64_t n,
+                               int32_t* __restrict__ inv) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += int64_t(gridDim.x) * blockDim.x)
+    inv[perm[t]] = int32_t(t);
+}
+
+__global__ void compose_kernel(const int64_t* __restrict__ permh, int64_t n,
+                               const int32_t* __restrict__ inv, int32_t* __restrict__ map) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += int64_t(gridDim.x) * blockDim.x)
+    map[t] = inv[permh[t]];
+}
+
 }  // namespace
 
-// Everything after the clustering: layer-2 digits and models over the corpus,
-// the reordered corpus, layer-1 digits and model over the centroids.
+// Everything after the clustering, for each hashkey array h: layer-2 digits
+// and models over the corpus, layer-1 digits and model over the centroids;
+// the corpus and centroids reordered by array 0's order, and the maps from
+// the other arrays' positions to array 0's.
 int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
   const int64_t n = ix.n;
-  const int32_t d = ix.d, C = ix.C, m = ix.m;
+  const int32_t d = ix.d, C = ix.C, m = ix.m, H = ix.H;
   Bufs B;
-  int64_t* list = B.get<int64_t>(size_t(n) * m);
+  int64_t* list = B.get<int64_t>(size_t(std::max<int64_t>(n, C)) * m);
   int32_t* cs = B.get<int32_t>(64);  // [0] counter, [1] status
   int64_t* l1off = B.get<int64_t>(2);
-  if (!list || !cs || !l1off) return set_error(LIDER_ENOMEM, "out of device memory (hash list)");
+  int32_t* inv = H > 1 ? B.get<int32_t>(size_t(n)) : nullptr;
+  int32_t* inv1 = H > 1 ? B.get<int32_t>(size_t(C)) : nullptr;
+  if (!list || !cs || !l1off || (H > 1 && (!inv || !inv1)))
+    return set_error(LIDER_ENOMEM, "out of device memory (hash list)");
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, cs, int64_t(64), 0);
   const bool binary = ix.hash_kind == LIDER_HASH_SIGN;
-  int rc = run_hash_ex(Xin, n, d, ix.A + size_t(m) * d, ix.b + m, ix.anorm + m, m, ix.w,
-                       ix.digits, list, cs, cs + 1, 0, nullptr, st, ix.hash_kind);
-  if (rc != LIDER_OK) return rc;
-  rc = build_layer(ix.digits, m, ix.assign, n, C, ix.F2, ix.models, 0, ix.leaves, ix.leaf_err,
-                   ix.perm, ix.keys, ix.off, binary, st);
-  if (rc != LIDER_OK) return rc;
+  const int64_t nleaf = int64_t(C) * ix.F2 + ix.F1;  // leaves of one array
+  int rc = LIDER_OK;
+  for (int32_t h = 0; h < H; ++h) {
+    const size_t r2 = size_t(H) * m + size_t(h) * m;  // layer-2 hash rows of array h
+    int32_t* dig = ix.digits + size_t(h) * n * m;
+    rc = run_hash_ex(Xin, n, d, ix.A + r2 * d, ix.b + r2, ix.anorm + r2, m, ix.w, dig, list, cs,
+                     cs + 1, 0, nullptr, st, ix.hash_kind);
+    if (rc != LIDER_OK) return rc;
+    rc = build_layer(dig, m, ix.assign, n, C, ix.F2, ix.models + size_t(h) * (C + 1),
+                     int64_t(h) * nleaf, ix.leaves, ix.leaf_err, ix.perm + size_t(h) * n,
+                     ix.keys + size_t(h) * n, ix.off, binary, st);
+    if (rc != LIDER_OK) return rc;
+    // layer 1: the centroids retriever
+    const size_t r1 = size_t(h) * m;
+    int32_t* dg1 = ix.l1_digits + size_t(h) * C * m;
+    rc = run_hash_ex(ix.cent, C, d, ix.A + r1 * d, ix.b + r1, ix.anorm + r1, m, ix.w, dg1, list,
+                     cs, cs + 1, 0, nullptr, st, ix.hash_kind);
+    if (rc != LIDER_OK) return rc;
+    rc = build_layer(dg1, m, nullptr, C, 1, ix.F1, ix.models + size_t(h) * (C + 1) + C,
+                     int64_t(h) * nleaf + int64_t(C) * ix.F2, ix.leaves, ix.leaf_err,
+                     ix.l1_order + size_t(h) * C, ix.l1_keys + size_t(h) * C, l1off, binary, st);
+    if (rc != LIDER_OK) return rc;
+  }
   {
     const int64_t blocks = std::min<int64_t>((n + 3) / 4, 65536);
     hipLaunchKernelGGL(reorder_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, Xin, d, ix.perm,
                        n, ix.X, ix.Xb, ix.perm32);
   }
-  // layer 1: the centroids retriever
-  rc = run_hash_ex(ix.cent, C, d, ix.A, ix.b, ix.anorm, m, ix.w, ix.l1_digits, list, cs, cs + 1, 0,
-                   nullptr, st, ix.hash_kind);
-  if (rc != LIDER_OK) return rc;
-  rc = build_layer(ix.l1_digits, m, nullptr, C, 1, ix.F1, ix.models + C, int64_t(C) * ix.F2,
-                   ix.leaves, ix.leaf_err, ix.l1_order, ix.l1_keys, l1off, binary, st);
-  if (rc != LIDER_OK) return rc;
   hipLaunchKernelGGL(reorder_kernel, dim3(unsigned((C + 3) / 4)), dim3(256), 0, st, ix.cent, d,
                      ix.l1_order, int64_t(C), ix.cent_l1, (__hip_bfloat16*)nullptr, ix.l1_order32);
+  if (H > 1) {
+    hipLaunchKernelGGL(inverse_kernel, dim3(1024), dim3(256), 0, st, ix.perm, n, inv);
+    hipLaunchKernelGGL(inverse_kernel, dim3(64), dim3(256), 0, st, ix.l1_order, int64_t(C), inv1);
+    for (int32_t h = 1; h < H; ++h) {
+      hipLaunchKernelGGL(compose_kernel, dim3(1024), dim3(256), 0, st, ix.perm + size_t(h) * n, n,
+                         inv, ix.amap + size_t(h - 1) * n);
+      hipLaunchKernelGGL(compose_kernel, dim3(64), dim3(256), 0, st,
+                         ix.l1_order + size_t(h) * C, int64_t(C), inv1,
+                         ix.l1map + size_t(h - 1) * C);
+    }
+  }
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, reinterpret_cast<int32_t*>(ix.cent_norm_max),
                      int64_t(1), 0);
   hipLaunchKernelGGL(cent_norm_max_kernel, dim3((C + 3) / 4), dim3(256), 0, st, ix.cent, C, d,
@@ -449,6 +491,8 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
   ix.max_cluster = 0;
   for (int32_t j = 0; j < C; ++j)
     ix.max_cluster = std::max<int64_t>(ix.max_cluster, ix.h_off[j + 1] - ix.h_off[j]);
+  if (H > 1 && ix.max_cluster > kMaxMultiCluster)
+    return set_error(LIDER_EINVAL, "with n_arrays > 1 no cluster may hold more than 65536 rows");
   // rerank tile tables for 32/64/128-row tiles, 4 int32 per tile: cluster,
   // first in-cluster row, first row in the reordered corpus, rows in the tile
   const int sizes[3] = {32, 64, 128};

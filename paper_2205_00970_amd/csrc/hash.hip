@@ -14,8 +14,8 @@
 
 namespace lider {
 
-// Projection kernel.  Block = 4 waves = 16 rows; the waves split the
-// dimension range (wave w owns a contiguous quarter of the 16-dimension
+// Projection kernel.  Block = 4 waves = 16 rows x (up to) 32 hashes, the
+// hashes [32 y, 32 y + 32) of grid row y; the waves split the dimension range (wave w owns a contiguous quarter of the 16-dimension
 // steps).  Lane l of a wave owns row / hash (l % 16) and the dimension slot
 // s = l / 16: per step it loads 4 consecutive dims [k0 + 4s, k0 + 4s + 4) of
 // its row and of its hash vector and feeds them to 4 MFMAs (the k index of an
@@ -35,11 +35,13 @@ __global__ __launch_bounds__(256) void hash_kernel(
   int64_t myrow = row0 + i;
   if (myrow >= n) myrow = n - 1;  // keep loads in bounds; outputs are skipped
   const float* xr = X + myrow * d;
-  const int h0 = i < nh ? i : nh - 1;
-  const int h1 = 16 + i < nh ? 16 + i : nh - 1;
+  const int hb = int(blockIdx.y) * 32;  // first hash of this block
+  const int nhc = min(32, nh - hb);     // hashes of this block
+  const int h0 = hb + (i < nhc ? i : nhc - 1);
+  const int h1 = hb + (16 + i < nhc ? 16 + i : nhc - 1);
   const float* a0 = A + int64_t(h0) * d;
   const float* a1 = A + int64_t(h1) * d;
-  const bool two = nh > 16;
+  const bool two = nhc > 16;
   floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
   float ss = 0.f;
   const int nk = (d + 15) / 16;
@@ -82,12 +84,12 @@ __global__ __launch_bounds__(256) void hash_kernel(
   __syncthreads();
   const double coef = dot_err_coef(d);
   const double gam = double(d + 2) * 5.9604644775390625e-08;
-  for (int o = threadIdx.x; o < 16 * nh; o += 256) {
-    const int ri = o / nh, hash = o - ri * nh;
+  for (int o = threadIdx.x; o < 16 * nhc; o += 256) {
+    const int ri = o / nhc, hl = o - ri * nhc, hash = hb + hl;
     const int64_t row = row0 + ri;
     if (row >= n) continue;
     const float ssr = ((pss[0][ri] + pss[1][ri]) + pss[2][ri]) + pss[3][ri];
-    const float sv = ((part[0][hash][ri] + part[1][hash][ri]) + part[2][hash][ri]) + part[3][hash][ri];
+    const float sv = ((part[0][hl][ri] + part[1][hl][ri]) + part[2][hl][ri]) + part[3][hl][ri];
     const double xn = sqrt(double(ssr) * (1.0 + 2.0 * gam)) * (1.0 + 9.5367431640625e-07);
     if (rownorm && hash == 0) rownorm[row] = float(xn * (1.0 + 9.5367431640625e-07));
     const int64_t oi = row * nh + hash;
@@ -233,7 +235,7 @@ int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const floa
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, counter, int64_t(1));
   const bool vec = (d % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-  const dim3 grid(unsigned((n + 15) / 16));
+  const dim3 grid(unsigned((n + 15) / 16), unsigned((nh + 31) / 32));
   if (vec)
     hipLaunchKernelGGL(hash_kernel<true>, grid, dim3(256), 0, st, X, n, d, A, b, anorm, nh, w,
                        out, list, counter, status, clamp, rownorm, kind);

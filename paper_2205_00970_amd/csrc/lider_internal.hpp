@@ -34,6 +34,10 @@ struct alignas(16) Model {
 
 static constexpr uint64_t kKeyLimit = uint64_t(1) << 53;
 
+// Largest cluster of a multi-array index: the union of a (query, cluster)
+// pair's windows is marked in a per-wave bitmap of this many bits.
+static constexpr int64_t kMaxMultiCluster = 65536;
+
 // Mixed-radix key of a data tuple over the model's digit box (Section 5.1
 // first step, generalised from binary digits to integer digits); digit 0 is
 // the most significant, so numeric order is the element-wise SK-LSH order.
@@ -153,14 +157,19 @@ struct Index {
   int64_t max_cluster = 0;
   int32_t storage = LIDER_F32, centroid_storage = LIDER_F32;
   int32_t hash_kind = LIDER_HASH_E2LSH;
+  int32_t H = 1;               // hashkey arrays per core model
   int32_t n_cu = 256;
 
-  float* X = nullptr;          // [n x d] reordered by (cluster, key, id)
+  // Per-array tables are array-major; array 0's sort order is the physical
+  // row order (the reordered corpus, tiles, search positions).
+  float* X = nullptr;          // [n x d] reordered by array 0's (cluster, key, id)
   __hip_bfloat16* Xb = nullptr;  // [n x d] bf16 copy (precision form)
-  int64_t* perm = nullptr;     // [n] sorted position -> original id
-  int32_t* perm32 = nullptr;   // [n] same, int32
-  uint64_t* keys = nullptr;    // [n]
-  int32_t* digits = nullptr;   // [n x m] per original id
+  int64_t* perm = nullptr;     // [H x n] sorted position of array h -> original id
+  int32_t* perm32 = nullptr;   // [n] array 0's, int32
+  uint64_t* keys = nullptr;    // [H x n]
+  int32_t* digits = nullptr;   // [H x n x m] per original id
+  int32_t* amap = nullptr;     // [(H-1) x n] array h's sorted position -> array 0's
+  int32_t* l1map = nullptr;    // [(H-1) x C] same for the centroids retriever
   int32_t* assign = nullptr;   // [n] per original id
   int64_t* off = nullptr;      // [C+1]
   float* cent = nullptr;       // [C x d] cluster-id order
@@ -168,17 +177,17 @@ struct Index {
   uint8_t* cent8 = nullptr;    // [C x d] fp8 e4m3, layer-1 order
   float* cent8_scale = nullptr;  // [C]
   __hip_bfloat16* cent_l1_b = nullptr;  // [C x d] bf16 copy of cent_l1 (routing candidates)
-  int64_t* l1_order = nullptr;   // [C] layer-1 position -> cluster id
-  int32_t* l1_order32 = nullptr;
-  uint64_t* l1_keys = nullptr;
-  int32_t* l1_digits = nullptr;  // [C x m]
-  float* A = nullptr;          // [2m x d]
-  float* b = nullptr;          // [2m]
-  float* anorm = nullptr;      // [2m] upper bounds of |A_i|
+  int64_t* l1_order = nullptr;   // [H x C] layer-1 position of array h -> cluster id
+  int32_t* l1_order32 = nullptr; // [C] array 0's
+  uint64_t* l1_keys = nullptr;   // [H x C]
+  int32_t* l1_digits = nullptr;  // [H x C x m]
+  float* A = nullptr;          // [2Hm x d]: layer-1 sets of arrays 0..H-1, then layer 2
+  float* b = nullptr;          // [2Hm]
+  float* anorm = nullptr;      // [2Hm] upper bounds of |A_i|
   float* cent_norm_max = nullptr;  // [1] upper bound of max |centroid|
-  Model* models = nullptr;     // [C+1], model C = layer 1
-  double* leaves = nullptr;    // [(C*F2 + F1) x 2]
-  int32_t* leaf_err = nullptr; // [(C*F2 + F1) x 2]
+  Model* models = nullptr;     // [H x (C+1)], model h*(C+1) + C = array h of layer 1
+  double* leaves = nullptr;    // [H x (C*F2 + F1) x 2]
+  int32_t* leaf_err = nullptr; // [H x (C*F2 + F1) x 2]
   // rerank tiles: (cluster, first row) of every tile of tile_rows rows, one
   // table per supported tile size (32, 64, 128)
   int32_t n_tiles[3] = {0, 0, 0};

@@ -41,8 +41,13 @@ constexpr int kCtrWords = 64;
 
 struct Plan {
   size_t o_ctr, o_qdig, o_hlist, o_qnorm, o_l1, o_l1p, o_l1cs, o_rs, o_rs64, o_routed, o_pairs,
-      o_ccount, o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, o_aflag, o_alist, o_kq, total;
+      o_ccount, o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, o_aflag, o_alist, o_kq, o_rsd,
+      o_lst, o_rw, o_pw, o_mask, total;
   int32_t r1, rcap, S;
+  // several hashkey arrays: lcap = layer-1 union capacity per query (list
+  // mode when r1 < C), mw = mask words per (query, cluster) pair
+  bool l1_list;
+  int32_t lcap, mw;
 };
 
 // Rerank tile table in use: 0/1/2 = 32/64/128 rows per tile.  Default: 128
@@ -57,10 +62,17 @@ int tile_index(const Index& ix, const lider_search_opts& o) {
 Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
                const lider_search_opts& o) {
   Plan p;
+  const int32_t H = ix.H;
   const int32_t r1 = int32_t(std::min<int64_t>(o.r1 > 0 ? o.r1 : r, ix.C));
-  const int32_t rcap = int32_t(std::max<int64_t>(1, std::min<int64_t>(r, ix.max_cluster)));
+  // several arrays: a pair's candidates span up to its whole cluster
+  const int32_t rcap = int32_t(std::max<int64_t>(
+      1, H > 1 ? ix.max_cluster : std::min<int64_t>(r, ix.max_cluster)));
   const int32_t mult = o.shortlist_mult > 0 ? o.shortlist_mult : 4;
   const int32_t S = o.precision == LIDER_BF16 ? std::min(4096, mult * k) : 0;
+  p.l1_list = H > 1 && r1 < ix.C;
+  p.lcap = p.l1_list ? int32_t(std::min<int64_t>(ix.C, int64_t(H) * r1)) : r1;
+  p.mw = H > 1 ? int32_t((ix.max_cluster + 127) / 128 * 4) : 0;
+  const int64_t np = nq * c;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t at = off;
@@ -68,14 +80,19 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
     return at;
   };
   p.o_ctr = take(kCtrWords * 4);
-  p.o_qdig = take(size_t(nq) * 2 * ix.m * 4);
-  p.o_hlist = take(size_t(nq) * 2 * ix.m * 8);
+  p.o_qdig = take(size_t(nq) * 2 * H * ix.m * 4);
+  p.o_hlist = take(size_t(nq) * 2 * H * ix.m * 8);
   p.o_qnorm = take(size_t(nq) * 4);
-  p.o_l1 = take(size_t(nq) * 3 * 4);
-  p.o_l1p = take(size_t(nq) * sizeof(Pair));
+  p.o_l1 = take(size_t(nq) * H * 3 * 4);
+  p.o_l1p = take(size_t(nq) * H * sizeof(Pair));
   p.o_l1cs = take(2 * 4);
-  p.o_rs = take(size_t(nq) * r1 * 4);
-  p.o_rs64 = take(size_t(nq) * r1 * 8);
+  p.o_rs = take(size_t(nq) * p.lcap * 4);
+  p.o_rs64 = take(size_t(nq) * p.lcap * 8);
+  p.o_rsd = take(p.l1_list ? size_t(nq) * ix.C * 4 : 0);
+  p.o_lst = take(p.l1_list ? size_t(nq) * p.lcap * 4 : 0);
+  p.o_rw = take(p.l1_list ? size_t(nq) * 3 * 4 : 0);
+  p.o_pw = take(H > 1 ? size_t(np) * H * sizeof(Pair) : 0);
+  p.o_mask = take(H > 1 ? size_t(np) * p.mw * 4 : 0);
   p.o_routed = take(size_t(nq) * c * 4);
   p.o_pairs = take(size_t(nq) * c * sizeof(Pair));
   p.o_ccount = take(size_t(ix.C) * 4);
@@ -89,7 +106,7 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   const size_t nt = o.persistent == 2 ? size_t(ix.n_tiles[ti]) : 0;
   p.o_aflag = take(nt * 4);
   p.o_alist = take(nt * 4);
-  p.o_kq = take(o.expand_bits > 0 ? size_t(nq) * std::max<int32_t>(c, 1) * 8 : 0);
+  p.o_kq = take(o.expand_bits > 0 ? size_t(nq) * std::max<int32_t>(c, 1) * H * 8 : 0);
   p.total = off;
   p.r1 = r1;
   p.rcap = rcap;
@@ -290,25 +307,87 @@ __host__ __device__ inline int pow2_at_least(int v) {
 // written as a (cluster 0, start, length) pair so the tile-scoring kernel can
 // score layer 1 exactly like a cluster of C rows.
 // kq (nullable) receives each query's layer-1 key for the dist_e expansion.
+// One thread per (query, array) item t = q H + h: array h's model, digits and
+// window.
 __global__ void l1_kernel(const Model* __restrict__ models, const double* __restrict__ leaves,
-                          const int32_t* __restrict__ qdig, int32_t m, int64_t nq, int32_t C,
-                          int32_t r1, int32_t* __restrict__ l1, Pair* __restrict__ l1pairs,
-                          int32_t* __restrict__ l1cs, uint64_t* __restrict__ kq) {
-  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q == 0) {
+                          const int32_t* __restrict__ qdig, int32_t m, int32_t H, int64_t nq,
+                          int32_t C, int32_t r1, int32_t* __restrict__ l1,
+                          Pair* __restrict__ l1pairs, int32_t* __restrict__ l1cs,
+                          uint64_t* __restrict__ kq) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t == 0) {
     l1cs[0] = 0;
     l1cs[1] = int32_t(nq);
   }
-  if (q >= nq) return;
+  if (t >= nq * H) return;
+  const int64_t q = t / H;
+  const int32_t h = int32_t(t - q * H);
   uint64_t K = 0;
-  const int64_t pos = locate(models[C], leaves, qdig + q * 2 * m, &K);
+  const int64_t pos = locate(models[int64_t(h) * (C + 1) + C], leaves,
+                             qdig + q * 2 * H * m + int64_t(h) * m, &K);
   int64_t s, len;
   window_of(pos, r1, C, &s, &len);  // the expansion (if any) replaces s later
-  if (kq) kq[q] = K;
-  l1[3 * q] = int32_t(pos);
-  l1[3 * q + 1] = int32_t(s);
-  l1[3 * q + 2] = int32_t(len);
-  l1pairs[q] = Pair{0, int32_t(s), int32_t(len), int32_t(pos)};
+  if (kq) kq[t] = K;
+  l1[3 * t] = int32_t(pos);
+  l1[3 * t + 1] = int32_t(s);
+  l1[3 * t + 2] = int32_t(len);
+  l1pairs[t] = Pair{0, int32_t(s), int32_t(len), int32_t(pos)};
+}
+
+// Union of a query's H layer-1 windows, as ascending positions of array 0's
+// layer-1 order, with their dense scores gathered from rsd [nq x C]: one wave
+// per query marks the windows in an LDS bitmap of C bits (dynamic shared
+// memory, 4 waves x ceil(C/32) words), then lists the set bits in order.
+// rw[q] = (0, 0, union size) is the query's window in list form.
+__global__ __launch_bounds__(256) void l1_union_kernel(
+    const int32_t* __restrict__ l1, int32_t H, int64_t nq, int32_t C,
+    const int32_t* __restrict__ l1map, const float* __restrict__ rsd, int32_t lcap,
+    int32_t* __restrict__ lst, float* __restrict__ rs, int32_t* __restrict__ rw) {
+  extern __shared__ uint32_t bm_all[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int32_t W = (C + 31) / 32;
+  uint32_t* bm = bm_all + wave * W;
+  for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
+    for (int32_t w = lane; w < W; w += 64) bm[w] = 0;
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t h = 0; h < H; ++h) {
+      const int32_t s = l1[3 * (q * H + h) + 1], len = l1[3 * (q * H + h) + 2];
+      for (int32_t p = lane; p < len; p += 64) {
+        const int32_t pos = h == 0 ? s + p : l1map[int64_t(h - 1) * C + s + p];
+        atomicOr(&bm[pos >> 5], 1u << (pos & 31));
+      }
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    int32_t base = 0;
+    for (int32_t w0 = 0; w0 < W; w0 += 64) {
+      const int32_t w = w0 + lane;
+      uint32_t bits = w < W ? bm[w] : 0u;
+      const int32_t cw = __popc(bits);
+      int32_t incl = cw;  // inclusive prefix of the word counts over the lanes
+      for (int o = 1; o < 64; o <<= 1) {
+        const int32_t v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+      }
+      int32_t at = base + incl - cw;
+      while (bits) {
+        const int32_t pos = w * 32 + (__ffs(bits) - 1);
+        bits &= bits - 1;
+        lst[q * lcap + at] = pos;
+        rs[q * lcap + at] = rsd[q * C + pos];
+        ++at;
+      }
+      base += __shfl(incl, 63);
+    }
+    if (lane == 0) {
+      rw[3 * q] = 0;
+      rw[3 * q + 1] = 0;
+      rw[3 * q + 2] = base;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+  }
 }
 
 constexpr int kRouteNT = 256;
@@ -343,13 +422,15 @@ __device__ inline double route_err(int d, float qn, float cmax) {
 
 // FP64 decision of the routed set by one wave: sequential FP64 inner products
 // of every window centroid, then c rounds of (score desc, cluster id asc).
+// Window entry p is layer-1 position lq[p] when a list is given, else s1 + p.
 __device__ void route_fp64_wave(const float* __restrict__ qv, int32_t d,
                                 const float* __restrict__ cent_l1,
                                 const int32_t* __restrict__ l1_order32, int32_t s1, int32_t len1,
-                                int32_t c, double* __restrict__ r64, int32_t* __restrict__ out) {
+                                const int32_t* __restrict__ lq, int32_t c,
+                                double* __restrict__ r64, int32_t* __restrict__ out) {
   const int lane = threadIdx.x & 63;
   for (int p = lane; p < len1; p += 64) {
-    const float* mu = cent_l1 + int64_t(s1 + p) * d;
+    const float* mu = cent_l1 + int64_t(lq ? lq[p] : s1 + p) * d;
     double acc = 0.0;
     for (int l = 0; l < d; ++l) acc = acc + double(qv[l]) * double(mu[l]);
     r64[p] = acc;
@@ -362,7 +443,7 @@ __device__ void route_fp64_wave(const float* __restrict__ qv, int32_t d,
     for (int p = lane; p < len1; p += 64) {
       const double v = r64[p];
       if (v == -INFINITY) continue;  // already chosen
-      const int32_t id = l1_order32[s1 + p];
+      const int32_t id = l1_order32[lq ? lq[p] : s1 + p];
       if (bp < 0 || v > bv || (v == bv && id < bi)) {
         bv = v;
         bi = id;
@@ -389,19 +470,22 @@ __device__ void route_fp64_wave(const float* __restrict__ qv, int32_t d,
 
 // Routing, one wave per query (c + 1 <= 64): extract the c + 1 best window
 // scores by repeated wave minima of (key, position); if the c-th and
-// (c+1)-th are closer than the error band, decide in FP64.
+// (c+1)-th are closer than the error band, decide in FP64.  The query's window
+// is (l1[ws q + 1], l1[ws q + 2]); with a list (several arrays), window entry p
+// is layer-1 position lst[q r1 + p] and rs holds the listed centroids' scores.
 template <bool FP8>
 __global__ __launch_bounds__(256) void route_select_wave_kernel(
     const float* __restrict__ Q, int32_t d, int64_t nq, const float* __restrict__ cent_l1,
     const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
     const float* __restrict__ qnorm, const float* __restrict__ cent_norm_max, int32_t c,
     int32_t r1, const float* __restrict__ rs, double* __restrict__ rs64,
-    int32_t* __restrict__ routed) {
+    int32_t* __restrict__ routed, int32_t ws, const int32_t* __restrict__ lst) {
   __shared__ uint64_t ext[4][65];
   __shared__ int32_t chosen[4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
-    const int32_t s1 = l1[3 * q + 1], len1 = l1[3 * q + 2];
+    const int32_t s1 = l1[ws * q + 1], len1 = l1[ws * q + 2];
+    const int32_t* lq = lst ? lst + q * r1 : nullptr;
     const float* rsq = rs + q * r1;
     const int want = min(len1, c + 1);
     uint64_t prev = 0;
@@ -426,11 +510,12 @@ __global__ __launch_bounds__(256) void route_select_wave_kernel(
       amb = (sc - sn) <= 4.0 * route_err(d, qnorm[q], *cent_norm_max);
     }
     if (!amb) {
-      for (int t = lane; t < c; t += 64)
-        routed[q * c + t] =
-            t < min(got, c) ? l1_order32[s1 + int32_t(ext[wave][t] & 0xffffffffu)] : -1;
+      for (int t = lane; t < c; t += 64) {
+        const int32_t p = int32_t(ext[wave][t] & 0xffffffffu);
+        routed[q * c + t] = t < min(got, c) ? l1_order32[lq ? lq[p] : s1 + p] : -1;
+      }
     } else {
-      route_fp64_wave(Q + q * d, d, cent_l1, l1_order32, s1, len1, c, rs64 + q * r1,
+      route_fp64_wave(Q + q * d, d, cent_l1, l1_order32, s1, len1, lq, c, rs64 + q * r1,
                       chosen[wave]);
       for (int t = lane; t < c; t += 64) routed[q * c + t] = chosen[wave][t];
     }
@@ -457,7 +542,7 @@ __global__ __launch_bounds__(256) void route_refine_kernel(
     const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
     const float* __restrict__ qnorm, const float* __restrict__ cent_norm_max, double ecoef,
     int32_t c, int32_t r1, const float* __restrict__ rs, double* __restrict__ rs64,
-    int32_t* __restrict__ routed) {
+    int32_t* __restrict__ routed, int32_t ws) {
   __shared__ int32_t cand[4][64];
   __shared__ int32_t chosen[4][64];
   __shared__ double csc[4][64];
@@ -466,7 +551,7 @@ __global__ __launch_bounds__(256) void route_refine_kernel(
   const bool staged = d <= kRefineLds;
   const uint64_t below = (uint64_t(1) << lane) - 1;
   for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
-    const int32_t s1 = l1[3 * q + 1], len1 = l1[3 * q + 2];
+    const int32_t s1 = l1[ws * q + 1], len1 = l1[ws * q + 2];
     const float* rsq = rs + q * r1;
     float v[R > 0 ? R : 1];
     if (R > 0) {
@@ -534,7 +619,8 @@ __global__ __launch_bounds__(256) void route_refine_kernel(
       for (int u = 0; u < c; ++u) rank += __shfl(key, u) < key;
       if (lane < c) routed[q * c + rank] = l1_order32[s1 + p];
     } else if (n > 64) {
-      route_fp64_wave(qv, d, cent_l1, l1_order32, s1, len1, c, rs64 + q * r1, chosen[wave]);
+      route_fp64_wave(qv, d, cent_l1, l1_order32, s1, len1, nullptr, c, rs64 + q * r1,
+                      chosen[wave]);
       for (int t = lane; t < c; t += 64) routed[q * c + t] = chosen[wave][t];
     } else {
       // sequential FP64 dot products, one candidate at a time: the wave stages
@@ -587,7 +673,7 @@ __global__ __launch_bounds__(kRouteNT) void route_select_block_kernel(
     const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
     const float* __restrict__ qnorm, const float* __restrict__ cent_norm_max, int32_t c,
     int32_t r1, const float* __restrict__ rs, double* __restrict__ rs64,
-    int32_t* __restrict__ routed) {
+    int32_t* __restrict__ routed, int32_t ws, const int32_t* __restrict__ lst) {
   __shared__ SelShared sh;
   __shared__ uint64_t srt[256];
   __shared__ int32_t sidx[256];
@@ -595,13 +681,14 @@ __global__ __launch_bounds__(kRouteNT) void route_select_block_kernel(
   __shared__ int32_t chosen[LIDER_MAX_C];
   const int tid = threadIdx.x;
   for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
-    const int32_t s1 = l1[3 * q + 1], len1 = l1[3 * q + 2];
+    const int32_t s1 = l1[ws * q + 1], len1 = l1[ws * q + 2];
+    const int32_t* lq = lst ? lst + q * r1 : nullptr;
     const float* rsq = rs + q * r1;
     const int K = min(c + 1, len1);
     const int KP = pow2_at_least(K);
     block_select<kRouteNT>(
         len1, K, KP, [&](int i) { return score_key(rsq[i]); },
-        [&](int i) { return uint32_t(l1_order32[s1 + i]); }, srt, sidx, sh);
+        [&](int i) { return uint32_t(l1_order32[lq ? lq[i] : s1 + i]); }, srt, sidx, sh);
     if (tid == 0) {
       s_amb = 0;
       if (!FP8 && len1 > c) {
@@ -616,7 +703,8 @@ __global__ __launch_bounds__(kRouteNT) void route_select_block_kernel(
         routed[q * c + t] = t < len1 ? int32_t(srt[t] & 0xffffffffu) : -1;
     } else {
       if (tid < 64)
-        route_fp64_wave(Q + q * d, d, cent_l1, l1_order32, s1, len1, c, rs64 + q * r1, chosen);
+        route_fp64_wave(Q + q * d, d, cent_l1, l1_order32, s1, len1, lq, c, rs64 + q * r1,
+                        chosen);
       __syncthreads();
       for (int t = tid; t < c; t += kRouteNT) routed[q * c + t] = chosen[t];
     }
@@ -625,26 +713,88 @@ __global__ __launch_bounds__(kRouteNT) void route_select_block_kernel(
 }
 
 // ------------------------------------------------------------ layer 2 pairs
+// One thread per (query, routed cluster) pair t.  One array: pairs[t] is the
+// window.  H arrays: pw[t H + h] is array h's window (positions of array h)
+// and pairs[t] gets the union's hull later (pair_mask_kernel).
 __global__ void pairs_kernel(const Model* __restrict__ models, const double* __restrict__ leaves,
-                             const int32_t* __restrict__ qdig, int32_t m, int64_t np, int32_t c,
-                             int32_t r, const int32_t* __restrict__ routed, Pair* __restrict__ pairs,
-                             int32_t* __restrict__ ccount, uint64_t* __restrict__ kq) {
+                             const int32_t* __restrict__ qdig, int32_t m, int32_t H, int32_t C,
+                             int64_t np, int32_t c, int32_t r,
+                             const int32_t* __restrict__ routed, Pair* __restrict__ pairs,
+                             Pair* __restrict__ pw, int32_t* __restrict__ ccount,
+                             uint64_t* __restrict__ kq) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= np) return;
   const int64_t q = t / c;
   const int32_t j = routed[t];
   Pair pr{-1, 0, 0, 0};
-  if (j >= 0) {
-    const Model& M = models[j];
-    uint64_t K = 0;
-    const int64_t pos = locate(M, leaves, qdig + q * 2 * m + m, &K);
-    int64_t s, len;
-    window_of(pos, r, M.L, &s, &len);  // the expansion (if any) replaces s later
-    if (kq) kq[t] = K;
-    pr = Pair{j, int32_t(s), int32_t(len), int32_t(pos)};
-    if (len > 0) atomicAdd(&ccount[j], 1);
+  for (int32_t h = 0; h < H; ++h) {
+    Pair ph{-1, 0, 0, 0};
+    if (j >= 0) {
+      const Model& M = models[int64_t(h) * (C + 1) + j];
+      uint64_t K = 0;
+      const int64_t pos =
+          locate(M, leaves, qdig + q * 2 * H * m + int64_t(H) * m + int64_t(h) * m, &K);
+      int64_t s, len;
+      window_of(pos, r, M.L, &s, &len);  // the expansion (if any) replaces s later
+      if (kq) kq[t * H + h] = K;
+      ph = Pair{j, int32_t(s), int32_t(len), int32_t(pos)};
+    }
+    if (pw) pw[t * H + h] = ph;
+    if (h == 0) pr = ph;
   }
+  if (j >= 0 && pr.len > 0) atomicAdd(&ccount[j], 1);
   pairs[t] = pr;
+}
+
+// Union of a pair's H windows (several arrays): one wave per pair marks the
+// rows (positions of array 0 within the cluster; array h's positions go
+// through amap) in an LDS bitmap of mw words (dynamic shared memory, 4 waves x
+// mw words), stores the bitmap as the pair's membership mask [mw words] and
+// sets pairs[t] to the hull [first, last] of the union.
+__global__ __launch_bounds__(256) void pair_mask_kernel(
+    const Pair* __restrict__ pw, int32_t H, int64_t np, const int64_t* __restrict__ off,
+    const int32_t* __restrict__ amap, int64_t n, int32_t mw, Pair* __restrict__ pairs,
+    uint32_t* __restrict__ mask) {
+  extern __shared__ uint32_t bm_all[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t* bm = bm_all + wave * mw;
+  for (int64_t t = int64_t(blockIdx.x) * 4 + wave; t < np; t += int64_t(gridDim.x) * 4) {
+    const int32_t j = pw[t * H].j;
+    if (j < 0) continue;  // wave-uniform
+    const int64_t o = off[j];
+    for (int32_t w = lane; w < mw; w += 64) bm[w] = 0;
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t h = 0; h < H; ++h) {
+      const Pair ph = pw[t * H + h];
+      for (int32_t p = lane; p < ph.len; p += 64) {
+        const int32_t row =
+            h == 0 ? ph.s + p : int32_t(amap[int64_t(h - 1) * n + o + ph.s + p] - o);
+        atomicOr(&bm[row >> 5], 1u << (row & 31));
+      }
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    int32_t lo = INT32_MAX, hi = -1;
+    for (int32_t w = lane; w < mw; w += 64) {
+      const uint32_t bits = bm[w];
+      mask[t * mw + w] = bits;
+      if (bits) {
+        lo = min(lo, w * 32 + __builtin_ctz(bits));
+        hi = max(hi, w * 32 + 31 - __builtin_clz(bits));
+      }
+    }
+    for (int o2 = 32; o2 > 0; o2 >>= 1) {
+      lo = min(lo, __shfl_xor(lo, o2));
+      hi = max(hi, __shfl_xor(hi, o2));
+    }
+    if (lane == 0) {
+      pairs[t].s = hi >= lo ? lo : 0;
+      pairs[t].len = hi >= lo ? hi - lo + 1 : 0;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+  }
 }
 
 // dist_e-guided bi-directional expansion (Sections 3.3.1, 4.2), one wave per
@@ -655,9 +805,10 @@ __global__ void pairs_kernel(const Model* __restrict__ models, const double* __r
 // scores the next 64 candidates of a side at once into LDS; lane 0 runs the
 // sequential two-pointer decisions over them and the exhausted side is
 // refilled.  Only the window start changes (the length is min(r, L)).
-// layer 1: items are queries, the array is the centroids retriever's keys
-// (L = C) and the l1 rows are updated too; else items are pairs and the array
-// of cluster j is keys + off[j].
+// Item t belongs to hashkey array h = t % H, whose keys start at
+// keys + h * kstride.  Layer 1: items are (query, array) windows, the array is
+// the centroids retriever's keys (L = C) and the l1 rows are updated too; else
+// items are (pair, array) windows and the array of cluster j starts at off[j].
 constexpr int64_t kNoDist = INT64_MAX;
 
 __global__ __launch_bounds__(256) void expand_kernel(const uint64_t* __restrict__ keys,
@@ -665,14 +816,16 @@ __global__ __launch_bounds__(256) void expand_kernel(const uint64_t* __restrict_
                                                      Pair* __restrict__ items, int64_t nitems,
                                                      const uint64_t* __restrict__ kq, int32_t r,
                                                      int32_t m, int32_t B,
-                                                     int32_t* __restrict__ l1) {
+                                                     int32_t* __restrict__ l1, int32_t H,
+                                                     int64_t kstride) {
   __shared__ int64_t dl[4][64], dr[4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t t = int64_t(blockIdx.x) * 4 + wave;
   if (t >= nitems) return;
   const Pair pr = items[t];
   if (pr.j < 0 || pr.len <= 0) return;
-  const uint64_t* ka = off ? keys + off[pr.j] : keys;
+  const uint64_t* kh = keys + (t % H) * kstride;
+  const uint64_t* ka = off ? kh + off[pr.j] : kh;
   const int64_t L = off ? off[pr.j + 1] - off[pr.j] : L1;
   const int64_t take = pr.len;  // = min(r, L)
   const uint64_t Kq = kq[t];
@@ -776,6 +929,7 @@ constexpr int kWavePairCap = 64;
 
 struct WaveShared {
   int32_t lp[kWavePairCap], lq[kWavePairCap], ls[kWavePairCap], le[kWavePairCap];
+  uint32_t lm[kWavePairCap][4];  // membership bits of the tile's rows (several arrays)
 };
 
 // Tile fetch, one tile per wave.  Direct (persistent = 0): workgroups are
@@ -1123,6 +1277,10 @@ __device__ __forceinline__ void pass_loop(const Src& xr,
   if (ks < ks1) mfma_step<F, RC, NPC>(xa, qa0, qa1, acc);
 }
 
+// pmask (several arrays): pair p's candidates are the rows whose bit is set in
+// pmask[p mw ..] (bit = row within the cluster); its window (s, len) is the
+// hull of that set, and hull rows outside the set get a NaN score, which
+// the selection drops.
 // wl == NULL: pair u of the cluster is pair u (identity work list).
 // pair_chunk > 0: workgroup (x, y) handles pairs [y*pair_chunk, (y+1)*pair_chunk)
 // of its tile's cluster.  row_scale (nullable) multiplies each row's scores.
@@ -1136,7 +1294,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(
     const int32_t* __restrict__ wl, const Pair* __restrict__ pairs, int32_t c,
     const void* __restrict__ Qv, float* __restrict__ sbuf, int32_t rcap, int persistent,
     int32_t* __restrict__ ctr, int32_t pair_chunk, const float* __restrict__ row_scale,
-    const int32_t* __restrict__ alist) {
+    const int32_t* __restrict__ alist, const uint32_t* __restrict__ pmask, int32_t mw) {
   typedef Feed<FMT, VEC> F;
   typedef typename F::XE XE;
   typedef typename F::QE QE;
@@ -1212,6 +1370,11 @@ __global__ __launch_bounds__(256) void rerank_kernel(
         sh.lq[slot] = pi / c;
         sh.ls[slot] = pr.s;
         sh.le[slot] = pr.s + pr.len;
+        if (pmask) {  // tiles start at multiples of 32 rows
+#pragma unroll
+          for (int w = 0; w < (RT + 31) / 32; ++w)
+            sh.lm[slot][w] = pmask[int64_t(pi) * mw + (row0 >> 5) + w];
+        }
       }
       __threadfence_block();
       __builtin_amdgcn_wave_barrier();
@@ -1248,6 +1411,8 @@ __global__ __launch_bounds__(256) void rerank_kernel(
                 if (rr < rows_here && row >= a && row < en) {
                   float v = acc[rc][pc][e];
                   if (row_scale) v *= row_scale[grow + rr];
+                  if (pmask && !((sh.lm[g0 + pp][rr >> 5] >> (rr & 31)) & 1u))
+                    v = __builtin_nanf("");
                   dst[row] = v;
                 }
               }
@@ -1383,12 +1548,13 @@ struct CandView {
 
 // Per query: top k (or a shortlist of S) over its windows.  MODE 0 = final
 // output; MODE 1 = shortlist of sorted-row indices for the fp32 rerank.
+// drop: NaN scores (key 0xffffffff, sorted last) are padding, not candidates.
 template <int KPMAX, int MODE>
 __global__ __launch_bounds__(kSelNT) void select_kernel(
     const Pair* __restrict__ pairs, const float* __restrict__ sbuf, int32_t rcap, int32_t c,
     int64_t nq, int32_t K, const int64_t* __restrict__ off, const int32_t* __restrict__ perm32,
     int64_t* __restrict__ ids, float* __restrict__ scores, int32_t kout,
-    int32_t* __restrict__ slist) {
+    int32_t* __restrict__ slist, int drop) {
   __shared__ SelShared sh;
   __shared__ uint64_t srt[KPMAX];
   __shared__ int32_t sidx[KPMAX];
@@ -1443,9 +1609,12 @@ __global__ __launch_bounds__(kSelNT) void select_kernel(
     const int KK = K;
     const int KP = pow2_at_least(KK);
     const int got = block_select<kSelNT>(n, KK, KP, key_of, id_of, srt, sidx, sh);
+    auto valid = [&](int t) {
+      return t < got && !(drop && uint32_t(srt[t] >> 32) == 0xffffffffu);
+    };
     if (MODE == 0) {
       for (int t = tid; t < kout; t += kSelNT) {
-        if (t < got) {
+        if (valid(t)) {
           ids[q * kout + t] = int64_t(srt[t] & 0xffffffffu);
           scores[q * kout + t] = key_score(uint32_t(srt[t] >> 32));
         } else {
@@ -1455,7 +1624,7 @@ __global__ __launch_bounds__(kSelNT) void select_kernel(
       }
     } else {
       for (int t = tid; t < K; t += kSelNT)
-        slist[q * K + t] = t < got ? int32_t(row_of(sidx[t])) : -1;
+        slist[q * K + t] = valid(t) ? int32_t(row_of(sidx[t])) : -1;
     }
     __syncthreads();
   }
@@ -1465,7 +1634,8 @@ __global__ __launch_bounds__(kSelNT) void select_kernel(
 // (key, candidate index) extract the K + 1 best; an exact key tie at the K-th
 // place is resolved by original id over all tied candidates; the winners are
 // finally ordered by (score desc, id asc).  MODE 0 writes ids / scores, MODE 1
-// the shortlist of sorted-row indices.
+// the shortlist of sorted-row indices.  drop: NaN scores (key 0xffffffff) are
+// not candidates (rows of a union's hull outside the union).
 constexpr int kWaveKeyCache = 2048;
 
 template <int MODE, int R>
@@ -1473,7 +1643,7 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
     const Pair* __restrict__ pairs, const float* __restrict__ sbuf, int32_t rcap, int32_t c,
     int64_t nq, int32_t K, const int64_t* __restrict__ off, const int32_t* __restrict__ perm32,
     int64_t* __restrict__ ids, float* __restrict__ scores, int32_t kout,
-    int32_t* __restrict__ slist) {
+    int32_t* __restrict__ slist, int drop) {
   __shared__ uint32_t keys[4][R == 0 ? kWaveKeyCache : 1];
   __shared__ int32_t start[4][LIDER_MAX_C + 1];
   __shared__ int32_t pj[4][LIDER_MAX_C], ps[4][LIDER_MAX_C];
@@ -1538,7 +1708,9 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
     }
     // extraction of the K + 1 smallest (key, index)
     const int want = min(n, K + 1);
+    const uint32_t kdrop = drop ? 0xffffffffu : 0u;  // 0: never matches a real key test below
     uint64_t prev = 0;
+    int nx = 0;
     for (int r = 0; r < want; ++r) {
       uint64_t best = ~uint64_t(0);
       if (R > 0) {
@@ -1546,30 +1718,33 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
         for (int j = 0; j < R; ++j) {
           const int32_t i = lane + 64 * j;
           const uint64_t v = (uint64_t(kr[j]) << 32) | uint32_t(i);
-          if (i < n && (r == 0 || v > prev) && v < best) best = v;
+          if (i < n && !(drop && kr[j] == kdrop) && (r == 0 || v > prev) && v < best) best = v;
         }
       } else if (cached) {
         for (int32_t i = lane; i < n; i += 64) {
-          const uint64_t v = (uint64_t(keys[wave][i]) << 32) | uint32_t(i);
-          if ((r == 0 || v > prev) && v < best) best = v;
+          const uint32_t kk = keys[wave][i];
+          const uint64_t v = (uint64_t(kk) << 32) | uint32_t(i);
+          if (!(drop && kk == kdrop) && (r == 0 || v > prev) && v < best) best = v;
         }
       } else {
         for (int t = 0; t < c; ++t) {
           const int32_t a = st[t], len = st[t + 1] - a;
           for (int p = lane; p < len; p += 64) {
-            const uint64_t v =
-                (uint64_t(score_key(sbq[int64_t(t) * rcap + p])) << 32) | uint32_t(a + p);
-            if ((r == 0 || v > prev) && v < best) best = v;
+            const uint32_t kk = score_key(sbq[int64_t(t) * rcap + p]);
+            const uint64_t v = (uint64_t(kk) << 32) | uint32_t(a + p);
+            if (!(drop && kk == kdrop) && (r == 0 || v > prev) && v < best) best = v;
           }
         }
       }
       best = wave_min_u64(best);
+      if (best == ~uint64_t(0)) break;  // no candidate left (wave-uniform)
       if (lane == 0) ext[wave][r] = best;
       prev = best;
+      ++nx;
     }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
-    const int got = min(want, K);
+    const int got = min(nx, K);
     if (lane < got) {
       const uint64_t v = ext[wave][lane];
       const int64_t row = row_of(int32_t(v & 0xffffffffu));
@@ -1579,7 +1754,7 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
     }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
-    if (want == K + 1 && uint32_t(ext[wave][K - 1] >> 32) == uint32_t(ext[wave][K] >> 32)) {
+    if (nx == K + 1 && uint32_t(ext[wave][K - 1] >> 32) == uint32_t(ext[wave][K] >> 32)) {
       // exact tie at the boundary: the tied places go to the smallest ids
       const uint32_t T = uint32_t(ext[wave][K - 1] >> 32);
       int need = 0;
@@ -1755,20 +1930,23 @@ __global__ __launch_bounds__(256) void wave_shortlist_kernel(
 
 // ------------------------------------------------------------ debug exports
 __global__ void debug_kernel(const int32_t* __restrict__ l1, const Pair* __restrict__ pairs,
+                             const Pair* __restrict__ pw, int32_t H,
                              const int32_t* __restrict__ routed, int64_t nq, int32_t c,
                              int64_t* __restrict__ l1o, int32_t* __restrict__ ro,
                              int64_t* __restrict__ po) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < nq && l1o)
+  if (t < nq * H && l1o)
     for (int u = 0; u < 3; ++u) l1o[3 * t + u] = l1[3 * t + u];
   if (t < nq * c) {
     if (ro) ro[t] = routed[t];
-    if (po) {
-      const Pair pr = pairs[t];
-      po[3 * t] = pr.j >= 0 ? pr.pos : 0;
-      po[3 * t + 1] = pr.j >= 0 ? pr.s : 0;
-      po[3 * t + 2] = pr.j >= 0 ? pr.len : 0;
-    }
+    if (po)
+      for (int32_t h = 0; h < H; ++h) {
+        const Pair pr = pw ? pw[t * H + h] : pairs[t];
+        int64_t* o = po + 3 * (t * H + h);
+        o[0] = pr.j >= 0 ? pr.pos : 0;
+        o[1] = pr.j >= 0 ? pr.s : 0;
+        o[2] = pr.j >= 0 ? pr.len : 0;
+      }
   }
 }
 
@@ -1778,27 +1956,28 @@ template <int MODE>
 void launch_wave_select(unsigned wgrid, hipStream_t st, const Pair* pairs, const float* sbuf,
                         int32_t rcap, int32_t c, int64_t nq, int32_t K, const int64_t* off,
                         const int32_t* perm32, int64_t* ids, float* scores, int32_t kout,
-                        int32_t* slist) {
+                        int32_t* slist, int drop) {
   const int64_t nmax = int64_t(c) * rcap;
   if (nmax <= 512)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 8>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
   else if (nmax <= 1024)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 16>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
   else if (nmax <= 2048)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 32>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
   else
     hipLaunchKernelGGL((wave_select_kernel<MODE, 0>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
 }
 
 template <int RT>
 void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, const int32_t* wl,
                   const Pair* pairs, int32_t c, const float* Q, const __hip_bfloat16* Qb,
                   float* sbuf, int32_t rcap, int persistent, int grid_mult, int32_t* ctr,
-                  const int32_t* alist, int npcm, hipStream_t st) {
+                  const int32_t* alist, int npcm, const uint32_t* pmask, int32_t mw,
+                  hipStream_t st) {
   const int32_t nt = ix.n_tiles[ti];
   unsigned grid;
   if (persistent)
@@ -1811,40 +1990,40 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
       hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false, 1>), dim3(grid), dim3(256), 0,
                          st, (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                          (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                         alist);
+                         alist, pmask, mw);
     else if (bf16)
       hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false, 1>), dim3(grid), dim3(256), 0,
                          st, (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                          (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                         alist);
+                         alist, pmask, mw);
     else if (vec)
       hipLaunchKernelGGL((rerank_kernel<RT, kF32W, true, false, 1>), dim3(grid), dim3(256), 0,
                          st, (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                          (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                         alist);
+                         alist, pmask, mw);
     else
       hipLaunchKernelGGL((rerank_kernel<RT, kF32W, false, false, 1>), dim3(grid), dim3(256), 0,
                          st, (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                          (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                         alist);
+                         alist, pmask, mw);
     return;
   }
   if (bf16 && ix.d % 64 != 0)
     hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
+                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw);
   else if (bf16)
     hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
+                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw);
   else if (vec)
     hipLaunchKernelGGL((rerank_kernel<RT, kF32W, true, false>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
+                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw);
   else
     hipLaunchKernelGGL((rerank_kernel<RT, kF32W, false, false>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist);
+                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw);
 }
 
 // Layer-1 window scores: the centroids (layer-1 order) are one "cluster" of C
@@ -1864,25 +2043,25 @@ void launch_l1_scores(const Index& ix, bool fp8, int64_t nq, const int32_t* l1cs
                        (const void*)ix.cent8, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale,
-                       (const int32_t*)nullptr);
+                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0);
   else if (fp8)
     hipLaunchKernelGGL((rerank_kernel<64, kFP8, true, false>), grid, dim3(256), 0, st,
                        (const void*)ix.cent8, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale,
-                       (const int32_t*)nullptr);
+                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0);
   else if (vec)
     hipLaunchKernelGGL((rerank_kernel<64, kF32, true, false>), grid, dim3(256), 0, st,
                        (const void*)ix.cent_l1, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr,
-                       (const int32_t*)nullptr);
+                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0);
   else
     hipLaunchKernelGGL((rerank_kernel<64, kF32, false, false>), grid, dim3(256), 0, st,
                        (const void*)ix.cent_l1, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr,
-                       (const int32_t*)nullptr);
+                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0);
 }
 
 // Dense layer-1 scores (r1 = C) on the GEMM kernel: 128-row query tiles when
@@ -1974,7 +2153,12 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   int32_t* aflag = reinterpret_cast<int32_t*>(W + p.o_aflag);
   int32_t* alist = reinterpret_cast<int32_t*>(W + p.o_alist);
   uint64_t* kq = reinterpret_cast<uint64_t*>(W + p.o_kq);
-  const int32_t m = ix.m, C = ix.C;
+  float* rsd = reinterpret_cast<float*>(W + p.o_rsd);
+  int32_t* lst = reinterpret_cast<int32_t*>(W + p.o_lst);
+  int32_t* rw = reinterpret_cast<int32_t*>(W + p.o_rw);
+  Pair* pw = reinterpret_cast<Pair*>(W + p.o_pw);
+  uint32_t* pmask = reinterpret_cast<uint32_t*>(W + p.o_mask);
+  const int32_t m = ix.m, C = ix.C, H = ix.H;
   const int64_t np = nq * c;
   const bool bf16 = o.precision == LIDER_BF16;
 
@@ -1985,67 +2169,88 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, st, ctr, int64_t(kCtrWords));
   hipLaunchKernelGGL(zero_kernel, dim3((C + 255) / 256), dim3(256), 0, st, ccount, int64_t(C));
   hipLaunchKernelGGL(zero_kernel, dim3((C + 255) / 256), dim3(256), 0, st, cfill, int64_t(C));
-  int rc = run_hash_ex(Q, nq, ix.d, ix.A, ix.b, ix.anorm, 2 * m, ix.w, qdig, hlist, ctr, ctr + 1,
-                       1, qnorm, st, ix.hash_kind);
+  int rc = run_hash_ex(Q, nq, ix.d, ix.A, ix.b, ix.anorm, 2 * H * m, ix.w, qdig, hlist, ctr,
+                       ctr + 1, 1, qnorm, st, ix.hash_kind);
   if (rc != LIDER_OK) return rc;
   mark(1);
-  hipLaunchKernelGGL(l1_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, st, ix.models,
-                     ix.leaves, qdig, m, nq, C, p.r1, l1, l1pairs, l1cs,
+  const int64_t nl1 = nq * H;  // (query, array) layer-1 items
+  hipLaunchKernelGGL(l1_kernel, dim3(unsigned((nl1 + 255) / 256)), dim3(256), 0, st, ix.models,
+                     ix.leaves, qdig, m, H, nq, C, p.r1, l1, l1pairs, l1cs,
                      o.expand_bits > 0 ? kq : (uint64_t*)nullptr);
   if (o.expand_bits > 0)
-    hipLaunchKernelGGL(expand_kernel, dim3(unsigned((nq + 3) / 4)), dim3(256), 0, st, ix.l1_keys,
-                       (const int64_t*)nullptr, int64_t(C), l1pairs, nq, kq, p.r1, m,
-                       o.expand_bits, l1);
+    hipLaunchKernelGGL(expand_kernel, dim3(unsigned((nl1 + 3) / 4)), dim3(256), 0, st,
+                       ix.l1_keys, (const int64_t*)nullptr, int64_t(C), l1pairs, nl1, kq, p.r1,
+                       m, o.expand_bits, l1, H, int64_t(C));
   const bool fp8 = bf16 && ix.cent8;
   // exact routing from bf16 candidates: dense layer 1, fp32 path, c < 64
   const bool refine = !bf16 && p.r1 == C && o.l1_dense == 0 && c + 1 <= 64 && ix.cent_l1_b;
   if (fp8 || bf16 || refine)
     hipLaunchKernelGGL(to_bf16_kernel, dim3(2048), dim3(256), 0, st, Q, nq * ix.d, qb);
-  if (refine)
-    launch_l1_gemm_bf16(ix, nq, qb, rs, st);
-  else if (p.r1 == C && o.l1_dense >= 0)
-    launch_l1_gemm(ix, fp8, nq, Q, qb, rs, st);
-  else
-    launch_l1_scores(ix, fp8, nq, l1cs, l1pairs, Q, qb, rs, p.r1, st);
   const unsigned qgrid = unsigned(std::min<int64_t>(nq, 65535));
   const unsigned wgrid = unsigned(std::min<int64_t>((nq + 3) / 4, 65535));
+  // the window each routing kernel reads: (l1[wst q + 1], l1[wst q + 2]); with
+  // several arrays and r1 < C, the union list in rw / lst with its scores in rs
+  const int32_t* l1w = l1;
+  int32_t wst = 3 * H;
+  const int32_t* lstp = nullptr;
+  if (refine) {
+    launch_l1_gemm_bf16(ix, nq, qb, rs, st);
+  } else if (p.l1_list) {
+    launch_l1_gemm(ix, fp8, nq, Q, qb, rsd, st);
+    const size_t lds = 4 * size_t((C + 31) / 32) * 4;
+    hipLaunchKernelGGL(l1_union_kernel, dim3(wgrid), dim3(256), lds, st, l1, H, nq, C, ix.l1map,
+                       rsd, p.lcap, lst, rs, rw);
+    l1w = rw;
+    wst = 3;
+    lstp = lst;
+  } else if (p.r1 == C && (o.l1_dense >= 0 || H > 1)) {
+    launch_l1_gemm(ix, fp8, nq, Q, qb, rs, st);
+  } else {
+    launch_l1_scores(ix, fp8, nq, l1cs, l1pairs, Q, qb, rs, p.r1, st);
+  }
   if (refine) {
     const double u = 0.00390625;  // 2^-8: bf16 rounding of each operand
     const double ecoef = 2.0 * u + u * u + dot_err_coef(ix.d) * (1.0 + u) * (1.0 + u);
     if (p.r1 <= 16 * 64)
       hipLaunchKernelGGL(route_refine_kernel<16>, dim3(wgrid), dim3(256), 0, st, Q, ix.d, nq,
-                         ix.cent_l1, ix.l1_order32, l1, qnorm, ix.cent_norm_max, ecoef, c, p.r1,
-                         rs, rs64, routed);
+                         ix.cent_l1, ix.l1_order32, l1w, qnorm, ix.cent_norm_max, ecoef, c, p.r1,
+                         rs, rs64, routed, wst);
     else
       hipLaunchKernelGGL(route_refine_kernel<0>, dim3(wgrid), dim3(256), 0, st, Q, ix.d, nq,
-                         ix.cent_l1, ix.l1_order32, l1, qnorm, ix.cent_norm_max, ecoef, c, p.r1,
-                         rs, rs64, routed);
+                         ix.cent_l1, ix.l1_order32, l1w, qnorm, ix.cent_norm_max, ecoef, c, p.r1,
+                         rs, rs64, routed, wst);
   } else if (c + 1 <= 64) {
     if (fp8)
       hipLaunchKernelGGL(route_select_wave_kernel<true>, dim3(wgrid), dim3(256), 0, st, Q, ix.d,
-                         nq, ix.cent_l1, ix.l1_order32, l1, qnorm, ix.cent_norm_max, c, p.r1, rs,
-                         rs64, routed);
+                         nq, ix.cent_l1, ix.l1_order32, l1w, qnorm, ix.cent_norm_max, c, p.lcap,
+                         rs, rs64, routed, wst, lstp);
     else
       hipLaunchKernelGGL(route_select_wave_kernel<false>, dim3(wgrid), dim3(256), 0, st, Q, ix.d,
-                         nq, ix.cent_l1, ix.l1_order32, l1, qnorm, ix.cent_norm_max, c, p.r1, rs,
-                         rs64, routed);
+                         nq, ix.cent_l1, ix.l1_order32, l1w, qnorm, ix.cent_norm_max, c, p.lcap,
+                         rs, rs64, routed, wst, lstp);
   } else {
     if (fp8)
       hipLaunchKernelGGL(route_select_block_kernel<true>, dim3(qgrid), dim3(kRouteNT), 0, st, Q,
-                         ix.d, nq, ix.cent_l1, ix.l1_order32, l1, qnorm, ix.cent_norm_max, c,
-                         p.r1, rs, rs64, routed);
+                         ix.d, nq, ix.cent_l1, ix.l1_order32, l1w, qnorm, ix.cent_norm_max, c,
+                         p.lcap, rs, rs64, routed, wst, lstp);
     else
       hipLaunchKernelGGL(route_select_block_kernel<false>, dim3(qgrid), dim3(kRouteNT), 0, st, Q,
-                         ix.d, nq, ix.cent_l1, ix.l1_order32, l1, qnorm, ix.cent_norm_max, c,
-                         p.r1, rs, rs64, routed);
+                         ix.d, nq, ix.cent_l1, ix.l1_order32, l1w, qnorm, ix.cent_norm_max, c,
+                         p.lcap, rs, rs64, routed, wst, lstp);
   }
   mark(2);
+  Pair* pwp = H > 1 ? pw : nullptr;
   hipLaunchKernelGGL(pairs_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, ix.models,
-                     ix.leaves, qdig, m, np, c, r, routed, pairs, ccount,
+                     ix.leaves, qdig, m, H, C, np, c, r, routed, pairs, pwp, ccount,
                      o.expand_bits > 0 ? kq : (uint64_t*)nullptr);
   if (o.expand_bits > 0)
-    hipLaunchKernelGGL(expand_kernel, dim3(unsigned((np + 3) / 4)), dim3(256), 0, st, ix.keys,
-                       ix.off, int64_t(0), pairs, np, kq, r, m, o.expand_bits, (int32_t*)nullptr);
+    hipLaunchKernelGGL(expand_kernel, dim3(unsigned((np * H + 3) / 4)), dim3(256), 0, st,
+                       ix.keys, ix.off, int64_t(0), H > 1 ? pw : pairs, np * H, kq, r, m,
+                       o.expand_bits, (int32_t*)nullptr, H, ix.n);
+  if (H > 1)
+    hipLaunchKernelGGL(pair_mask_kernel, dim3(unsigned(std::min<int64_t>((np + 3) / 4, 65535))),
+                       dim3(256), 4 * size_t(p.mw) * 4, st, pw, H, np, ix.off, ix.amap, ix.n,
+                       p.mw, pairs, pmask);
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, ccount, C, cstart);
   hipLaunchKernelGGL(scatter_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, pairs, np,
                      cstart, cfill, wl);
@@ -2065,34 +2270,34 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   }
   if (tr == 32)
     launch_score<32>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
-                     ctr + 8, alist, npcm, st);
+                     ctr + 8, alist, npcm, H > 1 ? pmask : (const uint32_t*)nullptr, p.mw, st);
   else if (tr == 64)
     launch_score<64>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
-                     ctr + 8, alist, npcm, st);
+                     ctr + 8, alist, npcm, H > 1 ? pmask : (const uint32_t*)nullptr, p.mw, st);
   else
     launch_score<128>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
-                      ctr + 8, alist, npcm, st);
+                      ctr + 8, alist, npcm, H > 1 ? pmask : (const uint32_t*)nullptr, p.mw, st);
   mark(4);
   if (!bf16) {
     if (k <= 64)
       launch_wave_select<0>(wgrid, st, pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids,
-                            scores, k, slist);
+                            scores, k, slist, int(H > 1));
     else if (k <= 128)
       hipLaunchKernelGGL((select_kernel<128, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist);
+                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1));
     else
       hipLaunchKernelGGL((select_kernel<1024, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist);
+                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1));
   } else {
     if (p.S <= 64)
       launch_wave_select<1>(wgrid, st, pairs, sbuf, p.rcap, c, nq, p.S, ix.off, ix.perm32, ids,
-                            scores, k, slist);
+                            scores, k, slist, int(H > 1));
     else if (p.S <= 512)
       hipLaunchKernelGGL((select_kernel<512, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist);
+                         p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1));
     else
       hipLaunchKernelGGL((select_kernel<4096, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist);
+                         p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1));
     if (p.S <= 64 && ix.d % 4 == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0)
       hipLaunchKernelGGL(wave_shortlist_kernel, dim3(wgrid), dim3(256), 0, st, ix.X, ix.d, Q, nq,
                          slist, p.S, ix.perm32, k, ids, scores);
@@ -2106,9 +2311,11 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   mark(5);
   if (dbg) {
     if (dbg->qdigits_dev)
-      (void)hipMemcpyAsync(dbg->qdigits_dev, qdig, size_t(nq) * 2 * m * 4, hipMemcpyDeviceToDevice, st);
-    hipLaunchKernelGGL(debug_kernel, dim3(unsigned((np + 255) / 256 + 1)), dim3(256), 0, st, l1,
-                       pairs, routed, nq, c, dbg->l1_dev, dbg->routed_dev, dbg->pairs_dev);
+      (void)hipMemcpyAsync(dbg->qdigits_dev, qdig, size_t(nq) * 2 * H * m * 4,
+                           hipMemcpyDeviceToDevice, st);
+    hipLaunchKernelGGL(debug_kernel, dim3(unsigned((std::max(np, nl1) + 255) / 256 + 1)),
+                       dim3(256), 0, st, l1, pairs, H > 1 ? pw : (const Pair*)nullptr, H, routed,
+                       nq, c, dbg->l1_dev, dbg->routed_dev, dbg->pairs_dev);
   }
   return check_hip(hipGetLastError(), "search kernels");
 }

@@ -40,7 +40,8 @@ class BuildParams(C.Structure):
                 ("lsh_b_host", C.c_void_p), ("assignment_dev", C.c_void_p),
                 ("kmeans_init_host", C.c_void_p), ("kmeans_iters", C.c_int32),
                 ("storage", C.c_int32), ("centroid_storage", C.c_int32),
-                ("kmeans_seeding", C.c_int32), ("hash_kind", C.c_int32)]
+                ("kmeans_seeding", C.c_int32), ("hash_kind", C.c_int32),
+                ("n_arrays", C.c_int32)]
 
 
 class SearchOpts(C.Structure):
@@ -59,7 +60,8 @@ class Info(C.Structure):
     _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("n_clusters", C.c_int32), ("m", C.c_int32),
                 ("rmi_fanout", C.c_int32), ("rmi_fanout_l1", C.c_int32),
                 ("kmeans_iters_run", C.c_int32), ("max_cluster", C.c_int64), ("w", C.c_double),
-                ("storage", C.c_int32), ("centroid_storage", C.c_int32)]
+                ("storage", C.c_int32), ("centroid_storage", C.c_int32),
+                ("n_arrays", C.c_int32)]
 
 
 SYMBOLS = ["lider_build", "lider_free", "lider_last_error", "lider_search_workspace",
@@ -146,17 +148,22 @@ class Index:
 
     def __init__(self, corpus, n_clusters, m, w, rmi_fanout, lsh, rmi_fanout_l1=0,
                  kmeans_init=None, kmeans_iters=20, assignment=None, storage="f32",
-                 centroid_storage="f32", seeding="given", hash_kind="e2lsh", stream=None):
+                 centroid_storage="f32", seeding="given", hash_kind="e2lsh", stream=None,
+                 n_arrays=1):
         """hash_kind "e2lsh": integer digits floor((a.x + b) / w); "sign": the
-        cosine variant (bits [a.x >= 0], key = Decimal(bits); w and b unused)."""
+        cosine variant (bits [a.x >= 0], key = Decimal(bits); w and b unused).
+        n_arrays = H hashkey arrays per core model: lsh = (A [2Hm, d], b [2Hm]),
+        rows h*m.. array h of layer 1, rows H*m + h*m.. array h of layer 2."""
         torch = _torch()
         cp = _dev_ptr(corpus, torch.float32, 2, "corpus")
         n, d = corpus.shape
         kind = {"e2lsh": 0, "sign": 1}[hash_kind]
+        H = int(n_arrays)
         A = np.ascontiguousarray(lsh[0], dtype=np.float32)
-        b = np.ascontiguousarray(lsh[1] if lsh[1] is not None else np.zeros(2 * m), dtype=np.float32)
-        if A.shape != (2 * m, d) or b.shape != (2 * m,):
-            raise ValueError("lsh must be (A [2m, d], b [2m])")
+        b = np.ascontiguousarray(lsh[1] if lsh[1] is not None else np.zeros(2 * H * m),
+                                 dtype=np.float32)
+        if A.shape != (2 * H * m, d) or b.shape != (2 * H * m,):
+            raise ValueError("lsh must be (A [2Hm, d], b [2Hm])")
         ini = None if kmeans_init is None else np.ascontiguousarray(kmeans_init, dtype=np.int64)
         seed_mode = {"given": 0, "farthest": 1}[seeding]
         if assignment is None and (ini is None or ini.shape[0] < (1 if seed_mode else n_clusters)):
@@ -166,7 +173,7 @@ class Index:
                         None if assignment is None else _dev_ptr(assignment, torch.int32, 1,
                                                                  "assignment"),
                         _np_ptr(ini), int(kmeans_iters), _STORAGE[storage],
-                        _CSTORAGE[centroid_storage], seed_mode, kind)
+                        _CSTORAGE[centroid_storage], seed_mode, kind, H)
         h = C.c_void_p()
         _check(lib().lider_build(cp, n, d, C.byref(P), _stream(stream), C.byref(h)))
         self._h = h
@@ -177,6 +184,7 @@ class Index:
         self.F2, self.F1 = info.rmi_fanout, info.rmi_fanout_l1
         self.max_cluster = info.max_cluster
         self.iters_run = info.kmeans_iters_run
+        self.H = info.n_arrays
         self.hash_kind = hash_kind
 
     def close(self):
@@ -244,17 +252,22 @@ class Index:
             ids, sc = out
         dbg = None
         dstruct = None
+        H = self.H
         if debug:
-            dbg = dict(qdigits=torch.empty((nq, 2 * self.m), dtype=torch.int32, device=queries.device),
-                       l1=torch.empty((nq, 3), dtype=torch.int64, device=queries.device),
-                       routed=torch.empty((nq, c), dtype=torch.int32, device=queries.device),
-                       pairs=torch.empty((nq, c, 3), dtype=torch.int64, device=queries.device))
+            dev = queries.device
+            dbg = dict(qdigits=torch.empty((nq, 2 * H * self.m), dtype=torch.int32, device=dev),
+                       l1=torch.empty((nq, H, 3), dtype=torch.int64, device=dev),
+                       routed=torch.empty((nq, c), dtype=torch.int32, device=dev),
+                       pairs=torch.empty((nq, c, H, 3), dtype=torch.int64, device=dev))
             dstruct = SearchDebug(dbg["qdigits"].data_ptr(), dbg["l1"].data_ptr(),
                                   dbg["routed"].data_ptr(), dbg["pairs"].data_ptr())
         _check(lib().lider_search_ex(self._h, qp, nq, k, c, r, C.c_void_p(ids.data_ptr()),
                                      C.c_void_p(sc.data_ptr()), C.c_void_p(ws.data_ptr()),
                                      ws.numel(), _stream(stream), C.byref(o),
                                      C.byref(dstruct) if dstruct is not None else None))
+        if debug and H == 1:  # one array: l1 [nq, 3], pairs [nq, c, 3]
+            dbg["l1"] = dbg["l1"][:, 0]
+            dbg["pairs"] = dbg["pairs"][:, :, 0]
         return (ids, sc, dbg) if debug else (ids, sc)
 
 

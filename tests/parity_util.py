@@ -8,7 +8,8 @@ SCORE_TOL = 1e-4  # |score difference| <= SCORE_TOL * |q| * |x| (fp32 vs FP64)
 
 
 def build_pair(X, n_clusters, m, w, F, A, b, assignment=None, init_ids=None, iters=20, F1=0,
-               storage="f32", centroid_storage="f32", seeding="given"):
+               storage="f32", centroid_storage="f32", seeding="given", n_arrays=1,
+               hash_kind="e2lsh"):
     """GPU index and oracle index over the same host data."""
     import torch
     from paper_2205_00970_amd import lider
@@ -17,36 +18,51 @@ def build_pair(X, n_clusters, m, w, F, A, b, assignment=None, init_ids=None, ite
         np.ascontiguousarray(assignment, dtype=np.int32)).cuda()
     gi = lider.Index(Xd, n_clusters, m, w, F, (A, b), rmi_fanout_l1=F1, kmeans_init=init_ids,
                      kmeans_iters=iters, assignment=asg_d, storage=storage,
-                     centroid_storage=centroid_storage, seeding=seeding)
+                     centroid_storage=centroid_storage, seeding=seeding, n_arrays=n_arrays,
+                     hash_kind=hash_kind)
     oi = oracle.Index(X, n_clusters, A, b, m, w, F, rmi_fanout_l1=(F1 or None),
                       assignment=assignment, init_ids=init_ids, kmeans_iters=iters,
-                      seeding=seeding)
+                      seeding=seeding, n_arrays=n_arrays, hash_kind=hash_kind)
     return gi, oi, Xd
 
 
 def compare_index(gi, oi):
-    """Everything the build produces must match bit for bit."""
-    C, m = oi.C, oi.m
+    """Everything the build produces must match bit for bit (every array)."""
+    C, m, H = oi.C, oi.m, oi.H
+    n = oi.n
+    assert gi.H == H
     assert gi.iters_run == oi.iters_run()
     assert np.array_equal(gi.export("assign"), oi.assignment())
     assert np.array_equal(gi.export("centroids").view(np.uint32),
                           oi.centroids().reshape(-1).view(np.uint32))
-    assert np.array_equal(gi.export("digits"), oi.digits().reshape(-1))
     assert np.array_equal(gi.export("offsets"), oi.offsets())
-    assert np.array_equal(gi.export("perm"), oi.perm())
-    assert np.array_equal(gi.export("keys"), oi.keys())
-    order, keys1, dig1 = oi.layer1()
-    assert np.array_equal(gi.export("l1_order"), order)
-    assert np.array_equal(gi.export("l1_keys"), keys1)
-    assert np.array_equal(gi.export("l1_digits"), dig1.reshape(-1))
-    mi = gi.export("model_int").reshape(C + 1, 3)
-    mb = gi.export("model_box").reshape(C + 1, 2 * m)
-    mk = gi.export("model_key").reshape(C + 1, 2)
-    md = gi.export("model_dbl").reshape(C + 1, 3)
-    lv = gi.export("leaves").reshape(-1, 2)
-    le = gi.export("leaf_err").reshape(-1, 2)
+    dg = gi.export("digits").reshape(H, n * m)
+    pm = gi.export("perm").reshape(H, n)
+    ky = gi.export("keys").reshape(H, n)
+    lo = gi.export("l1_order").reshape(H, C)
+    lk = gi.export("l1_keys").reshape(H, C)
+    ld = gi.export("l1_digits").reshape(H, C * m)
+    mi = gi.export("model_int").reshape(H, C + 1, 3)
+    mb = gi.export("model_box").reshape(H, C + 1, 2 * m)
+    mk = gi.export("model_key").reshape(H, C + 1, 2)
+    md = gi.export("model_dbl").reshape(H, C + 1, 3)
+    lv = gi.export("leaves").reshape(H, -1, 2)
+    le = gi.export("leaf_err").reshape(H, -1, 2)
+    for h in range(H):
+        assert np.array_equal(dg[h], oi.digits(h).reshape(-1)), h
+        assert np.array_equal(pm[h], oi.perm(h)), h
+        assert np.array_equal(ky[h], oi.keys(h)), h
+        order, keys1, dig1 = oi.layer1(h)
+        assert np.array_equal(lo[h], order), h
+        assert np.array_equal(lk[h], keys1), h
+        assert np.array_equal(ld[h], dig1.reshape(-1)), h
+        _compare_models(oi, h, mi[h], mb[h], mk[h], md[h], lv[h], le[h])
+
+
+def _compare_models(oi, h, mi, mb, mk, md, lv, le):
+    C, m = oi.C, oi.m
     for j in range(C + 1):
-        om = oi.model(j)
+        om = oi.model(j, array=h)
         assert (mi[j, 0], mi[j, 1], mi[j, 2]) == (om.L, om.m_eff, om.F), j
         assert np.array_equal(mb[j, :m], om.mins) and np.array_equal(mb[j, m:], om.maxs), j
         assert (int(mk[j, 0]), int(mk[j, 1])) == (om.kmin, om.kmax), j
@@ -69,8 +85,8 @@ def compare_debug(gdbg, odbg):
     gp = gdbg["pairs"].cpu().numpy()
     orr, op = odbg["routed"], odbg["pairs"]
     for q in range(gr.shape[0]):
-        gmap = {int(j): tuple(gp[q, t]) for t, j in enumerate(gr[q]) if j >= 0}
-        omap = {int(j): tuple(op[q, t]) for t, j in enumerate(orr[q]) if j >= 0}
+        gmap = {int(j): tuple(gp[q, t].reshape(-1)) for t, j in enumerate(gr[q]) if j >= 0}
+        omap = {int(j): tuple(op[q, t].reshape(-1)) for t, j in enumerate(orr[q]) if j >= 0}
         assert gmap == omap, (q, gmap, omap)
 
 
