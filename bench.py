@@ -263,6 +263,7 @@ def main():
             f"{extra['precision_bf16']['recall10']}")
         extra["persistent_qps"] = round(args.nq / timed(10, c, r, r1, reps=5, persistent=True)[0])
         extra["cosine"] = cosine_variant(args, torch, datagen, lider, X, lab, Q, C, F, log)
+        extra["arrays"] = arrays_variant(args, torch, datagen, lider, X, lab, Q, C, F, log, gt_sc)
 
     cpu = None
     if not args.quick and not args.no_cpu_baseline:
@@ -386,6 +387,44 @@ def cosine_variant(args, torch, datagen, lider, X, lab, Q, C, F, log):
         log(f"cosine {name}: {Qn.shape[0] / dt:,.0f} q/s, recall@10 {rec:.4f}")
     del gi, Xn
     torch.cuda.empty_cache()
+    return out
+
+
+def arrays_variant(args, torch, datagen, lider, X, lab, Q, C, F, log, gt_sc, H_list=(1, 4, 10)):
+    """Multi-array core models (Section 3.3.1) on the same mixture, clusters =
+    the generator's labels, E2LSH m=8 w=2 per array: recall@10 and q/s at the
+    literal window (c=8, r=r1=256) and at c=4, r=128, r1=C for H = 1, 4, 10
+    (H=10 is the paper's setting), with the per-stage times of each."""
+    m, w = 8, 2.0
+    out = {"m": m, "w": w}
+    for H in H_list:
+        A, b = datagen.lsh_params(m, X.shape[1], w, seed=31, n_arrays=H)
+        t0 = time.time()
+        gi = lider.Index(X, C, m, w, F, (A, b), assignment=lab.to(torch.int32), n_arrays=H)
+        torch.cuda.synchronize()
+        bs = time.time() - t0
+        res = {"build_s": round(bs, 2)}
+        for name, (c, r, r1) in {"literal": (8, 256, 256), "c4_r128": (4, 128, C)}.items():
+            ids = torch.empty((Q.shape[0], 10), dtype=torch.int64, device=Q.device)
+            sc = torch.empty((Q.shape[0], 10), dtype=torch.float32, device=Q.device)
+            gi.search(Q, 10, c, r, r1=r1, out=(ids, sc))
+            torch.cuda.synchronize()
+            lider.profile_begin(5)
+            t = time.perf_counter()
+            for _ in range(5):
+                gi.search(Q, 10, c, r, r1=r1, out=(ids, sc))
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / 5
+            stages, calls = lider.profile_end()
+            rec = recall_at(torch, X, Q, ids, gt_sc, 10)
+            res[name] = dict(c=c, r=r, r1=r1, qps=round(Q.shape[0] / dt), recall10=round(rec, 4),
+                             stage_ms={s: round(v / calls, 4) for s, v in stages.items()})
+            log(f"arrays H={H} {name}: {Q.shape[0] / dt:,.0f} q/s, recall@10 {rec:.4f}, "
+                + ", ".join(f"{s}={v / calls:.3f}" for s, v in stages.items()))
+        out[f"H{H}"] = res
+        gi.close()
+        del gi
+        torch.cuda.empty_cache()
     return out
 
 

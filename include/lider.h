@@ -145,8 +145,9 @@ const char* lider_last_error(void);
  *                 LIDER_BF16: precision form -- bf16 first pass over the
  *                 windows (needs storage = LIDER_BF16), shortlist of
  *                 shortlist_mult*k per query, fp32 rerank of the shortlist from
- *                 the fp32 copy; routing uses fp8 centroids if the index has
- *                 them, else fp32.
+ *                 the fp32 copy; routing takes the best fp8 centroid scores
+ *                 (approximate) if the index has fp8 centroids, else it is
+ *                 exact as in LIDER_F32.
  *  shortlist_mult shortlist length per query in units of k (0 = 4).
  *  persistent     0: one wave per row tile of the whole index (tiles no window
  *                 touches exit at once).  1: a persistent grid whose waves pull
@@ -156,17 +157,20 @@ const char* lider_last_error(void);
  *                 sparse batches on large indexes).  Results are identical.
  *  tile_rows      rows per rerank tile (one wave per tile): 32, 64, 128, or 0
  *                 (128 when clusters average at least 512 rows, else 64).
- *  l1_dense       0 (default): when r1 covers every centroid, the layer-1
- *                 scores are one dense query x centroid product on MFMA; with
- *                 precision LIDER_F32 and c < 64 it runs in bf16 and only the
- *                 centroids whose bf16 score is within twice its rigorous error
- *                 bound of the c-th best are rescored in sequential FP64 to
- *                 decide the routed set.  1: the dense product in fp32 (no
- *                 bf16 candidates).  -1: always the window kernel.  The routed
- *                 sets, and so all results, are identical.  With n_arrays > 1
- *                 and r1 < n_clusters, layer 1 always takes the dense fp32
- *                 product and routes among the union of the H windows (at
- *                 most 65536 clusters); with r1 = n_clusters, -1 acts as 1.
+ *  l1_dense       How the layer-1 scores are computed; the routed set is then
+ *                 decided exactly (the FP64 definition): the centroids whose
+ *                 score lies within twice its rigorous error bound of the c-th
+ *                 best window score are candidates, and unless they are
+ *                 exactly c they are rescored by sequential FP64 inner
+ *                 products.  0 (default): one dense query x centroid product
+ *                 on MFMA in bf16 (every centroid scored; each query's window
+ *                 read from its row).  1: the dense product in fp32.  -1: the
+ *                 window kernel (fp32 scores of the r1-windows only).  The
+ *                 routed sets, and so all results, are identical.  With
+ *                 n_arrays > 1, -1 acts as 1; with r1 < n_clusters the routing
+ *                 runs over the union of the H windows (at most 65536
+ *                 clusters).  The dense product needs nq x n_clusters floats
+ *                 of workspace.
  *  grid_mult      persistent grid = grid_mult * number of CUs (0 = 4).
  *  expand_bits    0: fixed window of r (r1) positions, floor(r/2) left of the
  *                 predicted location (shifted inward at the ends).  B in 1..16:

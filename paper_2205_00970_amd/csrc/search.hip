@@ -39,14 +39,21 @@ struct alignas(16) Pair {
 // count.
 constexpr int kCtrWords = 64;
 
+// Routing candidates kept per query for the FP64 rescoring.
+constexpr int kCandCap = 256;
+
+constexpr int32_t kBufWord3 = 0x00020000;  // buffer resource word 3 for gfx9-family targets
+
 struct Plan {
   size_t o_ctr, o_qdig, o_hlist, o_qnorm, o_l1, o_l1p, o_l1cs, o_rs, o_rs64, o_routed, o_pairs,
-      o_ccount, o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, o_aflag, o_alist, o_kq, o_rsd,
-      o_lst, o_rw, o_pw, o_mask, total;
+      o_ccount, o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, o_aflag, o_alist, o_kq, o_lst,
+      o_rw, o_pw, o_mask, o_rcand, o_rcnt, total;
   int32_t r1, rcap, S;
-  // several hashkey arrays: lcap = layer-1 union capacity per query (list
-  // mode when r1 < C), mw = mask words per (query, cluster) pair
-  bool l1_list;
+  // l1_dense_rows: layer-1 scores of every centroid (dense product), else of
+  // the r1-windows (window kernel).  Several hashkey arrays: lcap = layer-1
+  // union capacity per query (list mode when r1 < C), mw = mask words per
+  // (query, cluster) pair.
+  bool l1_dense_rows, l1_list;
   int32_t lcap, mw;
 };
 
@@ -70,6 +77,7 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   const int32_t mult = o.shortlist_mult > 0 ? o.shortlist_mult : 4;
   const int32_t S = o.precision == LIDER_BF16 ? std::min(4096, mult * k) : 0;
   p.l1_list = H > 1 && r1 < ix.C;
+  p.l1_dense_rows = H > 1 || o.l1_dense >= 0;
   p.lcap = p.l1_list ? int32_t(std::min<int64_t>(ix.C, int64_t(H) * r1)) : r1;
   p.mw = H > 1 ? int32_t((ix.max_cluster + 127) / 128 * 4) : 0;
   const int64_t np = nq * c;
@@ -86,9 +94,10 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   p.o_l1 = take(size_t(nq) * H * 3 * 4);
   p.o_l1p = take(size_t(nq) * H * sizeof(Pair));
   p.o_l1cs = take(2 * 4);
-  p.o_rs = take(size_t(nq) * p.lcap * 4);
+  p.o_rs = take(size_t(nq) * (p.l1_dense_rows ? ix.C : r1) * 4);
   p.o_rs64 = take(size_t(nq) * p.lcap * 8);
-  p.o_rsd = take(p.l1_list ? size_t(nq) * ix.C * 4 : 0);
+  p.o_rcand = take(size_t(nq) * kCandCap * 4);
+  p.o_rcnt = take(size_t(nq) * 4);
   p.o_lst = take(p.l1_list ? size_t(nq) * p.lcap * 4 : 0);
   p.o_rw = take(p.l1_list ? size_t(nq) * 3 * 4 : 0);
   p.o_pw = take(H > 1 ? size_t(np) * H * sizeof(Pair) : 0);
@@ -335,14 +344,14 @@ __global__ void l1_kernel(const Model* __restrict__ models, const double* __rest
 }
 
 // Union of a query's H layer-1 windows, as ascending positions of array 0's
-// layer-1 order, with their dense scores gathered from rsd [nq x C]: one wave
-// per query marks the windows in an LDS bitmap of C bits (dynamic shared
-// memory, 4 waves x ceil(C/32) words), then lists the set bits in order.
+// layer-1 order: one wave per query marks the windows in an LDS bitmap of C
+// bits (dynamic shared memory, 4 waves x ceil(C/32) words), then lists the
+// set bits in order.
 // rw[q] = (0, 0, union size) is the query's window in list form.
 __global__ __launch_bounds__(256) void l1_union_kernel(
     const int32_t* __restrict__ l1, int32_t H, int64_t nq, int32_t C,
-    const int32_t* __restrict__ l1map, const float* __restrict__ rsd, int32_t lcap,
-    int32_t* __restrict__ lst, float* __restrict__ rs, int32_t* __restrict__ rw) {
+    const int32_t* __restrict__ l1map, int32_t lcap, int32_t* __restrict__ lst,
+    int32_t* __restrict__ rw) {
   extern __shared__ uint32_t bm_all[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t W = (C + 31) / 32;
@@ -375,7 +384,6 @@ __global__ __launch_bounds__(256) void l1_union_kernel(
         const int32_t pos = w * 32 + (__ffs(bits) - 1);
         bits &= bits - 1;
         lst[q * lcap + at] = pos;
-        rs[q * lcap + at] = rsd[q * C + pos];
         ++at;
       }
       base += __shfl(incl, 63);
@@ -415,26 +423,41 @@ __device__ inline uint64_t wave_min_u64(uint64_t v) {
   return (uint64_t(hi) << 32) | lo;
 }
 
-// Error bound of one fp32 window score against its FP64 definition.
-__device__ inline double route_err(int d, float qn, float cmax) {
-  return dot_err_coef(d) * double(qn) * double(cmax) + double(d) * 7.888609052210118e-31;
+// Sequential FP64 inner product in dimension order (the definition).  The
+// fp32 products are exact in FP64, so a fused multiply-add rounds exactly
+// like the separate product and sum.  Rows of 4k floats at 16-byte aligned
+// addresses are read as float4.
+__device__ inline double seq_dot_f64(const float* __restrict__ q, const float* __restrict__ mu,
+                                     int32_t d) {
+  double acc = 0.0;
+  int32_t l = 0;
+  if ((d & 3) == 0 && ((reinterpret_cast<uintptr_t>(q) | reinterpret_cast<uintptr_t>(mu)) & 15) == 0) {
+#pragma unroll 4
+    for (; l < d; l += 4) {
+      const float4 m = *reinterpret_cast<const float4*>(mu + l);
+      const float4 x = *reinterpret_cast<const float4*>(q + l);
+      acc = fma(double(x.x), double(m.x), acc);
+      acc = fma(double(x.y), double(m.y), acc);
+      acc = fma(double(x.z), double(m.z), acc);
+      acc = fma(double(x.w), double(m.w), acc);
+    }
+  }
+  for (; l < d; ++l) acc = fma(double(q[l]), double(mu[l]), acc);
+  return acc;
 }
 
-// FP64 decision of the routed set by one wave: sequential FP64 inner products
-// of every window centroid, then c rounds of (score desc, cluster id asc).
-// Window entry p is layer-1 position lq[p] when a list is given, else s1 + p.
-__device__ void route_fp64_wave(const float* __restrict__ qv, int32_t d,
+// FP64 decision of the routed set by one wave: the sequential FP64 inner
+// product of every window centroid (one lane per centroid), then c rounds of
+// (score desc, cluster id asc).  Window entry p is layer-1 position lq[p]
+// when a list is given, else s1 + p.
+__device__ __attribute__((noinline)) void route_fp64_wave(const float* __restrict__ qv, int32_t d,
                                 const float* __restrict__ cent_l1,
                                 const int32_t* __restrict__ l1_order32, int32_t s1, int32_t len1,
                                 const int32_t* __restrict__ lq, int32_t c,
                                 double* __restrict__ r64, int32_t* __restrict__ out) {
   const int lane = threadIdx.x & 63;
-  for (int p = lane; p < len1; p += 64) {
-    const float* mu = cent_l1 + int64_t(lq ? lq[p] : s1 + p) * d;
-    double acc = 0.0;
-    for (int l = 0; l < d; ++l) acc = acc + double(qv[l]) * double(mu[l]);
-    r64[p] = acc;
-  }
+  for (int p = lane; p < len1; p += 64)
+    r64[p] = seq_dot_f64(qv, cent_l1 + int64_t(lq ? lq[p] : s1 + p) * d, d);
   __threadfence_block();
   __builtin_amdgcn_wave_barrier();
   for (int t = 0; t < c; ++t) {
@@ -468,100 +491,90 @@ __device__ void route_fp64_wave(const float* __restrict__ qv, int32_t d,
   }
 }
 
-// Routing, one wave per query (c + 1 <= 64): extract the c + 1 best window
-// scores by repeated wave minima of (key, position); if the c-th and
-// (c+1)-th are closer than the error band, decide in FP64.  The query's window
-// is (l1[ws q + 1], l1[ws q + 2]); with a list (several arrays), window entry p
-// is layer-1 position lst[q r1 + p] and rs holds the listed centroids' scores.
-template <bool FP8>
-__global__ __launch_bounds__(256) void route_select_wave_kernel(
-    const float* __restrict__ Q, int32_t d, int64_t nq, const float* __restrict__ cent_l1,
-    const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
-    const float* __restrict__ qnorm, const float* __restrict__ cent_norm_max, int32_t c,
-    int32_t r1, const float* __restrict__ rs, double* __restrict__ rs64,
-    int32_t* __restrict__ routed, int32_t ws, const int32_t* __restrict__ lst) {
-  __shared__ uint64_t ext[4][65];
-  __shared__ int32_t chosen[4][64];
+// Approximate routing of the precision form (fp8 centroid scores, no exact
+// decision), one wave per query (c <= 64): the c best window scores by
+// repeated wave minima of (key, window entry).  Window entries and score
+// addressing as in route_filter_kernel.
+__global__ __launch_bounds__(256) void route_approx_wave_kernel(
+    int64_t nq, const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
+    int32_t wst, const int32_t* __restrict__ lst, int32_t lcap, const float* __restrict__ rs,
+    int32_t rstride, int dense, int32_t c, int32_t* __restrict__ routed) {
+  __shared__ uint64_t ext[4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
-    const int32_t s1 = l1[ws * q + 1], len1 = l1[ws * q + 2];
-    const int32_t* lq = lst ? lst + q * r1 : nullptr;
-    const float* rsq = rs + q * r1;
-    const int want = min(len1, c + 1);
+    const int32_t s1 = l1[wst * q + 1], len1 = l1[wst * q + 2];
+    const int32_t* lq = lst ? lst + q * lcap : nullptr;
+    const float* rsq = rs + q * rstride;
+    auto pos_of = [&](int p) { return lq ? lq[p] : s1 + p; };
+    const int want = min(len1, c);
     uint64_t prev = 0;
-    int got = 0;
     for (int t = 0; t < want; ++t) {
       uint64_t best = ~uint64_t(0);
       for (int p = lane; p < len1; p += 64) {
-        const uint64_t v = (uint64_t(score_key(rsq[p])) << 32) | uint32_t(p);
+        const uint64_t v = (uint64_t(score_key(rsq[dense ? pos_of(p) : p])) << 32) | uint32_t(p);
         if ((t == 0 || v > prev) && v < best) best = v;
       }
       best = wave_min_u64(best);
       if (lane == 0) ext[wave][t] = best;
       prev = best;
-      ++got;
     }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
-    bool amb = false;
-    if (!FP8 && len1 > c) {
-      const double sc = double(key_score(uint32_t(ext[wave][c - 1] >> 32)));
-      const double sn = double(key_score(uint32_t(ext[wave][c] >> 32)));
-      amb = (sc - sn) <= 4.0 * route_err(d, qnorm[q], *cent_norm_max);
-    }
-    if (!amb) {
-      for (int t = lane; t < c; t += 64) {
-        const int32_t p = int32_t(ext[wave][t] & 0xffffffffu);
-        routed[q * c + t] = t < min(got, c) ? l1_order32[lq ? lq[p] : s1 + p] : -1;
-      }
-    } else {
-      route_fp64_wave(Q + q * d, d, cent_l1, l1_order32, s1, len1, lq, c, rs64 + q * r1,
-                      chosen[wave]);
-      for (int t = lane; t < c; t += 64) routed[q * c + t] = chosen[wave][t];
-    }
+    for (int t = lane; t < c; t += 64)
+      routed[q * c + t] =
+          t < want ? l1_order32[pos_of(int32_t(ext[wave][t] & 0xffffffffu))] : -1;
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
   }
 }
 
-constexpr int kRefineLds = 1024;
+// Exact routing from approximate layer-1 scores with a rigorous error bound,
+// in two kernels.  Window entry p (0 <= p < len1) is layer-1 position pos(p)
+// = lst[q lcap + p] with a union list, else s1 + p; its approximate score is
+// rs[q rstride + pos(p)] for dense score rows (every centroid scored), else
+// rs[q rstride + p].  Each approximate score is within E = ecoef |q| max|mu|
+// (+ a term for underflow) of the exact inner product.  Every centroid of the
+// exact top c has an approximate score of at least T - 2E, T the c-th largest
+// approximate score (the c best approximate scores bound the c-th best exact
+// score from below by T - E), so the exact top c lies among the candidates
+// above that threshold.
+//
+// route_filter_kernel, one wave per query: T, then the candidates.  Exactly c
+// candidates: they are the routed set (written directly, rcnt = 0).  More: the
+// candidates' positions go to rcand[q kCandCap ..] and rcnt[q] = their count,
+// or kCandCap + 1 when they do not fit (the whole window is then rescored).
+// R: approximate scores kept in registers per lane (len1 <= 64 R), else
+// re-read.
 
-// Exact routing from bf16 candidate scores (window = every centroid, c < 64),
-// one wave per query.  rs holds scores of bf16-rounded query and centroids
-// with fp32 accumulation; each is within E = ecoef |q| max|mu| of the exact
-// inner product.  Every centroid of the exact top c has an approximate score
-// of at least T - 2E, T the c-th largest approximate score, so the exact top c
-// is contained in the candidates above that threshold.  Exactly c candidates:
-// they are the routed set.  More (up to 64): they are rescored by the oracle's
-// sequential FP64 dot product and the top c taken by (score desc, cluster id
-// asc).  More than 64: the whole window is rescored (route_fp64_wave).  R:
-// approximate scores kept in registers per lane (len1 <= 64 R), else re-read.
 template <int R>
-__global__ __launch_bounds__(256) void route_refine_kernel(
-    const float* __restrict__ Q, int32_t d, int64_t nq, const float* __restrict__ cent_l1,
-    const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
-    const float* __restrict__ qnorm, const float* __restrict__ cent_norm_max, double ecoef,
-    int32_t c, int32_t r1, const float* __restrict__ rs, double* __restrict__ rs64,
-    int32_t* __restrict__ routed, int32_t ws) {
-  __shared__ int32_t cand[4][64];
-  __shared__ int32_t chosen[4][64];
-  __shared__ double csc[4][64];
-  __shared__ float sq[4][kRefineLds], smu[4][kRefineLds];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bool staged = d <= kRefineLds;
+__global__ __launch_bounds__(256) void route_filter_kernel(
+    int32_t d, int64_t nq, const int32_t* __restrict__ l1_order32,
+    const int32_t* __restrict__ l1, int32_t wst, const int32_t* __restrict__ lst, int32_t lcap,
+    const float* __restrict__ rs, int32_t rstride, int dense, const float* __restrict__ qnorm,
+    const float* __restrict__ cent_norm_max, double ecoef, int32_t c,
+    int32_t* __restrict__ rcand, int32_t* __restrict__ rcnt, int32_t* __restrict__ routed) {
+  const int lane = threadIdx.x & 63;
   const uint64_t below = (uint64_t(1) << lane) - 1;
-  for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
-    const int32_t s1 = l1[ws * q + 1], len1 = l1[ws * q + 2];
-    const float* rsq = rs + q * r1;
+  for (int64_t q = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); q < nq;
+       q += int64_t(gridDim.x) * 4) {
+    const int32_t s1 = l1[wst * q + 1], len1 = l1[wst * q + 2];
+    const int32_t* lq = lst ? lst + q * lcap : nullptr;
+    const float* rsq = rs + q * rstride;
+    auto pos_of = [&](int p) { return lq ? lq[p] : s1 + p; };
+    auto score_at = [&](int p) { return rsq[dense ? pos_of(p) : p]; };
+    if (len1 <= c) {  // every window entry is routed
+      for (int t = lane; t < c; t += 64) routed[q * c + t] = t < len1 ? l1_order32[pos_of(t)] : -1;
+      if (lane == 0) rcnt[q] = 0;
+      continue;
+    }
     float v[R > 0 ? R : 1];
     if (R > 0) {
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const int p = lane + 64 * j;
-        v[j] = p < len1 ? rsq[p] : 0.f;
+        v[j] = p < len1 ? score_at(p) : 0.f;
       }
     }
-    auto score = [&](int j, int p) { return R > 0 ? v[j] : rsq[p]; };
     // T: the c-th largest approximate score (c rounds of a wave minimum over
     // score keys; the index part keeps equal scores apart)
     uint64_t prev = 0;
@@ -576,15 +589,16 @@ __global__ __launch_bounds__(256) void route_refine_kernel(
         }
       } else {
         for (int p = lane; p < len1; p += 64) {
-          const uint64_t key = (uint64_t(score_key(rsq[p])) << 32) | uint32_t(p);
+          const uint64_t key = (uint64_t(score_key(score_at(p))) << 32) | uint32_t(p);
           if ((t == 0 || key > prev) && key < best) best = key;
         }
       }
       prev = wave_min_u64(best);
     }
     const double E = ecoef * double(qnorm[q]) * double(*cent_norm_max) +
-                     double(d) * 7.52316384526264e-37;  // d * 2^-120: subnormal products
+                     double(d) * 7.888609052210118e-31;  // d * 2^-100: subnormal products
     const double thr = double(key_score(uint32_t(prev >> 32))) - 2.0 * E;
+    int32_t* cq = rcand + q * kCandCap;
     int n = 0;
     const int nchunk = (len1 + 63) / 64;
     for (int jc = 0; jc < nchunk; ++jc) {
@@ -595,119 +609,201 @@ __global__ __launch_bounds__(256) void route_refine_kernel(
         for (int j = 0; j < R; ++j)
           if (j == jc) sv = v[j];
       } else if (p < len1) {
-        sv = rsq[p];
+        sv = score_at(p);
       }
       const bool in = p < len1 && double(sv) >= thr;
       const uint64_t m = __ballot(in);
       const int slot = n + __popcll(m & below);
-      if (in && slot < 64) cand[wave][slot] = p;
+      if (in && slot < kCandCap) cq[slot] = pos_of(p);
       n += __popcll(m);
     }
-    (void)score;
+    if (n == c) {  // the candidates are the routed set (listed in window order)
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+      for (int t = lane; t < c; t += 64) routed[q * c + t] = l1_order32[cq[t]];
+      if (lane == 0) rcnt[q] = 0;
+    } else if (lane == 0) {
+      rcnt[q] = n > kCandCap ? kCandCap + 1 : n;
+    }
+  }
+}
+
+// route_rescore_kernel, one wave per query with rcnt[q] > 0.  Each
+// candidate's FP64 inner product is summed in parallel (the products are
+// exact in FP64) by a group of 16 lanes, four candidates at a time; two FP64
+// sums of the same d terms in different orders differ by at most
+// 2 (d-1) 2^-53 sum|p| (to first order), so with the band 8 d 2^-53 sum|p|
+// around each value, the top c by parallel value are the exact top c whenever
+// every chosen band lies above every other band.  Otherwise, and when the
+// candidates did not fit (then the whole window), one lane per centroid sums
+// the FP64 inner product sequentially in dimension order (the definition) and
+// the top c by (score desc, cluster id asc) are taken.
+constexpr int kRescoreSteps = 16;  // float4 steps per lane of the fast path: d <= 1024
+
+__global__ __launch_bounds__(256) void route_rescore_kernel(
+    const float* __restrict__ Q, int32_t d, int64_t nq, const float* __restrict__ cent_l1,
+    const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1, int32_t wst,
+    const int32_t* __restrict__ lst, int32_t lcap, int32_t c, const int32_t* __restrict__ rcand,
+    const int32_t* __restrict__ rcnt, double* __restrict__ rs64, int32_t* __restrict__ routed) {
+  __shared__ float sq[4][64 * kRescoreSteps] __attribute__((aligned(16)));
+  __shared__ double clo[4][kCandCap], chi[4][kCandCap];
+  __shared__ int32_t cid[4][kCandCap];
+  __shared__ uint8_t cpick[4][kCandCap];
+  __shared__ int32_t chosen[4][LIDER_MAX_C];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, j = lane & 15;
+  const double u = 1.1102230246251565e-16;  // 2^-53
+  const bool fast = (d & 3) == 0 && d <= 64 * kRescoreSteps &&
+                    ((reinterpret_cast<uintptr_t>(Q) | reinterpret_cast<uintptr_t>(cent_l1)) & 15) == 0;
+  for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
+    const int32_t n = rcnt[q];
+    if (n == 0) continue;  // decided by the filter (wave-uniform)
+    const float* qv = Q + q * d;
+    const int32_t* cq = rcand + q * kCandCap;
+    if (n > kCandCap) {
+      const int32_t s1 = l1[wst * q + 1], len1 = l1[wst * q + 2];
+      route_fp64_wave(qv, d, cent_l1, l1_order32, s1, len1, lst ? lst + q * lcap : nullptr, c,
+                      rs64 + q * lcap, chosen[wave]);
+      for (int t = lane; t < c; t += 64) routed[q * c + t] = chosen[wave][t];
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+      continue;
+    }
+    // lane j of group g: dims 4 j + 64 i (fast path, query staged in LDS) or
+    // j + 16 i
+    if (fast) {  // zero beyond d: those products must be exact zeros
+      for (int k = 4 * lane; k < 64 * kRescoreSteps; k += 256)
+        *reinterpret_cast<float4*>(&sq[wave][k]) =
+            k < d ? *reinterpret_cast<const float4*>(qv + k) : float4{0.f, 0.f, 0.f, 0.f};
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+    }
+    for (int t0 = 0; t0 < n; t0 += 4) {
+      const int t = t0 + g;
+      const float* mu = cent_l1 + int64_t(cq[min(t, n - 1)]) * d;
+      double ps = 0.0, pa = 0.0;
+      if (fast) {
+        // the row through a buffer resource: reads past d return zeros
+        const __amdgpu_buffer_rsrc_t rsrc =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(mu), 0, d * 4, kBufWord3);
+#pragma unroll 1
+        for (int h = 0; h < kRescoreSteps; h += 8) {  // 8 float4 loads in flight per lane
+          float4 m[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, (4 * j + 64 * (h + i)) * 4,
+                                                                 0, 0);
+            m[i] = float4{__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
+                          __uint_as_float(v[3])};
+          }
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const float4 x = *reinterpret_cast<const float4*>(&sq[wave][4 * j + 64 * (h + i)]);
+            const double p0 = double(x.x) * double(m[i].x), p1 = double(x.y) * double(m[i].y);
+            const double p2 = double(x.z) * double(m[i].z), p3 = double(x.w) * double(m[i].w);
+            ps += p0;
+            ps += p1;
+            ps += p2;
+            ps += p3;
+            pa += fabs(p0);
+            pa += fabs(p1);
+            pa += fabs(p2);
+            pa += fabs(p3);
+          }
+        }
+      } else {
+        for (int k = j; k < d; k += 16) {
+          const double pr = double(qv[k]) * double(mu[k]);
+          ps += pr;
+          pa += fabs(pr);
+        }
+      }
+      for (int o = 8; o > 0; o >>= 1) {  // within the 16-lane group
+        ps += __shfl_xor(ps, o);
+        pa += __shfl_xor(pa, o);
+      }
+      if (j == 0 && t < n) {
+        const double band = 8.0 * double(d) * u * pa;
+        clo[wave][t] = ps - band;
+        chi[wave][t] = ps + band;
+        cid[wave][t] = l1_order32[cq[t]];
+        cpick[wave][t] = 0;
+      }
+    }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
-    const float* qv = Q + q * d;
-    if (n == c) {  // the candidates are the routed set; listed by approximate score
-      float sv = 0.f;
-      int32_t p = 0;
-      if (lane < c) {
-        p = cand[wave][lane];
-        sv = rsq[p];
-      }
-      const uint64_t key = (uint64_t(score_key(sv)) << 32) | uint32_t(p);
-      int rank = 0;
-      for (int u = 0; u < c; ++u) rank += __shfl(key, u) < key;
-      if (lane < c) routed[q * c + rank] = l1_order32[s1 + p];
-    } else if (n > 64) {
-      route_fp64_wave(qv, d, cent_l1, l1_order32, s1, len1, nullptr, c, rs64 + q * r1,
-                      chosen[wave]);
-      for (int t = lane; t < c; t += 64) routed[q * c + t] = chosen[wave][t];
-    } else {
-      // sequential FP64 dot products, one candidate at a time: the wave stages
-      // the query and the centroid row in LDS, lane 0 sums in dimension order
-      if (staged)
-        for (int l = lane; l < d; l += 64) sq[wave][l] = qv[l];
-      for (int t = 0; t < n; ++t) {
-        const float* mu = cent_l1 + int64_t(s1 + cand[wave][t]) * d;
-        if (staged) {
-          for (int l = lane; l < d; l += 64) smu[wave][l] = mu[l];
-          __threadfence_block();
-          __builtin_amdgcn_wave_barrier();
+    // top c by parallel value (band midpoint), ties to the smaller cluster id
+    for (int r = 0; r < c; ++r) {
+      double bv = -INFINITY;
+      int32_t bi = 0x7fffffff, bt = -1;
+      for (int t = lane; t < n; t += 64) {
+        if (cpick[wave][t]) continue;
+        const double v = 0.5 * (clo[wave][t] + chi[wave][t]);
+        const int32_t id = cid[wave][t];
+        if (bt < 0 || v > bv || (v == bv && id < bi)) {
+          bv = v;
+          bi = id;
+          bt = t;
         }
-        if (lane == 0) {
-          double acc = 0.0;
-          if (staged) {
-#pragma unroll 8
-            for (int l = 0; l < d; ++l) acc = acc + double(sq[wave][l]) * double(smu[wave][l]);
-          } else {
-            for (int l = 0; l < d; ++l) acc = acc + double(qv[l]) * double(mu[l]);
-          }
-          csc[wave][t] = acc;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o);
+        const int32_t oi = __shfl_xor(bi, o), ot = __shfl_xor(bt, o);
+        if (ot >= 0 && (bt < 0 || ov > bv || (ov == bv && oi < bi))) {
+          bv = ov;
+          bi = oi;
+          bt = ot;
         }
-        __threadfence_block();
-        __builtin_amdgcn_wave_barrier();
       }
-      double sc = -INFINITY;
-      int32_t id = 0x7fffffff;
-      if (lane < n) {
-        sc = csc[wave][lane];
-        id = l1_order32[s1 + cand[wave][lane]];
+      if (lane == 0) {
+        cpick[wave][bt] = 1;
+        chosen[wave][r] = bi;
       }
-      int rank = 0;
-      for (int u = 0; u < n; ++u) {
-        const double su = __shfl(sc, u);
-        const int32_t iu = __shfl(id, u);
-        rank += (su > sc) || (su == sc && iu < id);
-      }
-      if (lane < n && rank < c) routed[q * c + rank] = id;
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
     }
+    // decided when every chosen band lies above every other band
+    double lo = INFINITY, hi = -INFINITY;
+    for (int t = lane; t < n; t += 64) {
+      if (cpick[wave][t])
+        lo = fmin(lo, clo[wave][t]);
+      else
+        hi = fmax(hi, chi[wave][t]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, o));
+      hi = fmax(hi, __shfl_xor(hi, o));
+    }
+    if (!(lo > hi))
+      route_fp64_wave(qv, d, cent_l1, l1_order32, 0, n, cq, c, rs64 + q * lcap, chosen[wave]);
+    for (int t = lane; t < c; t += 64) routed[q * c + t] = chosen[wave][t];
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
   }
 }
 
-// Routing, one workgroup per query (any c): radix selection of c + 1.
-template <bool FP8>
-__global__ __launch_bounds__(kRouteNT) void route_select_block_kernel(
-    const float* __restrict__ Q, int32_t d, int64_t nq, const float* __restrict__ cent_l1,
-    const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
-    const float* __restrict__ qnorm, const float* __restrict__ cent_norm_max, int32_t c,
-    int32_t r1, const float* __restrict__ rs, double* __restrict__ rs64,
-    int32_t* __restrict__ routed, int32_t ws, const int32_t* __restrict__ lst) {
+// Approximate routing of the precision form for c > 64, one workgroup per
+// query: radix selection of the c best window scores.
+__global__ __launch_bounds__(kRouteNT) void route_approx_block_kernel(
+    int64_t nq, const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
+    int32_t wst, const int32_t* __restrict__ lst, int32_t lcap, const float* __restrict__ rs,
+    int32_t rstride, int dense, int32_t c, int32_t* __restrict__ routed) {
   __shared__ SelShared sh;
   __shared__ uint64_t srt[256];
   __shared__ int32_t sidx[256];
-  __shared__ int s_amb;
-  __shared__ int32_t chosen[LIDER_MAX_C];
   const int tid = threadIdx.x;
   for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
-    const int32_t s1 = l1[ws * q + 1], len1 = l1[ws * q + 2];
-    const int32_t* lq = lst ? lst + q * r1 : nullptr;
-    const float* rsq = rs + q * r1;
-    const int K = min(c + 1, len1);
+    const int32_t s1 = l1[wst * q + 1], len1 = l1[wst * q + 2];
+    const int32_t* lq = lst ? lst + q * lcap : nullptr;
+    const float* rsq = rs + q * rstride;
+    auto pos_of = [&](int i) { return lq ? lq[i] : s1 + i; };
+    const int K = min(c, len1);
     const int KP = pow2_at_least(K);
     block_select<kRouteNT>(
-        len1, K, KP, [&](int i) { return score_key(rsq[i]); },
-        [&](int i) { return uint32_t(l1_order32[lq ? lq[i] : s1 + i]); }, srt, sidx, sh);
-    if (tid == 0) {
-      s_amb = 0;
-      if (!FP8 && len1 > c) {
-        const double sc = double(key_score(uint32_t(srt[c - 1] >> 32)));
-        const double sn = double(key_score(uint32_t(srt[c] >> 32)));
-        s_amb = (sc - sn) <= 4.0 * route_err(d, qnorm[q], *cent_norm_max);
-      }
-    }
-    __syncthreads();
-    if (!s_amb) {
-      for (int t = tid; t < c; t += kRouteNT)
-        routed[q * c + t] = t < len1 ? int32_t(srt[t] & 0xffffffffu) : -1;
-    } else {
-      if (tid < 64)
-        route_fp64_wave(Q + q * d, d, cent_l1, l1_order32, s1, len1, lq, c, rs64 + q * r1,
-                        chosen);
-      __syncthreads();
-      for (int t = tid; t < c; t += kRouteNT) routed[q * c + t] = chosen[t];
-    }
+        len1, K, KP, [&](int i) { return score_key(rsq[dense ? pos_of(i) : i]); },
+        [&](int i) { return uint32_t(l1_order32[pos_of(i)]); }, srt, sidx, sh);
+    for (int t = tid; t < c; t += kRouteNT)
+      routed[q * c + t] = t < K ? int32_t(srt[t] & 0xffffffffu) : -1;
     __syncthreads();
   }
 }
@@ -1002,7 +1098,6 @@ constexpr int kRerankWaves = 4;
 __device__ inline int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-constexpr int32_t kBufWord3 = 0x00020000;  // buffer resource word 3 for gfx9-family targets
 
 // Operand feeds.  FMT 0: fp32 rows and queries; 1: bf16 rows and queries;
 // 2: fp8 e4m3 rows (decoded exactly to bf16) and bf16 queries; 3 / 4: fp32 /
@@ -1637,6 +1732,7 @@ __global__ __launch_bounds__(kSelNT) void select_kernel(
 // the shortlist of sorted-row indices.  drop: NaN scores (key 0xffffffff) are
 // not candidates (rows of a union's hull outside the union).
 constexpr int kWaveKeyCache = 2048;
+constexpr int kSelList = 256;
 
 template <int MODE, int R>
 __global__ __launch_bounds__(256) void wave_select_kernel(
@@ -1650,7 +1746,10 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
   __shared__ uint64_t ext[4][65];
   __shared__ uint32_t wkey[4][64], wid[4][64];
   __shared__ int64_t wrow[4][64];
+  __shared__ uint32_t lkey[4][kSelList];
+  __shared__ int32_t lidx[4][kSelList];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t below = (uint64_t(1) << lane) - 1;
   for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
     if (lane == 0) {
       int32_t acc = 0;
@@ -1706,41 +1805,101 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
         kr[j] = kv;
       }
     }
-    // extraction of the K + 1 smallest (key, index)
+    // extraction of the K + 1 smallest (key, index).  First a threshold: tau =
+    // the (K+1)-th smallest of the 64 lane minima, so at least K + 1
+    // candidates have key <= tau; those candidates (usually few) are listed
+    // in LDS and the extraction runs over the list.  The list holds every
+    // candidate the full extraction would take, so the result is the same;
+    // a list longer than kSelList falls back to extracting over everything.
     const int want = min(n, K + 1);
     const uint32_t kdrop = drop ? 0xffffffffu : 0u;  // 0: never matches a real key test below
-    uint64_t prev = 0;
-    int nx = 0;
-    for (int r = 0; r < want; ++r) {
-      uint64_t best = ~uint64_t(0);
+    // f(index, key, valid) over the lane's candidates, the same number of
+    // calls on every lane (ballots inside f see the whole wave)
+    auto scan = [&](auto&& f) {
       if (R > 0) {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
           const int32_t i = lane + 64 * j;
-          const uint64_t v = (uint64_t(kr[j]) << 32) | uint32_t(i);
-          if (i < n && !(drop && kr[j] == kdrop) && (r == 0 || v > prev) && v < best) best = v;
+          f(i, kr[j], i < n);
         }
       } else if (cached) {
-        for (int32_t i = lane; i < n; i += 64) {
-          const uint32_t kk = keys[wave][i];
-          const uint64_t v = (uint64_t(kk) << 32) | uint32_t(i);
-          if (!(drop && kk == kdrop) && (r == 0 || v > prev) && v < best) best = v;
+        for (int32_t i0 = 0; i0 < n; i0 += 64) {
+          const int32_t i = i0 + lane;
+          f(i, i < n ? keys[wave][i] : 0xffffffffu, i < n);
         }
       } else {
         for (int t = 0; t < c; ++t) {
           const int32_t a = st[t], len = st[t + 1] - a;
-          for (int p = lane; p < len; p += 64) {
-            const uint32_t kk = score_key(sbq[int64_t(t) * rcap + p]);
-            const uint64_t v = (uint64_t(kk) << 32) | uint32_t(a + p);
-            if (!(drop && kk == kdrop) && (r == 0 || v > prev) && v < best) best = v;
+          for (int p0 = 0; p0 < len; p0 += 64) {
+            const int p = p0 + lane;
+            f(a + p, p < len ? score_key(sbq[int64_t(t) * rcap + p]) : 0xffffffffu, p < len);
           }
         }
       }
-      best = wave_min_u64(best);
-      if (best == ~uint64_t(0)) break;  // no candidate left (wave-uniform)
-      if (lane == 0) ext[wave][r] = best;
-      prev = best;
-      ++nx;
+    };
+    uint32_t lmin = 0xffffffffu;
+    scan([&](int32_t, uint32_t kk, bool ok) {
+      if (ok && !(drop && kk == kdrop)) lmin = kk < lmin ? kk : lmin;
+    });
+    // tau by bisection on ballot counts: the smallest x with at least
+    // `want` lane minima <= x
+    uint32_t tau;
+    {
+      uint32_t lo = 0u, hi = 0xffffffffu;
+      while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (__popcll(__ballot(lmin <= mid)) >= want)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      tau = lo;
+    }
+    int m = 0;
+    scan([&](int32_t i, uint32_t kk, bool ok) {
+      const bool in = ok && kk <= tau && !(drop && kk == kdrop);
+      const uint64_t bal = __ballot(in);
+      const int slot = m + __popcll(bal & below);
+      if (in && slot < kSelList) {
+        lkey[wave][slot] = kk;
+        lidx[wave][slot] = i;
+      }
+      m += __popcll(bal);
+    });
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    const bool listed = m <= kSelList;
+    uint64_t prev = 0;
+    int nx = 0;
+    if (listed && m <= 64) {
+      // few listed: each lane ranks one entry against all of them
+      uint64_t mine = ~uint64_t(0);
+      if (lane < m) mine = (uint64_t(lkey[wave][lane]) << 32) | uint32_t(lidx[wave][lane]);
+      int rank = 0;
+      for (int u = 0; u < m; ++u)
+        rank += ((uint64_t(lkey[wave][u]) << 32) | uint32_t(lidx[wave][u])) < mine;
+      if (lane < m && rank < want) ext[wave][rank] = mine;
+      nx = min(m, want);
+    } else {
+      for (int r = 0; r < want; ++r) {
+        uint64_t best = ~uint64_t(0);
+        if (listed) {
+          for (int u = lane; u < m; u += 64) {
+            const uint64_t v = (uint64_t(lkey[wave][u]) << 32) | uint32_t(lidx[wave][u]);
+            if ((r == 0 || v > prev) && v < best) best = v;
+          }
+        } else {
+          scan([&](int32_t i, uint32_t kk, bool ok) {
+            const uint64_t v = (uint64_t(kk) << 32) | uint32_t(i);
+            if (ok && !(drop && kk == kdrop) && (r == 0 || v > prev) && v < best) best = v;
+          });
+        }
+        best = wave_min_u64(best);
+        if (best == ~uint64_t(0)) break;  // no candidate left (wave-uniform)
+        if (lane == 0) ext[wave][r] = best;
+        prev = best;
+        ++nx;
+      }
     }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
@@ -2153,11 +2312,12 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   int32_t* aflag = reinterpret_cast<int32_t*>(W + p.o_aflag);
   int32_t* alist = reinterpret_cast<int32_t*>(W + p.o_alist);
   uint64_t* kq = reinterpret_cast<uint64_t*>(W + p.o_kq);
-  float* rsd = reinterpret_cast<float*>(W + p.o_rsd);
   int32_t* lst = reinterpret_cast<int32_t*>(W + p.o_lst);
   int32_t* rw = reinterpret_cast<int32_t*>(W + p.o_rw);
   Pair* pw = reinterpret_cast<Pair*>(W + p.o_pw);
   uint32_t* pmask = reinterpret_cast<uint32_t*>(W + p.o_mask);
+  int32_t* rcand = reinterpret_cast<int32_t*>(W + p.o_rcand);
+  int32_t* rcnt = reinterpret_cast<int32_t*>(W + p.o_rcnt);
   const int32_t m = ix.m, C = ix.C, H = ix.H;
   const int64_t np = nq * c;
   const bool bf16 = o.precision == LIDER_BF16;
@@ -2182,61 +2342,59 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
                        ix.l1_keys, (const int64_t*)nullptr, int64_t(C), l1pairs, nl1, kq, p.r1,
                        m, o.expand_bits, l1, H, int64_t(C));
   const bool fp8 = bf16 && ix.cent8;
-  // exact routing from bf16 candidates: dense layer 1, fp32 path, c < 64
-  const bool refine = !bf16 && p.r1 == C && o.l1_dense == 0 && c + 1 <= 64 && ix.cent_l1_b;
-  if (fp8 || bf16 || refine)
+  // Layer-1 scores: dense rows (every centroid; bf16 product unless fp32 is
+  // asked for or the bf16 copy is missing, fp8 in the precision form) or the
+  // window kernel; then the exact routing (or the precision form's
+  // approximate fp8 routing) over each query's window or union list.
+  const bool l1b = !fp8 && o.l1_dense == 0 && ix.cent_l1_b;
+  if (fp8 || bf16 || l1b)
     hipLaunchKernelGGL(to_bf16_kernel, dim3(2048), dim3(256), 0, st, Q, nq * ix.d, qb);
   const unsigned qgrid = unsigned(std::min<int64_t>(nq, 65535));
   const unsigned wgrid = unsigned(std::min<int64_t>((nq + 3) / 4, 65535));
-  // the window each routing kernel reads: (l1[wst q + 1], l1[wst q + 2]); with
-  // several arrays and r1 < C, the union list in rw / lst with its scores in rs
+  // the window each routing kernel reads: (l1w[wst q + 1], l1w[wst q + 2]);
+  // with several arrays and r1 < C, the union list in rw / lst
   const int32_t* l1w = l1;
   int32_t wst = 3 * H;
   const int32_t* lstp = nullptr;
-  if (refine) {
-    launch_l1_gemm_bf16(ix, nq, qb, rs, st);
-  } else if (p.l1_list) {
-    launch_l1_gemm(ix, fp8, nq, Q, qb, rsd, st);
+  if (p.l1_list) {
     const size_t lds = 4 * size_t((C + 31) / 32) * 4;
     hipLaunchKernelGGL(l1_union_kernel, dim3(wgrid), dim3(256), lds, st, l1, H, nq, C, ix.l1map,
-                       rsd, p.lcap, lst, rs, rw);
+                       p.lcap, lst, rw);
     l1w = rw;
     wst = 3;
     lstp = lst;
-  } else if (p.r1 == C && (o.l1_dense >= 0 || H > 1)) {
-    launch_l1_gemm(ix, fp8, nq, Q, qb, rs, st);
-  } else {
-    launch_l1_scores(ix, fp8, nq, l1cs, l1pairs, Q, qb, rs, p.r1, st);
   }
-  if (refine) {
+  double ecoef = dot_err_coef(ix.d);  // fp32 scores
+  if (!p.l1_dense_rows) {
+    launch_l1_scores(ix, fp8, nq, l1cs, l1pairs, Q, qb, rs, p.r1, st);
+  } else if (l1b) {
+    launch_l1_gemm_bf16(ix, nq, qb, rs, st);
     const double u = 0.00390625;  // 2^-8: bf16 rounding of each operand
-    const double ecoef = 2.0 * u + u * u + dot_err_coef(ix.d) * (1.0 + u) * (1.0 + u);
-    if (p.r1 <= 16 * 64)
-      hipLaunchKernelGGL(route_refine_kernel<16>, dim3(wgrid), dim3(256), 0, st, Q, ix.d, nq,
-                         ix.cent_l1, ix.l1_order32, l1w, qnorm, ix.cent_norm_max, ecoef, c, p.r1,
-                         rs, rs64, routed, wst);
-    else
-      hipLaunchKernelGGL(route_refine_kernel<0>, dim3(wgrid), dim3(256), 0, st, Q, ix.d, nq,
-                         ix.cent_l1, ix.l1_order32, l1w, qnorm, ix.cent_norm_max, ecoef, c, p.r1,
-                         rs, rs64, routed, wst);
-  } else if (c + 1 <= 64) {
-    if (fp8)
-      hipLaunchKernelGGL(route_select_wave_kernel<true>, dim3(wgrid), dim3(256), 0, st, Q, ix.d,
-                         nq, ix.cent_l1, ix.l1_order32, l1w, qnorm, ix.cent_norm_max, c, p.lcap,
-                         rs, rs64, routed, wst, lstp);
-    else
-      hipLaunchKernelGGL(route_select_wave_kernel<false>, dim3(wgrid), dim3(256), 0, st, Q, ix.d,
-                         nq, ix.cent_l1, ix.l1_order32, l1w, qnorm, ix.cent_norm_max, c, p.lcap,
-                         rs, rs64, routed, wst, lstp);
+    ecoef = 2.0 * u + u * u + dot_err_coef(ix.d) * (1.0 + u) * (1.0 + u);
   } else {
-    if (fp8)
-      hipLaunchKernelGGL(route_select_block_kernel<true>, dim3(qgrid), dim3(kRouteNT), 0, st, Q,
-                         ix.d, nq, ix.cent_l1, ix.l1_order32, l1w, qnorm, ix.cent_norm_max, c,
-                         p.lcap, rs, rs64, routed, wst, lstp);
+    launch_l1_gemm(ix, fp8, nq, Q, qb, rs, st);
+  }
+  const int32_t rstride = p.l1_dense_rows ? C : p.r1;
+  const int dense = p.l1_dense_rows ? 1 : 0;
+  if (fp8) {
+    if (c <= 64)
+      hipLaunchKernelGGL(route_approx_wave_kernel, dim3(wgrid), dim3(256), 0, st, nq,
+                         ix.l1_order32, l1w, wst, lstp, p.lcap, rs, rstride, dense, c, routed);
     else
-      hipLaunchKernelGGL(route_select_block_kernel<false>, dim3(qgrid), dim3(kRouteNT), 0, st, Q,
-                         ix.d, nq, ix.cent_l1, ix.l1_order32, l1w, qnorm, ix.cent_norm_max, c,
-                         p.lcap, rs, rs64, routed, wst, lstp);
+      hipLaunchKernelGGL(route_approx_block_kernel, dim3(qgrid), dim3(kRouteNT), 0, st, nq,
+                         ix.l1_order32, l1w, wst, lstp, p.lcap, rs, rstride, dense, c, routed);
+  } else {
+    if (p.lcap <= 16 * 64)
+      hipLaunchKernelGGL(route_filter_kernel<16>, dim3(wgrid), dim3(256), 0, st, ix.d, nq,
+                         ix.l1_order32, l1w, wst, lstp, p.lcap, rs, rstride, dense, qnorm,
+                         ix.cent_norm_max, ecoef, c, rcand, rcnt, routed);
+    else
+      hipLaunchKernelGGL(route_filter_kernel<0>, dim3(wgrid), dim3(256), 0, st, ix.d, nq,
+                         ix.l1_order32, l1w, wst, lstp, p.lcap, rs, rstride, dense, qnorm,
+                         ix.cent_norm_max, ecoef, c, rcand, rcnt, routed);
+    hipLaunchKernelGGL(route_rescore_kernel, dim3(wgrid), dim3(256), 0, st, Q, ix.d, nq,
+                       ix.cent_l1, ix.l1_order32, l1w, wst, lstp, p.lcap, c, rcand, rcnt, rs64,
+                       routed);
   }
   mark(2);
   Pair* pwp = H > 1 ? pw : nullptr;
