@@ -38,7 +38,8 @@ typedef enum {
   LIDER_ENOMEM = -2,  /* device allocation failed (build only) */
   LIDER_EDEVICE = -3, /* a HIP runtime call failed */
   LIDER_ERANGE = -4,  /* a hash value does not fit in int32 */
-  LIDER_EBUSY = -5    /* reserved */
+  LIDER_EBUSY = -5,   /* reserved */
+  LIDER_EIO = -6      /* file open / read / write failed, or not an index file */
 } lider_status;
 
 typedef enum {
@@ -251,6 +252,7 @@ typedef struct {
   double w;
   int32_t storage, centroid_storage;
   int32_t n_arrays;         /* hashkey arrays per core model */
+  int32_t hash_kind;        /* LIDER_HASH_E2LSH or LIDER_HASH_SIGN */
 } lider_info;
 
 int lider_get_info(const lider_index* index, lider_info* out);
@@ -281,6 +283,23 @@ typedef enum {
 size_t lider_export_bytes(const lider_index* index, int32_t what);
 /* Copy one array to host memory dst_host of dst_bytes >= lider_export_bytes. */
 int lider_export(const lider_index* index, int32_t what, void* dst_host, size_t dst_bytes);
+
+/* ------------------------------------------------------------ persistence */
+
+/* Write the whole index (every device array and the parameters) to the file
+ * `path` (created or truncated), synchronously: the parameters, then each
+ * array as a tagged, sized section in a fixed order (the format is this
+ * library's own, for the same byte order).  A corpus of n x d fp32 takes
+ * 4 n d bytes plus the per-array tables.  Errors: EINVAL, EIO, EDEVICE. */
+int lider_save(const lider_index* index, const char* path);
+
+/* Read an index written by lider_save onto the current HIP device: allocate
+ * its device memory, copy every section, rebuild the host-side tables.  The
+ * loaded index searches bit-identically to the saved one.  Runs on `stream`
+ * and synchronises it.  Errors: EINVAL (NULL argument), EIO (missing or
+ * truncated file, wrong format or version, section sizes that do not match
+ * the parameters), ENOMEM, EDEVICE; on error *out is NULL. */
+int lider_load(const char* path, void* stream, lider_index** out);
 
 /* ------------------------------------------------------- stand-alone kernels */
 

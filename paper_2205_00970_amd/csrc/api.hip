@@ -1,5 +1,6 @@
 // The C ABI (include/lider.h): argument validation, index allocation and
 // lifetime, build orchestration, search dispatch, exports and error state.
+#include <cstdio>
 #include <cstring>
 #include <new>
 
@@ -45,6 +46,50 @@ void free_device(Index& ix) {
                   ix.tile_base[2], ix.amap,  ix.l1map};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+}
+
+// Device arrays of an index whose parameters are set (build and load).
+int alloc_index(Index& ix) {
+  const int64_t n = ix.n, d = ix.d, C = ix.C, m = ix.m, H = ix.H;
+  const int64_t nleaf = H * (C * ix.F2 + ix.F1);
+  const int64_t nh = 2 * H * m;
+  int rc = LIDER_OK;
+#define TRY(x)                    \
+  do {                            \
+    if (rc == LIDER_OK) rc = (x); \
+  } while (0)
+  TRY(alloc(&ix.X, size_t(n) * d, "reordered corpus"));
+  if (ix.storage == LIDER_BF16) TRY(alloc(&ix.Xb, size_t(n) * d, "bf16 corpus"));
+  TRY(alloc(&ix.perm, size_t(H) * n, "perm"));
+  TRY(alloc(&ix.perm32, size_t(n), "perm32"));
+  TRY(alloc(&ix.keys, size_t(H) * n, "keys"));
+  TRY(alloc(&ix.digits, size_t(H) * n * m, "digits"));
+  if (H > 1) {
+    TRY(alloc(&ix.amap, size_t(H - 1) * n, "array position maps"));
+    TRY(alloc(&ix.l1map, size_t(H - 1) * C, "layer-1 array position maps"));
+  }
+  TRY(alloc(&ix.assign, size_t(n), "assignment"));
+  TRY(alloc(&ix.off, size_t(C) + 1, "offsets"));
+  TRY(alloc(&ix.cent, size_t(C) * d, "centroids"));
+  TRY(alloc(&ix.cent_l1, size_t(C) * d, "layer-1 centroids"));
+  if (ix.centroid_storage == LIDER_FP8E4M3) {
+    TRY(alloc(&ix.cent8, size_t(C) * d, "fp8 centroids"));
+    TRY(alloc(&ix.cent8_scale, size_t(C), "fp8 scales"));
+  }
+  if (d % 8 == 0) TRY(alloc(&ix.cent_l1_b, size_t(C) * d, "bf16 layer-1 centroids"));
+  TRY(alloc(&ix.l1_order, size_t(H) * C, "layer-1 order"));
+  TRY(alloc(&ix.l1_order32, size_t(C), "layer-1 order"));
+  TRY(alloc(&ix.l1_keys, size_t(H) * C, "layer-1 keys"));
+  TRY(alloc(&ix.l1_digits, size_t(H) * C * m, "layer-1 digits"));
+  TRY(alloc(&ix.A, size_t(nh) * d, "LSH projections"));
+  TRY(alloc(&ix.b, size_t(nh), "LSH offsets"));
+  TRY(alloc(&ix.anorm, size_t(nh), "LSH norms"));
+  TRY(alloc(&ix.cent_norm_max, 64, "centroid norm"));
+  TRY(alloc(&ix.models, size_t(H) * (C + 1), "models"));
+  TRY(alloc(&ix.leaves, size_t(nleaf) * 2, "leaves"));
+  TRY(alloc(&ix.leaf_err, size_t(nleaf) * 2, "leaf errors"));
+#undef TRY
+  return rc;
 }
 
 }  // namespace
@@ -135,43 +180,13 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
       ix.n_cu = prop.multiProcessorCount;
   }
   const int64_t C = ix.C, m = ix.m, H = ix.H;
-  const int64_t nleaf = H * (C * ix.F2 + ix.F1);
   int rc = LIDER_OK;
 #define TRY(x)                 \
   do {                         \
     if (rc == LIDER_OK) rc = (x); \
   } while (0)
-  TRY(alloc(&ix.X, size_t(n) * d, "reordered corpus"));
-  if (ix.storage == LIDER_BF16) TRY(alloc(&ix.Xb, size_t(n) * d, "bf16 corpus"));
-  TRY(alloc(&ix.perm, size_t(H) * n, "perm"));
-  TRY(alloc(&ix.perm32, size_t(n), "perm32"));
-  TRY(alloc(&ix.keys, size_t(H) * n, "keys"));
-  TRY(alloc(&ix.digits, size_t(H) * n * m, "digits"));
-  if (H > 1) {
-    TRY(alloc(&ix.amap, size_t(H - 1) * n, "array position maps"));
-    TRY(alloc(&ix.l1map, size_t(H - 1) * C, "layer-1 array position maps"));
-  }
-  TRY(alloc(&ix.assign, size_t(n), "assignment"));
-  TRY(alloc(&ix.off, size_t(C) + 1, "offsets"));
-  TRY(alloc(&ix.cent, size_t(C) * d, "centroids"));
-  TRY(alloc(&ix.cent_l1, size_t(C) * d, "layer-1 centroids"));
-  if (ix.centroid_storage == LIDER_FP8E4M3) {
-    TRY(alloc(&ix.cent8, size_t(C) * d, "fp8 centroids"));
-    TRY(alloc(&ix.cent8_scale, size_t(C), "fp8 scales"));
-  }
-  if (d % 8 == 0) TRY(alloc(&ix.cent_l1_b, size_t(C) * d, "bf16 layer-1 centroids"));
-  TRY(alloc(&ix.l1_order, size_t(H) * C, "layer-1 order"));
-  TRY(alloc(&ix.l1_order32, size_t(C), "layer-1 order"));
-  TRY(alloc(&ix.l1_keys, size_t(H) * C, "layer-1 keys"));
-  TRY(alloc(&ix.l1_digits, size_t(H) * C * m, "layer-1 digits"));
+  TRY(alloc_index(ix));
   const int64_t nh = 2 * H * m;
-  TRY(alloc(&ix.A, size_t(nh) * d, "LSH projections"));
-  TRY(alloc(&ix.b, size_t(nh), "LSH offsets"));
-  TRY(alloc(&ix.anorm, size_t(nh), "LSH norms"));
-  TRY(alloc(&ix.cent_norm_max, 64, "centroid norm"));
-  TRY(alloc(&ix.models, size_t(H) * (C + 1), "models"));
-  TRY(alloc(&ix.leaves, size_t(nleaf) * 2, "leaves"));
-  TRY(alloc(&ix.leaf_err, size_t(nleaf) * 2, "leaf errors"));
   TRY(check_hip(hipMemcpyAsync(ix.A, P->lsh_a_host, size_t(nh) * d * 4, hipMemcpyHostToDevice, st),
                 "copy LSH projections"));
   if (P->lsh_b_host)
@@ -238,6 +253,7 @@ int lider_get_info(const lider_index* index, lider_info* out) {
   out->storage = ix.storage;
   out->centroid_storage = ix.centroid_storage;
   out->n_arrays = ix.H;
+  out->hash_kind = ix.hash_kind;
   return LIDER_OK;
 }
 
@@ -431,6 +447,192 @@ int lider_export(const lider_index* index, int32_t what, void* dst_host, size_t 
       o[2] = M[j].root_b;
     }
   }
+  return LIDER_OK;
+}
+
+// ------------------------------------------------------------ persistence
+namespace {
+constexpr char kMagic[8] = {'L', 'I', 'D', 'E', 'R', 'I', 'X', '1'};
+constexpr uint32_t kVersion = 1;
+
+struct FileHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  int64_t n, max_cluster;
+  int32_t d, C, m, F2, F1, H, iters_run, storage, centroid_storage, hash_kind, has_cent_l1_b, pad;
+  double w;
+};
+
+struct Section {
+  uint32_t tag;
+  void* dev;
+  size_t bytes;
+};
+
+// Every device array of the index in file order (absent ones have 0 bytes).
+std::vector<Section> sections(const Index& ix) {
+  const size_t n = size_t(ix.n), d = size_t(ix.d), C = size_t(ix.C), m = size_t(ix.m);
+  const size_t H = size_t(ix.H), nh = 2 * H * m, nleaf = H * (C * ix.F2 + ix.F1);
+  auto sz = [](const void* p, size_t b) { return p ? b : size_t(0); };
+  return {{1, ix.X, n * d * 4},
+          {2, ix.Xb, sz(ix.Xb, n * d * 2)},
+          {3, ix.perm, H * n * 8},
+          {4, ix.perm32, n * 4},
+          {5, ix.keys, H * n * 8},
+          {6, ix.digits, H * n * m * 4},
+          {7, ix.assign, n * 4},
+          {8, ix.off, (C + 1) * 8},
+          {9, ix.cent, C * d * 4},
+          {10, ix.cent_l1, C * d * 4},
+          {11, ix.cent8, sz(ix.cent8, C * d)},
+          {12, ix.cent8_scale, sz(ix.cent8_scale, C * 4)},
+          {13, ix.cent_l1_b, sz(ix.cent_l1_b, C * d * 2)},
+          {14, ix.l1_order, H * C * 8},
+          {15, ix.l1_order32, C * 4},
+          {16, ix.l1_keys, H * C * 8},
+          {17, ix.l1_digits, H * C * m * 4},
+          {18, ix.A, nh * d * 4},
+          {19, ix.b, nh * 4},
+          {20, ix.anorm, nh * 4},
+          {21, ix.cent_norm_max, 4},
+          {22, ix.models, H * (C + 1) * sizeof(Model)},
+          {23, ix.leaves, nleaf * 2 * 8},
+          {24, ix.leaf_err, nleaf * 2 * 4},
+          {25, ix.amap, sz(ix.amap, (H - 1) * n * 4)},
+          {26, ix.l1map, sz(ix.l1map, (H - 1) * C * 4)}};
+}
+
+constexpr size_t kStage = size_t(64) << 20;  // host staging per copy
+
+struct FileCloser {
+  FILE* f;
+  ~FileCloser() {
+    if (f) fclose(f);
+  }
+};
+}  // namespace
+
+int lider_save(const lider_index* index, const char* path) {
+  g_err.clear();
+  if (!index || !path) return set_error(LIDER_EINVAL, "NULL argument");
+  const Index& ix = index->ix;
+  FileCloser fc{fopen(path, "wb")};
+  if (!fc.f) return set_error(LIDER_EIO, std::string("cannot open ") + path + " for writing");
+  FileHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kMagic, 8);
+  h.version = kVersion;
+  h.header_bytes = sizeof(FileHeader);
+  h.n = ix.n;
+  h.max_cluster = ix.max_cluster;
+  h.d = ix.d;
+  h.C = ix.C;
+  h.m = ix.m;
+  h.F2 = ix.F2;
+  h.F1 = ix.F1;
+  h.H = ix.H;
+  h.iters_run = ix.iters_run;
+  h.storage = ix.storage;
+  h.centroid_storage = ix.centroid_storage;
+  h.hash_kind = ix.hash_kind;
+  h.has_cent_l1_b = ix.cent_l1_b != nullptr;
+  h.w = ix.w;
+  if (fwrite(&h, sizeof(h), 1, fc.f) != 1) return set_error(LIDER_EIO, "write failed");
+  std::vector<char> stage;
+  for (const Section& sec : sections(ix)) {
+    const uint64_t bytes = sec.bytes;
+    if (fwrite(&sec.tag, 4, 1, fc.f) != 1 || fwrite(&bytes, 8, 1, fc.f) != 1)
+      return set_error(LIDER_EIO, "write failed");
+    stage.resize(std::min(sec.bytes, kStage));
+    for (size_t at = 0; at < sec.bytes; at += kStage) {
+      const size_t nb = std::min(kStage, sec.bytes - at);
+      int rc = check_hip(hipMemcpy(stage.data(), static_cast<char*>(sec.dev) + at, nb,
+                                   hipMemcpyDeviceToHost),
+                         "save: device to host");
+      if (rc != LIDER_OK) return rc;
+      if (fwrite(stage.data(), 1, nb, fc.f) != nb) return set_error(LIDER_EIO, "write failed");
+    }
+  }
+  if (fflush(fc.f) != 0) return set_error(LIDER_EIO, "write failed");
+  return LIDER_OK;
+}
+
+int lider_load(const char* path, void* stream, lider_index** out) {
+  g_err.clear();
+  if (!out) return set_error(LIDER_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!path) return set_error(LIDER_EINVAL, "path is NULL");
+  FileCloser fc{fopen(path, "rb")};
+  if (!fc.f) return set_error(LIDER_EIO, std::string("cannot open ") + path);
+  FileHeader h;
+  if (fread(&h, sizeof(h), 1, fc.f) != 1 || std::memcmp(h.magic, kMagic, 8) != 0 ||
+      h.version != kVersion || h.header_bytes != sizeof(FileHeader))
+    return set_error(LIDER_EIO, "not a LIDER index file of this version");
+  if (h.n < 1 || h.n > INT32_MAX || h.d < 1 || h.d > 65536 || h.C < 1 || h.C > h.n || h.m < 1 ||
+      h.m > LIDER_MAX_M || h.H < 1 || h.H > LIDER_MAX_H || h.F2 < 1 || h.F1 < 1 ||
+      (h.storage != LIDER_F32 && h.storage != LIDER_BF16) ||
+      (h.centroid_storage != LIDER_F32 && h.centroid_storage != LIDER_FP8E4M3) ||
+      (h.hash_kind != LIDER_HASH_E2LSH && h.hash_kind != LIDER_HASH_SIGN) ||
+      h.has_cent_l1_b != (h.d % 8 == 0))
+    return set_error(LIDER_EIO, "index file parameters out of range");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  lider_index* li = new (std::nothrow) lider_index();
+  if (!li) return set_error(LIDER_ENOMEM, "out of host memory");
+  Index& ix = li->ix;
+  ix.n = h.n;
+  ix.d = h.d;
+  ix.C = h.C;
+  ix.m = h.m;
+  ix.F2 = h.F2;
+  ix.F1 = h.F1;
+  ix.H = h.H;
+  ix.w = h.w;
+  ix.iters_run = h.iters_run;
+  ix.storage = h.storage;
+  ix.centroid_storage = h.centroid_storage;
+  ix.hash_kind = h.hash_kind;
+  (void)hipGetDevice(&ix.device);
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ix.device) == hipSuccess && prop.multiProcessorCount > 0)
+      ix.n_cu = prop.multiProcessorCount;
+  }
+  int rc = alloc_index(ix);
+  std::vector<char> stage;
+  if (rc == LIDER_OK) {
+    for (const Section& sec : sections(ix)) {
+      uint32_t tag = 0;
+      uint64_t bytes = 0;
+      if (fread(&tag, 4, 1, fc.f) != 1 || fread(&bytes, 8, 1, fc.f) != 1 || tag != sec.tag ||
+          bytes != sec.bytes) {
+        rc = set_error(LIDER_EIO, "index file section " + std::to_string(sec.tag) +
+                                      " missing or of the wrong size");
+        break;
+      }
+      stage.resize(std::min(sec.bytes, kStage));
+      for (size_t at = 0; at < sec.bytes && rc == LIDER_OK; at += kStage) {
+        const size_t nb = std::min(kStage, sec.bytes - at);
+        if (fread(stage.data(), 1, nb, fc.f) != nb) {
+          rc = set_error(LIDER_EIO, "index file truncated");
+          break;
+        }
+        rc = check_hip(hipMemcpyAsync(static_cast<char*>(sec.dev) + at, stage.data(), nb,
+                                      hipMemcpyHostToDevice, st),
+                       "load: host to device");
+        if (rc == LIDER_OK) rc = check_hip(hipStreamSynchronize(st), "load");
+      }
+      if (rc != LIDER_OK) break;
+    }
+  }
+  if (rc == LIDER_OK && fgetc(fc.f) != EOF) rc = set_error(LIDER_EIO, "trailing bytes in index file");
+  if (rc == LIDER_OK) rc = finish_index(ix);
+  if (rc == LIDER_OK && ix.max_cluster != h.max_cluster)
+    rc = set_error(LIDER_EIO, "index file offsets do not match its parameters");
+  if (rc != LIDER_OK) {
+    lider_free(li);
+    return rc;
+  }
+  *out = li;
   return LIDER_OK;
 }
 

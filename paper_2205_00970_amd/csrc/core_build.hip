@@ -484,6 +484,14 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
   if (rc != LIDER_OK) return rc;
   if (h_status != 0)
     return set_error(LIDER_ERANGE, "a corpus or centroid hash value does not fit in int32");
+  return finish_index(ix);
+}
+
+// Host copy of the offsets, largest cluster and the rerank tile tables (all
+// derived from the offsets); shared by the build and the index loader.
+int finish_index(Index& ix) {
+  const int32_t C = ix.C;
+  int rc = LIDER_OK;
   ix.h_off.resize(size_t(C) + 1);
   rc = check_hip(hipMemcpy(ix.h_off.data(), ix.off, (size_t(C) + 1) * 8, hipMemcpyDeviceToHost),
                  "copy offsets");
@@ -491,7 +499,7 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
   ix.max_cluster = 0;
   for (int32_t j = 0; j < C; ++j)
     ix.max_cluster = std::max<int64_t>(ix.max_cluster, ix.h_off[j + 1] - ix.h_off[j]);
-  if (H > 1 && ix.max_cluster > kMaxMultiCluster)
+  if (ix.H > 1 && ix.max_cluster > kMaxMultiCluster)
     return set_error(LIDER_EINVAL, "with n_arrays > 1 no cluster may hold more than 65536 rows");
   // rerank tile tables for 32/64/128-row tiles, 4 int32 per tile: cluster,
   // first in-cluster row, first row in the reordered corpus, rows in the tile

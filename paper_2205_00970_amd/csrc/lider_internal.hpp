@@ -224,6 +224,8 @@ size_t centroid_means_scratch(int64_t n, int32_t C);
 
 // core_build.hip
 int build_core_models(Index& ix, const float* Xin, hipStream_t st);
+// offsets on the host, largest cluster, rerank tile tables (after build or load)
+int finish_index(Index& ix);
 
 // search.hip
 size_t search_workspace(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,

@@ -14,7 +14,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libliderhip.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ERANGE, EBUSY = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, ERANGE, EBUSY, EIO = 0, -1, -2, -3, -4, -5, -6
 F32, BF16, FP8E4M3 = 0, 1, 2
 MAX_K, MAX_C, MAX_M = 1024, 128, 16
 
@@ -61,13 +61,13 @@ class Info(C.Structure):
                 ("rmi_fanout", C.c_int32), ("rmi_fanout_l1", C.c_int32),
                 ("kmeans_iters_run", C.c_int32), ("max_cluster", C.c_int64), ("w", C.c_double),
                 ("storage", C.c_int32), ("centroid_storage", C.c_int32),
-                ("n_arrays", C.c_int32)]
+                ("n_arrays", C.c_int32), ("hash_kind", C.c_int32)]
 
 
 SYMBOLS = ["lider_build", "lider_free", "lider_last_error", "lider_search_workspace",
            "lider_search", "lider_search_ex", "lider_get_info", "lider_export_bytes",
            "lider_export", "lider_hash", "lider_kmeans_assign", "lider_profile_begin",
-           "lider_profile_end", "lider_debug_fail_next"]
+           "lider_profile_end", "lider_debug_fail_next", "lider_save", "lider_load"]
 NSTAGES = 5
 STAGES = ["hash", "route", "worklist", "rerank", "select"]
 
@@ -101,6 +101,8 @@ def lib():
         L.lider_profile_end.argtypes = [C.POINTER(C.c_double), C.POINTER(i32)]
         L.lider_debug_fail_next.argtypes = [i32]
         L.lider_debug_fail_next.restype = None
+        L.lider_save.argtypes = [p, C.c_char_p]
+        L.lider_load.argtypes = [C.c_char_p, p, C.POINTER(p)]
         _lib = L
     return _lib
 
@@ -178,14 +180,34 @@ class Index:
         _check(lib().lider_build(cp, n, d, C.byref(P), _stream(stream), C.byref(h)))
         self._h = h
         self._ws = None
-        self.n, self.d = int(n), int(d)
+        self._set_info()
+        self.hash_kind = hash_kind
+
+    def save(self, path):
+        """Write the index to `path` (lider_save)."""
+        _check(lib().lider_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path, stream=None):
+        """Read an index written by save() onto the current device (lider_load)."""
+        h = C.c_void_p()
+        _check(lib().lider_load(os.fsencode(path), _stream(stream), C.byref(h)))
+        self = cls.__new__(cls)
+        self._h = h
+        self._ws = None
+        self._set_info()
+        self.hash_kind = "sign" if self._hash_kind_code == 1 else "e2lsh"
+        return self
+
+    def _set_info(self):
         info = self.info()
+        self.n, self.d = int(info.n), int(info.d)
         self.C, self.m = info.n_clusters, info.m
         self.F2, self.F1 = info.rmi_fanout, info.rmi_fanout_l1
         self.max_cluster = info.max_cluster
         self.iters_run = info.kmeans_iters_run
         self.H = info.n_arrays
-        self.hash_kind = hash_kind
+        self._hash_kind_code = info.hash_kind
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

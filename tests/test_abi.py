@@ -104,3 +104,17 @@ def test_fail_next_hook_precedes_validation():
     L.lider_debug_fail_next(lider.EBUSY)
     assert L.lider_search(None, None, 0, 1, 1, 1, None, None, None, 0, None) == lider.EBUSY
     assert L.lider_search(None, None, 0, 1, 1, 1, None, None, None, 0, None) == lider.EINVAL
+
+
+def test_save_load_reject_bad_arguments_on_cpu(tmp_path):
+    """Argument checks of the persistence entry points run before any device
+    call: NULL arguments and files that are not index files are rejected."""
+    L = lider.lib()
+    out = C.c_void_p(1)
+    assert L.lider_load(None, None, C.byref(out)) == lider.EINVAL and not out.value
+    assert L.lider_load(os.fsencode(str(tmp_path / "missing.idx")), None, C.byref(out)) == lider.EIO
+    bad = tmp_path / "bad.idx"
+    bad.write_bytes(b"NOTANIDX" + bytes(200))
+    assert L.lider_load(os.fsencode(str(bad)), None, C.byref(out)) == lider.EIO
+    assert not out.value
+    assert L.lider_save(None, os.fsencode(str(tmp_path / "x.idx"))) == lider.EINVAL
