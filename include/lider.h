@@ -157,7 +157,7 @@ const char* lider_last_error(void);
  *                 device and a persistent grid pulls only those (for small or
  *                 sparse batches on large indexes).  Results are identical.
  *  tile_rows      rows per rerank tile (one wave per tile): 32, 64, 128, or 0
- *                 (128 when clusters average at least 512 rows, else 64).
+ *                 (64).
  *  l1_dense       How the layer-1 scores are computed; the routed set is then
  *                 decided exactly (the FP64 definition): the centroids whose
  *                 score lies within twice its rigorous error bound of the c-th
@@ -181,8 +181,7 @@ const char* lider_last_error(void);
  *                 query's in dist_e (ties to the left) until r (r1) positions
  *                 are taken.  Applies to both layers.
  *  pass_pairs     (query, cluster) pairs per MFMA pass of the rerank: 16, 32,
- *                 or 0 (16 when there are at most 12 pairs per cluster on
- *                 average, else 32).  Results are identical. */
+ *                 or 0 (32).  Results are identical. */
 typedef struct {
   int32_t r1;
   int32_t precision;

@@ -17,9 +17,9 @@ import os
 
 KEYS = ("tile_rows", "persistent", "grid_mult", "pass_pairs")
 CANDIDATES = ([dict(tile_rows=t, persistent=0, grid_mult=0, pass_pairs=pp)
-               for t in (64, 128) for pp in (16, 32)]
+               for t in (32, 64, 128) for pp in (16, 32)]
               + [dict(tile_rows=t, persistent=p, grid_mult=g, pass_pairs=0)
-                 for p in (1, 2) for t in (64, 128) for g in (1, 2, 4)])
+                 for p in (1, 2) for t in (32, 64) for g in (1, 2, 4)])
 
 
 def bucket(nq):

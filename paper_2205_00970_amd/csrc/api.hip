@@ -43,7 +43,8 @@ void free_device(Index& ix) {
                   ix.l1_digits, ix.A,        ix.b,        ix.anorm,     ix.cent_norm_max,
                   ix.models, ix.leaves,      ix.leaf_err, ix.tiles[0],  ix.tiles[1],
                   ix.tiles[2], ix.l1_tiles,  ix.tile_base[0], ix.tile_base[1],
-                  ix.tile_base[2], ix.amap,  ix.l1map};
+                  ix.tile_base[2], ix.amap,  ix.l1map,     ix.Xt,        ix.tile_blk[0],
+                  ix.tile_blk[1], ix.tile_blk[2]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }

@@ -406,6 +406,32 @@ __global__ void compose_kernel(const int64_t* __restrict__ permh, int64_t n,
     map[t] = inv[permh[t]];
 }
 
+// Operand-ordered copy of the reordered corpus, one wave per 16-row block:
+// block b takes rows src[b].x .. src[b].x + src[b].y - 1 of X (zeros past
+// them); for every 32-dim k-step and half h, lane l = i + 16 s writes dims
+// [32 ks + 16 h + 4 s, + 4) of row i at float offset ((b nks + ks) 2 + h) 256 + 4 l.
+__global__ __launch_bounds__(256) void tile_corpus_kernel(const float* __restrict__ X, int32_t d,
+                                                          const int2* __restrict__ src,
+                                                          int64_t nblk, float* __restrict__ Xt) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, s = lane >> 4;
+  const int32_t nks = d / kTileKS;
+  for (int64_t b = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); b < nblk;
+       b += int64_t(gridDim.x) * 4) {
+    const int2 sr = src[b];
+    const bool ok = i < sr.y;
+    const float* xr = X + (int64_t(sr.x) + (ok ? i : 0)) * d;
+    float4* out = reinterpret_cast<float4*>(Xt + b * int64_t(nks) * 512);
+    for (int32_t ks = 0; ks < nks; ++ks)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float4 v = ok ? *reinterpret_cast<const float4*>(xr + ks * kTileKS + 16 * h + 4 * s)
+                      : float4{0.f, 0.f, 0.f, 0.f};
+        out[(ks * 2 + h) * 64 + lane] = v;
+      }
+  }
+}
+
 }  // namespace
 
 // Everything after the clustering, for each hashkey array h: layer-2 digits
@@ -501,11 +527,40 @@ int finish_index(Index& ix) {
     ix.max_cluster = std::max<int64_t>(ix.max_cluster, ix.h_off[j + 1] - ix.h_off[j]);
   if (ix.H > 1 && ix.max_cluster > kMaxMultiCluster)
     return set_error(LIDER_EINVAL, "with n_arrays > 1 no cluster may hold more than 65536 rows");
+  // clusters padded to whole 16-row blocks in the operand-ordered copy
+  std::vector<int64_t> pblk(size_t(C) + 1, 0);  // first 16-row block of each cluster
+  for (int32_t j = 0; j < C; ++j) pblk[j + 1] = pblk[j] + (ix.h_off[j + 1] - ix.h_off[j] + 15) / 16;
+  if (ix.d % kTileKS == 0 && pblk[C] > 0) {
+    const int64_t nblk = pblk[C];
+    std::vector<int2> src(static_cast<size_t>(nblk));
+    for (int32_t j = 0; j < C; ++j)
+      for (int64_t b = pblk[j]; b < pblk[j + 1]; ++b) {
+        const int64_t r0 = ix.h_off[j] + 16 * (b - pblk[j]);
+        src[b] = make_int2(int32_t(r0), int32_t(std::min<int64_t>(16, ix.h_off[j + 1] - r0)));
+      }
+    int2* dsrc = nullptr;
+    if (hipMalloc(&ix.Xt, al256(size_t(nblk) * (ix.d / kTileKS) * 512 * 4)) != hipSuccess ||
+        hipMalloc(&dsrc, al256(src.size() * sizeof(int2))) != hipSuccess) {
+      if (dsrc) (void)hipFree(dsrc);
+      return set_error(LIDER_ENOMEM, "out of device memory (operand-ordered corpus)");
+    }
+    rc = check_hip(hipMemcpy(dsrc, src.data(), src.size() * sizeof(int2), hipMemcpyHostToDevice),
+                   "copy block table");
+    if (rc == LIDER_OK) {
+      hipLaunchKernelGGL(tile_corpus_kernel, dim3(unsigned(std::min<int64_t>((nblk + 3) / 4, 65536))),
+                         dim3(256), 0, nullptr, ix.X, ix.d, dsrc, nblk, ix.Xt);
+      rc = check_hip(hipGetLastError(), "operand-ordered corpus");
+      if (rc == LIDER_OK) rc = check_hip(hipDeviceSynchronize(), "operand-ordered corpus");
+    }
+    (void)hipFree(dsrc);
+    if (rc != LIDER_OK) return rc;
+  }
   // rerank tile tables for 32/64/128-row tiles, 4 int32 per tile: cluster,
-  // first in-cluster row, first row in the reordered corpus, rows in the tile
+  // first in-cluster row, first row in the reordered corpus, rows in the tile;
+  // and each tile's first 16-row block in the operand-ordered copy
   const int sizes[3] = {32, 64, 128};
   for (int s = 0; s < 3; ++s) {
-    std::vector<int32_t> t, tb;
+    std::vector<int32_t> t, tb, tk;
     for (int32_t j = 0; j < C; ++j) {
       tb.push_back(int32_t(t.size() / 4));
       const int64_t L = ix.h_off[j + 1] - ix.h_off[j];
@@ -514,9 +569,15 @@ int finish_index(Index& ix) {
         t.push_back(int32_t(r0));
         t.push_back(int32_t(ix.h_off[j] + r0));
         t.push_back(int32_t(std::min<int64_t>(sizes[s], L - r0)));
+        tk.push_back(int32_t(pblk[j] + r0 / 16));
       }
     }
     tb.push_back(int32_t(t.size() / 4));
+    if (hipMalloc(&ix.tile_blk[s], al256(tk.size() * 4 + 4)) != hipSuccess)
+      return set_error(LIDER_ENOMEM, "out of device memory (tile table)");
+    rc = check_hip(hipMemcpy(ix.tile_blk[s], tk.data(), tk.size() * 4, hipMemcpyHostToDevice),
+                   "copy tile blocks");
+    if (rc != LIDER_OK) return rc;
     if (hipMalloc(&ix.tile_base[s], al256(tb.size() * 4)) != hipSuccess)
       return set_error(LIDER_ENOMEM, "out of device memory (tile table)");
     rc = check_hip(hipMemcpy(ix.tile_base[s], tb.data(), tb.size() * 4, hipMemcpyHostToDevice),

@@ -34,6 +34,9 @@ struct alignas(16) Model {
 
 static constexpr uint64_t kKeyLimit = uint64_t(1) << 53;
 
+// Dims per k-step chunk of the operand-ordered corpus copy (Xt).
+static constexpr int kTileKS = 32;
+
 // Largest cluster of a multi-array index: the union of a (query, cluster)
 // pair's windows is marked in a per-wave bitmap of this many bits.
 static constexpr int64_t kMaxMultiCluster = 65536;
@@ -163,6 +166,12 @@ struct Index {
   // Per-array tables are array-major; array 0's sort order is the physical
   // row order (the reordered corpus, tiles, search positions).
   float* X = nullptr;          // [n x d] reordered by array 0's (cluster, key, id)
+  // The same rows in the rerank's MFMA operand order (d a multiple of 32):
+  // each cluster padded with zero rows to a multiple of 16; per 16-row block
+  // and 32-dim k-step one 2 KB chunk of two 1 KB halves, in which lane
+  // l = i + 16 s holds dims [4 s, 4 s + 4) (then [16 + 4 s, 16 + 4 s + 4)) of
+  // row i -- one contiguous 1 KB wave load per half.
+  float* Xt = nullptr;
   __hip_bfloat16* Xb = nullptr;  // [n x d] bf16 copy (precision form)
   int64_t* perm = nullptr;     // [H x n] sorted position of array h -> original id
   int32_t* perm32 = nullptr;   // [n] array 0's, int32
@@ -193,6 +202,7 @@ struct Index {
   int32_t n_tiles[3] = {0, 0, 0};
   int32_t* tiles[3] = {nullptr, nullptr, nullptr};  // [n_tiles x 4]: cluster, row0, global row0, rows
   int32_t* tile_base[3] = {nullptr, nullptr, nullptr};  // [C+1] first tile of each cluster
+  int32_t* tile_blk[3] = {nullptr, nullptr, nullptr};   // [n_tiles] first 16-row block in Xt
   // layer-1 scoring: the C centroids as one 64-row-tiled "cluster"
   int32_t n_l1_tiles = 0;
   int32_t* l1_tiles = nullptr;  // [n_l1_tiles x 4]: 0, row0, row0, rows

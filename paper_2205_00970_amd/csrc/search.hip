@@ -57,13 +57,13 @@ struct Plan {
   int32_t lcap, mw;
 };
 
-// Rerank tile table in use: 0/1/2 = 32/64/128 rows per tile.  Default: 128
-// when clusters average at least 512 rows, else 64.
+// Rerank tile table in use: 0/1/2 = 32/64/128 rows per tile (default 64:
+// measured fastest or within 2 % of it from whole clusters to 256-row windows).
 int tile_index(const Index& ix, const lider_search_opts& o) {
+  (void)ix;
   if (o.tile_rows == 32) return 0;
-  if (o.tile_rows == 64) return 1;
   if (o.tile_rows == 128) return 2;
-  return ix.n >= 512 * int64_t(ix.C) ? 2 : 1;
+  return 1;
 }
 
 Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
@@ -1316,6 +1316,26 @@ struct BufRows {
   }
 };
 
+// Rows of the operand-ordered corpus copy (fp32, 32-dim k-steps): the row
+// block rc of the tile starts rc * nks * 512 floats after the tile's first
+// block, k-step ks 512 floats further; the lane's two 16-byte halves are at
+// 4 lane and 256 + 4 lane -- each half one contiguous 1 KB wave load, read
+// nontemporally (the corpus is streamed once per batch).  Row blocks past
+// the tile's rows are not read (zeros).
+template <int RC>
+struct TileRows {
+  const float* base;  // the tile's first block, plus 4 lane
+  int32_t bstride;    // floats between row blocks
+  int32_t rows;       // rows in the tile
+  __device__ F32x2 load(int rc, int k, int, bool) const {
+    if (16 * rc >= rows) return F32x2{float4{0.f, 0.f, 0.f, 0.f}, float4{0.f, 0.f, 0.f, 0.f}};
+    const float* p = base + rc * bstride + (k / kTileKS) * 512;
+    const floatx4 a = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(p));
+    const floatx4 b = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(p + 256));
+    return F32x2{__builtin_bit_cast(float4, a), __builtin_bit_cast(float4, b)};
+  }
+};
+
 // The k-loop of one pass, software-pipelined with two register sets (no
 // copies of loaded data): the loads of one step are in flight while the MFMAs
 // of the previous step run.  The last load of the paired loop is clamped to
@@ -1389,16 +1409,22 @@ __global__ __launch_bounds__(256) void rerank_kernel(
     const int32_t* __restrict__ wl, const Pair* __restrict__ pairs, int32_t c,
     const void* __restrict__ Qv, float* __restrict__ sbuf, int32_t rcap, int persistent,
     int32_t* __restrict__ ctr, int32_t pair_chunk, const float* __restrict__ row_scale,
-    const int32_t* __restrict__ alist, const uint32_t* __restrict__ pmask, int32_t mw) {
+    const int32_t* __restrict__ alist, const uint32_t* __restrict__ pmask, int32_t mw,
+    const int32_t* __restrict__ tblk) {
   typedef Feed<FMT, VEC> F;
   typedef typename F::XE XE;
   typedef typename F::QE QE;
   constexpr int RC = RT / 16;
   constexpr int PP = 16 * NPCM;  // pairs per pass
-  // full-line corpus feeds stream through a buffer resource (fewer address
-  // registers; rows past a partial tile read as zero instead of being clamped)
-  constexpr bool kBuf = VEC && (FMT == kF32W || FMT == kBF16W);
-  typedef typename std::conditional<kBuf, BufRows<F, RC>, PtrRows<F, RC>>::type Src;
+  // the fp32 wide feed streams the operand-ordered copy (Xv = Xt, tblk = the
+  // tiles' first blocks); the bf16 wide feed streams row-major rows through a
+  // buffer resource (fewer address registers; rows past a partial tile read
+  // as zero instead of being clamped)
+  constexpr bool kTiled = VEC && FMT == kF32W;
+  constexpr bool kBuf = VEC && FMT == kBF16W;
+  typedef typename std::conditional<
+      kTiled, TileRows<RC>,
+      typename std::conditional<kBuf, BufRows<F, RC>, PtrRows<F, RC>>::type>::type Src;
   __shared__ WaveShared shw[kRerankWaves];
   const XE* X = static_cast<const XE*>(Xv);
   const QE* Q = static_cast<const QE*>(Qv);
@@ -1431,7 +1457,12 @@ __global__ __launch_bounds__(256) void rerank_kernel(
       phi = min(phi, plo + pair_chunk);
     }
     Src xr;
-    if constexpr (kBuf) {
+    if constexpr (kTiled) {
+      const int32_t nks = d / kTileKS;
+      xr.base = reinterpret_cast<const float*>(Xv) + int64_t(uni(tblk[tile])) * nks * 512 + 4 * lane;
+      xr.bstride = nks * 512;
+      xr.rows = rows_here;
+    } else if constexpr (kBuf) {
       xr.esz = int32_t(sizeof(XE));
       xr.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<XE*>(X + grow * d), 0,
                                                 int32_t(rows_here) * d * xr.esz, kBufWord3);
@@ -1618,6 +1649,104 @@ __global__ __launch_bounds__(256) void l1_gemm_kernel(const void* __restrict__ Q
       for (int e = 0; e < 4; ++e) {
         const int64_t q = q0 + 16 * mb + 4 * s + e;
         if (q < nq) rs[q * C + p] = row_scale ? acc[mb][nb][e] * sc : acc[mb][nb][e];
+      }
+  }
+}
+
+// bf16 layer-1 product staged through LDS (d a multiple of 64): a workgroup
+// owns a 128 x 128 tile of [queries x centroids], the 4 waves 64 x 64 each
+// (4 x 4 blocks of v_mfma_f32_16x16x32_bf16).  K runs in chunks of 64: the
+// workgroup loads the chunk's 128 query rows and 128 centroid rows (16 KB
+// each, one 16-byte load per thread per 16 rows) into registers while the
+// previous chunk is consumed from LDS, then swaps buffers -- each operand
+// byte is read from L2 once per tile instead of once per wave.  Rows are
+// padded to 72 bf16 (144 B) so the 16 lanes of a fragment read spread over
+// the LDS banks.  Tiles are dealt to the 8 XCDs round-robin so consecutive
+// tiles of one XCD share their query rows in its L2.
+constexpr int kLdsK = 64, kLdsRow = 72;
+
+__global__ __launch_bounds__(256) void l1_gemm_lds_kernel(const __hip_bfloat16* __restrict__ Q,
+                                                          int64_t nq,
+                                                          const __hip_bfloat16* __restrict__ Cc,
+                                                          int32_t C, int32_t d,
+                                                          float* __restrict__ rs) {
+  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sa[2][128 * kLdsRow];
+  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sb[2][128 * kLdsRow];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, s = lane >> 4;
+  const int64_t ntc = (C + 127) / 128;
+  const int64_t nblk = (nq + 127) / 128 * ntc;
+  const int64_t per = (nblk + 7) / 8;
+  const int64_t t = int64_t(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if ((blockIdx.x >> 3) >= per || t >= nblk) return;
+  const int64_t m0 = (t / ntc) * 128;
+  const int32_t n0 = int32_t(t % ntc) * 128;
+  // loader: thread tid moves 16 B (8 bf16) of rows tid / 8 + 32 j, columns 8 (tid % 8)
+  const int lr = tid >> 3, lc = 8 * (tid & 7);
+  const __hip_bfloat16* qsrc[4];
+  const __hip_bfloat16* csrc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    qsrc[j] = Q + min(m0 + lr + 32 * j, nq - 1) * d + lc;
+    csrc[j] = Cc + int64_t(min(n0 + lr + 32 * j, C - 1)) * d + lc;
+  }
+  bf16x8 ra[4], rb[4];
+  auto gload = [&](int kc) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      ra[j] = *reinterpret_cast<const bf16x8*>(qsrc[j] + kc * kLdsK);
+      rb[j] = *reinterpret_cast<const bf16x8*>(csrc[j] + kc * kLdsK);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      *reinterpret_cast<bf16x8*>(&sa[buf][(lr + 32 * j) * kLdsRow + lc]) = ra[j];
+      *reinterpret_cast<bf16x8*>(&sb[buf][(lr + 32 * j) * kLdsRow + lc]) = rb[j];
+    }
+  };
+  const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int nk = d / kLdsK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) gload(kc + 1);  // in flight while this chunk is consumed
+#pragma unroll
+    for (int kk = 0; kk < kLdsK; kk += 32) {
+      bf16x8 fa[4], fb[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        fa[a] = *reinterpret_cast<const bf16x8*>(&sa[buf][(wr + 16 * a + i) * kLdsRow + kk + 8 * s]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        fb[b] = *reinterpret_cast<const bf16x8*>(&sb[buf][(wc + 16 * b + i) * kLdsRow + kk + 8 * s]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    if (kc + 1 < nk) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  // D layout: acc[a][b][e] = query wr + 16 a + 4 s + e, centroid wc + 16 b + i
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int32_t p = n0 + wc + 16 * b + i;
+    if (p >= C) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t q = m0 + wr + 16 * a + 4 * s + e;
+        if (q < nq) rs[q * C + p] = acc[a][b][e];
       }
   }
 }
@@ -2149,40 +2278,40 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
       hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false, 1>), dim3(grid), dim3(256), 0,
                          st, (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                          (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                         alist, pmask, mw);
+                         alist, pmask, mw, ix.tile_blk[ti]);
     else if (bf16)
       hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false, 1>), dim3(grid), dim3(256), 0,
                          st, (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                          (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                         alist, pmask, mw);
+                         alist, pmask, mw, ix.tile_blk[ti]);
     else if (vec)
       hipLaunchKernelGGL((rerank_kernel<RT, kF32W, true, false, 1>), dim3(grid), dim3(256), 0,
-                         st, (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                         st, (const void*)ix.Xt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                          (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                         alist, pmask, mw);
+                         alist, pmask, mw, ix.tile_blk[ti]);
     else
       hipLaunchKernelGGL((rerank_kernel<RT, kF32W, false, false, 1>), dim3(grid), dim3(256), 0,
                          st, (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                          (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                         alist, pmask, mw);
+                         alist, pmask, mw, ix.tile_blk[ti]);
     return;
   }
   if (bf16 && ix.d % 64 != 0)
     hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw);
+                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw, ix.tile_blk[ti]);
   else if (bf16)
     hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw);
+                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw, ix.tile_blk[ti]);
   else if (vec)
     hipLaunchKernelGGL((rerank_kernel<RT, kF32W, true, false>), dim3(grid), dim3(256), 0, st,
-                       (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw);
+                       (const void*)ix.Xt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw, ix.tile_blk[ti]);
   else
     hipLaunchKernelGGL((rerank_kernel<RT, kF32W, false, false>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw);
+                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw, ix.tile_blk[ti]);
 }
 
 // Layer-1 window scores: the centroids (layer-1 order) are one "cluster" of C
@@ -2202,25 +2331,25 @@ void launch_l1_scores(const Index& ix, bool fp8, int64_t nq, const int32_t* l1cs
                        (const void*)ix.cent8, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale,
-                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0);
+                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr);
   else if (fp8)
     hipLaunchKernelGGL((rerank_kernel<64, kFP8, true, false>), grid, dim3(256), 0, st,
                        (const void*)ix.cent8, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale,
-                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0);
+                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr);
   else if (vec)
     hipLaunchKernelGGL((rerank_kernel<64, kF32, true, false>), grid, dim3(256), 0, st,
                        (const void*)ix.cent_l1, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr,
-                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0);
+                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr);
   else
     hipLaunchKernelGGL((rerank_kernel<64, kF32, false, false>), grid, dim3(256), 0, st,
                        (const void*)ix.cent_l1, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr,
-                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0);
+                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr);
 }
 
 // Dense layer-1 scores (r1 = C) on the GEMM kernel: 128-row query tiles when
@@ -2248,6 +2377,12 @@ void launch_l1_gemm_mb(const Index& ix, bool fp8, int64_t nq, const float* Q,
 // bf16 query x bf16 centroid product (candidate scores of the exact routing).
 void launch_l1_gemm_bf16(const Index& ix, int64_t nq, const __hip_bfloat16* Qb, float* rs,
                          hipStream_t st) {
+  if (ix.d % kLdsK == 0) {
+    const int64_t nblk = (nq + 127) / 128 * ((ix.C + 127) / 128);
+    hipLaunchKernelGGL(l1_gemm_lds_kernel, dim3(unsigned((nblk + 7) / 8 * 8)), dim3(256), 0, st, Qb,
+                       nq, ix.cent_l1_b, ix.C, ix.d, rs);
+    return;
+  }
   const int64_t nblk4 = (nq + 127) / 128 * ((ix.C + kGemmTileN - 1) / kGemmTileN);
   const int mb = nblk4 >= int64_t(ix.n_cu) ? 4 : 2;  // operand traffic from L2 bounds it
   const int64_t nblk = (nq + 32 * mb - 1) / (32 * mb) * ((ix.C + kGemmTileN - 1) / kGemmTileN);
@@ -2416,9 +2551,9 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   const int ti = tile_index(ix, o);
   const int tr = 32 << ti;
   const int gm = o.grid_mult > 0 ? o.grid_mult : 4;
-  // pairs per MFMA pass: 16 when clusters average few pairs (fewer registers,
-  // higher occupancy), else 32
-  const int npcm = o.pass_pairs == 16 ? 1 : o.pass_pairs == 32 ? 2 : (np <= 12 * int64_t(C) ? 1 : 2);
+  // pairs per MFMA pass: up to 32 by default (a tile with at most 16 pairs
+  // still takes the 16-pair pass), 16 on request
+  const int npcm = o.pass_pairs == 16 ? 1 : 2;
   if (o.persistent == 2) {
     const int32_t nt = ix.n_tiles[ti];
     hipLaunchKernelGGL(zero_kernel, dim3(unsigned(std::min<int64_t>((nt + 255) / 256, 4096))),
