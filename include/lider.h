@@ -146,9 +146,10 @@ const char* lider_last_error(void);
  *                 LIDER_BF16: precision form -- bf16 first pass over the
  *                 windows (needs storage = LIDER_BF16), shortlist of
  *                 shortlist_mult*k per query, fp32 rerank of the shortlist from
- *                 the fp32 copy; routing takes the best fp8 centroid scores
- *                 (approximate) if the index has fp8 centroids, else it is
- *                 exact as in LIDER_F32.
+ *                 the fp32 copy; routing is exact as in LIDER_F32, except with
+ *                 l1_dense = -1 on an index with fp8 centroids, where the
+ *                 window kernel scores the fp8 copy and the best scores route
+ *                 (approximate).
  *  shortlist_mult shortlist length per query in units of k (0 = 4).
  *  persistent     0: one wave per row tile of the whole index (tiles no window
  *                 touches exit at once).  1: a persistent grid whose waves pull

@@ -408,26 +408,37 @@ __global__ void compose_kernel(const int64_t* __restrict__ permh, int64_t n,
 
 // Operand-ordered copy of the reordered corpus, one wave per 16-row block:
 // block b takes rows src[b].x .. src[b].x + src[b].y - 1 of X (zeros past
-// them); for every 32-dim k-step and half h, lane l = i + 16 s writes dims
-// [32 ks + 16 h + 4 s, + 4) of row i at float offset ((b nks + ks) 2 + h) 256 + 4 l.
+// them).  fp32 (KS = 32): for every k-step and half h, lane l = i + 16 s writes
+// dims [32 ks + 16 h + 4 s, + 4) of row i at float offset ((b nks + ks) 2 + h)
+// 256 + 4 l.  bf16 (KS = 64): dims [64 ks + 32 h + 8 s, + 8), rounded to
+// nearest even like the row-major bf16 copy, at element offset
+// ((b nks + ks) 2 + h) 512 + 8 l.
+template <bool BF>
 __global__ __launch_bounds__(256) void tile_corpus_kernel(const float* __restrict__ X, int32_t d,
                                                           const int2* __restrict__ src,
-                                                          int64_t nblk, float* __restrict__ Xt) {
+                                                          int64_t nblk, void* __restrict__ out) {
+  constexpr int KS = BF ? 64 : kTileKS, EPL = BF ? 8 : 4;  // dims per k-step, per lane
   const int lane = threadIdx.x & 63;
   const int i = lane & 15, s = lane >> 4;
-  const int32_t nks = d / kTileKS;
+  const int32_t nks = d / KS;
   for (int64_t b = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); b < nblk;
        b += int64_t(gridDim.x) * 4) {
     const int2 sr = src[b];
     const bool ok = i < sr.y;
     const float* xr = X + (int64_t(sr.x) + (ok ? i : 0)) * d;
-    float4* out = reinterpret_cast<float4*>(Xt + b * int64_t(nks) * 512);
     for (int32_t ks = 0; ks < nks; ++ks)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        float4 v = ok ? *reinterpret_cast<const float4*>(xr + ks * kTileKS + 16 * h + 4 * s)
-                      : float4{0.f, 0.f, 0.f, 0.f};
-        out[(ks * 2 + h) * 64 + lane] = v;
+        const int k = ks * KS + (KS / 2) * h + EPL * s;
+        const int64_t at = ((b * nks + ks) * 2 + h) * (64 * EPL) + EPL * lane;
+        if (BF) {
+          __hip_bfloat16* o = static_cast<__hip_bfloat16*>(out) + at;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) o[e] = __float2bfloat16(ok ? xr[k + e] : 0.f);
+        } else {
+          const float4 v = ok ? *reinterpret_cast<const float4*>(xr + k) : float4{0.f, 0.f, 0.f, 0.f};
+          *reinterpret_cast<float4*>(static_cast<float*>(out) + at) = v;
+        }
       }
   }
 }
@@ -530,7 +541,8 @@ int finish_index(Index& ix) {
   // clusters padded to whole 16-row blocks in the operand-ordered copy
   std::vector<int64_t> pblk(size_t(C) + 1, 0);  // first 16-row block of each cluster
   for (int32_t j = 0; j < C; ++j) pblk[j + 1] = pblk[j] + (ix.h_off[j + 1] - ix.h_off[j] + 15) / 16;
-  if (ix.d % kTileKS == 0 && pblk[C] > 0) {
+  const bool want_t = ix.d % kTileKS == 0, want_bt = ix.Xb && ix.d % 64 == 0;
+  if ((want_t || want_bt) && pblk[C] > 0) {
     const int64_t nblk = pblk[C];
     std::vector<int2> src(static_cast<size_t>(nblk));
     for (int32_t j = 0; j < C; ++j)
@@ -539,19 +551,24 @@ int finish_index(Index& ix) {
         src[b] = make_int2(int32_t(r0), int32_t(std::min<int64_t>(16, ix.h_off[j + 1] - r0)));
       }
     int2* dsrc = nullptr;
-    if (hipMalloc(&ix.Xt, al256(size_t(nblk) * (ix.d / kTileKS) * 512 * 4)) != hipSuccess ||
-        hipMalloc(&dsrc, al256(src.size() * sizeof(int2))) != hipSuccess) {
+    const size_t elems = size_t(nblk) * 16 * size_t(ix.d);  // per copy
+    if (hipMalloc(&dsrc, al256(src.size() * sizeof(int2))) != hipSuccess ||
+        (want_t && hipMalloc(&ix.Xt, al256(elems * 4)) != hipSuccess) ||
+        (want_bt && hipMalloc(&ix.Xbt, al256(elems * 2)) != hipSuccess)) {
       if (dsrc) (void)hipFree(dsrc);
       return set_error(LIDER_ENOMEM, "out of device memory (operand-ordered corpus)");
     }
     rc = check_hip(hipMemcpy(dsrc, src.data(), src.size() * sizeof(int2), hipMemcpyHostToDevice),
                    "copy block table");
-    if (rc == LIDER_OK) {
-      hipLaunchKernelGGL(tile_corpus_kernel, dim3(unsigned(std::min<int64_t>((nblk + 3) / 4, 65536))),
-                         dim3(256), 0, nullptr, ix.X, ix.d, dsrc, nblk, ix.Xt);
-      rc = check_hip(hipGetLastError(), "operand-ordered corpus");
-      if (rc == LIDER_OK) rc = check_hip(hipDeviceSynchronize(), "operand-ordered corpus");
-    }
+    const dim3 grid(unsigned(std::min<int64_t>((nblk + 3) / 4, 65536)));
+    if (rc == LIDER_OK && want_t)
+      hipLaunchKernelGGL(tile_corpus_kernel<false>, grid, dim3(256), 0, nullptr, ix.X, ix.d, dsrc,
+                         nblk, (void*)ix.Xt);
+    if (rc == LIDER_OK && want_bt)
+      hipLaunchKernelGGL(tile_corpus_kernel<true>, grid, dim3(256), 0, nullptr, ix.X, ix.d, dsrc,
+                         nblk, (void*)ix.Xbt);
+    if (rc == LIDER_OK) rc = check_hip(hipGetLastError(), "operand-ordered corpus");
+    if (rc == LIDER_OK) rc = check_hip(hipDeviceSynchronize(), "operand-ordered corpus");
     (void)hipFree(dsrc);
     if (rc != LIDER_OK) return rc;
   }

@@ -172,6 +172,9 @@ struct Index {
   // l = i + 16 s holds dims [4 s, 4 s + 4) (then [16 + 4 s, 16 + 4 s + 4)) of
   // row i -- one contiguous 1 KB wave load per half.
   float* Xt = nullptr;
+  // bf16 copy in the same order (storage bf16, d a multiple of 64): 64-dim
+  // k-steps, lane l holds dims [8 s, 8 s + 8) then [32 + 8 s, 32 + 8 s + 8).
+  __hip_bfloat16* Xbt = nullptr;
   __hip_bfloat16* Xb = nullptr;  // [n x d] bf16 copy (precision form)
   int64_t* perm = nullptr;     // [H x n] sorted position of array h -> original id
   int32_t* perm32 = nullptr;   // [n] array 0's, int32

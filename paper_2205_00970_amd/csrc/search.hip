@@ -1247,13 +1247,6 @@ struct Feed<kF32W, VEC> {  // 32 dims per k-step: 4 + 4 per lane
   }
   __device__ static Raw raw(const float* row, int k, int d, bool nt) { return loadx(row, k, d, nt); }
   __device__ static T dec(const Raw& v, int, int) { return v; }
-  // Both 16-byte halves from a buffer resource at byte offset voff (range
-  // checked: out-of-range reads return zero).
-  __device__ static T loadb(__amdgpu_buffer_rsrc_t rs, int32_t voff) {
-    const i32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 0);
-    const i32x4 b = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 64, 0, 0);
-    return T{__builtin_bit_cast(float4, a), __builtin_bit_cast(float4, b)};
-  }
   __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
     Feed<kF32, VEC>::mfma(q.a, x.a, acc);
     Feed<kF32, VEC>::mfma(q.b, x.b, acc);
@@ -1282,21 +1275,14 @@ struct Feed<kBF16W, VEC> {  // 64 dims per k-step: 8 + 8 per lane
     return loadx(row, k, d, nt);
   }
   __device__ static T dec(const Raw& v, int, int) { return v; }
-  __device__ static T loadb(__amdgpu_buffer_rsrc_t rs, int32_t voff) {
-    const i32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 0);
-    const i32x4 b = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 64, 0, 0);
-    return T{__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b)};
-  }
   __device__ static void mfma(const T& q, const T& x, floatx4& acc) {
     Feed<kBF16, VEC>::mfma(q.a, x.a, acc);
     Feed<kBF16, VEC>::mfma(q.b, x.b, acc);
   }
 };
 
-// Row sources of a tile.  PtrRows: one pointer per 16-row block (rows past the
-// tile clamped to its last row).  BufRows: the tile as one buffer resource of
-// rows * d elements; lane row r of block rc sits at byte (16 rc + r) d esz, and
-// rows past the tile fall outside the resource and read as zero.
+// Row source of a tile read in row-major order: one pointer per 16-row block
+// (rows past the tile clamped to its last row).
 template <class F, int RC>
 struct PtrRows {
   const typename F::XE* xr[RC];
@@ -1305,34 +1291,31 @@ struct PtrRows {
   }
 };
 
-template <class F, int RC>
-struct BufRows {
-  __amdgpu_buffer_rsrc_t rs;
-  int32_t vbase;    // byte offset of the lane's row in block 0
-  int32_t rstride;  // bytes between row blocks (16 rows)
-  int32_t esz;
-  __device__ typename F::T load(int rc, int k, int, bool) const {
-    return F::loadb(rs, vbase + rc * rstride + k * esz);
-  }
-};
 
-// Rows of the operand-ordered corpus copy (fp32, 32-dim k-steps): the row
-// block rc of the tile starts rc * nks * 512 floats after the tile's first
-// block, k-step ks 512 floats further; the lane's two 16-byte halves are at
-// 4 lane and 256 + 4 lane -- each half one contiguous 1 KB wave load, read
-// nontemporally (the corpus is streamed once per batch).  Row blocks past
-// the tile's rows are not read (zeros).
-template <int RC>
+// Rows of an operand-ordered corpus copy (fp32 with 32-dim k-steps, or bf16
+// with 64-dim k-steps): the row block rc of the tile starts rc * bstride
+// elements after the tile's first block, k-step ks one 2 KB chunk further
+// per step; the lane's two 16-byte halves sit at 16 lane bytes into each 1 KB
+// half -- each half one contiguous 1 KB wave load, read nontemporally (the
+// corpus is streamed once per batch).  Row blocks past the tile's rows are
+// not read (zeros).
+template <class F, int RC>
 struct TileRows {
-  const float* base;  // the tile's first block, plus 4 lane
-  int32_t bstride;    // floats between row blocks
+  typedef typename F::XE XE;
+  static constexpr int kHalf = 1024 / int(sizeof(XE));  // elements per 1 KB half
+  const XE* base;     // the tile's first block, plus the lane's 16 bytes
+  int32_t bstride;    // elements between row blocks
   int32_t rows;       // rows in the tile
-  __device__ F32x2 load(int rc, int k, int, bool) const {
-    if (16 * rc >= rows) return F32x2{float4{0.f, 0.f, 0.f, 0.f}, float4{0.f, 0.f, 0.f, 0.f}};
-    const float* p = base + rc * bstride + (k / kTileKS) * 512;
+  __device__ typename F::T load(int rc, int k, int, bool) const {
+    typedef typename F::T T;
+    if (16 * rc >= rows) {
+      const floatx4 z{0.f, 0.f, 0.f, 0.f};
+      return T{__builtin_bit_cast(decltype(T::a), z), __builtin_bit_cast(decltype(T::b), z)};
+    }
+    const XE* p = base + rc * bstride + (k / F::KS) * (2 * kHalf);
     const floatx4 a = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(p));
-    const floatx4 b = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(p + 256));
-    return F32x2{__builtin_bit_cast(float4, a), __builtin_bit_cast(float4, b)};
+    const floatx4 b = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(p + kHalf));
+    return T{__builtin_bit_cast(decltype(T::a), a), __builtin_bit_cast(decltype(T::b), b)};
   }
 };
 
@@ -1416,15 +1399,10 @@ __global__ __launch_bounds__(256) void rerank_kernel(
   typedef typename F::QE QE;
   constexpr int RC = RT / 16;
   constexpr int PP = 16 * NPCM;  // pairs per pass
-  // the fp32 wide feed streams the operand-ordered copy (Xv = Xt, tblk = the
-  // tiles' first blocks); the bf16 wide feed streams row-major rows through a
-  // buffer resource (fewer address registers; rows past a partial tile read
-  // as zero instead of being clamped)
-  constexpr bool kTiled = VEC && FMT == kF32W;
-  constexpr bool kBuf = VEC && FMT == kBF16W;
-  typedef typename std::conditional<
-      kTiled, TileRows<RC>,
-      typename std::conditional<kBuf, BufRows<F, RC>, PtrRows<F, RC>>::type>::type Src;
+  // the wide feeds stream an operand-ordered copy (Xv = Xt or Xbt, tblk =
+  // the tiles' first blocks); the others read row-major rows
+  constexpr bool kTiled = VEC && (FMT == kF32W || FMT == kBF16W);
+  typedef typename std::conditional<kTiled, TileRows<F, RC>, PtrRows<F, RC>>::type Src;
   __shared__ WaveShared shw[kRerankWaves];
   const XE* X = static_cast<const XE*>(Xv);
   const QE* Q = static_cast<const QE*>(Qv);
@@ -1458,16 +1436,11 @@ __global__ __launch_bounds__(256) void rerank_kernel(
     }
     Src xr;
     if constexpr (kTiled) {
-      const int32_t nks = d / kTileKS;
-      xr.base = reinterpret_cast<const float*>(Xv) + int64_t(uni(tblk[tile])) * nks * 512 + 4 * lane;
-      xr.bstride = nks * 512;
+      constexpr int kChunk = 2 * TileRows<F, RC>::kHalf;  // elements per (block, k-step)
+      const int32_t nks = d / F::KS;
+      xr.base = X + int64_t(uni(tblk[tile])) * nks * kChunk + lane * (16 / int(sizeof(XE)));
+      xr.bstride = nks * kChunk;
       xr.rows = rows_here;
-    } else if constexpr (kBuf) {
-      xr.esz = int32_t(sizeof(XE));
-      xr.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<XE*>(X + grow * d), 0,
-                                                int32_t(rows_here) * d * xr.esz, kBufWord3);
-      xr.vbase = i * d * xr.esz;
-      xr.rstride = 16 * d * xr.esz;
     } else {
 #pragma unroll
       for (int rc = 0; rc < RC; ++rc)
@@ -2281,7 +2254,7 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
                          alist, pmask, mw, ix.tile_blk[ti]);
     else if (bf16)
       hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false, 1>), dim3(grid), dim3(256), 0,
-                         st, (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                         st, (const void*)ix.Xbt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                          (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
                          alist, pmask, mw, ix.tile_blk[ti]);
     else if (vec)
@@ -2302,7 +2275,7 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
                        (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw, ix.tile_blk[ti]);
   else if (bf16)
     hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false>), dim3(grid), dim3(256), 0, st,
-                       (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)ix.Xbt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw, ix.tile_blk[ti]);
   else if (vec)
     hipLaunchKernelGGL((rerank_kernel<RT, kF32W, true, false>), dim3(grid), dim3(256), 0, st,
@@ -2476,11 +2449,12 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
     hipLaunchKernelGGL(expand_kernel, dim3(unsigned((nl1 + 3) / 4)), dim3(256), 0, st,
                        ix.l1_keys, (const int64_t*)nullptr, int64_t(C), l1pairs, nl1, kq, p.r1,
                        m, o.expand_bits, l1, H, int64_t(C));
-  const bool fp8 = bf16 && ix.cent8;
+  // fp8 centroids (precision form) only feed the window kernel
+  const bool fp8 = bf16 && ix.cent8 && !p.l1_dense_rows;
   // Layer-1 scores: dense rows (every centroid; bf16 product unless fp32 is
-  // asked for or the bf16 copy is missing, fp8 in the precision form) or the
-  // window kernel; then the exact routing (or the precision form's
-  // approximate fp8 routing) over each query's window or union list.
+  // asked for or the bf16 copy is missing) or the window kernel; then the
+  // exact routing (or, for fp8 window scores, the approximate routing) over
+  // each query's window or union list.
   const bool l1b = !fp8 && o.l1_dense == 0 && ix.cent_l1_b;
   if (fp8 || bf16 || l1b)
     hipLaunchKernelGGL(to_bf16_kernel, dim3(2048), dim3(256), 0, st, Q, nq * ix.d, qb);

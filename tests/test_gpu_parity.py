@@ -107,7 +107,9 @@ def test_mid_schedules_identical(mid):
 @pytest.mark.parametrize("precision", ["f32", "bf16"])
 def test_mid_dense_layer1_identical(mid, precision):
     """r1 = C: the bf16-candidate routing, the fp32 dense GEMM and the window
-    kernel route identically."""
+    kernel route identically (the window kernel on an index with fp8
+    centroids scores those, approximately, in the precision form: not
+    compared here)."""
     torch = _torch()
     from paper_2205_00970_amd import lider
     X, Q = mid["X"], mid["Q"]
@@ -121,7 +123,8 @@ def test_mid_dense_layer1_identical(mid, precision):
     for sl in (slice(None), slice(5, 6), slice(17, 300)):
         q = Qd[sl].contiguous()
         a = gi.search(q, 10, 3, 500, r1=64, precision=precision, debug=True)
-        for mode in (False, 1):  # window kernel; dense fp32 without bf16 candidates
+        for mode in ((False, 1) if precision == "f32" else (1,)):
+            # window kernel; dense fp32 without bf16 candidates
             b = gi.search(q, 10, 3, 500, r1=64, precision=precision, debug=True, l1_dense=mode)
             # the routed sets agree (their listing order is not part of the result)
             assert torch.equal(a[2]["routed"].sort(dim=1)[0], b[2]["routed"].sort(dim=1)[0])
@@ -244,11 +247,13 @@ def test_errors_and_edge_cases(tiny):
         gi.search(Qd, 10, 4, 64, precision="bf16")  # index has no bf16 copy
 
 
-@pytest.mark.parametrize("k", [10, 100])
-def test_precision_form(mid, k):
-    """bf16 windows + fp8 routing + fp32 rerank of a 4k shortlist: every
-    returned score is the exact fp32 score of its id (within tolerance of
-    FP64), ids are unique, and the results agree closely with the fp32 path."""
+@pytest.mark.parametrize("k,l1_dense", [(10, True), (100, True), (10, False)])
+def test_precision_form(mid, k, l1_dense):
+    """bf16 windows + fp32 rerank of a 4k shortlist, with exact routing (dense
+    layer 1) or fp8 window routing: every returned score is the exact fp32
+    score of its id (within tolerance of FP64), ids are unique, and the
+    results agree closely with the fp32 path; with exact routing the routed
+    sets equal the fp32 path's."""
     torch = _torch()
     from paper_2205_00970_amd import lider
     X, Q = mid["X"], mid["Q"]
@@ -258,8 +263,13 @@ def test_precision_form(mid, k):
                      assignment=torch.from_numpy(lab).cuda(), storage="bf16",
                      centroid_storage="fp8")
     Qd = torch.from_numpy(Q).cuda()
-    ids, sc = gi.search(Qd, k, 4, 4000, r1=64, precision="bf16")
-    ref, _ = gi.search(Qd, k, 4, 4000, r1=64)
+    ids, sc, dbg = gi.search(Qd, k, 4, 4000, r1=64, precision="bf16", l1_dense=l1_dense,
+                             debug=True)
+    ref, _, rdbg = gi.search(Qd, k, 4, 4000, r1=64, debug=True)
+    if l1_dense:
+        a = np.sort(dbg["routed"].cpu().numpy(), axis=1)
+        b2 = np.sort(rdbg["routed"].cpu().numpy(), axis=1)
+        assert np.array_equal(a, b2)
     ids, sc, ref = ids.cpu().numpy(), sc.cpu().numpy(), ref.cpu().numpy()
     qn = np.linalg.norm(Q.astype(np.float64), axis=1)
     xn = np.linalg.norm(X.astype(np.float64), axis=1)
