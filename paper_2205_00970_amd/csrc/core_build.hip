@@ -552,19 +552,25 @@ int finish_index(Index& ix) {
       }
     int2* dsrc = nullptr;
     const size_t elems = size_t(nblk) * 16 * size_t(ix.d);  // per copy
-    if (hipMalloc(&dsrc, al256(src.size() * sizeof(int2))) != hipSuccess ||
-        (want_t && hipMalloc(&ix.Xt, al256(elems * 4)) != hipSuccess) ||
-        (want_bt && hipMalloc(&ix.Xbt, al256(elems * 2)) != hipSuccess)) {
-      if (dsrc) (void)hipFree(dsrc);
+    if (hipMalloc(&dsrc, al256(src.size() * sizeof(int2))) != hipSuccess)
       return set_error(LIDER_ENOMEM, "out of device memory (operand-ordered corpus)");
+    // the copies are an optimisation: without room for one, the rerank reads
+    // the row-major rows instead
+    if (want_t && hipMalloc(&ix.Xt, al256(elems * 4)) != hipSuccess) {
+      (void)hipGetLastError();
+      ix.Xt = nullptr;
+    }
+    if (want_bt && hipMalloc(&ix.Xbt, al256(elems * 2)) != hipSuccess) {
+      (void)hipGetLastError();
+      ix.Xbt = nullptr;
     }
     rc = check_hip(hipMemcpy(dsrc, src.data(), src.size() * sizeof(int2), hipMemcpyHostToDevice),
                    "copy block table");
     const dim3 grid(unsigned(std::min<int64_t>((nblk + 3) / 4, 65536)));
-    if (rc == LIDER_OK && want_t)
+    if (rc == LIDER_OK && ix.Xt)
       hipLaunchKernelGGL(tile_corpus_kernel<false>, grid, dim3(256), 0, nullptr, ix.X, ix.d, dsrc,
                          nblk, (void*)ix.Xt);
-    if (rc == LIDER_OK && want_bt)
+    if (rc == LIDER_OK && ix.Xbt)
       hipLaunchKernelGGL(tile_corpus_kernel<true>, grid, dim3(256), 0, nullptr, ix.X, ix.d, dsrc,
                          nblk, (void*)ix.Xbt);
     if (rc == LIDER_OK) rc = check_hip(hipGetLastError(), "operand-ordered corpus");

@@ -2245,9 +2245,12 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
     grid = unsigned(std::max(8, ix.n_cu * grid_mult / 8 * 8));
   else
     grid = unsigned(((nt + 3) / 4 + 7) / 8 * 8);
-  const bool vec = (ix.d % 32 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
+  // the wide feeds read the operand-ordered copies; without one (no room at
+  // build time), the row-major rows
+  const bool vec = (ix.d % 32 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0) && ix.Xt;
+  const bool bvec = ix.d % 64 == 0 && ix.Xbt;
   if (npcm == 1) {
-    if (bf16 && ix.d % 64 != 0)
+    if (bf16 && !bvec)
       hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false, 1>), dim3(grid), dim3(256), 0,
                          st, (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                          (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
@@ -2269,7 +2272,7 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
                          alist, pmask, mw, ix.tile_blk[ti]);
     return;
   }
-  if (bf16 && ix.d % 64 != 0)
+  if (bf16 && !bvec)
     hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false>), dim3(grid), dim3(256), 0, st,
                        (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw, ix.tile_blk[ti]);
