@@ -250,7 +250,7 @@ def main():
         dt, li, _ = timed(100, c, r, r1, reps=5)
         extra["point_k100"] = dict(qps=round(args.nq / dt),
                                    recall100=round(recall_at(torch, X, Q, li, gt_sc, 100), 4))
-        # precision form: bf16 windows + fp8 routing + fp32 rerank of 4k shortlist
+        # precision form: bf16 windows + exact routing from the bf16 layer-1 product + fp32 rerank of a 4k shortlist
         dt, pi, ps = timed(10, c, r, r1, reps=5, precision="bf16")
         rows = X[pi.clamp(min=0)]
         xs = (rows.double() * Q.double()[:, None, :]).sum(-1)
