@@ -3,31 +3,37 @@
 // random-hyperplane bits h_i(x) = [a_i . x >= 0] (the cosine variant, Section
 // 4.1).
 //
-// The projection [rows x d] . [d x nh] runs on fp32 MFMA (v_mfma_f32_16x16x4f32,
+// The projection [rows x d] . [d x nh] runs on FP64 MFMA (v_mfma_f64_16x16x4f64,
 // one wave = 16 rows x 16 hashes).  The digit is an integer decided by a
-// floating-point value, so it must equal the FP64 definition exactly: a
-// projection whose fp32 value lies within a rigorous rounding-error band of a
-// bucket edge is queued and recomputed by a sequential FP64 dot product in
-// dimension order (fp32 products are exact in FP64, so FMA or not, every
-// rounding matches the definition).
+// floating-point value, so it must equal the FP64 definition exactly.  The
+// fp32 x fp32 products are exact in FP64, so the MFMA sum differs from the
+// sequential FP64 sum of the definition only by the rounding of its d + 3
+// additions: within 8 (d + 4) 2^-53 |a| |x|.  A projection whose value lies
+// within that band of a bucket edge (about 1e-10 relative at d = 768, so almost
+// never) is queued and recomputed by the sequential FP64 dot product in
+// dimension order.
 #include "lider_internal.hpp"
 
 namespace lider {
 
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
 // Projection kernel.  Block = 4 waves = 16 rows x (up to) 32 hashes, the
-// hashes [32 y, 32 y + 32) of grid row y; the waves split the dimension range (wave w owns a contiguous quarter of the 16-dimension
-// steps).  Lane l of a wave owns row / hash (l % 16) and the dimension slot
-// s = l / 16: per step it loads 4 consecutive dims [k0 + 4s, k0 + 4s + 4) of
-// its row and of its hash vector and feeds them to 4 MFMAs (the k index of an
-// MFMA only needs to map to the same dimension on both operands).  Partial
-// projections are added in wave order through LDS.
+// hashes [32 y, 32 y + 32) of grid row y; the waves split the dimension range
+// (wave w owns a contiguous quarter of the 16-dimension steps).  Lane l of a
+// wave owns row / hash (l % 16) and the dimension slot s = l / 16: per step it
+// loads 4 consecutive dims [k0 + 4s, k0 + 4s + 4) of its row and of its hash
+// vectors and feeds them to 4 MFMAs (the k index of an MFMA only needs to map
+// to the same dimension on both operands).  The next step's operands are
+// loaded before the current step's MFMAs are issued.  Partial projections are
+// added in wave order through LDS.
 template <bool VEC>
 __global__ __launch_bounds__(256) void hash_kernel(
     const float* __restrict__ X, int64_t n, int32_t d, const float* __restrict__ A,
     const float* __restrict__ bvec, const float* __restrict__ anorm, int32_t nh, double w,
     int32_t* __restrict__ out, int64_t* __restrict__ list, int32_t* __restrict__ counter,
     int32_t* __restrict__ status, int clamp, float* __restrict__ rownorm, int kind) {
-  __shared__ float part[4][32][16];  // [wave][hash][row]
+  __shared__ double part[4][32][16];  // [wave][hash][row]
   __shared__ float pss[4][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, s = lane >> 4;
@@ -42,74 +48,93 @@ __global__ __launch_bounds__(256) void hash_kernel(
   const float* a0 = A + int64_t(h0) * d;
   const float* a1 = A + int64_t(h1) * d;
   const bool two = nhc > 16;
-  floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  doublex4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
   float ss = 0.f;
   const int nk = (d + 15) / 16;
   const int k0s = wave * nk / 4, k1s = (wave + 1) * nk / 4;
-  for (int ks = k0s; ks < k1s; ++ks) {
+  float xe[4], ae[4], be[4] = {0.f, 0.f, 0.f, 0.f};
+  auto load = [&](int ks, float* xo, float* ao, float* bo) {
     const int kk = ks * 16 + 4 * s;
-    float xe[4], ae[4], be[4];
     if (VEC && kk + 3 < d) {
       const float4 xv = *reinterpret_cast<const float4*>(xr + kk);
       const float4 av = *reinterpret_cast<const float4*>(a0 + kk);
-      const float4 bv = *reinterpret_cast<const float4*>(a1 + kk);
-      xe[0] = xv.x; xe[1] = xv.y; xe[2] = xv.z; xe[3] = xv.w;
-      ae[0] = av.x; ae[1] = av.y; ae[2] = av.z; ae[3] = av.w;
-      be[0] = bv.x; be[1] = bv.y; be[2] = bv.z; be[3] = bv.w;
+      xo[0] = xv.x; xo[1] = xv.y; xo[2] = xv.z; xo[3] = xv.w;
+      ao[0] = av.x; ao[1] = av.y; ao[2] = av.z; ao[3] = av.w;
+      if (two) {
+        const float4 bv = *reinterpret_cast<const float4*>(a1 + kk);
+        bo[0] = bv.x; bo[1] = bv.y; bo[2] = bv.z; bo[3] = bv.w;
+      }
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const bool in = kk + e < d;
-        xe[e] = in ? xr[kk + e] : 0.f;
-        ae[e] = in ? a0[kk + e] : 0.f;
-        be[e] = in ? a1[kk + e] : 0.f;
+        xo[e] = in ? xr[kk + e] : 0.f;
+        ao[e] = in ? a0[kk + e] : 0.f;
+        if (two) bo[e] = in ? a1[kk + e] : 0.f;
       }
     }
+  };
+  if (k0s < k1s) load(k0s, xe, ae, be);
+  for (int ks = k0s; ks < k1s; ++ks) {
+    float xn[4], an[4], bn[4] = {0.f, 0.f, 0.f, 0.f};
+    load(ks + 1 < k1s ? ks + 1 : ks, xn, an, bn);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       ss += xe[e] * xe[e];
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xe[e], ae[e], acc0, 0, 0, 0);
-      if (two) acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xe[e], be[e], acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(double(xe[e]), double(ae[e]), acc0, 0, 0, 0);
+      if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(double(xe[e]), double(be[e]), acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      xe[e] = xn[e];
+      ae[e] = an[e];
+      be[e] = bn[e];
     }
   }
   // |x|^2 of row i over this wave's dims: sum the four dimension slots
   ss += __shfl_xor(ss, 16);
   ss += __shfl_xor(ss, 32);
   if (s == 0) pss[wave][i] = ss;
+  // FP64 MFMA result layout: element e of lane l is (row l / 16 + 4 e, hash l % 16)
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    part[wave][i][4 * s + e] = acc0[e];
-    if (two) part[wave][16 + i][4 * s + e] = acc1[e];
+    part[wave][i][s + 4 * e] = acc0[e];
+    if (two) part[wave][16 + i][s + 4 * e] = acc1[e];
   }
   __syncthreads();
-  const double coef = dot_err_coef(d);
+  const double u = 1.1102230246251565e-16;  // 2^-53
   const double gam = double(d + 2) * 5.9604644775390625e-08;
   for (int o = threadIdx.x; o < 16 * nhc; o += 256) {
     const int ri = o / nhc, hl = o - ri * nhc, hash = hb + hl;
     const int64_t row = row0 + ri;
     if (row >= n) continue;
     const float ssr = ((pss[0][ri] + pss[1][ri]) + pss[2][ri]) + pss[3][ri];
-    const float sv = ((part[0][hl][ri] + part[1][hl][ri]) + part[2][hl][ri]) + part[3][hl][ri];
+    const double sv = ((part[0][hl][ri] + part[1][hl][ri]) + part[2][hl][ri]) + part[3][hl][ri];
     const double xn = sqrt(double(ssr) * (1.0 + 2.0 * gam)) * (1.0 + 9.5367431640625e-07);
     if (rownorm && hash == 0) rownorm[row] = float(xn * (1.0 + 9.5367431640625e-07));
     const int64_t oi = row * nh + hash;
+    // sum |a_i x_i| <= |a| |x|; the last term covers fp32 subnormal inputs
+    // flushed to zero on the way into FP64.
+    const double an = double(anorm[hash]);
+    const double pa = an * xn + double(d) * an * 1.1754943508222875e-38;
     if (kind == LIDER_HASH_SIGN) {  // bit = [a.x >= 0]: decided unless |a.x| is within the band
-      const double E = coef * double(anorm[hash]) * xn + double(d) * 7.888609052210118e-31;
-      if (!(fabs(double(sv)) > 2.0 * E)) {
+      const double E = 8.0 * double(d + 4) * u * pa;
+      if (!(fabs(sv) > E)) {
         const int32_t slot = atomicAdd(counter, 1);
         list[slot] = oi;
       } else {
-        out[oi] = sv > 0.f ? 1 : 0;
+        out[oi] = sv > 0.0 ? 1 : 0;
       }
       continue;
     }
-    const double tv = (double(sv) + double(bvec[hash])) / w;
-    const double E = (coef * double(anorm[hash]) * xn + double(d) * 7.888609052210118e-31) / w +
-                     8.881784197001252e-16 * fabs(tv);
+    const double bh = double(bvec[hash]);
+    const double tv = (sv + bh) / w;
+    const double E = 8.0 * (double(d + 4) * u * pa + u * (fabs(sv) + fabs(bh))) / w +
+                     8.0 * u * fabs(tv);
     const double fl = floor(tv);
     const double fr = tv - fl;
     const double dist = fr < 1.0 - fr ? fr : 1.0 - fr;
-    if (!(dist > 2.0 * E)) {
+    if (!(dist > E)) {
       const int32_t slot = atomicAdd(counter, 1);
       list[slot] = oi;
     } else if (fl >= -2147483648.0 && fl <= 2147483647.0) {
@@ -244,7 +269,7 @@ int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const floa
                        out, list, counter, status, clamp, rownorm, kind);
   int64_t cap = n * nh;
   int64_t blocks = (cap + 3) / 4;
-  if (blocks > 4096) blocks = 4096;
+  if (blocks > 512) blocks = 512;  // queued entries are rare; the grid strides over them
   hipLaunchKernelGGL(hash_fixup_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, X, d, A, b, nh,
                      w, out, list, counter, status, clamp, kind);
   return check_hip(hipGetLastError(), "hash kernels");
