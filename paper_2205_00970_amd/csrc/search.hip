@@ -1844,36 +1844,81 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
     int32_t* __restrict__ slist, int drop) {
   __shared__ uint32_t keys[4][R == 0 ? kWaveKeyCache : 1];
   __shared__ int32_t start[4][LIDER_MAX_C + 1];
-  __shared__ int32_t pj[4][LIDER_MAX_C], ps[4][LIDER_MAX_C];
+  __shared__ int64_t pbase[4][LIDER_MAX_C];  // sorted row of each slot's first candidate
   __shared__ uint64_t ext[4][65];
   __shared__ uint32_t wkey[4][64], wid[4][64];
   __shared__ int64_t wrow[4][64];
   __shared__ uint32_t lkey[4][kSelList];
   __shared__ int32_t lidx[4][kSelList];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));  // uniform, in SGPRs
   const uint64_t below = (uint64_t(1) << lane) - 1;
-  for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
-    if (lane == 0) {
-      int32_t acc = 0;
-      for (int t = 0; t < c; ++t) {
-        const Pair pr = pairs[q * c + t];
-        start[wave][t] = acc;
-        pj[wave][t] = pr.j;
-        ps[wave][t] = pr.s;
-        acc += pr.j >= 0 ? pr.len : 0;
-      }
-      start[wave][c] = acc;
+  // one query per wave, no loop: per-query index arithmetic is not hoisted
+  // into registers held across queries
+  const int64_t q = int64_t(blockIdx.x) * 4 + wave;
+  if (q >= nq) return;
+  {
+    const float* sbq = sbuf + q * int64_t(c) * rcap;
+    // R > 0 (n <= 64 R): candidate i = lane + 64 j keeps its key in register
+    // j.  With one slot the scores are sbq[0, len): their loads are issued
+    // before the pair is read (an index past the slot re-reads an entry of
+    // the query's own buffer and is masked below).
+    float fv[R > 0 ? R : 1];
+    const bool pre = R > 0 && c == 1;
+    if (pre) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) fv[j] = sbq[uint32_t(min(lane + 64 * j, rcap - 1))];
     }
+    // slot table: lane t reads pair t (64 at a time); start[] is the
+    // exclusive prefix sum of the slot lengths, pbase[] each slot's first row
+    int32_t n = 0;
+    for (int t0 = 0; t0 < c; t0 += 64) {
+      const int t = t0 + lane;
+      int32_t len = 0;
+      int64_t base = 0;
+      if (t < c) {
+        const Pair pr = pairs[q * c + t];
+        if (pr.j >= 0) {
+          len = pr.len;
+          base = off[pr.j] + pr.s;
+        }
+      }
+      int32_t incl = len;
+      if (c > 1) {
+        for (int o = 1; o < 64; o <<= 1) {
+          const int32_t y = __shfl_up(incl, o);
+          if (lane >= o) incl += y;
+        }
+      }
+      if (t < c) {
+        start[wave][t] = n + incl - len;
+        pbase[wave][t] = base;
+      }
+      n += __shfl(incl, c > 1 ? 63 : 0);
+    }
+    if (lane == 0) start[wave][c] = n;
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
     const int32_t* st = start[wave];
-    const int32_t n = st[c];
-    const float* sbq = sbuf + q * int64_t(c) * rcap;
     const bool cached = R == 0 && n <= kWaveKeyCache;
     if (cached) {
+      // 8 loads in flight per lane before their keys are stored
       for (int t = 0; t < c; ++t) {
         const int32_t a = st[t], len = st[t + 1] - a;
-        for (int p = lane; p < len; p += 64) keys[wave][a + p] = score_key(sbq[int64_t(t) * rcap + p]);
+        const float* src = sbq + int64_t(t) * rcap;
+        for (int p0 = 0; p0 < len; p0 += 512) {
+          float v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int p = p0 + lane + 64 * u;
+            v[u] = src[p < len ? p : len - 1];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int p = p0 + lane + 64 * u;
+            if (p < len) keys[wave][a + p] = score_key(v[u]);
+          }
+        }
       }
       __threadfence_block();
       __builtin_amdgcn_wave_barrier();
@@ -1891,21 +1936,23 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
     };
     auto row_of = [&](int32_t i) {
       const int t = slot_of(i);
-      return off[pj[wave][t]] + ps[wave][t] + (i - st[t]);
+      return pbase[wave][t] + (i - st[t]);
     };
-    // R > 0 (n <= 64 R): candidate i = lane + 64 j keeps its key in register j
     uint32_t kr[R > 0 ? R : 1];
     if (R > 0) {
+      if (!pre && n > 0) {
+        // several slots: all R loads issued before any key is formed; the
+        // slot of candidate i only moves forward as i grows
+        int t = 0;
 #pragma unroll
-      for (int j = 0; j < R; ++j) {
-        const int32_t i = lane + 64 * j;
-        uint32_t kv = 0xffffffffu;
-        if (i < n) {
-          const int t = slot_of(i);
-          kv = score_key(sbq[int64_t(t) * rcap + (i - st[t])]);
+        for (int j = 0; j < R; ++j) {
+          const int32_t i = min(lane + 64 * j, n - 1);
+          while (t + 1 < c && st[t + 1] <= i) ++t;
+          fv[j] = sbq[int64_t(t) * rcap + (i - st[t])];
         }
-        kr[j] = kv;
       }
+#pragma unroll
+      for (int j = 0; j < R; ++j) kr[j] = lane + 64 * j < n ? score_key(fv[j]) : 0xffffffffu;
     }
     // extraction of the K + 1 smallest (key, index).  First a threshold: tau =
     // the (K+1)-th smallest of the 64 lane minima, so at least K + 1
@@ -1974,13 +2021,20 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
     uint64_t prev = 0;
     int nx = 0;
     if (listed && m <= 64) {
-      // few listed: each lane ranks one entry against all of them
-      uint64_t mine = ~uint64_t(0);
-      if (lane < m) mine = (uint64_t(lkey[wave][lane]) << 32) | uint32_t(lidx[wave][lane]);
+      // few listed: each lane ranks one entry against all of them, reading
+      // the others' (key, index) from their lanes
+      uint32_t mk = 0xffffffffu, mi = 0xffffffffu;
+      if (lane < m) {
+        mk = lkey[wave][lane];
+        mi = uint32_t(lidx[wave][lane]);
+      }
       int rank = 0;
-      for (int u = 0; u < m; ++u)
-        rank += ((uint64_t(lkey[wave][u]) << 32) | uint32_t(lidx[wave][u])) < mine;
-      if (lane < m && rank < want) ext[wave][rank] = mine;
+      for (int u = 0; u < m; ++u) {
+        const uint32_t ku = uint32_t(__builtin_amdgcn_readlane(int(mk), u));
+        const uint32_t iu = uint32_t(__builtin_amdgcn_readlane(int(mi), u));
+        rank += (ku < mk) || (ku == mk && iu < mi);
+      }
+      if (lane < m && rank < want) ext[wave][rank] = (uint64_t(mk) << 32) | mi;
       nx = min(m, want);
     } else {
       for (int r = 0; r < want; ++r) {
@@ -2028,7 +2082,7 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
           for (int p = lane; p < len; p += 64) {
             const uint32_t kk = cached ? keys[wave][a + p] : score_key(sbq[int64_t(t) * rcap + p]);
             if (kk != T) continue;
-            const int64_t row = off[pj[wave][t]] + ps[wave][t] + p;
+            const int64_t row = pbase[wave][t] + p;
             const uint64_t v = (uint64_t(uint32_t(perm32[row])) << 32) | uint32_t(row);
             if ((r == 0 || v > last) && v < best) best = v;
           }
@@ -2044,17 +2098,18 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
       __builtin_amdgcn_wave_barrier();
     }
     // order the winners by (key, id) and write
-    int rank = 0;
-    uint32_t myk = 0, myid = 0;
+    uint32_t myk = 0xffffffffu, myid = 0xffffffffu;
     int64_t myrow = 0;
     if (lane < got) {
       myk = wkey[wave][lane];
       myid = wid[wave][lane];
       myrow = wrow[wave][lane];
-      for (int u = 0; u < got; ++u) {
-        const uint32_t ku = wkey[wave][u], iu = wid[wave][u];
-        rank += (ku < myk) || (ku == myk && iu < myid);
-      }
+    }
+    int rank = 0;
+    for (int u = 0; u < got; ++u) {
+      const uint32_t ku = uint32_t(__builtin_amdgcn_readlane(int(myk), u));
+      const uint32_t iu = uint32_t(__builtin_amdgcn_readlane(int(myid), u));
+      rank += (ku < myk) || (ku == myk && iu < myid);
     }
     if (MODE == 0) {
       if (lane < got) {
@@ -2214,11 +2269,12 @@ __global__ void debug_kernel(const int32_t* __restrict__ l1, const Pair* __restr
 // Wave-per-query selection; candidate keys live in registers when every
 // query's candidate count (at most c * rcap) fits 64 R of them.
 template <int MODE>
-void launch_wave_select(unsigned wgrid, hipStream_t st, const Pair* pairs, const float* sbuf,
-                        int32_t rcap, int32_t c, int64_t nq, int32_t K, const int64_t* off,
+void launch_wave_select(hipStream_t st, const Pair* pairs, const float* sbuf, int32_t rcap,
+                        int32_t c, int64_t nq, int32_t K, const int64_t* off,
                         const int32_t* perm32, int64_t* ids, float* scores, int32_t kout,
                         int32_t* slist, int drop) {
   const int64_t nmax = int64_t(c) * rcap;
+  const unsigned wgrid = unsigned((nq + 3) / 4);  // one wave per query (nq < 2^31)
   if (nmax <= 512)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 8>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
                        rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
@@ -2550,7 +2606,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   mark(4);
   if (!bf16) {
     if (k <= 64)
-      launch_wave_select<0>(wgrid, st, pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids,
+      launch_wave_select<0>(st, pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids,
                             scores, k, slist, int(H > 1));
     else if (k <= 128)
       hipLaunchKernelGGL((select_kernel<128, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
@@ -2560,7 +2616,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
                          p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1));
   } else {
     if (p.S <= 64)
-      launch_wave_select<1>(wgrid, st, pairs, sbuf, p.rcap, c, nq, p.S, ix.off, ix.perm32, ids,
+      launch_wave_select<1>(st, pairs, sbuf, p.rcap, c, nq, p.S, ix.off, ix.perm32, ids,
                             scores, k, slist, int(H > 1));
     else if (p.S <= 512)
       hipLaunchKernelGGL((select_kernel<512, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
