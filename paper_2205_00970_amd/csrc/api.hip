@@ -647,16 +647,14 @@ int lider_hash(const float* X_dev, int64_t n, int32_t d, const float* A_dev, con
   if (n == 0) return LIDER_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   float* anorm = nullptr;
-  int64_t* list = nullptr;
   int32_t* cs = nullptr;
   int rc = alloc(&anorm, size_t(nh), "norms");
-  if (rc == LIDER_OK) rc = alloc(&list, size_t(n) * nh, "hash list");
   if (rc == LIDER_OK) rc = alloc(&cs, 64, "counters");
   if (rc == LIDER_OK) rc = check_hip(hipMemsetAsync(cs, 0, 256, st), "zero");
   if (rc == LIDER_OK) {
     launch_norm_bounds(A_dev, nh, d, anorm, st);
-    rc = run_hash_ex(X_dev, n, d, A_dev, b_dev, anorm, nh, w, out_dev, list, cs, cs + 1, 0,
-                     nullptr, st, LIDER_HASH_E2LSH);
+    rc = run_hash_ex(X_dev, n, d, A_dev, b_dev, anorm, nh, w, out_dev, cs + 1, 0, nullptr, st,
+                     LIDER_HASH_E2LSH);
   }
   int32_t h_status = 0;
   if (rc == LIDER_OK)
@@ -664,7 +662,6 @@ int lider_hash(const float* X_dev, int64_t n, int32_t d, const float* A_dev, con
   if (rc == LIDER_OK) rc = check_hip(hipStreamSynchronize(st), "hash");
   if (rc == LIDER_OK && h_status) rc = set_error(LIDER_ERANGE, "a hash value does not fit in int32");
   if (anorm) (void)hipFree(anorm);
-  if (list) (void)hipFree(list);
   if (cs) (void)hipFree(cs);
   return rc;
 }

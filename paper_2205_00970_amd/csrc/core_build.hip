@@ -453,13 +453,12 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
   const int64_t n = ix.n;
   const int32_t d = ix.d, C = ix.C, m = ix.m, H = ix.H;
   Bufs B;
-  int64_t* list = B.get<int64_t>(size_t(std::max<int64_t>(n, C)) * m);
-  int32_t* cs = B.get<int32_t>(64);  // [0] counter, [1] status
+  int32_t* cs = B.get<int32_t>(64);  // [1] status
   int64_t* l1off = B.get<int64_t>(2);
   int32_t* inv = H > 1 ? B.get<int32_t>(size_t(n)) : nullptr;
   int32_t* inv1 = H > 1 ? B.get<int32_t>(size_t(C)) : nullptr;
-  if (!list || !cs || !l1off || (H > 1 && (!inv || !inv1)))
-    return set_error(LIDER_ENOMEM, "out of device memory (hash list)");
+  if (!cs || !l1off || (H > 1 && (!inv || !inv1)))
+    return set_error(LIDER_ENOMEM, "out of device memory (build scratch)");
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, cs, int64_t(64), 0);
   const bool binary = ix.hash_kind == LIDER_HASH_SIGN;
   const int64_t nleaf = int64_t(C) * ix.F2 + ix.F1;  // leaves of one array
@@ -467,8 +466,8 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
   for (int32_t h = 0; h < H; ++h) {
     const size_t r2 = size_t(H) * m + size_t(h) * m;  // layer-2 hash rows of array h
     int32_t* dig = ix.digits + size_t(h) * n * m;
-    rc = run_hash_ex(Xin, n, d, ix.A + r2 * d, ix.b + r2, ix.anorm + r2, m, ix.w, dig, list, cs,
-                     cs + 1, 0, nullptr, st, ix.hash_kind);
+    rc = run_hash_ex(Xin, n, d, ix.A + r2 * d, ix.b + r2, ix.anorm + r2, m, ix.w, dig, cs + 1, 0,
+                     nullptr, st, ix.hash_kind);
     if (rc != LIDER_OK) return rc;
     rc = build_layer(dig, m, ix.assign, n, C, ix.F2, ix.models + size_t(h) * (C + 1),
                      int64_t(h) * nleaf, ix.leaves, ix.leaf_err, ix.perm + size_t(h) * n,
@@ -477,8 +476,8 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
     // layer 1: the centroids retriever
     const size_t r1 = size_t(h) * m;
     int32_t* dg1 = ix.l1_digits + size_t(h) * C * m;
-    rc = run_hash_ex(ix.cent, C, d, ix.A + r1 * d, ix.b + r1, ix.anorm + r1, m, ix.w, dg1, list,
-                     cs, cs + 1, 0, nullptr, st, ix.hash_kind);
+    rc = run_hash_ex(ix.cent, C, d, ix.A + r1 * d, ix.b + r1, ix.anorm + r1, m, ix.w, dg1, cs + 1,
+                     0, nullptr, st, ix.hash_kind);
     if (rc != LIDER_OK) return rc;
     rc = build_layer(dg1, m, nullptr, C, 1, ix.F1, ix.models + size_t(h) * (C + 1) + C,
                      int64_t(h) * nleaf + int64_t(C) * ix.F2, ix.leaves, ix.leaf_err,

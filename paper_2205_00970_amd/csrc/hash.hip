@@ -18,6 +18,56 @@ namespace lider {
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
+__device__ inline double wave_sum_f64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// FP64 decision of one projection whose MFMA value lay inside the band, by
+// one wave.  The wave first sums the same exact products (fp32 x fp32 is
+// exact in FP64) in parallel; two FP64 sums of the same d terms in different
+// orders differ by at most 2 (d-1) 2^-53 sum|p| (to first order), so when the
+// parallel value is farther than a generous multiple of that from a bucket
+// edge, both floors agree.  Only entries inside that much narrower band run
+// the sequential loop of the definition (one lane, dimension order).  The
+// butterfly sums leave bit-identical totals on every lane, so the branch is
+// wave-uniform.
+__device__ void hash_decide_wave(const float* __restrict__ xr, const float* __restrict__ ar,
+                                 int32_t d, double bh, double w, int kind, int clamp,
+                                 int32_t* __restrict__ out, int32_t* __restrict__ status) {
+  const int lane = threadIdx.x & 63;
+  double ps = 0.0, pa = 0.0;
+  for (int l = lane; l < d; l += 64) {
+    const double pr = double(ar[l]) * double(xr[l]);
+    ps += pr;
+    pa += fabs(pr);
+  }
+  ps = wave_sum_f64(ps);
+  pa = wave_sum_f64(pa);
+  const double u = 1.1102230246251565e-16;  // 2^-53
+  const bool sign = kind == LIDER_HASH_SIGN;
+  const double tp = sign ? ps : (ps + bh) / w;
+  const double fr = tp - floor(tp);
+  const double dist = sign ? fabs(ps) : (fr < 1.0 - fr ? fr : 1.0 - fr);
+  const double band = sign ? 8.0 * double(d) * u * pa
+                           : 8.0 * (double(d) * u * pa + u * (fabs(ps) + fabs(bh))) / w +
+                                 8.0 * u * fabs(tp);
+  if (lane != 0) return;
+  double fl = sign ? (ps >= 0.0 ? 1.0 : 0.0) : floor(tp);
+  if (!(dist > band)) {
+    double sacc = 0.0;
+    for (int l = 0; l < d; ++l) sacc = sacc + double(ar[l]) * double(xr[l]);
+    fl = sign ? (sacc >= 0.0 ? 1.0 : 0.0) : floor((sacc + bh) / w);
+  }
+  if (fl >= -2147483648.0 && fl <= 2147483647.0) {
+    *out = int32_t(fl);
+  } else if (clamp) {
+    *out = fl < 0 ? INT32_MIN : INT32_MAX;
+  } else {
+    atomicExch(status, int32_t(LIDER_ERANGE));
+  }
+}
+
 // Projection kernel.  Block = 4 waves = 16 rows x (up to) 32 hashes, the
 // hashes [32 y, 32 y + 32) of grid row y; the waves split the dimension range
 // (wave w owns a contiguous quarter of the 16-dimension steps).  Lane l of a
@@ -26,15 +76,20 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 // vectors and feeds them to 4 MFMAs (the k index of an MFMA only needs to map
 // to the same dimension on both operands).  The next step's operands are
 // loaded before the current step's MFMAs are issued.  Partial projections are
-// added in wave order through LDS.
+// added in wave order through LDS; the projections inside the band are listed
+// in LDS and decided by hash_decide_wave after the block's other outputs.
+// xb (nullable): the rows rounded to bf16 (round to nearest even), written by
+// the blocks of grid row 0 from the values they load anyway.
 template <bool VEC>
 __global__ __launch_bounds__(256) void hash_kernel(
     const float* __restrict__ X, int64_t n, int32_t d, const float* __restrict__ A,
     const float* __restrict__ bvec, const float* __restrict__ anorm, int32_t nh, double w,
-    int32_t* __restrict__ out, int64_t* __restrict__ list, int32_t* __restrict__ counter,
-    int32_t* __restrict__ status, int clamp, float* __restrict__ rownorm, int kind) {
+    int32_t* __restrict__ out, int32_t* __restrict__ status, int clamp,
+    float* __restrict__ rownorm, int kind, __hip_bfloat16* __restrict__ xb) {
   __shared__ double part[4][32][16];  // [wave][hash][row]
   __shared__ float pss[4][16];
+  __shared__ int32_t qlist[16 * 32];  // (row, hash) entries inside the band
+  __shared__ int32_t qn;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, s = lane >> 4;
   const int64_t row0 = int64_t(blockIdx.x) * 16;
@@ -48,6 +103,7 @@ __global__ __launch_bounds__(256) void hash_kernel(
   const float* a0 = A + int64_t(h0) * d;
   const float* a1 = A + int64_t(h1) * d;
   const bool two = nhc > 16;
+  __hip_bfloat16* xbr = (xb && blockIdx.y == 0 && row0 + i < n) ? xb + (row0 + i) * d : nullptr;
   doublex4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
   float ss = 0.f;
   const int nk = (d + 15) / 16;
@@ -78,6 +134,19 @@ __global__ __launch_bounds__(256) void hash_kernel(
   for (int ks = k0s; ks < k1s; ++ks) {
     float xn[4], an[4], bn[4] = {0.f, 0.f, 0.f, 0.f};
     load(ks + 1 < k1s ? ks + 1 : ks, xn, an, bn);
+    if (xbr) {
+      const int kk = ks * 16 + 4 * s;
+      if (VEC && kk + 3 < d) {
+        __hip_bfloat16 v4[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v4[e] = __float2bfloat16(xe[e]);
+        *reinterpret_cast<uint2*>(xbr + kk) = *reinterpret_cast<const uint2*>(v4);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (kk + e < d) xbr[kk + e] = __float2bfloat16(xe[e]);
+      }
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       ss += xe[e] * xe[e];
@@ -101,6 +170,7 @@ __global__ __launch_bounds__(256) void hash_kernel(
     part[wave][i][s + 4 * e] = acc0[e];
     if (two) part[wave][16 + i][s + 4 * e] = acc1[e];
   }
+  if (threadIdx.x == 0) qn = 0;
   __syncthreads();
   const double u = 1.1102230246251565e-16;  // 2^-53
   const double gam = double(d + 2) * 5.9604644775390625e-08;
@@ -119,12 +189,10 @@ __global__ __launch_bounds__(256) void hash_kernel(
     const double pa = an * xn + double(d) * an * 1.1754943508222875e-38;
     if (kind == LIDER_HASH_SIGN) {  // bit = [a.x >= 0]: decided unless |a.x| is within the band
       const double E = 8.0 * double(d + 4) * u * pa;
-      if (!(fabs(sv) > E)) {
-        const int32_t slot = atomicAdd(counter, 1);
-        list[slot] = oi;
-      } else {
+      if (!(fabs(sv) > E))
+        qlist[atomicAdd(&qn, 1)] = o;
+      else
         out[oi] = sv > 0.0 ? 1 : 0;
-      }
       continue;
     }
     const double bh = double(bvec[hash]);
@@ -135,8 +203,7 @@ __global__ __launch_bounds__(256) void hash_kernel(
     const double fr = tv - fl;
     const double dist = fr < 1.0 - fr ? fr : 1.0 - fr;
     if (!(dist > E)) {
-      const int32_t slot = atomicAdd(counter, 1);
-      list[slot] = oi;
+      qlist[atomicAdd(&qn, 1)] = o;
     } else if (fl >= -2147483648.0 && fl <= 2147483647.0) {
       out[oi] = int32_t(fl);
     } else if (clamp) {
@@ -145,85 +212,15 @@ __global__ __launch_bounds__(256) void hash_kernel(
       atomicExch(status, int32_t(LIDER_ERANGE));
     }
   }
-}
-
-// FP64 recompute of queued (row, hash) projections, one wave per entry.  The
-// definition is the sequential FP64 sum in dimension order.  The wave first
-// sums the same exact products (fp32 x fp32 is exact in FP64) in parallel; two
-// FP64 sums of the same d terms in different orders differ by at most
-// 2 (d-1) 2^-53 sum|p| (to first order), so when the parallel value is farther
-// than a generous multiple of that from a bucket edge, both floors agree.
-// Only entries inside that much narrower band run the sequential loop (one
-// lane, operands staged in LDS).
-constexpr int kFixupLds = 1024;
-
-__device__ inline double wave_sum_f64(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-__global__ __launch_bounds__(256) void hash_fixup_kernel(
-    const float* __restrict__ X, int32_t d, const float* __restrict__ A,
-    const float* __restrict__ bvec, int32_t nh, double w, int32_t* __restrict__ out,
-    const int64_t* __restrict__ list, const int32_t* __restrict__ counter,
-    int32_t* __restrict__ status, int clamp, int kind) {
-  __shared__ float sx[4][kFixupLds], sa[4][kFixupLds];
-  __shared__ int s_seq[4];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int32_t cnt = *counter;
-  const bool staged = d <= kFixupLds;
-  for (int32_t t = blockIdx.x * 4 + wave; t < cnt; t += gridDim.x * 4) {
-    const int64_t o = list[t];
-    const int64_t row = o / nh;
-    const int hash = int(o - row * nh);
-    const float* xr = X + row * d;
-    const float* ar = A + int64_t(hash) * d;
-    double ps = 0.0, pa = 0.0;
-    for (int l = lane; l < d; l += 64) {
-      const float xv = xr[l], av = ar[l];
-      if (staged) {
-        sx[wave][l] = xv;
-        sa[wave][l] = av;
-      }
-      const double pr = double(av) * double(xv);
-      ps += pr;
-      pa += fabs(pr);
-    }
-    ps = wave_sum_f64(ps);
-    pa = wave_sum_f64(pa);
-    const double u = 1.1102230246251565e-16;  // 2^-53
-    const bool sign = kind == LIDER_HASH_SIGN;
-    const double bh = sign ? 0.0 : double(bvec[hash]);
-    const double tp = sign ? ps : (ps + bh) / w;
-    const double fp = sign ? (ps >= 0.0 ? 1.0 : 0.0) : floor(tp);
-    const double fr = tp - floor(tp);
-    const double dist = sign ? fabs(ps) : (fr < 1.0 - fr ? fr : 1.0 - fr);
-    const double band = sign ? 8.0 * double(d) * u * pa
-                             : 8.0 * (double(d) * u * pa + u * (fabs(ps) + fabs(bh))) / w +
-                                   8.0 * u * fabs(tp);
-    if (lane == 0) s_seq[wave] = !(dist > band);
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-    if (lane == 0) {
-      double fl = fp;
-      if (s_seq[wave]) {
-        double sacc = 0.0;
-        if (staged)
-          for (int l = 0; l < d; ++l) sacc = sacc + double(sa[wave][l]) * double(sx[wave][l]);
-        else
-          for (int l = 0; l < d; ++l) sacc = sacc + double(ar[l]) * double(xr[l]);
-        fl = sign ? (sacc >= 0.0 ? 1.0 : 0.0) : floor((sacc + bh) / w);
-      }
-      if (fl >= -2147483648.0 && fl <= 2147483647.0) {
-        out[o] = int32_t(fl);
-      } else if (clamp) {
-        out[o] = fl < 0 ? INT32_MIN : INT32_MAX;
-      } else {
-        atomicExch(status, int32_t(LIDER_ERANGE));
-      }
-    }
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
+  __syncthreads();
+  const int nq = qn;
+  for (int e = wave; e < nq; e += 4) {
+    const int o = qlist[e];
+    const int ri = o / nhc, hash = hb + (o - ri * nhc);
+    const int64_t row = row0 + ri;
+    hash_decide_wave(X + row * d, A + int64_t(hash) * d, d,
+                     kind == LIDER_HASH_SIGN ? 0.0 : double(bvec[hash]), w, kind, clamp,
+                     out + row * nh + hash, status);
   }
 }
 
@@ -237,42 +234,29 @@ __global__ void norm_bound_kernel(const float* __restrict__ A, int32_t rows, int
   out[r] = float(sqrt(s) * (1.0 + 9.5367431640625e-07));
 }
 
-__global__ void zero_i32_kernel(int32_t* p, int64_t cnt) {
-  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < cnt;
-       t += int64_t(gridDim.x) * blockDim.x)
-    p[t] = 0;
-}
-
 void launch_norm_bounds(const float* A, int32_t rows, int32_t d, float* out, hipStream_t st) {
   hipLaunchKernelGGL(norm_bound_kernel, dim3((rows + 63) / 64), dim3(64), 0, st, A, rows, d, out);
 }
 
-size_t hash_list_capacity(int64_t n, int32_t nh) { return size_t(n) * size_t(nh); }
-
-// Enqueue digits of n rows into out [n x nh].  list must hold n*nh int64;
-// counter and status are single device ints (zeroed here).  rownorm (nullable)
-// receives an upper bound of each row's norm.
+// Digits of n rows into out [n x nh].  status is a device int set to
+// LIDER_ERANGE when a digit does not fit int32 and clamp is 0.  rownorm
+// (nullable) receives an upper bound of each row's norm, xb (nullable) the
+// rows rounded to bf16.
 int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const float* b,
-                const float* anorm, int32_t nh, double w, int32_t* out, int64_t* list,
-                int32_t* counter, int32_t* status, int clamp, float* rownorm, hipStream_t st,
-                int kind) {
+                const float* anorm, int32_t nh, double w, int32_t* out, int32_t* status,
+                int clamp, float* rownorm, hipStream_t st, int kind, __hip_bfloat16* xb) {
   if (n <= 0) return LIDER_OK;
-  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, counter, int64_t(1));
   const bool vec = (d % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
-                   ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+                   ((reinterpret_cast<uintptr_t>(A) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(xb) & 7) == 0);
   const dim3 grid(unsigned((n + 15) / 16), unsigned((nh + 31) / 32));
   if (vec)
     hipLaunchKernelGGL(hash_kernel<true>, grid, dim3(256), 0, st, X, n, d, A, b, anorm, nh, w,
-                       out, list, counter, status, clamp, rownorm, kind);
+                       out, status, clamp, rownorm, kind, xb);
   else
     hipLaunchKernelGGL(hash_kernel<false>, grid, dim3(256), 0, st, X, n, d, A, b, anorm, nh, w,
-                       out, list, counter, status, clamp, rownorm, kind);
-  int64_t cap = n * nh;
-  int64_t blocks = (cap + 3) / 4;
-  if (blocks > 512) blocks = 512;  // queued entries are rare; the grid strides over them
-  hipLaunchKernelGGL(hash_fixup_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, X, d, A, b, nh,
-                     w, out, list, counter, status, clamp, kind);
-  return check_hip(hipGetLastError(), "hash kernels");
+                       out, status, clamp, rownorm, kind, xb);
+  return check_hip(hipGetLastError(), "hash kernel");
 }
 
 }  // namespace lider

@@ -218,10 +218,9 @@ int check_hip(hipError_t e, const char* what);
 // ------------------------------------------------------------- build kernels
 // hash.hip
 int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const float* b,
-                const float* anorm, int32_t nh, double w, int32_t* out, int64_t* list,
-                int32_t* counter, int32_t* status, int clamp, float* rownorm, hipStream_t st,
-                int kind = 0);
-size_t hash_list_capacity(int64_t n, int32_t nh);
+                const float* anorm, int32_t nh, double w, int32_t* out, int32_t* status,
+                int clamp, float* rownorm, hipStream_t st, int kind = 0,
+                __hip_bfloat16* xb = nullptr);
 void launch_norm_bounds(const float* A, int32_t rows, int32_t d, float* out, hipStream_t st);
 
 // kmeans.hip

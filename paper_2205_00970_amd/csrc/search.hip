@@ -34,7 +34,7 @@ struct alignas(16) Pair {
   int32_t j, s, len, pos;
 };
 
-// Counters block layout (int32): [0] hash list count, [1] status,
+// Counters block layout (int32): [0] unused, [1] status,
 // [8..15] per-XCD tile counters of the persistent rerank, [16] active-tile
 // count.
 constexpr int kCtrWords = 64;
@@ -45,7 +45,7 @@ constexpr int kCandCap = 256;
 constexpr int32_t kBufWord3 = 0x00020000;  // buffer resource word 3 for gfx9-family targets
 
 struct Plan {
-  size_t o_ctr, o_qdig, o_hlist, o_qnorm, o_l1, o_l1p, o_l1cs, o_rs, o_rs64, o_routed, o_pairs,
+  size_t o_ctr, o_qdig, o_qnorm, o_l1, o_l1p, o_l1cs, o_rs, o_rs64, o_routed, o_pairs,
       o_ccount, o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, o_aflag, o_alist, o_kq, o_lst,
       o_rw, o_pw, o_mask, o_rcand, o_rcnt, total;
   int32_t r1, rcap, S;
@@ -89,7 +89,6 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   };
   p.o_ctr = take(kCtrWords * 4);
   p.o_qdig = take(size_t(nq) * 2 * H * ix.m * 4);
-  p.o_hlist = take(size_t(nq) * 2 * H * ix.m * 8);
   p.o_qnorm = take(size_t(nq) * 4);
   p.o_l1 = take(size_t(nq) * H * 3 * 4);
   p.o_l1p = take(size_t(nq) * H * sizeof(Pair));
@@ -121,6 +120,17 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   p.rcap = rcap;
   p.S = S;
   return p;
+}
+
+// Zeroes a [0, na) and both b and c [0, nbc): the search's counters in one launch.
+__global__ void zero3_kernel(int32_t* __restrict__ a, int32_t na, int32_t* __restrict__ b,
+                             int32_t* __restrict__ c, int32_t nbc) {
+  const int32_t t = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < na) a[t] = 0;
+  if (t < nbc) {
+    b[t] = 0;
+    c[t] = 0;
+  }
 }
 
 __global__ void zero_kernel(int32_t* p, int64_t cnt) {
@@ -1724,13 +1734,6 @@ __global__ __launch_bounds__(256) void l1_gemm_lds_kernel(const __hip_bfloat16* 
   }
 }
 
-__global__ void to_bf16_kernel(const float* __restrict__ a, int64_t cnt,
-                               __hip_bfloat16* __restrict__ b) {
-  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < cnt;
-       t += int64_t(gridDim.x) * blockDim.x)
-    b[t] = __float2bfloat16(a[t]);
-}
-
 // ------------------------------------------------------------ final top-k
 constexpr int kSelNT = 256;
 constexpr int kKeyCache = 8192;
@@ -2460,7 +2463,6 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   char* W = static_cast<char*>(ws);
   int32_t* ctr = reinterpret_cast<int32_t*>(W + p.o_ctr);
   int32_t* qdig = reinterpret_cast<int32_t*>(W + p.o_qdig);
-  int64_t* hlist = reinterpret_cast<int64_t*>(W + p.o_hlist);
   float* qnorm = reinterpret_cast<float*>(W + p.o_qnorm);
   int32_t* l1 = reinterpret_cast<int32_t*>(W + p.o_l1);
   Pair* l1pairs = reinterpret_cast<Pair*>(W + p.o_l1p);
@@ -2492,12 +2494,19 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   auto mark = [&](int i) {
     if (ev) (void)hipEventRecord(ev[i], st);
   };
+  // fp8 centroids (precision form) only feed the window kernel
+  const bool fp8 = bf16 && ix.cent8 && !p.l1_dense_rows;
+  // Layer-1 scores: dense rows (every centroid; bf16 product unless fp32 is
+  // asked for or the bf16 copy is missing) or the window kernel; then the
+  // exact routing (or, for fp8 window scores, the approximate routing) over
+  // each query's window or union list.  The bf16 queries these need are
+  // written by the hash kernel.
+  const bool l1b = !fp8 && o.l1_dense == 0 && ix.cent_l1_b;
   mark(0);
-  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, st, ctr, int64_t(kCtrWords));
-  hipLaunchKernelGGL(zero_kernel, dim3((C + 255) / 256), dim3(256), 0, st, ccount, int64_t(C));
-  hipLaunchKernelGGL(zero_kernel, dim3((C + 255) / 256), dim3(256), 0, st, cfill, int64_t(C));
-  int rc = run_hash_ex(Q, nq, ix.d, ix.A, ix.b, ix.anorm, 2 * H * m, ix.w, qdig, hlist, ctr,
-                       ctr + 1, 1, qnorm, st, ix.hash_kind);
+  hipLaunchKernelGGL(zero3_kernel, dim3(unsigned(std::max(1, (C + 255) / 256))), dim3(256), 0, st,
+                     ctr, int32_t(kCtrWords), ccount, cfill, C);
+  int rc = run_hash_ex(Q, nq, ix.d, ix.A, ix.b, ix.anorm, 2 * H * m, ix.w, qdig, ctr + 1, 1, qnorm,
+                       st, ix.hash_kind, (fp8 || bf16 || l1b) ? qb : nullptr);
   if (rc != LIDER_OK) return rc;
   mark(1);
   const int64_t nl1 = nq * H;  // (query, array) layer-1 items
@@ -2508,15 +2517,6 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
     hipLaunchKernelGGL(expand_kernel, dim3(unsigned((nl1 + 3) / 4)), dim3(256), 0, st,
                        ix.l1_keys, (const int64_t*)nullptr, int64_t(C), l1pairs, nl1, kq, p.r1,
                        m, o.expand_bits, l1, H, int64_t(C));
-  // fp8 centroids (precision form) only feed the window kernel
-  const bool fp8 = bf16 && ix.cent8 && !p.l1_dense_rows;
-  // Layer-1 scores: dense rows (every centroid; bf16 product unless fp32 is
-  // asked for or the bf16 copy is missing) or the window kernel; then the
-  // exact routing (or, for fp8 window scores, the approximate routing) over
-  // each query's window or union list.
-  const bool l1b = !fp8 && o.l1_dense == 0 && ix.cent_l1_b;
-  if (fp8 || bf16 || l1b)
-    hipLaunchKernelGGL(to_bf16_kernel, dim3(2048), dim3(256), 0, st, Q, nq * ix.d, qb);
   const unsigned qgrid = unsigned(std::min<int64_t>(nq, 65535));
   const unsigned wgrid = unsigned(std::min<int64_t>((nq + 3) / 4, 65535));
   // the window each routing kernel reads: (l1w[wst q + 1], l1w[wst q + 2]);
