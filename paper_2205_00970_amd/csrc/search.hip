@@ -562,79 +562,102 @@ __global__ __launch_bounds__(256) void route_filter_kernel(
     const int32_t* __restrict__ l1, int32_t wst, const int32_t* __restrict__ lst, int32_t lcap,
     const float* __restrict__ rs, int32_t rstride, int dense, const float* __restrict__ qnorm,
     const float* __restrict__ cent_norm_max, double ecoef, int32_t c,
-    int32_t* __restrict__ rcand, int32_t* __restrict__ rcnt, int32_t* __restrict__ routed) {
+    int32_t* __restrict__ rcand, int32_t* __restrict__ rcnt, int32_t* __restrict__ routed,
+    int whole) {
+  __shared__ int32_t cpos[4][kCandCap];
   const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));  // uniform
   const uint64_t below = (uint64_t(1) << lane) - 1;
-  for (int64_t q = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); q < nq;
-       q += int64_t(gridDim.x) * 4) {
-    const int32_t s1 = l1[wst * q + 1], len1 = l1[wst * q + 2];
-    const int32_t* lq = lst ? lst + q * lcap : nullptr;
-    const float* rsq = rs + q * rstride;
-    auto pos_of = [&](int p) { return lq ? lq[p] : s1 + p; };
-    auto score_at = [&](int p) { return rsq[dense ? pos_of(p) : p]; };
-    if (len1 <= c) {  // every window entry is routed
-      for (int t = lane; t < c; t += 64) routed[q * c + t] = t < len1 ? l1_order32[pos_of(t)] : -1;
-      if (lane == 0) rcnt[q] = 0;
-      continue;
+  // one query per wave, no loop (per-query index arithmetic is not hoisted
+  // into registers held across queries)
+  const int64_t q = int64_t(blockIdx.x) * 4 + wave;
+  if (q >= nq) return;
+  const float* rsq = rs + q * rstride;
+  // whole: every query's window is the whole dense row [0, rstride), so the
+  // score loads are issued before the window is read
+  float v[R > 0 ? R : 1];
+  if (R > 0 && whole) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) v[j] = rsq[uint32_t(min(lane + 64 * j, rstride - 1))];
+  }
+  const float qn = qnorm[q], cmax = *cent_norm_max;
+  const int32_t s1 = l1[wst * q + 1], len1 = l1[wst * q + 2];
+  const int32_t* lq = lst ? lst + q * lcap : nullptr;
+  auto pos_of = [&](int p) { return lq ? lq[p] : s1 + p; };
+  auto score_at = [&](int p) { return rsq[dense ? pos_of(p) : p]; };
+  if (len1 <= c) {  // every window entry is routed
+    for (int t = lane; t < c; t += 64) routed[q * c + t] = t < len1 ? l1_order32[pos_of(t)] : -1;
+    if (lane == 0) rcnt[q] = 0;
+    return;
+  }
+  if (R > 0 && !whole) {
+    // all loads of a kind issued together (an index past the window re-reads
+    // its last entry; those lanes are masked below)
+    if (lq && dense) {
+      int32_t pp[R > 0 ? R : 1];
+#pragma unroll
+      for (int j = 0; j < R; ++j) pp[j] = lq[min(lane + 64 * j, len1 - 1)];
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[j] = rsq[pp[j]];
+    } else {
+      const int32_t o0 = dense ? s1 : 0;
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[j] = rsq[o0 + min(lane + 64 * j, len1 - 1)];
     }
-    float v[R > 0 ? R : 1];
+  }
+  // T: the c-th largest approximate score (c rounds of a wave minimum over
+  // score keys; the index part keeps equal scores apart)
+  uint64_t prev = 0;
+  for (int t = 0; t < c; ++t) {
+    uint64_t best = ~uint64_t(0);
     if (R > 0) {
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const int p = lane + 64 * j;
-        v[j] = p < len1 ? score_at(p) : 0.f;
+        const uint64_t key = (uint64_t(score_key(v[j])) << 32) | uint32_t(p);
+        if (p < len1 && (t == 0 || key > prev) && key < best) best = key;
+      }
+    } else {
+      for (int p = lane; p < len1; p += 64) {
+        const uint64_t key = (uint64_t(score_key(score_at(p))) << 32) | uint32_t(p);
+        if ((t == 0 || key > prev) && key < best) best = key;
       }
     }
-    // T: the c-th largest approximate score (c rounds of a wave minimum over
-    // score keys; the index part keeps equal scores apart)
-    uint64_t prev = 0;
-    for (int t = 0; t < c; ++t) {
-      uint64_t best = ~uint64_t(0);
-      if (R > 0) {
+    prev = wave_min_u64(best);
+  }
+  const double E = ecoef * double(qn) * double(cmax) +
+                   double(d) * 7.888609052210118e-31;  // d * 2^-100: subnormal products
+  const double thr = double(key_score(uint32_t(prev >> 32))) - 2.0 * E;
+  // candidates in window order: their window entries in LDS (positions are
+  // looked up only for them)
+  int n = 0;
+  const int nchunk = (len1 + 63) / 64;
+  for (int jc = 0; jc < nchunk; ++jc) {
+    const int p = jc * 64 + lane;
+    float sv = 0.f;
+    if (R > 0) {
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-          const int p = lane + 64 * j;
-          const uint64_t key = (uint64_t(score_key(v[j])) << 32) | uint32_t(p);
-          if (p < len1 && (t == 0 || key > prev) && key < best) best = key;
-        }
-      } else {
-        for (int p = lane; p < len1; p += 64) {
-          const uint64_t key = (uint64_t(score_key(score_at(p))) << 32) | uint32_t(p);
-          if ((t == 0 || key > prev) && key < best) best = key;
-        }
-      }
-      prev = wave_min_u64(best);
+      for (int j = 0; j < R; ++j)
+        if (j == jc) sv = v[j];
+    } else if (p < len1) {
+      sv = score_at(p);
     }
-    const double E = ecoef * double(qnorm[q]) * double(*cent_norm_max) +
-                     double(d) * 7.888609052210118e-31;  // d * 2^-100: subnormal products
-    const double thr = double(key_score(uint32_t(prev >> 32))) - 2.0 * E;
+    const bool in = p < len1 && double(sv) >= thr;
+    const uint64_t m = __ballot(in);
+    const int slot = n + __popcll(m & below);
+    if (in && slot < kCandCap) cpos[wave][slot] = p;
+    n += __popcll(m);
+  }
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+  if (n == c) {  // the candidates are the routed set (listed in window order)
+    for (int t = lane; t < c; t += 64) routed[q * c + t] = l1_order32[pos_of(cpos[wave][t])];
+    if (lane == 0) rcnt[q] = 0;
+  } else {
     int32_t* cq = rcand + q * kCandCap;
-    int n = 0;
-    const int nchunk = (len1 + 63) / 64;
-    for (int jc = 0; jc < nchunk; ++jc) {
-      const int p = jc * 64 + lane;
-      float sv = 0.f;
-      if (R > 0) {
-#pragma unroll
-        for (int j = 0; j < R; ++j)
-          if (j == jc) sv = v[j];
-      } else if (p < len1) {
-        sv = score_at(p);
-      }
-      const bool in = p < len1 && double(sv) >= thr;
-      const uint64_t m = __ballot(in);
-      const int slot = n + __popcll(m & below);
-      if (in && slot < kCandCap) cq[slot] = pos_of(p);
-      n += __popcll(m);
-    }
-    if (n == c) {  // the candidates are the routed set (listed in window order)
-      __threadfence_block();
-      __builtin_amdgcn_wave_barrier();
-      for (int t = lane; t < c; t += 64) routed[q * c + t] = l1_order32[cq[t]];
-      if (lane == 0) rcnt[q] = 0;
-    } else if (lane == 0) {
-      rcnt[q] = n > kCandCap ? kCandCap + 1 : n;
-    }
+    const int nl = min(n, kCandCap);
+    for (int t = lane; t < nl; t += 64) cq[t] = pos_of(cpos[wave][t]);
+    if (lane == 0) rcnt[q] = n > kCandCap ? kCandCap + 1 : n;
   }
 }
 
@@ -2552,14 +2575,17 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
       hipLaunchKernelGGL(route_approx_block_kernel, dim3(qgrid), dim3(kRouteNT), 0, st, nq,
                          ix.l1_order32, l1w, wst, lstp, p.lcap, rs, rstride, dense, c, routed);
   } else {
+    // every window is the whole dense row when r1 >= C with a single window per query
+    const int whole = dense && !lstp && p.r1 >= C && o.expand_bits == 0;
+    const unsigned fgrid = unsigned((nq + 3) / 4);  // one wave per query (nq < 2^31)
     if (p.lcap <= 16 * 64)
-      hipLaunchKernelGGL(route_filter_kernel<16>, dim3(wgrid), dim3(256), 0, st, ix.d, nq,
+      hipLaunchKernelGGL(route_filter_kernel<16>, dim3(fgrid), dim3(256), 0, st, ix.d, nq,
                          ix.l1_order32, l1w, wst, lstp, p.lcap, rs, rstride, dense, qnorm,
-                         ix.cent_norm_max, ecoef, c, rcand, rcnt, routed);
+                         ix.cent_norm_max, ecoef, c, rcand, rcnt, routed, whole);
     else
-      hipLaunchKernelGGL(route_filter_kernel<0>, dim3(wgrid), dim3(256), 0, st, ix.d, nq,
+      hipLaunchKernelGGL(route_filter_kernel<0>, dim3(fgrid), dim3(256), 0, st, ix.d, nq,
                          ix.l1_order32, l1w, wst, lstp, p.lcap, rs, rstride, dense, qnorm,
-                         ix.cent_norm_max, ecoef, c, rcand, rcnt, routed);
+                         ix.cent_norm_max, ecoef, c, rcand, rcnt, routed, whole);
     hipLaunchKernelGGL(route_rescore_kernel, dim3(wgrid), dim3(256), 0, st, Q, ix.d, nq,
                        ix.cent_l1, ix.l1_order32, l1w, wst, lstp, p.lcap, c, rcand, rcnt, rs64,
                        routed);
