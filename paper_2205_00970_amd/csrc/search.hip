@@ -328,30 +328,40 @@ __host__ __device__ inline int pow2_at_least(int v) {
 // kq (nullable) receives each query's layer-1 key for the dist_e expansion.
 // One thread per (query, array) item t = q H + h: array h's model, digits and
 // window.
-__global__ void l1_kernel(const Model* __restrict__ models, const double* __restrict__ leaves,
-                          const int32_t* __restrict__ qdig, int32_t m, int32_t H, int64_t nq,
-                          int32_t C, int32_t r1, int32_t* __restrict__ l1,
-                          Pair* __restrict__ l1pairs, int32_t* __restrict__ l1cs,
-                          uint64_t* __restrict__ kq) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+struct L1Args {
+  const Model* models;
+  const double* leaves;
+  const int32_t* qdig;
+  int32_t m, H;
+  int64_t nq;
+  int32_t C, r1;
+  int32_t* l1;
+  Pair* l1pairs;
+  int32_t* l1cs;
+  uint64_t* kq;
+};
+
+__device__ inline void l1_item(const L1Args& a, int64_t t) {
   if (t == 0) {
-    l1cs[0] = 0;
-    l1cs[1] = int32_t(nq);
+    a.l1cs[0] = 0;
+    a.l1cs[1] = int32_t(a.nq);
   }
-  if (t >= nq * H) return;
-  const int64_t q = t / H;
-  const int32_t h = int32_t(t - q * H);
+  if (t >= a.nq * a.H) return;
+  const int64_t q = t / a.H;
+  const int32_t h = int32_t(t - q * a.H);
   uint64_t K = 0;
-  const int64_t pos = locate(models[int64_t(h) * (C + 1) + C], leaves,
-                             qdig + q * 2 * H * m + int64_t(h) * m, &K);
+  const int64_t pos = locate(a.models[int64_t(h) * (a.C + 1) + a.C], a.leaves,
+                             a.qdig + q * 2 * a.H * a.m + int64_t(h) * a.m, &K);
   int64_t s, len;
-  window_of(pos, r1, C, &s, &len);  // the expansion (if any) replaces s later
-  if (kq) kq[t] = K;
-  l1[3 * t] = int32_t(pos);
-  l1[3 * t + 1] = int32_t(s);
-  l1[3 * t + 2] = int32_t(len);
-  l1pairs[t] = Pair{0, int32_t(s), int32_t(len), int32_t(pos)};
+  window_of(pos, a.r1, a.C, &s, &len);  // the expansion (if any) replaces s later
+  if (a.kq) a.kq[t] = K;
+  a.l1[3 * t] = int32_t(pos);
+  a.l1[3 * t + 1] = int32_t(s);
+  a.l1[3 * t + 2] = int32_t(len);
+  a.l1pairs[t] = Pair{0, int32_t(s), int32_t(len), int32_t(pos)};
 }
+
+__global__ void l1_kernel(L1Args a) { l1_item(a, int64_t(blockIdx.x) * blockDim.x + threadIdx.x); }
 
 // Union of a query's H layer-1 windows, as ascending positions of array 0's
 // layer-1 order: one wave per query marks the windows in an LDS bitmap of C
@@ -1671,20 +1681,30 @@ __global__ __launch_bounds__(256) void l1_gemm_kernel(const void* __restrict__ Q
 // tiles of one XCD share their query rows in its L2.
 constexpr int kLdsK = 64, kLdsRow = 72;
 
+//
+// The first l1_blocks workgroups (a multiple of 8) instead run the layer-1
+// locate (l1_item) of 256 items each: both only need the hash kernel's
+// output, so one launch runs them side by side.
 __global__ __launch_bounds__(256) void l1_gemm_lds_kernel(const __hip_bfloat16* __restrict__ Q,
                                                           int64_t nq,
                                                           const __hip_bfloat16* __restrict__ Cc,
                                                           int32_t C, int32_t d,
-                                                          float* __restrict__ rs) {
+                                                          float* __restrict__ rs, L1Args la,
+                                                          unsigned l1_blocks) {
   __shared__ __attribute__((aligned(16))) __hip_bfloat16 sa[2][128 * kLdsRow];
   __shared__ __attribute__((aligned(16))) __hip_bfloat16 sb[2][128 * kLdsRow];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (blockIdx.x < l1_blocks) {
+    l1_item(la, int64_t(blockIdx.x) * 256 + tid);
+    return;
+  }
+  const unsigned bid = blockIdx.x - l1_blocks;
   const int i = lane & 15, s = lane >> 4;
   const int64_t ntc = (C + 127) / 128;
   const int64_t nblk = (nq + 127) / 128 * ntc;
   const int64_t per = (nblk + 7) / 8;
-  const int64_t t = int64_t(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if ((blockIdx.x >> 3) >= per || t >= nblk) return;
+  const int64_t t = int64_t(bid & 7) * per + (bid >> 3);
+  if ((bid >> 3) >= per || t >= nblk) return;
   const int64_t m0 = (t / ntc) * 128;
   const int32_t n0 = int32_t(t % ntc) * 128;
   // loader: thread tid moves 16 B (8 bf16) of rows tid / 8 + 32 j, columns 8 (tid % 8)
@@ -2433,12 +2453,15 @@ void launch_l1_gemm_mb(const Index& ix, bool fp8, int64_t nq, const float* Q,
 }
 
 // bf16 query x bf16 centroid product (candidate scores of the exact routing).
+// With la (d a multiple of 64 only), the same launch also runs the layer-1
+// locate of every (query, array) item.
 void launch_l1_gemm_bf16(const Index& ix, int64_t nq, const __hip_bfloat16* Qb, float* rs,
-                         hipStream_t st) {
+                         hipStream_t st, const L1Args* la = nullptr) {
   if (ix.d % kLdsK == 0) {
     const int64_t nblk = (nq + 127) / 128 * ((ix.C + 127) / 128);
-    hipLaunchKernelGGL(l1_gemm_lds_kernel, dim3(unsigned((nblk + 7) / 8 * 8)), dim3(256), 0, st, Qb,
-                       nq, ix.cent_l1_b, ix.C, ix.d, rs);
+    const unsigned l1b = la ? unsigned((la->nq * la->H + 255) / 256 + 7) / 8 * 8 : 0u;
+    hipLaunchKernelGGL(l1_gemm_lds_kernel, dim3(l1b + unsigned((nblk + 7) / 8 * 8)), dim3(256), 0,
+                       st, Qb, nq, ix.cent_l1_b, ix.C, ix.d, rs, la ? *la : L1Args{}, l1b);
     return;
   }
   const int64_t nblk4 = (nq + 127) / 128 * ((ix.C + kGemmTileN - 1) / kGemmTileN);
@@ -2533,9 +2556,15 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   if (rc != LIDER_OK) return rc;
   mark(1);
   const int64_t nl1 = nq * H;  // (query, array) layer-1 items
-  hipLaunchKernelGGL(l1_kernel, dim3(unsigned((nl1 + 255) / 256)), dim3(256), 0, st, ix.models,
-                     ix.leaves, qdig, m, H, nq, C, p.r1, l1, l1pairs, l1cs,
-                     o.expand_bits > 0 ? kq : (uint64_t*)nullptr);
+  const L1Args la{ix.models, ix.leaves, qdig, m, H, nq, C, p.r1, l1, l1pairs, l1cs,
+                  o.expand_bits > 0 ? kq : (uint64_t*)nullptr};
+  // the dense bf16 product on the LDS kernel carries the layer-1 locate in its
+  // launch; otherwise it has a launch of its own
+  const bool l1_fused = p.l1_dense_rows && l1b && ix.d % kLdsK == 0;
+  if (l1_fused)
+    launch_l1_gemm_bf16(ix, nq, qb, rs, st, &la);
+  else
+    hipLaunchKernelGGL(l1_kernel, dim3(unsigned((nl1 + 255) / 256)), dim3(256), 0, st, la);
   if (o.expand_bits > 0)
     hipLaunchKernelGGL(expand_kernel, dim3(unsigned((nl1 + 3) / 4)), dim3(256), 0, st,
                        ix.l1_keys, (const int64_t*)nullptr, int64_t(C), l1pairs, nl1, kq, p.r1,
@@ -2559,7 +2588,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   if (!p.l1_dense_rows) {
     launch_l1_scores(ix, fp8, nq, l1cs, l1pairs, Q, qb, rs, p.r1, st);
   } else if (l1b) {
-    launch_l1_gemm_bf16(ix, nq, qb, rs, st);
+    if (!l1_fused) launch_l1_gemm_bf16(ix, nq, qb, rs, st);
     const double u = 0.00390625;  // 2^-8: bf16 rounding of each operand
     ecoef = 2.0 * u + u * u + dot_err_coef(ix.d) * (1.0 + u) * (1.0 + u);
   } else {
