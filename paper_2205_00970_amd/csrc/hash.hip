@@ -79,13 +79,24 @@ __device__ void hash_decide_wave(const float* __restrict__ xr, const float* __re
 // added in wave order through LDS; the projections inside the band are listed
 // in LDS and decided by hash_decide_wave after the block's other outputs.
 // xb (nullable): the rows rounded to bf16 (round to nearest even), written by
-// the blocks of grid row 0 from the values they load anyway.
+// the blocks of grid row 0 from the values they load anyway.  z: counters
+// the caller's later kernels need cleared, cleared by the blocks of grid row
+// 0 (status must not be among them unless clamp is set: this kernel only
+// writes status when it is not).
 template <bool VEC>
 __global__ __launch_bounds__(256) void hash_kernel(
     const float* __restrict__ X, int64_t n, int32_t d, const float* __restrict__ A,
     const float* __restrict__ bvec, const float* __restrict__ anorm, int32_t nh, double w,
     int32_t* __restrict__ out, int32_t* __restrict__ status, int clamp,
-    float* __restrict__ rownorm, int kind, __hip_bfloat16* __restrict__ xb) {
+    float* __restrict__ rownorm, int kind, __hip_bfloat16* __restrict__ xb, HashZero z) {
+  if (blockIdx.y == 0 && z.nz > 0) {
+    for (int32_t t = int32_t(blockIdx.x) * 256 + threadIdx.x; t < z.nz;
+         t += int32_t(gridDim.x) * 256) {
+      if (z.a && t < z.na) z.a[t] = 0;
+      if (z.b && t < z.nb) z.b[t] = 0;
+      if (z.c && t < z.nb) z.c[t] = 0;
+    }
+  }
   __shared__ double part[4][32][16];  // [wave][hash][row]
   __shared__ float pss[4][16];
   __shared__ int32_t qlist[16 * 32];  // (row, hash) entries inside the band
@@ -244,18 +255,27 @@ void launch_norm_bounds(const float* A, int32_t rows, int32_t d, float* out, hip
 // rows rounded to bf16.
 int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const float* b,
                 const float* anorm, int32_t nh, double w, int32_t* out, int32_t* status,
-                int clamp, float* rownorm, hipStream_t st, int kind, __hip_bfloat16* xb) {
-  if (n <= 0) return LIDER_OK;
+                int clamp, float* rownorm, hipStream_t st, int kind, __hip_bfloat16* xb,
+                const HashZero* zero) {
+  HashZero z{};
+  if (zero) {
+    z = *zero;
+    z.nz = std::max(z.a ? z.na : 0, (z.b || z.c) ? z.nb : 0);
+  }
+  if (n <= 0) {
+    if (z.nz > 0) return set_error(LIDER_EINVAL, "hash: counters to clear without rows");
+    return LIDER_OK;
+  }
   const bool vec = (d % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(A) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(xb) & 7) == 0);
   const dim3 grid(unsigned((n + 15) / 16), unsigned((nh + 31) / 32));
   if (vec)
     hipLaunchKernelGGL(hash_kernel<true>, grid, dim3(256), 0, st, X, n, d, A, b, anorm, nh, w,
-                       out, status, clamp, rownorm, kind, xb);
+                       out, status, clamp, rownorm, kind, xb, z);
   else
     hipLaunchKernelGGL(hash_kernel<false>, grid, dim3(256), 0, st, X, n, d, A, b, anorm, nh, w,
-                       out, status, clamp, rownorm, kind, xb);
+                       out, status, clamp, rownorm, kind, xb, z);
   return check_hip(hipGetLastError(), "hash kernel");
 }
 

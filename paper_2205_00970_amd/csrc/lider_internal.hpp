@@ -217,10 +217,20 @@ int check_hip(hipError_t e, const char* what);
 
 // ------------------------------------------------------------- build kernels
 // hash.hip
+// Counters a hash launch clears on the side: a [0, na), b and c [0, nb)
+// (nullable each); nz is set by run_hash_ex.
+struct HashZero {
+  int32_t* a;
+  int32_t na;
+  int32_t* b;
+  int32_t* c;
+  int32_t nb;
+  int32_t nz;
+};
 int run_hash_ex(const float* X, int64_t n, int32_t d, const float* A, const float* b,
                 const float* anorm, int32_t nh, double w, int32_t* out, int32_t* status,
                 int clamp, float* rownorm, hipStream_t st, int kind = 0,
-                __hip_bfloat16* xb = nullptr);
+                __hip_bfloat16* xb = nullptr, const HashZero* zero = nullptr);
 void launch_norm_bounds(const float* A, int32_t rows, int32_t d, float* out, hipStream_t st);
 
 // kmeans.hip

@@ -122,17 +122,6 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   return p;
 }
 
-// Zeroes a [0, na) and both b and c [0, nbc): the search's counters in one launch.
-__global__ void zero3_kernel(int32_t* __restrict__ a, int32_t na, int32_t* __restrict__ b,
-                             int32_t* __restrict__ c, int32_t nbc) {
-  const int32_t t = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < na) a[t] = 0;
-  if (t < nbc) {
-    b[t] = 0;
-    c[t] = 0;
-  }
-}
-
 __global__ void zero_kernel(int32_t* p, int64_t cnt) {
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < cnt;
        t += int64_t(gridDim.x) * blockDim.x)
@@ -2549,10 +2538,10 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   // written by the hash kernel.
   const bool l1b = !fp8 && o.l1_dense == 0 && ix.cent_l1_b;
   mark(0);
-  hipLaunchKernelGGL(zero3_kernel, dim3(unsigned(std::max(1, (C + 255) / 256))), dim3(256), 0, st,
-                     ctr, int32_t(kCtrWords), ccount, cfill, C);
+  // the hash launch also clears the counters (it writes no status: digits are clamped)
+  const HashZero zr{ctr, int32_t(kCtrWords), ccount, cfill, C, 0};
   int rc = run_hash_ex(Q, nq, ix.d, ix.A, ix.b, ix.anorm, 2 * H * m, ix.w, qdig, ctr + 1, 1, qnorm,
-                       st, ix.hash_kind, (fp8 || bf16 || l1b) ? qb : nullptr);
+                       st, ix.hash_kind, (fp8 || bf16 || l1b) ? qb : nullptr, &zr);
   if (rc != LIDER_OK) return rc;
   mark(1);
   const int64_t nl1 = nq * H;  // (query, array) layer-1 items

@@ -210,6 +210,27 @@ def test_hash_near_bucket_edges():
     assert np.array_equal(got, ref)
 
 
+def test_hash_exact_bucket_edges():
+    """Integer data and projections: every a.x + b is an exact multiple of w
+    (and zero rows give exactly b), so every projection sits on a bucket edge
+    and is decided by the sequential FP64 sum of the definition; the digits
+    still equal it."""
+    torch = _torch()
+    from paper_2205_00970_amd import lider
+    g = np.random.default_rng(21)
+    d, nh, w = 768, 32, 1.0
+    A = g.integers(-3, 4, (nh, d)).astype(np.float32)
+    b = g.integers(-2, 3, nh).astype(np.float32)
+    X = g.integers(-3, 4, (1000, d)).astype(np.float32)
+    X[:7] = 0.0
+    got = lider.hash(torch.from_numpy(X).cuda(), torch.from_numpy(A).cuda(),
+                     torch.from_numpy(b).cuda(), w).cpu().numpy()
+    ref = oracle.digits(X, A, b, w)
+    assert np.array_equal(got, ref)
+    exact = (X.astype(np.float64) @ A.T.astype(np.float64) + b) / w
+    assert np.array_equal(ref, np.floor(exact).astype(np.int64))
+
+
 def test_kmeans_assign_step():
     """One assignment step on 768-d data with 1,000 centroids (FP64 decision)."""
     torch = _torch()
