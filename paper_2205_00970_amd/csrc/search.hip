@@ -1526,7 +1526,8 @@ __global__ __launch_bounds__(256) void rerank_kernel(
         else
           pass_loop<F, RC, 1, NT, Src>(xr, q0, q1, 0, nsteps, sub, d, acc, xa, pre);
         pre = false;
-        // D layout: acc[rc][pc][e] = pair g0 + 16 pc + 4 s + e, row 16 rc + i
+        // D layout: acc[rc][pc][e] = pair g0 + 16 pc + 4 s + e, row 16 rc + i.
+        // The score stores are nontemporal: the selection reads them once.
 #pragma unroll
         for (int pc = 0; pc < NPCM; ++pc) {
 #pragma unroll
@@ -1544,7 +1545,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(
                   if (row_scale) v *= row_scale[grow + rr];
                   if (pmask && !((sh.lm[g0 + pp][rr >> 5] >> (rr & 31)) & 1u))
                     v = __builtin_nanf("");
-                  dst[row] = v;
+                  __builtin_nontemporal_store(v, &dst[row]);
                 }
               }
             }
