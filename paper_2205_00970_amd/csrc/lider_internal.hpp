@@ -32,6 +32,8 @@ struct alignas(16) Model {
   int32_t maxs[LIDER_MAX_M];
 };
 
+static_assert(sizeof(Model) % 16 == 0, "models are copied in 16-byte pieces");
+
 static constexpr uint64_t kKeyLimit = uint64_t(1) << 53;
 
 // Dims per k-step chunk of the operand-ordered corpus copy (Xt).
@@ -116,10 +118,42 @@ __host__ __device__ inline void window_of(int64_t pos, int64_t r, int64_t L, int
   *len = lenv;
 }
 
-__device__ inline int64_t locate(const Model& M, const double* leaves, const int32_t* qd,
+// encode_query with the digit loop unrolled over LIDER_MAX_M and the early
+// exits turned into a saturation state (the same integer arithmetic), so that
+// the model's box and the digits are read from registers.
+__device__ inline uint64_t encode_query_unrolled(const int32_t (&h)[LIDER_MAX_M], const Model& M) {
+  uint64_t K = 0;
+  int mode = 0;  // 0: inside the box so far, 1: saturated below, 2: above
+#pragma unroll
+  for (int i = 0; i < LIDER_MAX_M; ++i) {
+    if (i < M.m_eff) {
+      const uint64_t R = uint64_t(int64_t(M.maxs[i]) - int64_t(M.mins[i]) + 1);
+      if (mode == 0) mode = h[i] < M.mins[i] ? 1 : (h[i] > M.maxs[i] ? 2 : 0);
+      const uint64_t dg = mode == 0 ? uint64_t(int64_t(h[i]) - int64_t(M.mins[i]))
+                                    : (mode == 1 ? uint64_t(0) : R - 1);
+      K = K * R + dg;
+    }
+  }
+  return mode == 2 ? K + 1 : K;
+}
+
+// Predicted location of a query in one core model.  The model (192 bytes)
+// and the query's m digits are loaded with all their loads in flight before
+// the arithmetic starts.
+__device__ inline int64_t locate(const Model* Mp, const double* leaves, const int32_t* qd, int m,
                                  uint64_t* Kout = nullptr) {
+  Model M;
+  {
+    const int4* src = reinterpret_cast<const int4*>(Mp);
+    int4* dst = reinterpret_cast<int4*>(&M);
+#pragma unroll
+    for (int w = 0; w < int(sizeof(Model) / 16); ++w) dst[w] = src[w];
+  }
+  int32_t h[LIDER_MAX_M];
+#pragma unroll
+  for (int i = 0; i < LIDER_MAX_M; ++i) h[i] = i < m ? qd[i] : 0;
   if (M.L <= 0) return 0;
-  uint64_t K = encode_query(qd, M);
+  uint64_t K = encode_query_unrolled(h, M);
   if (Kout) *Kout = K;
   double x = rescale(K, M);
   int32_t j = leaf_of(M.root_a, M.root_b, M.F, M.L, x);

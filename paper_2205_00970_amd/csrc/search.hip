@@ -339,8 +339,8 @@ __device__ inline void l1_item(const L1Args& a, int64_t t) {
   const int64_t q = t / a.H;
   const int32_t h = int32_t(t - q * a.H);
   uint64_t K = 0;
-  const int64_t pos = locate(a.models[int64_t(h) * (a.C + 1) + a.C], a.leaves,
-                             a.qdig + q * 2 * a.H * a.m + int64_t(h) * a.m, &K);
+  const int64_t pos = locate(a.models + int64_t(h) * (a.C + 1) + a.C, a.leaves,
+                             a.qdig + q * 2 * a.H * a.m + int64_t(h) * a.m, a.m, &K);
   int64_t s, len;
   window_of(pos, a.r1, a.C, &s, &len);  // the expansion (if any) replaces s later
   if (a.kq) a.kq[t] = K;
@@ -858,12 +858,13 @@ __global__ void pairs_kernel(const Model* __restrict__ models, const double* __r
   for (int32_t h = 0; h < H; ++h) {
     Pair ph{-1, 0, 0, 0};
     if (j >= 0) {
-      const Model& M = models[int64_t(h) * (C + 1) + j];
+      const Model* Mp = models + int64_t(h) * (C + 1) + j;
+      const int64_t L = Mp->L;
       uint64_t K = 0;
       const int64_t pos =
-          locate(M, leaves, qdig + q * 2 * H * m + int64_t(H) * m + int64_t(h) * m, &K);
+          locate(Mp, leaves, qdig + q * 2 * H * m + int64_t(H) * m + int64_t(h) * m, m, &K);
       int64_t s, len;
-      window_of(pos, r, M.L, &s, &len);  // the expansion (if any) replaces s later
+      window_of(pos, r, L, &s, &len);  // the expansion (if any) replaces s later
       if (kq) kq[t * H + h] = K;
       ph = Pair{j, int32_t(s), int32_t(len), int32_t(pos)};
     }
