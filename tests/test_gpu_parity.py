@@ -48,6 +48,28 @@ def test_tiny_search(tiny, k, c, r, r1):
     compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
 
 
+def test_tiny_queries_outside_the_digit_box(tiny):
+    """Queries scaled far out (and mirrored): their digits leave the models'
+    digit boxes below and above, so the keys saturate (Sec. 5.1); keys,
+    positions, windows, routing and results still equal the oracle's."""
+    torch = _torch()
+    X, Q, gi, oi = tiny["X"], tiny["Q"], tiny["gi"], tiny["oi"]
+    Qo = np.concatenate([Q[:30] * 25.0, -Q[30:60] * 25.0, Q[60:] + 40.0]).astype(np.float32)
+    ids, sc, dbg = gi.search(torch.from_numpy(Qo).cuda(), 10, 3, 64, r1=8, debug=True)
+    torch.cuda.synchronize()
+    oids, osc, odbg = oi.search(Qo, 10, 3, 64, 8, debug=True)
+    # the case is exercised: layer-1 digit vectors below and above the box
+    m, C = 4, 16
+    box = gi.export("model_box").reshape(1, C + 1, 2 * m)[0, C]
+    qd = odbg["qdigits"][:, :m]
+    first_out = [next((i for i in range(m) if not box[i] <= v[i] <= box[m + i]), None) for v in qd]
+    below = sum(1 for v, i in zip(qd, first_out) if i is not None and v[i] < box[i])
+    above = sum(1 for v, i in zip(qd, first_out) if i is not None and v[i] > box[m + i])
+    assert below > 0 and above > 0, (below, above)
+    compare_debug(dbg, odbg)
+    compare_topk(X, Qo, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+
+
 def test_tiny_flat_special_case(tiny):
     """All clusters, whole clusters, whole layer 1: exact (Flat) search."""
     torch = _torch()
