@@ -1904,7 +1904,8 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
     const bool pre = R > 0 && c == 1;
     if (pre) {
 #pragma unroll
-      for (int j = 0; j < R; ++j) fv[j] = sbq[uint32_t(min(lane + 64 * j, rcap - 1))];
+      for (int j = 0; j < R; ++j)
+        if (64 * j < rcap) fv[j] = sbq[uint32_t(min(lane + 64 * j, rcap - 1))];
     }
     // slot table: lane t reads pair t (64 at a time); start[] is the
     // exclusive prefix sum of the slot lengths, pbase[] each slot's first row
@@ -1983,6 +1984,7 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
         int t = 0;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
+          if (64 * j >= n) continue;  // wave-uniform: register slots past the candidates
           const int32_t i = min(lane + 64 * j, n - 1);
           while (t + 1 < c && st[t + 1] <= i) ++t;
           fv[j] = sbq[int64_t(t) * rcap + (i - st[t])];
@@ -2006,7 +2008,7 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
 #pragma unroll
         for (int j = 0; j < R; ++j) {
           const int32_t i = lane + 64 * j;
-          f(i, kr[j], i < n);
+          if (64 * j < n) f(i, kr[j], i < n);  // wave-uniform: skips slots past the candidates
         }
       } else if (cached) {
         for (int32_t i0 = 0; i0 < n; i0 += 64) {
