@@ -305,10 +305,12 @@ int lider_load(const char* path, void* stream, lider_index** out);
 
 /* E2LSH digits (Section 4): out_dev[r*nh + i] = floor((A[i].X[r] + b[i]) / w)
  * for X_dev [n x d], A_dev [nh x d], b_dev [nh] (all fp32, device), nh in 1..512.
- * Projections run on fp32 MFMA; values within the rounding-error band of a
- * bucket edge are recomputed sequentially in FP64, so the digits equal the
- * FP64 definition exactly.  Allocates a temporary device list; synchronises
- * `stream`.  Errors: EINVAL, ENOMEM, EDEVICE, ERANGE. */
+ * Projections run on FP64 MFMA over the exact fp32 x fp32 products; values
+ * within the rounding-error band of a bucket edge are recomputed by the
+ * sequential FP64 sum, so the digits equal the FP64 definition exactly.
+ * Allocates small temporary device buffers (row-norm bounds of A, a status
+ * word); synchronises `stream`.  Errors: EINVAL, ENOMEM, EDEVICE, ERANGE (a
+ * digit outside int32). */
 int lider_hash(const float* X_dev, int64_t n, int32_t d, const float* A_dev, const float* b_dev,
                int32_t nh, double w, int32_t* out_dev, void* stream);
 
