@@ -2323,6 +2323,12 @@ void launch_wave_select(hipStream_t st, const Pair* pairs, const float* sbuf, in
   else if (nmax <= 2048)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 32>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
                        rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
+  else if (nmax <= 4096)
+    hipLaunchKernelGGL((wave_select_kernel<MODE, 64>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
+  else if (nmax <= 6144)
+    hipLaunchKernelGGL((wave_select_kernel<MODE, 96>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
   else
     hipLaunchKernelGGL((wave_select_kernel<MODE, 0>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
                        rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);

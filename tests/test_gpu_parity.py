@@ -36,7 +36,10 @@ def test_tiny_build_bit_exact(tiny):
 
 
 @pytest.mark.parametrize("k,c,r,r1", [(10, 4, 64, 0), (1, 1, 1, 0), (100, 4, 64, 8),
-                                       (10, 16, 5000, 16), (7, 3, 33, 5)])
+                                       (10, 16, 5000, 16), (7, 3, 33, 5),
+                                       # up to 4096 / 6144 candidates per query: the
+                                       # 64- and 96-register selections
+                                       (10, 4, 1000, 0), (10, 5, 1100, 16)])
 def test_tiny_search(tiny, k, c, r, r1):
     torch = _torch()
     X, Q, gi, oi = tiny["X"], tiny["Q"], tiny["gi"], tiny["oi"]
