@@ -2220,10 +2220,11 @@ __global__ __launch_bounds__(kSelNT) void rerank_shortlist_kernel(
 }
 
 // Precision form, second pass for short lists (S <= 64): one wave per query.
-// The wave scores 4 shortlisted rows at a time, 16 lanes per row, each lane
-// owning the float4 slots [4 c + 64 j, 4 c + 64 j + 4) of the dimension range
-// (every load instruction reads 256 contiguous bytes of each of 4 rows);
-// lane partials are reduced over the 16 lanes by a fixed xor tree.  Then each
+// The wave scores 8 shortlisted rows per round (all their loads in flight
+// together), 16 lanes per row, each lane owning the float4 slots
+// [4 c + 64 j, 4 c + 64 j + 4) of the dimension range (every load instruction
+// reads 256 contiguous bytes of each of 4 rows); lane partials are reduced
+// over the 16 lanes by a fixed xor tree.  Then each
 // lane ranks one candidate by (score desc, id asc).  Needs d % 4 == 0 and
 // 16-byte aligned rows.
 __global__ __launch_bounds__(256) void wave_shortlist_kernel(
@@ -2232,32 +2233,45 @@ __global__ __launch_bounds__(256) void wave_shortlist_kernel(
     int64_t* __restrict__ ids, float* __restrict__ scores) {
   __shared__ float sc[4][64];
   __shared__ uint32_t sid[4][64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));  // uniform
   const int g = lane >> 4, c16 = lane & 15;
-  for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
+  // one query per wave, no loop
+  const int64_t q = int64_t(blockIdx.x) * 4 + wave;
+  if (q >= nq) return;
+  {
     const int32_t myrow = lane < S ? slist[q * S + lane] : -1;
     const uint64_t valid = __ballot(myrow >= 0);
     const int n = valid == ~uint64_t(0) ? 64 : __ffsll((long long)~valid) - 1;  // valid prefix
     const float* qv = Q + q * d;
-    for (int t0 = 0; t0 < n; t0 += 4) {
-      const int t = min(t0 + g, n - 1);
-      const int32_t rw = __shfl(myrow, t);
-      const float* xr = X + int64_t(rw) * d;
-      float acc = 0.f;
+    // 8 rows per round (two groups of 4): every load of the round is issued
+    // before its products are summed
+    for (int t0 = 0; t0 < n; t0 += 8) {
+      const int ta = min(t0 + g, n - 1), tb = min(t0 + 4 + g, n - 1);
+      const float* xa = X + int64_t(__shfl(myrow, ta)) * d;
+      const float* xb = X + int64_t(__shfl(myrow, tb)) * d;
+      float acca = 0.f, accb = 0.f;
 #pragma unroll 4
       for (int l = 4 * c16; l < d; l += 64) {
-        const float4 xv = *reinterpret_cast<const float4*>(xr + l);
+        const float4 va = *reinterpret_cast<const float4*>(xa + l);
+        const float4 vb = *reinterpret_cast<const float4*>(xb + l);
         const float4 qq = *reinterpret_cast<const float4*>(qv + l);
-        acc += xv.x * qq.x;
-        acc += xv.y * qq.y;
-        acc += xv.z * qq.z;
-        acc += xv.w * qq.w;
+        acca += va.x * qq.x;
+        acca += va.y * qq.y;
+        acca += va.z * qq.z;
+        acca += va.w * qq.w;
+        accb += vb.x * qq.x;
+        accb += vb.y * qq.y;
+        accb += vb.z * qq.z;
+        accb += vb.w * qq.w;
       }
-      acc += __shfl_xor(acc, 8);
-      acc += __shfl_xor(acc, 4);
-      acc += __shfl_xor(acc, 2);
-      acc += __shfl_xor(acc, 1);
-      if (c16 == 0 && t0 + g < n) sc[wave][t0 + g] = acc;
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) {
+        acca += __shfl_xor(acca, o);
+        accb += __shfl_xor(accb, o);
+      }
+      if (c16 == 0 && t0 + g < n) sc[wave][t0 + g] = acca;
+      if (c16 == 0 && t0 + 4 + g < n) sc[wave][t0 + 4 + g] = accb;
     }
     if (lane < n) sid[wave][lane] = uint32_t(perm32[myrow]);
     __threadfence_block();
@@ -2679,8 +2693,8 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
       hipLaunchKernelGGL((select_kernel<4096, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
                          p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1));
     if (p.S <= 64 && ix.d % 4 == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0)
-      hipLaunchKernelGGL(wave_shortlist_kernel, dim3(wgrid), dim3(256), 0, st, ix.X, ix.d, Q, nq,
-                         slist, p.S, ix.perm32, k, ids, scores);
+      hipLaunchKernelGGL(wave_shortlist_kernel, dim3(unsigned((nq + 3) / 4)), dim3(256), 0, st,
+                         ix.X, ix.d, Q, nq, slist, p.S, ix.perm32, k, ids, scores);
     else if (k <= 128)
       hipLaunchKernelGGL(rerank_shortlist_kernel<128>, dim3(qgrid), dim3(kSelNT), 0, st, ix.X,
                          ix.d, Q, nq, slist, p.S, ix.perm32, k, ids, scores);
