@@ -1676,14 +1676,14 @@ constexpr int kLdsK = 64, kLdsRow = 72;
 // The first l1_blocks workgroups (a multiple of 8) instead run the layer-1
 // locate (l1_item) of 256 items each: both only need the hash kernel's
 // output, so one launch runs them side by side.
-__global__ __launch_bounds__(256) void l1_gemm_lds_kernel(const __hip_bfloat16* __restrict__ Q,
+__global__ __launch_bounds__(256, 3) void l1_gemm_lds_kernel(const __hip_bfloat16* __restrict__ Q,
                                                           int64_t nq,
                                                           const __hip_bfloat16* __restrict__ Cc,
                                                           int32_t C, int32_t d,
                                                           float* __restrict__ rs, L1Args la,
                                                           unsigned l1_blocks) {
-  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sa[2][128 * kLdsRow];
-  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sb[2][128 * kLdsRow];
+  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sa[1][128 * kLdsRow];
+  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sb[1][128 * kLdsRow];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (blockIdx.x < l1_blocks) {
     l1_item(la, int64_t(blockIdx.x) * 256 + tid);
@@ -1733,7 +1733,7 @@ __global__ __launch_bounds__(256) void l1_gemm_lds_kernel(const __hip_bfloat16* 
   lstore(0);
   __syncthreads();
   for (int kc = 0; kc < nk; ++kc) {
-    const int buf = kc & 1;
+    const int buf = 0;
     if (kc + 1 < nk) gload(kc + 1);  // in flight while this chunk is consumed
 #pragma unroll
     for (int kk = 0; kk < kLdsK; kk += 32) {
@@ -1750,8 +1750,11 @@ __global__ __launch_bounds__(256) void l1_gemm_lds_kernel(const __hip_bfloat16* 
         for (int b = 0; b < 4; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
     }
-    if (kc + 1 < nk) lstore(buf ^ 1);
-    __syncthreads();
+    __syncthreads();  // every wave is done with this chunk before it is overwritten
+    if (kc + 1 < nk) {
+      lstore(0);
+      __syncthreads();
+    }
   }
   // D layout: acc[a][b][e] = query wr + 16 a + 4 s + e, centroid wc + 16 b + i
 #pragma unroll
