@@ -10,8 +10,8 @@
 // sequential FP64 sum of the definition only by the rounding of its d + 3
 // additions: within 8 (d + 4) 2^-53 |a| |x|.  A projection whose value lies
 // within that band of a bucket edge (about 1e-10 relative at d = 768, so almost
-// never) is queued and recomputed by the sequential FP64 dot product in
-// dimension order.
+// never) is listed and decided by hash_decide_wave in the same kernel, down to
+// the sequential FP64 dot product in dimension order where needed.
 #include "lider_internal.hpp"
 
 namespace lider {
