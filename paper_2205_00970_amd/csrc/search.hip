@@ -2337,6 +2337,9 @@ void launch_wave_select(hipStream_t st, const Pair* pairs, const float* sbuf, in
   else if (nmax <= 1024)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 16>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
                        rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
+  else if (nmax <= 1280)
+    hipLaunchKernelGGL((wave_select_kernel<MODE, 20>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
   else if (nmax <= 2048)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 32>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
                        rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
