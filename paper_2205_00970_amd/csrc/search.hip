@@ -1035,6 +1035,52 @@ __global__ void scatter_kernel(const Pair* __restrict__ pairs, int64_t np,
   wl[start[pr.j] + atomicAdd(&fill[pr.j], 1)] = int32_t(t);
 }
 
+// scan_kernel + scatter_kernel in one launch for C <= kFusedScanMax: every
+// workgroup scans the cluster counts itself in LDS (they are few), workgroup 0
+// also writes start[0..C], then each scatters its 256 pairs.
+constexpr int kFusedScanMax = 8192;
+
+__global__ __launch_bounds__(256) void scan_scatter_kernel(const int32_t* __restrict__ cnt,
+                                                           int32_t C, const Pair* __restrict__ pairs,
+                                                           int64_t np, int32_t* __restrict__ start,
+                                                           int32_t* __restrict__ fill,
+                                                           int32_t* __restrict__ wl) {
+  __shared__ int32_t st[kFusedScanMax + 1];
+  __shared__ int32_t part[256];
+  const int tid = threadIdx.x;
+  const int per = (C + 255) / 256;
+  const int a = tid * per, e = min(C, a + per);
+  int32_t sum = 0;
+  for (int i = a; i < e; ++i) {
+    const int32_t v = cnt[i];
+    st[i] = v;
+    sum += v;
+  }
+  part[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int32_t v = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int32_t run = tid ? part[tid - 1] : 0;
+  for (int i = a; i < e; ++i) {
+    const int32_t v = st[i];
+    st[i] = run;
+    run += v;
+  }
+  if (tid == 255) st[C] = part[255];
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int i = tid; i <= C; i += 256) start[i] = st[i];
+  const int64_t t = int64_t(blockIdx.x) * 256 + tid;
+  if (t >= np) return;
+  const Pair pr = pairs[t];
+  if (pr.j < 0 || pr.len <= 0) return;
+  wl[st[pr.j] + atomicAdd(&fill[pr.j], 1)] = int32_t(t);
+}
+
 // Active-tile work list: every pair marks the tiles its window overlaps; the
 // first marker of a tile appends it to the list (order unspecified; each
 // tile's result does not depend on the order).
@@ -2651,9 +2697,14 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
     hipLaunchKernelGGL(pair_mask_kernel, dim3(unsigned(std::min<int64_t>((np + 3) / 4, 65535))),
                        dim3(256), 4 * size_t(p.mw) * 4, st, pw, H, np, ix.off, ix.amap, ix.n,
                        p.mw, pairs, pmask);
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, ccount, C, cstart);
-  hipLaunchKernelGGL(scatter_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, pairs, np,
-                     cstart, cfill, wl);
+  if (C <= kFusedScanMax) {
+    hipLaunchKernelGGL(scan_scatter_kernel, dim3(unsigned(std::max<int64_t>(1, (np + 255) / 256))),
+                       dim3(256), 0, st, ccount, C, pairs, np, cstart, cfill, wl);
+  } else {
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, ccount, C, cstart);
+    hipLaunchKernelGGL(scatter_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, pairs,
+                       np, cstart, cfill, wl);
+  }
   mark(3);
   const int ti = tile_index(ix, o);
   const int tr = 32 << ti;
