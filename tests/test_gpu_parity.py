@@ -214,6 +214,23 @@ def test_odd_dimensions(d):
         compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
 
 
+def test_many_clusters_unfused_work_list():
+    """More than 8,192 clusters: the cluster-count scan and the pair scatter run
+    as two launches (the fused launch keeps the counts in LDS); build and
+    search still equal the oracle."""
+    torch = _torch()
+    X, lab, Q, src = datagen.tiny(n=30000, d=32, ncomp=16, nq=64, seed=40, qseed=41)
+    C = 9000
+    asg = (np.arange(X.shape[0]) % C).astype(np.int32)
+    A, b = datagen.lsh_params(4, 32, 1.0, seed=42)
+    gi, oi, _ = build_pair(X, C, 4, 1.0, 8, A, b, assignment=asg)
+    compare_index(gi, oi)
+    ids, sc, dbg = gi.search(torch.from_numpy(Q).cuda(), 10, 6, 4, r1=64, debug=True)
+    oids, osc, odbg = oi.search(Q, 10, 6, 4, 64, debug=True)
+    compare_debug(dbg, odbg)
+    compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+
+
 def test_hash_near_bucket_edges():
     """Projections placed within 1e-7 of bucket edges take the FP64 path and
     still equal the FP64 definition."""
