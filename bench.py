@@ -271,10 +271,10 @@ def main():
         extra["precision_bf16_shortlist"] = []
         for mult in (2, 1):
             dt, pi, _ = timed(10, c, r, r1, reps=5, precision="bf16", shortlist_mult=mult)
-            rec = round(recall_at(torch, X, Q, pi, gt_sc, 10), 4)
+            rec_s = round(recall_at(torch, X, Q, pi, gt_sc, 10), 4)
             extra["precision_bf16_shortlist"].append(dict(shortlist=f"{mult}k", qps=round(args.nq / dt),
-                                                          recall10=rec))
-            log(f"precision form, shortlist {mult}k: {args.nq / dt:,.0f} q/s, recall@10 {rec}")
+                                                          recall10=rec_s))
+            log(f"precision form, shortlist {mult}k: {args.nq / dt:,.0f} q/s, recall@10 {rec_s}")
         extra["persistent_qps"] = round(args.nq / timed(10, c, r, r1, reps=5, persistent=True)[0])
         extra["cosine"] = cosine_variant(args, torch, datagen, lider, X, lab, Q, C, F, log)
         extra["arrays"] = arrays_variant(args, torch, datagen, lider, X, lab, Q, C, F, log, gt_sc)
