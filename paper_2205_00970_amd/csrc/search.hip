@@ -71,9 +71,13 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   Plan p;
   const int32_t H = ix.H;
   const int32_t r1 = int32_t(std::min<int64_t>(o.r1 > 0 ? o.r1 : r, ix.C));
-  // several arrays: a pair's candidates span up to its whole cluster
-  const int32_t rcap = int32_t(std::max<int64_t>(
-      1, H > 1 ? ix.max_cluster : std::min<int64_t>(r, ix.max_cluster)));
+  // several arrays: a pair's candidates span up to its whole cluster.  The
+  // score row stride is a multiple of 32 floats: rerank tiles start at
+  // multiples of 64 rows of their cluster, so whole-cluster windows store
+  // whole 128-byte lines (an odd stride splits every 16-row store segment
+  // over two lines: 1.6x the score bytes reached HBM).
+  const int32_t rcap = int32_t((std::max<int64_t>(
+      1, H > 1 ? ix.max_cluster : std::min<int64_t>(r, ix.max_cluster)) + 31) / 32 * 32);
   const int32_t mult = o.shortlist_mult > 0 ? o.shortlist_mult : 4;
   const int32_t S = o.precision == LIDER_BF16 ? std::min(4096, mult * k) : 0;
   p.l1_list = H > 1 && r1 < ix.C;
