@@ -99,8 +99,8 @@ def union_rows(pairs):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--nq", type=int, default=10_000)
     ap.add_argument("--clusters", type=int, default=1000)
@@ -108,6 +108,10 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="profiling run: no sweep, no side measurements, no CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--streams", type=int, default=1,
+                    help="consecutive batches alternate over this many streams, each with its own "
+                         "workspace and outputs (1: every step on one stream, the kernels' isolated "
+                         "durations; the other setting of 1 / 2 is timed after it and reported too)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="search", choices=["search", "batching", "serving"],
                     help="search: the 1M x 768 headline; batching: 4M x 768 Zipf clusters, "
@@ -188,18 +192,45 @@ def main():
         point = best[1] if best else (8, Lmax, C)
     c, r, r1 = point
 
-    # ---- timed region: W warmup steps, then exactly K steps
+    # ---- timed region: W warmup steps, then exactly K steps.  Step i runs on
+    # stream i mod S with that stream's workspace and output buffers; with
+    # S = 2 one batch's short latency-bound stages (hashing, routing, work
+    # list, selection) overlap the previous batch's HBM-bound rerank.  Every
+    # step is one whole pass of the path over one 10,000-query batch.
     k = 10
-    ids = torch.empty((args.nq, k), dtype=torch.int64, device=dev)
-    sc = torch.empty((args.nq, k), dtype=torch.float32, device=dev)
-    for _ in range(args.warmup):
-        run(k, c, r, r1, out=(ids, sc))
+    nst = max(1, args.streams)
+    need = gi.workspace_bytes(args.nq, k, c, r, r1=r1)
+    streams = [torch.cuda.Stream() for _ in range(max(nst, 2))]
+    wss = [torch.empty(max(need, 256), dtype=torch.uint8, device=dev) for _ in streams]
+    outs = [(torch.empty((args.nq, k), dtype=torch.int64, device=dev),
+             torch.empty((args.nq, k), dtype=torch.float32, device=dev)) for _ in streams]
+    torch.cuda.synchronize()
+
+    def steps_on(ns, count):
+        for i in range(count):
+            run(k, c, r, r1, out=outs[i % ns], stream=streams[i % ns], ws=wss[i % ns])
+
+    steps_on(nst, args.warmup)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for _ in range(args.steps):
-        run(k, c, r, r1, out=(ids, sc))
+    steps_on(nst, args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
+    # the other stream setting (2 when the timed steps used 1), for reference;
+    # not under --quick, whose kernel traces then hold isolated launches only
+    alt_nst = 2 if nst == 1 else 1
+    alt_qps = None
+    if not args.quick:
+        steps_on(alt_nst, args.warmup)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        steps_on(alt_nst, args.steps)
+        torch.cuda.synchronize()
+        alt_qps = args.nq / ((time.perf_counter() - t) / args.steps)
+    ids, sc = outs[0]
+    used = max(nst, alt_nst) if alt_qps else nst  # output buffers written
+    if not all(torch.equal(ids, o[0]) and torch.equal(sc, o[1]) for o in outs[1:used]):
+        raise RuntimeError("batches on different streams gave different results")
     # stage times: the same steps again with HIP events between the stages
     # (recording them costs a few microseconds each, so they stay out of the
     # timed region above)
@@ -212,7 +243,8 @@ def main():
     value = args.nq / (elapsed / args.steps)
     rec = recall_at(torch, X, Q, ids, gt_sc, 10)
     stage_avg = {s: v / calls for s, v in stages.items()}
-    log(f"point c={c} r={r} r1={r1}: {value:,.0f} q/s, {ms_per_step:.3f} ms/step, recall@10 {rec:.4f}")
+    log(f"point c={c} r={r} r1={r1}: {value:,.0f} q/s, {ms_per_step:.3f} ms/step, recall@10 {rec:.4f} "
+        f"({nst} stream(s)" + (f"; {alt_nst} stream(s): {alt_qps:,.0f} q/s)" if alt_qps else ")"))
     log("stage ms/step: " + ", ".join(f"{s}={v:.3f}" for s, v in stage_avg.items()))
 
     # ---- roofline of the rerank kernel (algorithmic bytes / measured duration)
@@ -299,7 +331,8 @@ def main():
         "config": {"workload": f"gaussian-mixture N={n} d={d} fp32, {C} k-means clusters, "
                                f"m={m} w={w} rmi_fanout={F}, {args.nq} queries (noise 0.1)",
                    "global_batch": args.nq, "k": k, "c": c, "r": r, "r1": r1,
-                   "recall10": round(rec, 4), "parallelism": "single-gpu"},
+                   "recall10": round(rec, 4), "parallelism": "single-gpu", "streams": nst},
+        f"qps_{alt_nst}_stream{'s' if alt_nst > 1 else ''}": round(alt_qps) if alt_qps else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stage_ms": {s: round(v, 4) for s, v in stage_avg.items()},
