@@ -129,6 +129,28 @@ def test_mid_schedules_identical(mid):
     assert torch.equal(sub[0], ref[0][37:90]) and torch.equal(sub[1], ref[1][37:90])
 
 
+def test_mid_two_streams_identical(mid):
+    """Consecutive searches alternating over two streams, each with its own
+    workspace and outputs and no synchronisation between them (the batches
+    overlap on the device): every result equals the one-stream search."""
+    torch = _torch()
+    Qd = torch.from_numpy(mid["Q"]).cuda()
+    gi = mid["gi"]
+    ref = gi.search(Qd, 10, 2, 4000, r1=64)
+    need = gi.workspace_bytes(Qd.shape[0], 10, 2, 4000, r1=64)
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    wss = [torch.empty(need, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    outs = [[(torch.empty_like(ref[0]), torch.empty_like(ref[1])) for _ in range(3)] for _ in range(2)]
+    torch.cuda.synchronize()
+    for it in range(3):
+        for j in range(2):
+            gi.search(Qd, 10, 2, 4000, r1=64, stream=streams[j], ws=wss[j], out=outs[j][it])
+    torch.cuda.synchronize()
+    for j in range(2):
+        for it in range(3):
+            assert torch.equal(outs[j][it][0], ref[0]) and torch.equal(outs[j][it][1], ref[1]), (j, it)
+
+
 @pytest.mark.parametrize("precision", ["f32", "bf16"])
 def test_mid_dense_layer1_identical(mid, precision):
     """r1 = C: the bf16-candidate routing, the fp32 dense GEMM and the window
