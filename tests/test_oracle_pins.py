@@ -108,6 +108,49 @@ def test_hand_rmi():
         assert pos == qc["pos"]
 
 
+@pytest.mark.parametrize("F", [2, 4])
+def test_hand_rmi_leaf_routing(F):
+    """Two-stage RMI with F >= 2 worked out by hand (golden "rmi_leaves"):
+    the root line, which leaf owns each key, each leaf's least-squares line
+    (an empty leaf copies the root), the error bounds, and the leaf and
+    location of query keys on both sides of every leaf boundary, beyond
+    both ends of the location range, and NaN."""
+    gc = GOLD["rmi_leaves"]
+    fc = gc[f"F{F}"]
+    L = gc["L"]
+    x = np.array(gc["x"])
+    root, leaf, elo, ehi = oracle.rmi_train(x, F)
+    rs = Fraction(gc["root_slope_num"], gc["root_slope_den"])
+    ri = Fraction(gc["root_icpt_num"], gc["root_icpt_den"])
+    assert root[0] == float(rs)  # 42 / 49.875, both exact: one correctly rounded division
+    assert abs(root[1] - float(ri)) <= 2e-16 * 4
+    for j, want in enumerate(fc["leaves"]):
+        if want == "root":
+            assert (leaf[2 * j], leaf[2 * j + 1]) == (root[0], root[1])
+        else:  # collinear members with dyadic coordinates: the fit is exact
+            assert (leaf[2 * j], leaf[2 * j + 1]) == tuple(want)
+    assert list(elo) == fc["elo"] and list(ehi) == fc["ehi"]
+    for i in range(L):
+        assert oracle.rmi_leaf(root, F, L, x[i]) == fc["leaf_of_key"][i]
+        assert oracle.rmi_predict(root, leaf, F, L, x[i]) == i
+    for qc in fc["queries"]:
+        xq = float(qc["x"])
+        if "p0" in qc:
+            assert abs(root[0] * xq + root[1] - float(Fraction(qc["p0"]))) < 1e-12
+        assert oracle.rmi_leaf(root, F, L, xq) == qc["leaf"], qc
+        assert oracle.rmi_predict(root, leaf, F, L, xq) == qc["pos"], qc
+    # the same model built from one-digit keys, and queried through the key path
+    order, keys, model = oracle.core(np.array(gc["keys"], np.int32)[:, None], F)
+    assert list(order) == list(range(L)) and [int(k) for k in keys] == gc["keys"]
+    assert model.scale == 0.5
+    assert np.array_equal(model.root, root) and np.array_equal(model.leaf, leaf)
+    for qc in fc["key_queries"]:
+        K, xq, pos = oracle.core_query(model, np.array([qc["digit"]], np.int32))
+        assert K == qc["K"] and xq == K / 2
+        assert oracle.rmi_leaf(model.root, F, L, xq) == qc["leaf"]
+        assert pos == qc["pos"], qc
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_ols_matches_numpy_least_squares(seed):
     g = np.random.default_rng(seed)
