@@ -76,14 +76,17 @@ typedef struct lider_index lider_index; /* opaque; owns its device memory */
  *                 of the centroids retriever, rows H*m + h*m.. array h of
  *                 every in-cluster retriever (one set per array, shared by the
  *                 clusters).  For H = 1: rows 0..m-1 layer 1, m..2m-1 layer 2.
- *                 Copied; may be freed after the call.
- *  lsh_b_host     [2Hm] fp32 offsets in [0, w), same row order.
+ *                 Copied; may be freed after the call.  NULL: drawn from
+ *                 `seed` (see lider_draw_params), together with lsh_b_host.
+ *  lsh_b_host     [2Hm] fp32 offsets in [0, w), same row order (required
+ *                 with lsh_a_host for E2LSH).
  *  assignment_dev optional [n] int32 cluster of each row (0..n_clusters-1);
  *                 NULL runs k-means.  Empty clusters are allowed (their
  *                 centroid is the zero vector).
  *  kmeans_init_host [n_clusters] int64 row ids of the initial centroids
- *                 (required when assignment_dev is NULL, distinct not required);
- *                 with kmeans_seeding = 1 only element 0 is read.
+ *                 (distinct not required); with kmeans_seeding = 1 only
+ *                 element 0 is read.  NULL (and assignment_dev NULL): drawn
+ *                 from `seed` (see lider_draw_params).
  *  kmeans_iters   maximum Lloyd iterations (>= 1); stops early when an
  *                 assignment repeats the previous one.
  *  storage        LIDER_F32, or LIDER_BF16 to add a bf16 copy of the corpus
@@ -102,7 +105,10 @@ typedef struct lider_index lider_index; /* opaque; owns its device memory */
  *                 lsh_b_host are ignored, lsh_b_host may be NULL), key =
  *                 Decimal(bits) (Section 5.1), i.e. the box is [0, 1] for
  *                 every bit.  Use on normalised embeddings (inner product =
- *                 cosine similarity). */
+ *                 cosine similarity).
+ *  seed           seed of the draws the caller leaves to the library (the
+ *                 hash parameters when lsh_a_host is NULL, the k-means seed
+ *                 rows when kmeans_init_host is NULL); ignored otherwise. */
 typedef struct {
   int32_t n_clusters;
   int32_t m;
@@ -119,6 +125,7 @@ typedef struct {
   int32_t kmeans_seeding;
   int32_t hash_kind;
   int32_t n_arrays;
+  uint64_t seed;
 } lider_build_params;
 
 /* Build an index over corpus_dev [n x d] fp32 (Sections 3.2, 3.3.1, 3.3.2):
@@ -131,6 +138,32 @@ typedef struct {
  * n in 1..2^31-1, d in 1..65536.  Errors: EINVAL, ENOMEM, EDEVICE, ERANGE. */
 int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build_params* params,
                 void* stream, lider_index** out);
+
+/* The library's seeded draws (host only; no device work, no allocation on the
+ * device).  The random inputs of a build -- the E2LSH projections
+ * a_i ~ N(0, I_d) and offsets b_i ~ U[0, w) of Section 4, and the rows that
+ * seed k-means (Section 3.2) -- as lider_build draws them from `seed` when the
+ * caller gives none:
+ *  - words: SplitMix64 (Steele, Lea, Flood, OOPSLA 2014); stream s (0: hash
+ *    parameters, 1: k-means rows) starts from the state seed xor the (s+1)-th
+ *    output of the generator started at state 0; a uniform is
+ *    (word >> 11) * 2^-53.
+ *  - lsh_a_host [2Hm x d] (H = n_arrays, 0 means 1), filled row by row with
+ *    Box-Muller normals: each pair of uniforms (u1, u2) gives
+ *    sqrt(-2 ln(1 - u1)) * cos(2 pi u2), then the same times sin(2 pi u2),
+ *    computed in FP64 and rounded to fp32 (an odd count drops the last sine);
+ *    then lsh_b_host [2Hm] = fp32(u * w), one uniform per row in order
+ *    (LIDER_HASH_SIGN: all zero, no draws).  Both NULL: not drawn; one NULL:
+ *    EINVAL.
+ *  - rows_host [n_rows]: the first n_rows ids of a Fisher-Yates shuffle of
+ *    0..n-1 on stream 1 (position i takes the id at i + floor(x (n - i) /
+ *    2^64) for the next word x).  lider_build uses n_rows = n_clusters (1 with
+ *    farthest-first seeding).  NULL: not drawn.
+ * Errors: EINVAL for sizes out of range (m 1..16, d 1..65536, n_arrays 0..16,
+ * w > 0 for E2LSH, 1 <= n <= 2^31-1, 0 <= n_rows <= n). */
+int lider_draw_params(uint64_t seed, int32_t n_arrays, int32_t m, int32_t d, double w,
+                      int32_t hash_kind, float* lsh_a_host, float* lsh_b_host, int64_t n,
+                      int32_t n_rows, int64_t* rows_host);
 
 /* Release the index and all its device memory.  NULL is a no-op.  Must not be
  * called while a search on the index is still running. */
@@ -158,7 +191,8 @@ const char* lider_last_error(void);
  *                 device and a persistent grid pulls only those (for small or
  *                 sparse batches on large indexes).  Results are identical.
  *  tile_rows      rows per rerank tile (one wave per tile): 32, 64, 128, or 0
- *                 (64).
+ *                 (chosen with pass_pairs from the expected number of pairs
+ *                 overlapping a tile: 64 when it is at most 16, else 32).
  *  l1_dense       How the layer-1 scores are computed; the routed set is then
  *                 decided exactly (the FP64 definition): the centroids whose
  *                 score lies within twice its rigorous error bound of the c-th
@@ -181,8 +215,11 @@ const char* lider_last_error(void);
  *                 range grows on the side whose next hashkey is closer to the
  *                 query's in dist_e (ties to the left) until r (r1) positions
  *                 are taken.  Applies to both layers.
- *  pass_pairs     (query, cluster) pairs per MFMA pass of the rerank: 16, 32,
- *                 or 0 (32).  Results are identical. */
+ *  pass_pairs     most (query, cluster) pairs per MFMA pass of the rerank:
+ *                 16, 32, 64, 128, or 0 (32, 64 or 128 as that expected
+ *                 overlap is at most 16, at most 48, or more); 64-row tiles
+ *                 take at most 64, 128-row tiles at most 32.  A tile overlapped by P pairs is
+ *                 streamed ceil(P / pass_pairs) times.  Results are identical. */
 typedef struct {
   int32_t r1;
   int32_t precision;

@@ -75,6 +75,10 @@ def lib():
         L.or_core.argtypes = [i64, i32, i32, p, i32, p, p, p, p, p, p, p, p, p, p]
         L.or_core_query.argtypes = [i64, i32, i32, i32, p, p, p, p, p, p, p, p]
         L.or_core_query.restype = i64
+        L.or_splitmix64.argtypes = [u64, i64, p]
+        L.or_splitmix64.restype = None
+        L.or_seeded_lsh.argtypes = [u64, i32, i32, f64, i32, p, p]
+        L.or_seeded_rows.argtypes = [u64, i64, i32, p]
         _lib = L
     return _lib
 
@@ -90,6 +94,31 @@ def _check(st: int, what: str):
 
 def _f32(a):
     return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def splitmix64(state, count):
+    """`count` consecutive SplitMix64 outputs from `state` (uint64 array)."""
+    out = np.empty(count, np.uint64)
+    lib().or_splitmix64(int(state) & (2**64 - 1), count, _ptr(out))
+    return out
+
+
+def seeded_params(seed, m, d, w, n_arrays=1, hash_kind="e2lsh"):
+    """The seeded hash draws (A [2Hm, d], b [2Hm]) of a build from `seed`."""
+    nh = 2 * int(n_arrays) * int(m)
+    A = np.empty((nh, d), np.float32)
+    b = np.empty(nh, np.float32)
+    _check(lib().or_seeded_lsh(int(seed) & (2**64 - 1), nh, d, float(w),
+                               int(hash_kind == "sign"), _ptr(A), _ptr(b)), "seeded_lsh")
+    return A, b
+
+
+def seeded_rows(seed, n, count):
+    """The seeded k-means rows: the first `count` ids of a seeded shuffle."""
+    out = np.empty(count, np.int64)
+    _check(lib().or_seeded_rows(int(seed) & (2**64 - 1), int(n), int(count), _ptr(out)),
+           "seeded_rows")
+    return out
 
 
 def digits(X, A, b, w):

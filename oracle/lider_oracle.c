@@ -146,6 +146,81 @@ int or_kmeans_update(const float* X, int64_t n, int32_t d, const int32_t* assign
   return OR_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Seeded draws of the method's random inputs: the E2LSH projections
+ * a_i ~ N(0, I_d) and offsets b_i ~ U[0, w) (Section 4) and the rows that seed
+ * k-means (Section 3.2 only says k-means).
+ * Reading: one 64-bit seed S; the draws come from SplitMix64 (Steele, Lea and
+ * Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014: add
+ * the golden-ratio increment to the state, then two xor-shift-multiply rounds
+ * and a final xor-shift).  Stream s (0: hash parameters, 1: k-means rows)
+ * starts from the state S xor (the (s+1)-th output of the generator started
+ * at state 0).  A uniform is u = (x >> 11) * 2^-53 in [0, 1).  Normals come
+ * in pairs from the Box-Muller transform (1958) of (u1, u2):
+ * sqrt(-2 ln(1 - u1)) * (cos, sin)(2 pi u2), in that order, in FP64, then
+ * rounded to fp32.  A is filled row by row ([2Hm x d], the layout of the hash
+ * sets), then b_i = fp32(u * w) for each row in order (sign hashes: b = 0, no
+ * draws).  k-means rows: the first `count` entries of a Fisher-Yates shuffle
+ * of the ids 0..n-1 drawn from stream 1, position i swapped with
+ * i + floor(x * (n - i) / 2^64) for the next output x. */
+static uint64_t or_sm64(uint64_t* state) {
+  *state = *state + 0x9E3779B97F4A7C15ULL;
+  uint64_t z = *state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+/* `count` consecutive outputs of the generator started at `state`. */
+void or_splitmix64(uint64_t state, int64_t count, uint64_t* out) {
+  for (int64_t i = 0; i < count; ++i) out[i] = or_sm64(&state);
+}
+
+static uint64_t or_stream(uint64_t seed, int32_t s) {
+  uint64_t t = 0, v = 0;
+  for (int32_t i = 0; i <= s; ++i) v = or_sm64(&t);
+  return seed ^ v;
+}
+
+static double or_uniform(uint64_t* state) {
+  return (double)(or_sm64(state) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+int or_seeded_lsh(uint64_t seed, int32_t nh, int32_t d, double w, int32_t sign, float* A,
+                  float* b) {
+  if (nh < 1 || d < 1) return OR_EINVAL;
+  uint64_t st = or_stream(seed, 0);
+  const int64_t total = (int64_t)nh * d;
+  const double two_pi = 6.283185307179586;
+  for (int64_t i = 0; i < total; i += 2) {
+    double u1 = or_uniform(&st);
+    double u2 = or_uniform(&st);
+    double rad = sqrt(-2.0 * log(1.0 - u1));
+    A[i] = (float)(rad * cos(two_pi * u2));
+    if (i + 1 < total) A[i + 1] = (float)(rad * sin(two_pi * u2));
+  }
+  for (int32_t i = 0; i < nh; ++i) b[i] = sign ? 0.0f : (float)(or_uniform(&st) * w);
+  return OR_OK;
+}
+
+int or_seeded_rows(uint64_t seed, int64_t n, int32_t count, int64_t* out) {
+  if (n < 1 || count < 0 || count > n) return OR_EINVAL;
+  int64_t* ids = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  if (!ids) return OR_ENOMEM;
+  for (int64_t i = 0; i < n; ++i) ids[i] = i;
+  uint64_t st = or_stream(seed, 1);
+  for (int32_t i = 0; i < count; ++i) {
+    uint64_t x = or_sm64(&st);
+    int64_t j = i + (int64_t)(((unsigned __int128)x * (uint64_t)(n - i)) >> 64);
+    int64_t t = ids[i];
+    ids[i] = ids[j];
+    ids[j] = t;
+    out[i] = ids[i];
+  }
+  free(ids);
+  return OR_OK;
+}
+
 /* Reading: k-means initial centres by farthest-first traversal (the maximin
  * rule of Gonzalez's k-center heuristic): the first centre is a given row;
  * every next centre is the row whose squared Euclidean distance (FP64) to its

@@ -3,6 +3,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <unordered_map>
 
 #include "lider_internal.hpp"
 
@@ -93,6 +94,68 @@ int alloc_index(Index& ix) {
   return rc;
 }
 
+// Seeded draws of the method's random inputs (lider_build_params.seed,
+// lider_draw_params): the E2LSH projections a_i ~ N(0, I_d) and offsets
+// b_i ~ U[0, w) of Section 4, and the rows that seed k-means (Section 3.2).
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) supplies 64-bit words;
+// stream s (0: hash parameters, 1: k-means rows) starts from the seed xor the
+// (s+1)-th word of the generator started at state 0.  Uniforms take the top
+// 53 bits; normals are Box-Muller pairs (cosine first) in FP64 rounded to
+// fp32, filling A row by row; then one uniform per offset.  Seed rows are the
+// prefix of a Fisher-Yates shuffle of 0..n-1 (position i takes the id at
+// i + floor(x (n - i) / 2^64)).  Host code.
+struct SplitMix64 {
+  uint64_t state;
+  uint64_t next() {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double unit() { return double(next() >> 11) * 0x1.0p-53; }
+};
+
+SplitMix64 draw_stream(uint64_t seed, int s) {
+  SplitMix64 zero{0};
+  uint64_t word = 0;
+  for (int i = 0; i <= s; ++i) word = zero.next();
+  return SplitMix64{seed ^ word};
+}
+
+void draw_hash_params(uint64_t seed, int64_t nh, int64_t d, double w, bool sign, float* A,
+                      float* b) {
+#pragma clang fp contract(off)
+  SplitMix64 g = draw_stream(seed, 0);
+  const int64_t total = nh * d;
+  for (int64_t i = 0; i < total; i += 2) {
+    const double u1 = g.unit();
+    const double u2 = g.unit();
+    const double radius = std::sqrt(-2.0 * std::log(1.0 - u1));
+    const double angle = 6.283185307179586 * u2;
+    A[i] = float(radius * std::cos(angle));
+    if (i + 1 < total) A[i + 1] = float(radius * std::sin(angle));
+  }
+  for (int64_t i = 0; i < nh; ++i) b[i] = sign ? 0.f : float(g.unit() * w);
+}
+
+void draw_seed_rows(uint64_t seed, int64_t n, int64_t count, int64_t* out) {
+  SplitMix64 g = draw_stream(seed, 1);
+  std::unordered_map<int64_t, int64_t> moved;  // positions whose id has changed
+  auto id_at = [&](int64_t p) {
+    const auto it = moved.find(p);
+    return it == moved.end() ? p : it->second;
+  };
+  for (int64_t i = 0; i < count; ++i) {
+    const uint64_t x = g.next();
+    const int64_t j = i + int64_t((static_cast<unsigned __int128>(x) * uint64_t(n - i)) >> 64);
+    const int64_t vi = id_at(i), vj = id_at(j);
+    moved[j] = vi;
+    moved[i] = vj;
+    out[i] = vj;
+  }
+}
+
 }  // namespace
 
 int set_error(int status, const std::string& msg) {
@@ -143,10 +206,10 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
     return set_error(LIDER_EINVAL, "w must be > 0");
   if (P->rmi_fanout < 1 || P->rmi_fanout_l1 < 0)
     return set_error(LIDER_EINVAL, "rmi_fanout must be >= 1");
-  if (!P->lsh_a_host || (!sign && !P->lsh_b_host))
-    return set_error(LIDER_EINVAL, "LSH parameters are NULL");
-  if (!P->assignment_dev && (!P->kmeans_init_host || P->kmeans_iters < 1))
-    return set_error(LIDER_EINVAL, "k-means needs kmeans_init_host and kmeans_iters >= 1");
+  if (P->lsh_a_host && !sign && !P->lsh_b_host)
+    return set_error(LIDER_EINVAL, "lsh_b_host is NULL while lsh_a_host is given");
+  if (!P->assignment_dev && P->kmeans_iters < 1)
+    return set_error(LIDER_EINVAL, "k-means needs kmeans_iters >= 1");
   if (P->storage != LIDER_F32 && P->storage != LIDER_BF16)
     return set_error(LIDER_EINVAL, "storage must be LIDER_F32 or LIDER_BF16");
   if (P->centroid_storage != LIDER_F32 && P->centroid_storage != LIDER_FP8E4M3)
@@ -155,7 +218,7 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
     return set_error(LIDER_EINVAL, "kmeans_seeding must be 0 or 1");
   if (P->n_arrays < 0 || P->n_arrays > LIDER_MAX_H)
     return set_error(LIDER_EINVAL, "n_arrays must be in 0..16");
-  if (!P->assignment_dev)
+  if (!P->assignment_dev && P->kmeans_init_host)
     for (int32_t j = 0; j < (P->kmeans_seeding ? 1 : P->n_clusters); ++j)
       if (P->kmeans_init_host[j] < 0 || P->kmeans_init_host[j] >= n)
         return set_error(LIDER_EINVAL, "kmeans_init_host id out of range");
@@ -188,10 +251,28 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
   } while (0)
   TRY(alloc_index(ix));
   const int64_t nh = 2 * H * m;
-  TRY(check_hip(hipMemcpyAsync(ix.A, P->lsh_a_host, size_t(nh) * d * 4, hipMemcpyHostToDevice, st),
+  // draws from the seed where the caller gave none
+  std::vector<float> seeded_a, seeded_b;
+  std::vector<int64_t> seeded_rows;
+  const float* a_host = P->lsh_a_host;
+  const float* b_host = P->lsh_b_host;
+  const int64_t* init_host = P->kmeans_init_host;
+  if (rc == LIDER_OK && !a_host) {
+    seeded_a.resize(size_t(nh) * d);
+    seeded_b.resize(size_t(nh));
+    draw_hash_params(P->seed, nh, d, ix.w, sign, seeded_a.data(), seeded_b.data());
+    a_host = seeded_a.data();
+    b_host = seeded_b.data();
+  }
+  if (rc == LIDER_OK && !P->assignment_dev && !init_host) {
+    seeded_rows.resize(size_t(P->kmeans_seeding ? 1 : C));
+    draw_seed_rows(P->seed, n, int64_t(seeded_rows.size()), seeded_rows.data());
+    init_host = seeded_rows.data();
+  }
+  TRY(check_hip(hipMemcpyAsync(ix.A, a_host, size_t(nh) * d * 4, hipMemcpyHostToDevice, st),
                 "copy LSH projections"));
-  if (P->lsh_b_host)
-    TRY(check_hip(hipMemcpyAsync(ix.b, P->lsh_b_host, size_t(nh) * 4, hipMemcpyHostToDevice,
+  if (b_host)
+    TRY(check_hip(hipMemcpyAsync(ix.b, b_host, size_t(nh) * 4, hipMemcpyHostToDevice,
                                  st),
                   "copy LSH offsets"));
   else
@@ -225,7 +306,7 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
       if (scr) (void)hipFree(scr);
       ix.iters_run = 0;
     } else {
-      TRY(run_kmeans(ix, corpus_dev, P->kmeans_init_host, P->kmeans_iters, P->kmeans_seeding, st));
+      TRY(run_kmeans(ix, corpus_dev, init_host, P->kmeans_iters, P->kmeans_seeding, st));
     }
   }
   TRY(build_core_models(ix, corpus_dev, st));
@@ -236,6 +317,30 @@ int lider_build(const float* corpus_dev, int64_t n, int32_t d, const lider_build
     return rc;
   }
   *out = h;
+  return LIDER_OK;
+}
+
+int lider_draw_params(uint64_t seed, int32_t n_arrays, int32_t m, int32_t d, double w,
+                      int32_t hash_kind, float* lsh_a_host, float* lsh_b_host, int64_t n,
+                      int32_t n_rows, int64_t* rows_host) {
+  g_err.clear();
+  const int32_t H = n_arrays > 0 ? n_arrays : 1;
+  if (n_arrays < 0 || n_arrays > LIDER_MAX_H) return set_error(LIDER_EINVAL, "n_arrays must be in 0..16");
+  if (m < 1 || m > LIDER_MAX_M) return set_error(LIDER_EINVAL, "m must be in 1..16");
+  if (d < 1 || d > 65536) return set_error(LIDER_EINVAL, "d must be in 1..65536");
+  if (hash_kind != LIDER_HASH_E2LSH && hash_kind != LIDER_HASH_SIGN)
+    return set_error(LIDER_EINVAL, "hash_kind must be LIDER_HASH_E2LSH or LIDER_HASH_SIGN");
+  const bool sign = hash_kind == LIDER_HASH_SIGN;
+  if (lsh_a_host || lsh_b_host) {
+    if (!lsh_a_host || !lsh_b_host) return set_error(LIDER_EINVAL, "give both lsh_a_host and lsh_b_host");
+    if (!sign && (!(w > 0.0) || !std::isfinite(w))) return set_error(LIDER_EINVAL, "w must be > 0");
+    draw_hash_params(seed, 2 * int64_t(H) * m, d, sign ? 1.0 : w, sign, lsh_a_host, lsh_b_host);
+  }
+  if (rows_host) {
+    if (n < 1 || n > INT32_MAX || n_rows < 0 || n_rows > n)
+      return set_error(LIDER_EINVAL, "need 1 <= n <= 2^31-1 and 0 <= n_rows <= n");
+    draw_seed_rows(seed, n, n_rows, rows_host);
+  }
   return LIDER_OK;
 }
 
@@ -281,8 +386,9 @@ static int validate_search(const lider_index* index, const float* Q, int64_t nq,
   if (o.grid_mult < 0 || o.grid_mult > 64) return set_error(LIDER_EINVAL, "grid_mult out of range");
   if (o.persistent < 0 || o.persistent > 2) return set_error(LIDER_EINVAL, "persistent must be 0, 1 or 2");
   if (o.l1_dense < -1 || o.l1_dense > 1) return set_error(LIDER_EINVAL, "l1_dense must be -1, 0 or 1");
-  if (o.pass_pairs != 0 && o.pass_pairs != 16 && o.pass_pairs != 32)
-    return set_error(LIDER_EINVAL, "pass_pairs must be 0, 16 or 32");
+  if (o.pass_pairs != 0 && o.pass_pairs != 16 && o.pass_pairs != 32 && o.pass_pairs != 64 &&
+      o.pass_pairs != 128)
+    return set_error(LIDER_EINVAL, "pass_pairs must be 0, 16, 32, 64 or 128");
   if (o.expand_bits < 0 || o.expand_bits > 16)
     return set_error(LIDER_EINVAL, "expand_bits must be in 0..16");
   if (o.expand_bits > 0 && index->ix.hash_kind != LIDER_HASH_SIGN)

@@ -41,7 +41,7 @@ class BuildParams(C.Structure):
                 ("kmeans_init_host", C.c_void_p), ("kmeans_iters", C.c_int32),
                 ("storage", C.c_int32), ("centroid_storage", C.c_int32),
                 ("kmeans_seeding", C.c_int32), ("hash_kind", C.c_int32),
-                ("n_arrays", C.c_int32)]
+                ("n_arrays", C.c_int32), ("seed", C.c_uint64)]
 
 
 class SearchOpts(C.Structure):
@@ -67,7 +67,8 @@ class Info(C.Structure):
 SYMBOLS = ["lider_build", "lider_free", "lider_last_error", "lider_search_workspace",
            "lider_search", "lider_search_ex", "lider_get_info", "lider_export_bytes",
            "lider_export", "lider_hash", "lider_kmeans_assign", "lider_profile_begin",
-           "lider_profile_end", "lider_debug_fail_next", "lider_save", "lider_load"]
+           "lider_profile_end", "lider_debug_fail_next", "lider_save", "lider_load",
+           "lider_draw_params"]
 NSTAGES = 5
 STAGES = ["hash", "route", "worklist", "rerank", "select"]
 
@@ -103,6 +104,8 @@ def lib():
         L.lider_debug_fail_next.restype = None
         L.lider_save.argtypes = [p, C.c_char_p]
         L.lider_load.argtypes = [C.c_char_p, p, C.POINTER(p)]
+        L.lider_draw_params.argtypes = [C.c_uint64, i32, i32, i32, C.c_double, i32, p, p, i64,
+                                        i32, p]
         _lib = L
     return _lib
 
@@ -148,34 +151,39 @@ _PREC = {"f32": F32, "bf16": BF16}
 class Index:
     """A LIDER index resident in device memory (lider_build / lider_free)."""
 
-    def __init__(self, corpus, n_clusters, m, w, rmi_fanout, lsh, rmi_fanout_l1=0,
+    def __init__(self, corpus, n_clusters, m, w, rmi_fanout, lsh=None, rmi_fanout_l1=0,
                  kmeans_init=None, kmeans_iters=20, assignment=None, storage="f32",
                  centroid_storage="f32", seeding="given", hash_kind="e2lsh", stream=None,
-                 n_arrays=1):
+                 n_arrays=1, seed=0):
         """hash_kind "e2lsh": integer digits floor((a.x + b) / w); "sign": the
         cosine variant (bits [a.x >= 0], key = Decimal(bits); w and b unused).
         n_arrays = H hashkey arrays per core model: lsh = (A [2Hm, d], b [2Hm]),
-        rows h*m.. array h of layer 1, rows H*m + h*m.. array h of layer 2."""
+        rows h*m.. array h of layer 1, rows H*m + h*m.. array h of layer 2.
+        lsh None / kmeans_init None: the library draws them from `seed`."""
         torch = _torch()
         cp = _dev_ptr(corpus, torch.float32, 2, "corpus")
         n, d = corpus.shape
         kind = {"e2lsh": 0, "sign": 1}[hash_kind]
         H = int(n_arrays)
-        A = np.ascontiguousarray(lsh[0], dtype=np.float32)
-        b = np.ascontiguousarray(lsh[1] if lsh[1] is not None else np.zeros(2 * H * m),
-                                 dtype=np.float32)
-        if A.shape != (2 * H * m, d) or b.shape != (2 * H * m,):
-            raise ValueError("lsh must be (A [2Hm, d], b [2Hm])")
+        A = b = None
+        if lsh is not None:
+            A = np.ascontiguousarray(lsh[0], dtype=np.float32)
+            b = np.ascontiguousarray(lsh[1] if lsh[1] is not None else np.zeros(2 * H * m),
+                                     dtype=np.float32)
+            if A.shape != (2 * H * m, d) or b.shape != (2 * H * m,):
+                raise ValueError("lsh must be (A [2Hm, d], b [2Hm])")
         ini = None if kmeans_init is None else np.ascontiguousarray(kmeans_init, dtype=np.int64)
         seed_mode = {"given": 0, "farthest": 1}[seeding]
-        if assignment is None and (ini is None or ini.shape[0] < (1 if seed_mode else n_clusters)):
-            raise ValueError("k-means needs kmeans_init row ids")
+        if assignment is None and ini is not None and \
+                ini.shape[0] < (1 if seed_mode else n_clusters):
+            raise ValueError("kmeans_init needs n_clusters row ids (1 with farthest-first)")
         P = BuildParams(int(n_clusters), int(m), int(rmi_fanout), int(rmi_fanout_l1), float(w),
                         _np_ptr(A), _np_ptr(b),
                         None if assignment is None else _dev_ptr(assignment, torch.int32, 1,
                                                                  "assignment"),
                         _np_ptr(ini), int(kmeans_iters), _STORAGE[storage],
-                        _CSTORAGE[centroid_storage], seed_mode, kind, H)
+                        _CSTORAGE[centroid_storage], seed_mode, kind, H,
+                        int(seed) & (2**64 - 1))
         h = C.c_void_p()
         _check(lib().lider_build(cp, n, d, C.byref(P), _stream(stream), C.byref(h)))
         self._h = h
@@ -291,6 +299,19 @@ class Index:
             dbg["l1"] = dbg["l1"][:, 0]
             dbg["pairs"] = dbg["pairs"][:, :, 0]
         return (ids, sc, dbg) if debug else (ids, sc)
+
+
+def draw_params(seed, m, d, w, n_arrays=1, hash_kind="e2lsh", n=0, n_rows=0):
+    """The library's seeded draws (lider_draw_params, host only): returns
+    (A [2Hm, d] f32, b [2Hm] f32, rows [n_rows] int64 or None)."""
+    H = max(1, int(n_arrays))
+    A = np.empty((2 * H * m, d), np.float32)
+    b = np.empty(2 * H * m, np.float32)
+    rows = np.empty(n_rows, np.int64) if n else None
+    _check(lib().lider_draw_params(int(seed) & (2**64 - 1), int(n_arrays), int(m), int(d),
+                                   float(w), {"e2lsh": 0, "sign": 1}[hash_kind], _np_ptr(A),
+                                   _np_ptr(b), int(n), int(n_rows), _np_ptr(rows)))
+    return A, b, rows
 
 
 def hash(X, A, b, w, stream=None):

@@ -42,6 +42,7 @@ int main(void) {
   P(lider_build_params, w) P(lider_build_params, lsh_a_host) P(lider_build_params, assignment_dev)
   P(lider_build_params, kmeans_init_host) P(lider_build_params, kmeans_iters)
   P(lider_build_params, centroid_storage) P(lider_build_params, kmeans_seeding)
+  P(lider_build_params, n_arrays) P(lider_build_params, seed)
   printf("lider_search_opts %zu\n", sizeof(lider_search_opts));
   P(lider_search_opts, grid_mult)
   printf("lider_search_debug %zu\n", sizeof(lider_search_debug));
@@ -65,6 +66,8 @@ int main(void) {
         "lider_build_params.kmeans_iters": lider.BuildParams.kmeans_iters.offset,
         "lider_build_params.centroid_storage": lider.BuildParams.centroid_storage.offset,
         "lider_build_params.kmeans_seeding": lider.BuildParams.kmeans_seeding.offset,
+        "lider_build_params.n_arrays": lider.BuildParams.n_arrays.offset,
+        "lider_build_params.seed": lider.BuildParams.seed.offset,
         "lider_search_opts": C.sizeof(lider.SearchOpts),
         "lider_search_opts.grid_mult": lider.SearchOpts.grid_mult.offset,
         "lider_search_debug": C.sizeof(lider.SearchDebug),
