@@ -2,8 +2,8 @@
 
 For one shape bucket -- (index shape, precision, k, c, r, r1, batch-size
 bucket) -- it times every candidate schedule of the window-scoring kernel
-(rows per wave tile 64 / 128; 16 or 32 pairs per MFMA pass; one wave per tile
-of the whole index, a persistent grid of 1 / 2 / 4 workgroups per CU pulling
+(rows per wave tile 32 / 64 / 128; 16, 32, 64 or 128 pairs per MFMA pass;
+the library's own default shape; one wave per tile of the whole index, a persistent grid of 1 / 2 / 4 workgroups per CU pulling
 tiles in chunks from per-XCD counters, or the same grid dealt only the tiles
 some window overlaps from a list built on the device) on a representative
 batch, checks that every candidate returns bit-identical ids and scores, and
@@ -16,10 +16,13 @@ import json
 import os
 
 KEYS = ("tile_rows", "persistent", "grid_mult", "pass_pairs")
-CANDIDATES = ([dict(tile_rows=t, persistent=0, grid_mult=0, pass_pairs=pp)
-               for t in (32, 64, 128) for pp in (16, 32)]
-              + [dict(tile_rows=t, persistent=p, grid_mult=g, pass_pairs=0)
-                 for p in (1, 2) for t in (32, 64) for g in (1, 2, 4)])
+CANDIDATES = ([dict(tile_rows=0, persistent=0, grid_mult=0, pass_pairs=0)]
+              + [dict(tile_rows=t, persistent=0, grid_mult=0, pass_pairs=pp)
+                 for t in (32, 64, 128) for pp in (16, 32)]
+              + [dict(tile_rows=t, persistent=0, grid_mult=0, pass_pairs=pp)
+                 for t in (32, 64) for pp in (64, 128) if t * pp <= 4096]
+              + [dict(tile_rows=t, persistent=p, grid_mult=g, pass_pairs=pp)
+                 for p in (1, 2) for t in (32, 64) for g in (1, 2, 4) for pp in (0, 64)])
 
 
 def bucket(nq):

@@ -49,6 +49,7 @@ struct Plan {
       o_ccount, o_cstart, o_cfill, o_wl, o_sbuf, o_qb, o_slist, o_aflag, o_alist, o_kq, o_lst,
       o_rw, o_pw, o_mask, o_rcand, o_rcnt, total;
   int32_t r1, rcap, S;
+  int ti, npcm;  // rerank tile table and 16-pair blocks per pass
   // l1_dense_rows: layer-1 scores of every centroid (dense product), else of
   // the r1-windows (window kernel).  Several hashkey arrays: lcap = layer-1
   // union capacity per query (list mode when r1 < C), mw = mask words per
@@ -59,11 +60,27 @@ struct Plan {
 
 // Rerank tile table in use: 0/1/2 = 32/64/128 rows per tile (default 64:
 // measured fastest or within 2 % of it from whole clusters to 256-row windows).
-int tile_index(const Index& ix, const lider_search_opts& o) {
-  (void)ix;
-  if (o.tile_rows == 32) return 0;
-  if (o.tile_rows == 128) return 2;
-  return 1;
+// Rerank shape: rows per tile (index into the tile tables: 32, 64, 128) and
+// 16-pair column blocks per MFMA pass.  A tile overlapped by P pairs is
+// streamed ceil(P / pass) times, while a wider pass holds more accumulators
+// (fewer waves per SIMD to hide latency).  Unless the caller fixes them, both
+// follow the expected overlap: the pairs per cluster times the share of a
+// cluster that one pair's window (for several arrays, the hull of its H
+// windows) covers, widened by a 64-row tile.  On the 1M x 768 workload about
+// 10 pairs per tile (each query's whole top cluster) run fastest with 64-row
+// tiles and 32-pair passes, about 26 (c = 8, r = 256) with 32-row tiles and
+// 64-pair passes, about 80 (ten arrays) with 32-row tiles and 128-pair passes.
+void rerank_shape(const Index& ix, int64_t nq, int32_t c, int32_t r, const lider_search_opts& o,
+                  int* ti, int* npcm) {
+  const double lbar = std::max(1.0, double(ix.n) / double(ix.C));
+  const double span = std::min(lbar, double(ix.H) * std::min(double(r), lbar));
+  const double est = double(nq) * c / double(ix.C) * std::min(1.0, (span + 64.0) / lbar);
+  const int wide = est <= 16.0 ? 0 : est <= 48.0 ? 1 : 2;
+  if (o.tile_rows == 32) *ti = 0;
+  else if (o.tile_rows == 64) *ti = 1;
+  else if (o.tile_rows == 128) *ti = 2;
+  else *ti = wide == 0 ? 1 : 0;
+  *npcm = o.pass_pairs > 0 ? o.pass_pairs / 16 : (wide == 0 ? 2 : wide == 1 ? 4 : 8);
 }
 
 Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
@@ -114,8 +131,8 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   p.o_sbuf = take(size_t(nq) * c * rcap * 4);
   p.o_qb = take((S || ix.cent8 || ix.cent_l1_b) ? size_t(nq) * ix.d * 2 : 0);
   p.o_slist = take(S ? size_t(nq) * S * 4 : 0);
-  const int ti = tile_index(ix, o);
-  const size_t nt = o.persistent == 2 ? size_t(ix.n_tiles[ti]) : 0;
+  rerank_shape(ix, nq, c, r, o, &p.ti, &p.npcm);
+  const size_t nt = o.persistent == 2 ? size_t(ix.n_tiles[p.ti]) : 0;
   p.o_aflag = take(nt * 4);
   p.o_alist = take(nt * 4);
   p.o_kq = take(o.expand_bits > 0 ? size_t(nq) * std::max<int32_t>(c, 1) * H * 8 : 0);
@@ -1102,13 +1119,16 @@ __global__ void mark_tiles_kernel(const Pair* __restrict__ pairs, int64_t np, in
 }
 
 // ------------------------------------------------------------ rerank
-// Per-wave list of the pairs overlapping the wave's current tile (one ballot
-// round of 64 pairs at a time).
+// Per-wave list of the pairs overlapping the wave's current tile.  The pairs
+// of the tile's cluster are tested 64 at a time (one ballot round); hits are
+// appended until a whole pass (CAP - 64 pairs) is listed, so a round may
+// overshoot by up to 63 entries, which carry over to the next pass.
 constexpr int kWavePairCap = 64;
 
+template <int CAP>
 struct WaveShared {
-  int32_t lp[kWavePairCap], lq[kWavePairCap], ls[kWavePairCap], le[kWavePairCap];
-  uint32_t lm[kWavePairCap][4];  // membership bits of the tile's rows (several arrays)
+  int32_t lp[CAP], lq[CAP], ls[CAP], le[CAP];
+  uint32_t lm[CAP][4];  // membership bits of the tile's rows (several arrays)
 };
 
 // Tile fetch, one tile per wave.  Direct (persistent = 0): workgroups are
@@ -1406,56 +1426,92 @@ struct TileRows {
 // copies of loaded data): the loads of one step are in flight while the MFMAs
 // of the previous step run.  The last load of the paired loop is clamped to
 // the final step (a redundant cache hit when the step count is even).
+// One k-step's operands: the tile's RC row blocks and the NPC query column
+// blocks (q[pc] = the query row of the lane's pair in column block pc).
 template <class F, int RC, int NPC, bool NT, class Src>
-__device__ __forceinline__ void load_step(const Src& src,
-                                          const typename F::QE* q0, const typename F::QE* q1,
-                                          int k, int d, typename F::T (&x)[RC],
-                                          typename F::T& qa, typename F::T& qb) {
+__device__ __forceinline__ void load_step(const Src& src, const typename F::QE* const* q, int k,
+                                          int d, typename F::T (&x)[RC],
+                                          typename F::T (&qv)[NPC]) {
 #pragma unroll
   for (int rc = 0; rc < RC; ++rc) x[rc] = src.load(rc, k, d, NT);
-  qa = F::load(q0, k, d);
-  if (NPC > 1) qb = F::load(q1, k, d);
+#pragma unroll
+  for (int pc = 0; pc < NPC; ++pc) qv[pc] = F::load(q[pc], k, d);
 }
 
-template <class F, int RC, int NPC>
-__device__ __forceinline__ void mfma_step(const typename F::T (&x)[RC], const typename F::T& qa,
-                                          const typename F::T& qb, floatx4 (&acc)[RC][2]) {
+template <class F, int RC, int NPC, int NPCM>
+__device__ __forceinline__ void mfma_step(const typename F::T (&x)[RC],
+                                          const typename F::T (&qv)[NPC],
+                                          floatx4 (&acc)[RC][NPCM]) {
 #pragma unroll
-  for (int rc = 0; rc < RC; ++rc) F::mfma(qa, x[rc], acc[rc][0]);
-  if (NPC > 1) {
+  for (int pc = 0; pc < NPC; ++pc) {
 #pragma unroll
-    for (int rc = 0; rc < RC; ++rc) F::mfma(qb, x[rc], acc[rc][1]);
+    for (int rc = 0; rc < RC; ++rc) F::mfma(qv[pc], x[rc], acc[rc][pc]);
   }
 }
 
-// xa holds the rows' first k-step when `pre` is set (issued before the pair
-// scan so that the tile's first HBM reads overlap it).
-template <class F, int RC, int NPC, bool NT, class Src>
-__device__ __forceinline__ void pass_loop(const Src& xr,
-                                          const typename F::QE* q0, const typename F::QE* q1,
-                                          int ks0, int ks1, int sub, int d,
-                                          floatx4 (&acc)[RC][2], typename F::T (&xa)[RC],
-                                          bool pre) {
-  typename F::T xb[RC], qa0, qa1, qb0, qb1;
+// The k-loop of one pass over NPC column blocks of 16 pairs, software-
+// pipelined with two register sets (no copies of loaded data): the loads of
+// one step are in flight while the MFMAs of the previous step run.  The last
+// load of the paired loop is clamped to the final step (a redundant cache hit
+// when the step count is even).  xa holds the rows' first k-step when `pre`
+// is set (issued before the pair scan so that the tile's first HBM reads
+// overlap it).
+template <class F, int RC, int NPC, int NPCM, bool NT, class Src>
+__device__ __forceinline__ void pass_loop(const Src& xr, const typename F::QE* const* q, int ks0,
+                                          int ks1, int sub, int d, floatx4 (&acc)[RC][NPCM],
+                                          typename F::T (&xa)[RC], bool pre) {
+  typename F::T xb[RC], qa[NPC], qb[NPC];
   if (pre) {
-    qa0 = F::load(q0, ks0 * F::KS + sub, d);
-    if (NPC > 1) qa1 = F::load(q1, ks0 * F::KS + sub, d);
+#pragma unroll
+    for (int pc = 0; pc < NPC; ++pc) qa[pc] = F::load(q[pc], ks0 * F::KS + sub, d);
   } else {
-    load_step<F, RC, NPC, NT>(xr, q0, q1, ks0 * F::KS + sub, d, xa, qa0, qa1);
+    load_step<F, RC, NPC, NT>(xr, q, ks0 * F::KS + sub, d, xa, qa);
   }
   int ks = ks0;
   for (; ks + 1 < ks1; ks += 2) {
-    load_step<F, RC, NPC, NT>(xr, q0, q1, (ks + 1) * F::KS + sub, d, xb, qb0, qb1);
+    load_step<F, RC, NPC, NT>(xr, q, (ks + 1) * F::KS + sub, d, xb, qb);
     __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
-    mfma_step<F, RC, NPC>(xa, qa0, qa1, acc);
+    mfma_step<F, RC, NPC, NPCM>(xa, qa, acc);
     __builtin_amdgcn_sched_barrier(0);
     const int kn = (ks + 2 < ks1 ? ks + 2 : ks1 - 1) * F::KS + sub;
-    load_step<F, RC, NPC, NT>(xr, q0, q1, kn, d, xa, qa0, qa1);
+    load_step<F, RC, NPC, NT>(xr, q, kn, d, xa, qa);
     __builtin_amdgcn_sched_barrier(0);
-    mfma_step<F, RC, NPC>(xb, qb0, qb1, acc);
+    mfma_step<F, RC, NPC, NPCM>(xb, qb, acc);
     __builtin_amdgcn_sched_barrier(0);
   }
-  if (ks < ks1) mfma_step<F, RC, NPC>(xa, qa0, qa1, acc);
+  if (ks < ks1) mfma_step<F, RC, NPC, NPCM>(xa, qa, acc);
+}
+
+// A pass over npc (1..NPCM) column blocks: the register arrays are sized at
+// compile time, so each count has its own k-loop.
+template <class F, int RC, int NPCM, bool NT, class Src>
+__device__ __forceinline__ void pass_any(int npc, const Src& xr, const typename F::QE* const* q,
+                                         int nsteps, int sub, int d, floatx4 (&acc)[RC][NPCM],
+                                         typename F::T (&xa)[RC], bool pre) {
+  switch (npc) {
+    case 1: pass_loop<F, RC, 1, NPCM, NT, Src>(xr, q, 0, nsteps, sub, d, acc, xa, pre); break;
+    case 2:
+      if constexpr (NPCM >= 2) pass_loop<F, RC, 2, NPCM, NT, Src>(xr, q, 0, nsteps, sub, d, acc, xa, pre);
+      break;
+    case 3:
+      if constexpr (NPCM >= 3) pass_loop<F, RC, 3, NPCM, NT, Src>(xr, q, 0, nsteps, sub, d, acc, xa, pre);
+      break;
+    case 4:
+      if constexpr (NPCM >= 4) pass_loop<F, RC, 4, NPCM, NT, Src>(xr, q, 0, nsteps, sub, d, acc, xa, pre);
+      break;
+    case 5:
+      if constexpr (NPCM >= 5) pass_loop<F, RC, 5, NPCM, NT, Src>(xr, q, 0, nsteps, sub, d, acc, xa, pre);
+      break;
+    case 6:
+      if constexpr (NPCM >= 6) pass_loop<F, RC, 6, NPCM, NT, Src>(xr, q, 0, nsteps, sub, d, acc, xa, pre);
+      break;
+    case 7:
+      if constexpr (NPCM >= 7) pass_loop<F, RC, 7, NPCM, NT, Src>(xr, q, 0, nsteps, sub, d, acc, xa, pre);
+      break;
+    default:
+      if constexpr (NPCM >= 8) pass_loop<F, RC, 8, NPCM, NT, Src>(xr, q, 0, nsteps, sub, d, acc, xa, pre);
+      break;
+  }
 }
 
 // pmask (several arrays): pair p's candidates are the rows whose bit is set in
@@ -1465,11 +1521,21 @@ __device__ __forceinline__ void pass_loop(const Src& xr,
 // wl == NULL: pair u of the cluster is pair u (identity work list).
 // pair_chunk > 0: workgroup (x, y) handles pairs [y*pair_chunk, (y+1)*pair_chunk)
 // of its tile's cluster.  row_scale (nullable) multiplies each row's scores.
-// NPCM: 16-pair column blocks per MFMA pass (1 or 2); tiles overlapped by more
-// pairs take several passes.  Each pair's accumulation is the same in every
-// grouping, so results do not depend on NPCM.
+// NPCM: 16-pair column blocks per MFMA pass (1, 2, 4 or 8).  The pairs that
+// overlap the tile are listed across ballot rounds until a whole pass is
+// full, so a tile overlapped by P pairs is streamed ceil(P / (16 NPCM))
+// times.  Each pair's accumulation is the same in every grouping, so results
+// do not depend on NPCM.
+// Waves per SIMD the compiler must allow: two where the accumulators and
+// double-buffered operands fit 256 registers without spilling, one (with
+// accumulators in AGPRs) for the widest passes.
+template <int RT, int NPCM>
+constexpr int rerank_waves_per_eu() {
+  return RT * NPCM <= 128 ? 2 : 1;
+}
+
 template <int RT, int FMT, bool VEC, bool NT, int NPCM = 2>
-__global__ __launch_bounds__(256) void rerank_kernel(
+__global__ __launch_bounds__(256, (rerank_waves_per_eu<RT, NPCM>())) void rerank_kernel(
     const void* __restrict__ Xv, int32_t d, const int32_t* __restrict__ tiles, int32_t ntiles,
     const int32_t* __restrict__ cstart,
     const int32_t* __restrict__ wl, const Pair* __restrict__ pairs, int32_t c,
@@ -1482,15 +1548,16 @@ __global__ __launch_bounds__(256) void rerank_kernel(
   typedef typename F::QE QE;
   constexpr int RC = RT / 16;
   constexpr int PP = 16 * NPCM;  // pairs per pass
+  constexpr int CAP = PP + kWavePairCap;
   // the wide feeds stream an operand-ordered copy (Xv = Xt or Xbt, tblk =
   // the tiles' first blocks); the others read row-major rows
   constexpr bool kTiled = VEC && (FMT == kF32W || FMT == kBF16W);
   typedef typename std::conditional<kTiled, TileRows<F, RC>, PtrRows<F, RC>>::type Src;
-  __shared__ WaveShared shw[kRerankWaves];
+  __shared__ WaveShared<CAP> shw[kRerankWaves];
   const XE* X = static_cast<const XE*>(Xv);
   const QE* Q = static_cast<const QE*>(Qv);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  WaveShared& sh = shw[wave];
+  WaveShared<CAP>& sh = shw[wave];
   const int i = lane & 15, s = lane >> 4;
   const int nsteps = (d + F::KS - 1) / F::KS;
   const int sub = F::SUBW * s;
@@ -1535,74 +1602,109 @@ __global__ __launch_bounds__(256) void rerank_kernel(
 #pragma unroll
       for (int rc = 0; rc < RC; ++rc) xa[rc] = xr.load(rc, sub, d, NT);
     }
-    for (int32_t pb = plo; pb < phi; pb += kWavePairCap) {
-      const int32_t u = pb + lane;
-      bool hit = false;
-      int32_t pi = 0;
-      Pair pr{0, 0, 0, 0};
-      if (u < phi) {
-        pi = wl ? wl[u] : u;
-        pr = pairs[pi];
-        hit = pr.s < row0 + rows_here && pr.s + pr.len > row0;
-      }
-      const uint64_t m = __ballot(hit);
-      if (hit) {
-        const int slot = __popcll(m & below);
-        sh.lp[slot] = pi;
-        sh.lq[slot] = pi / c;
-        sh.ls[slot] = pr.s;
-        sh.le[slot] = pr.s + pr.len;
-        if (pmask) {  // tiles start at multiples of 32 rows
-#pragma unroll
-          for (int w = 0; w < (RT + 31) / 32; ++w)
-            sh.lm[slot][w] = pmask[int64_t(pi) * mw + (row0 >> 5) + w];
+    int32_t pb = plo;
+    int n = 0;  // listed pairs not yet scored (wave-uniform)
+    for (;;) {
+      // list the overlapping pairs until a pass is full or the cluster's
+      // pairs are exhausted
+      while (n < PP && pb < phi) {
+        const int32_t u = pb + lane;
+        bool hit = false;
+        int32_t pi = 0;
+        Pair pr{0, 0, 0, 0};
+        if (u < phi) {
+          pi = wl ? wl[u] : u;
+          pr = pairs[pi];
+          hit = pr.s < row0 + rows_here && pr.s + pr.len > row0;
         }
+        const uint64_t m = __ballot(hit);
+        if (hit) {
+          const int slot = n + __popcll(m & below);
+          sh.lp[slot] = pi;
+          sh.lq[slot] = pi / c;
+          sh.ls[slot] = pr.s;
+          sh.le[slot] = pr.s + pr.len;
+          if (pmask) {  // tiles start at multiples of 32 rows
+#pragma unroll
+            for (int w = 0; w < (RT + 31) / 32; ++w)
+              sh.lm[slot][w] = pmask[int64_t(pi) * mw + (row0 >> 5) + w];
+          }
+        }
+        n += __popcll(m);
+        pb += kWavePairCap;
       }
       __threadfence_block();
       __builtin_amdgcn_wave_barrier();
-      const int P = __popcll(m);
-      for (int g0 = 0; g0 < P; g0 += PP) {
-        const int np = min(PP, P - g0);
-        const int npc = NPCM == 1 ? 1 : (np + 15) / 16;
-        floatx4 acc[RC][2];
+      if (n == 0) break;
+      const int np = min(PP, n);
+      const int npc = NPCM == 1 ? 1 : (np + 15) / 16;
+      floatx4 acc[RC][NPCM];
 #pragma unroll
-        for (int rc = 0; rc < RC; ++rc) {
-          acc[rc][0] = floatx4{0.f, 0.f, 0.f, 0.f};
-          acc[rc][1] = floatx4{0.f, 0.f, 0.f, 0.f};
-        }
-        const QE* q0 = Q + int64_t(sh.lq[g0 + min(i, np - 1)]) * d;
-        const QE* q1 = Q + int64_t(sh.lq[g0 + min(16 + i, np - 1)]) * d;
-        if (NPCM > 1 && npc > 1)
-          pass_loop<F, RC, 2, NT, Src>(xr, q0, q1, 0, nsteps, sub, d, acc, xa, pre);
-        else
-          pass_loop<F, RC, 1, NT, Src>(xr, q0, q1, 0, nsteps, sub, d, acc, xa, pre);
-        pre = false;
-        // D layout: acc[rc][pc][e] = pair g0 + 16 pc + 4 s + e, row 16 rc + i.
-        // The score stores are nontemporal: the selection reads them once.
+      for (int rc = 0; rc < RC; ++rc) {
 #pragma unroll
-        for (int pc = 0; pc < NPCM; ++pc) {
+        for (int pc = 0; pc < NPCM; ++pc) acc[rc][pc] = floatx4{0.f, 0.f, 0.f, 0.f};
+      }
+      const QE* q[NPCM];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int pp = 16 * pc + 4 * s + e;
-            if (pc < npc && pp < np) {
-              const int32_t a = sh.ls[g0 + pp], en = sh.le[g0 + pp];
-              float* dst = sbuf + int64_t(sh.lp[g0 + pp]) * rcap - a;
+      for (int pc = 0; pc < NPCM; ++pc) q[pc] = Q + int64_t(sh.lq[min(16 * pc + i, np - 1)]) * d;
+      pass_any<F, RC, NPCM, NT, Src>(npc, xr, q, nsteps, sub, d, acc, xa, pre);
+      pre = false;
+      // D layout: acc[rc][pc][e] = pair 16 pc + 4 s + e, row 16 rc + i.
+      // The score stores are nontemporal: the selection reads them once.
 #pragma unroll
-              for (int rc = 0; rc < RC; ++rc) {
-                const int rr = 16 * rc + i;
-                const int32_t row = row0 + rr;
-                if (rr < rows_here && row >= a && row < en) {
-                  float v = acc[rc][pc][e];
-                  if (row_scale) v *= row_scale[grow + rr];
-                  if (pmask && !((sh.lm[g0 + pp][rr >> 5] >> (rr & 31)) & 1u))
-                    v = __builtin_nanf("");
-                  __builtin_nontemporal_store(v, &dst[row]);
-                }
+      for (int pc = 0; pc < NPCM; ++pc) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int pp = 16 * pc + 4 * s + e;
+          if (pc < npc && pp < np) {
+            const int32_t a = sh.ls[pp], en = sh.le[pp];
+            float* dst = sbuf + int64_t(sh.lp[pp]) * rcap - a;
+#pragma unroll
+            for (int rc = 0; rc < RC; ++rc) {
+              const int rr = 16 * rc + i;
+              const int32_t row = row0 + rr;
+              if (rr < rows_here && row >= a && row < en) {
+                float v = acc[rc][pc][e];
+                if (row_scale) v *= row_scale[grow + rr];
+                if (pmask && !((sh.lm[pp][rr >> 5] >> (rr & 31)) & 1u))
+                  v = __builtin_nanf("");
+                __builtin_nontemporal_store(v, &dst[row]);
               }
             }
           }
         }
       }
+      // the entries past this pass (at most 63) move to the front of the list
+      const int rest = n - np;
+      if (rest > 0) {
+        int32_t vp = 0, vq = 0, vs = 0, ve = 0;
+        uint32_t vm[4] = {0u, 0u, 0u, 0u};
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rest) {
+          vp = sh.lp[np + lane];
+          vq = sh.lq[np + lane];
+          vs = sh.ls[np + lane];
+          ve = sh.le[np + lane];
+          if (pmask) {
+#pragma unroll
+            for (int w = 0; w < (RT + 31) / 32; ++w) vm[w] = sh.lm[np + lane][w];
+          }
+        }
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rest) {
+          sh.lp[lane] = vp;
+          sh.lq[lane] = vq;
+          sh.ls[lane] = vs;
+          sh.le[lane] = ve;
+          if (pmask) {
+#pragma unroll
+            for (int w = 0; w < (RT + 31) / 32; ++w) sh.lm[lane][w] = vm[w];
+          }
+        }
+      }
+      n = rest;
       __threadfence_block();
       __builtin_amdgcn_wave_barrier();
     }
@@ -2404,6 +2506,37 @@ void launch_wave_select(hipStream_t st, const Pair* pairs, const float* sbuf, in
                        rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
 }
 
+template <int RT, int NPCM>
+void launch_score_n(const Index& ix, bool bf16, bool vec, bool bvec, unsigned grid, int ti,
+                    const int32_t* cstart, const int32_t* wl, const Pair* pairs, int32_t c,
+                    const float* Q, const __hip_bfloat16* Qb, float* sbuf, int32_t rcap,
+                    int persistent, int32_t* ctr, const int32_t* alist, const uint32_t* pmask,
+                    int32_t mw, hipStream_t st) {
+  const int32_t nt = ix.n_tiles[ti];
+  if (bf16 && !bvec)
+    hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false, NPCM>), dim3(grid), dim3(256), 0,
+                       st, (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
+                       alist, pmask, mw, ix.tile_blk[ti]);
+  else if (bf16)
+    hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false, NPCM>), dim3(grid), dim3(256), 0,
+                       st, (const void*)ix.Xbt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
+                       alist, pmask, mw, ix.tile_blk[ti]);
+  else if (vec)
+    hipLaunchKernelGGL((rerank_kernel<RT, kF32W, true, false, NPCM>), dim3(grid), dim3(256), 0,
+                       st, (const void*)ix.Xt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
+                       alist, pmask, mw, ix.tile_blk[ti]);
+  else
+    hipLaunchKernelGGL((rerank_kernel<RT, kF32W, false, false, NPCM>), dim3(grid), dim3(256), 0,
+                       st, (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
+                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
+                       alist, pmask, mw, ix.tile_blk[ti]);
+}
+
+// npcm: 16-pair column blocks per pass (1, 2, 4 or 8; 128-row tiles take at
+// most 2, 64-row tiles at most 4).
 template <int RT>
 void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, const int32_t* wl,
                   const Pair* pairs, int32_t c, const float* Q, const __hip_bfloat16* Qb,
@@ -2420,45 +2553,18 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
   // build time), the row-major rows
   const bool vec = (ix.d % 32 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0) && ix.Xt;
   const bool bvec = ix.d % 64 == 0 && ix.Xbt;
-  if (npcm == 1) {
-    if (bf16 && !bvec)
-      hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false, 1>), dim3(grid), dim3(256), 0,
-                         st, (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                         (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                         alist, pmask, mw, ix.tile_blk[ti]);
-    else if (bf16)
-      hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false, 1>), dim3(grid), dim3(256), 0,
-                         st, (const void*)ix.Xbt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                         (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                         alist, pmask, mw, ix.tile_blk[ti]);
-    else if (vec)
-      hipLaunchKernelGGL((rerank_kernel<RT, kF32W, true, false, 1>), dim3(grid), dim3(256), 0,
-                         st, (const void*)ix.Xt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                         (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                         alist, pmask, mw, ix.tile_blk[ti]);
-    else
-      hipLaunchKernelGGL((rerank_kernel<RT, kF32W, false, false, 1>), dim3(grid), dim3(256), 0,
-                         st, (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                         (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                         alist, pmask, mw, ix.tile_blk[ti]);
-    return;
-  }
-  if (bf16 && !bvec)
-    hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false>), dim3(grid), dim3(256), 0, st,
-                       (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw, ix.tile_blk[ti]);
-  else if (bf16)
-    hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false>), dim3(grid), dim3(256), 0, st,
-                       (const void*)ix.Xbt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw, ix.tile_blk[ti]);
-  else if (vec)
-    hipLaunchKernelGGL((rerank_kernel<RT, kF32W, true, false>), dim3(grid), dim3(256), 0, st,
-                       (const void*)ix.Xt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw, ix.tile_blk[ti]);
+#define LIDER_SCORE_ARGS                                                                   \
+  ix, bf16, vec, bvec, grid, ti, cstart, wl, pairs, c, Q, Qb, sbuf, rcap, persistent, ctr, \
+      alist, pmask, mw, st
+  if (npcm == 1)
+    launch_score_n<RT, 1>(LIDER_SCORE_ARGS);
+  else if (npcm == 2 || RT > 64)
+    launch_score_n<RT, 2>(LIDER_SCORE_ARGS);
+  else if (npcm == 4 || RT > 32)
+    launch_score_n<(RT > 64 ? 64 : RT), 4>(LIDER_SCORE_ARGS);
   else
-    hipLaunchKernelGGL((rerank_kernel<RT, kF32W, false, false>), dim3(grid), dim3(256), 0, st,
-                       (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
-                       (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr, alist, pmask, mw, ix.tile_blk[ti]);
+    launch_score_n<32, 8>(LIDER_SCORE_ARGS);
+#undef LIDER_SCORE_ARGS
 }
 
 // Layer-1 window scores: the centroids (layer-1 order) are one "cluster" of C
@@ -2710,12 +2816,10 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
                        np, cstart, cfill, wl);
   }
   mark(3);
-  const int ti = tile_index(ix, o);
+  const int ti = p.ti;
   const int tr = 32 << ti;
   const int gm = o.grid_mult > 0 ? o.grid_mult : 4;
-  // pairs per MFMA pass: up to 32 by default (a tile with at most 16 pairs
-  // still takes the 16-pair pass), 16 on request
-  const int npcm = o.pass_pairs == 16 ? 1 : 2;
+  const int npcm = p.npcm;
   if (o.persistent == 2) {
     const int32_t nt = ix.n_tiles[ti];
     hipLaunchKernelGGL(zero_kernel, dim3(unsigned(std::min<int64_t>((nt + 255) / 256, 4096))),

@@ -85,7 +85,8 @@ def test_mid10_schedules_identical(mid10):
     ref = gi.search(Qd, 10, 8, 256, r1=32)
     for kw in [dict(persistent=True), dict(tile_rows=32), dict(tile_rows=64),
                dict(persistent=2), dict(tile_rows=32, persistent=2, grid_mult=1),
-               dict(pass_pairs=16), dict(pass_pairs=32)]:
+               dict(pass_pairs=16), dict(pass_pairs=32), dict(pass_pairs=64),
+               dict(tile_rows=32, pass_pairs=128)]:
         got = gi.search(Qd, 10, 8, 256, r1=32, **kw)
         assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), kw
     sub = gi.search(Qd[11:50].contiguous(), 10, 8, 256, r1=32)

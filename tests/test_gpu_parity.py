@@ -122,11 +122,37 @@ def test_mid_schedules_identical(mid):
     for kw in [dict(persistent=True), dict(tile_rows=32), dict(tile_rows=128),
                dict(tile_rows=128, persistent=True, grid_mult=1), dict(persistent=2),
                dict(tile_rows=32, persistent=2, grid_mult=1),
-               dict(tile_rows=128, persistent=2, grid_mult=8), dict()]:
+               dict(tile_rows=128, persistent=2, grid_mult=8), dict(pass_pairs=16),
+               dict(pass_pairs=64), dict(pass_pairs=128), dict(tile_rows=32, pass_pairs=64),
+               dict(tile_rows=32, pass_pairs=128), dict(tile_rows=128, pass_pairs=128),
+               dict(tile_rows=32, pass_pairs=128, persistent=2), dict()]:
         got = gi.search(Qd, 10, 8, 256, r1=32, **kw)
         assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), kw
     sub = gi.search(Qd[37:90].contiguous(), 10, 8, 256, r1=32)
     assert torch.equal(sub[0], ref[0][37:90]) and torch.equal(sub[1], ref[1][37:90])
+
+
+def test_mid_many_pairs_per_tile(mid):
+    """Every tile overlapped by hundreds of pairs (3,000 queries, c = 8, whole
+    clusters): the listed pairs of a tile carry over between passes for every
+    pass width and tile size; results are bitwise equal across them and equal
+    the oracle's on a sample."""
+    torch = _torch()
+    X, Q, gi, oi = mid["X"], mid["Q"], mid["gi"], mid["oi"]
+    g = np.random.default_rng(11)
+    Qm = np.concatenate([Q + 0.01 * g.standard_normal(Q.shape) for _ in range(10)]).astype(np.float32)
+    Qd = torch.from_numpy(Qm).cuda()
+    L = int(gi.max_cluster)
+    ref = gi.search(Qd, 10, 8, L, r1=64, pass_pairs=16, tile_rows=32)
+    for tr in (32, 64, 128):
+        for pp in (16, 32, 64, 128):
+            got = gi.search(Qd, 10, 8, L, r1=64, pass_pairs=pp, tile_rows=tr)
+            assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), (tr, pp)
+    got = gi.search(Qd, 10, 8, L, r1=64, pass_pairs=128, tile_rows=32, persistent=1)
+    assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+    sel = np.arange(0, Qm.shape[0], 10)
+    oids, osc = oi.search(Qm[sel], 10, 8, L, 64)
+    compare_topk(X, Qm[sel], ref[0].cpu().numpy()[sel], ref[1].cpu().numpy()[sel], oids, osc)
 
 
 def test_mid_two_streams_identical(mid):
