@@ -77,23 +77,77 @@ def recall_at(torch, X, Q, ids, gt_scores, k, tol=1e-4, chunk=1000):
     return hits / float(ids.shape[0] * k)
 
 
-def union_rows(pairs):
-    """Distinct rows covered by the windows (per cluster union of intervals)."""
-    p = pairs.reshape(-1, 4)
-    p = p[p[:, 0] >= 0]
-    tot = 0
-    order = np.lexsort((p[:, 1], p[:, 0]))
-    p = p[order]
-    cur_j, cur_e = -1, -1
-    for j, s, ln in zip(p[:, 0], p[:, 1], p[:, 2]):
-        e = s + ln
-        if j != cur_j:
-            cur_j, cur_e = j, -1
-        if e <= cur_e:
-            continue
-        tot += e - max(s, cur_e)
-        cur_e = e
-    return int(tot)
+def pair_unions(torch, gi, dbg, c):
+    """Per (query, routed cluster) pair: the number of distinct window rows
+    (the union of its H windows, in the stored corpus order), and the set of
+    distinct rows over all pairs.  Returns (per-pair counts [nq*c] int64 with
+    0 for pads, union row count, hull rows summed over pairs)."""
+    dev = dbg["routed"].device
+    H = gi.H
+    routed = dbg["routed"].reshape(-1).long()
+    pr = dbg["pairs"].reshape(routed.shape[0], H, 3)
+    off = torch.from_numpy(gi.export("offsets")).to(dev)
+    perm = torch.from_numpy(gi.export("perm")).to(dev).reshape(H, -1)
+    n = perm.shape[1]
+    inv0 = torch.empty_like(perm[0])
+    inv0[perm[0]] = torch.arange(n, device=dev)
+    seen = torch.zeros(n, dtype=torch.bool, device=dev)
+    counts = torch.zeros(routed.shape[0], dtype=torch.int64, device=dev)
+    hull = 0
+    valid = torch.nonzero(routed >= 0).reshape(-1)
+    rmax = int(pr[..., 2].max().item()) if valid.numel() else 0
+    ar = torch.arange(max(rmax, 1), device=dev)
+    for a in range(0, valid.numel(), 4096):
+        v = valid[a:a + 4096]
+        j = routed[v]
+        st = pr[v, :, 1]
+        ln = pr[v, :, 2]
+        gpos = off[j][:, None, None] + st[..., None] + ar[None, None, :]  # [P, H, rmax]
+        ok = ar[None, None, :] < ln[..., None]
+        hidx = torch.arange(H, device=dev)[None, :, None].expand_as(gpos)
+        ids = perm[hidx, gpos.clamp(max=n - 1)]
+        p0 = torch.where(ok, inv0[ids], torch.full_like(ids, -1)).reshape(v.numel(), -1)
+        p0s, _ = torch.sort(p0, dim=1)
+        distinct = ((p0s[:, 1:] != p0s[:, :-1]) & (p0s[:, 1:] >= 0)).sum(1) + (p0s[:, 0] >= 0).long()
+        counts[v] = distinct
+        seen[p0s[p0s >= 0]] = True
+        mx = torch.where(p0 >= 0, p0, torch.full_like(p0, -1)).max(1).values
+        mn = torch.where(p0 >= 0, p0, torch.full_like(p0, n)).min(1).values
+        hull += int((mx - mn + 1).clamp(min=0).sum().item())
+    return counts, int(seen.sum().item()), hull
+
+
+def rerank_roofline(torch, gi, Q, k, c, r, r1, rr_ms, **kw):
+    """Roofline of one rerank launch.  Algorithmic bytes = the distinct window
+    rows U times 4d (each row of the union read once); algorithmic flops = 2d
+    per (pair, distinct row of the pair's union).  The bound is whichever of
+    HBM (8 TB/s) and fp32 MFMA (157.3 TFLOP/s) takes longer for these amounts;
+    `achieved` / `frac` are for that bound.  Query and score bytes are
+    reported separately (not part of the algorithmic figure)."""
+    _, _, dbg = gi.search(Q, k, c, r, r1=r1, debug=True, **kw)
+    if gi.H == 1:
+        dbg = dict(routed=dbg["routed"], pairs=dbg["pairs"][:, :, None, :])
+    counts, U, hull = pair_unions(torch, gi, dbg, c)
+    d = gi.d
+    t = rr_ms * 1e-3
+    alg_bytes = U * 4 * d
+    flops = int(counts.sum().item()) * 2 * d
+    pairs_rows = int(counts.sum().item())
+    t_hbm, t_mfma = alg_bytes / 8.0e12, flops / 157.3e12
+    hbm = dict(bound="hbm", achieved=round(alg_bytes / t / 1e9, 1), peak=8000.0, unit="GB/s",
+               frac=round(alg_bytes / t / 8.0e12, 4))
+    mf = dict(bound="mfma", achieved=round(flops / t / 1e12, 2), peak=157.3, unit="TFLOP/s",
+              frac=round(flops / t / 157.3e12, 4))
+    main_b, other = (hbm, mf) if t_hbm >= t_mfma else (mf, hbm)
+    out = dict(main_b)
+    out.update(traffic=None,
+               traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+               kernel="rerank_kernel (fp32 operand-ordered feed, one wave per row tile)",
+               kernel_ms=round(rr_ms, 4), union_rows=U, hull_rows=hull, pair_rows=pairs_rows,
+               algorithmic_bytes=alg_bytes, algorithmic_flops=flops,
+               query_bytes=Q.shape[0] * 4 * d, score_bytes=hull * 4,
+               other_bound={kk: other[kk] for kk in ("bound", "achieved", "peak", "unit", "frac")})
+    return out
 
 
 def main():
@@ -122,6 +176,11 @@ def main():
                     help="queries per arrival rate in the serving workload (default 110,000)")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB fp32 copy kernel (HBM counter calibration)")
+    ap.add_argument("--labels", action="store_true",
+                    help="cluster by the generator's component labels instead of k-means")
+    ap.add_argument("--arrays", type=int, default=0,
+                    help="H hashkey arrays per core model (implies --labels; E2LSH draws of seed 31, "
+                         "the same as the bench line's several-arrays measurements)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -148,8 +207,15 @@ def main():
     torch.cuda.synchronize()
     log(f"data {n}x{d} + {args.nq} queries in {time.time() - t0:.1f}s")
     t0 = time.time()
-    gi = lider.Index(X, C, m, w, F, (A, b), kmeans_init=init, kmeans_iters=20, storage="bf16",
-                     centroid_storage="fp8", seeding="farthest")
+    H = max(1, args.arrays)
+    if args.labels or args.arrays:
+        if args.arrays:
+            A, b = datagen.lsh_params(m, d, w, seed=31, n_arrays=H)
+        gi = lider.Index(X, C, m, w, F, (A, b), assignment=lab, storage="bf16",
+                         centroid_storage="fp8", n_arrays=H)
+    else:
+        gi = lider.Index(X, C, m, w, F, (A, b), kmeans_init=init, kmeans_iters=20, storage="bf16",
+                         centroid_storage="fp8", seeding="farthest")
     torch.cuda.synchronize()
     build_s = time.time() - t0
     log(f"build {build_s:.2f}s, k-means iterations {gi.iters_run}, largest cluster {gi.max_cluster}")
@@ -248,24 +314,12 @@ def main():
     log("stage ms/step: " + ", ".join(f"{s}={v:.3f}" for s, v in stage_avg.items()))
 
     # ---- roofline of the rerank kernel (algorithmic bytes / measured duration)
-    _, _, dbg = gi.search(Q, k, c, r, r1=r1, debug=True)
-    pr = dbg["pairs"].cpu().numpy()
-    routed = dbg["routed"].cpu().numpy()
-    pairs = np.concatenate([routed[..., None], pr[..., 1:3]], axis=-1)
-    pairs = np.concatenate([pairs, np.zeros_like(pairs[..., :1])], axis=-1)
-    U = union_rows(pairs)
-    sum_len = int(pr[..., 2][routed >= 0].sum())
-    alg_bytes = U * d * 4 + args.nq * d * 4 + sum_len * 4
     rr_ms = stage_avg["rerank"]
-    achieved = alg_bytes / (rr_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                "frac": round(achieved / 8000.0, 4), "traffic": measured_traffic(),
-                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": "rerank_kernel (fp32 wide feed, one wave per row tile)",
-                "kernel_ms": round(rr_ms, 4),
-                "union_rows": U, "window_rows": sum_len, "algorithmic_bytes": alg_bytes}
-    log(f"rerank: union rows {U:,}, {alg_bytes / 1e9:.3f} GB algorithmic, {rr_ms:.3f} ms -> "
-        f"{achieved:,.0f} GB/s ({achieved / 8000:.1%} of 8 TB/s)")
+    roofline = rerank_roofline(torch, gi, Q, k, c, r, r1, rr_ms)
+    roofline["traffic"] = measured_traffic() if H == 1 and not args.labels else None
+    log(f"rerank: union rows {roofline['union_rows']:,}, {rr_ms:.3f} ms -> "
+        f"{roofline['achieved']:,.1f} {roofline['unit']} ({roofline['frac']:.1%} of peak, "
+        f"bound {roofline['bound']})")
 
     extra = {}
     if args.calib:
@@ -328,8 +382,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"gaussian-mixture N={n} d={d} fp32, {C} k-means clusters, "
-                               f"m={m} w={w} rmi_fanout={F}, {args.nq} queries (noise 0.1)",
+        "config": {"workload": f"gaussian-mixture N={n} d={d} fp32, {C} "
+                               + ("clusters = the generator's labels" if args.labels or args.arrays
+                                  else "k-means clusters")
+                               + (f", H={H} hashkey arrays" if H > 1 else "")
+                               + f", m={m} w={w} rmi_fanout={F}, {args.nq} queries (noise 0.1)",
                    "global_batch": args.nq, "k": k, "c": c, "r": r, "r1": r1,
                    "recall10": round(rec, 4), "parallelism": "single-gpu", "streams": nst},
         f"qps_{alt_nst}_stream{'s' if alt_nst > 1 else ''}": round(alt_qps) if alt_qps else None,
@@ -466,6 +523,10 @@ def arrays_variant(args, torch, datagen, lider, X, lab, Q, C, F, log, gt_sc, H_l
             rec = recall_at(torch, X, Q, ids, gt_sc, 10)
             res[name] = dict(c=c, r=r, r1=r1, qps=round(Q.shape[0] / dt), recall10=round(rec, 4),
                              stage_ms={s: round(v / calls, 4) for s, v in stages.items()})
+            rl = rerank_roofline(torch, gi, Q, 10, c, r, r1, stages["rerank"] / calls)
+            res[name]["roofline"] = {kk: rl[kk] for kk in ("bound", "achieved", "unit", "frac",
+                                                          "union_rows", "hull_rows", "pair_rows",
+                                                          "other_bound")}
             log(f"arrays H={H} {name}: {Q.shape[0] / dt:,.0f} q/s, recall@10 {rec:.4f}, "
                 + ", ".join(f"{s}={v / calls:.3f}" for s, v in stages.items()))
         out[f"H{H}"] = res
