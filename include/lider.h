@@ -279,6 +279,25 @@ int lider_search_ex(const lider_index* index, const float* queries_dev, int64_t 
                     size_t ws_bytes, void* stream, const lider_search_opts* opts,
                     const lider_search_debug* debug);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the search of
+ * lider_search_ex (same arguments, results bit-identical) with its workspace in
+ * a fixed array inside the library instead of a caller's buffer.  No
+ * allocation of any kind, no synchronisation.  The array holds
+ * lider_noalloc_scratch_bytes() bytes (64 MiB) on every GPU the library runs
+ * on, until the process ends; a batch whose lider_search_workspace exceeds it
+ * is rejected with LIDER_EINVAL before anything is enqueued.  Every call on a
+ * GPU uses that GPU's one array: calls that overlap on one GPU (on different
+ * streams, or from several threads without ordering) race and are not
+ * allowed; consecutive calls on one stream are fine.  The first call on a
+ * device resolves the array's device address (once per device). */
+int lider_search_noalloc(const lider_index* index, const float* queries_dev, int64_t nq,
+                         int32_t k, int32_t c, int32_t r, int64_t* ids_dev, float* scores_dev,
+                         void* stream, const lider_search_opts* opts);
+
+/* Size in bytes of lider_search_noalloc's fixed workspace. */
+size_t lider_noalloc_scratch_bytes(void);
+
 /* ---------------------------------------------------------------- inspection */
 
 typedef struct {

@@ -2,6 +2,7 @@
 // lifetime, build orchestration, search dispatch, exports and error state.
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <unordered_map>
 
@@ -477,6 +478,65 @@ int lider_search(const lider_index* index, const float* queries_dev, int64_t nq,
                  size_t ws_bytes, void* stream) {
   return lider_search_ex(index, queries_dev, nq, k, c, r, ids_dev, scores_dev, ws_dev, ws_bytes,
                          stream, nullptr, nullptr);
+}
+
+// --------------------------------------------------- allocation-free search
+// lider_search_noalloc's workspace: one array in the library's code object,
+// which every GPU the library runs on holds until the process ends.  Host
+// code reaches it only through the device address hipGetSymbolAddress
+// returns for the current device (the array's name is a host-side stand-in).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch`, per device
+
+int scratch_address(void** out) {
+  *out = nullptr;
+  int dev = 0;
+  const int grc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (grc != LIDER_OK) return grc;
+  if (dev < 0 || dev >= kMaxDevices) return set_error(LIDER_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return set_error(LIDER_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                          hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return LIDER_OK;
+}
+}  // namespace
+
+size_t lider_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+int lider_search_noalloc(const lider_index* index, const float* queries_dev, int64_t nq,
+                         int32_t k, int32_t c, int32_t r, int64_t* ids_dev, float* scores_dev,
+                         void* stream, const lider_search_opts* opts) {
+  g_err.clear();
+  lider_search_opts o;
+  std::memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  int rc = validate_search(index, queries_dev, nq, k, c, r, o);
+  if (rc != LIDER_OK) return rc;
+  if (nq == 0) return LIDER_OK;
+  const size_t need = lider_search_workspace(index, nq, k, c, r, &o);
+  if (need > kNoAllocScratchBytes)
+    return set_error(LIDER_EINVAL, "batch needs " + std::to_string(need) +
+                                       " bytes of workspace, more than the " +
+                                       std::to_string(kNoAllocScratchBytes) +
+                                       "-byte scratch of lider_search_noalloc (use lider_search "
+                                       "with a workspace, or a smaller batch)");
+  void* ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc != LIDER_OK) return rc;
+  return lider_search_ex(index, queries_dev, nq, k, c, r, ids_dev, scores_dev, ws,
+                         kNoAllocScratchBytes, stream, &o, nullptr);
 }
 
 // ------------------------------------------------------------------ exports

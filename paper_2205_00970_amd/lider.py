@@ -68,7 +68,7 @@ SYMBOLS = ["lider_build", "lider_free", "lider_last_error", "lider_search_worksp
            "lider_search", "lider_search_ex", "lider_get_info", "lider_export_bytes",
            "lider_export", "lider_hash", "lider_kmeans_assign", "lider_profile_begin",
            "lider_profile_end", "lider_debug_fail_next", "lider_save", "lider_load",
-           "lider_draw_params"]
+           "lider_draw_params", "lider_search_noalloc", "lider_noalloc_scratch_bytes"]
 NSTAGES = 5
 STAGES = ["hash", "route", "worklist", "rerank", "select"]
 
@@ -106,6 +106,10 @@ def lib():
         L.lider_load.argtypes = [C.c_char_p, p, C.POINTER(p)]
         L.lider_draw_params.argtypes = [C.c_uint64, i32, i32, i32, C.c_double, i32, p, p, i64,
                                         i32, p]
+        L.lider_search_noalloc.argtypes = [p, p, i64, i32, i32, i32, p, p, p,
+                                           C.POINTER(SearchOpts)]
+        L.lider_noalloc_scratch_bytes.argtypes = []
+        L.lider_noalloc_scratch_bytes.restype = sz
         _lib = L
     return _lib
 
@@ -312,6 +316,24 @@ def draw_params(seed, m, d, w, n_arrays=1, hash_kind="e2lsh", n=0, n_rows=0):
                                    float(w), {"e2lsh": 0, "sign": 1}[hash_kind], _np_ptr(A),
                                    _np_ptr(b), int(n), int(n_rows), _np_ptr(rows)))
     return A, b, rows
+
+
+def noalloc_scratch_bytes():
+    """Size of lider_search_noalloc's fixed workspace."""
+    return int(lib().lider_noalloc_scratch_bytes())
+
+
+def search_noalloc(index, queries, k, c, r, out, stream=None, **opts):
+    """lider_search_noalloc: the search with the library's fixed workspace
+    (no allocation).  `out` = (ids int64 [nq,k], scores f32 [nq,k]) tensors."""
+    torch = _torch()
+    qp = _dev_ptr(queries, torch.float32, 2, "queries")
+    ids, sc = out
+    o = Index._opts(**opts)
+    _check(lib().lider_search_noalloc(index._h, qp, queries.shape[0], k, c, r,
+                                      _dev_ptr(ids, torch.int64, 2, "ids"),
+                                      _dev_ptr(sc, torch.float32, 2, "scores"), _stream(stream),
+                                      C.byref(o)))
 
 
 def hash(X, A, b, w, stream=None):
