@@ -177,13 +177,20 @@ const char* lider_last_error(void);
  *                 centroids retriever's predicted location.
  *  precision      LIDER_F32: exact fp32 rerank of every window row.
  *                 LIDER_BF16: precision form -- bf16 first pass over the
- *                 windows (needs storage = LIDER_BF16), shortlist of
- *                 shortlist_mult*k per query, fp32 rerank of the shortlist from
- *                 the fp32 copy; routing is exact as in LIDER_F32, except with
- *                 l1_dense = -1 on an index with fp8 centroids, where the
- *                 window kernel scores the fp8 copy and the best scores route
- *                 (approximate).
- *  shortlist_mult shortlist length per query in units of k (0 = 4).
+ *                 windows (needs storage = LIDER_BF16), a shortlist per query,
+ *                 fp32 rerank of the shortlist from the fp32 copy.  Routing is
+ *                 exact as in LIDER_F32; with l1_dense = -1 on an index with
+ *                 fp8 centroids the window kernel scores the fp8 copy, and the
+ *                 routed set is decided from those scores with the fp8 error
+ *                 bound (FP64 rescoring inside it), like the bf16 scores.
+ *  shortlist_mult 0: certified shortlist -- every candidate whose bf16 score
+ *                 is at least the k-th best bf16 score minus twice the bf16
+ *                 error bound of the query (|q - bf16(q)| max|x| +
+ *                 |bf16(q)| max|x - bf16(x)| + 2 d 2^-24 |bf16(q)| max|bf16(x)|,
+ *                 the maxima over the index's rows): it contains the exact
+ *                 top k, so the result is the fp32 top k of all candidates;
+ *                 its length adapts per query (up to all candidates).
+ *                 m > 0: the m*k best bf16 scores (m*k <= 4096; approximate).
  *  persistent     0: one wave per row tile of the whole index (tiles no window
  *                 touches exit at once).  1: a persistent grid whose waves pull
  *                 the index's tiles from per-XCD counters.  2: the tiles some

@@ -380,7 +380,7 @@ static int validate_search(const lider_index* index, const float* Q, int64_t nq,
     return set_error(LIDER_EINVAL, "precision LIDER_BF16 needs an index built with storage BF16");
   if (o.precision == LIDER_BF16 && (ix.d % 8 != 0))
     return set_error(LIDER_EINVAL, "precision LIDER_BF16 needs d divisible by 8");
-  if (o.shortlist_mult < 0 || (o.precision == LIDER_BF16 && int64_t(o.shortlist_mult > 0 ? o.shortlist_mult : 4) * k > 4096))
+  if (o.shortlist_mult < 0 || (o.precision == LIDER_BF16 && int64_t(o.shortlist_mult) * k > 4096))
     return set_error(LIDER_EINVAL, "shortlist_mult * k must be at most 4096");
   if (o.tile_rows != 0 && o.tile_rows != 32 && o.tile_rows != 64 && o.tile_rows != 128)
     return set_error(LIDER_EINVAL, "tile_rows must be 0, 32, 64 or 128");

@@ -11,6 +11,8 @@
 
 #include <algorithm>
 
+#include <cstring>
+
 #include "lider_internal.hpp"
 
 namespace lider {
@@ -390,6 +392,38 @@ __global__ void cent_norm_max_kernel(const float* __restrict__ cent, int32_t C, 
   if (lane == 0) atomicMax(maxbits, __float_as_uint(float(sqrt(s) * (1.0 + 9.5367431640625e-07))));
 }
 
+// Precision form: per row, |x|, |x - bf16(x)| and |bf16(x)| (bf16 rounded to
+// nearest even like the corpus copy) from FP64 sums of squares, and their
+// maxima over the rows as fp32 upper bounds (the squares are exact, the
+// factor 1 + 2^-20 covers the sums' and the conversion's roundings).
+__global__ void bf16_bounds_kernel(const float* __restrict__ X, int64_t n, int32_t d,
+                                   uint32_t* __restrict__ maxbits) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); r < n;
+       r += int64_t(gridDim.x) * 4) {
+    double sx = 0.0, sr = 0.0, sb = 0.0;
+    for (int l = lane; l < d; l += 64) {
+      const float v = X[r * d + l];
+      const double b = double(__bfloat162float(__float2bfloat16(v)));
+      const double e = double(v) - b;
+      sx += double(v) * double(v);
+      sr += e * e;
+      sb += b * b;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      sx += __shfl_xor(sx, o);
+      sr += __shfl_xor(sr, o);
+      sb += __shfl_xor(sb, o);
+    }
+    if (lane == 0) {
+      const double up = 1.0 + 9.5367431640625e-07;
+      atomicMax(&maxbits[0], __float_as_uint(float(sqrt(sx) * up)));
+      atomicMax(&maxbits[1], __float_as_uint(float(sqrt(sr) * up)));
+      atomicMax(&maxbits[2], __float_as_uint(float(sqrt(sb) * up)));
+    }
+  }
+}
+
 // Position maps between hashkey arrays: inv[perm0[p]] = p, then
 // map[p] = inv[permh[p]] (array h's sorted position -> array 0's).
 __global__ void inverse_kernel(const int64_t* __restrict__ perm, int64_t n,
@@ -576,6 +610,22 @@ int finish_index(Index& ix) {
     if (rc == LIDER_OK) rc = check_hip(hipDeviceSynchronize(), "operand-ordered corpus");
     (void)hipFree(dsrc);
     if (rc != LIDER_OK) return rc;
+  }
+  if (ix.Xb) {  // bounds of the precision form's certified shortlist
+    uint32_t* mb = nullptr;
+    uint32_t hb[4] = {0u, 0u, 0u, 0u};
+    if (hipMalloc(&mb, 256) != hipSuccess)
+      return set_error(LIDER_ENOMEM, "out of device memory (bf16 bounds)");
+    rc = check_hip(hipMemcpy(mb, hb, 16, hipMemcpyHostToDevice), "bf16 bounds");
+    if (rc == LIDER_OK) {
+      hipLaunchKernelGGL(bf16_bounds_kernel, dim3(unsigned(std::min<int64_t>((ix.n + 3) / 4, 65536))),
+                         dim3(256), 0, nullptr, ix.X, ix.n, ix.d, mb);
+      rc = check_hip(hipGetLastError(), "bf16 bounds");
+    }
+    if (rc == LIDER_OK) rc = check_hip(hipMemcpy(hb, mb, 16, hipMemcpyDeviceToHost), "bf16 bounds");
+    (void)hipFree(mb);
+    if (rc != LIDER_OK) return rc;
+    for (int i = 0; i < 3; ++i) std::memcpy(&ix.xb_bound[i], &hb[i], 4);
   }
   // rerank tile tables for 32/64/128-row tiles, 4 int32 per tile: cluster,
   // first in-cluster row, first row in the reordered corpus, rows in the tile;

@@ -231,6 +231,9 @@ struct Index {
   float* b = nullptr;          // [2Hm]
   float* anorm = nullptr;      // [2Hm] upper bounds of |A_i|
   float* cent_norm_max = nullptr;  // [1] upper bound of max |centroid|
+  // precision form (bf16 copy): upper bounds over the rows of max |x|,
+  // max |x - bf16(x)| and max |bf16(x)| (host copies)
+  float xb_bound[3] = {0.f, 0.f, 0.f};
   Model* models = nullptr;     // [H x (C+1)], model h*(C+1) + C = array h of layer 1
   double* leaves = nullptr;    // [H x (C*F2 + F1) x 2]
   int32_t* leaf_err = nullptr; // [H x (C*F2 + F1) x 2]

@@ -50,6 +50,8 @@ struct Plan {
       o_rw, o_pw, o_mask, o_rcand, o_rcnt, total;
   int32_t r1, rcap, S;
   int ti, npcm;  // rerank tile table and 16-pair blocks per pass
+  bool cert;     // precision form with the certified shortlist
+  size_t o_scnt;
   // l1_dense_rows: layer-1 scores of every centroid (dense product), else of
   // the r1-windows (window kernel).  Several hashkey arrays: lcap = layer-1
   // union capacity per query (list mode when r1 < C), mw = mask words per
@@ -95,8 +97,10 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   // over two lines: 1.6x the score bytes reached HBM).
   const int32_t rcap = int32_t((std::max<int64_t>(
       1, H > 1 ? ix.max_cluster : std::min<int64_t>(r, ix.max_cluster)) + 31) / 32 * 32);
-  const int32_t mult = o.shortlist_mult > 0 ? o.shortlist_mult : 4;
-  const int32_t S = o.precision == LIDER_BF16 ? std::min(4096, mult * k) : 0;
+  // precision form: shortlist_mult 0 lists a certified shortlist (up to every
+  // candidate of the query), > 0 the best shortlist_mult * k bf16 scores
+  const bool cert = o.precision == LIDER_BF16 && o.shortlist_mult == 0;
+  const int32_t S = o.precision == LIDER_BF16 && !cert ? std::min(4096, o.shortlist_mult * k) : 0;
   p.l1_list = H > 1 && r1 < ix.C;
   p.l1_dense_rows = H > 1 || o.l1_dense >= 0;
   p.lcap = p.l1_list ? int32_t(std::min<int64_t>(ix.C, int64_t(H) * r1)) : r1;
@@ -129,8 +133,10 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   p.o_cfill = take(size_t(ix.C) * 4);
   p.o_wl = take(size_t(nq) * c * 4);
   p.o_sbuf = take(size_t(nq) * c * rcap * 4);
-  p.o_qb = take((S || ix.cent8 || ix.cent_l1_b) ? size_t(nq) * ix.d * 2 : 0);
-  p.o_slist = take(S ? size_t(nq) * S * 4 : 0);
+  p.o_qb = take((S || cert || ix.cent8 || ix.cent_l1_b) ? size_t(nq) * ix.d * 2 : 0);
+  p.cert = cert;
+  p.o_slist = take(cert ? size_t(nq) * c * rcap * 4 : S ? size_t(nq) * S * 4 : 0);
+  p.o_scnt = take(cert ? size_t(nq) * 4 : 0);
   rerank_shape(ix, nq, c, r, o, &p.ti, &p.npcm);
   const size_t nt = o.persistent == 2 ? size_t(ix.n_tiles[p.ti]) : 0;
   p.o_aflag = take(nt * 4);
@@ -331,6 +337,57 @@ __host__ __device__ inline int pow2_at_least(int v) {
   return p;
 }
 
+// Precision form, certified shortlist.  The bf16 window score s~ of row x for
+// query q differs from the exact inner product q.x by at most
+//   E = |q - bf16(q)| |x| + |bf16(q)| |x - bf16(x)| + 2 g_d |bf16(q)| |bf16(x)|
+// (q.x - bq.bx = (q - bq).x + bq.(x - bx), each term bounded by
+// Cauchy-Schwarz; the products of bf16 values are exact in fp32 and g_d =
+// d u / (1 - d u), u = 2^-24, bounds their fp32 accumulation in any order,
+// doubled to cover the accumulator's rounding mode).  The index keeps
+// Xmax >= |x|, Xres >= |x - bf16(x)| and XBmax >= |bf16(x)| over its rows, so
+// E_q bounds every row of query q.  A row of the exact top k then has
+// s~ >= T - 2 E_q, with T the k-th best s~ (at least k rows have
+// s~ >= T, so the k-th best exact score is >= T - E_q): listing every
+// candidate above that threshold and reranking the list in fp32 returns the
+// fp32 top k of all candidates.
+struct CertArgs {
+  const float* Q = nullptr;
+  const __hip_bfloat16* Qb = nullptr;
+  int32_t d = 0;
+  float xmax = 0.f, xres = 0.f, xbmax = 0.f;
+  int32_t* scnt = nullptr;  // [nq] rows listed per query
+  int64_t cap = 0;          // list entries per query (all its candidates)
+};
+
+// Wave-wide (64 active lanes): the largest key (lowest score) still listed,
+// from the k-th best key T; T = 0xffffffff (fewer than k candidates) lists
+// every candidate.
+__device__ uint32_t cert_threshold(const CertArgs& ca, int64_t q, uint32_t T, int lane) {
+  double sr = 0.0, sb = 0.0;
+  const float* qv = ca.Q + q * ca.d;
+  const __hip_bfloat16* qb = ca.Qb + q * ca.d;
+  for (int l = lane; l < ca.d; l += 64) {
+    const double b = double(__bfloat162float(qb[l]));
+    const double r = double(qv[l]) - b;  // exact
+    sr += r * r;
+    sb += b * b;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sr += __shfl_xor(sr, o);
+    sb += __shfl_xor(sb, o);
+  }
+  if (T == 0xffffffffu) return 0xfffffffeu;
+  const double up = 1.0 + 0x1p-20;  // covers the roundings of this bound's own arithmetic
+  const double qres = sqrt(sr) * up, qbn = sqrt(sb) * up;
+  const double du = double(ca.d) * 0x1p-24;
+  const double gam = 2.0 * du / (1.0 - du);
+  const double E = (qres * double(ca.xmax) + qbn * double(ca.xres) + gam * qbn * double(ca.xbmax)) * up;
+  const double thr = double(key_score(T)) - 2.0 * E;
+  float f = float(thr);
+  if (double(f) > thr) f = nextafterf(f, -INFINITY);
+  return score_key(f);
+}
+
 // ------------------------------------------------------------ layer 1
 // Centroids retriever: location and window of every query; the window is also
 // written as a (cluster 0, start, length) pair so the tile-scoring kernel can
@@ -428,8 +485,6 @@ __global__ __launch_bounds__(256) void l1_union_kernel(
   }
 }
 
-constexpr int kRouteNT = 256;
-
 // Minimum over the 64 lanes of a wave (all lanes active), on DPP: inclusive
 // prefix minima within each row of 16 (row_shr 1, 2, 4, 8; a lane whose
 // source lies before its row keeps its own value), then row_bcast:15 and
@@ -516,43 +571,6 @@ __device__ __attribute__((noinline)) void route_fp64_wave(const float* __restric
       out[t] = bp >= 0 ? bi : -1;
       if (bp >= 0) r64[bp] = -INFINITY;
     }
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-  }
-}
-
-// Approximate routing of the precision form (fp8 centroid scores, no exact
-// decision), one wave per query (c <= 64): the c best window scores by
-// repeated wave minima of (key, window entry).  Window entries and score
-// addressing as in route_filter_kernel.
-__global__ __launch_bounds__(256) void route_approx_wave_kernel(
-    int64_t nq, const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
-    int32_t wst, const int32_t* __restrict__ lst, int32_t lcap, const float* __restrict__ rs,
-    int32_t rstride, int dense, int32_t c, int32_t* __restrict__ routed) {
-  __shared__ uint64_t ext[4][64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
-    const int32_t s1 = l1[wst * q + 1], len1 = l1[wst * q + 2];
-    const int32_t* lq = lst ? lst + q * lcap : nullptr;
-    const float* rsq = rs + q * rstride;
-    auto pos_of = [&](int p) { return lq ? lq[p] : s1 + p; };
-    const int want = min(len1, c);
-    uint64_t prev = 0;
-    for (int t = 0; t < want; ++t) {
-      uint64_t best = ~uint64_t(0);
-      for (int p = lane; p < len1; p += 64) {
-        const uint64_t v = (uint64_t(score_key(rsq[dense ? pos_of(p) : p])) << 32) | uint32_t(p);
-        if ((t == 0 || v > prev) && v < best) best = v;
-      }
-      best = wave_min_u64(best);
-      if (lane == 0) ext[wave][t] = best;
-      prev = best;
-    }
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-    for (int t = lane; t < c; t += 64)
-      routed[q * c + t] =
-          t < want ? l1_order32[pos_of(int32_t(ext[wave][t] & 0xffffffffu))] : -1;
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
   }
@@ -835,31 +853,6 @@ __global__ __launch_bounds__(256) void route_rescore_kernel(
   }
 }
 
-// Approximate routing of the precision form for c > 64, one workgroup per
-// query: radix selection of the c best window scores.
-__global__ __launch_bounds__(kRouteNT) void route_approx_block_kernel(
-    int64_t nq, const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1,
-    int32_t wst, const int32_t* __restrict__ lst, int32_t lcap, const float* __restrict__ rs,
-    int32_t rstride, int dense, int32_t c, int32_t* __restrict__ routed) {
-  __shared__ SelShared sh;
-  __shared__ uint64_t srt[256];
-  __shared__ int32_t sidx[256];
-  const int tid = threadIdx.x;
-  for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
-    const int32_t s1 = l1[wst * q + 1], len1 = l1[wst * q + 2];
-    const int32_t* lq = lst ? lst + q * lcap : nullptr;
-    const float* rsq = rs + q * rstride;
-    auto pos_of = [&](int i) { return lq ? lq[i] : s1 + i; };
-    const int K = min(c, len1);
-    const int KP = pow2_at_least(K);
-    block_select<kRouteNT>(
-        len1, K, KP, [&](int i) { return score_key(rsq[dense ? pos_of(i) : i]); },
-        [&](int i) { return uint32_t(l1_order32[pos_of(i)]); }, srt, sidx, sh);
-    for (int t = tid; t < c; t += kRouteNT)
-      routed[q * c + t] = t < K ? int32_t(srt[t] & 0xffffffffu) : -1;
-    __syncthreads();
-  }
-}
 
 // ------------------------------------------------------------ layer 2 pairs
 // One thread per (query, routed cluster) pair t.  One array: pairs[t] is the
@@ -1943,11 +1936,13 @@ __global__ __launch_bounds__(kSelNT) void select_kernel(
     const Pair* __restrict__ pairs, const float* __restrict__ sbuf, int32_t rcap, int32_t c,
     int64_t nq, int32_t K, const int64_t* __restrict__ off, const int32_t* __restrict__ perm32,
     int64_t* __restrict__ ids, float* __restrict__ scores, int32_t kout,
-    int32_t* __restrict__ slist, int drop) {
+    int32_t* __restrict__ slist, int drop, CertArgs ca) {
   __shared__ SelShared sh;
   __shared__ uint64_t srt[KPMAX];
   __shared__ int32_t sidx[KPMAX];
   __shared__ uint32_t keys[kKeyCache];
+  __shared__ uint32_t s_thr;
+  __shared__ int32_t s_m;
   __shared__ int32_t start[LIDER_MAX_C + 1];
   __shared__ int32_t pj[LIDER_MAX_C], ps[LIDER_MAX_C];
   const int tid = threadIdx.x;
@@ -2011,9 +2006,27 @@ __global__ __launch_bounds__(kSelNT) void select_kernel(
           scores[q * kout + t] = -INFINITY;
         }
       }
-    } else {
+    } else if (MODE == 1) {
       for (int t = tid; t < K; t += kSelNT)
         slist[q * K + t] = valid(t) ? int32_t(row_of(sidx[t])) : -1;
+    } else {
+      // certified shortlist: every candidate within the margin of the k-th
+      // best (list order is immaterial: the fp32 rerank ranks by score, id)
+      if (tid < 64) {
+        const uint32_t T = valid(K - 1) ? uint32_t(srt[K - 1] >> 32) : 0xffffffffu;
+        const uint32_t thr = cert_threshold(ca, q, T, tid);
+        if (tid == 0) {
+          s_thr = thr;
+          s_m = 0;
+        }
+      }
+      __syncthreads();
+      const uint32_t thr = s_thr;
+      for (int i = tid; i < n; i += kSelNT) {
+        if (key_of(i) <= thr) slist[q * ca.cap + atomicAdd(&s_m, 1)] = int32_t(row_of(i));
+      }
+      __syncthreads();
+      if (tid == 0) ca.scnt[q] = s_m;
     }
     __syncthreads();
   }
@@ -2033,7 +2046,7 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
     const Pair* __restrict__ pairs, const float* __restrict__ sbuf, int32_t rcap, int32_t c,
     int64_t nq, int32_t K, const int64_t* __restrict__ off, const int32_t* __restrict__ perm32,
     int64_t* __restrict__ ids, float* __restrict__ scores, int32_t kout,
-    int32_t* __restrict__ slist, int drop) {
+    int32_t* __restrict__ slist, int drop, CertArgs ca) {
   __shared__ uint32_t keys[4][R == 0 ? kWaveKeyCache : 1];
   __shared__ int32_t start[4][LIDER_MAX_C + 1];
   __shared__ int64_t pbase[4][LIDER_MAX_C];  // sorted row of each slot's first candidate
@@ -2314,9 +2327,23 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
         ids[q * kout + t] = -1;
         scores[q * kout + t] = -INFINITY;
       }
-    } else {
+    } else if (MODE == 1) {
       if (lane < got) slist[q * K + rank] = int32_t(myrow);
       for (int t = got + lane; t < K; t += 64) slist[q * K + t] = -1;
+    } else {
+      // certified shortlist: every candidate within the margin of the k-th
+      // best key (the largest winner key when all K places are taken)
+      uint32_t tk = lane < got ? myk : 0u;
+      for (int o = 32; o > 0; o >>= 1) tk = max(tk, uint32_t(__shfl_xor(tk, o)));
+      const uint32_t thr = cert_threshold(ca, q, got == K ? tk : 0xffffffffu, lane);
+      int m = 0;
+      scan([&](int32_t i, uint32_t kk, bool ok) {
+        const bool in = ok && kk <= thr;
+        const uint64_t bal = __ballot(in);
+        if (in) slist[q * ca.cap + m + __popcll(bal & below)] = int32_t(row_of(i));
+        m += __popcll(bal);
+      });
+      if (lane == 0) ca.scnt[q] = m;
     }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
@@ -2452,6 +2479,80 @@ __global__ __launch_bounds__(256) void wave_shortlist_kernel(
   }
 }
 
+// Precision form, certified second pass: exact fp32 inner products of every
+// listed row (from the fp32 copy) and the top k by (score desc, id asc).  One
+// workgroup per query; the list is taken in chunks of kCertChunk rows, each
+// merged with the best k so far.  16 lanes per row (float4 slots when d % 4
+// == 0 and the rows are 16-byte aligned, else scalar), reduced over the 16
+// lanes by a fixed xor tree.
+constexpr int kCertChunk = 1024;
+
+template <int KPMAX>
+__global__ __launch_bounds__(kSelNT) void cert_rerank_kernel(
+    const float* __restrict__ X, int32_t d, const float* __restrict__ Q, int64_t nq,
+    const int32_t* __restrict__ slist, int64_t cap, const int32_t* __restrict__ scnt,
+    const int32_t* __restrict__ perm32, int32_t k, int vec, int64_t* __restrict__ ids,
+    float* __restrict__ scores) {
+  __shared__ SelShared sh;
+  __shared__ uint64_t srt[KPMAX];
+  __shared__ int32_t sidx[KPMAX];
+  __shared__ uint64_t best[KPMAX];
+  __shared__ float sc[kCertChunk];
+  __shared__ int32_t rows[kCertChunk];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int KP = pow2_at_least(k);
+  for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    const int32_t n = scnt[q];
+    const float* qv = Q + q * d;
+    int nb = 0;
+    for (int32_t c0 = 0; c0 < n; c0 += kCertChunk) {
+      const int m = min(kCertChunk, n - c0);
+      for (int t = tid; t < m; t += kSelNT) rows[t] = slist[q * cap + c0 + t];
+      __syncthreads();
+      for (int t0 = 4 * wave; t0 < m; t0 += 4 * (kSelNT / 64)) {
+        const int t = t0 + g;
+        const float* xr = X + int64_t(rows[min(t, m - 1)]) * d;
+        float acc = 0.f;
+        if (vec) {
+          for (int l = 4 * c16; l < d; l += 64) {
+            const float4 v = *reinterpret_cast<const float4*>(xr + l);
+            const float4 w = *reinterpret_cast<const float4*>(qv + l);
+            acc += v.x * w.x;
+            acc += v.y * w.y;
+            acc += v.z * w.z;
+            acc += v.w * w.w;
+          }
+        } else {
+          for (int l = c16; l < d; l += 16) acc += xr[l] * qv[l];
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (c16 == 0 && t < m) sc[t] = acc;
+      }
+      __syncthreads();
+      const int got = block_select<kSelNT>(
+          m + nb, k, KP,
+          [&](int i) { return i < m ? score_key(sc[i]) : uint32_t(best[i - m] >> 32); },
+          [&](int i) { return i < m ? uint32_t(perm32[rows[i]]) : uint32_t(best[i - m]); }, srt,
+          sidx, sh);
+      for (int t = tid; t < got; t += kSelNT) best[t] = srt[t];
+      nb = got;
+      __syncthreads();
+    }
+    for (int t = tid; t < k; t += kSelNT) {
+      if (t < nb) {
+        ids[q * k + t] = int64_t(best[t] & 0xffffffffu);
+        scores[q * k + t] = key_score(uint32_t(best[t] >> 32));
+      } else {
+        ids[q * k + t] = -1;
+        scores[q * k + t] = -INFINITY;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------ debug exports
 __global__ void debug_kernel(const int32_t* __restrict__ l1, const Pair* __restrict__ pairs,
                              const Pair* __restrict__ pw, int32_t H,
@@ -2480,30 +2581,30 @@ template <int MODE>
 void launch_wave_select(hipStream_t st, const Pair* pairs, const float* sbuf, int32_t rcap,
                         int32_t c, int64_t nq, int32_t K, const int64_t* off,
                         const int32_t* perm32, int64_t* ids, float* scores, int32_t kout,
-                        int32_t* slist, int drop) {
+                        int32_t* slist, int drop, CertArgs ca = CertArgs()) {
   const int64_t nmax = int64_t(c) * rcap;
   const unsigned wgrid = unsigned((nq + 3) / 4);  // one wave per query (nq < 2^31)
   if (nmax <= 512)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 8>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
   else if (nmax <= 1024)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 16>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
   else if (nmax <= 1280)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 20>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
   else if (nmax <= 2048)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 32>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
   else if (nmax <= 4096)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 64>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
   else if (nmax <= 6144)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 96>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
   else
     hipLaunchKernelGGL((wave_select_kernel<MODE, 0>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
 }
 
 template <int RT, int NPCM>
@@ -2762,6 +2863,16 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   double ecoef = dot_err_coef(ix.d);  // fp32 scores
   if (!p.l1_dense_rows) {
     launch_l1_scores(ix, fp8, nq, l1cs, l1pairs, Q, qb, rs, p.r1, st);
+    if (fp8) {
+      // s (bq . e) with e the fp8 codes of mu / s: |q - bq| <= ub |q|;
+      // |mu - s e| <= (u8 + 2^-22) |mu| + 2^-10 s sqrt(d) (normal / subnormal
+      // codes, s = max|mu_l| / 448, the division's rounding); fp32
+      // accumulation of the exact products and the final scaling
+      const double ub = 0.00390625, u8 = 0.0625;
+      const double sub = 0.0009765625 * std::sqrt(double(ix.d)) / 448.0;
+      ecoef = (ub + (1.0 + ub) * (u8 + 2.384185791015625e-07 + sub) +
+               1.1 * dot_err_coef(ix.d) * (1.0 + ub) + 2.0 * 5.9604644775390625e-08) * 1.01;
+    }
   } else if (l1b) {
     if (!l1_fused) launch_l1_gemm_bf16(ix, nq, qb, rs, st);
     const double u = 0.00390625;  // 2^-8: bf16 rounding of each operand
@@ -2771,14 +2882,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   }
   const int32_t rstride = p.l1_dense_rows ? C : p.r1;
   const int dense = p.l1_dense_rows ? 1 : 0;
-  if (fp8) {
-    if (c <= 64)
-      hipLaunchKernelGGL(route_approx_wave_kernel, dim3(wgrid), dim3(256), 0, st, nq,
-                         ix.l1_order32, l1w, wst, lstp, p.lcap, rs, rstride, dense, c, routed);
-    else
-      hipLaunchKernelGGL(route_approx_block_kernel, dim3(qgrid), dim3(kRouteNT), 0, st, nq,
-                         ix.l1_order32, l1w, wst, lstp, p.lcap, rs, rstride, dense, c, routed);
-  } else {
+  {
     // every window is the whole dense row when r1 >= C with a single window per query
     const int whole = dense && !lstp && p.r1 >= C && o.expand_bits == 0;
     const unsigned fgrid = unsigned((nq + 3) / 4);  // one wave per query (nq < 2^31)
@@ -2843,20 +2947,48 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
                             scores, k, slist, int(H > 1));
     else if (k <= 128)
       hipLaunchKernelGGL((select_kernel<128, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1));
+                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), CertArgs());
     else
       hipLaunchKernelGGL((select_kernel<1024, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1));
+                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), CertArgs());
+  } else if (p.cert) {
+    // certified shortlist (every candidate within the bf16 error margin of the
+    // k-th best), then the fp32 rerank of each query's list
+    CertArgs ca;
+    ca.Q = Q;
+    ca.Qb = qb;
+    ca.d = ix.d;
+    ca.xmax = ix.xb_bound[0];
+    ca.xres = ix.xb_bound[1];
+    ca.xbmax = ix.xb_bound[2];
+    ca.scnt = reinterpret_cast<int32_t*>(W + p.o_scnt);
+    ca.cap = int64_t(c) * p.rcap;
+    if (k <= 64)
+      launch_wave_select<2>(st, pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k,
+                            slist, int(H > 1), ca);
+    else if (k <= 128)
+      hipLaunchKernelGGL((select_kernel<128, 2>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
+                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), ca);
+    else
+      hipLaunchKernelGGL((select_kernel<1024, 2>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
+                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), ca);
+    const int vec = ix.d % 4 == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0;
+    if (k <= 128)
+      hipLaunchKernelGGL(cert_rerank_kernel<128>, dim3(qgrid), dim3(kSelNT), 0, st, ix.X, ix.d, Q,
+                         nq, slist, ca.cap, ca.scnt, ix.perm32, k, vec, ids, scores);
+    else
+      hipLaunchKernelGGL(cert_rerank_kernel<1024>, dim3(qgrid), dim3(kSelNT), 0, st, ix.X, ix.d,
+                         Q, nq, slist, ca.cap, ca.scnt, ix.perm32, k, vec, ids, scores);
   } else {
     if (p.S <= 64)
       launch_wave_select<1>(st, pairs, sbuf, p.rcap, c, nq, p.S, ix.off, ix.perm32, ids,
                             scores, k, slist, int(H > 1));
     else if (p.S <= 512)
       hipLaunchKernelGGL((select_kernel<512, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1));
+                         p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), CertArgs());
     else
       hipLaunchKernelGGL((select_kernel<4096, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1));
+                         p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), CertArgs());
     if (p.S <= 64 && ix.d % 4 == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0)
       hipLaunchKernelGGL(wave_shortlist_kernel, dim3(unsigned((nq + 3) / 4)), dim3(256), 0, st,
                          ix.X, ix.d, Q, nq, slist, p.S, ix.perm32, k, ids, scores);

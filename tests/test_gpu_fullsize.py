@@ -80,21 +80,22 @@ def test_full_schedules_identical(full):
         assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), kw
 
 
-def test_full_precision_form(full):
-    """bf16 windows + fp8 routing + fp32 shortlist rerank on the full batch:
-    returned scores are exact fp32 scores of their ids (within tolerance of
-    FP64) on a sample, sorted, ids unique."""
-    gi, X, Q = full["gi"], full["X"], full["Q"]
-    ids, sc = gi.search(full["Qd"], 10, 8, 256, r1=256, precision="bf16")
-    ids, sc = ids.cpu().numpy(), sc.cpu().numpy()
-    qn = np.linalg.norm(Q.astype(np.float64), axis=1)
-    xn = np.linalg.norm(X.astype(np.float64), axis=1)
-    for q in range(0, NQ, 50):
-        g = ids[q][ids[q] >= 0]
-        assert len(set(g.tolist())) == len(g)
-        s64 = oracle.pair_scores(X, Q, np.full(len(g), q), g)
-        assert np.all(np.abs(sc[q][:len(g)] - s64) <= 1e-4 * qn[q] * xn[g]), q
-        assert np.all(np.diff(sc[q][:len(g)]) <= 0), q
+@pytest.mark.parametrize("k,c,r,r1", [(10, 8, 256, 256), (100, 8, 256, 256), (10, 1, 0, 1000)])
+def test_full_precision_form(full, k, c, r, r1):
+    """Precision form (bf16 windows, certified shortlist, fp32 rerank) on the
+    full batch in one call: routing and windows of every query equal the
+    oracle's, and 1,000 sampled top-k lists equal the oracle's within the
+    fp32 tolerance."""
+    torch = _torch()
+    gi, oi, X, Q = full["gi"], full["oi"], full["X"], full["Q"]
+    r = r or int(gi.max_cluster)
+    ids, sc, dbg = gi.search(full["Qd"], k, c, r, r1=r1, precision="bf16", debug=True)
+    torch.cuda.synchronize()
+    sel = np.arange(0, NQ, NQ // 1000)
+    oids, osc, odbg = oi.search(Q[sel], k, c, r, r1, debug=True)
+    tsel = torch.from_numpy(sel).cuda()
+    compare_debug({kk: v[tsel] for kk, v in dbg.items()}, odbg)
+    compare_topk(X, Q[sel], ids.cpu().numpy()[sel], sc.cpu().numpy()[sel], oids, osc)
 
 
 def test_full_kmeans_properties(full):
