@@ -1,10 +1,14 @@
 """Serving form on the GPU: requests served by continuous batching over
 several HIP streams give bit-identical results to the same requests searched
-alone."""
+alone, and every served request equals the FP64 oracle's answer within the
+fp32 tolerance."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2205_00970_amd import datagen
+
+from parity_util import compare_topk
 
 pytestmark = pytest.mark.gpu
 
@@ -26,6 +30,11 @@ def test_results_identical_alone_and_in_the_mix(precision):
     out = sch.run(reqs)
     assert all(q.status == "done" for q in out)
     assert max(len(bt.reqs) for bt in sch.batches) > 1  # requests were merged
+    oi = oracle.Index(X, 16, A, b, 4, 1.0, 8, assignment=lab)
+    ores = {kk: oi.search(Q, kk, c, r, r1) for kk in sorted({q.k for q in out})}
+    for q in out:
+        oids, osc = ores[q.k]
+        compare_topk(X, Q[q.rows], q.ids, q.scores, oids[q.rows], osc[q.rows])
     for q in out:
         rows = torch.from_numpy(q.rows).cuda()
         ids, sc = gi.search(Qd[rows].contiguous(), q.k, c, r, r1=r1, precision=precision)
