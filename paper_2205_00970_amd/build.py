@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libliderhip.so")
-SOURCES = ["hash.hip", "kmeans.hip", "core_build.hip", "search.hip", "api.hip"]
+SOURCES = ["hash.hip", "kmeans.hip", "core_build.hip", "radix_sort.hip", "search.hip", "api.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 VALU ops are disabled for all device code

@@ -7,7 +7,6 @@
 // centroids).  RMI training is FP64 with the sums in location order and no
 // contraction, one thread per model (root) or per (model, leaf).
 #include <hip/hip_fp8.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 
@@ -20,7 +19,6 @@ namespace lider {
 
 namespace {
 
-inline size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
 __global__ void fill_i32(int32_t* p, int64_t cnt, int32_t v) {
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < cnt;
@@ -301,20 +299,15 @@ int build_layer(const int32_t* dig, int32_t m, const int32_t* seg, int64_t n, in
   hipLaunchKernelGGL(key_kernel, g, blk, 0, st, dig, m, seg, n, mb, K);
   hipLaunchKernelGGL(iota_i32, g, blk, 0, st, io, n);
   // stable sort by key (ties keep ascending id), then stable by model
-  size_t t1 = 0, t2 = 0;
-  hipcub::DeviceRadixSort::SortPairs(nullptr, t1, K, K1, io, id1, int(n), 0, 53, st);
-  hipcub::DeviceRadixSort::SortPairs(nullptr, t2, segk, seg2, io, idx2, int(n), 0,
-                                     sort_bits_for(nseg), st);
-  void* tmp = B.get<char>(std::max(t1, t2));
+  const size_t tb = radix_sort_temp_bytes(n, 8);
+  void* tmp = B.get<char>(tb);
   if (!tmp) return set_error(LIDER_ENOMEM, "out of device memory for the key sort");
-  size_t tb = std::max(t1, t2);
-  hipError_t e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, K, K1, io, id1, int(n), 0, 53, st);
-  if (e != hipSuccess) return check_hip(e, "key sort");
+  int rc = radix_sort_pairs<uint64_t>(K, io, K1, id1, n, 53, tmp, tb, st);
+  if (rc != LIDER_OK) return rc;
   hipLaunchKernelGGL(seg_of_kernel, g, blk, 0, st, seg, id1, n, segk);
-  tb = std::max(t1, t2);
-  e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, segk, seg2, io, idx2, int(n), 0,
-                                         sort_bits_for(nseg), st);
-  if (e != hipSuccess) return check_hip(e, "model sort");
+  rc = radix_sort_pairs<uint32_t>(segk, io, seg2, idx2, n, sort_bits_for(nseg), tmp, tb, st);
+  if (rc != LIDER_OK) return rc;
+  hipError_t e;
   hipLaunchKernelGGL(final_gather_kernel, g, blk, 0, st, K1, id1, idx2, n, keys, perm);
   hipLaunchKernelGGL(lower_bound_u32, dim3((nseg + 1 + 255) / 256), blk, 0, st, seg2, n, nseg,
                      off);

@@ -9,7 +9,6 @@
 //
 // Update = FP64 mean of each cluster's members summed in ascending id order,
 // rounded once to fp32; an empty cluster keeps its centroid.
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 
@@ -310,14 +309,10 @@ static int sort_bits(int32_t C) {
   return b;
 }
 
-// scratch: keys_out [n] u32 | iota [n] i32 | members [n] i32 | off [C+1] i64 | cub temp
+// scratch: keys_out [n] u32 | iota [n] i32 | members [n] i32 | off [C+1] i64 | sort temp
 size_t centroid_means_scratch(int64_t n, int32_t C) {
-  size_t tmp = 0;
-  hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                     (const int32_t*)nullptr, (int32_t*)nullptr, int(n), 0,
-                                     sort_bits(C), (hipStream_t)0);
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-  return al(size_t(n) * 4) * 3 + al((size_t(C) + 1) * 8) + al(tmp);
+  return al(size_t(n) * 4) * 3 + al((size_t(C) + 1) * 8) + al(radix_sort_temp_bytes(n, 4));
 }
 
 int run_centroid_means(const float* X, int64_t n, int32_t d, const int32_t* assign, int32_t C,
@@ -334,10 +329,9 @@ int run_centroid_means(const float* X, int64_t n, int32_t d, const int32_t* assi
   p += al((size_t(C) + 1) * 8);
   size_t tmp = scratch_bytes - size_t(p - static_cast<char*>(scratch));
   hipLaunchKernelGGL(iota_kernel, dim3(1024), dim3(256), 0, st, io, n);
-  hipError_t e = hipcub::DeviceRadixSort::SortPairs(
-      p, tmp, reinterpret_cast<const uint32_t*>(assign), kout, io, members, int(n), 0,
-      sort_bits(C), st);
-  if (e != hipSuccess) return check_hip(e, "cluster grouping sort");
+  const int rc = radix_sort_pairs<uint32_t>(reinterpret_cast<const uint32_t*>(assign), io, kout,
+                                            members, n, sort_bits(C), p, tmp, st);
+  if (rc != LIDER_OK) return rc;
   hipLaunchKernelGGL(lower_bound_kernel, dim3((C + 1 + 255) / 256), dim3(256), 0, st, kout, n, C,
                      off);
   const int64_t tot = int64_t(C) * d;

@@ -184,6 +184,8 @@ __host__ __device__ inline double dot_err_coef(int d) {
   return double(d + 2) * (5.9604644775390625e-08 /* 2^-24 */ + 2.220446049250313e-16);
 }
 
+inline size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
 // ----------------------------------------------------------------- the index
 struct Index {
   int device = 0;
@@ -280,6 +282,14 @@ size_t kmeans_assign_scratch(int64_t n, int32_t C);
 int run_centroid_means(const float* X, int64_t n, int32_t d, const int32_t* assign, int32_t C,
                        float* cent, void* scratch, size_t scratch_bytes, hipStream_t st);
 size_t centroid_means_scratch(int64_t n, int32_t C);
+
+// radix_sort.hip: stable LSD radix sort of (key, value) pairs by key bits
+// [0, bits), 8 bits per pass (n < 2^31; inputs and outputs distinct buffers;
+// temp holds radix_sort_temp_bytes).  Asynchronous on st.
+size_t radix_sort_temp_bytes(int64_t n, int key_bytes);
+template <class K>
+int radix_sort_pairs(const K* keys_in, const int32_t* vals_in, K* keys_out, int32_t* vals_out,
+                     int64_t n, int bits, void* temp, size_t temp_bytes, hipStream_t st);
 
 // core_build.hip
 int build_core_models(Index& ix, const float* Xin, hipStream_t st);

@@ -28,7 +28,6 @@ namespace lider {
 
 namespace {
 
-inline size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct alignas(16) Pair {
   int32_t j, s, len, pos;
