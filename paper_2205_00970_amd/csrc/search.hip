@@ -2552,6 +2552,109 @@ __global__ __launch_bounds__(kSelNT) void cert_rerank_kernel(
   }
 }
 
+// Certified second pass for k <= 64, one wave per query: the listed rows are
+// scored 64 at a time (8 rows per round with all their loads in flight, 16
+// lanes per row as in wave_shortlist_kernel), and each chunk is merged with
+// the best k so far: every entry of the chunk and of the current best is
+// ranked against all others by (score desc, id asc) through readlane, and the
+// k first ranks become the new best, kept in LDS in rank order.
+__global__ __launch_bounds__(256) void cert_wave_kernel(
+    const float* __restrict__ X, int32_t d, const float* __restrict__ Q, int64_t nq,
+    const int32_t* __restrict__ slist, int64_t cap, const int32_t* __restrict__ scnt,
+    const int32_t* __restrict__ perm32, int32_t k, int vec, int64_t* __restrict__ ids,
+    float* __restrict__ scores) {
+  __shared__ float sc[4][64];
+  __shared__ uint32_t bkey[4][64], bid[4][64];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));  // uniform
+  const int g = lane >> 4, c16 = lane & 15;
+  const int64_t q = int64_t(blockIdx.x) * 4 + wave;
+  if (q >= nq) return;
+  {
+    const int32_t n = scnt[q];
+    const int32_t* lq = slist + q * cap;
+    const float* qv = Q + q * d;
+    int nb = 0;  // entries of the best list (wave-uniform)
+    for (int32_t c0 = 0; c0 < n; c0 += 64) {
+      const int m = min(64, n - c0);
+      const int32_t myrow = lane < m ? lq[c0 + lane] : 0;
+      for (int t0 = 0; t0 < m; t0 += 8) {
+        const int ta = min(t0 + g, m - 1), tb = min(t0 + 4 + g, m - 1);
+        const float* xa = X + int64_t(__shfl(myrow, ta)) * d;
+        const float* xb = X + int64_t(__shfl(myrow, tb)) * d;
+        float acca = 0.f, accb = 0.f;
+        if (vec) {
+#pragma unroll 4
+          for (int l = 4 * c16; l < d; l += 64) {
+            const float4 va = *reinterpret_cast<const float4*>(xa + l);
+            const float4 vb = *reinterpret_cast<const float4*>(xb + l);
+            const float4 qq = *reinterpret_cast<const float4*>(qv + l);
+            acca += va.x * qq.x;
+            acca += va.y * qq.y;
+            acca += va.z * qq.z;
+            acca += va.w * qq.w;
+            accb += vb.x * qq.x;
+            accb += vb.y * qq.y;
+            accb += vb.z * qq.z;
+            accb += vb.w * qq.w;
+          }
+        } else {
+          for (int l = c16; l < d; l += 16) {
+            acca += xa[l] * qv[l];
+            accb += xb[l] * qv[l];
+          }
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+          acca += __shfl_xor(acca, o);
+          accb += __shfl_xor(accb, o);
+        }
+        if (c16 == 0 && t0 + g < m) sc[wave][t0 + g] = acca;
+        if (c16 == 0 && t0 + 4 + g < m) sc[wave][t0 + 4 + g] = accb;
+      }
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+      // entry A of a lane: its chunk row; entry B: its place in the best list
+      const uint32_t ka = lane < m ? score_key(sc[wave][lane]) : 0xffffffffu;
+      const uint32_t ia = lane < m ? uint32_t(perm32[myrow]) : 0xffffffffu;
+      const uint32_t kb = lane < nb ? bkey[wave][lane] : 0xffffffffu;
+      const uint32_t ib = lane < nb ? bid[wave][lane] : 0xffffffffu;
+      int ra = 0, rb = 0;
+      for (int u = 0; u < 64; ++u) {
+        const uint32_t ku = uint32_t(__builtin_amdgcn_readlane(int(ka), u));
+        const uint32_t iu = uint32_t(__builtin_amdgcn_readlane(int(ia), u));
+        const uint32_t kv = uint32_t(__builtin_amdgcn_readlane(int(kb), u));
+        const uint32_t iv = uint32_t(__builtin_amdgcn_readlane(int(ib), u));
+        const bool uok = u < m, vok = u < nb;
+        ra += (uok && ((ku < ka) || (ku == ka && iu < ia))) + (vok && ((kv < ka) || (kv == ka && iv < ia)));
+        rb += (uok && ((ku < kb) || (ku == kb && iu < ib))) + (vok && ((kv < kb) || (kv == kb && iv < ib)));
+      }
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+      if (lane < m && ra < k) {
+        bkey[wave][ra] = ka;
+        bid[wave][ra] = ia;
+      }
+      if (lane < nb && rb < k) {
+        bkey[wave][rb] = kb;
+        bid[wave][rb] = ib;
+      }
+      nb = min(k, nb + m);
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (lane < k) {
+      if (lane < nb) {
+        ids[q * k + lane] = int64_t(bid[wave][lane]);
+        scores[q * k + lane] = key_score(bkey[wave][lane]);
+      } else {
+        ids[q * k + lane] = -1;
+        scores[q * k + lane] = -INFINITY;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------ debug exports
 __global__ void debug_kernel(const int32_t* __restrict__ l1, const Pair* __restrict__ pairs,
                              const Pair* __restrict__ pw, int32_t H,
@@ -2972,7 +3075,10 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
       hipLaunchKernelGGL((select_kernel<1024, 2>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
                          p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), ca);
     const int vec = ix.d % 4 == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0;
-    if (k <= 128)
+    if (k <= 64)
+      hipLaunchKernelGGL(cert_wave_kernel, dim3(unsigned((nq + 3) / 4)), dim3(256), 0, st, ix.X,
+                         ix.d, Q, nq, slist, ca.cap, ca.scnt, ix.perm32, k, vec, ids, scores);
+    else if (k <= 128)
       hipLaunchKernelGGL(cert_rerank_kernel<128>, dim3(qgrid), dim3(kSelNT), 0, st, ix.X, ix.d, Q,
                          nq, slist, ca.cap, ca.scnt, ix.perm32, k, vec, ids, scores);
     else

@@ -275,13 +275,28 @@ class Index:
             # invalid arguments: let lider_search_ex report which
             _check(lib().lider_search_ex(self._h, qp, nq, k, c, r, None, None, None, 0,
                                          _stream(stream), C.byref(o), None))
+        cur = torch.cuda.current_stream(queries.device)
+        st_obj = stream if stream is not None else cur
         if ws is None:
-            if self._ws is None or self._ws.numel() < need:
-                self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=queries.device)
-            ws = self._ws
+            # one cached workspace per stream: searches on different streams
+            # never share one, and a buffer replaced by a larger one is not
+            # reused by the allocator while its stream may still read it
+            key = int(st_obj.cuda_stream)
+            if self._ws is None:
+                self._ws = {}
+            wsb = self._ws.get(key)
+            if wsb is None or wsb.numel() < need:
+                wsb = torch.empty(max(need, 256), dtype=torch.uint8, device=queries.device)
+                if st_obj != cur:
+                    wsb.record_stream(st_obj)
+                self._ws[key] = wsb
+            ws = wsb
         if out is None:
             ids = torch.empty((nq, k), dtype=torch.int64, device=queries.device)
             sc = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+            if st_obj != cur:
+                ids.record_stream(st_obj)
+                sc.record_stream(st_obj)
         else:
             ids, sc = out
         dbg = None
