@@ -62,7 +62,6 @@ int alloc_index(Index& ix) {
     if (rc == LIDER_OK) rc = (x); \
   } while (0)
   TRY(alloc(&ix.X, size_t(n) * d, "reordered corpus"));
-  if (ix.storage == LIDER_BF16) TRY(alloc(&ix.Xb, size_t(n) * d, "bf16 corpus"));
   TRY(alloc(&ix.perm, size_t(H) * n, "perm"));
   TRY(alloc(&ix.perm32, size_t(n), "perm32"));
   TRY(alloc(&ix.keys, size_t(H) * n, "keys"));
@@ -376,7 +375,7 @@ static int validate_search(const lider_index* index, const float* Q, int64_t nq,
   if (o.r1 < 0) return set_error(LIDER_EINVAL, "r1 must be >= 0");
   if (o.precision != LIDER_F32 && o.precision != LIDER_BF16)
     return set_error(LIDER_EINVAL, "precision must be LIDER_F32 or LIDER_BF16");
-  if (o.precision == LIDER_BF16 && !ix.Xb)
+  if (o.precision == LIDER_BF16 && !ix.Xb && !ix.Xbt)
     return set_error(LIDER_EINVAL, "precision LIDER_BF16 needs an index built with storage BF16");
   if (o.precision == LIDER_BF16 && (ix.d % 8 != 0))
     return set_error(LIDER_EINVAL, "precision LIDER_BF16 needs d divisible by 8");
@@ -642,7 +641,7 @@ std::vector<Section> sections(const Index& ix) {
   const size_t H = size_t(ix.H), nh = 2 * H * m, nleaf = H * (C * ix.F2 + ix.F1);
   auto sz = [](const void* p, size_t b) { return p ? b : size_t(0); };
   return {{1, ix.X, n * d * 4},
-          {2, ix.Xb, sz(ix.Xb, n * d * 2)},
+          {2, nullptr, 0},  // bf16 copies are derived from section 1 on load
           {3, ix.perm, H * n * 8},
           {4, ix.perm32, n * 4},
           {5, ix.keys, H * n * 8},

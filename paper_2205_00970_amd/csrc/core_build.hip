@@ -567,7 +567,8 @@ int finish_index(Index& ix) {
   // clusters padded to whole 16-row blocks in the operand-ordered copy
   std::vector<int64_t> pblk(size_t(C) + 1, 0);  // first 16-row block of each cluster
   for (int32_t j = 0; j < C; ++j) pblk[j + 1] = pblk[j] + (ix.h_off[j + 1] - ix.h_off[j] + 15) / 16;
-  const bool want_t = ix.d % kTileKS == 0, want_bt = ix.Xb && ix.d % 64 == 0;
+  const bool want_t = ix.d % kTileKS == 0;
+  const bool want_bt = ix.storage == LIDER_BF16 && ix.d % 64 == 0 && !ix.Xbt;
   if ((want_t || want_bt) && pblk[C] > 0) {
     const int64_t nblk = pblk[C];
     std::vector<int2> src(static_cast<size_t>(nblk));
@@ -604,7 +605,19 @@ int finish_index(Index& ix) {
     (void)hipFree(dsrc);
     if (rc != LIDER_OK) return rc;
   }
-  if (ix.Xb) {  // bounds of the precision form's certified shortlist
+  // the row-major bf16 copy only where the operand-ordered one is missing
+  // (d not a multiple of 64, or no room for it)
+  if (ix.storage == LIDER_BF16 && !ix.Xbt && !ix.Xb && ix.n > 0) {
+    if (hipMalloc(&ix.Xb, al256(size_t(ix.n) * size_t(ix.d) * 2)) != hipSuccess) {
+      ix.Xb = nullptr;
+      return set_error(LIDER_ENOMEM, "out of device memory (bf16 corpus)");
+    }
+    hipLaunchKernelGGL(bf16_copy_kernel, dim3(4096), dim3(256), 0, nullptr, ix.X,
+                       ix.n * int64_t(ix.d), ix.Xb);
+    rc = check_hip(hipDeviceSynchronize(), "bf16 corpus");
+    if (rc != LIDER_OK) return rc;
+  }
+  if (ix.storage == LIDER_BF16) {  // bounds of the precision form's certified shortlist
     uint32_t* mb = nullptr;
     uint32_t hb[4] = {0u, 0u, 0u, 0u};
     if (hipMalloc(&mb, 256) != hipSuccess)

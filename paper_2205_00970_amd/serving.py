@@ -149,6 +149,8 @@ class Scheduler:
         self.clock = clock or time.perf_counter
         self.sleep = sleep or (lambda s: time.sleep(s))
         self.batches = []
+        self.max_used = 0      # most workspace bytes in flight at once
+        self.mem_limited = 0   # batch formations cut short by the memory budget
 
     def run(self, requests, t0=None):
         """Serve `requests` (arrival offsets in seconds, sorted); returns them."""
@@ -195,6 +197,7 @@ class Scheduler:
                         break
                     ws = self.ex.workspace_bytes(nq + q.nq, k)
                     if self.mem_budget is not None and used + ws > self.mem_budget:
+                        self.mem_limited += 1
                         break
                     if self.ex.slot_bytes is not None and ws > self.ex.slot_bytes:
                         break
@@ -219,6 +222,7 @@ class Scheduler:
                 for q in take:
                     q.status, q.launch = "running", t
                 used += ws
+                self.max_used = max(self.max_used, used)
                 inflight.append(b)
                 self.batches.append(b)
             if done < len(reqs):
@@ -286,8 +290,12 @@ def fresh(reqs):
 def bench_main(args, exact_topk, recall_at):
     """Serving benchmark: N=21,000,000 d=768 (bf16 copy + fp32 master), 8,192
     clusters (the generator's components), m=8; Poisson arrivals at 5k-1M
-    queries/s, request size U[1, 256], k in {10, 100}; continuous batching with
-    the precision form on 4 streams vs one-request-at-a-time plain fp32 search."""
+    queries/s, request size U[1, 256], k in {10, 100}.  The same continuous-
+    batching scheduler (4 streams, a memory budget of two full-size batches'
+    workspaces) runs the precision form (bf16 windows, certified shortlist,
+    fp32 rerank) and the plain fp32 search; one request at a time on one
+    stream is reported as a third reference at the lowest and highest rate.
+    Per-result score errors against FP64 are reported as percentiles."""
     import json
     import sys
 
@@ -319,29 +327,45 @@ def bench_main(args, exact_topk, recall_at):
                        f"arrivals, request size U[1,256], k in {{10,100}}", "c": c, "r": r,
            "r1": r1}
     for prec in ("f32", "bf16"):
-        ids, _ = gi.search(sample, 10, c, r, r1=r1, precision=prec)
+        ids, sc = gi.search(sample, 10, c, r, r1=r1, precision=prec)
         out[f"recall10_{prec}"] = round(recall_at(torch, X, sample, ids, gt_sc, 10), 4)
+        # per-result error of the returned score against the FP64 inner product,
+        # relative to |q| |x|
+        rows = X[ids.clamp(min=0)].double()
+        s64 = (rows * sample.double()[:, None, :]).sum(-1)
+        rel = ((sc.double() - s64).abs() / (sample.double().norm(dim=1, keepdim=True)
+                                            * rows.norm(dim=2)))[ids >= 0].cpu().numpy()
+        out[f"score_err_{prec}"] = {f"p{p}": float(np.percentile(rel, p)) for p in (50, 90, 99)}
+        out[f"score_err_{prec}"]["max"] = float(rel.max())
+        del rows, s64
     del X, gt_ids, gt_sc
     torch.cuda.empty_cache()
     nq_total = int(getattr(args, "serve_queries", 0) or 110_000)
-    # Small batches touch few of the index's row tiles: both executors pull
+    # Small batches touch few of the index's row tiles: the executors pull
     # only the overlapped tiles from a device-built work list.
     sched = dict(persistent=2, grid_mult=4)
     out["schedule"] = sched
-    serve_ex = GpuExecutor(gi, Q, c, r, r1, precision="bf16", slots=4, max_batch=4096,
-                           schedule=sched)
+    exs = {p: GpuExecutor(gi, Q, c, r, r1, precision=p, slots=4, max_batch=4096, schedule=sched)
+           for p in ("bf16", "f32")}
+    budget = {p: 2 * e.workspace_bytes(4096, 100) for p, e in exs.items()}
+    out["mem_budget_bytes"] = budget
     plain_ex = GpuExecutor(gi, Q, c, r, r1, precision="f32", slots=1, max_batch=256,
                            schedule=sched)
     for lam in (5_000, 10_000, 20_000, 50_000, 200_000, 1_000_000):
         reqs = make_requests(lam, nq_total, pool, seed=4)
-        t = time.time()
-        res = Scheduler(serve_ex, slots=4, max_batch=4096, poll_interval=0).run(fresh(reqs))
-        st = latency_stats(res)
-        out[f"serving_bf16_{lam}"] = st
-        log(f"lambda={lam} serving bf16, 4 streams: {st} ({time.time() - t:.1f}s)")
-        t = time.time()
-        res = run_plain(plain_ex, fresh(reqs))
-        st = latency_stats(res)
-        out[f"plain_f32_{lam}"] = st
-        log(f"lambda={lam} plain fp32, one request at a time: {st} ({time.time() - t:.1f}s)")
+        for p, ex in exs.items():
+            t = time.time()
+            sch = Scheduler(ex, slots=4, mem_budget=budget[p], max_batch=4096, poll_interval=0)
+            res = sch.run(fresh(reqs))
+            st = latency_stats(res)
+            st.update(batches=len(sch.batches), max_inflight_bytes=sch.max_used,
+                      memory_limited=sch.mem_limited)
+            out[f"continuous_{p}_{lam}"] = st
+            log(f"lambda={lam} continuous {p}, 4 streams: {st} ({time.time() - t:.1f}s)")
+        if lam in (5_000, 1_000_000):
+            t = time.time()
+            res = run_plain(plain_ex, fresh(reqs))
+            st = latency_stats(res)
+            out[f"one_at_a_time_f32_{lam}"] = st
+            log(f"lambda={lam} fp32, one request at a time: {st} ({time.time() - t:.1f}s)")
     print(json.dumps(out), flush=True)
