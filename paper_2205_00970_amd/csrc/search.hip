@@ -894,13 +894,18 @@ __global__ void pairs_kernel(const Model* __restrict__ models, const double* __r
 // mw words), stores the bitmap as the pair's membership mask [mw words] and
 // sets pairs[t] to the hull [first, last] of the union.
 __global__ __launch_bounds__(256) void pair_mask_kernel(
-    const Pair* __restrict__ pw, int32_t H, int64_t np, const int64_t* __restrict__ off,
+    const Pair* __restrict__ pw, int32_t H, const int32_t* __restrict__ wl,
+    const int32_t* __restrict__ wl_end, const int64_t* __restrict__ off,
     const int32_t* __restrict__ amap, int64_t n, int32_t mw, Pair* __restrict__ pairs,
     uint32_t* __restrict__ mask) {
   extern __shared__ uint32_t bm_all[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* bm = bm_all + wave * mw;
-  for (int64_t t = int64_t(blockIdx.x) * 4 + wave; t < np; t += int64_t(gridDim.x) * 4) {
+  // pairs in work-list order: consecutive waves take pairs of one cluster,
+  // whose position maps then stay in L2
+  const int64_t nwl = *wl_end;
+  for (int64_t u = int64_t(blockIdx.x) * 4 + wave; u < nwl; u += int64_t(gridDim.x) * 4) {
+    const int64_t t = wl[u];
     const int32_t j = pw[t * H].j;
     if (j < 0) continue;  // wave-uniform
     const int64_t o = off[j];
@@ -3009,10 +3014,6 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
     hipLaunchKernelGGL(expand_kernel, dim3(unsigned((np * H + 3) / 4)), dim3(256), 0, st,
                        ix.keys, ix.off, int64_t(0), H > 1 ? pw : pairs, np * H, kq, r, m,
                        o.expand_bits, (int32_t*)nullptr, H, ix.n);
-  if (H > 1)
-    hipLaunchKernelGGL(pair_mask_kernel, dim3(unsigned(std::min<int64_t>((np + 3) / 4, 65535))),
-                       dim3(256), 4 * size_t(p.mw) * 4, st, pw, H, np, ix.off, ix.amap, ix.n,
-                       p.mw, pairs, pmask);
   if (C <= kFusedScanMax) {
     hipLaunchKernelGGL(scan_scatter_kernel, dim3(unsigned(std::max<int64_t>(1, (np + 255) / 256))),
                        dim3(256), 0, st, ccount, C, pairs, np, cstart, cfill, wl);
@@ -3021,6 +3022,12 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
     hipLaunchKernelGGL(scatter_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, pairs,
                        np, cstart, cfill, wl);
   }
+  // several arrays: each listed pair's union of windows as a membership mask
+  // over its cluster's rows, and its window set to the union's hull
+  if (H > 1)
+    hipLaunchKernelGGL(pair_mask_kernel, dim3(unsigned(std::min<int64_t>((np + 3) / 4, 65535))),
+                       dim3(256), 4 * size_t(p.mw) * 4, st, pw, H, wl, cstart + C, ix.off,
+                       ix.amap, ix.n, p.mw, pairs, pmask);
   mark(3);
   const int ti = p.ti;
   const int tr = 32 << ti;
