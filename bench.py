@@ -331,31 +331,55 @@ def main():
         del a, bcopy
         log("calibration copy: 3 x (1 GiB read + 1 GiB write)")
     if not args.quick:
-        # literal point (c=8, r=256, r1=r) for k=10 and k=100
+        # literal point (c=8, r=256, r1=r) for k=10 and k=100, with its stages
+        # and the rerank's roofline
         for kk in (10, 100):
             dt, li, _ = timed(kk, 8, 256, 0, reps=5)
-            extra[f"literal_k{kk}"] = dict(c=8, r=256, r1=256, qps=round(args.nq / dt),
-                                           recall10=round(recall_at(torch, X, Q, li, gt_sc, 10), 4))
+            lider.profile_begin(5)
+            for _ in range(5):
+                run(kk, 8, 256, 256)
+            torch.cuda.synchronize()
+            lst, lcalls = lider.profile_end()
+            rl = rerank_roofline(torch, gi, Q, kk, 8, 256, 256, lst["rerank"] / lcalls)
+            extra[f"literal_k{kk}"] = dict(
+                c=8, r=256, r1=256, qps=round(args.nq / dt),
+                recall10=round(recall_at(torch, X, Q, li, gt_sc, 10), 4),
+                stage_ms={s2: round(v / lcalls, 4) for s2, v in lst.items()},
+                roofline={kk2: rl[kk2] for kk2 in ("bound", "achieved", "unit", "frac", "union_rows",
+                                                  "pair_rows", "other_bound")})
             log(f"literal c=8 r=256 k={kk}: {args.nq / dt:,.0f} q/s, recall@10 "
-                f"{extra[f'literal_k{kk}']['recall10']}")
+                f"{extra[f'literal_k{kk}']['recall10']}, rerank {rl['frac']:.1%} of {rl['bound']} peak")
         # k=100 at the operating point
         dt, li, _ = timed(100, c, r, r1, reps=5)
         extra["point_k100"] = dict(qps=round(args.nq / dt),
                                    recall100=round(recall_at(torch, X, Q, li, gt_sc, 100), 4))
-        # precision form: bf16 windows + exact routing from the bf16 layer-1 product + fp32 rerank of a 4k shortlist
-        dt, pi, ps = timed(10, c, r, r1, reps=5, precision="bf16")
-        rows = X[pi.clamp(min=0)]
-        xs = (rows.double() * Q.double()[:, None, :]).sum(-1)
-        err = (ps.double() - xs).abs() / (Q.double().norm(dim=1, keepdim=True) * rows.double().norm(dim=2))
-        extra["precision_bf16"] = dict(qps=round(args.nq / dt),
-                                       recall10=round(recall_at(torch, X, Q, pi, gt_sc, 10), 4),
-                                       max_rel_score_err=float(err[pi >= 0].max().item()))
-        del rows, xs, err
-        log(f"precision form: {args.nq / dt:,.0f} q/s, recall@10 "
+        # precision form: bf16 windows, exact routing from the bf16 layer-1
+        # product, the certified shortlist (every candidate within the bf16
+        # error margin of the k-th best) reranked in fp32: the fp32 top k
+        def precision_entry(kk, cc, rr, rr1):
+            dt, pi, ps = timed(kk, cc, rr, rr1, reps=5, precision="bf16")
+            fi, _ = run(kk, cc, rr, rr1)
+            rows = X[pi.clamp(min=0)]
+            xs = (rows.double() * Q.double()[:, None, :]).sum(-1)
+            err = ((ps.double() - xs).abs()
+                   / (Q.double().norm(dim=1, keepdim=True) * rows.double().norm(dim=2)))[pi >= 0]
+            e = err.cpu().numpy()
+            out = dict(c=cc, r=rr, r1=rr1, k=kk, shortlist="certified", qps=round(args.nq / dt),
+                       recall10=round(recall_at(torch, X, Q, pi, gt_sc, 10), 4),
+                       ids_equal_fp32_path=round(float((pi == fi).float().mean().item()), 6),
+                       rel_score_err={"p50": float(np.percentile(e, 50)),
+                                      "p99": float(np.percentile(e, 99)), "max": float(e.max())})
+            del rows, xs, err
+            return out
+        extra["precision_bf16"] = precision_entry(10, c, r, r1)
+        log(f"precision form (certified): {extra['precision_bf16']['qps']:,} q/s, recall@10 "
             f"{extra['precision_bf16']['recall10']}")
-        # shorter fp32 shortlists (the default is 4k): the trade-off of the precision form
+        extra["precision_bf16_literal"] = precision_entry(10, 8, 256, 256)
+        log(f"precision form (certified), literal point: "
+            f"{extra['precision_bf16_literal']['qps']:,} q/s")
+        # fixed-length shortlists (the mult*k best bf16 scores): approximate
         extra["precision_bf16_shortlist"] = []
-        for mult in (2, 1):
+        for mult in (4, 2):
             dt, pi, _ = timed(10, c, r, r1, reps=5, precision="bf16", shortlist_mult=mult)
             rec_s = round(recall_at(torch, X, Q, pi, gt_sc, 10), 4)
             extra["precision_bf16_shortlist"].append(dict(shortlist=f"{mult}k", qps=round(args.nq / dt),
@@ -504,7 +528,8 @@ def arrays_variant(args, torch, datagen, lider, X, lab, Q, C, F, log, gt_sc, H_l
     for H in H_list:
         A, b = datagen.lsh_params(m, X.shape[1], w, seed=31, n_arrays=H)
         t0 = time.time()
-        gi = lider.Index(X, C, m, w, F, (A, b), assignment=lab.to(torch.int32), n_arrays=H)
+        gi = lider.Index(X, C, m, w, F, (A, b), assignment=lab.to(torch.int32), n_arrays=H,
+                         storage="bf16" if H > 1 else "f32")
         torch.cuda.synchronize()
         bs = time.time() - t0
         res = {"build_s": round(bs, 2)}
@@ -524,6 +549,17 @@ def arrays_variant(args, torch, datagen, lider, X, lab, Q, C, F, log, gt_sc, H_l
             res[name] = dict(c=c, r=r, r1=r1, qps=round(Q.shape[0] / dt), recall10=round(rec, 4),
                              stage_ms={s: round(v / calls, 4) for s, v in stages.items()})
             rl = rerank_roofline(torch, gi, Q, 10, c, r, r1, stages["rerank"] / calls)
+            if H > 1 and name == "literal":  # the precision form (certified shortlist) beside it
+                gi.search(Q, 10, c, r, r1=r1, precision="bf16", out=(ids, sc))
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(5):
+                    gi.search(Q, 10, c, r, r1=r1, precision="bf16", out=(ids, sc))
+                torch.cuda.synchronize()
+                dtp = (time.perf_counter() - t) / 5
+                res["precision_bf16_literal"] = dict(
+                    qps=round(Q.shape[0] / dtp), recall10=round(recall_at(torch, X, Q, ids, gt_sc, 10), 4))
+                log(f"arrays H={H} literal, precision form: {Q.shape[0] / dtp:,.0f} q/s")
             res[name]["roofline"] = {kk: rl[kk] for kk in ("bound", "achieved", "unit", "frac",
                                                           "union_rows", "hull_rows", "pair_rows",
                                                           "other_bound")}
