@@ -912,12 +912,21 @@ __global__ __launch_bounds__(256) void pair_mask_kernel(
     for (int32_t w = lane; w < mw; w += 64) bm[w] = 0;
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
+    // every array's window positions mapped to array 0's, up to 4 position
+    // loads per lane in flight before their bits are set
     for (int32_t h = 0; h < H; ++h) {
       const Pair ph = pw[t * H + h];
-      for (int32_t p = lane; p < ph.len; p += 64) {
-        const int32_t row =
-            h == 0 ? ph.s + p : int32_t(amap[int64_t(h - 1) * n + o + ph.s + p] - o);
-        atomicOr(&bm[row >> 5], 1u << (row & 31));
+      const int32_t* mp = h == 0 ? nullptr : amap + int64_t(h - 1) * n + o + ph.s;
+      for (int32_t p0 = 0; p0 < ph.len; p0 += 256) {
+        int32_t row[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t p = min(p0 + lane + 64 * u, ph.len - 1);
+          row[u] = h == 0 ? ph.s + p : int32_t(mp[p] - o);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (p0 + lane + 64 * u < ph.len) atomicOr(&bm[row[u] >> 5], 1u << (row[u] & 31));
       }
     }
     __threadfence_block();
@@ -2188,11 +2197,24 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
           f(i, i < n ? keys[wave][i] : 0xffffffffu, i < n);
         }
       } else {
+        // re-read from the score rows, 8 loads per lane in flight before
+        // their keys are used
         for (int t = 0; t < c; ++t) {
           const int32_t a = st[t], len = st[t + 1] - a;
-          for (int p0 = 0; p0 < len; p0 += 64) {
-            const int p = p0 + lane;
-            f(a + p, p < len ? score_key(sbq[int64_t(t) * rcap + p]) : 0xffffffffu, p < len);
+          const float* src = sbq + int64_t(t) * rcap;
+          for (int p0 = 0; p0 < len; p0 += 512) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int p = p0 + lane + 64 * u;
+              v[u] = src[p < len ? p : len - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int p = p0 + lane + 64 * u;
+              if (p0 + 64 * u < len)  // wave-uniform
+                f(a + p, p < len ? score_key(v[u]) : 0xffffffffu, p < len);
+            }
           }
         }
       }
