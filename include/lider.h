@@ -207,14 +207,22 @@ const char* lider_last_error(void);
  *                 exactly c they are rescored by sequential FP64 inner
  *                 products.  0 (default): one dense query x centroid product
  *                 on MFMA in bf16 (every centroid scored; each query's window
- *                 read from its row).  1: the dense product in fp32.  -1: the
+ *                 read from its row), split when c > 1 (as 3).  1: the dense
+ *                 product in fp32.  2: the plain bf16 product (bf16 roundings
+ *                 of both operands).  3: the split bf16 product: each fp32
+ *                 value x becomes h = bf16(x) and l = bf16(x - h), and the
+ *                 score sums h_q h_mu + h_q l_mu + l_q h_mu (error about
+ *                 3 2^-16 |q| |mu| instead of 2^-7 |q| |mu|: far fewer
+ *                 candidates to rescore when c > 1; needs d a multiple of 64
+ *                 and 16-byte aligned queries, else acts as 2).  -1: the
  *                 window kernel (fp32 scores of the r1-windows only).  The
  *                 routed sets, and so all results, are identical.  With
  *                 n_arrays > 1, -1 acts as 1; with r1 < n_clusters the routing
  *                 runs over the union of the H windows (at most 65536
  *                 clusters).  The dense product needs nq x n_clusters floats
  *                 of workspace.
- *  grid_mult      persistent grid = grid_mult * number of CUs (0 = 4).
+ *  grid_mult      persistent grid: grid_mult waves per SIMD, i.e. 4 * grid_mult *
+ *                 number of CUs one-wave workgroups (0 = 4).
  *  expand_bits    0: fixed window of r (r1) positions, floor(r/2) left of the
  *                 predicted location (shifted inward at the ends).  B in 1..16:
  *                 dist_e-guided expansion (Section 4.2, C = 2^B), only for

@@ -385,7 +385,7 @@ static int validate_search(const lider_index* index, const float* Q, int64_t nq,
     return set_error(LIDER_EINVAL, "tile_rows must be 0, 32, 64 or 128");
   if (o.grid_mult < 0 || o.grid_mult > 64) return set_error(LIDER_EINVAL, "grid_mult out of range");
   if (o.persistent < 0 || o.persistent > 2) return set_error(LIDER_EINVAL, "persistent must be 0, 1 or 2");
-  if (o.l1_dense < -1 || o.l1_dense > 1) return set_error(LIDER_EINVAL, "l1_dense must be -1, 0 or 1");
+  if (o.l1_dense < -1 || o.l1_dense > 3) return set_error(LIDER_EINVAL, "l1_dense must be -1, 0, 1, 2 or 3");
   if (o.pass_pairs != 0 && o.pass_pairs != 16 && o.pass_pairs != 32 && o.pass_pairs != 64 &&
       o.pass_pairs != 128)
     return set_error(LIDER_EINVAL, "pass_pairs must be 0, 16, 32, 64 or 128");

@@ -580,7 +580,8 @@ __device__ __attribute__((noinline)) void route_fp64_wave(const float* __restric
 // = lst[q lcap + p] with a union list, else s1 + p; its approximate score is
 // rs[q rstride + pos(p)] for dense score rows (every centroid scored), else
 // rs[q rstride + p].  Each approximate score is within E = ecoef |q| max|mu|
-// (+ a term for underflow) of the exact inner product.  Every centroid of the
+// + eadd + esub (|q| + max|mu|) (the last two for underflow) of the exact
+// inner product.  Every centroid of the
 // exact top c has an approximate score of at least T - 2E, T the c-th largest
 // approximate score (the c best approximate scores bound the c-th best exact
 // score from below by T - E), so the exact top c lies among the candidates
@@ -598,7 +599,7 @@ __global__ __launch_bounds__(256) void route_filter_kernel(
     int32_t d, int64_t nq, const int32_t* __restrict__ l1_order32,
     const int32_t* __restrict__ l1, int32_t wst, const int32_t* __restrict__ lst, int32_t lcap,
     const float* __restrict__ rs, int32_t rstride, int dense, const float* __restrict__ qnorm,
-    const float* __restrict__ cent_norm_max, double ecoef, int32_t c,
+    const float* __restrict__ cent_norm_max, double ecoef, double eadd, double esub, int32_t c,
     int32_t* __restrict__ rcand, int32_t* __restrict__ rcnt, int32_t* __restrict__ routed,
     int whole) {
   __shared__ int32_t cpos[4][kCandCap];
@@ -662,8 +663,7 @@ __global__ __launch_bounds__(256) void route_filter_kernel(
     }
     prev = wave_min_u64(best);
   }
-  const double E = ecoef * double(qn) * double(cmax) +
-                   double(d) * 7.888609052210118e-31;  // d * 2^-100: subnormal products
+  const double E = ecoef * double(qn) * double(cmax) + eadd + esub * (double(qn) + double(cmax));
   const double thr = double(key_score(uint32_t(prev >> 32))) - 2.0 * E;
   // candidates in window order: their window entries in LDS (positions are
   // looked up only for them)
@@ -1137,17 +1137,15 @@ struct WaveShared {
   uint32_t lm[CAP][4];  // membership bits of the tile's rows (several arrays)
 };
 
-// Tile fetch, one tile per wave.  Direct (persistent = 0): workgroups are
-// dealt to the 8 XCDs round-robin, so the block -> tile map gives each XCD a
-// contiguous run of tiles (the same clusters, the same query rows, one L2) and
-// the 4 waves of a block take 4 consecutive tiles.
+// Tile fetch, one tile per wave.  Direct (persistent = 0): the workgroups
+// (one wave each) are dealt to the 8 XCDs round-robin, so the block -> tile
+// map gives each XCD a contiguous run of tiles (the same clusters, the same
+// query rows, one L2).
 __device__ inline int32_t direct_tile(int32_t ntiles) {
-  const int32_t nb = (ntiles + 3) / 4;  // blocks of 4 tiles
-  const int32_t per = (nb + 7) / 8;
+  const int32_t per = (ntiles + 7) / 8;
   const int32_t xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
-  const int32_t b = xcd * per + loc;
-  const int32_t t = b * 4 + int32_t(threadIdx.x >> 6);
-  return (loc < per && b < nb && t < ntiles) ? t : -1;
+  const int32_t t = xcd * per + loc;
+  return (loc < per && t < ntiles) ? t : -1;
 }
 
 // Persistent fetch state of one wave.
@@ -1197,11 +1195,13 @@ __device__ inline int32_t fetch_tile(int persistent, int32_t ntiles, int32_t* __
 // v_mfma_f32_16x16x4f32, one float4 of both operands feeds 4 MFMAs; bf16:
 // v_mfma_f32_16x16x32_bf16, 8 consecutive bf16 per lane), then writes each
 // finished score from its accumulator straight into the pair's window score
-// row (16 consecutive rows per store).  No cross-wave reduction or barrier:
-// the 4 waves of a workgroup run their tiles independently.  A score is one
+// row (16 consecutive rows per store).  A workgroup is one wave: no
+// cross-wave reduction or barrier, and a wave that finishes early frees its
+// slot for the next tile at once (a workgroup of 4 tiles held all 4 slots
+// until its slowest tile was done: 2-10 % slower).  A score is one
 // accumulator summed over the k-steps in order, so results do not depend on
 // the tile size, the schedule or which other pairs share a pass.
-constexpr int kRerankWaves = 4;
+constexpr int kRerankNT = 64;  // threads per rerank workgroup (one wave)
 
 // A wave-uniform value, moved to a scalar register.
 __device__ inline int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -1541,7 +1541,7 @@ constexpr int rerank_waves_per_eu() {
 }
 
 template <int RT, int FMT, bool VEC, bool NT, int NPCM = 2>
-__global__ __launch_bounds__(256, (rerank_waves_per_eu<RT, NPCM>())) void rerank_kernel(
+__global__ __launch_bounds__(kRerankNT, (rerank_waves_per_eu<RT, NPCM>())) void rerank_kernel(
     const void* __restrict__ Xv, int32_t d, const int32_t* __restrict__ tiles, int32_t ntiles,
     const int32_t* __restrict__ cstart,
     const int32_t* __restrict__ wl, const Pair* __restrict__ pairs, int32_t c,
@@ -1559,11 +1559,10 @@ __global__ __launch_bounds__(256, (rerank_waves_per_eu<RT, NPCM>())) void rerank
   // the tiles' first blocks); the others read row-major rows
   constexpr bool kTiled = VEC && (FMT == kF32W || FMT == kBF16W);
   typedef typename std::conditional<kTiled, TileRows<F, RC>, PtrRows<F, RC>>::type Src;
-  __shared__ WaveShared<CAP> shw[kRerankWaves];
+  __shared__ WaveShared<CAP> sh;
   const XE* X = static_cast<const XE*>(Xv);
   const QE* Q = static_cast<const QE*>(Qv);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  WaveShared<CAP>& sh = shw[wave];
+  const int lane = threadIdx.x & 63;
   const int i = lane & 15, s = lane >> 4;
   const int nsteps = (d + F::KS - 1) / F::KS;
   const int sub = F::SUBW * s;
@@ -1828,25 +1827,47 @@ __global__ __launch_bounds__(256) void l1_gemm_kernel(const void* __restrict__ Q
 // padded to 72 bf16 (144 B) so the 16 lanes of a fragment read spread over
 // the LDS banks.  Tiles are dealt to the 8 XCDs round-robin so consecutive
 // tiles of one XCD share their query rows in its L2.
+//
+// SPLIT: both operands are read in fp32 and each value x is split on its way
+// into LDS into h = bf16(x) and l = bf16(x - h) (x - h is exact in fp32), and
+// the tile accumulates h_q h_mu + h_q l_mu + l_q h_mu: three MFMAs per
+// fragment pair, scores within about 3 2^-16 |q| |mu| plus the fp32
+// accumulation error instead of 2^-7 |q| |mu|.  With c > 1 that decides the
+// routing for most queries without FP64 rescoring (1M x 768, 1,000 clusters,
+// c = 8: 21 candidates per query with the bf16 band, 8.2 with the split one).
 constexpr int kLdsK = 64, kLdsRow = 72;
+
+__device__ inline void split_bf16x8(const float4& a, const float4& b, bf16x8& hi, bf16x8& lo) {
+  const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  __hip_bfloat16 h[8], l[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    h[e] = __float2bfloat16(v[e]);
+    l[e] = __float2bfloat16(v[e] - __bfloat162float(h[e]));
+  }
+  hi = __builtin_bit_cast(bf16x8, h);
+  lo = __builtin_bit_cast(bf16x8, l);
+}
 
 //
 // The first l1_blocks workgroups (a multiple of 8) instead run the layer-1
 // locate (l1_item) of 256 items each: both only need the hash kernel's
 // output, so one launch runs them side by side.
-__global__ __launch_bounds__(256, 3) void l1_gemm_lds_kernel(const __hip_bfloat16* __restrict__ Q,
-                                                          int64_t nq,
-                                                          const __hip_bfloat16* __restrict__ Cc,
-                                                          int32_t C, int32_t d,
-                                                          float* __restrict__ rs, L1Args la,
-                                                          unsigned l1_blocks) {
-  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sa[1][128 * kLdsRow];
-  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sb[1][128 * kLdsRow];
+template <bool SPLIT>
+__global__ __launch_bounds__(256, SPLIT ? 2 : 3) void l1_gemm_lds_kernel(
+    const void* __restrict__ Qv, int64_t nq, const void* __restrict__ Cv, int32_t C, int32_t d,
+    float* __restrict__ rs, L1Args la, unsigned l1_blocks) {
+  constexpr int NP = SPLIT ? 2 : 1;  // operand parts in LDS (high, low)
+  typedef typename std::conditional<SPLIT, float, __hip_bfloat16>::type E;
+  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sa[NP][128 * kLdsRow];
+  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sb[NP][128 * kLdsRow];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (blockIdx.x < l1_blocks) {
     l1_item(la, int64_t(blockIdx.x) * 256 + tid);
     return;
   }
+  const E* Q = static_cast<const E*>(Qv);
+  const E* Cc = static_cast<const E*>(Cv);
   const unsigned bid = blockIdx.x - l1_blocks;
   const int i = lane & 15, s = lane >> 4;
   const int64_t ntc = (C + 127) / 128;
@@ -1856,28 +1877,49 @@ __global__ __launch_bounds__(256, 3) void l1_gemm_lds_kernel(const __hip_bfloat1
   if ((bid >> 3) >= per || t >= nblk) return;
   const int64_t m0 = (t / ntc) * 128;
   const int32_t n0 = int32_t(t % ntc) * 128;
-  // loader: thread tid moves 16 B (8 bf16) of rows tid / 8 + 32 j, columns 8 (tid % 8)
+  // loader: thread tid moves 8 values of rows tid / 8 + 32 j, columns 8 (tid % 8)
   const int lr = tid >> 3, lc = 8 * (tid & 7);
-  const __hip_bfloat16* qsrc[4];
-  const __hip_bfloat16* csrc[4];
+  const E* qsrc[4];
+  const E* csrc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     qsrc[j] = Q + min(m0 + lr + 32 * j, nq - 1) * d + lc;
     csrc[j] = Cc + int64_t(min(n0 + lr + 32 * j, C - 1)) * d + lc;
   }
-  bf16x8 ra[4], rb[4];
+  bf16x8 ra[4], rb[4];          // bf16 operands in flight
+  float4 fa4[4][2], fb4[4][2];  // fp32 operands in flight (SPLIT)
   auto gload = [&](int kc) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      ra[j] = *reinterpret_cast<const bf16x8*>(qsrc[j] + kc * kLdsK);
-      rb[j] = *reinterpret_cast<const bf16x8*>(csrc[j] + kc * kLdsK);
+      if constexpr (SPLIT) {
+        const float4* qa = reinterpret_cast<const float4*>(qsrc[j] + kc * kLdsK);
+        const float4* ca = reinterpret_cast<const float4*>(csrc[j] + kc * kLdsK);
+        fa4[j][0] = qa[0];
+        fa4[j][1] = qa[1];
+        fb4[j][0] = ca[0];
+        fb4[j][1] = ca[1];
+      } else {
+        ra[j] = *reinterpret_cast<const bf16x8*>(qsrc[j] + kc * kLdsK);
+        rb[j] = *reinterpret_cast<const bf16x8*>(csrc[j] + kc * kLdsK);
+      }
     }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&]() {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      *reinterpret_cast<bf16x8*>(&sa[buf][(lr + 32 * j) * kLdsRow + lc]) = ra[j];
-      *reinterpret_cast<bf16x8*>(&sb[buf][(lr + 32 * j) * kLdsRow + lc]) = rb[j];
+      const int o = (lr + 32 * j) * kLdsRow + lc;
+      if constexpr (SPLIT) {
+        bf16x8 h, l;
+        split_bf16x8(fa4[j][0], fa4[j][1], h, l);
+        *reinterpret_cast<bf16x8*>(&sa[0][o]) = h;
+        *reinterpret_cast<bf16x8*>(&sa[NP - 1][o]) = l;
+        split_bf16x8(fb4[j][0], fb4[j][1], h, l);
+        *reinterpret_cast<bf16x8*>(&sb[0][o]) = h;
+        *reinterpret_cast<bf16x8*>(&sb[NP - 1][o]) = l;
+      } else {
+        *reinterpret_cast<bf16x8*>(&sa[0][o]) = ra[j];
+        *reinterpret_cast<bf16x8*>(&sb[0][o]) = rb[j];
+      }
     }
   };
   const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;
@@ -1888,29 +1930,43 @@ __global__ __launch_bounds__(256, 3) void l1_gemm_lds_kernel(const __hip_bfloat1
     for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int nk = d / kLdsK;
   gload(0);
-  lstore(0);
+  lstore();
   __syncthreads();
   for (int kc = 0; kc < nk; ++kc) {
-    const int buf = 0;
     if (kc + 1 < nk) gload(kc + 1);  // in flight while this chunk is consumed
 #pragma unroll
     for (int kk = 0; kk < kLdsK; kk += 32) {
-      bf16x8 fa[4], fb[4];
+      bf16x8 fa[NP][4], fb[NP][4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-        fa[a] = *reinterpret_cast<const bf16x8*>(&sa[buf][(wr + 16 * a + i) * kLdsRow + kk + 8 * s]);
+      for (int h = 0; h < NP; ++h) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        fb[b] = *reinterpret_cast<const bf16x8*>(&sb[buf][(wc + 16 * b + i) * kLdsRow + kk + 8 * s]);
+        for (int a = 0; a < 4; ++a)
+          fa[h][a] = *reinterpret_cast<const bf16x8*>(&sa[h][(wr + 16 * a + i) * kLdsRow + kk + 8 * s]);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          fb[h][b] = *reinterpret_cast<const bf16x8*>(&sb[h][(wc + 16 * b + i) * kLdsRow + kk + 8 * s]);
+      }
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][a], fb[0][b], acc[a][b], 0, 0, 0);
+      if constexpr (SPLIT) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][a], fb[NP - 1][b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[NP - 1][a], fb[0][b], acc[a][b], 0, 0, 0);
+      }
     }
     __syncthreads();  // every wave is done with this chunk before it is overwritten
     if (kc + 1 < nk) {
-      lstore(0);
+      lstore();
       __syncthreads();
     }
   }
@@ -2744,22 +2800,22 @@ void launch_score_n(const Index& ix, bool bf16, bool vec, bool bvec, unsigned gr
                     int32_t mw, hipStream_t st) {
   const int32_t nt = ix.n_tiles[ti];
   if (bf16 && !bvec)
-    hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false, NPCM>), dim3(grid), dim3(256), 0,
+    hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false, NPCM>), dim3(grid), dim3(kRerankNT), 0,
                        st, (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
                        alist, pmask, mw, ix.tile_blk[ti]);
   else if (bf16)
-    hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false, NPCM>), dim3(grid), dim3(256), 0,
+    hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false, NPCM>), dim3(grid), dim3(kRerankNT), 0,
                        st, (const void*)ix.Xbt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
                        alist, pmask, mw, ix.tile_blk[ti]);
   else if (vec)
-    hipLaunchKernelGGL((rerank_kernel<RT, kF32W, true, false, NPCM>), dim3(grid), dim3(256), 0,
+    hipLaunchKernelGGL((rerank_kernel<RT, kF32W, true, false, NPCM>), dim3(grid), dim3(kRerankNT), 0,
                        st, (const void*)ix.Xt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
                        alist, pmask, mw, ix.tile_blk[ti]);
   else
-    hipLaunchKernelGGL((rerank_kernel<RT, kF32W, false, false, NPCM>), dim3(grid), dim3(256), 0,
+    hipLaunchKernelGGL((rerank_kernel<RT, kF32W, false, false, NPCM>), dim3(grid), dim3(kRerankNT), 0,
                        st, (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
                        alist, pmask, mw, ix.tile_blk[ti]);
@@ -2775,10 +2831,10 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
                   hipStream_t st) {
   const int32_t nt = ix.n_tiles[ti];
   unsigned grid;
-  if (persistent)
-    grid = unsigned(std::max(8, ix.n_cu * grid_mult / 8 * 8));
+  if (persistent)  // grid_mult waves per SIMD
+    grid = unsigned(std::max(8, 4 * ix.n_cu * grid_mult / 8 * 8));
   else
-    grid = unsigned(((nt + 3) / 4 + 7) / 8 * 8);
+    grid = unsigned((nt + 7) / 8 * 8);
   // the wide feeds read the operand-ordered copies; without one (no room at
   // build time), the row-major rows
   const bool vec = (ix.d % 32 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0) && ix.Xt;
@@ -2806,29 +2862,28 @@ void launch_l1_scores(const Index& ix, bool fp8, int64_t nq, const int32_t* l1cs
                       const Pair* l1pairs, const float* Q, const __hip_bfloat16* Qb, float* rs,
                       int32_t r1, hipStream_t st) {
   const int32_t nt = ix.n_l1_tiles;
-  const dim3 grid(unsigned(((nt + 3) / 4 + 7) / 8 * 8),
-                  unsigned((nq + kL1PairChunk - 1) / kL1PairChunk));
+  const dim3 grid(unsigned((nt + 7) / 8 * 8), unsigned((nq + kL1PairChunk - 1) / kL1PairChunk));
   const bool vec = (ix.d % 16 == 0) && ((reinterpret_cast<uintptr_t>(Q) & 15) == 0);
   if (fp8 && ix.d % 32 != 0)
-    hipLaunchKernelGGL((rerank_kernel<64, kFP8, false, false>), grid, dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<64, kFP8, false, false>), grid, dim3(kRerankNT), 0, st,
                        (const void*)ix.cent8, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale,
                        (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr);
   else if (fp8)
-    hipLaunchKernelGGL((rerank_kernel<64, kFP8, true, false>), grid, dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<64, kFP8, true, false>), grid, dim3(kRerankNT), 0, st,
                        (const void*)ix.cent8, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale,
                        (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr);
   else if (vec)
-    hipLaunchKernelGGL((rerank_kernel<64, kF32, true, false>), grid, dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<64, kF32, true, false>), grid, dim3(kRerankNT), 0, st,
                        (const void*)ix.cent_l1, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr,
                        (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr);
   else
-    hipLaunchKernelGGL((rerank_kernel<64, kF32, false, false>), grid, dim3(256), 0, st,
+    hipLaunchKernelGGL((rerank_kernel<64, kF32, false, false>), grid, dim3(kRerankNT), 0, st,
                        (const void*)ix.cent_l1, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr,
@@ -2859,14 +2914,20 @@ void launch_l1_gemm_mb(const Index& ix, bool fp8, int64_t nq, const float* Q,
 
 // bf16 query x bf16 centroid product (candidate scores of the exact routing).
 // With la (d a multiple of 64 only), the same launch also runs the layer-1
-// locate of every (query, array) item.
+// locate of every (query, array) item.  Qf (d a multiple of 64, 16-byte
+// aligned): the split product of the fp32 queries and centroids instead.
 void launch_l1_gemm_bf16(const Index& ix, int64_t nq, const __hip_bfloat16* Qb, float* rs,
-                         hipStream_t st, const L1Args* la = nullptr) {
+                         hipStream_t st, const L1Args* la = nullptr, const float* Qf = nullptr) {
   if (ix.d % kLdsK == 0) {
     const int64_t nblk = (nq + 127) / 128 * ((ix.C + 127) / 128);
     const unsigned l1b = la ? unsigned((la->nq * la->H + 255) / 256 + 7) / 8 * 8 : 0u;
-    hipLaunchKernelGGL(l1_gemm_lds_kernel, dim3(l1b + unsigned((nblk + 7) / 8 * 8)), dim3(256), 0,
-                       st, Qb, nq, ix.cent_l1_b, ix.C, ix.d, rs, la ? *la : L1Args{}, l1b);
+    const dim3 grid(l1b + unsigned((nblk + 7) / 8 * 8));
+    if (Qf)
+      hipLaunchKernelGGL(l1_gemm_lds_kernel<true>, grid, dim3(256), 0, st, (const void*)Qf, nq,
+                         (const void*)ix.cent_l1, ix.C, ix.d, rs, la ? *la : L1Args{}, l1b);
+    else
+      hipLaunchKernelGGL(l1_gemm_lds_kernel<false>, grid, dim3(256), 0, st, (const void*)Qb, nq,
+                         (const void*)ix.cent_l1_b, ix.C, ix.d, rs, la ? *la : L1Args{}, l1b);
     return;
   }
   const int64_t nblk4 = (nq + 127) / 128 * ((ix.C + kGemmTileN - 1) / kGemmTileN);
@@ -2952,7 +3013,11 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   // exact routing (or, for fp8 window scores, the approximate routing) over
   // each query's window or union list.  The bf16 queries these need are
   // written by the hash kernel.
-  const bool l1b = !fp8 && o.l1_dense == 0 && ix.cent_l1_b;
+  const bool l1b = !fp8 && (o.l1_dense == 0 || o.l1_dense >= 2) && ix.cent_l1_b;
+  // the split bf16 product (three MFMAs per fragment pair) when c > 1 or asked
+  // for; it reads the fp32 queries with 16-byte loads
+  const bool split = l1b && ix.d % kLdsK == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0 &&
+                     (o.l1_dense == 3 || (o.l1_dense == 0 && c > 1));
   mark(0);
   // the hash launch also clears the counters (it writes no status: digits are clamped)
   const HashZero zr{ctr, int32_t(kCtrWords), ccount, cfill, C, 0};
@@ -2967,7 +3032,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   // launch; otherwise it has a launch of its own
   const bool l1_fused = p.l1_dense_rows && l1b && ix.d % kLdsK == 0;
   if (l1_fused)
-    launch_l1_gemm_bf16(ix, nq, qb, rs, st, &la);
+    launch_l1_gemm_bf16(ix, nq, qb, rs, st, &la, split ? Q : nullptr);
   else
     hipLaunchKernelGGL(l1_kernel, dim3(unsigned((nl1 + 255) / 256)), dim3(256), 0, st, la);
   if (o.expand_bits > 0)
@@ -2990,6 +3055,9 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
     lstp = lst;
   }
   double ecoef = dot_err_coef(ix.d);  // fp32 scores
+  // absolute terms: subnormal products (d 2^-100) and, for the split product,
+  // operand parts flushed or rounded below 2^-126 (a multiple of |q| + max|mu|)
+  double eadd = double(ix.d) * 7.888609052210118e-31, esub = 0.0;
   if (!p.l1_dense_rows) {
     launch_l1_scores(ix, fp8, nq, l1cs, l1pairs, Q, qb, rs, p.r1, st);
     if (fp8) {
@@ -3002,6 +3070,19 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
       ecoef = (ub + (1.0 + ub) * (u8 + 2.384185791015625e-07 + sub) +
                1.1 * dot_err_coef(ix.d) * (1.0 + ub) + 2.0 * 5.9604644775390625e-08) * 1.01;
     }
+  } else if (split) {
+    if (!l1_fused) launch_l1_gemm_bf16(ix, nq, qb, rs, st, nullptr, Q);
+    // x = h + l + r with |x - h| <= u |x|, |l| <= u (1 + u) |x|, |r| <= u^2 |x|
+    // (u = 2^-8) for q and mu elementwise; the terms the three products drop,
+    // h_q r_mu + l_q l_mu + l_q r_mu + r_q mu, are within (2 (1 + u)^2 + 1) u^2
+    // sum |q_l mu_l|, and the fp32 accumulation of the 3d exact products within
+    // dot_err_coef(3d) of their absolute sum, at most (1 + u)^2 (1 + 2u) sum
+    // |q_l mu_l|; sum |q_l mu_l| <= |q| |mu|
+    const double u = 0.00390625;
+    ecoef = ((2.0 * (1.0 + u) * (1.0 + u) + 1.0) * u * u +
+             dot_err_coef(3 * ix.d) * (1.0 + u) * (1.0 + u) * (1.0 + 2.0 * u)) * 1.01;
+    eadd = 3.0 * double(ix.d) * 7.888609052210118e-31;
+    esub = 3.0 * std::sqrt(double(ix.d)) * 1.1754943508222875e-38;  // 2^-126
   } else if (l1b) {
     if (!l1_fused) launch_l1_gemm_bf16(ix, nq, qb, rs, st);
     const double u = 0.00390625;  // 2^-8: bf16 rounding of each operand
@@ -3018,11 +3099,11 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
     if (p.lcap <= 16 * 64)
       hipLaunchKernelGGL(route_filter_kernel<16>, dim3(fgrid), dim3(256), 0, st, ix.d, nq,
                          ix.l1_order32, l1w, wst, lstp, p.lcap, rs, rstride, dense, qnorm,
-                         ix.cent_norm_max, ecoef, c, rcand, rcnt, routed, whole);
+                         ix.cent_norm_max, ecoef, eadd, esub, c, rcand, rcnt, routed, whole);
     else
       hipLaunchKernelGGL(route_filter_kernel<0>, dim3(fgrid), dim3(256), 0, st, ix.d, nq,
                          ix.l1_order32, l1w, wst, lstp, p.lcap, rs, rstride, dense, qnorm,
-                         ix.cent_norm_max, ecoef, c, rcand, rcnt, routed, whole);
+                         ix.cent_norm_max, ecoef, eadd, esub, c, rcand, rcnt, routed, whole);
     hipLaunchKernelGGL(route_rescore_kernel, dim3(wgrid), dim3(256), 0, st, Q, ix.d, nq,
                        ix.cent_l1, ix.l1_order32, l1w, wst, lstp, p.lcap, c, rcand, rcnt, rs64,
                        routed);

@@ -179,10 +179,10 @@ def test_mid_two_streams_identical(mid):
 
 @pytest.mark.parametrize("precision", ["f32", "bf16"])
 def test_mid_dense_layer1_identical(mid, precision):
-    """r1 = C: the bf16-candidate routing, the fp32 dense GEMM and the window
-    kernel route identically (the window kernel on an index with fp8
-    centroids scores those, approximately, in the precision form: not
-    compared here)."""
+    """r1 = C: the bf16-candidate routing (split by default at c > 1, plain
+    and split forced), the fp32 dense GEMM and the window kernel route
+    identically (the window kernel on an index with fp8 centroids scores
+    those, approximately, in the precision form: not compared here)."""
     torch = _torch()
     from paper_2205_00970_amd import lider
     X, Q = mid["X"], mid["Q"]
@@ -196,7 +196,7 @@ def test_mid_dense_layer1_identical(mid, precision):
     for sl in (slice(None), slice(5, 6), slice(17, 300)):
         q = Qd[sl].contiguous()
         a = gi.search(q, 10, 3, 500, r1=64, precision=precision, debug=True)
-        for mode in ((False, 1) if precision == "f32" else (1,)):
+        for mode in ((False, 1, 2, 3) if precision == "f32" else (1, 2, 3)):
             # window kernel; dense fp32 without bf16 candidates
             b = gi.search(q, 10, 3, 500, r1=64, precision=precision, debug=True, l1_dense=mode)
             # the routed sets agree (their listing order is not part of the result)
@@ -204,10 +204,12 @@ def test_mid_dense_layer1_identical(mid, precision):
             assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
 
 
-def test_mid_routing_near_ties(mid):
+@pytest.mark.parametrize("l1_dense", [0, 2, 3])
+def test_mid_routing_near_ties(mid, l1_dense):
     """Queries with many equal or nearly equal centroid scores (zero vectors,
     midpoints of two centroids, tiny perturbations of them): the bf16-candidate
-    routing still returns the FP64 routed sets of the oracle."""
+    routing (automatic, plain bf16, split bf16) still returns the FP64 routed
+    sets of the oracle."""
     torch = _torch()
     X, gi, oi = mid["X"], mid["gi"], mid["oi"]
     cent = oi.centroids()
@@ -220,7 +222,8 @@ def test_mid_routing_near_ties(mid):
         rows.append(mpt + 1e-6 * rng.standard_normal(768))
     Q = np.ascontiguousarray(np.stack(rows).astype(np.float32))
     for c in (1, 2, 5):
-        ids, sc, dbg = gi.search(torch.from_numpy(Q).cuda(), 10, c, 300, r1=64, debug=True)
+        ids, sc, dbg = gi.search(torch.from_numpy(Q).cuda(), 10, c, 300, r1=64, debug=True,
+                                 l1_dense=l1_dense)
         oids, osc, odbg = oi.search(Q, 10, c, 300, 64, debug=True)
         compare_debug(dbg, odbg)
         compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
