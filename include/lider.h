@@ -197,9 +197,14 @@ const char* lider_last_error(void);
  *                 window overlaps are first collected into a work list on the
  *                 device and a persistent grid pulls only those (for small or
  *                 sparse batches on large indexes).  Results are identical.
- *  tile_rows      rows per rerank tile (one wave per tile): 32, 64, 128, or 0
- *                 (chosen with pass_pairs from the expected number of pairs
- *                 overlapping a tile: 64 when it is at most 16, else 32).
+ *  tile_rows      rows per rerank tile: 32 or 64 (one wave per tile), 128 (with
+ *                 the operand-ordered copy of the precision asked for and
+ *                 persistent = 0: a workgroup of 4 waves per tile, 32 rows
+ *                 each, sharing the tile's pair list and each pass's query
+ *                 rows through LDS; else one wave per tile), or 0: 128 when
+ *                 the workgroup form applies, else 64 or 32 from the expected
+ *                 number of pairs overlapping a tile.  pass_pairs 0 then
+ *                 follows the same estimate.  Results are identical.
  *  l1_dense       How the layer-1 scores are computed; the routed set is then
  *                 decided exactly (the FP64 definition): the centroids whose
  *                 score lies within twice its rigorous error bound of the c-th

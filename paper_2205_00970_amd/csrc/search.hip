@@ -59,23 +59,41 @@ struct Plan {
   int32_t lcap, mw;
 };
 
-// Rerank tile table in use: 0/1/2 = 32/64/128 rows per tile (default 64:
-// measured fastest or within 2 % of it from whole clusters to 256-row windows).
 // Rerank shape: rows per tile (index into the tile tables: 32, 64, 128) and
 // 16-pair column blocks per MFMA pass.  A tile overlapped by P pairs is
-// streamed ceil(P / pass) times, while a wider pass holds more accumulators
-// (fewer waves per SIMD to hide latency).  Unless the caller fixes them, both
-// follow the expected overlap: the pairs per cluster times the share of a
-// cluster that one pair's window (for several arrays, the hull of its H
-// windows) covers, widened by a 64-row tile.  On the 1M x 768 workload about
-// 10 pairs per tile (each query's whole top cluster) run fastest with 64-row
-// tiles and 32-pair passes, about 26 (c = 8, r = 256) with 32-row tiles and
-// 64-pair passes, about 80 (ten arrays) with 32-row tiles and 128-pair passes.
+// streamed ceil(P / pass) times, while a wider pass holds more accumulators.
+// Unless the caller fixes them, both follow the expected overlap: the pairs
+// per cluster times the share of a cluster that one pair's window (for several
+// arrays, the hull of its H windows) covers, widened by the tile.  With the
+// operand-ordered copy of the precision asked for and the direct schedule the
+// workgroup rerank takes 128-row tiles and a pass of at least twice the
+// expected overlap (the overlap varies from tile to tile; a second pass
+// re-streams the tile): 16 or 32 pairs, else 128 (1M x 768: about 10 pairs per
+// 128-row tile at c = 1 -> 32-pair passes; 31 at c = 8, r = 256 and 80 with
+// ten arrays -> 128).  Otherwise the per-wave
+// rerank: about 10 pairs per tile run fastest with 64-row tiles and 32-pair
+// passes, about 26 with 32-row tiles and 64-pair passes, about 80 with 32-row
+// tiles and 128-pair passes.
 void rerank_shape(const Index& ix, int64_t nq, int32_t c, int32_t r, const lider_search_opts& o,
                   int* ti, int* npcm) {
   const double lbar = std::max(1.0, double(ix.n) / double(ix.C));
   const double span = std::min(lbar, double(ix.H) * std::min(double(r), lbar));
-  const double est = double(nq) * c / double(ix.C) * std::min(1.0, (span + 64.0) / lbar);
+  const double per_cluster = double(nq) * c / double(ix.C);
+  const bool bf16 = o.precision == LIDER_BF16;
+  const bool wg_ok = o.persistent == 0 && (bf16 ? (ix.d % 64 == 0 && ix.Xbt) : (ix.d % 32 == 0 && ix.Xt));
+  if (wg_ok && (o.tile_rows == 0 || o.tile_rows == 128)) {
+    *ti = 2;
+    if (o.pass_pairs > 0) {
+      *npcm = o.pass_pairs / 16;
+    } else {
+      // 16 or 32 pairs keep three waves per SIMD; wider passes hold two
+      // either way, so beyond 32 the widest (one pass for most tiles)
+      const double est = per_cluster * std::min(1.0, (span + 128.0) / lbar);
+      *npcm = 2.0 * est <= 16.0 ? 1 : 2.0 * est <= 32.0 ? 2 : 8;
+    }
+    return;
+  }
+  const double est = per_cluster * std::min(1.0, (span + 64.0) / lbar);
   const int wide = est <= 16.0 ? 0 : est <= 48.0 ? 1 : 2;
   if (o.tile_rows == 32) *ti = 0;
   else if (o.tile_rows == 64) *ti = 1;
@@ -1716,6 +1734,271 @@ __global__ __launch_bounds__(kRerankNT, (rerank_waves_per_eu<RT, NPCM>())) void 
   }
 }
 
+// Workgroup rerank of one 128-row tile (the operand-ordered feeds, direct
+// schedule).  The 4 waves of a workgroup take 32 rows each and share one list
+// of the pairs overlapping the whole tile, so every query row a pass needs is
+// read from L2 once per workgroup instead of once per wave: per k-step the
+// workgroup stages the pass's query block (16 NPC rows x one k-step) in LDS,
+// two steps ahead through registers, and each wave reads it back with 16-byte
+// LDS loads.  The registers the per-wave query buffers held now carry a
+// deeper row stream: each wave's own rows are loaded three k-steps ahead (a
+// ring of four register sets).  One barrier per k-step publishes the next
+// query block.  The MFMA sequence of every (pair, row) score is the one of
+// rerank_kernel (same feed, same k order), so scores are bit-identical to it.
+//
+// Per k-step k: issue the staging loads of query block k + 2 and the row
+// loads of step k + 3; read query block k from LDS; the MFMAs of step k;
+// write the staged block k + 1 to LDS; barrier.  The list is filled by all 4
+// waves, 256 pairs per round (each wave 64, slots by an LDS counter); the
+// order of the entries is immaterial to the results.  Every loop bound and
+// branch around a barrier is workgroup-uniform.
+constexpr int kWgRing = 4;    // row register sets per wave (rows three steps ahead)
+constexpr int kWgRound = 256;  // pairs tested per fill round
+constexpr int kWgQRow = 144;   // bytes per staged query row: one k-step (128 B) + 16 B pad
+constexpr int kWgQBlk = 16 * kWgQRow;
+
+template <int FMT, int NPCM>
+struct WgShared {
+  static constexpr int CAP = 16 * NPCM + kWgRound;
+  int32_t lp[CAP], lq[CAP], ls[CAP], le[CAP];
+  uint32_t lm[CAP][4];  // membership bits of the tile's 128 rows (several arrays)
+  __attribute__((aligned(16))) unsigned char qs[2][NPCM * kWgQBlk];
+  int32_t n;
+};
+
+// One pass over NPC column blocks: acc[rc][pc] of the wave's 32 rows.
+template <int FMT, int NPC, int NPCM>
+__device__ __forceinline__ void wg_pass(WgShared<FMT, NPCM>& sh, const TileRows<Feed<FMT, true>, 2>& xr,
+                                        const typename Feed<FMT, true>::QE* __restrict__ Q, int32_t d,
+                                        int np, int nsteps, floatx4 (&acc)[2][NPCM]) {
+  typedef Feed<FMT, true> F;
+  typedef typename F::T T;
+  typedef typename F::QE QE;
+  constexpr int RC = 2;
+  constexpr int NCH = (NPC * 128 + 255) / 256;  // 16-byte staging chunks per thread
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int i = lane & 15, s = lane >> 4;
+  const int sub = F::SUBW * s;
+  // staging chunk u = tid + 256 j: column block u / 128, pair row (u / 8) % 16,
+  // 16-byte part u % 8 of the k-step
+  const QE* qsrc[NCH];
+  int qdst[NCH];
+  bool qon[NCH];
+#pragma unroll
+  for (int j = 0; j < NCH; ++j) {
+    const int u = tid + 256 * j;
+    const int pc = u >> 7, r = (u >> 3) & 15, part = u & 7;
+    qon[j] = pc < NPC;
+    const int e = qon[j] ? min(16 * pc + r, np - 1) : 0;
+    qsrc[j] = Q + int64_t(sh.lq[e]) * d + part * (16 / int(sizeof(QE)));
+    qdst[j] = pc * kWgQBlk + r * kWgQRow + part * 16;
+  }
+  floatx4 sg[2][NCH];
+  auto stage_load = [&](int k, floatx4 (&dst)[NCH]) {
+#pragma unroll
+    for (int j = 0; j < NCH; ++j)
+      if (qon[j]) dst[j] = *reinterpret_cast<const floatx4*>(qsrc[j] + k * F::KS);
+  };
+  auto stage_store = [&](int slot, const floatx4 (&src)[NCH]) {
+#pragma unroll
+    for (int j = 0; j < NCH; ++j)
+      if (qon[j]) *reinterpret_cast<floatx4*>(&sh.qs[slot][qdst[j]]) = src[j];
+  };
+  // the wave's query operands of step k from LDS slot k % 2: lane (i, s)
+  // reads pair row i of each block at the lane's two 16-byte halves
+  auto qread = [&](int slot, T (&qv)[NPC]) {
+#pragma unroll
+    for (int pc = 0; pc < NPC; ++pc) {
+      const unsigned char* b = &sh.qs[slot][pc * kWgQBlk + i * kWgQRow + 16 * s];
+      qv[pc] = T{__builtin_bit_cast(decltype(T::a), *reinterpret_cast<const floatx4*>(b)),
+                 __builtin_bit_cast(decltype(T::b), *reinterpret_cast<const floatx4*>(b + 64))};
+    }
+  };
+  T xs[kWgRing][RC];
+  auto xload = [&](int k, T (&dst)[RC]) {
+#pragma unroll
+    for (int rc = 0; rc < RC; ++rc) dst[rc] = xr.load(rc, k * F::KS + sub, d, true);
+  };
+  // prologue: block 0 in LDS slot 0, block 1 staged, rows of steps 0..2 in flight
+  stage_load(0, sg[0]);
+  if (1 < nsteps) stage_load(1, sg[1]);
+  xload(0, xs[0]);
+  if (1 < nsteps) xload(1, xs[1]);
+  if (2 < nsteps) xload(2, xs[2]);
+  stage_store(0, sg[0]);
+  __syncthreads();
+#define LIDER_WG_STEP(K, XC, XN, SGN, SGW)                          \
+  if ((K) < nsteps) {                                               \
+    if ((K) + 2 < nsteps) stage_load((K) + 2, sg[SGN]);             \
+    if ((K) + 3 < nsteps) xload((K) + 3, xs[XN]);                   \
+    T qv[NPC];                                                      \
+    qread((K) & 1, qv);                                             \
+    mfma_step<F, RC, NPC, NPCM>(xs[XC], qv, acc);                   \
+    if ((K) + 1 < nsteps) stage_store(((K) + 1) & 1, sg[SGW]);      \
+    __syncthreads();                                                \
+  }
+  for (int k = 0; k < nsteps; k += 4) {
+    LIDER_WG_STEP(k, 0, 3, 0, 1)
+    LIDER_WG_STEP(k + 1, 1, 0, 1, 0)
+    LIDER_WG_STEP(k + 2, 2, 1, 0, 1)
+    LIDER_WG_STEP(k + 3, 3, 2, 1, 0)
+  }
+#undef LIDER_WG_STEP
+}
+
+template <int FMT, int NPCM>
+__global__ __launch_bounds__(256, 2) void rerank_wg_kernel(
+    const void* __restrict__ Xv, int32_t d, const int32_t* __restrict__ tiles, int32_t ntiles,
+    const int32_t* __restrict__ cstart, const int32_t* __restrict__ wl,
+    const Pair* __restrict__ pairs, int32_t c, const void* __restrict__ Qv,
+    float* __restrict__ sbuf, int32_t rcap, const uint32_t* __restrict__ pmask, int32_t mw,
+    const int32_t* __restrict__ tblk) {
+  typedef Feed<FMT, true> F;
+  typedef typename F::XE XE;
+  typedef typename F::QE QE;
+  constexpr int PP = 16 * NPCM;
+  constexpr int CAP = WgShared<FMT, NPCM>::CAP;
+  __shared__ WgShared<FMT, NPCM> sh;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, s = lane >> 4;
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  // workgroups dealt to the 8 XCDs round-robin: each XCD a contiguous run of tiles
+  const int32_t per = (ntiles + 7) / 8;
+  const int32_t tile = int32_t(blockIdx.x & 7) * per + int32_t(blockIdx.x >> 3);
+  if (int32_t(blockIdx.x >> 3) >= per || tile >= ntiles) return;  // the whole workgroup
+  const XE* X = static_cast<const XE*>(Xv);
+  const QE* Q = static_cast<const QE*>(Qv);
+  const int4 td = reinterpret_cast<const int4*>(tiles)[tile];
+  const int32_t j = td.x, row0 = td.y, rows_here = td.w;
+  const int32_t plo = cstart[j], phi = cstart[j + 1];
+  const int nsteps = d / F::KS;
+  TileRows<F, 2> xr;
+  {
+    constexpr int kChunk = 2 * TileRows<F, 2>::kHalf;
+    xr.base = X + (int64_t(tblk[tile]) + 2 * wave) * nsteps * kChunk + lane * (16 / int(sizeof(XE)));
+    xr.bstride = nsteps * kChunk;
+    xr.rows = max(0, min(32, rows_here - 32 * wave));
+  }
+  if (tid == 0) sh.n = 0;
+  __syncthreads();
+  int32_t pb = plo;
+  int n = 0;  // listed pairs not yet scored (workgroup-uniform)
+  for (;;) {
+    while (n < PP && pb < phi) {
+      const int32_t u = pb + 64 * wave + lane;
+      bool hit = false;
+      int32_t pi = 0;
+      Pair pr{0, 0, 0, 0};
+      if (u < phi) {
+        pi = wl ? wl[u] : u;
+        pr = pairs[pi];
+        hit = pr.s < row0 + rows_here && pr.s + pr.len > row0;
+      }
+      const uint64_t m = __ballot(hit);
+      int base = 0;
+      if (lane == 0 && m) base = atomicAdd(&sh.n, __popcll(m));
+      base = __shfl(base, 0);
+      if (hit) {
+        const int slot = base + __popcll(m & below);
+        sh.lp[slot] = pi;
+        sh.lq[slot] = pi / c;
+        sh.ls[slot] = pr.s;
+        sh.le[slot] = pr.s + pr.len;
+        if (pmask) {  // 128-row tiles start at multiples of 128 rows of the cluster
+#pragma unroll
+          for (int w = 0; w < 4; ++w) sh.lm[slot][w] = pmask[int64_t(pi) * mw + (row0 >> 5) + w];
+        }
+      }
+      pb += kWgRound;
+      __syncthreads();
+      n = sh.n;
+      __syncthreads();
+    }
+    if (n == 0) break;
+    const int np = min(PP, n);
+    const int npc = (np + 15) / 16;
+    floatx4 acc[2][NPCM];
+#pragma unroll
+    for (int rc = 0; rc < 2; ++rc)
+#pragma unroll
+      for (int pc = 0; pc < NPCM; ++pc) acc[rc][pc] = floatx4{0.f, 0.f, 0.f, 0.f};
+    switch (npc) {
+      case 1: wg_pass<FMT, 1, NPCM>(sh, xr, Q, d, np, nsteps, acc); break;
+      case 2:
+        if constexpr (NPCM >= 2) wg_pass<FMT, 2, NPCM>(sh, xr, Q, d, np, nsteps, acc);
+        break;
+      case 3:
+        if constexpr (NPCM >= 3) wg_pass<FMT, 3, NPCM>(sh, xr, Q, d, np, nsteps, acc);
+        break;
+      case 4:
+        if constexpr (NPCM >= 4) wg_pass<FMT, 4, NPCM>(sh, xr, Q, d, np, nsteps, acc);
+        break;
+      case 5:
+        if constexpr (NPCM >= 5) wg_pass<FMT, 5, NPCM>(sh, xr, Q, d, np, nsteps, acc);
+        break;
+      case 6:
+        if constexpr (NPCM >= 6) wg_pass<FMT, 6, NPCM>(sh, xr, Q, d, np, nsteps, acc);
+        break;
+      case 7:
+        if constexpr (NPCM >= 7) wg_pass<FMT, 7, NPCM>(sh, xr, Q, d, np, nsteps, acc);
+        break;
+      default:
+        if constexpr (NPCM >= 8) wg_pass<FMT, 8, NPCM>(sh, xr, Q, d, np, nsteps, acc);
+        break;
+    }
+    // D layout: acc[rc][pc][e] = pair 16 pc + 4 s + e, row 32 wave + 16 rc + i
+#pragma unroll
+    for (int pc = 0; pc < NPCM; ++pc) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int pp = 16 * pc + 4 * s + e;
+        if (pc < npc && pp < np) {
+          const int32_t a = sh.ls[pp], en = sh.le[pp];
+          float* dst = sbuf + int64_t(sh.lp[pp]) * rcap - a;
+#pragma unroll
+          for (int rc = 0; rc < 2; ++rc) {
+            const int rr = 32 * wave + 16 * rc + i;
+            const int32_t row = row0 + rr;
+            if (rr < rows_here && row >= a && row < en) {
+              float v = acc[rc][pc][e];
+              if (pmask && !((sh.lm[pp][rr >> 5] >> (rr & 31)) & 1u)) v = __builtin_nanf("");
+              __builtin_nontemporal_store(v, &dst[row]);
+            }
+          }
+        }
+      }
+    }
+    // the entries past this pass move to the front of the list
+    const int rest = n - np;
+    int32_t vp = 0, vq = 0, vs = 0, ve = 0;
+    uint32_t vm[4] = {0u, 0u, 0u, 0u};
+    if (tid < rest) {
+      vp = sh.lp[np + tid];
+      vq = sh.lq[np + tid];
+      vs = sh.ls[np + tid];
+      ve = sh.le[np + tid];
+      if (pmask) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) vm[w] = sh.lm[np + tid][w];
+      }
+    }
+    __syncthreads();
+    if (tid < rest) {
+      sh.lp[tid] = vp;
+      sh.lq[tid] = vq;
+      sh.ls[tid] = vs;
+      sh.le[tid] = ve;
+      if (pmask) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) sh.lm[tid][w] = vm[w];
+      }
+    }
+    if (tid == 0) sh.n = rest;
+    n = rest;
+    __syncthreads();
+  }
+}
+
 // Layer-1 scores when every query's centroid window is the whole layer 1
 // (r1 = C): the dense product rs[q][p] = <Q[q], cent_l1[p]>, a GEMM on MFMA.
 // One (32 MB) x 128 output tile per workgroup; workgroups are dealt to the 8
@@ -2821,8 +3104,46 @@ void launch_score_n(const Index& ix, bool bf16, bool vec, bool bvec, unsigned gr
                        alist, pmask, mw, ix.tile_blk[ti]);
 }
 
-// npcm: 16-pair column blocks per pass (1, 2, 4 or 8; 128-row tiles take at
-// most 2, 64-row tiles at most 4).
+template <int FMT, int NPCM>
+void launch_wg_n(const Index& ix, const void* X, const void* Qv, const int32_t* cstart,
+                 const int32_t* wl, const Pair* pairs, int32_t c, float* sbuf, int32_t rcap,
+                 const uint32_t* pmask, int32_t mw, hipStream_t st) {
+  const int32_t nt = ix.n_tiles[2];
+  hipLaunchKernelGGL((rerank_wg_kernel<FMT, NPCM>), dim3(unsigned((nt + 7) / 8 * 8)), dim3(256), 0,
+                     st, X, ix.d, ix.tiles[2], nt, cstart, wl, pairs, c, Qv, sbuf, rcap, pmask, mw,
+                     ix.tile_blk[2]);
+}
+
+// The workgroup rerank (128-row tiles, direct schedule) on the operand-ordered
+// copy of the precision asked for; false when that copy is missing.
+bool launch_score_wg(const Index& ix, bool bf16, const int32_t* cstart, const int32_t* wl,
+                     const Pair* pairs, int32_t c, const float* Q, const __hip_bfloat16* Qb,
+                     float* sbuf, int32_t rcap, int npcm, const uint32_t* pmask, int32_t mw,
+                     hipStream_t st) {
+  if (bf16 ? !(ix.d % 64 == 0 && ix.Xbt)
+           : !(ix.d % 32 == 0 && ix.Xt && (reinterpret_cast<uintptr_t>(Q) & 15) == 0))
+    return false;
+#define LIDER_WG(FMT, X, QP)                                                                   \
+  {                                                                                            \
+    if (npcm <= 1)                                                                             \
+      launch_wg_n<FMT, 1>(ix, X, QP, cstart, wl, pairs, c, sbuf, rcap, pmask, mw, st);         \
+    else if (npcm == 2)                                                                        \
+      launch_wg_n<FMT, 2>(ix, X, QP, cstart, wl, pairs, c, sbuf, rcap, pmask, mw, st);         \
+    else if (npcm <= 4)                                                                        \
+      launch_wg_n<FMT, 4>(ix, X, QP, cstart, wl, pairs, c, sbuf, rcap, pmask, mw, st);         \
+    else                                                                                       \
+      launch_wg_n<FMT, 8>(ix, X, QP, cstart, wl, pairs, c, sbuf, rcap, pmask, mw, st);         \
+  }
+  if (bf16)
+    LIDER_WG(kBF16W, (const void*)ix.Xbt, (const void*)Qb)
+  else
+    LIDER_WG(kF32W, (const void*)ix.Xt, (const void*)Q)
+#undef LIDER_WG
+  return true;
+}
+
+// npcm: 16-pair column blocks per pass (1, 2, 4 or 8; the per-wave rerank
+// takes at most 2 with 128-row tiles, at most 4 with 64-row tiles).
 template <int RT>
 void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, const int32_t* wl,
                   const Pair* pairs, int32_t c, const float* Q, const __hip_bfloat16* Qb,
@@ -3149,7 +3470,9 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   else if (tr == 64)
     launch_score<64>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
                      ctr + 8, alist, npcm, H > 1 ? pmask : (const uint32_t*)nullptr, p.mw, st);
-  else
+  else if (o.persistent || !launch_score_wg(ix, bf16, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap,
+                                            npcm, H > 1 ? pmask : (const uint32_t*)nullptr,
+                                            p.mw, st))
     launch_score<128>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
                       ctr + 8, alist, npcm, H > 1 ? pmask : (const uint32_t*)nullptr, p.mw, st);
   mark(4);

@@ -78,7 +78,8 @@ def test_mid10_search(mid10, k, c, r, r1):
 
 
 def test_mid10_schedules_identical(mid10):
-    """Persistent / plain rerank, all tile sizes, routing paths: bitwise equal."""
+    """Persistent / plain / workgroup rerank, all tile sizes, routing paths:
+    bitwise equal."""
     torch = _torch()
     Qd = torch.from_numpy(mid10["Q"]).cuda()
     gi = mid10["gi"]
@@ -86,7 +87,8 @@ def test_mid10_schedules_identical(mid10):
     for kw in [dict(persistent=True), dict(tile_rows=32), dict(tile_rows=64),
                dict(persistent=2), dict(tile_rows=32, persistent=2, grid_mult=1),
                dict(pass_pairs=16), dict(pass_pairs=32), dict(pass_pairs=64),
-               dict(tile_rows=32, pass_pairs=128)]:
+               dict(tile_rows=32, pass_pairs=128), dict(tile_rows=128),
+               dict(tile_rows=128, pass_pairs=128), dict(tile_rows=128, pass_pairs=16)]:
         got = gi.search(Qd, 10, 8, 256, r1=32, **kw)
         assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), kw
     sub = gi.search(Qd[11:50].contiguous(), 10, 8, 256, r1=32)

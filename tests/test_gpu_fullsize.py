@@ -75,7 +75,8 @@ def test_full_schedules_identical(full):
     ref = gi.search(Qd, 10, 8, 256, r1=256)
     for kw in [dict(tile_rows=32), dict(tile_rows=128), dict(persistent=1, grid_mult=4),
                dict(persistent=2, grid_mult=4), dict(tile_rows=128, persistent=2, grid_mult=8),
-               dict(pass_pairs=64), dict(tile_rows=32, pass_pairs=128)]:
+               dict(pass_pairs=64), dict(tile_rows=32, pass_pairs=128),
+               dict(tile_rows=128, pass_pairs=64)]:
         got = gi.search(Qd, 10, 8, 256, r1=256, **kw)
         assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), kw
 

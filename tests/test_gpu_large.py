@@ -50,6 +50,8 @@ def test_past_2_to_31_elements():
         compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
         pr = dbg["pairs"].cpu().numpy()
         routed = dbg["routed"].cpu().numpy()
-        rows = off[routed[:, 0]] + pr[:, 0, 1]
-        assert (rows * D > 2**31).mean() > 0.9  # the windows read past element 2^31
+        # the windows read past element 2^31 (the routed set is listed in no
+        # particular order: some window of each query)
+        rows = off[routed] + pr[:, :, 1]
+        assert (rows * D > 2**31).any(axis=1).mean() > 0.9
     gi.close()

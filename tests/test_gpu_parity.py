@@ -389,6 +389,11 @@ def test_precision_form(mid, k, l1_dense):
     oids, osc, odbg = oi.search(Q, k, 8, 256, 32, debug=True)
     compare_debug(dbg, odbg)
     compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+    # the bf16 windows through the workgroup rerank (128-row tiles): the same
+    # scores bit for bit, so the same results
+    for kw in (dict(tile_rows=128), dict(tile_rows=128, pass_pairs=64)):
+        got = gi.search(Qd, k, 8, 256, r1=32, precision="bf16", l1_dense=l1_dense, **kw)
+        assert torch.equal(got[0], ids) and torch.equal(got[1], sc), kw
     gi.close()
 
 
