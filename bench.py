@@ -142,7 +142,7 @@ def rerank_roofline(torch, gi, Q, k, c, r, r1, rr_ms, **kw):
     out = dict(main_b)
     out.update(traffic=None,
                traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-               kernel="rerank_kernel (fp32 operand-ordered feed, one wave per row tile)",
+               kernel="rerank_wg_kernel (fp32 operand-ordered feed, a workgroup of 4 waves per 128-row tile)",
                kernel_ms=round(rr_ms, 4), union_rows=U, hull_rows=hull, pair_rows=pairs_rows,
                algorithmic_bytes=alg_bytes, algorithmic_flops=flops,
                query_bytes=Q.shape[0] * 4 * d, score_bytes=hull * 4,

@@ -924,7 +924,10 @@ __global__ __launch_bounds__(256) void pair_mask_kernel(
   const int64_t nwl = *wl_end;
   for (int64_t u = int64_t(blockIdx.x) * 4 + wave; u < nwl; u += int64_t(gridDim.x) * 4) {
     const int64_t t = wl[u];
-    const int32_t j = pw[t * H].j;
+    // the pair's H windows, one per lane (H <= 16), read with one load
+    Pair myw{-1, 0, 0, 0};
+    if (lane < H) myw = pw[t * H + lane];
+    const int32_t j = __shfl(myw.j, 0);
     if (j < 0) continue;  // wave-uniform
     const int64_t o = off[j];
     for (int32_t w = lane; w < mw; w += 64) bm[w] = 0;
@@ -933,7 +936,7 @@ __global__ __launch_bounds__(256) void pair_mask_kernel(
     // every array's window positions mapped to array 0's, up to 4 position
     // loads per lane in flight before their bits are set
     for (int32_t h = 0; h < H; ++h) {
-      const Pair ph = pw[t * H + h];
+      const Pair ph{j, __shfl(myw.s, h), __shfl(myw.len, h), 0};
       const int32_t* mp = h == 0 ? nullptr : amap + int64_t(h - 1) * n + o + ph.s;
       for (int32_t p0 = 0; p0 < ph.len; p0 += 256) {
         int32_t row[4];
