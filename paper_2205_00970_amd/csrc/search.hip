@@ -464,11 +464,26 @@ __global__ __launch_bounds__(256) void l1_union_kernel(
     for (int32_t w = lane; w < W; w += 64) bm[w] = 0;
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
+    // the H windows, one per lane (H <= 16), then each window's positions 4
+    // loads per lane at a time before their bits are set
+    int32_t ms = 0, ml = 0;
+    if (lane < H) {
+      ms = l1[3 * (q * H + lane) + 1];
+      ml = l1[3 * (q * H + lane) + 2];
+    }
     for (int32_t h = 0; h < H; ++h) {
-      const int32_t s = l1[3 * (q * H + h) + 1], len = l1[3 * (q * H + h) + 2];
-      for (int32_t p = lane; p < len; p += 64) {
-        const int32_t pos = h == 0 ? s + p : l1map[int64_t(h - 1) * C + s + p];
-        atomicOr(&bm[pos >> 5], 1u << (pos & 31));
+      const int32_t s = __shfl(ms, h), len = __shfl(ml, h);
+      const int32_t* mp = l1map + int64_t(h > 0 ? h - 1 : 0) * C + s;
+      for (int32_t p0 = 0; p0 < len; p0 += 256) {
+        int32_t pos[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t p = p0 + lane + 64 * u;
+          pos[u] = p >= len ? -1 : h == 0 ? s + p : mp[p];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (pos[u] >= 0) atomicOr(&bm[pos[u] >> 5], 1u << (pos[u] & 31));
       }
     }
     __threadfence_block();
@@ -881,29 +896,30 @@ __global__ void pairs_kernel(const Model* __restrict__ models, const double* __r
                              const int32_t* __restrict__ routed, Pair* __restrict__ pairs,
                              Pair* __restrict__ pw, int32_t* __restrict__ ccount,
                              uint64_t* __restrict__ kq) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= np) return;
+  // one thread per (pair, array): the H locates of a pair run side by side
+  const int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (u >= np * H) return;
+  const int64_t t = u / H;
+  const int32_t h = int32_t(u - t * H);
   const int64_t q = t / c;
   const int32_t j = routed[t];
-  Pair pr{-1, 0, 0, 0};
-  for (int32_t h = 0; h < H; ++h) {
-    Pair ph{-1, 0, 0, 0};
-    if (j >= 0) {
-      const Model* Mp = models + int64_t(h) * (C + 1) + j;
-      const int64_t L = Mp->L;
-      uint64_t K = 0;
-      const int64_t pos =
-          locate(Mp, leaves, qdig + q * 2 * H * m + int64_t(H) * m + int64_t(h) * m, m, &K);
-      int64_t s, len;
-      window_of(pos, r, L, &s, &len);  // the expansion (if any) replaces s later
-      if (kq) kq[t * H + h] = K;
-      ph = Pair{j, int32_t(s), int32_t(len), int32_t(pos)};
-    }
-    if (pw) pw[t * H + h] = ph;
-    if (h == 0) pr = ph;
+  Pair ph{-1, 0, 0, 0};
+  if (j >= 0) {
+    const Model* Mp = models + int64_t(h) * (C + 1) + j;
+    const int64_t L = Mp->L;
+    uint64_t K = 0;
+    const int64_t pos =
+        locate(Mp, leaves, qdig + q * 2 * H * m + int64_t(H) * m + int64_t(h) * m, m, &K);
+    int64_t s, len;
+    window_of(pos, r, L, &s, &len);  // the expansion (if any) replaces s later
+    if (kq) kq[t * H + h] = K;
+    ph = Pair{j, int32_t(s), int32_t(len), int32_t(pos)};
   }
-  if (j >= 0 && pr.len > 0) atomicAdd(&ccount[j], 1);
-  pairs[t] = pr;
+  if (pw) pw[t * H + h] = ph;
+  if (h == 0) {
+    if (j >= 0 && ph.len > 0) atomicAdd(&ccount[j], 1);
+    pairs[t] = ph;
+  }
 }
 
 // Union of a pair's H windows (several arrays): one wave per pair marks the
@@ -3408,7 +3424,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   }
   mark(2);
   Pair* pwp = H > 1 ? pw : nullptr;
-  hipLaunchKernelGGL(pairs_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, ix.models,
+  hipLaunchKernelGGL(pairs_kernel, dim3(unsigned((np * H + 255) / 256)), dim3(256), 0, st, ix.models,
                      ix.leaves, qdig, m, H, C, np, c, r, routed, pairs, pwp, ccount,
                      o.expand_bits > 0 ? kq : (uint64_t*)nullptr);
   if (o.expand_bits > 0)
