@@ -57,6 +57,9 @@ struct Plan {
   // (query, cluster) pair.
   bool l1_dense_rows, l1_list;
   int32_t lcap, mw;
+  // block keys (the block form of the selection): nbcap per pair, 0 = none
+  size_t o_bkey;
+  int32_t nbcap;
 };
 
 // Rerank shape: rows per tile (index into the tile tables: 32, 64, 128) and
@@ -154,6 +157,12 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   p.cert = cert;
   p.o_slist = take(cert ? size_t(nq) * c * rcap * 4 : S ? size_t(nq) * S * 4 : 0);
   p.o_scnt = take(cert ? size_t(nq) * 4 : 0);
+  // the selection's block form serves k (or the shortlist) <= 64 over more
+  // than 2,048 candidates per query (fewer fit the per-wave selection's
+  // registers, which is faster there than reading the block keys first); a
+  // window of at most rcap rows spans at most rcap / 32 + 1 blocks of 32 rows
+  p.nbcap = (S ? S : k) <= 64 && int64_t(c) * rcap > 2048 ? rcap / 32 + 1 : 0;
+  p.o_bkey = take(size_t(np) * p.nbcap * 4);
   rerank_shape(ix, nq, c, r, o, &p.ti, &p.npcm);
   const size_t nt = o.persistent == 2 ? size_t(ix.n_tiles[p.ti]) : 0;
   p.o_aflag = take(nt * 4);
@@ -447,10 +456,51 @@ __device__ inline void l1_item(const L1Args& a, int64_t t) {
 
 __global__ void l1_kernel(L1Args a) { l1_item(a, int64_t(blockIdx.x) * blockDim.x + threadIdx.x); }
 
+// Bits of the positions [a, b) that fall in word w of a bitmap (bit i of word
+// w is position 32 w + i).
+__device__ inline uint32_t range_bits(int32_t w, int32_t a, int32_t b) {
+  const int32_t lo = max(a - 32 * w, 0), hi = min(b - 32 * w, 32);
+  if (hi <= lo) return 0u;
+  const uint32_t span = hi - lo == 32 ? 0xffffffffu : (1u << (hi - lo)) - 1u;
+  return span << lo;
+}
+
+// Positions p (0 <= p < len) of arrays h0 .. h0 + 3's windows, mapped to array
+// 0's positions by map(g, p), set in the wave's LDS bitmap: the lane's four
+// positions of each of the four arrays are loaded together, then their bits
+// set.  ws / wl hold array h's window start and length in lane h.
+template <class Map>
+__device__ inline void mark_windows4(uint32_t* bm, int32_t h0, int32_t H, int32_t ws, int32_t wl,
+                                     int lane, Map map) {
+  int32_t hs[4], hl[4], lmax = 0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    hs[g] = __shfl(ws, min(h0 + g, H - 1));
+    hl[g] = h0 + g < H ? __shfl(wl, h0 + g) : 0;
+    lmax = max(lmax, hl[g]);
+  }
+  for (int32_t p0 = 0; p0 < lmax; p0 += 256) {
+    int32_t pos[4][4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int32_t p = p0 + lane + 64 * u;
+        pos[g][u] = p < hl[g] ? map(h0 + g, hs[g], p) : -1;
+      }
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (pos[g][u] >= 0) atomicOr(&bm[pos[g][u] >> 5], 1u << (pos[g][u] & 31));
+  }
+}
+
 // Union of a query's H layer-1 windows, as ascending positions of array 0's
-// layer-1 order: one wave per query marks the windows in an LDS bitmap of C
-// bits (dynamic shared memory, 4 waves x ceil(C/32) words), then lists the
-// set bits in order.
+// layer-1 order: one wave per query sets the windows in an LDS bitmap of C
+// bits (dynamic shared memory, 4 waves x ceil(C/32) words; array 0's window is
+// a range of positions, written as whole words), then lists the set bits in
+// order, 64 positions per step with one store.
 // rw[q] = (0, 0, union size) is the query's window in list form.
 __global__ __launch_bounds__(256) void l1_union_kernel(
     const int32_t* __restrict__ l1, int32_t H, int64_t nq, int32_t C,
@@ -459,53 +509,30 @@ __global__ __launch_bounds__(256) void l1_union_kernel(
   extern __shared__ uint32_t bm_all[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t W = (C + 31) / 32;
+  const uint64_t below = (uint64_t(1) << lane) - 1;
   uint32_t* bm = bm_all + wave * W;
   for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
-    for (int32_t w = lane; w < W; w += 64) bm[w] = 0;
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-    // the H windows, one per lane (H <= 16), then each window's positions 4
-    // loads per lane at a time before their bits are set
+    // the H windows, one per lane (H <= 16)
     int32_t ms = 0, ml = 0;
     if (lane < H) {
       ms = l1[3 * (q * H + lane) + 1];
       ml = l1[3 * (q * H + lane) + 2];
     }
-    for (int32_t h = 0; h < H; ++h) {
-      const int32_t s = __shfl(ms, h), len = __shfl(ml, h);
-      const int32_t* mp = l1map + int64_t(h > 0 ? h - 1 : 0) * C + s;
-      for (int32_t p0 = 0; p0 < len; p0 += 256) {
-        int32_t pos[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int32_t p = p0 + lane + 64 * u;
-          pos[u] = p >= len ? -1 : h == 0 ? s + p : mp[p];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (pos[u] >= 0) atomicOr(&bm[pos[u] >> 5], 1u << (pos[u] & 31));
-      }
-    }
+    const int32_t s0 = __shfl(ms, 0), e0 = s0 + __shfl(ml, 0);
+    for (int32_t w = lane; w < W; w += 64) bm[w] = range_bits(w, s0, e0);
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    auto map = [&](int32_t h, int32_t s, int32_t p) { return l1map[int64_t(h - 1) * C + s + p]; };
+    for (int32_t h0 = 1; h0 < H; h0 += 4) mark_windows4(bm, h0, H, ms, ml, lane, map);
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
     int32_t base = 0;
-    for (int32_t w0 = 0; w0 < W; w0 += 64) {
-      const int32_t w = w0 + lane;
-      uint32_t bits = w < W ? bm[w] : 0u;
-      const int32_t cw = __popc(bits);
-      int32_t incl = cw;  // inclusive prefix of the word counts over the lanes
-      for (int o = 1; o < 64; o <<= 1) {
-        const int32_t v = __shfl_up(incl, o);
-        if (lane >= o) incl += v;
-      }
-      int32_t at = base + incl - cw;
-      while (bits) {
-        const int32_t pos = w * 32 + (__ffs(bits) - 1);
-        bits &= bits - 1;
-        lst[q * lcap + at] = pos;
-        ++at;
-      }
-      base += __shfl(incl, 63);
+    for (int32_t p0 = 0; p0 < C; p0 += 64) {
+      const int32_t p = p0 + lane;
+      const bool in = p < C && ((bm[p >> 5] >> (p & 31)) & 1u);
+      const uint64_t b = __ballot(in);
+      if (in) lst[q * lcap + base + __popcll(b & below)] = p;
+      base += __popcll(b);
     }
     if (lane == 0) {
       rw[3 * q] = 0;
@@ -922,7 +949,34 @@ __global__ void pairs_kernel(const Model* __restrict__ models, const double* __r
   }
 }
 
-// Union of a pair's H windows (several arrays): one wave per pair marks the
+// Block -> tile map of the direct schedules.  Workgroups go to the 8 XCDs
+// round-robin (XCD blockIdx % 8); the tiles are cut into chunks of S
+// consecutive tiles (about 8,192 rows), chunk k belongs to XCD k % 8, and an
+// XCD runs its chunks in order.  Consecutive tiles -- the same clusters, the
+// same query rows -- share one XCD's L2, while every XCD gets chunks from all
+// over the index: with one contiguous eighth of the tiles per XCD, a
+// clustering that numbers its busiest clusters together left one XCD with most
+// of the work (1M x 768, c = 8, r = 256: 1.04 ms against 0.81 ms for the same
+// clusters in another order).  Grid: 8 S ceil(ceil(ntiles / S) / 8) blocks.
+__device__ inline int32_t xcd_chunk_tile(int32_t ntiles, int32_t S) {
+  const int32_t xcd = int32_t(blockIdx.x & 7), loc = int32_t(blockIdx.x >> 3);
+  const int32_t t = (xcd + 8 * (loc / S)) * S + loc % S;
+  return t < ntiles ? t : -1;
+}
+
+__host__ __device__ constexpr int32_t tile_chunk(int32_t rows_per_tile) {
+  return 8192 / rows_per_tile;
+}
+
+inline unsigned chunk_grid(int32_t ntiles, int32_t S) {
+  const int32_t nch = (ntiles + S - 1) / S;
+  return unsigned(8 * ((nch + 7) / 8) * S);
+}
+
+// Pairs per pair-mask workgroup run dealt to one XCD: 4 x 64.
+constexpr int32_t kMaskChunk = 64;
+
+// Union of a pair's H windows (several arrays): one wave per pair sets the
 // rows (positions of array 0 within the cluster; array h's positions go
 // through amap) in an LDS bitmap of mw words (dynamic shared memory, 4 waves x
 // mw words), stores the bitmap as the pair's membership mask [mw words] and
@@ -931,41 +985,35 @@ __global__ __launch_bounds__(256) void pair_mask_kernel(
     const Pair* __restrict__ pw, int32_t H, const int32_t* __restrict__ wl,
     const int32_t* __restrict__ wl_end, const int64_t* __restrict__ off,
     const int32_t* __restrict__ amap, int64_t n, int32_t mw, Pair* __restrict__ pairs,
-    uint32_t* __restrict__ mask) {
+    uint32_t* __restrict__ mask, int32_t nblk) {
   extern __shared__ uint32_t bm_all[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* bm = bm_all + wave * mw;
-  // pairs in work-list order: consecutive waves take pairs of one cluster,
-  // whose position maps then stay in L2
+  // pairs in work-list order, 4 per workgroup, runs of kMaskChunk
+  // workgroups dealt to the XCDs in turn: the pairs of a cluster go to one
+  // XCD, whose L2 then holds the cluster's position maps
   const int64_t nwl = *wl_end;
-  for (int64_t u = int64_t(blockIdx.x) * 4 + wave; u < nwl; u += int64_t(gridDim.x) * 4) {
+  const int32_t blk = xcd_chunk_tile(nblk, kMaskChunk);
+  const int64_t u = int64_t(blk) * 4 + wave;
+  if (blk >= 0 && u < nwl) {
     const int64_t t = wl[u];
     // the pair's H windows, one per lane (H <= 16), read with one load
     Pair myw{-1, 0, 0, 0};
     if (lane < H) myw = pw[t * H + lane];
     const int32_t j = __shfl(myw.j, 0);
-    if (j < 0) continue;  // wave-uniform
+    if (j < 0) return;  // wave-uniform
     const int64_t o = off[j];
-    for (int32_t w = lane; w < mw; w += 64) bm[w] = 0;
+    // array 0's window is a range of positions: whole words
+    const int32_t s0 = __shfl(myw.s, 0), e0 = s0 + __shfl(myw.len, 0);
+    for (int32_t w = lane; w < mw; w += 64) bm[w] = range_bits(w, s0, e0);
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
-    // every array's window positions mapped to array 0's, up to 4 position
-    // loads per lane in flight before their bits are set
-    for (int32_t h = 0; h < H; ++h) {
-      const Pair ph{j, __shfl(myw.s, h), __shfl(myw.len, h), 0};
-      const int32_t* mp = h == 0 ? nullptr : amap + int64_t(h - 1) * n + o + ph.s;
-      for (int32_t p0 = 0; p0 < ph.len; p0 += 256) {
-        int32_t row[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int32_t p = min(p0 + lane + 64 * u, ph.len - 1);
-          row[u] = h == 0 ? ph.s + p : int32_t(mp[p] - o);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (p0 + lane + 64 * u < ph.len) atomicOr(&bm[row[u] >> 5], 1u << (row[u] & 31));
-      }
-    }
+    // the other arrays' window positions mapped to array 0's, four arrays at
+    // a time
+    auto map = [&](int32_t h, int32_t s, int32_t p) {
+      return int32_t(amap[int64_t(h - 1) * n + o + s + p] - o);
+    };
+    for (int32_t h0 = 1; h0 < H; h0 += 4) mark_windows4(bm, h0, H, myw.s, myw.len, lane, map);
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
     int32_t lo = INT32_MAX, hi = -1;
@@ -1172,31 +1220,8 @@ template <int CAP>
 struct WaveShared {
   int32_t lp[CAP], lq[CAP], ls[CAP], le[CAP];
   uint32_t lm[CAP][4];  // membership bits of the tile's rows (several arrays)
+  uint32_t bk[CAP][4];  // block keys of the pass's pairs (32-row blocks of the tile)
 };
-
-// Block -> tile map of the direct schedules.  Workgroups go to the 8 XCDs
-// round-robin (XCD blockIdx % 8); the tiles are cut into chunks of S
-// consecutive tiles (about 8,192 rows), chunk k belongs to XCD k % 8, and an
-// XCD runs its chunks in order.  Consecutive tiles -- the same clusters, the
-// same query rows -- share one XCD's L2, while every XCD gets chunks from all
-// over the index: with one contiguous eighth of the tiles per XCD, a
-// clustering that numbers its busiest clusters together left one XCD with most
-// of the work (1M x 768, c = 8, r = 256: 1.04 ms against 0.81 ms for the same
-// clusters in another order).  Grid: 8 S ceil(ceil(ntiles / S) / 8) blocks.
-__device__ inline int32_t xcd_chunk_tile(int32_t ntiles, int32_t S) {
-  const int32_t xcd = int32_t(blockIdx.x & 7), loc = int32_t(blockIdx.x >> 3);
-  const int32_t t = (xcd + 8 * (loc / S)) * S + loc % S;
-  return t < ntiles ? t : -1;
-}
-
-__host__ __device__ constexpr int32_t tile_chunk(int32_t rows_per_tile) {
-  return 8192 / rows_per_tile;
-}
-
-inline unsigned chunk_grid(int32_t ntiles, int32_t S) {
-  const int32_t nch = (ntiles + S - 1) / S;
-  return unsigned(8 * ((nch + 7) / 8) * S);
-}
 
 // Tile fetch, one tile per wave (direct: persistent = 0), one workgroup per
 // wave.
@@ -1604,7 +1629,7 @@ __global__ __launch_bounds__(kRerankNT, (rerank_waves_per_eu<RT, NPCM>())) void 
     const void* __restrict__ Qv, float* __restrict__ sbuf, int32_t rcap, int persistent,
     int32_t* __restrict__ ctr, int32_t pair_chunk, const float* __restrict__ row_scale,
     const int32_t* __restrict__ alist, const uint32_t* __restrict__ pmask, int32_t mw,
-    const int32_t* __restrict__ tblk) {
+    const int32_t* __restrict__ tblk, uint32_t* __restrict__ bkey, int32_t nbcap) {
   typedef Feed<FMT, VEC> F;
   typedef typename F::XE XE;
   typedef typename F::QE QE;
@@ -1712,6 +1737,15 @@ __global__ __launch_bounds__(kRerankNT, (rerank_waves_per_eu<RT, NPCM>())) void 
       pre = false;
       // D layout: acc[rc][pc][e] = pair 16 pc + 4 s + e, row 16 rc + i.
       // The score stores are nontemporal: the selection reads them once.
+      // Block keys: the smallest score key of each (pair, 32-row block of the
+      // tile) over the rows stored (NaN, a row outside the union, has the
+      // largest key), gathered in LDS and written once per block.
+      constexpr int NB = RT / 32;
+      if (bkey) {
+        for (int u = lane; u < PP * 4; u += 64) sh.bk[u >> 2][u & 3] = 0xffffffffu;
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+      }
 #pragma unroll
       for (int pc = 0; pc < NPCM; ++pc) {
 #pragma unroll
@@ -1720,6 +1754,9 @@ __global__ __launch_bounds__(kRerankNT, (rerank_waves_per_eu<RT, NPCM>())) void 
           if (pc < npc && pp < np) {
             const int32_t a = sh.ls[pp], en = sh.le[pp];
             float* dst = sbuf + int64_t(sh.lp[pp]) * rcap - a;
+            uint32_t km[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) km[b] = 0xffffffffu;
 #pragma unroll
             for (int rc = 0; rc < RC; ++rc) {
               const int rr = 16 * rc + i;
@@ -1730,9 +1767,25 @@ __global__ __launch_bounds__(kRerankNT, (rerank_waves_per_eu<RT, NPCM>())) void 
                 if (pmask && !((sh.lm[pp][rr >> 5] >> (rr & 31)) & 1u))
                   v = __builtin_nanf("");
                 __builtin_nontemporal_store(v, &dst[row]);
+                km[rc >> 1] = min(km[rc >> 1], score_key(v));
               }
             }
+            if (bkey) {
+#pragma unroll
+              for (int b = 0; b < NB; ++b)
+                if (km[b] != 0xffffffffu) atomicMin(&sh.bk[pp][b], km[b]);
+            }
           }
+        }
+      }
+      if (bkey) {
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+        for (int u = lane; u < np * NB; u += 64) {
+          const int pp = u / NB, b = u - pp * NB;
+          const int32_t a = sh.ls[pp], en = sh.le[pp], b0 = row0 + 32 * b;
+          if (32 * b < rows_here && b0 < en && b0 + 32 > a)
+            bkey[int64_t(sh.lp[pp]) * nbcap + ((b0 >> 5) - (a >> 5))] = sh.bk[pp][b];
         }
       }
       // the entries past this pass (at most 63) move to the front of the list
@@ -1802,6 +1855,7 @@ struct WgShared {
   int32_t lp[CAP], lq[CAP], ls[CAP], le[CAP];
   uint32_t lm[CAP][4];  // membership bits of the tile's 128 rows (several arrays)
   __attribute__((aligned(16))) unsigned char qs[2][NPCM * kWgQBlk];
+  uint32_t bk[4][16 * NPCM];  // block keys of the pass's pairs, per wave
   int32_t n;
 };
 
@@ -1893,7 +1947,7 @@ __global__ __launch_bounds__(256, 2) void rerank_wg_kernel(
     const int32_t* __restrict__ cstart, const int32_t* __restrict__ wl,
     const Pair* __restrict__ pairs, int32_t c, const void* __restrict__ Qv,
     float* __restrict__ sbuf, int32_t rcap, const uint32_t* __restrict__ pmask, int32_t mw,
-    const int32_t* __restrict__ tblk) {
+    const int32_t* __restrict__ tblk, uint32_t* __restrict__ bkey, int32_t nbcap) {
   typedef Feed<FMT, true> F;
   typedef typename F::XE XE;
   typedef typename F::QE QE;
@@ -1985,7 +2039,14 @@ __global__ __launch_bounds__(256, 2) void rerank_wg_kernel(
         if constexpr (NPCM >= 8) wg_pass<FMT, 8, NPCM, wg_ring(NPCM)>(sh, xr, Q, d, np, nsteps, acc);
         break;
     }
-    // D layout: acc[rc][pc][e] = pair 16 pc + 4 s + e, row 32 wave + 16 rc + i
+    // D layout: acc[rc][pc][e] = pair 16 pc + 4 s + e, row 32 wave + 16 rc + i.
+    // Block keys: the smallest score key of the rows a wave stores for a pair
+    // (NaN, a row outside the union, has the largest key), gathered in LDS.
+    if (bkey) {
+      for (int u = lane; u < PP; u += 64) sh.bk[wave][u] = 0xffffffffu;
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+    }
 #pragma unroll
     for (int pc = 0; pc < NPCM; ++pc) {
 #pragma unroll
@@ -1994,6 +2055,7 @@ __global__ __launch_bounds__(256, 2) void rerank_wg_kernel(
         if (pc < npc && pp < np) {
           const int32_t a = sh.ls[pp], en = sh.le[pp];
           float* dst = sbuf + int64_t(sh.lp[pp]) * rcap - a;
+          uint32_t km = 0xffffffffu;
 #pragma unroll
           for (int rc = 0; rc < 2; ++rc) {
             const int rr = 32 * wave + 16 * rc + i;
@@ -2002,9 +2064,22 @@ __global__ __launch_bounds__(256, 2) void rerank_wg_kernel(
               float v = acc[rc][pc][e];
               if (pmask && !((sh.lm[pp][rr >> 5] >> (rr & 31)) & 1u)) v = __builtin_nanf("");
               __builtin_nontemporal_store(v, &dst[row]);
+              km = min(km, score_key(v));
             }
           }
+          if (bkey && km != 0xffffffffu) atomicMin(&sh.bk[wave][pp], km);
         }
+      }
+    }
+    if (bkey) {
+      // the wave's 32 rows are one block of 32 rows of the cluster
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+      const int32_t b0 = row0 + 32 * wave;
+      for (int pp = lane; pp < np; pp += 64) {
+        const int32_t a = sh.ls[pp], en = sh.le[pp];
+        if (32 * wave < rows_here && b0 < en && b0 + 32 > a)
+          bkey[int64_t(sh.lp[pp]) * nbcap + ((b0 >> 5) - (a >> 5))] = sh.bk[wave][pp];
       }
     }
     // the entries past this pass move to the front of the list
@@ -2434,15 +2509,22 @@ __global__ __launch_bounds__(kSelNT) void select_kernel(
 // the kernel to 3 workgroups per CU, and re-reading the rows from L2 at 4x
 // that occupancy is faster, 0.22 -> 0.16 ms for 8 windows of 1,000 rows).
 constexpr int kSelList = 256;
+// Block keys per lane in the block form of the selection: queries whose
+// windows span more than 64 kSelBlk blocks take the other forms.
+constexpr int kSelBlk = 8;
 
 template <int MODE, int R>
 __global__ __launch_bounds__(256) void wave_select_kernel(
     const Pair* __restrict__ pairs, const float* __restrict__ sbuf, int32_t rcap, int32_t c,
     int64_t nq, int32_t K, const int64_t* __restrict__ off, const int32_t* __restrict__ perm32,
     int64_t* __restrict__ ids, float* __restrict__ scores, int32_t kout,
-    int32_t* __restrict__ slist, int drop, CertArgs ca) {
+    int32_t* __restrict__ slist, int drop, CertArgs ca, const uint32_t* __restrict__ bkey,
+    int32_t nbcap) {
   __shared__ int32_t start[4][LIDER_MAX_C + 1];
   __shared__ int64_t pbase[4][LIDER_MAX_C];  // sorted row of each slot's first candidate
+  __shared__ int32_t bstart[4][LIDER_MAX_C + 1];  // block form: first block of each slot
+  __shared__ int32_t wstart[4][LIDER_MAX_C];      // block form: window start in the cluster
+  __shared__ int32_t bsel[4][64];                 // block form: blocks being read
   __shared__ uint64_t ext[4][65];
   __shared__ uint32_t wkey[4][64], wid[4][64];
   __shared__ int64_t wrow[4][64];
@@ -2469,33 +2551,49 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
         if (64 * j < rcap) fv[j] = sbq[uint32_t(min(lane + 64 * j, rcap - 1))];
     }
     // slot table: lane t reads pair t (64 at a time); start[] is the
-    // exclusive prefix sum of the slot lengths, pbase[] each slot's first row
-    int32_t n = 0;
+    // exclusive prefix sum of the slot lengths, pbase[] each slot's first row.
+    // Block form: the window of slot t spans the blocks of 32 cluster rows
+    // from (s >> 5) to ((s + len - 1) >> 5); bstart[] is the exclusive
+    // prefix sum of their counts
+    int32_t n = 0, nbt = 0;
     for (int t0 = 0; t0 < c; t0 += 64) {
       const int t = t0 + lane;
-      int32_t len = 0;
+      int32_t len = 0, s0 = 0;
       int64_t base = 0;
       if (t < c) {
         const Pair pr = pairs[q * c + t];
         if (pr.j >= 0) {
           len = pr.len;
+          s0 = pr.s;
           base = off[pr.j] + pr.s;
         }
       }
-      int32_t incl = len;
+      const int32_t nb = len > 0 ? ((s0 + len - 1) >> 5) - (s0 >> 5) + 1 : 0;
+      int32_t incl = len, inclb = nb;
       if (c > 1) {
         for (int o = 1; o < 64; o <<= 1) {
-          const int32_t y = __shfl_up(incl, o);
-          if (lane >= o) incl += y;
+          const int32_t y = __shfl_up(incl, o), yb = __shfl_up(inclb, o);
+          if (lane >= o) {
+            incl += y;
+            inclb += yb;
+          }
         }
       }
       if (t < c) {
         start[wave][t] = n + incl - len;
         pbase[wave][t] = base;
+        if (bkey) {
+          bstart[wave][t] = nbt + inclb - nb;
+          wstart[wave][t] = s0;
+        }
       }
       n += __shfl(incl, c > 1 ? 63 : 0);
+      nbt += __shfl(inclb, c > 1 ? 63 : 0);
     }
-    if (lane == 0) start[wave][c] = n;
+    if (lane == 0) {
+      start[wave][c] = n;
+      bstart[wave][c] = nbt;
+    }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
     const int32_t* st = start[wave];
@@ -2541,6 +2639,18 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
     const uint32_t kdrop = drop ? 0xffffffffu : 0u;  // 0: never matches a real key test below
     // f(index, key, valid) over the lane's candidates, the same number of
     // calls on every lane (ballots inside f see the whole wave)
+    // R == 0: the scores are re-read from the score rows in chunks of 1,024
+    // entries of one slot (16 loads per lane); the next chunk's loads are
+    // issued before the current chunk's keys are used
+    auto load_chunk = [&](int t, int p0, float(&v)[16]) {
+      const int32_t len = st[t + 1] - st[t];
+      const float* src = sbq + int64_t(t) * rcap;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int p = p0 + lane + 64 * u;
+        v[u] = src[p < len ? p : max(len - 1, 0)];
+      }
+    };
     auto scan = [&](auto&& f) {
       if (R > 0) {
 #pragma unroll
@@ -2549,57 +2659,280 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
           if (64 * j < n) f(i, kr[j], i < n);  // wave-uniform: skips slots past the candidates
         }
       } else {
-        // re-read from the score rows, 8 loads per lane in flight before
-        // their keys are used
-        for (int t = 0; t < c; ++t) {
-          const int32_t a = st[t], len = st[t + 1] - a;
-          const float* src = sbq + int64_t(t) * rcap;
-          for (int p0 = 0; p0 < len; p0 += 512) {
-            float v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int p = p0 + lane + 64 * u;
-              v[u] = src[p < len ? p : len - 1];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int p = p0 + lane + 64 * u;
-              if (p0 + 64 * u < len)  // wave-uniform
-                f(a + p, p < len ? score_key(v[u]) : 0xffffffffu, p < len);
-            }
+        int t = 0, p0 = 0;
+        float v[16];
+        load_chunk(0, 0, v);
+        while (true) {
+          const int32_t a = __builtin_amdgcn_readfirstlane(st[t]);
+          const int32_t len = __builtin_amdgcn_readfirstlane(st[t + 1]) - a;
+          int tn = t, pn = p0 + 1024;
+          if (pn >= len) {
+            tn = t + 1;
+            pn = 0;
           }
+          float w[16];
+          if (tn < c) load_chunk(tn, pn, w);
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int p = p0 + lane + 64 * u;
+            if (p0 + 64 * u < len)  // wave-uniform
+              f(a + p, p < len ? score_key(v[u]) : 0xffffffffu, p < len);
+          }
+          if (tn >= c) break;
+#pragma unroll
+          for (int u = 0; u < 16; ++u) v[u] = w[u];
+          t = tn;
+          p0 = pn;
         }
       }
     };
-    uint32_t lmin = 0xffffffffu;
-    scan([&](int32_t, uint32_t kk, bool ok) {
-      if (ok && !(drop && kk == kdrop)) lmin = kk < lmin ? kk : lmin;
-    });
-    // tau by bisection on ballot counts: the smallest x with at least
-    // `want` lane minima <= x
-    uint32_t tau;
-    {
+    // the smallest x with at least `want` of the lanes' values <= x, by
+    // bisection on ballot counts
+    auto bisect = [&](uint32_t lv) {
       uint32_t lo = 0u, hi = 0xffffffffu;
       while (lo < hi) {
         const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (__popcll(__ballot(lmin <= mid)) >= want)
+        if (__popcll(__ballot(lv <= mid)) >= want)
           hi = mid;
         else
           lo = mid + 1;
       }
-      tau = lo;
-    }
+      return lo;
+    };
+    // f that lists every candidate with key <= th (the first kSelList in
+    // LDS) and takes the lane minima on the way; the slots are formed only
+    // for a ballot that lists some candidate
+    uint32_t lmin = 0xffffffffu;
     int m = 0;
-    scan([&](int32_t i, uint32_t kk, bool ok) {
-      const bool in = ok && kk <= tau && !(drop && kk == kdrop);
+    auto list_one = [&](int32_t i, uint32_t kk, bool in) {
       const uint64_t bal = __ballot(in);
-      const int slot = m + __popcll(bal & below);
-      if (in && slot < kSelList) {
-        lkey[wave][slot] = kk;
-        lidx[wave][slot] = i;
+      if (bal) {  // wave-uniform
+        const int slot = m + __popcll(bal & below);
+        if (in && slot < kSelList) {
+          lkey[wave][slot] = kk;
+          lidx[wave][slot] = i;
+        }
+        m += __popcll(bal);
       }
-      m += __popcll(bal);
-    });
+    };
+    auto lister = [&](uint32_t th) {
+      m = 0;
+      return [&, th](int32_t i, uint32_t kk, bool ok) {
+        const bool valid = ok && !(drop && kk == kdrop);
+        if (valid) lmin = kk < lmin ? kk : lmin;
+        list_one(i, kk, valid && kk <= th);
+      };
+    };
+    auto list_below = [&](uint32_t th) { scan(lister(th)); };
+    bool have_min = false, done = false;
+    // Block form (R == 0 with block keys: the smallest key of every 32-row
+    // block of every window, written by the rerank).  T = the want-th
+    // smallest block key: at least `want` candidates (one per block) have
+    // key <= T, so the K + 1 smallest all do, and each lies in a block whose
+    // key is <= T.  Only those blocks are read (about want of them, against
+    // every candidate of the query); their keys <= T are listed.
+    uint32_t bk[kSelBlk];
+    int32_t bt[kSelBlk];  // (slot << 16) | block of the slot, -1 past the blocks
+    const bool bform = R == 0 && bkey && nbt <= 64 * kSelBlk && want > 0;
+    // f(index, key, in window) over every candidate of the blocks with key
+    // <= th, two blocks per step and four steps' loads in flight
+    auto for_blocks = [&](uint32_t th, auto&& f) {
+#pragma unroll
+      for (int j = 0; j < kSelBlk; ++j) {
+        if (64 * j >= nbt) break;  // wave-uniform
+        const bool sel = bt[j] >= 0 && bk[j] <= th;
+        const uint64_t bal = __ballot(sel);
+        if (!bal) continue;  // wave-uniform
+        if (sel) bsel[wave][__popcll(bal & below)] = bt[j];
+        const int nsel = __popcll(bal);
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+        for (int g0 = 0; g0 < nsel; g0 += 8) {
+          float v[4];
+          int32_t ix[4];
+          bool ok[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int g = g0 + 2 * u + (lane >> 5);
+            ok[u] = false;
+            ix[u] = 0;
+            v[u] = 0.f;
+            if (g < nsel) {
+              const int32_t e = bsel[wave][g], tt = e >> 16;
+              const int32_t s0 = wstart[wave][tt], len = st[tt + 1] - st[tt];
+              const int32_t pos = (((s0 >> 5) + (e & 0xffff)) << 5) + (lane & 31) - s0;
+              ok[u] = pos >= 0 && pos < len;
+              ix[u] = st[tt] + pos;
+              v[u] = sbq[int64_t(tt) * rcap + (ok[u] ? pos : 0)];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) f(ix[u], score_key(v[u]), ok[u]);
+        }
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+      }
+    };
+    if (bform) {
+      int t = 0;
+#pragma unroll
+      for (int j = 0; j < kSelBlk; ++j) {
+        bk[j] = 0xffffffffu;
+        bt[j] = -1;
+        if (64 * j >= nbt) continue;  // wave-uniform
+        const int32_t b = min(lane + 64 * j, nbt - 1);
+        while (t + 1 < c && bstart[wave][t + 1] <= b) ++t;
+        const int32_t kb = b - bstart[wave][t];
+        bk[j] = bkey[(q * c + t) * int64_t(nbcap) + kb];
+        if (lane + 64 * j < nbt) bt[j] = (t << 16) | kb;
+      }
+#pragma unroll
+      for (int j = 0; j < kSelBlk; ++j)
+        if (bt[j] < 0) bk[j] = 0xffffffffu;
+      // T by bisection on the count of block keys <= x
+      uint32_t lo = 0u, hi = 0xffffffffu;
+      while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        int cnt = 0;
+#pragma unroll
+        for (int j = 0; j < kSelBlk; ++j)
+          if (64 * j < nbt) cnt += __popcll(__ballot(bk[j] <= mid));
+        if (cnt >= want)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      const uint32_t T = lo;
+      int nsel = 0;
+#pragma unroll
+      for (int j = 0; j < kSelBlk; ++j)
+        if (64 * j < nbt) nsel += __popcll(__ballot(bt[j] >= 0 && bk[j] <= T));
+      if (T != 0xffffffffu && nsel <= 16) {
+        // up to 16 blocks: their candidates in registers (block g = 2 u +
+        // lane / 32, row lane % 32), then a tighter threshold th = the
+        // want-th smallest lane minimum of their keys <= T (at least `want`
+        // candidates <= th, all of them in these blocks); the keys <= th
+        // are listed
+        int nb0 = 0;
+#pragma unroll
+        for (int j = 0; j < kSelBlk; ++j) {
+          if (64 * j >= nbt) break;  // wave-uniform
+          const bool sel = bt[j] >= 0 && bk[j] <= T;
+          const uint64_t bal = __ballot(sel);
+          if (sel) bsel[wave][nb0 + __popcll(bal & below)] = bt[j];
+          nb0 += __popcll(bal);
+        }
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+        auto cand = [&](int u, int32_t* ixp) {  // window position check and flat index
+          const int g = 2 * u + (lane >> 5);
+          if (g >= nsel) return -1;
+          const int32_t e = bsel[wave][g], tt = e >> 16;
+          const int32_t s0 = wstart[wave][tt], len = st[tt + 1] - st[tt];
+          const int32_t pos = (((s0 >> 5) + (e & 0xffff)) << 5) + (lane & 31) - s0;
+          if (pos < 0 || pos >= len) return -1;
+          *ixp = st[tt] + pos;
+          return int(int64_t(tt) * rcap + pos);
+        };
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          int32_t ixu;
+          const int at = cand(u, &ixu);
+          v[u] = at >= 0 ? sbq[at] : 0.f;
+        }
+        uint32_t kk[8], lm2 = 0xffffffffu;
+        uint32_t okm = 0;  // candidates with key <= T
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          int32_t ixu;
+          kk[u] = score_key(v[u]);
+          if (cand(u, &ixu) >= 0 && !(drop && kk[u] == kdrop) && kk[u] <= T) {
+            okm |= 1u << u;
+            lm2 = kk[u] < lm2 ? kk[u] : lm2;
+          }
+        }
+        const uint32_t th = min(T, bisect(lm2));
+        m = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (2 * u >= nsel) break;  // wave-uniform
+          int32_t ixu = 0;
+          const bool in = ((okm >> u) & 1u) && kk[u] <= th;
+          if (in) cand(u, &ixu);
+          list_one(ixu, kk[u], in);
+        }
+        done = m <= kSelList;
+      } else if (T != 0xffffffffu) {
+        m = 0;
+        for_blocks(T, [&](int32_t i, uint32_t kk, bool ok) {
+          list_one(i, kk, ok && !(drop && kk == kdrop) && kk <= T);
+        });
+        done = m <= kSelList;
+      }
+    }
+    if (R == 0 && !done) {
+      // One pass over the chunks.  Each chunk's keys update the lane minima;
+      // a chunk holding a key at or below the threshold th first tightens th
+      // to the want-th smallest lane minimum (at least `want` candidates seen
+      // so far are <= it, so the K + 1 smallest of all are too; th never
+      // grows), then lists its keys <= th.  Every candidate <= the final th
+      // is listed when its chunk is read, so the list holds all the
+      // extraction takes; a list past kSelList falls back to the two passes
+      // below.
+      uint32_t th = 0xffffffffu;
+      int t = 0, p0 = 0;
+      float v[16];
+      load_chunk(0, 0, v);
+      while (true) {
+        const int32_t a = __builtin_amdgcn_readfirstlane(st[t]);
+        const int32_t len = __builtin_amdgcn_readfirstlane(st[t + 1]) - a;
+        int tn = t, pn = p0 + 1024;
+        if (pn >= len) {
+          tn = t + 1;
+          pn = 0;
+        }
+        float w[16];
+        if (tn < c) load_chunk(tn, pn, w);
+        uint32_t cmin = 0xffffffffu;
+        bool cv = false;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const uint32_t kk = score_key(v[u]);
+          if (p0 + lane + 64 * u < len && !(drop && kk == kdrop)) {
+            cmin = kk < cmin ? kk : cmin;
+            cv = true;
+          }
+        }
+        if (cv) lmin = cmin < lmin ? cmin : lmin;
+        if (__ballot(cv && cmin <= th)) {  // wave-uniform
+          th = bisect(lmin);
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int p = p0 + lane + 64 * u;
+            const uint32_t kk = score_key(v[u]);
+            if (p0 + 64 * u < len)  // wave-uniform
+              list_one(a + p, kk, p < len && !(drop && kk == kdrop) && kk <= th);
+          }
+        }
+        if (tn >= c) break;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = w[u];
+        t = tn;
+        p0 = pn;
+      }
+      have_min = true;
+      done = m <= kSelList;
+    }
+    if (!done) {
+      // tau = the want-th smallest lane minimum: at least `want` candidates
+      // have key <= tau, and the list holds them all when it fits
+      if (!have_min)
+        scan([&](int32_t, uint32_t kk, bool ok) {
+          if (ok && !(drop && kk == kdrop)) lmin = kk < lmin ? kk : lmin;
+        });
+      list_below(bisect(lmin));
+    }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
     const bool listed = m <= kSelList;
@@ -2715,12 +3048,16 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
       for (int o = 32; o > 0; o >>= 1) tk = max(tk, uint32_t(__shfl_xor(tk, o)));
       const uint32_t thr = cert_threshold(ca, q, got == K ? tk : 0xffffffffu, lane);
       int m = 0;
-      scan([&](int32_t i, uint32_t kk, bool ok) {
+      auto cert = [&](int32_t i, uint32_t kk, bool ok) {
         const bool in = ok && kk <= thr;
         const uint64_t bal = __ballot(in);
         if (in) slist[q * ca.cap + m + __popcll(bal & below)] = int32_t(row_of(i));
         m += __popcll(bal);
-      });
+      };
+      if (bform)  // the blocks hold every candidate with key <= thr
+        for_blocks(thr, cert);
+      else
+        scan(cert);
       if (lane == 0) ca.scnt[q] = m;
     }
     __threadfence_block();
@@ -3062,30 +3399,42 @@ template <int MODE>
 void launch_wave_select(hipStream_t st, const Pair* pairs, const float* sbuf, int32_t rcap,
                         int32_t c, int64_t nq, int32_t K, const int64_t* off,
                         const int32_t* perm32, int64_t* ids, float* scores, int32_t kout,
-                        int32_t* slist, int drop, CertArgs ca = CertArgs()) {
+                        int32_t* slist, int drop, CertArgs ca, const uint32_t* bkey,
+                        int32_t nbcap) {
   const int64_t nmax = int64_t(c) * rcap;
   const unsigned wgrid = unsigned((nq + 3) / 4);  // one wave per query (nq < 2^31)
-  if (nmax <= 512)
+  if (bkey)  // the block form (and the re-reading form past its limits)
+    hipLaunchKernelGGL((wave_select_kernel<MODE, 0>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca, bkey,
+                       nbcap);
+  else if (nmax <= 512)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 8>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca,
+                       (const uint32_t*)nullptr, 0);
   else if (nmax <= 1024)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 16>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca,
+                       (const uint32_t*)nullptr, 0);
   else if (nmax <= 1280)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 20>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca,
+                       (const uint32_t*)nullptr, 0);
   else if (nmax <= 2048)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 32>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca,
+                       (const uint32_t*)nullptr, 0);
   else if (nmax <= 4096)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 64>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca,
+                       (const uint32_t*)nullptr, 0);
   else if (nmax <= 6144)
     hipLaunchKernelGGL((wave_select_kernel<MODE, 96>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca,
+                       (const uint32_t*)nullptr, 0);
   else
     hipLaunchKernelGGL((wave_select_kernel<MODE, 0>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
-                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
+                       rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca,
+                       (const uint32_t*)nullptr, 0);
 }
 
 template <int RT, int NPCM>
@@ -3093,38 +3442,39 @@ void launch_score_n(const Index& ix, bool bf16, bool vec, bool bvec, unsigned gr
                     const int32_t* cstart, const int32_t* wl, const Pair* pairs, int32_t c,
                     const float* Q, const __hip_bfloat16* Qb, float* sbuf, int32_t rcap,
                     int persistent, int32_t* ctr, const int32_t* alist, const uint32_t* pmask,
-                    int32_t mw, hipStream_t st) {
+                    int32_t mw, uint32_t* bkey, int32_t nbcap, hipStream_t st) {
   const int32_t nt = ix.n_tiles[ti];
   if (bf16 && !bvec)
     hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, false, false, NPCM>), dim3(grid), dim3(kRerankNT), 0,
                        st, (const void*)ix.Xb, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                       alist, pmask, mw, ix.tile_blk[ti]);
+                       alist, pmask, mw, ix.tile_blk[ti], bkey, nbcap);
   else if (bf16)
     hipLaunchKernelGGL((rerank_kernel<RT, kBF16W, true, false, NPCM>), dim3(grid), dim3(kRerankNT), 0,
                        st, (const void*)ix.Xbt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Qb, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                       alist, pmask, mw, ix.tile_blk[ti]);
+                       alist, pmask, mw, ix.tile_blk[ti], bkey, nbcap);
   else if (vec)
     hipLaunchKernelGGL((rerank_kernel<RT, kF32W, true, false, NPCM>), dim3(grid), dim3(kRerankNT), 0,
                        st, (const void*)ix.Xt, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                       alist, pmask, mw, ix.tile_blk[ti]);
+                       alist, pmask, mw, ix.tile_blk[ti], bkey, nbcap);
   else
     hipLaunchKernelGGL((rerank_kernel<RT, kF32W, false, false, NPCM>), dim3(grid), dim3(kRerankNT), 0,
                        st, (const void*)ix.X, ix.d, ix.tiles[ti], nt, cstart, wl, pairs, c,
                        (const void*)Q, sbuf, rcap, persistent, ctr, 0, (const float*)nullptr,
-                       alist, pmask, mw, ix.tile_blk[ti]);
+                       alist, pmask, mw, ix.tile_blk[ti], bkey, nbcap);
 }
 
 template <int FMT, int NPCM>
 void launch_wg_n(const Index& ix, const void* X, const void* Qv, const int32_t* cstart,
                  const int32_t* wl, const Pair* pairs, int32_t c, float* sbuf, int32_t rcap,
-                 const uint32_t* pmask, int32_t mw, hipStream_t st) {
+                 const uint32_t* pmask, int32_t mw, uint32_t* bkey, int32_t nbcap,
+                 hipStream_t st) {
   const int32_t nt = ix.n_tiles[2];
   hipLaunchKernelGGL((rerank_wg_kernel<FMT, NPCM>), dim3(chunk_grid(nt, tile_chunk(128))), dim3(256), 0,
                      st, X, ix.d, ix.tiles[2], nt, cstart, wl, pairs, c, Qv, sbuf, rcap, pmask, mw,
-                     ix.tile_blk[2]);
+                     ix.tile_blk[2], bkey, nbcap);
 }
 
 // The workgroup rerank (128-row tiles, direct schedule) on the operand-ordered
@@ -3132,20 +3482,24 @@ void launch_wg_n(const Index& ix, const void* X, const void* Qv, const int32_t* 
 bool launch_score_wg(const Index& ix, bool bf16, const int32_t* cstart, const int32_t* wl,
                      const Pair* pairs, int32_t c, const float* Q, const __hip_bfloat16* Qb,
                      float* sbuf, int32_t rcap, int npcm, const uint32_t* pmask, int32_t mw,
-                     hipStream_t st) {
+                     uint32_t* bkey, int32_t nbcap, hipStream_t st) {
   if (bf16 ? !(ix.d % 64 == 0 && ix.Xbt)
            : !(ix.d % 32 == 0 && ix.Xt && (reinterpret_cast<uintptr_t>(Q) & 15) == 0))
     return false;
-#define LIDER_WG(FMT, X, QP)                                                                   \
-  {                                                                                            \
-    if (npcm <= 1)                                                                             \
-      launch_wg_n<FMT, 1>(ix, X, QP, cstart, wl, pairs, c, sbuf, rcap, pmask, mw, st);         \
-    else if (npcm == 2)                                                                        \
-      launch_wg_n<FMT, 2>(ix, X, QP, cstart, wl, pairs, c, sbuf, rcap, pmask, mw, st);         \
-    else if (npcm <= 4)                                                                        \
-      launch_wg_n<FMT, 4>(ix, X, QP, cstart, wl, pairs, c, sbuf, rcap, pmask, mw, st);         \
-    else                                                                                       \
-      launch_wg_n<FMT, 8>(ix, X, QP, cstart, wl, pairs, c, sbuf, rcap, pmask, mw, st);         \
+#define LIDER_WG(FMT, X, QP)                                                            \
+  {                                                                                     \
+    if (npcm <= 1)                                                                      \
+      launch_wg_n<FMT, 1>(ix, X, QP, cstart, wl, pairs, c, sbuf, rcap, pmask, mw, bkey, \
+                          nbcap, st);                                                   \
+    else if (npcm == 2)                                                                 \
+      launch_wg_n<FMT, 2>(ix, X, QP, cstart, wl, pairs, c, sbuf, rcap, pmask, mw, bkey, \
+                          nbcap, st);                                                   \
+    else if (npcm <= 4)                                                                 \
+      launch_wg_n<FMT, 4>(ix, X, QP, cstart, wl, pairs, c, sbuf, rcap, pmask, mw, bkey, \
+                          nbcap, st);                                                   \
+    else                                                                                \
+      launch_wg_n<FMT, 8>(ix, X, QP, cstart, wl, pairs, c, sbuf, rcap, pmask, mw, bkey, \
+                          nbcap, st);                                                   \
   }
   if (bf16)
     LIDER_WG(kBF16W, (const void*)ix.Xbt, (const void*)Qb)
@@ -3162,7 +3516,7 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
                   const Pair* pairs, int32_t c, const float* Q, const __hip_bfloat16* Qb,
                   float* sbuf, int32_t rcap, int persistent, int grid_mult, int32_t* ctr,
                   const int32_t* alist, int npcm, const uint32_t* pmask, int32_t mw,
-                  hipStream_t st) {
+                  uint32_t* bkey, int32_t nbcap, hipStream_t st) {
   const int32_t nt = ix.n_tiles[ti];
   unsigned grid;
   if (persistent)  // grid_mult waves per SIMD
@@ -3175,7 +3529,7 @@ void launch_score(const Index& ix, bool bf16, int ti, const int32_t* cstart, con
   const bool bvec = ix.d % 64 == 0 && ix.Xbt;
 #define LIDER_SCORE_ARGS                                                                   \
   ix, bf16, vec, bvec, grid, ti, cstart, wl, pairs, c, Q, Qb, sbuf, rcap, persistent, ctr, \
-      alist, pmask, mw, st
+      alist, pmask, mw, bkey, nbcap, st
   if (npcm == 1)
     launch_score_n<RT, 1>(LIDER_SCORE_ARGS);
   else if (npcm == 2 || RT > 64)
@@ -3203,25 +3557,29 @@ void launch_l1_scores(const Index& ix, bool fp8, int64_t nq, const int32_t* l1cs
                        (const void*)ix.cent8, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale,
-                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr);
+                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr,
+                       (uint32_t*)nullptr, 0);
   else if (fp8)
     hipLaunchKernelGGL((rerank_kernel<64, kFP8, true, false>), grid, dim3(kRerankNT), 0, st,
                        (const void*)ix.cent8, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Qb, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)ix.cent8_scale,
-                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr);
+                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr,
+                       (uint32_t*)nullptr, 0);
   else if (vec)
     hipLaunchKernelGGL((rerank_kernel<64, kF32, true, false>), grid, dim3(kRerankNT), 0, st,
                        (const void*)ix.cent_l1, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr,
-                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr);
+                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr,
+                       (uint32_t*)nullptr, 0);
   else
     hipLaunchKernelGGL((rerank_kernel<64, kF32, false, false>), grid, dim3(kRerankNT), 0, st,
                        (const void*)ix.cent_l1, ix.d, ix.l1_tiles, nt, l1cs,
                        (const int32_t*)nullptr, l1pairs, 1, (const void*)Q, rs, r1, 0,
                        (int32_t*)nullptr, kL1PairChunk, (const float*)nullptr,
-                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr);
+                       (const int32_t*)nullptr, (const uint32_t*)nullptr, 0, (const int32_t*)nullptr,
+                       (uint32_t*)nullptr, 0);
 }
 
 // Dense layer-1 scores (r1 = C) on the GEMM kernel: 128-row query tiles when
@@ -3333,6 +3691,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   uint32_t* pmask = reinterpret_cast<uint32_t*>(W + p.o_mask);
   int32_t* rcand = reinterpret_cast<int32_t*>(W + p.o_rcand);
   int32_t* rcnt = reinterpret_cast<int32_t*>(W + p.o_rcnt);
+  uint32_t* bkey = p.nbcap ? reinterpret_cast<uint32_t*>(W + p.o_bkey) : nullptr;
   const int32_t m = ix.m, C = ix.C, H = ix.H;
   const int64_t np = nq * c;
   const bool bf16 = o.precision == LIDER_BF16;
@@ -3461,10 +3820,12 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   }
   // several arrays: each listed pair's union of windows as a membership mask
   // over its cluster's rows, and its window set to the union's hull
-  if (H > 1)
-    hipLaunchKernelGGL(pair_mask_kernel, dim3(unsigned(std::min<int64_t>((np + 3) / 4, 65535))),
-                       dim3(256), 4 * size_t(p.mw) * 4, st, pw, H, wl, cstart + C, ix.off,
-                       ix.amap, ix.n, p.mw, pairs, pmask);
+  if (H > 1) {
+    const int32_t nblk = int32_t((np + 3) / 4);
+    hipLaunchKernelGGL(pair_mask_kernel, dim3(chunk_grid(nblk, kMaskChunk)), dim3(256),
+                       4 * size_t(p.mw) * 4, st, pw, H, wl, cstart + C, ix.off, ix.amap, ix.n,
+                       p.mw, pairs, pmask, nblk);
+  }
   mark(3);
   const int ti = p.ti;
   const int tr = 32 << ti;
@@ -3479,20 +3840,23 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   }
   if (tr == 32)
     launch_score<32>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
-                     ctr + 8, alist, npcm, H > 1 ? pmask : (const uint32_t*)nullptr, p.mw, st);
+                     ctr + 8, alist, npcm, H > 1 ? pmask : (const uint32_t*)nullptr, p.mw, bkey,
+                     p.nbcap, st);
   else if (tr == 64)
     launch_score<64>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
-                     ctr + 8, alist, npcm, H > 1 ? pmask : (const uint32_t*)nullptr, p.mw, st);
+                     ctr + 8, alist, npcm, H > 1 ? pmask : (const uint32_t*)nullptr, p.mw, bkey,
+                     p.nbcap, st);
   else if (o.persistent || !launch_score_wg(ix, bf16, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap,
                                             npcm, H > 1 ? pmask : (const uint32_t*)nullptr,
-                                            p.mw, st))
+                                            p.mw, bkey, p.nbcap, st))
     launch_score<128>(ix, bf16, ti, cstart, wl, pairs, c, Q, qb, sbuf, p.rcap, o.persistent, gm,
-                      ctr + 8, alist, npcm, H > 1 ? pmask : (const uint32_t*)nullptr, p.mw, st);
+                      ctr + 8, alist, npcm, H > 1 ? pmask : (const uint32_t*)nullptr, p.mw, bkey,
+                      p.nbcap, st);
   mark(4);
   if (!bf16) {
     if (k <= 64)
       launch_wave_select<0>(st, pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids,
-                            scores, k, slist, int(H > 1));
+                            scores, k, slist, int(H > 1), CertArgs(), bkey, p.nbcap);
     else if (k <= 128)
       hipLaunchKernelGGL((select_kernel<128, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
                          p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), CertArgs());
@@ -3513,7 +3877,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
     ca.cap = int64_t(c) * p.rcap;
     if (k <= 64)
       launch_wave_select<2>(st, pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k,
-                            slist, int(H > 1), ca);
+                            slist, int(H > 1), ca, bkey, p.nbcap);
     else if (k <= 128)
       hipLaunchKernelGGL((select_kernel<128, 2>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
                          p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), ca);
@@ -3533,7 +3897,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   } else {
     if (p.S <= 64)
       launch_wave_select<1>(st, pairs, sbuf, p.rcap, c, nq, p.S, ix.off, ix.perm32, ids,
-                            scores, k, slist, int(H > 1));
+                            scores, k, slist, int(H > 1), CertArgs(), bkey, p.nbcap);
     else if (p.S <= 512)
       hipLaunchKernelGGL((select_kernel<512, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
                          p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), CertArgs());

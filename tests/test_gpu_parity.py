@@ -132,6 +132,30 @@ def test_mid_schedules_identical(mid):
     assert torch.equal(sub[0], ref[0][37:90]) and torch.equal(sub[1], ref[1][37:90])
 
 
+@pytest.mark.parametrize("k,c,r", [(1, 16, 256), (10, 16, 256), (10, 16, 100), (64, 16, 256),
+                                   (10, 16, 1200), (10, 20, 1200)])
+def test_mid_block_selection(mid, k, c, r):
+    """More than 2,048 candidates per query: the rerank writes the smallest
+    key of every 32-row block of every window and the selection reads only
+    the blocks that can hold the k + 1 best (windows of 100 rows start inside
+    blocks; k = 64 reads more than 16 blocks; 20 whole clusters of about 950
+    rows span more than 512 blocks and take the re-reading selection).
+    Results equal the oracle's, and every rerank schedule (each writes the
+    block keys its own way) returns the same bits."""
+    torch = _torch()
+    X, Q, gi, oi = mid["X"], mid["Q"], mid["gi"], mid["oi"]
+    Qd = torch.from_numpy(Q).cuda()
+    ids, sc, dbg = gi.search(Qd, k, c, r, r1=32, debug=True)
+    torch.cuda.synchronize()
+    oids, osc, odbg = oi.search(Q, k, c, r, 32, debug=True)
+    compare_debug(dbg, odbg)
+    compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+    for kw in [dict(tile_rows=32), dict(tile_rows=64), dict(tile_rows=128, pass_pairs=16),
+               dict(persistent=True), dict(tile_rows=32, persistent=2, grid_mult=1)]:
+        got = gi.search(Qd, k, c, r, r1=32, **kw)
+        assert torch.equal(got[0], ids) and torch.equal(got[1], sc), kw
+
+
 def test_mid_many_pairs_per_tile(mid):
     """Every tile overlapped by hundreds of pairs (3,000 queries, c = 8, whole
     clusters): the listed pairs of a tile carry over between passes for every
