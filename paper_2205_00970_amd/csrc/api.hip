@@ -46,7 +46,7 @@ void free_device(Index& ix) {
                   ix.models, ix.leaves,      ix.leaf_err, ix.tiles[0],  ix.tiles[1],
                   ix.tiles[2], ix.l1_tiles,  ix.tile_base[0], ix.tile_base[1],
                   ix.tile_base[2], ix.amap,  ix.l1map,     ix.Xt,        ix.tile_blk[0],
-                  ix.tile_blk[1], ix.tile_blk[2], ix.Xbt};
+                  ix.tile_blk[1], ix.tile_blk[2], ix.Xbt,      ix.amap16};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }

@@ -550,8 +550,19 @@ int build_core_models(Index& ix, const float* Xin, hipStream_t st) {
   return finish_index(ix);
 }
 
-// Host copy of the offsets, largest cluster and the rerank tile tables (all
-// derived from the offsets); shared by the build and the index loader.
+// amap16[h-1][o + p] = amap[h-1][o + p] - o: cluster j = blockIdx.x (rows o ..
+// o + L - 1), array h = blockIdx.y + 1.
+__global__ void amap16_kernel(const int32_t* __restrict__ amap, const int64_t* __restrict__ off,
+                              int64_t n, uint16_t* __restrict__ amap16) {
+  const int64_t o = off[blockIdx.x], L = off[blockIdx.x + 1] - o;
+  const int64_t base = int64_t(blockIdx.y) * n + o;
+  for (int64_t p = threadIdx.x; p < L; p += blockDim.x)
+    amap16[base + p] = uint16_t(amap[base + p] - o);
+}
+
+// Host copy of the offsets, largest cluster, the 16-bit position maps and the
+// rerank tile tables (all derived from the offsets and maps); shared by the
+// build and the index loader.
 int finish_index(Index& ix) {
   const int32_t C = ix.C;
   int rc = LIDER_OK;
@@ -564,6 +575,19 @@ int finish_index(Index& ix) {
     ix.max_cluster = std::max<int64_t>(ix.max_cluster, ix.h_off[j + 1] - ix.h_off[j]);
   if (ix.H > 1 && ix.max_cluster > kMaxMultiCluster)
     return set_error(LIDER_EINVAL, "with n_arrays > 1 no cluster may hold more than 65536 rows");
+  // several arrays: the position maps as positions within the cluster, 16 bits
+  // each (the search's pair masks read them)
+  if (ix.H > 1 && !ix.amap16 && ix.n > 0) {
+    const size_t cnt = size_t(ix.H - 1) * size_t(ix.n) + 8;
+    if (hipMalloc(&ix.amap16, al256(cnt * 2)) != hipSuccess) {
+      ix.amap16 = nullptr;
+      return set_error(LIDER_ENOMEM, "out of device memory (array position maps)");
+    }
+    hipLaunchKernelGGL(amap16_kernel, dim3(unsigned(C), unsigned(ix.H - 1)), dim3(256), 0,
+                       nullptr, ix.amap, ix.off, ix.n, ix.amap16);
+    rc = check_hip(hipDeviceSynchronize(), "array position maps");
+    if (rc != LIDER_OK) return rc;
+  }
   // clusters padded to whole 16-row blocks in the operand-ordered copy
   std::vector<int64_t> pblk(size_t(C) + 1, 0);  // first 16-row block of each cluster
   for (int32_t j = 0; j < C; ++j) pblk[j + 1] = pblk[j] + (ix.h_off[j + 1] - ix.h_off[j] + 15) / 16;

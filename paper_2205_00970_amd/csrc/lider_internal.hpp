@@ -218,6 +218,10 @@ struct Index {
   int32_t* digits = nullptr;   // [H x n x m] per original id
   int32_t* amap = nullptr;     // [(H-1) x n] array h's sorted position -> array 0's
   int32_t* l1map = nullptr;    // [(H-1) x C] same for the centroids retriever
+  // [(H-1) x n + 8] amap as positions within the cluster (o_j + p -> the row's
+  // position in cluster j): clusters hold at most 65,536 rows; 8 elements of
+  // padding for whole 16-byte reads
+  uint16_t* amap16 = nullptr;
   int32_t* assign = nullptr;   // [n] per original id
   int64_t* off = nullptr;      // [C+1]
   float* cent = nullptr;       // [C x d] cluster-id order

@@ -978,13 +978,13 @@ constexpr int32_t kMaskChunk = 64;
 
 // Union of a pair's H windows (several arrays): one wave per pair sets the
 // rows (positions of array 0 within the cluster; array h's positions go
-// through amap) in an LDS bitmap of mw words (dynamic shared memory, 4 waves x
-// mw words), stores the bitmap as the pair's membership mask [mw words] and
+// through amap16) in an LDS bitmap of mw words (dynamic shared memory, 4 waves
+// x mw words), stores the bitmap as the pair's membership mask [mw words] and
 // sets pairs[t] to the hull [first, last] of the union.
 __global__ __launch_bounds__(256) void pair_mask_kernel(
     const Pair* __restrict__ pw, int32_t H, const int32_t* __restrict__ wl,
     const int32_t* __restrict__ wl_end, const int64_t* __restrict__ off,
-    const int32_t* __restrict__ amap, int64_t n, int32_t mw, Pair* __restrict__ pairs,
+    const uint16_t* __restrict__ amap16, int64_t n, int32_t mw, Pair* __restrict__ pairs,
     uint32_t* __restrict__ mask, int32_t nblk) {
   extern __shared__ uint32_t bm_all[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1008,12 +1008,42 @@ __global__ __launch_bounds__(256) void pair_mask_kernel(
     for (int32_t w = lane; w < mw; w += 64) bm[w] = range_bits(w, s0, e0);
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
-    // the other arrays' window positions mapped to array 0's, four arrays at
-    // a time
-    auto map = [&](int32_t h, int32_t s, int32_t p) {
-      return int32_t(amap[int64_t(h - 1) * n + o + s + p] - o);
-    };
-    for (int32_t h0 = 1; h0 < H; h0 += 4) mark_windows4(bm, h0, H, myw.s, myw.len, lane, map);
+    // the other arrays' window positions mapped to array 0's: each lane reads
+    // 8 consecutive map entries (16 bytes, from the window's first entry
+    // rounded down to a multiple of 8), four arrays' reads in flight
+    for (int32_t h0 = 1; h0 < H; h0 += 4) {
+      int64_t ea[4];
+      int32_t lead[4], span[4], smax = 0;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int32_t h = min(h0 + g, H - 1);
+        const int64_t e = int64_t(h - 1) * n + o + __shfl(myw.s, h);
+        const int32_t len = h0 + g < H ? __shfl(myw.len, h) : 0;
+        ea[g] = e & ~int64_t(7);
+        lead[g] = int32_t(e - ea[g]);
+        span[g] = len > 0 ? lead[g] + len : 0;  // entries from ea[g] through the window's end
+        smax = max(smax, span[g]);
+      }
+      for (int32_t c0 = 0; c0 < smax; c0 += 512) {
+        uint4 v[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int32_t c = c0 + 8 * lane;
+          v[g] = c < span[g] ? *reinterpret_cast<const uint4*>(amap16 + ea[g] + c)
+                             : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const uint32_t wd[4] = {v[g].x, v[g].y, v[g].z, v[g].w};
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int32_t c = c0 + 8 * lane + k;
+            const uint32_t row = (wd[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+            if (c >= lead[g] && c < span[g]) atomicOr(&bm[row >> 5], 1u << (row & 31));
+          }
+        }
+      }
+    }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
     int32_t lo = INT32_MAX, hi = -1;
@@ -3823,7 +3853,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   if (H > 1) {
     const int32_t nblk = int32_t((np + 3) / 4);
     hipLaunchKernelGGL(pair_mask_kernel, dim3(chunk_grid(nblk, kMaskChunk)), dim3(256),
-                       4 * size_t(p.mw) * 4, st, pw, H, wl, cstart + C, ix.off, ix.amap, ix.n,
+                       4 * size_t(p.mw) * 4, st, pw, H, wl, cstart + C, ix.off, ix.amap16, ix.n,
                        p.mw, pairs, pmask, nblk);
   }
   mark(3);
