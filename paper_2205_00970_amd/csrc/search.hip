@@ -1971,7 +1971,7 @@ __device__ __forceinline__ void wg_pass(WgShared<FMT, NPCM>& sh, const TileRows<
   }
 }
 
-template <int FMT, int NPCM>
+template <int FMT, int NPCM, bool BK>
 __global__ __launch_bounds__(256, 2) void rerank_wg_kernel(
     const void* __restrict__ Xv, int32_t d, const int32_t* __restrict__ tiles, int32_t ntiles,
     const int32_t* __restrict__ cstart, const int32_t* __restrict__ wl,
@@ -2072,7 +2072,7 @@ __global__ __launch_bounds__(256, 2) void rerank_wg_kernel(
     // D layout: acc[rc][pc][e] = pair 16 pc + 4 s + e, row 32 wave + 16 rc + i.
     // Block keys: the smallest score key of the rows a wave stores for a pair
     // (NaN, a row outside the union, has the largest key), gathered in LDS.
-    if (bkey) {
+    if constexpr (BK) {
       for (int u = lane; u < PP; u += 64) sh.bk[wave][u] = 0xffffffffu;
       __threadfence_block();
       __builtin_amdgcn_wave_barrier();
@@ -2094,14 +2094,14 @@ __global__ __launch_bounds__(256, 2) void rerank_wg_kernel(
               float v = acc[rc][pc][e];
               if (pmask && !((sh.lm[pp][rr >> 5] >> (rr & 31)) & 1u)) v = __builtin_nanf("");
               __builtin_nontemporal_store(v, &dst[row]);
-              km = min(km, score_key(v));
+              if (BK) km = min(km, score_key(v));
             }
           }
-          if (bkey && km != 0xffffffffu) atomicMin(&sh.bk[wave][pp], km);
+          if (BK && km != 0xffffffffu) atomicMin(&sh.bk[wave][pp], km);
         }
       }
     }
-    if (bkey) {
+    if constexpr (BK) {
       // the wave's 32 rows are one block of 32 rows of the cluster
       __threadfence_block();
       __builtin_amdgcn_wave_barrier();
@@ -3502,9 +3502,15 @@ void launch_wg_n(const Index& ix, const void* X, const void* Qv, const int32_t* 
                  const uint32_t* pmask, int32_t mw, uint32_t* bkey, int32_t nbcap,
                  hipStream_t st) {
   const int32_t nt = ix.n_tiles[2];
-  hipLaunchKernelGGL((rerank_wg_kernel<FMT, NPCM>), dim3(chunk_grid(nt, tile_chunk(128))), dim3(256), 0,
-                     st, X, ix.d, ix.tiles[2], nt, cstart, wl, pairs, c, Qv, sbuf, rcap, pmask, mw,
-                     ix.tile_blk[2], bkey, nbcap);
+  // the block keys' epilogue only in the instantiation that writes them
+  if (bkey)
+    hipLaunchKernelGGL((rerank_wg_kernel<FMT, NPCM, true>), dim3(chunk_grid(nt, tile_chunk(128))),
+                       dim3(256), 0, st, X, ix.d, ix.tiles[2], nt, cstart, wl, pairs, c, Qv, sbuf,
+                       rcap, pmask, mw, ix.tile_blk[2], bkey, nbcap);
+  else
+    hipLaunchKernelGGL((rerank_wg_kernel<FMT, NPCM, false>), dim3(chunk_grid(nt, tile_chunk(128))),
+                       dim3(256), 0, st, X, ix.d, ix.tiles[2], nt, cstart, wl, pairs, c, Qv, sbuf,
+                       rcap, pmask, mw, ix.tile_blk[2], bkey, nbcap);
 }
 
 // The workgroup rerank (128-row tiles, direct schedule) on the operand-ordered
