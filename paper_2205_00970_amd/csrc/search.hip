@@ -157,11 +157,13 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   p.cert = cert;
   p.o_slist = take(cert ? size_t(nq) * c * rcap * 4 : S ? size_t(nq) * S * 4 : 0);
   p.o_scnt = take(cert ? size_t(nq) * 4 : 0);
-  // the selection's block form serves k (or the shortlist) <= 64 over more
-  // than 2,048 candidates per query (fewer fit the per-wave selection's
-  // registers, which is faster there than reading the block keys first); a
-  // window of at most rcap rows spans at most rcap / 32 + 1 blocks of 32 rows
-  p.nbcap = (S ? S : k) <= 64 && int64_t(c) * rcap > 2048 ? rcap / 32 + 1 : 0;
+  // the selection's block form serves k (or the shortlist) < 16 over more
+  // than 2,048 candidates per query: fewer candidates fit the per-wave
+  // selection's registers, which is faster there than reading the block keys
+  // first, and a larger k reads more blocks than it holds in registers (at
+  // k = 64 the listing overflows and the selection falls back to its slowest
+  // form); a window of at most rcap rows spans at most rcap / 32 + 1 blocks
+  p.nbcap = (S ? S : k) < 16 && int64_t(c) * rcap > 2048 ? rcap / 32 + 1 : 0;
   p.o_bkey = take(size_t(np) * p.nbcap * 4);
   rerank_shape(ix, nq, c, r, o, &p.ti, &p.npcm);
   const size_t nt = o.persistent == 2 ? size_t(ix.n_tiles[p.ti]) : 0;
@@ -2432,11 +2434,11 @@ __global__ __launch_bounds__(kSelNT) void select_kernel(
     const Pair* __restrict__ pairs, const float* __restrict__ sbuf, int32_t rcap, int32_t c,
     int64_t nq, int32_t K, const int64_t* __restrict__ off, const int32_t* __restrict__ perm32,
     int64_t* __restrict__ ids, float* __restrict__ scores, int32_t kout,
-    int32_t* __restrict__ slist, int drop, CertArgs ca) {
+    int32_t* __restrict__ slist, int drop, CertArgs ca, int32_t kcap) {
   __shared__ SelShared sh;
   __shared__ uint64_t srt[KPMAX];
   __shared__ int32_t sidx[KPMAX];
-  __shared__ uint32_t keys[kKeyCache];
+  extern __shared__ uint32_t keys[];  // dynamic: kcap keys (at most kKeyCache)
   __shared__ uint32_t s_thr;
   __shared__ int32_t s_m;
   __shared__ int32_t start[LIDER_MAX_C + 1];
@@ -2468,7 +2470,7 @@ __global__ __launch_bounds__(kSelNT) void select_kernel(
       }
       return lo;
     };
-    const bool cached = n <= kKeyCache;
+    const bool cached = n <= kcap;
     if (cached) {
       for (int t = 0; t < c; ++t) {
         const int32_t a = start[t], len = start[t + 1] - a;
@@ -2533,11 +2535,12 @@ __global__ __launch_bounds__(kSelNT) void select_kernel(
 // place is resolved by original id over all tied candidates; the winners are
 // finally ordered by (score desc, id asc).  MODE 0 writes ids / scores, MODE 1
 // the shortlist of sorted-row indices.  drop: NaN scores (key 0xffffffff) are
-// not candidates (rows of a union's hull outside the union).  R = 0 (more
-// than 64 R candidates): the keys are re-read from the score rows at each of
-// the two scans (no LDS copy of them: an LDS cache of 2,048 keys per wave held
-// the kernel to 3 workgroups per CU, and re-reading the rows from L2 at 4x
-// that occupancy is faster, 0.22 -> 0.16 ms for 8 windows of 1,000 rows).
+// not candidates (rows of a union's hull outside the union).  R = 0: with
+// block keys (bkey), the block form reads only the blocks that can hold the
+// K + 1 best; else, or past its limits, the keys are re-read from the score
+// rows in one pass that lists the candidates at or below a threshold that it
+// tightens as it goes (no LDS copy of the keys: an LDS cache of 2,048 keys
+// per wave held the kernel to 3 workgroups per CU).
 constexpr int kSelList = 256;
 // Block keys per lane in the block form of the selection: queries whose
 // windows span more than 64 kSelBlk blocks take the other forms.
@@ -3889,16 +3892,21 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
                       ctr + 8, alist, npcm, H > 1 ? pmask : (const uint32_t*)nullptr, p.mw, bkey,
                       p.nbcap, st);
   mark(4);
+  // the block selection's LDS key cache, sized to the candidates per query
+  // (a fixed 32 KB cache held it to three workgroups per CU)
+  const int32_t skc = int32_t(std::min<int64_t>(kKeyCache, int64_t(c) * p.rcap));
   if (!bf16) {
     if (k <= 64)
       launch_wave_select<0>(st, pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids,
                             scores, k, slist, int(H > 1), CertArgs(), bkey, p.nbcap);
     else if (k <= 128)
-      hipLaunchKernelGGL((select_kernel<128, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), CertArgs());
+      hipLaunchKernelGGL((select_kernel<128, 0>), dim3(qgrid), dim3(kSelNT), skc * 4, st,
+                         pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k,
+                         slist, int(H > 1), CertArgs(), skc);
     else
-      hipLaunchKernelGGL((select_kernel<1024, 0>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), CertArgs());
+      hipLaunchKernelGGL((select_kernel<1024, 0>), dim3(qgrid), dim3(kSelNT), skc * 4, st,
+                         pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k,
+                         slist, int(H > 1), CertArgs(), skc);
   } else if (p.cert) {
     // certified shortlist (every candidate within the bf16 error margin of the
     // k-th best), then the fp32 rerank of each query's list
@@ -3915,11 +3923,13 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
       launch_wave_select<2>(st, pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k,
                             slist, int(H > 1), ca, bkey, p.nbcap);
     else if (k <= 128)
-      hipLaunchKernelGGL((select_kernel<128, 2>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), ca);
+      hipLaunchKernelGGL((select_kernel<128, 2>), dim3(qgrid), dim3(kSelNT), skc * 4, st,
+                         pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k,
+                         slist, int(H > 1), ca, skc);
     else
-      hipLaunchKernelGGL((select_kernel<1024, 2>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), ca);
+      hipLaunchKernelGGL((select_kernel<1024, 2>), dim3(qgrid), dim3(kSelNT), skc * 4, st,
+                         pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k,
+                         slist, int(H > 1), ca, skc);
     const int vec = ix.d % 4 == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0;
     if (k <= 64)
       hipLaunchKernelGGL(cert_wave_kernel, dim3(unsigned((nq + 3) / 4)), dim3(256), 0, st, ix.X,
@@ -3935,11 +3945,13 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
       launch_wave_select<1>(st, pairs, sbuf, p.rcap, c, nq, p.S, ix.off, ix.perm32, ids,
                             scores, k, slist, int(H > 1), CertArgs(), bkey, p.nbcap);
     else if (p.S <= 512)
-      hipLaunchKernelGGL((select_kernel<512, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), CertArgs());
+      hipLaunchKernelGGL((select_kernel<512, 1>), dim3(qgrid), dim3(kSelNT), skc * 4, st,
+                         pairs, sbuf, p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k,
+                         slist, int(H > 1), CertArgs(), skc);
     else
-      hipLaunchKernelGGL((select_kernel<4096, 1>), dim3(qgrid), dim3(kSelNT), 0, st, pairs, sbuf,
-                         p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k, slist, int(H > 1), CertArgs());
+      hipLaunchKernelGGL((select_kernel<4096, 1>), dim3(qgrid), dim3(kSelNT), skc * 4, st,
+                         pairs, sbuf, p.rcap, c, nq, p.S, ix.off, ix.perm32, ids, scores, k,
+                         slist, int(H > 1), CertArgs(), skc);
     if (p.S <= 64 && ix.d % 4 == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0)
       hipLaunchKernelGGL(wave_shortlist_kernel, dim3(unsigned((nq + 3) / 4)), dim3(256), 0, st,
                          ix.X, ix.d, Q, nq, slist, p.S, ix.perm32, k, ids, scores);

@@ -132,16 +132,17 @@ def test_mid_schedules_identical(mid):
     assert torch.equal(sub[0], ref[0][37:90]) and torch.equal(sub[1], ref[1][37:90])
 
 
-@pytest.mark.parametrize("k,c,r", [(1, 16, 256), (10, 16, 256), (10, 16, 100), (64, 16, 256),
-                                   (10, 16, 1200), (10, 20, 1200)])
+@pytest.mark.parametrize("k,c,r", [(1, 16, 256), (10, 16, 256), (10, 16, 100), (15, 16, 256),
+                                   (64, 16, 256), (10, 16, 1200), (10, 20, 1200)])
 def test_mid_block_selection(mid, k, c, r):
-    """More than 2,048 candidates per query: the rerank writes the smallest
-    key of every 32-row block of every window and the selection reads only
-    the blocks that can hold the k + 1 best (windows of 100 rows start inside
-    blocks; k = 64 reads more than 16 blocks; 20 whole clusters of about 950
-    rows span more than 512 blocks and take the re-reading selection).
-    Results equal the oracle's, and every rerank schedule (each writes the
-    block keys its own way) returns the same bits."""
+    """More than 2,048 candidates per query and k < 16: the rerank writes the
+    smallest key of every 32-row block of every window and the selection
+    reads only the blocks that can hold the k + 1 best (windows of 100 rows
+    start inside blocks; k = 15 reads up to 16 blocks; k = 64 takes the
+    register selection instead; 20 whole clusters of about 950 rows span
+    more than 512 blocks and take the re-reading selection).  Results equal
+    the oracle's, and every rerank schedule (each writes the block keys its
+    own way) returns the same bits."""
     torch = _torch()
     X, Q, gi, oi = mid["X"], mid["Q"], mid["gi"], mid["oi"]
     Qd = torch.from_numpy(Q).cuda()
