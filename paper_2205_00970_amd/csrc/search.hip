@@ -561,6 +561,18 @@ __device__ inline uint32_t dpp_min_u32(uint32_t v) {
   return uint32_t(__builtin_amdgcn_readlane(int(v), 63));
 }
 
+// Sum over the 64 lanes of a wave (all lanes active), the same DPP pattern as
+// dpp_min_u32 with additions (a lane whose source lies before its row adds 0).
+__device__ inline int32_t dpp_sum_i32(int32_t v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
 // 64-bit minimum: the minimum high word, then the minimum low word among the
 // lanes holding it.
 __device__ inline uint64_t wave_min_u64(uint64_t v) {
@@ -3098,6 +3110,263 @@ __global__ __launch_bounds__(256) void wave_select_kernel(
   }
 }
 
+// Per query top K for 64 < K <= 128 (MODE 0: ids and scores, MODE 2: the
+// certified shortlist), one wave per query with the candidates' keys in
+// registers (n <= 64 R).  T = the (K+1)-th smallest key, by bisection on
+// counts over all candidates; the candidates with key <= T (K + 1 and
+// any ties) are listed in LDS and each ranked against the others by (key,
+// index), which places the K + 1 smallest.  A list past kSelList (ties)
+// extracts by repeated wave minima instead.  Boundary ties go to the smallest
+// ids, and the winners are ordered by (score desc, id asc), as in the
+// selection for k <= 64.
+constexpr int kWideK = 128;
+
+template <int MODE, int R>
+__global__ __launch_bounds__(256) void wave_select_wide_kernel(
+    const Pair* __restrict__ pairs, const float* __restrict__ sbuf, int32_t rcap, int32_t c,
+    int64_t nq, int32_t K, const int64_t* __restrict__ off, const int32_t* __restrict__ perm32,
+    int64_t* __restrict__ ids, float* __restrict__ scores, int32_t kout,
+    int32_t* __restrict__ slist, int drop, CertArgs ca) {
+  __shared__ int32_t start[4][LIDER_MAX_C + 1];
+  __shared__ int64_t pbase[4][LIDER_MAX_C];
+  __shared__ uint32_t lkey[4][kSelList];
+  __shared__ int32_t lidx[4][kSelList];
+  __shared__ uint64_t ext[4][kWideK + 1];
+  __shared__ uint32_t wk[4][kWideK], wid[4][kWideK];
+  __shared__ int64_t wrow[4][kWideK];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  const int64_t q = int64_t(blockIdx.x) * 4 + wave;
+  if (q >= nq) return;
+  const float* sbq = sbuf + q * int64_t(c) * rcap;
+  // slot table: start[] the exclusive prefix sum of the slot lengths,
+  // pbase[] each slot's first row
+  int32_t n = 0;
+  for (int t0 = 0; t0 < c; t0 += 64) {
+    const int t = t0 + lane;
+    int32_t len = 0;
+    int64_t base = 0;
+    if (t < c) {
+      const Pair pr = pairs[q * c + t];
+      if (pr.j >= 0) {
+        len = pr.len;
+        base = off[pr.j] + pr.s;
+      }
+    }
+    int32_t incl = len;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    if (t < c) {
+      start[wave][t] = n + incl - len;
+      pbase[wave][t] = base;
+    }
+    n += __shfl(incl, 63);
+  }
+  if (lane == 0) start[wave][c] = n;
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+  const int32_t* st = start[wave];
+  auto row_of = [&](int32_t i) {
+    int lo = 0, hi = c;  // the largest slot t with st[t] <= i
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (st[mid] <= i)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    return pbase[wave][lo] + (i - st[lo]);
+  };
+  // candidate i = lane + 64 j in register j (its score's bits, then its key);
+  // all loads issued before any key is formed (the slot of i only moves
+  // forward as i grows)
+  float fv[R];
+  {
+    int t = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (64 * j >= n) continue;  // wave-uniform
+      const int32_t i = min(lane + 64 * j, n - 1);
+      while (t + 1 < c && st[t + 1] <= i) ++t;
+      fv[j] = sbq[int64_t(t) * rcap + (i - st[t])];
+    }
+  }
+  uint32_t kr[R];
+  uint32_t vm = 0;  // bit j: register j holds a candidate
+  uint32_t kmin = 0xffffffffu, kmax = 0u;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    kr[j] = lane + 64 * j < n ? score_key(fv[j]) : 0xffffffffu;
+    if (lane + 64 * j < n && !(drop && kr[j] == 0xffffffffu)) {
+      vm |= 1u << j;
+      kmin = min(kmin, kr[j]);
+      kmax = max(kmax, kr[j]);
+    }
+  }
+  const int want = min(n, K + 1);
+  // T: the smallest x with at least `want` candidates <= x, by bisection
+  // over [min, max] of the keys on per-lane counts summed across the wave
+  // (no candidate: T = 0xffffffff, which lists nothing)
+  uint32_t lo = dpp_min_u32(kmin), hi = ~dpp_min_u32(~kmax);
+  if (lo > hi) lo = hi = 0xffffffffu;
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    int32_t c0 = 0, c1 = 0;
+#pragma unroll
+    for (int j = 0; j < R; j += 2) {
+      c0 += ((vm >> j) & 1u) && kr[j] <= mid;
+      if (j + 1 < R) c1 += ((vm >> (j + 1)) & 1u) && kr[j + 1] <= mid;
+    }
+    if (dpp_sum_i32(c0 + c1) >= want)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  const uint32_t T = lo;
+  int m = 0;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    if (64 * j >= n) break;  // wave-uniform
+    const bool in = ((vm >> j) & 1u) && kr[j] <= T;
+    const uint64_t bal = __ballot(in);
+    if (bal) {  // wave-uniform
+      const int slot = m + __popcll(bal & below);
+      if (in && slot < kSelList) {
+        lkey[wave][slot] = kr[j];
+        lidx[wave][slot] = lane + 64 * j;
+      }
+      m += __popcll(bal);
+    }
+  }
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+  int nx;
+  if (m <= kSelList) {
+    // each listed entry's rank among the listed, by (key, index)
+    uint64_t me[kSelList / 64];
+    int rk[kSelList / 64];
+#pragma unroll
+    for (int v = 0; v < kSelList / 64; ++v) {
+      const int e = lane + 64 * v;
+      me[v] = e < m ? (uint64_t(lkey[wave][e]) << 32) | uint32_t(lidx[wave][e]) : ~uint64_t(0);
+      rk[v] = 0;
+    }
+#pragma unroll 4
+    for (int u = 0; u < m; ++u) {
+      const uint64_t x = (uint64_t(lkey[wave][u]) << 32) | uint32_t(lidx[wave][u]);
+#pragma unroll
+      for (int v = 0; v < kSelList / 64; ++v) rk[v] += x < me[v];
+    }
+#pragma unroll
+    for (int v = 0; v < kSelList / 64; ++v)
+      if (lane + 64 * v < m && rk[v] < want) ext[wave][rk[v]] = me[v];
+    nx = min(m, want);
+  } else {
+    // many ties at T: repeated wave minima over all candidates
+    uint64_t prev = 0;
+    nx = 0;
+    for (int r = 0; r < want; ++r) {
+      uint64_t best = ~uint64_t(0);
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const uint64_t v = (uint64_t(kr[j]) << 32) | uint32_t(lane + 64 * j);
+        if (((vm >> j) & 1u) && (r == 0 || v > prev) && v < best) best = v;
+      }
+      best = wave_min_u64(best);
+      if (best == ~uint64_t(0)) break;  // wave-uniform
+      if (lane == 0) ext[wave][r] = best;
+      prev = best;
+      ++nx;
+    }
+  }
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+  const int got = min(nx, K);
+  for (int t = lane; t < got; t += 64) {
+    const uint64_t v = ext[wave][t];
+    const int64_t row = row_of(int32_t(v & 0xffffffffu));
+    wk[wave][t] = uint32_t(v >> 32);
+    wid[wave][t] = uint32_t(perm32[row]);
+    wrow[wave][t] = row;
+  }
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+  if (nx == K + 1 && uint32_t(ext[wave][K - 1] >> 32) == uint32_t(ext[wave][K] >> 32)) {
+    // exact tie at the boundary: the tied places go to the smallest ids
+    const uint32_t TT = uint32_t(ext[wave][K - 1] >> 32);
+    int need = 0;
+    for (int t = 0; t < K; ++t) need += wk[wave][t] == TT;
+    uint64_t last = 0;
+    for (int r = 0; r < need; ++r) {
+      uint64_t best = ~uint64_t(0);
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (!(((vm >> j) & 1u) && kr[j] == TT)) continue;
+        const int64_t row = row_of(lane + 64 * j);
+        const uint64_t v = (uint64_t(uint32_t(perm32[row])) << 32) | uint32_t(row);
+        if ((r == 0 || v > last) && v < best) best = v;
+      }
+      best = wave_min_u64(best);
+      if (lane == 0) {
+        wid[wave][K - need + r] = uint32_t(best >> 32);
+        wrow[wave][K - need + r] = int64_t(uint32_t(best & 0xffffffffu));
+      }
+      last = best;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+  }
+  // the winners ordered by (key, id); lane holds winners lane and lane + 64
+  uint32_t mk[2], mi[2];
+  int rank[2] = {0, 0};
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    const int t = lane + 64 * v;
+    mk[v] = t < got ? wk[wave][t] : 0xffffffffu;
+    mi[v] = t < got ? wid[wave][t] : 0xffffffffu;
+  }
+#pragma unroll 4
+  for (int u = 0; u < got; ++u) {
+    const uint32_t ku = wk[wave][u], iu = wid[wave][u];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) rank[v] += (ku < mk[v]) || (ku == mk[v] && iu < mi[v]);
+  }
+  if (MODE == 0) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+      if (lane + 64 * v < got) {
+        ids[q * kout + rank[v]] = int64_t(mi[v]);
+        scores[q * kout + rank[v]] = key_score(mk[v]);
+      }
+    for (int t = got + lane; t < kout; t += 64) {
+      ids[q * kout + t] = -1;
+      scores[q * kout + t] = -INFINITY;
+    }
+  } else {
+    // certified shortlist: every candidate within the margin of the k-th
+    // best key (the largest winner key when all K places are taken)
+    uint32_t tk = 0u;
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+      if (lane + 64 * v < got) tk = max(tk, mk[v]);
+    for (int o = 32; o > 0; o >>= 1) tk = max(tk, uint32_t(__shfl_xor(tk, o)));
+    const uint32_t thr = cert_threshold(ca, q, got == K ? tk : 0xffffffffu, lane);
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (64 * j >= n) break;  // wave-uniform
+      const bool in = ((vm >> j) & 1u) && kr[j] <= thr;
+      const uint64_t bal = __ballot(in);
+      if (in) slist[q * ca.cap + cnt + __popcll(bal & below)] = int32_t(row_of(lane + 64 * j));
+      cnt += __popcll(bal);
+    }
+    if (lane == 0) ca.scnt[q] = cnt;
+  }
+}
+
 // Precision form, second pass: exact fp32 inner products of the shortlisted
 // rows (from the fp32 copy), then the top k.  One workgroup per query; one
 // wave per row at a time, lanes over dimensions.
@@ -3468,6 +3737,21 @@ void launch_wave_select(hipStream_t st, const Pair* pairs, const float* sbuf, in
     hipLaunchKernelGGL((wave_select_kernel<MODE, 0>), dim3(wgrid), dim3(256), 0, st, pairs, sbuf,
                        rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca,
                        (const uint32_t*)nullptr, 0);
+}
+
+// 64 < K <= 128 over at most 2,048 candidates per query.
+template <int MODE>
+void launch_wave_wide(hipStream_t st, const Pair* pairs, const float* sbuf, int32_t rcap,
+                      int32_t c, int64_t nq, int32_t K, const int64_t* off, const int32_t* perm32,
+                      int64_t* ids, float* scores, int32_t kout, int32_t* slist, int drop,
+                      CertArgs ca) {
+  const unsigned wgrid = unsigned((nq + 3) / 4);  // one wave per query (nq < 2^31)
+  if (int64_t(c) * rcap <= 1024)
+    hipLaunchKernelGGL((wave_select_wide_kernel<MODE, 16>), dim3(wgrid), dim3(256), 0, st, pairs,
+                       sbuf, rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
+  else
+    hipLaunchKernelGGL((wave_select_wide_kernel<MODE, 32>), dim3(wgrid), dim3(256), 0, st, pairs,
+                       sbuf, rcap, c, nq, K, off, perm32, ids, scores, kout, slist, drop, ca);
 }
 
 template <int RT, int NPCM>
@@ -3899,6 +4183,9 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
     if (k <= 64)
       launch_wave_select<0>(st, pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids,
                             scores, k, slist, int(H > 1), CertArgs(), bkey, p.nbcap);
+    else if (k <= 128 && int64_t(c) * p.rcap <= 2048)
+      launch_wave_wide<0>(st, pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k,
+                          slist, int(H > 1), CertArgs());
     else if (k <= 128)
       hipLaunchKernelGGL((select_kernel<128, 0>), dim3(qgrid), dim3(kSelNT), skc * 4, st,
                          pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k,
@@ -3922,6 +4209,9 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
     if (k <= 64)
       launch_wave_select<2>(st, pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k,
                             slist, int(H > 1), ca, bkey, p.nbcap);
+    else if (k <= 128 && int64_t(c) * p.rcap <= 2048)
+      launch_wave_wide<2>(st, pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k,
+                          slist, int(H > 1), ca);
     else if (k <= 128)
       hipLaunchKernelGGL((select_kernel<128, 2>), dim3(qgrid), dim3(kSelNT), skc * 4, st,
                          pairs, sbuf, p.rcap, c, nq, k, ix.off, ix.perm32, ids, scores, k,
