@@ -232,28 +232,59 @@ __device__ int block_select(int n, int K, int KP, KeyF key_of, IdF id_of, uint64
       sh.mask = 0;
       sh.kneed = uint32_t(K);
     }
+    const int lane = tid & 63;
     for (int shift = 24; shift >= 0; shift -= 8) {
       for (int b = tid; b < 256; b += NT) sh.hist[b] = 0;
       __syncthreads();
       const uint32_t pre = sh.prefix, msk = sh.mask;
-      for (int i = tid; i < n; i += NT) {
-        const uint32_t k = key_of(i);
-        if ((k & msk) == pre) atomicAdd(&sh.hist[(k >> shift) & 255u], 1u);
+      // lanes of a wave with equal digits add once, by their lowest lane
+      // (the keys share their high bits: one bin takes most of them)
+      for (int i0 = 0; i0 < n; i0 += NT) {
+        const int i = i0 + tid;
+        const uint32_t k = i < n ? key_of(i) : 0u;
+        const bool act = i < n && (k & msk) == pre;
+        const uint32_t dg = (k >> shift) & 255u;
+        uint64_t peers = __ballot(act);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const uint64_t mb = __ballot((dg >> b) & 1u);
+          peers &= ((dg >> b) & 1u) ? mb : ~mb;
+        }
+        if (act && int(__builtin_ctzll(peers)) == lane)
+          atomicAdd(&sh.hist[dg], uint32_t(__popcll(peers)));
       }
       __syncthreads();
-      if (tid == 0) {
-        uint32_t cum = 0, need = sh.kneed;
-        for (int b = 0; b < 256; ++b) {
-          if (cum + sh.hist[b] >= need) {
-            sh.prefix |= uint32_t(b) << shift;
-            sh.mask |= 255u << shift;
-            sh.kneed = need - cum;
-            break;
-          }
-          cum += sh.hist[b];
+      if (tid < 64) {
+        // the bin holding the kneed-th key: 4 bins per lane, a scan over lanes
+        const uint32_t need = sh.kneed;
+        uint32_t h[4], sum = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          h[b] = sh.hist[4 * lane + b];
+          sum += h[b];
         }
-        sh.cnt_less = 0;
-        sh.cnt_tie = 0;
+        uint32_t incl = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t y = __shfl_up(incl, o);
+          if (lane >= o) incl += y;
+        }
+        uint32_t cum = incl - sum;
+        if (cum < need && need <= incl) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            if (cum + h[b] >= need) {
+              sh.prefix |= uint32_t(4 * lane + b) << shift;
+              sh.mask |= 255u << shift;
+              sh.kneed = need - cum;
+              break;
+            }
+            cum += h[b];
+          }
+        }
+        if (tid == 0) {
+          sh.cnt_less = 0;
+          sh.cnt_tie = 0;
+        }
       }
       __syncthreads();
     }
