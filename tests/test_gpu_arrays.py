@@ -48,7 +48,10 @@ def test_tiny3_build_bit_exact(tiny3):
 
 @pytest.mark.parametrize("k,c,r,r1", [(10, 4, 64, 3), (10, 2, 200, 16), (100, 4, 64, 5),
                                        (7, 3, 33, 1), (1, 1, 1, 0), (10, 16, 5000, 16),
-                                       (200, 2, 40, 2)])
+                                       (200, 2, 40, 2),
+                                       # 64 < k <= 128 over at most 2,048 hull rows per
+                                       # query: the wave selection with dropped rows
+                                       (100, 1, 64, 5), (70, 1, 300, 3)])
 def test_tiny3_search(tiny3, k, c, r, r1):
     _run(tiny3, k, c, r, r1)
 
@@ -72,7 +75,8 @@ def test_mid10_build_bit_exact(mid10):
 
 
 @pytest.mark.parametrize("k,c,r,r1", [(10, 8, 256, 32), (100, 8, 256, 32), (10, 4, 64, 64),
-                                       (1000, 16, 100, 20), (3, 1, 17, 1), (10, 2, 2000, 6)])
+                                       (1000, 16, 100, 20), (3, 1, 17, 1), (10, 2, 2000, 6),
+                                       (100, 2, 256, 32)])
 def test_mid10_search(mid10, k, c, r, r1):
     _run(mid10, k, c, r, r1)
 
