@@ -271,7 +271,9 @@ typedef struct {
 } lider_search_debug;
 
 /* Bytes of device workspace lider_search / lider_search_ex need for a batch.
- * Returns 0 for invalid arguments. */
+ * Non-decreasing in nq and in k (all else equal): a workspace sized for the
+ * largest batch and k serves every smaller one.  Returns 0 for invalid
+ * arguments. */
 size_t lider_search_workspace(const lider_index* index, int64_t nq, int32_t k, int32_t c,
                               int32_t r, const lider_search_opts* opts);
 

@@ -162,9 +162,12 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   // selection's registers, which is faster there than reading the block keys
   // first, and a larger k reads more blocks than it holds in registers (at
   // k = 64 the listing overflows and the selection falls back to its slowest
-  // form); a window of at most rcap rows spans at most rcap / 32 + 1 blocks
-  p.nbcap = (S ? S : k) < 16 && int64_t(c) * rcap > 2048 ? rcap / 32 + 1 : 0;
-  p.o_bkey = take(size_t(np) * p.nbcap * 4);
+  // form); a window of at most rcap rows spans at most rcap / 32 + 1 blocks.
+  // The room is taken whatever k is, so that the workspace never shrinks as
+  // k grows (a workspace sized for the largest k serves every smaller one)
+  const int32_t nbroom = int64_t(c) * rcap > 2048 ? rcap / 32 + 1 : 0;
+  p.nbcap = (S ? S : k) < 16 ? nbroom : 0;
+  p.o_bkey = take(size_t(np) * nbroom * 4);
   rerank_shape(ix, nq, c, r, o, &p.ti, &p.npcm);
   const size_t nt = o.persistent == 2 ? size_t(ix.n_tiles[p.ti]) : 0;
   p.o_aflag = take(nt * 4);

@@ -157,6 +157,21 @@ def test_mid_block_selection(mid, k, c, r):
         assert torch.equal(got[0], ids) and torch.equal(got[1], sc), kw
 
 
+def test_workspace_monotone_in_k(mid):
+    """The workspace never shrinks as k grows (the block keys' room is taken
+    whatever k is): one sized for the largest k serves every smaller k."""
+    torch = _torch()
+    gi, Q = mid["gi"], mid["Q"]
+    for c, r in [(16, 256), (8, 256), (2, 1200), (1, 17)]:
+        sizes = [gi.workspace_bytes(len(Q), k, c, r, r1=32) for k in (1, 10, 15, 16, 64, 65, 100, 128, 1000)]
+        assert sizes == sorted(sizes), (c, r, sizes)
+    Qd = torch.from_numpy(Q).cuda()
+    ws = torch.empty(gi.workspace_bytes(len(Q), 100, 16, 256, r1=32), dtype=torch.uint8, device="cuda")
+    ref = gi.search(Qd, 10, 16, 256, r1=32)
+    got = gi.search(Qd, 10, 16, 256, r1=32, ws=ws)
+    assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+
+
 def test_mid_many_pairs_per_tile(mid):
     """Every tile overlapped by hundreds of pairs (3,000 queries, c = 8, whole
     clusters): the listed pairs of a tile carry over between passes for every
