@@ -817,23 +817,27 @@ __global__ __launch_bounds__(256) void route_filter_kernel(
 // the FP64 inner product sequentially in dimension order (the definition) and
 // the top c by (score desc, cluster id asc) are taken.
 constexpr int kRescoreSteps = 16;  // float4 steps per lane of the fast path: d <= 1024
+// one wave per workgroup: a query that needs no rescoring frees its slot at
+// once instead of waiting for three busy neighbours
+constexpr int kRescoreWaves = 1;
 
-__global__ __launch_bounds__(256) void route_rescore_kernel(
+__global__ __launch_bounds__(64 * kRescoreWaves) void route_rescore_kernel(
     const float* __restrict__ Q, int32_t d, int64_t nq, const float* __restrict__ cent_l1,
     const int32_t* __restrict__ l1_order32, const int32_t* __restrict__ l1, int32_t wst,
     const int32_t* __restrict__ lst, int32_t lcap, int32_t c, const int32_t* __restrict__ rcand,
     const int32_t* __restrict__ rcnt, double* __restrict__ rs64, int32_t* __restrict__ routed) {
-  __shared__ float sq[4][64 * kRescoreSteps] __attribute__((aligned(16)));
-  __shared__ double clo[4][kCandCap], chi[4][kCandCap];
-  __shared__ int32_t cid[4][kCandCap];
-  __shared__ uint8_t cpick[4][kCandCap];
-  __shared__ int32_t chosen[4][LIDER_MAX_C];
+  __shared__ float sq[kRescoreWaves][64 * kRescoreSteps] __attribute__((aligned(16)));
+  __shared__ double clo[kRescoreWaves][kCandCap], chi[kRescoreWaves][kCandCap];
+  __shared__ int32_t cid[kRescoreWaves][kCandCap];
+  __shared__ uint8_t cpick[kRescoreWaves][kCandCap];
+  __shared__ int32_t chosen[kRescoreWaves][LIDER_MAX_C];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
   const double u = 1.1102230246251565e-16;  // 2^-53
   const bool fast = (d & 3) == 0 && d <= 64 * kRescoreSteps &&
                     ((reinterpret_cast<uintptr_t>(Q) | reinterpret_cast<uintptr_t>(cent_l1)) & 15) == 0;
-  for (int64_t q = int64_t(blockIdx.x) * 4 + wave; q < nq; q += int64_t(gridDim.x) * 4) {
+  for (int64_t q = int64_t(blockIdx.x) * kRescoreWaves + wave; q < nq;
+       q += int64_t(gridDim.x) * kRescoreWaves) {
     const int32_t n = rcnt[q];
     if (n == 0) continue;  // decided by the filter (wave-uniform)
     const float* qv = Q + q * d;
@@ -864,30 +868,26 @@ __global__ __launch_bounds__(256) void route_rescore_kernel(
         // the row through a buffer resource: reads past d return zeros
         const __amdgpu_buffer_rsrc_t rsrc =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(mu), 0, d * 4, kBufWord3);
-#pragma unroll 1
-        for (int h = 0; h < kRescoreSteps; h += 8) {  // 8 float4 loads in flight per lane
-          float4 m[8];
+        float4 m[kRescoreSteps];  // every load of the row in flight at once
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, (4 * j + 64 * (h + i)) * 4,
-                                                                 0, 0);
-            m[i] = float4{__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
-                          __uint_as_float(v[3])};
-          }
+        for (int i = 0; i < kRescoreSteps; ++i) {
+          const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, (4 * j + 64 * i) * 4, 0, 0);
+          m[i] = float4{__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
+                        __uint_as_float(v[3])};
+        }
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const float4 x = *reinterpret_cast<const float4*>(&sq[wave][4 * j + 64 * (h + i)]);
-            const double p0 = double(x.x) * double(m[i].x), p1 = double(x.y) * double(m[i].y);
-            const double p2 = double(x.z) * double(m[i].z), p3 = double(x.w) * double(m[i].w);
-            ps += p0;
-            ps += p1;
-            ps += p2;
-            ps += p3;
-            pa += fabs(p0);
-            pa += fabs(p1);
-            pa += fabs(p2);
-            pa += fabs(p3);
-          }
+        for (int i = 0; i < kRescoreSteps; ++i) {
+          const float4 x = *reinterpret_cast<const float4*>(&sq[wave][4 * j + 64 * i]);
+          const double p0 = double(x.x) * double(m[i].x), p1 = double(x.y) * double(m[i].y);
+          const double p2 = double(x.z) * double(m[i].z), p3 = double(x.w) * double(m[i].w);
+          ps += p0;
+          ps += p1;
+          ps += p2;
+          ps += p3;
+          pa += fabs(p0);
+          pa += fabs(p1);
+          pa += fabs(p2);
+          pa += fabs(p3);
         }
       } else {
         for (int k = j; k < d; k += 16) {
@@ -910,36 +910,27 @@ __global__ __launch_bounds__(256) void route_rescore_kernel(
     }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
-    // top c by parallel value (band midpoint), ties to the smaller cluster id
-    for (int r = 0; r < c; ++r) {
-      double bv = -INFINITY;
-      int32_t bi = 0x7fffffff, bt = -1;
-      for (int t = lane; t < n; t += 64) {
-        if (cpick[wave][t]) continue;
-        const double v = 0.5 * (clo[wave][t] + chi[wave][t]);
-        const int32_t id = cid[wave][t];
-        if (bt < 0 || v > bv || (v == bv && id < bi)) {
-          bv = v;
-          bi = id;
-          bt = t;
-        }
+    // top c by parallel value (band midpoint), ties to the smaller cluster id:
+    // a candidate's place is the number of candidates ahead of it in that order
+    // (a NaN midpoint counts as -inf, so the order stays total)
+    const auto mid = [&](int t) {
+      const double v = 0.5 * (clo[wave][t] + chi[wave][t]);
+      return v == v ? v : -INFINITY;
+    };
+    for (int t = lane; t < n; t += 64) {
+      const double v = mid(t);
+      const int32_t id = cid[wave][t];
+      int32_t place = 0;
+#pragma unroll 4
+      for (int s = 0; s < n; ++s) {
+        const double vs = mid(s);
+        place += (vs > v || (vs == v && cid[wave][s] < id)) ? 1 : 0;
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(bv, o);
-        const int32_t oi = __shfl_xor(bi, o), ot = __shfl_xor(bt, o);
-        if (ot >= 0 && (bt < 0 || ov > bv || (ov == bv && oi < bi))) {
-          bv = ov;
-          bi = oi;
-          bt = ot;
-        }
-      }
-      if (lane == 0) {
-        cpick[wave][bt] = 1;
-        chosen[wave][r] = bi;
-      }
-      __threadfence_block();
-      __builtin_amdgcn_wave_barrier();
+      cpick[wave][t] = place < c;
+      if (place < c) chosen[wave][place] = id;
     }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
     // decided when every chosen band lies above every other band
     double lo = INFINITY, hi = -INFINITY;
     for (int t = lane; t < n; t += 64) {
@@ -2294,13 +2285,14 @@ __global__ __launch_bounds__(256) void l1_gemm_kernel(const void* __restrict__ Q
 
 // bf16 layer-1 product staged through LDS (d a multiple of 64): a workgroup
 // owns a 128 x 128 tile of [queries x centroids], the 4 waves 64 x 64 each
-// (4 x 4 blocks of v_mfma_f32_16x16x32_bf16).  K runs in chunks of 64: the
-// workgroup loads the chunk's 128 query rows and 128 centroid rows (16 KB
-// each, one 16-byte load per thread per 16 rows) into registers while the
+// (4 x 4 blocks of v_mfma_f32_16x16x32_bf16).  K runs in chunks of 64 (32
+// with SPLIT below): the workgroup loads the chunk's 128 query rows and 128
+// centroid rows (16 KB each) into registers while the
 // previous chunk is consumed from LDS, then swaps buffers -- each operand
 // byte is read from L2 once per tile instead of once per wave.  Rows are
-// padded to 72 bf16 (144 B) so the 16 lanes of a fragment read spread over
-// the LDS banks.  Tiles are dealt to the 8 XCDs round-robin so consecutive
+// padded by 8 bf16 (16 B) so the 16 lanes of a fragment read spread over the
+// LDS banks.  Three workgroups fit a CU, so the 632 tiles of 10,000 queries x
+// 1,000 centroids run in one round on 256 CUs.  Tiles are dealt to the 8 XCDs round-robin so consecutive
 // tiles of one XCD share their query rows in its L2.
 //
 // SPLIT: both operands are read in fp32 and each value x is split on its way
@@ -2310,7 +2302,7 @@ __global__ __launch_bounds__(256) void l1_gemm_kernel(const void* __restrict__ Q
 // accumulation error instead of 2^-7 |q| |mu|.  With c > 1 that decides the
 // routing for most queries without FP64 rescoring (1M x 768, 1,000 clusters,
 // c = 8: 21 candidates per query with the bf16 band, 8.2 with the split one).
-constexpr int kLdsK = 64, kLdsRow = 72;
+constexpr int kLdsK = 64;
 
 __device__ inline void split_bf16x8(const float4& a, const float4& b, bf16x8& hi, bf16x8& lo) {
   const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
@@ -2329,13 +2321,17 @@ __device__ inline void split_bf16x8(const float4& a, const float4& b, bf16x8& hi
 // locate (l1_item) of 256 items each: both only need the hash kernel's
 // output, so one launch runs them side by side.
 template <bool SPLIT>
-__global__ __launch_bounds__(256, SPLIT ? 2 : 3) void l1_gemm_lds_kernel(
+__global__ __launch_bounds__(256, 3) void l1_gemm_lds_kernel(
     const void* __restrict__ Qv, int64_t nq, const void* __restrict__ Cv, int32_t C, int32_t d,
     float* __restrict__ rs, L1Args la, unsigned l1_blocks) {
   constexpr int NP = SPLIT ? 2 : 1;  // operand parts in LDS (high, low)
+  // K chunk and padded LDS row (bf16): the split parts double the LDS bytes
+  // per value, so SPLIT takes half the chunk and three workgroups still fit a CU
+  constexpr int KCH = SPLIT ? kLdsK / 2 : kLdsK, ROW = KCH + 8;
+  constexpr int TPR = KCH / 8, RPP = 256 / TPR, NJ = 128 / RPP;  // loader shape
   typedef typename std::conditional<SPLIT, float, __hip_bfloat16>::type E;
-  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sa[NP][128 * kLdsRow];
-  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sb[NP][128 * kLdsRow];
+  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sa[NP][128 * ROW];
+  __shared__ __attribute__((aligned(16))) __hip_bfloat16 sb[NP][128 * ROW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (blockIdx.x < l1_blocks) {
     l1_item(la, int64_t(blockIdx.x) * 256 + tid);
@@ -2352,37 +2348,38 @@ __global__ __launch_bounds__(256, SPLIT ? 2 : 3) void l1_gemm_lds_kernel(
   if ((bid >> 3) >= per || t >= nblk) return;
   const int64_t m0 = (t / ntc) * 128;
   const int32_t n0 = int32_t(t % ntc) * 128;
-  // loader: thread tid moves 8 values of rows tid / 8 + 32 j, columns 8 (tid % 8)
-  const int lr = tid >> 3, lc = 8 * (tid & 7);
-  const E* qsrc[4];
-  const E* csrc[4];
+  // loader: thread tid moves 8 values of rows tid / TPR + RPP j, columns
+  // 8 (tid % TPR)
+  const int lr = tid / TPR, lc = 8 * (tid % TPR);
+  const E* qsrc[NJ];
+  const E* csrc[NJ];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    qsrc[j] = Q + min(m0 + lr + 32 * j, nq - 1) * d + lc;
-    csrc[j] = Cc + int64_t(min(n0 + lr + 32 * j, C - 1)) * d + lc;
+  for (int j = 0; j < NJ; ++j) {
+    qsrc[j] = Q + min(m0 + lr + RPP * j, nq - 1) * d + lc;
+    csrc[j] = Cc + int64_t(min(n0 + lr + RPP * j, C - 1)) * d + lc;
   }
-  bf16x8 ra[4], rb[4];          // bf16 operands in flight
-  float4 fa4[4][2], fb4[4][2];  // fp32 operands in flight (SPLIT)
+  bf16x8 ra[NJ], rb[NJ];          // bf16 operands in flight
+  float4 fa4[NJ][2], fb4[NJ][2];  // fp32 operands in flight (SPLIT)
   auto gload = [&](int kc) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       if constexpr (SPLIT) {
-        const float4* qa = reinterpret_cast<const float4*>(qsrc[j] + kc * kLdsK);
-        const float4* ca = reinterpret_cast<const float4*>(csrc[j] + kc * kLdsK);
+        const float4* qa = reinterpret_cast<const float4*>(qsrc[j] + kc * KCH);
+        const float4* ca = reinterpret_cast<const float4*>(csrc[j] + kc * KCH);
         fa4[j][0] = qa[0];
         fa4[j][1] = qa[1];
         fb4[j][0] = ca[0];
         fb4[j][1] = ca[1];
       } else {
-        ra[j] = *reinterpret_cast<const bf16x8*>(qsrc[j] + kc * kLdsK);
-        rb[j] = *reinterpret_cast<const bf16x8*>(csrc[j] + kc * kLdsK);
+        ra[j] = *reinterpret_cast<const bf16x8*>(qsrc[j] + kc * KCH);
+        rb[j] = *reinterpret_cast<const bf16x8*>(csrc[j] + kc * KCH);
       }
     }
   };
   auto lstore = [&]() {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int o = (lr + 32 * j) * kLdsRow + lc;
+    for (int j = 0; j < NJ; ++j) {
+      const int o = (lr + RPP * j) * ROW + lc;
       if constexpr (SPLIT) {
         bf16x8 h, l;
         split_bf16x8(fa4[j][0], fa4[j][1], h, l);
@@ -2403,23 +2400,23 @@ __global__ __launch_bounds__(256, SPLIT ? 2 : 3) void l1_gemm_lds_kernel(
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int nk = d / kLdsK;
+  const int nk = d / KCH;
   gload(0);
   lstore();
   __syncthreads();
   for (int kc = 0; kc < nk; ++kc) {
     if (kc + 1 < nk) gload(kc + 1);  // in flight while this chunk is consumed
 #pragma unroll
-    for (int kk = 0; kk < kLdsK; kk += 32) {
+    for (int kk = 0; kk < KCH; kk += 32) {
       bf16x8 fa[NP][4], fb[NP][4];
 #pragma unroll
       for (int h = 0; h < NP; ++h) {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
-          fa[h][a] = *reinterpret_cast<const bf16x8*>(&sa[h][(wr + 16 * a + i) * kLdsRow + kk + 8 * s]);
+          fa[h][a] = *reinterpret_cast<const bf16x8*>(&sa[h][(wr + 16 * a + i) * ROW + kk + 8 * s]);
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-          fb[h][b] = *reinterpret_cast<const bf16x8*>(&sb[h][(wc + 16 * b + i) * kLdsRow + kk + 8 * s]);
+          fb[h][b] = *reinterpret_cast<const bf16x8*>(&sb[h][(wc + 16 * b + i) * ROW + kk + 8 * s]);
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a)
@@ -4154,7 +4151,9 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
       hipLaunchKernelGGL(route_filter_kernel<0>, dim3(fgrid), dim3(256), 0, st, ix.d, nq,
                          ix.l1_order32, l1w, wst, lstp, p.lcap, rs, rstride, dense, qnorm,
                          ix.cent_norm_max, ecoef, eadd, esub, c, rcand, rcnt, routed, whole);
-    hipLaunchKernelGGL(route_rescore_kernel, dim3(wgrid), dim3(256), 0, st, Q, ix.d, nq,
+    const unsigned rgrid =
+        unsigned(std::min<int64_t>((nq + kRescoreWaves - 1) / kRescoreWaves, 65535));
+    hipLaunchKernelGGL(route_rescore_kernel, dim3(rgrid), dim3(64 * kRescoreWaves), 0, st, Q, ix.d, nq,
                        ix.cent_l1, ix.l1_order32, l1w, wst, lstp, p.lcap, c, rcand, rcnt, rs64,
                        routed);
   }
