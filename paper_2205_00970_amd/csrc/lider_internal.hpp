@@ -7,6 +7,7 @@
 #include <hip/hip_bf16.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -137,21 +138,42 @@ __device__ inline uint64_t encode_query_unrolled(const int32_t (&h)[LIDER_MAX_M]
   return mode == 2 ? K + 1 : K;
 }
 
-// Predicted location of a query in one core model.  The model (192 bytes)
-// and the query's m digits are loaded with all their loads in flight before
-// the arithmetic starts.
+// Predicted location of a query in one core model.  The model's header, its
+// first m digit bounds (the key reads no others: m_eff <= m) and the query's
+// m digits are loaded with all their loads in flight before the arithmetic
+// starts; 16-byte loads throughout when the digits are 16-byte aligned.
 __device__ inline int64_t locate(const Model* Mp, const double* leaves, const int32_t* qd, int m,
                                  uint64_t* Kout = nullptr) {
   Model M;
   {
+    constexpr int kHead = int(offsetof(Model, mins) / 16), kB = LIDER_MAX_M / 4;
+    static_assert(offsetof(Model, mins) % 16 == 0 && offsetof(Model, maxs) == offsetof(Model, mins) + 16 * kB,
+                  "the digit bounds are whole 16-byte pieces after the header");
     const int4* src = reinterpret_cast<const int4*>(Mp);
     int4* dst = reinterpret_cast<int4*>(&M);
+    const int nb = (m + 3) >> 2;
 #pragma unroll
-    for (int w = 0; w < int(sizeof(Model) / 16); ++w) dst[w] = src[w];
+    for (int w = 0; w < kHead; ++w) dst[w] = src[w];
+#pragma unroll
+    for (int w = 0; w < kB; ++w) {
+      dst[kHead + w] = w < nb ? src[kHead + w] : int4{0, 0, 0, 0};
+      dst[kHead + kB + w] = w < nb ? src[kHead + kB + w] : int4{0, 0, 0, 0};
+    }
   }
   int32_t h[LIDER_MAX_M];
+  if ((m & 3) == 0 && (reinterpret_cast<uintptr_t>(qd) & 15) == 0) {
 #pragma unroll
-  for (int i = 0; i < LIDER_MAX_M; ++i) h[i] = i < m ? qd[i] : 0;
+    for (int w = 0; w < LIDER_MAX_M / 4; ++w) {
+      const int4 v = 4 * w < m ? reinterpret_cast<const int4*>(qd)[w] : int4{0, 0, 0, 0};
+      h[4 * w] = v.x;
+      h[4 * w + 1] = v.y;
+      h[4 * w + 2] = v.z;
+      h[4 * w + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < LIDER_MAX_M; ++i) h[i] = i < m ? qd[i] : 0;
+  }
   if (M.L <= 0) return 0;
   uint64_t K = encode_query_unrolled(h, M);
   if (Kout) *Kout = K;

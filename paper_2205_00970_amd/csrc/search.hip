@@ -40,6 +40,7 @@ constexpr int kCtrWords = 64;
 
 // Routing candidates kept per query for the FP64 rescoring.
 constexpr int kCandCap = 256;
+constexpr int kCntCopies = 8;  // copies of the per-cluster pair counters (layer 2 pairs)
 
 constexpr int32_t kBufWord3 = 0x00020000;  // buffer resource word 3 for gfx9-family targets
 
@@ -148,9 +149,9 @@ Plan make_plan(const Index& ix, int64_t nq, int32_t k, int32_t c, int32_t r,
   p.o_mask = take(H > 1 ? size_t(np) * p.mw * 4 : 0);
   p.o_routed = take(size_t(nq) * c * 4);
   p.o_pairs = take(size_t(nq) * c * sizeof(Pair));
-  p.o_ccount = take(size_t(ix.C) * 4);
+  p.o_ccount = take(size_t(kCntCopies) * ix.C * 4);
   p.o_cstart = take((size_t(ix.C) + 1) * 4);
-  p.o_cfill = take(size_t(ix.C) * 4);
+  p.o_cfill = take(size_t(kCntCopies) * ix.C * 4);
   p.o_wl = take(size_t(nq) * c * 4);
   p.o_sbuf = take(size_t(nq) * c * rcap * 4);
   p.o_qb = take((S || cert || ix.cent8 || ix.cent_l1_b) ? size_t(nq) * ix.d * 2 : 0);
@@ -953,6 +954,32 @@ __global__ __launch_bounds__(64 * kRescoreWaves) void route_rescore_kernel(
 
 
 // ------------------------------------------------------------ layer 2 pairs
+// The per-cluster pair counts and scatter cursors are kept in kCntCopies
+// copies (copy x of cluster j at x C + j), pair t using copy (t / 256) % 8:
+// at c = 8 about 80 pairs of 10,000 queries hit each of 1,000 clusters, and
+// the atomics on one address queue behind each other; the copies shorten
+// each queue eightfold.  A cluster's pairs stay contiguous in the work list,
+// copy by copy.
+
+__device__ inline int cnt_copy(int64_t t) { return int((t >> 8) & (kCntCopies - 1)); }
+
+__device__ inline int32_t cluster_count(const int32_t* __restrict__ cnt, int32_t C, int32_t j) {
+  int32_t v = 0;
+#pragma unroll
+  for (int x = 0; x < kCntCopies; ++x) v += cnt[int64_t(x) * C + j];
+  return v;
+}
+
+// Work-list slot of pair t of cluster j (first slot of the cluster: s0): the
+// counts of the copies before t's, then t's place in its own copy.
+__device__ inline int32_t copy_slot(const int32_t* __restrict__ cnt, int32_t* __restrict__ fill,
+                                    int32_t C, int64_t t, int32_t j, int32_t s0) {
+  const int x0 = cnt_copy(t);
+  int32_t o = s0;
+  for (int x = 0; x < x0; ++x) o += cnt[int64_t(x) * C + j];
+  return o + atomicAdd(&fill[int64_t(x0) * C + j], 1);
+}
+
 // One thread per (query, routed cluster) pair t.  One array: pairs[t] is the
 // window.  H arrays: pw[t H + h] is array h's window (positions of array h)
 // and pairs[t] gets the union's hull later (pair_mask_kernel).
@@ -983,7 +1010,7 @@ __global__ void pairs_kernel(const Model* __restrict__ models, const double* __r
   }
   if (pw) pw[t * H + h] = ph;
   if (h == 0) {
-    if (j >= 0 && ph.len > 0) atomicAdd(&ccount[j], 1);
+    if (j >= 0 && ph.len > 0) atomicAdd(&ccount[cnt_copy(t) * C + j], 1);
     pairs[t] = ph;
   }
 }
@@ -1189,7 +1216,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int32_t* __restrict__ 
   const int per = (C + 1023) / 1024;
   const int a = tid * per, e = min(C, a + per);
   int32_t s = 0;
-  for (int i = a; i < e; ++i) s += cnt[i];
+  for (int i = a; i < e; ++i) s += cluster_count(cnt, C, i);
   part[tid] = s;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -1201,19 +1228,20 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int32_t* __restrict__ 
   int32_t run = tid ? part[tid - 1] : 0;
   for (int i = a; i < e; ++i) {
     start[i] = run;
-    run += cnt[i];
+    run += cluster_count(cnt, C, i);
   }
   if (tid == 1023) start[C] = part[1023];
 }
 
 __global__ void scatter_kernel(const Pair* __restrict__ pairs, int64_t np,
+                               const int32_t* __restrict__ cnt, int32_t C,
                                const int32_t* __restrict__ start, int32_t* __restrict__ fill,
                                int32_t* __restrict__ wl) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= np) return;
   const Pair pr = pairs[t];
   if (pr.j < 0 || pr.len <= 0) return;
-  wl[start[pr.j] + atomicAdd(&fill[pr.j], 1)] = int32_t(t);
+  wl[copy_slot(cnt, fill, C, t, pr.j, start[pr.j])] = int32_t(t);
 }
 
 // scan_kernel + scatter_kernel in one launch for C <= kFusedScanMax: every
@@ -1233,7 +1261,7 @@ __global__ __launch_bounds__(256) void scan_scatter_kernel(const int32_t* __rest
   const int a = tid * per, e = min(C, a + per);
   int32_t sum = 0;
   for (int i = a; i < e; ++i) {
-    const int32_t v = cnt[i];
+    const int32_t v = cluster_count(cnt, C, i);
     st[i] = v;
     sum += v;
   }
@@ -1259,7 +1287,7 @@ __global__ __launch_bounds__(256) void scan_scatter_kernel(const int32_t* __rest
   if (t >= np) return;
   const Pair pr = pairs[t];
   if (pr.j < 0 || pr.len <= 0) return;
-  wl[st[pr.j] + atomicAdd(&fill[pr.j], 1)] = int32_t(t);
+  wl[copy_slot(cnt, fill, C, t, pr.j, st[pr.j])] = int32_t(t);
 }
 
 // Active-tile work list: every pair marks the tiles its window overlaps; the
@@ -4067,7 +4095,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
                      (o.l1_dense == 3 || (o.l1_dense == 0 && c > 1));
   mark(0);
   // the hash launch also clears the counters (it writes no status: digits are clamped)
-  const HashZero zr{ctr, int32_t(kCtrWords), ccount, cfill, C, 0};
+  const HashZero zr{ctr, int32_t(kCtrWords), ccount, cfill, kCntCopies * C, 0};
   int rc = run_hash_ex(Q, nq, ix.d, ix.A, ix.b, ix.anorm, 2 * H * m, ix.w, qdig, ctr + 1, 1, qnorm,
                        st, ix.hash_kind, (fp8 || bf16 || l1b) ? qb : nullptr, &zr);
   if (rc != LIDER_OK) return rc;
@@ -4172,7 +4200,7 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   } else {
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, ccount, C, cstart);
     hipLaunchKernelGGL(scatter_kernel, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, pairs,
-                       np, cstart, cfill, wl);
+                       np, ccount, C, cstart, cfill, wl);
   }
   // several arrays: each listed pair's union of windows as a membership mask
   // over its cluster's rows, and its window set to the union's hull
