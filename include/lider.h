@@ -290,6 +290,9 @@ size_t lider_search_workspace(const lider_index* index, int64_t nq, int32_t k, i
  * byte aligned).  Asynchronous on `stream`: nothing is allocated, nothing is
  * synchronised, no host read-back.  k in 1..LIDER_MAX_K, c in
  * 1..min(LIDER_MAX_C, n_clusters), r >= 1, nq >= 0 (0 is a no-op).
+ * A query holding a NaN or an infinity gets ids that are -1 or rows of the
+ * corpus (which ones is unspecified); the other queries of the batch are
+ * unaffected.
  * Safe to call concurrently on different streams with separate workspaces. */
 int lider_search(const lider_index* index, const float* queries_dev, int64_t nq, int32_t k,
                  int32_t c, int32_t r, int64_t* ids_dev, float* scores_dev, void* ws_dev,

@@ -699,7 +699,8 @@ __device__ __attribute__((noinline)) void route_fp64_wave(const float* __restric
 // route_filter_kernel, one wave per query: T, then the candidates.  Exactly c
 // candidates: they are the routed set (written directly, rcnt = 0).  More: the
 // candidates' positions go to rcand[q kCandCap ..] and rcnt[q] = their count,
-// or kCandCap + 1 when they do not fit (the whole window is then rescored).
+// or kCandCap + 1 when they do not fit or are fewer than c (the whole window
+// is then rescored).
 // R: approximate scores kept in registers per lane (len1 <= 64 R), else
 // re-read.
 
@@ -803,7 +804,10 @@ __global__ __launch_bounds__(256) void route_filter_kernel(
     int32_t* cq = rcand + q * kCandCap;
     const int nl = min(n, kCandCap);
     for (int t = lane; t < nl; t += 64) cq[t] = pos_of(cpos[wave][t]);
-    if (lane == 0) rcnt[q] = n > kCandCap ? kCandCap + 1 : n;
+    // fewer than c candidates only with non-finite scores (a query holding a
+    // NaN or an infinity): the whole window is then decided sequentially,
+    // which routes c valid clusters (or -1) whatever the scores
+    if (lane == 0) rcnt[q] = (n > kCandCap || n < c) ? kCandCap + 1 : n;
   }
 }
 

@@ -305,6 +305,32 @@ def test_odd_dimensions(d):
         compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
 
 
+@pytest.mark.parametrize("c,r1", [(1, 64), (5, 64), (5, 32)])
+def test_mid_non_finite_queries(mid, c, r1):
+    """Queries holding a NaN, an infinity or a value whose products overflow
+    fp32, in one coordinate or all of them, inside a batch of ordinary ones:
+    the search returns, their ids are -1 or corpus rows, and the ordinary
+    queries still equal the oracle (a routing window whose scores are not
+    finite is decided by the sequential FP64 pass)."""
+    torch = _torch()
+    X, Q, gi, oi = mid["X"], mid["Q"], mid["gi"], mid["oi"]
+    bad = Q[40:47].copy()
+    bad[0, 5] = np.nan
+    bad[1, :] = np.nan
+    bad[2, 7] = np.inf
+    bad[3, 100] = -np.inf
+    bad[4, :] = np.inf
+    bad[5, 3] = 3e38
+    bad[6, :] = -3e38
+    Qm = np.ascontiguousarray(np.concatenate([Q[:20], bad, Q[20:40]]))
+    ids, sc = gi.search(torch.from_numpy(Qm).cuda(), 10, c, 300, r1=r1)
+    ids, sc = ids.cpu().numpy(), sc.cpu().numpy()
+    assert ((ids >= -1) & (ids < X.shape[0])).all()
+    fin = np.r_[0:20, 27:47]
+    oids, osc = oi.search(Q[:40], 10, c, 300, r1)[:2]
+    compare_topk(X, Q[:40], ids[fin], sc[fin], oids, osc)
+
+
 def test_many_clusters_unfused_work_list():
     """More than 8,192 clusters: the cluster-count scan and the pair scatter run
     as two launches (the fused launch keeps the counts in LDS); build and
