@@ -331,12 +331,19 @@ def test_mid_non_finite_queries(mid, c, r1):
     compare_topk(X, Q[:40], ids[fin], sc[fin], oids, osc)
 
 
-def test_many_clusters_unfused_work_list():
+@pytest.mark.parametrize("nrep", [1, 12])
+def test_many_clusters_unfused_work_list(nrep):
     """More than 8,192 clusters: the cluster-count scan and the pair scatter run
     as two launches (the fused launch keeps the counts in LDS); build and
-    search still equal the oracle."""
+    search still equal the oracle.  nrep = 12: 768 queries, 4,608 pairs, so
+    every copy of the per-cluster counters holds pairs and clusters take pairs
+    in several copies."""
     torch = _torch()
     X, lab, Q, src = datagen.tiny(n=30000, d=32, ncomp=16, nq=64, seed=40, qseed=41)
+    if nrep > 1:
+        g = np.random.default_rng(43)
+        Q = np.concatenate([Q] + [Q + 0.05 * g.standard_normal(Q.shape) for _ in range(nrep - 1)])
+        Q = np.ascontiguousarray(Q.astype(np.float32))
     C = 9000
     asg = (np.arange(X.shape[0]) % C).astype(np.int32)
     A, b = datagen.lsh_params(4, 32, 1.0, seed=42)
