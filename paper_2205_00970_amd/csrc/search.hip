@@ -1045,6 +1045,9 @@ inline unsigned chunk_grid(int32_t ntiles, int32_t S) {
 
 // Pairs per pair-mask workgroup run dealt to one XCD: 4 x 64.
 constexpr int32_t kMaskChunk = 64;
+// Map segments (8 entries) per lane in flight in the pair masks (8, one
+// round for the 297 segments of nine windows of 256 entries, was no faster).
+constexpr int kMaskSegs = 4;
 
 // Union of a pair's H windows (several arrays): one wave per pair sets the
 // rows (positions of array 0 within the cluster; array h's positions go
@@ -1057,6 +1060,8 @@ __global__ __launch_bounds__(256) void pair_mask_kernel(
     const uint16_t* __restrict__ amap16, int64_t n, int32_t mw, Pair* __restrict__ pairs,
     uint32_t* __restrict__ mask, int32_t nblk) {
   extern __shared__ uint32_t bm_all[];
+  __shared__ int64_t sea[4][LIDER_MAX_H];  // per wave and array: first map entry read
+  __shared__ int32_t slead[4][LIDER_MAX_H], sspan[4][LIDER_MAX_H], sx[4][LIDER_MAX_H];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* bm = bm_all + wave * mw;
   // pairs in work-list order, 4 per workgroup, runs of kMaskChunk
@@ -1078,39 +1083,64 @@ __global__ __launch_bounds__(256) void pair_mask_kernel(
     for (int32_t w = lane; w < mw; w += 64) bm[w] = range_bits(w, s0, e0);
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
-    // the other arrays' window positions mapped to array 0's: each lane reads
-    // 8 consecutive map entries (16 bytes, from the window's first entry
-    // rounded down to a multiple of 8), four arrays' reads in flight
-    for (int32_t h0 = 1; h0 < H; h0 += 4) {
-      int64_t ea[4];
-      int32_t lead[4], span[4], smax = 0;
+    // the other arrays' window positions mapped to array 0's, in segments of 8
+    // consecutive map entries (16 bytes; an array's first segment starts at
+    // its window's first entry rounded down to a multiple of 8).  The
+    // segments of all H - 1 arrays are numbered in array order and dealt over
+    // the lanes, kMaskSegs per lane in flight, so every lane has work whatever
+    // the window lengths (one array's window of 256 entries is 33 segments).
+    // Lane h (1 <= h < H) sets up array h: map address, lead, span.
+    int32_t nseg = 0;
+    if (lane >= 1 && lane < H) {
+      const int64_t e = int64_t(lane - 1) * n + o + myw.s;
+      const int64_t ea = e & ~int64_t(7);
+      const int32_t lead = int32_t(e - ea);
+      const int32_t span = myw.len > 0 ? lead + myw.len : 0;  // entries from ea through the end
+      nseg = (span + 7) >> 3;
+      sea[wave][lane] = ea;
+      slead[wave][lane] = lead;
+      sspan[wave][lane] = span;
+    }
+    int32_t incl = nseg;  // inclusive prefix of the segment counts over lanes 0..15
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int32_t h = min(h0 + g, H - 1);
-        const int64_t e = int64_t(h - 1) * n + o + __shfl(myw.s, h);
-        const int32_t len = h0 + g < H ? __shfl(myw.len, h) : 0;
-        ea[g] = e & ~int64_t(7);
-        lead[g] = int32_t(e - ea[g]);
-        span[g] = len > 0 ? lead[g] + len : 0;  // entries from ea[g] through the window's end
-        smax = max(smax, span[g]);
-      }
-      for (int32_t c0 = 0; c0 < smax; c0 += 512) {
-        uint4 v[4];
+    for (int o2 = 1; o2 < LIDER_MAX_H; o2 <<= 1) {
+      const int32_t y = __shfl_up(incl, o2);
+      if (lane >= o2) incl += y;
+    }
+    if (lane < LIDER_MAX_H) sx[wave][lane] = incl - nseg;  // first segment of array lane
+    const int32_t total = __shfl(incl, LIDER_MAX_H - 1);
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t g0 = 0; g0 < total; g0 += 64 * kMaskSegs) {
+      uint4 v[kMaskSegs];
+      int32_t hh[kMaskSegs], cc[kMaskSegs];
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const int32_t c = c0 + 8 * lane;
-          v[g] = c < span[g] ? *reinterpret_cast<const uint4*>(amap16 + ea[g] + c)
-                             : make_uint4(0u, 0u, 0u, 0u);
+      for (int u = 0; u < kMaskSegs; ++u) {
+        const int32_t g = g0 + 64 * u + lane;
+        hh[u] = 1;
+        cc[u] = 0;
+        v[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (g < total) {
+          // the array holding segment g: the last one starting at or before g
+          // (arrays without segments start where the next one does)
+          int32_t h = 1;
+          for (int32_t x = 2; x < H; ++x)
+            if (sx[wave][x] <= g) h = x;
+          hh[u] = h;
+          cc[u] = 8 * (g - sx[wave][h]);  // < span: inside the allocation's padding at most
+          v[u] = *reinterpret_cast<const uint4*>(amap16 + sea[wave][h] + cc[u]);
         }
+      }
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const uint32_t wd[4] = {v[g].x, v[g].y, v[g].z, v[g].w};
+      for (int u = 0; u < kMaskSegs; ++u) {
+        if (g0 + 64 * u + lane >= total) continue;
+        const int32_t lead = slead[wave][hh[u]], span = sspan[wave][hh[u]];
+        const uint32_t wd[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const int32_t c = c0 + 8 * lane + k;
-            const uint32_t row = (wd[k >> 1] >> (16 * (k & 1))) & 0xffffu;
-            if (c >= lead[g] && c < span[g]) atomicOr(&bm[row >> 5], 1u << (row & 31));
-          }
+        for (int k = 0; k < 8; ++k) {
+          const int32_t c = cc[u] + k;
+          const uint32_t row = (wd[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+          if (c >= lead && c < span) atomicOr(&bm[row >> 5], 1u << (row & 31));
         }
       }
     }
@@ -2324,8 +2354,9 @@ __global__ __launch_bounds__(256) void l1_gemm_kernel(const void* __restrict__ Q
 // byte is read from L2 once per tile instead of once per wave.  Rows are
 // padded by 8 bf16 (16 B) so the 16 lanes of a fragment read spread over the
 // LDS banks.  Three workgroups fit a CU, so the 632 tiles of 10,000 queries x
-// 1,000 centroids run in one round on 256 CUs.  Tiles are dealt to the 8 XCDs round-robin so consecutive
-// tiles of one XCD share their query rows in its L2.
+// 1,000 centroids run in one round on 256 CUs.  Tiles are dealt to the 8
+// XCDs round-robin so consecutive tiles of one XCD share their query rows in
+// its L2.
 //
 // SPLIT: both operands are read in fp32 and each value x is split on its way
 // into LDS into h = bf16(x) and l = bf16(x - h) (x - h is exact in fp32), and
