@@ -1045,15 +1045,23 @@ inline unsigned chunk_grid(int32_t ntiles, int32_t S) {
 
 // Pairs per pair-mask workgroup run dealt to one XCD: 4 x 64.
 constexpr int32_t kMaskChunk = 64;
+// Copies of a pair's LDS bitmap in the pair masks (a power of two): eight or
+// four while the 4 waves' copies stay within 24 KB.
+__host__ __device__ inline int32_t mask_copies(int32_t mw) {
+  return mw <= 192 ? 8 : mw <= 384 ? 4 : 1;
+}
 // Map segments (8 entries) per lane in flight in the pair masks (8, one
 // round for the 297 segments of nine windows of 256 entries, was no faster).
 constexpr int kMaskSegs = 4;
 
 // Union of a pair's H windows (several arrays): one wave per pair sets the
 // rows (positions of array 0 within the cluster; array h's positions go
-// through amap16) in an LDS bitmap of mw words (dynamic shared memory, 4 waves
-// x mw words), stores the bitmap as the pair's membership mask [mw words] and
-// sets pairs[t] to the hull [first, last] of the union.
+// through amap16) in an LDS bitmap of mw words, stores the bitmap as the
+// pair's membership mask [mw words] and sets pairs[t] to the hull [first,
+// last] of the union.  The bitmap has mask_copies(mw) copies at a stride of
+// mw + 1 words (dynamic shared memory, 4 waves x copies x (mw + 1) words):
+// lane l marks copy l % copies, so fewer lanes of one atomic instruction hit
+// the same word, and the copies are ORed when the mask is stored.
 __global__ __launch_bounds__(256) void pair_mask_kernel(
     const Pair* __restrict__ pw, int32_t H, const int32_t* __restrict__ wl,
     const int32_t* __restrict__ wl_end, const int64_t* __restrict__ off,
@@ -1063,7 +1071,9 @@ __global__ __launch_bounds__(256) void pair_mask_kernel(
   __shared__ int64_t sea[4][LIDER_MAX_H];  // per wave and array: first map entry read
   __shared__ int32_t slead[4][LIDER_MAX_H], sspan[4][LIDER_MAX_H], sx[4][LIDER_MAX_H];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t* bm = bm_all + wave * mw;
+  const int32_t nc = mask_copies(mw), nbw = nc * (mw + 1);  // copies, words per wave
+  uint32_t* bm = bm_all + wave * nbw;
+  uint32_t* mine = bm + (lane & (nc - 1)) * (mw + 1);  // this lane's copy
   // pairs in work-list order, 4 per workgroup, runs of kMaskChunk
   // workgroups dealt to the XCDs in turn: the pairs of a cluster go to one
   // XCD, whose L2 then holds the cluster's position maps
@@ -1080,7 +1090,7 @@ __global__ __launch_bounds__(256) void pair_mask_kernel(
     const int64_t o = off[j];
     // array 0's window is a range of positions: whole words
     const int32_t s0 = __shfl(myw.s, 0), e0 = s0 + __shfl(myw.len, 0);
-    for (int32_t w = lane; w < mw; w += 64) bm[w] = range_bits(w, s0, e0);
+    for (int32_t w = lane; w < nbw; w += 64) bm[w] = w < mw ? range_bits(w, s0, e0) : 0u;
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
     // the other arrays' window positions mapped to array 0's, in segments of 8
@@ -1140,7 +1150,7 @@ __global__ __launch_bounds__(256) void pair_mask_kernel(
         for (int k = 0; k < 8; ++k) {
           const int32_t c = cc[u] + k;
           const uint32_t row = (wd[k >> 1] >> (16 * (k & 1))) & 0xffffu;
-          if (c >= lead && c < span) atomicOr(&bm[row >> 5], 1u << (row & 31));
+          if (c >= lead && c < span) atomicOr(&mine[row >> 5], 1u << (row & 31));
         }
       }
     }
@@ -1148,7 +1158,8 @@ __global__ __launch_bounds__(256) void pair_mask_kernel(
     __builtin_amdgcn_wave_barrier();
     int32_t lo = INT32_MAX, hi = -1;
     for (int32_t w = lane; w < mw; w += 64) {
-      const uint32_t bits = bm[w];
+      uint32_t bits = bm[w];
+      for (int32_t k = 1; k < nc; ++k) bits |= bm[k * (mw + 1) + w];
       mask[t * mw + w] = bits;
       if (bits) {
         lo = min(lo, w * 32 + __builtin_ctz(bits));
@@ -4242,8 +4253,8 @@ int run_search(const Index& ix, const float* Q, int64_t nq, int32_t k, int32_t c
   if (H > 1) {
     const int32_t nblk = int32_t((np + 3) / 4);
     hipLaunchKernelGGL(pair_mask_kernel, dim3(chunk_grid(nblk, kMaskChunk)), dim3(256),
-                       4 * size_t(p.mw) * 4, st, pw, H, wl, cstart + C, ix.off, ix.amap16, ix.n,
-                       p.mw, pairs, pmask, nblk);
+                       4 * size_t(mask_copies(p.mw)) * (p.mw + 1) * 4, st, pw, H, wl, cstart + C,
+                       ix.off, ix.amap16, ix.n, p.mw, pairs, pmask, nblk);
   }
   mark(3);
   const int ti = p.ti;
