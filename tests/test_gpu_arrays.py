@@ -162,6 +162,25 @@ def test_cos4_search(cos4, k, c, r, r1, eb):
     _run(cos4, k, c, r, r1, expand_bits=eb)
 
 
+@pytest.mark.parametrize("C", [3, 2])
+def test_large_clusters_union_masks(C):
+    """Two arrays over clusters of about 8,700 rows (C = 3) and 13,000 rows
+    (C = 2): the pair masks' LDS bitmap takes four copies, then one (the
+    clusters of the other fixtures take eight); masks, windows and results
+    equal the oracle."""
+    _torch()
+    X, lab, Q, _ = datagen.tiny(n=26000, d=32, ncomp=C, nq=64, seed=50, qseed=51)
+    asg = (np.arange(X.shape[0]) % C).astype(np.int32)
+    A, b = datagen.lsh_params(3, 32, 1.0, seed=52, n_arrays=2)
+    fx = {}
+    fx["gi"], fx["oi"], _ = build_pair(X, C, 3, 1.0, 4, A, b, assignment=asg, n_arrays=2)
+    fx["X"], fx["Q"] = X, Q
+    compare_index(fx["gi"], fx["oi"])
+    assert int(fx["gi"].max_cluster) > (6144 if C == 3 else 12288)
+    for k, c, r in ((10, 1, 300), (10, 2, 2000)):
+        _run(fx, k, c, r, C)
+
+
 def test_max_arrays_and_limits():
     """H = 16 (the maximum) on a small index; H = 17 and clusters above 65,536
     rows with several arrays are rejected."""
