@@ -305,6 +305,31 @@ def test_odd_dimensions(d):
         compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
 
 
+@pytest.mark.parametrize("d", [64, 192])
+def test_lds_product_ragged_tiles(d):
+    """The LDS-staged layer-1 product at the smallest dimensions it takes (two
+    and six K chunks of 32 in the split form, one and three of 64 in the plain
+    one), 200 centroids (a ragged second centroid tile) and 300 queries (a
+    ragged third query tile): plain and split bf16 routing equal the oracle's
+    FP64 routed sets and results, and each other."""
+    torch = _torch()
+    X, lab, Q, src = datagen.tiny(n=20000, d=d, ncomp=40, nq=300, seed=60, qseed=61)
+    C = 200
+    asg = (np.arange(X.shape[0]) % C).astype(np.int32)
+    A, b = datagen.lsh_params(4, d, 1.5, seed=62)
+    gi, oi, _ = build_pair(X, C, 4, 1.5, 8, A, b, assignment=asg)
+    Qd = torch.from_numpy(Q).cuda()
+    for c in (1, 4):
+        oids, osc, odbg = oi.search(Q, 10, c, 60, C, debug=True)
+        res = []
+        for mode in (2, 3):
+            ids, sc, dbg = gi.search(Qd, 10, c, 60, r1=C, debug=True, l1_dense=mode)
+            compare_debug(dbg, odbg)
+            compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+            res.append((ids, sc))
+        assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+
+
 @pytest.mark.parametrize("c,r1", [(1, 64), (5, 64), (5, 32)])
 def test_mid_non_finite_queries(mid, c, r1):
     """Queries holding a NaN, an infinity or a value whose products overflow
