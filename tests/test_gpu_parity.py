@@ -261,7 +261,7 @@ def test_mid_routing_near_ties(mid, l1_dense):
         rows.append(mpt)
         rows.append(mpt + 1e-6 * rng.standard_normal(768))
     Q = np.ascontiguousarray(np.stack(rows).astype(np.float32))
-    for c in (1, 2, 5):
+    for c in (1, 2, 5, 40):
         ids, sc, dbg = gi.search(torch.from_numpy(Q).cuda(), 10, c, 300, r1=64, debug=True,
                                  l1_dense=l1_dense)
         oids, osc, odbg = oi.search(Q, 10, c, 300, 64, debug=True)
@@ -328,6 +328,27 @@ def test_lds_product_ragged_tiles(d):
             compare_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
             res.append((ids, sc))
         assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+
+
+def test_routing_window_past_candidate_room():
+    """400 centroids and queries whose scores all tie (the zero vector) or
+    nearly tie (a centroid midpoint): more candidates than the rescoring's
+    room of 256, so the whole window is decided by the sequential FP64 pass;
+    routed sets and results equal the oracle's."""
+    torch = _torch()
+    X, lab, Q, src = datagen.tiny(n=24000, d=64, ncomp=40, nq=20, seed=70, qseed=71)
+    C = 400
+    asg = (np.arange(X.shape[0]) % C).astype(np.int32)
+    A, b = datagen.lsh_params(4, 64, 1.5, seed=72)
+    gi, oi, _ = build_pair(X, C, 4, 1.5, 8, A, b, assignment=asg)
+    cent = oi.centroids()
+    rows = [np.zeros(64, np.float32), 0.5 * (cent[3] + cent[7])]
+    Qm = np.ascontiguousarray(np.concatenate([np.stack(rows), Q]).astype(np.float32))
+    for c in (1, 3):
+        ids, sc, dbg = gi.search(torch.from_numpy(Qm).cuda(), 10, c, 60, r1=C, debug=True)
+        oids, osc, odbg = oi.search(Qm, 10, c, 60, C, debug=True)
+        compare_debug(dbg, odbg)
+        compare_topk(X, Qm, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
 
 
 @pytest.mark.parametrize("c,r1", [(1, 64), (5, 64), (5, 32)])
